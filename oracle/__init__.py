@@ -1,0 +1,363 @@
+"""FP64 CPU oracle for one FLIP timestep (arXiv 2404.01931).
+
+TEST INFRASTRUCTURE ONLY. The slow, plain reference the GPU library is checked
+against. Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may import it. It shares no code with the GPU library and
+the library never calls it.
+
+The arithmetic lives in ``flip_oracle.c`` (plain C, double precision); this
+module only marshals numpy arrays and composes the stages of one step in the
+order the paper's splitting fixes (Sec. 2.1.3: force, advect, project; with the
+particle stages of Sec. 3.1.3-3.1.8):
+
+    bin -> particle-to-grid -> gravity + walls -> right-hand side
+        -> PCG solve -> projection -> grid-to-particle + advection
+
+The dense solve used as a pin in the tests is numpy's, not this module's.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "flip_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+PRECOND_MIC0 = 0
+PRECOND_JACOBI = 1
+ADVECT_PARTICLE_VEL = 4
+
+STATUS_CONVERGED = 0
+STATUS_MAX_ITERS = 1
+STATUS_BREAKDOWN = 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liborc.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+               "-o", _LIB, _SRC, "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("dx", ctypes.c_double)]
+
+
+class _Region(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("center", ctypes.c_double * 3), ("radius", ctypes.c_double),
+                ("vel", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        G = ctypes.POINTER(_Grid)
+        i64, i32, dbl, u64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_uint64
+        sig = {
+            "orc_face_count": (i64, [G, i32]),
+            "orc_uniform01": (dbl, [u64, u64]),
+            "orc_seed": (i64, [G, ctypes.POINTER(_Region), i32, i32, u64, P, P, P, P, P, P]),
+            "orc_cell_keys": (None, [G, i64, P, P, P, P]),
+            "orc_bin": (None, [G, i64, P, P, P, P, P, P, P]),
+            "orc_fluid_flags": (None, [G, P, P]),
+            "orc_p2g": (None, [G, i32, i64, P, P, P, P, P, P]),
+            "orc_forces_walls": (None, [G, i32, dbl, dbl, P]),
+            "orc_divergence": (None, [G, P, P, P, P]),
+            "orc_rhs": (None, [G, P, P, P, P, dbl, dbl, P]),
+            "orc_apply_A": (None, [G, P, P, P]),
+            "orc_pcg": (i32, [G, P, P, P, dbl, i32, i32, P, P, P]),
+            "orc_project": (None, [G, i32, P, P, dbl, dbl, P, P]),
+            "orc_interp": (dbl, [G, i32, P, dbl, dbl, dbl]),
+            "orc_g2p_advect": (None, [G, i64, P, P, P, P, P, P, P, P, dbl, dbl, ctypes.c_uint]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"], "oracle arrays must be contiguous"
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass(frozen=True)
+class Grid:
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def ncells(self):
+        return self.nx * self.ny * self.nz
+
+    def face_shape(self, a: int):
+        d = [self.nx, self.ny, self.nz]
+        d[a] += 1
+        return (d[2], d[1], d[0])
+
+    def nfaces(self, a: int):
+        s = self.face_shape(a)
+        return s[0] * s[1] * s[2]
+
+    def c(self):
+        return ctypes.byref(_Grid(self.nx, self.ny, self.nz, float(self.dx)))
+
+
+@dataclass
+class Region:
+    kind: str  # "box" or "sphere"
+    lo: tuple = (-np.inf, -np.inf, -np.inf)
+    hi: tuple = (np.inf, np.inf, np.inf)
+    center: tuple = (0.0, 0.0, 0.0)
+    radius: float = 0.0
+    vel: tuple = (0.0, 0.0, 0.0)
+
+
+def _regions(regions):
+    arr = (_Region * max(1, len(regions)))()
+    for t, r in enumerate(regions):
+        arr[t].kind = 0 if r.kind == "box" else 1
+        for a in range(3):
+            arr[t].lo[a] = r.lo[a]
+            arr[t].hi[a] = r.hi[a]
+            arr[t].center[a] = r.center[a]
+            arr[t].vel[a] = r.vel[a]
+        arr[t].radius = r.radius
+    return arr
+
+
+def uniform01(seed: int, counter: int) -> float:
+    return _load().orc_uniform01(seed, counter)
+
+
+def seed(grid: Grid, regions, sub: int, seed_value: int):
+    """Jittered seeding (paper Sec. 3.1.2). Returns pos (3, n) and vel (3, n)."""
+    lib = _load()
+    regs = _regions(regions)
+    n = lib.orc_seed(grid.c(), regs, len(regions), sub, seed_value, None, None, None, None, None, None)
+    pos = np.zeros((3, n), np.float64)
+    vel = np.zeros((3, n), np.float64)
+    lib.orc_seed(grid.c(), regs, len(regions), sub, seed_value,
+                 _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]), _ptr(vel[0]), _ptr(vel[1]), _ptr(vel[2]))
+    return pos, vel
+
+
+def cell_keys(grid: Grid, pos) -> np.ndarray:
+    pos = _f64(pos)
+    n = pos.shape[1]
+    key = np.zeros(n, np.uint32)
+    _load().orc_cell_keys(grid.c(), n, _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]), _ptr(key))
+    return key
+
+
+def bin_particles(grid: Grid, pos):
+    """Binning (paper Sec. 3.1.5): key, count, start (exclusive scan), perm."""
+    pos = _f64(pos)
+    n = pos.shape[1]
+    key = np.zeros(n, np.uint32)
+    count = np.zeros(grid.ncells, np.uint32)
+    start = np.zeros(grid.ncells, np.uint32)
+    perm = np.zeros(n, np.int64)
+    _load().orc_bin(grid.c(), n, _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]), _ptr(key),
+                    _ptr(count), _ptr(start), _ptr(perm))
+    return key, count, start, perm
+
+
+def fluid_flags(grid: Grid, count) -> np.ndarray:
+    count = np.ascontiguousarray(count, dtype=np.uint32)
+    fluid = np.zeros(grid.ncells, np.uint8)
+    _load().orc_fluid_flags(grid.c(), _ptr(count), _ptr(fluid))
+    return fluid
+
+
+def p2g(grid: Grid, pos, vel, return_weights: bool = False):
+    """Particle-to-grid (paper Eq. (4)); returns [u, v, w] flat face arrays."""
+    pos, vel = _f64(pos), _f64(vel)
+    n = pos.shape[1]
+    out, wts = [], []
+    for a in range(3):
+        f = np.zeros(grid.nfaces(a), np.float64)
+        w = np.zeros(grid.nfaces(a), np.float64)
+        _load().orc_p2g(grid.c(), a, n, _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]), _ptr(vel[a]),
+                        _ptr(f), _ptr(w))
+        out.append(f)
+        wts.append(w)
+    return (out, wts) if return_weights else out
+
+
+def forces_walls(grid: Grid, faces, gravity, dt: float):
+    res = []
+    for a in range(3):
+        f = _f64(faces[a]).copy()
+        _load().orc_forces_walls(grid.c(), a, float(gravity[a]), float(dt), _ptr(f))
+        res.append(f)
+    return res
+
+
+def divergence(grid: Grid, faces) -> np.ndarray:
+    u, v, w = (_f64(f) for f in faces)
+    div = np.zeros(grid.ncells, np.float64)
+    _load().orc_divergence(grid.c(), _ptr(u), _ptr(v), _ptr(w), _ptr(div))
+    return div
+
+
+def rhs(grid: Grid, fluid, faces, density: float, dt: float) -> np.ndarray:
+    fluid = np.ascontiguousarray(fluid, dtype=np.uint8)
+    u, v, w = (_f64(f) for f in faces)
+    b = np.zeros(grid.ncells, np.float64)
+    _load().orc_rhs(grid.c(), _ptr(fluid), _ptr(u), _ptr(v), _ptr(w), float(density), float(dt), _ptr(b))
+    return b
+
+
+def apply_A(grid: Grid, fluid, x) -> np.ndarray:
+    fluid = np.ascontiguousarray(fluid, dtype=np.uint8)
+    x = _f64(x)
+    y = np.zeros(grid.ncells, np.float64)
+    _load().orc_apply_A(grid.c(), _ptr(fluid), _ptr(x), _ptr(y))
+    return y
+
+
+@dataclass
+class SolveResult:
+    p: np.ndarray
+    status: int
+    iterations: int
+    max_r: float
+    max_b: float
+
+
+def pcg(grid: Grid, fluid, b, tol: float, max_iters: int, precond: int = PRECOND_MIC0) -> SolveResult:
+    fluid = np.ascontiguousarray(fluid, dtype=np.uint8)
+    b = _f64(b)
+    p = np.zeros(grid.ncells, np.float64)
+    it = ctypes.c_int(0)
+    mr = ctypes.c_double(0)
+    mb = ctypes.c_double(0)
+    st = _load().orc_pcg(grid.c(), _ptr(fluid), _ptr(b), _ptr(p), float(tol), int(max_iters), int(precond),
+                         ctypes.byref(it), ctypes.byref(mr), ctypes.byref(mb))
+    return SolveResult(p, st, it.value, mr.value, mb.value)
+
+
+def project(grid: Grid, fluid, p, density: float, dt: float, star):
+    fluid = np.ascontiguousarray(fluid, dtype=np.uint8)
+    p = _f64(p)
+    out = []
+    for a in range(3):
+        s = _f64(star[a])
+        o = np.zeros_like(s)
+        _load().orc_project(grid.c(), a, _ptr(fluid), _ptr(p), float(density), float(dt), _ptr(s), _ptr(o))
+        out.append(o)
+    return out
+
+
+def interp(grid: Grid, a: int, f, x: float, y: float, z: float) -> float:
+    f = _f64(f)
+    return _load().orc_interp(grid.c(), a, _ptr(f), float(x), float(y), float(z))
+
+
+def g2p_advect(grid: Grid, pos, vel, unew, uold, flip_ratio: float, dt: float, flags: int = 0):
+    """Grid-to-particle, PIC/FLIP blend, forward Euler and clamp; returns new (pos, vel)."""
+    pos = _f64(pos).copy()
+    vel = _f64(vel).copy()
+    n = pos.shape[1]
+    un = [_f64(f) for f in unew]
+    uo = [_f64(f) for f in uold]
+    arr_n = (ctypes.c_void_p * 3)(*[f.ctypes.data for f in un])
+    arr_o = (ctypes.c_void_p * 3)(*[f.ctypes.data for f in uo])
+    _load().orc_g2p_advect(grid.c(), n, _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]),
+                           _ptr(vel[0]), _ptr(vel[1]), _ptr(vel[2]), arr_n, arr_o,
+                           float(flip_ratio), float(dt), int(flags))
+    return pos, vel
+
+
+@dataclass
+class Params:
+    grid: Grid
+    gravity: tuple = (0.0, -9.81, 0.0)
+    dt: float = 1.0 / 240.0
+    flip_ratio: float = 0.95
+    density: float = 1.0
+    tol: float = 1e-12
+    max_iters: int = 0  # 0 -> 20 * max(nx, ny, nz)
+    precond: int = PRECOND_MIC0
+    no_projection: bool = False
+    advect_particle_vel: bool = False
+
+    def iters_cap(self):
+        g = self.grid
+        return self.max_iters if self.max_iters > 0 else 20 * max(g.nx, g.ny, g.nz)
+
+
+@dataclass
+class StepResult:
+    key: np.ndarray
+    count: np.ndarray
+    start: np.ndarray
+    perm: np.ndarray
+    fluid: np.ndarray
+    pos_sorted: np.ndarray
+    vel_sorted: np.ndarray
+    ids: np.ndarray
+    u_old: list
+    u_star: list
+    b: np.ndarray
+    solve: SolveResult
+    u_new: list
+    pos: np.ndarray
+    vel: np.ndarray
+    extra: dict = field(default_factory=dict)
+
+
+def step(prm: Params, pos, vel, ids=None) -> StepResult:
+    """One FLIP timestep in FP64, stages in the order given in the module docstring."""
+    g = prm.grid
+    pos, vel = _f64(pos), _f64(vel)
+    n = pos.shape[1]
+    if ids is None:
+        ids = np.arange(n, dtype=np.uint32)
+    key, count, start, perm = bin_particles(g, pos)
+    pos_s = np.ascontiguousarray(pos[:, perm])
+    vel_s = np.ascontiguousarray(vel[:, perm])
+    ids_s = np.ascontiguousarray(np.asarray(ids)[perm])
+    fluid = fluid_flags(g, count)
+    u_old = p2g(g, pos_s, vel_s)
+    u_star = forces_walls(g, u_old, prm.gravity, prm.dt)
+    b = rhs(g, fluid, u_star, prm.density, prm.dt)
+    if prm.no_projection:
+        sol = SolveResult(np.zeros(g.ncells), STATUS_CONVERGED, 0, 0.0, float(np.max(np.abs(b), initial=0)))
+        u_new = [f.copy() for f in u_star]
+    else:
+        sol = pcg(g, fluid, b, prm.tol, prm.iters_cap(), prm.precond)
+        u_new = project(g, fluid, sol.p, prm.density, prm.dt, u_star)
+    flags = ADVECT_PARTICLE_VEL if prm.advect_particle_vel else 0
+    pos_n, vel_n = g2p_advect(g, pos_s, vel_s, u_new, u_old, prm.flip_ratio, prm.dt, flags)
+    return StepResult(key, count, start, perm, fluid, pos_s, vel_s, ids_s, u_old, u_star, b, sol,
+                      u_new, pos_n, vel_n)

@@ -1,0 +1,664 @@
+/*
+ * FP64 CPU oracle for one FLIP timestep (Centeno & Pereira, "Fluid Implicit
+ * Particle Simulation for CPU and GPU", arXiv 2404.01931).
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the slow, plain, obviously-correct
+ * reference that the GPU library is checked against. Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it. It shares
+ * no code, header, table or helper with the GPU library, and the GPU library
+ * never calls it.
+ *
+ * Every stage is a direct transcription of the definition it follows, in
+ * double precision, with no blocking, fusion or reordering:
+ *   seeding            paper Sec. 3.1.2 (jittered subcells, Fig. 3)
+ *   binning            paper Sec. 3.1.5 (raw cell index, sort, space hash,
+ *                      Fig. 4) and Sec. 3.2.2 (exclusive scan with identity)
+ *   particle-to-grid   paper Sec. 3.1.6, Eq. (4a), (4b) and the normalised
+ *                      weighted sum that follows them
+ *   forces / walls     paper Sec. 2.1.1 Eq. (1) (gravity), Sec. 3.1.7 (solid
+ *                      walls, free surface p = 0)
+ *   right-hand side    paper Sec. 3.1.7, Eq. (6) by central differences
+ *   operator           paper Sec. 3.1.7 (seven-point Laplacian, symmetric)
+ *   solve              paper Sec. 3.1.7 (PCG on the CPU); preconditioner
+ *                      MIC(0) as in Bridson's book (paper ref. [5]) or Jacobi
+ *   projection         paper Sec. 3.1.7, Eq. (5)
+ *   grid-to-particle   paper Sec. 3.1.8 (trilinear interpolation of the new
+ *                      field and of the change, PIC/FLIP blend)
+ *   advection / clamp  paper Sec. 3.1.3 (forward Euler, skin-width clamp)
+ *
+ * Readings of points the paper leaves open are stated where they are used.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "flip_oracle.h"
+
+/* ------------------------------------------------------------------------ */
+/* Indexing. Cells are flattened x-fastest (paper Sec. 3.1.1, Fig. 2).      */
+/* Face arrays of component a have one extra entry along axis a.            */
+/* ------------------------------------------------------------------------ */
+
+static int64_t n_cells(const orc_grid* g) { return (int64_t)g->nx * g->ny * g->nz; }
+
+static int64_t cell_index(const orc_grid* g, int i, int j, int k)
+{
+    return i + (int64_t)g->nx * (j + (int64_t)g->ny * k);
+}
+
+static void face_dims(const orc_grid* g, int a, int d[3])
+{
+    d[0] = g->nx + (a == 0);
+    d[1] = g->ny + (a == 1);
+    d[2] = g->nz + (a == 2);
+}
+
+static int64_t face_index(const int d[3], int i, int j, int k)
+{
+    return i + (int64_t)d[0] * (j + (int64_t)d[1] * k);
+}
+
+int64_t orc_face_count(const orc_grid* g, int a)
+{
+    int d[3];
+    face_dims(g, a, d);
+    return (int64_t)d[0] * d[1] * d[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Seeding (paper Sec. 3.1.2): a cell whose centre lies inside the fluid    */
+/* region gets sub^3 subcells, each with one particle at a uniformly random */
+/* point of the subcell. Random numbers: the SplitMix64 output sequence     */
+/* (Steele, Lea & Flood, OOPSLA 2014), element number `counter` of the      */
+/* sequence started at `seed`, top 53 bits scaled to [0, 1).                */
+/* ------------------------------------------------------------------------ */
+
+static uint64_t splitmix64_element(uint64_t seed, uint64_t counter)
+{
+    uint64_t z = seed + (counter + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double orc_uniform01(uint64_t seed, uint64_t counter)
+{
+    return (double)(splitmix64_element(seed, counter) >> 11) * 0x1.0p-53;
+}
+
+static int region_contains(const orc_region* r, const double x[3])
+{
+    if (r->kind == ORC_REGION_BOX) {
+        for (int a = 0; a < 3; ++a)
+            if (!(r->lo[a] <= x[a] && x[a] < r->hi[a])) return 0;
+        return 1;
+    }
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double d = x[a] - r->center[a];
+        d2 += d * d;
+    }
+    return d2 < r->radius * r->radius;
+}
+
+int64_t orc_seed(const orc_grid* g, const orc_region* regs, int nreg, int sub,
+                 uint64_t seed, double* px, double* py, double* pz,
+                 double* vx, double* vy, double* vz)
+{
+    int64_t n = 0;
+    const int64_t per_cell = (int64_t)sub * sub * sub;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                double centre[3] = {(i + 0.5) * g->dx, (j + 0.5) * g->dx, (k + 0.5) * g->dx};
+                const orc_region* hit = NULL;
+                for (int r = 0; r < nreg && !hit; ++r)
+                    if (region_contains(&regs[r], centre)) hit = &regs[r];
+                if (!hit) continue;
+                int64_t lin = cell_index(g, i, j, k);
+                for (int sz = 0; sz < sub; ++sz)
+                    for (int sy = 0; sy < sub; ++sy)
+                        for (int sx = 0; sx < sub; ++sx) {
+                            if (px) {
+                                int64_t s = sx + (int64_t)sub * (sy + (int64_t)sub * sz);
+                                uint64_t ctr = 3u * (uint64_t)(per_cell * lin + s);
+                                double xi = orc_uniform01(seed, ctr + 0);
+                                double yi = orc_uniform01(seed, ctr + 1);
+                                double zi = orc_uniform01(seed, ctr + 2);
+                                px[n] = ((sx + xi) / sub + i) * g->dx;
+                                py[n] = ((sy + yi) / sub + j) * g->dx;
+                                pz[n] = ((sz + zi) / sub + k) * g->dx;
+                                vx[n] = hit->vel[0];
+                                vy[n] = hit->vel[1];
+                                vz[n] = hit->vel[2];
+                            }
+                            ++n;
+                        }
+            }
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Binning (paper Sec. 3.1.5, Fig. 4; Sec. 3.2.2).                          */
+/* The raw cell index of a particle is the floor of the exact quotient      */
+/* x / dx on each axis (clamped into the grid). The floor is taken on the   */
+/* real number x / dx, not on its rounded value: the candidate q is         */
+/* corrected until q*dx <= x < (q+1)*dx, each comparison made exactly with  */
+/* a fused multiply-add whose sign equals the sign of the exact difference. */
+/* ------------------------------------------------------------------------ */
+
+static int exact_floor_div(double x, double dx, int n)
+{
+    double q = floor(x / dx);
+    while (fma(q, dx, -x) > 0.0) q -= 1.0;          /* q*dx > x     */
+    while (fma(q + 1.0, dx, -x) <= 0.0) q += 1.0;   /* (q+1)*dx <= x */
+    if (q < 0.0) q = 0.0;
+    if (q > n - 1) q = n - 1;
+    return (int)q;
+}
+
+void orc_cell_keys(const orc_grid* g, int64_t n, const double* px, const double* py,
+                   const double* pz, uint32_t* key)
+{
+    for (int64_t p = 0; p < n; ++p) {
+        int i = exact_floor_div(px[p], g->dx, g->nx);
+        int j = exact_floor_div(py[p], g->dx, g->ny);
+        int k = exact_floor_div(pz[p], g->dx, g->nz);
+        key[p] = (uint32_t)cell_index(g, i, j, k);
+    }
+}
+
+void orc_bin(const orc_grid* g, int64_t n, const double* px, const double* py,
+             const double* pz, uint32_t* key, uint32_t* count, uint32_t* start,
+             int64_t* perm)
+{
+    const int64_t C = n_cells(g);
+    orc_cell_keys(g, n, px, py, pz, key);
+    memset(count, 0, sizeof(uint32_t) * (size_t)C);
+    for (int64_t p = 0; p < n; ++p) count[key[p]]++;
+    /* all-prefix-sums with identity 0: start[c] = count[0] + ... + count[c-1] */
+    uint32_t run = 0;
+    for (int64_t c = 0; c < C; ++c) {
+        start[c] = run;
+        run += count[c];
+    }
+    /* stable counting sort: particles of one cell keep their current order */
+    uint32_t* fill = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)C);
+    memcpy(fill, start, sizeof(uint32_t) * (size_t)C);
+    for (int64_t p = 0; p < n; ++p) perm[fill[key[p]]++] = p;
+    free(fill);
+}
+
+void orc_fluid_flags(const orc_grid* g, const uint32_t* count, uint8_t* fluid)
+{
+    const int64_t C = n_cells(g);
+    for (int64_t c = 0; c < C; ++c) fluid[c] = count[c] > 0 ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle-to-grid (paper Sec. 3.1.6, Eq. (4)).                            */
+/* Face sample points: component a sits at the cell-centre offset (1/2)     */
+/* on the two other axes and at offset 0 on axis a (MAC grid, Sec. 3.1.1).  */
+/* For each face: q_f = sum_P q_P k(x_P - x_f) / sum_P k(x_P - x_f), with   */
+/* k the trilinear hat; a face no particle reaches gets 0.                  */
+/* The sums are accumulated particle by particle over the faces the         */
+/* particle reaches; addition order does not change the definition.         */
+/* ------------------------------------------------------------------------ */
+
+static double hat(double r)
+{
+    if (0.0 <= r && r <= 1.0) return 1.0 - r;
+    if (-1.0 <= r && r < 0.0) return 1.0 + r;
+    return 0.0;
+}
+
+static double face_coord(const orc_grid* g, int a, int axis, int idx)
+{
+    double off = (axis == a) ? 0.0 : 0.5;
+    return (idx + off) * g->dx;
+}
+
+void orc_p2g(const orc_grid* g, int a, int64_t n, const double* px, const double* py,
+             const double* pz, const double* vel, double* out, double* weight_out)
+{
+    int d[3];
+    face_dims(g, a, d);
+    const int64_t F = (int64_t)d[0] * d[1] * d[2];
+    double* W = (double*)calloc((size_t)F, sizeof(double));
+    double* M = (double*)calloc((size_t)F, sizeof(double));
+    for (int64_t p = 0; p < n; ++p) {
+        const double x[3] = {px[p], py[p], pz[p]};
+        int base[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            double off = (ax == a) ? 0.0 : 0.5;
+            base[ax] = (int)floor(x[ax] / g->dx - off);
+        }
+        /* the hat has support |r| < 1: only the two nearest sample planes on */
+        /* each axis can receive a non-zero weight                             */
+        for (int dk = 0; dk <= 1; ++dk)
+            for (int dj = 0; dj <= 1; ++dj)
+                for (int di = 0; di <= 1; ++di) {
+                    int fi = base[0] + di, fj = base[1] + dj, fk = base[2] + dk;
+                    if (fi < 0 || fi >= d[0] || fj < 0 || fj >= d[1] || fk < 0 || fk >= d[2])
+                        continue;
+                    double k = hat((x[0] - face_coord(g, a, 0, fi)) / g->dx) *
+                               hat((x[1] - face_coord(g, a, 1, fj)) / g->dx) *
+                               hat((x[2] - face_coord(g, a, 2, fk)) / g->dx);
+                    int64_t f = face_index(d, fi, fj, fk);
+                    W[f] += k;
+                    M[f] += vel[p] * k;
+                }
+    }
+    for (int64_t f = 0; f < F; ++f) {
+        out[f] = W[f] > 0.0 ? M[f] / W[f] : 0.0;
+        if (weight_out) weight_out[f] = W[f];
+    }
+    free(W);
+    free(M);
+}
+
+/* ------------------------------------------------------------------------ */
+/* External force and solid walls. Gravity is added to every face sample of */
+/* its component (force step of the splitting, paper Sec. 2.1.3); the       */
+/* normal velocity on the six domain faces is then set to zero (solid-wall  */
+/* condition, paper Sec. 3.1.7).                                            */
+/* ------------------------------------------------------------------------ */
+
+void orc_forces_walls(const orc_grid* g, int a, double accel, double dt, double* f_in_out)
+{
+    int d[3];
+    face_dims(g, a, d);
+    for (int k = 0; k < d[2]; ++k)
+        for (int j = 0; j < d[1]; ++j)
+            for (int i = 0; i < d[0]; ++i) {
+                int64_t f = face_index(d, i, j, k);
+                f_in_out[f] += accel * dt;
+                int idx = (a == 0) ? i : (a == 1) ? j : k;
+                int lim = (a == 0) ? g->nx : (a == 1) ? g->ny : g->nz;
+                if (idx == 0 || idx == lim) f_in_out[f] = 0.0;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete divergence by central differences (paper Eq. (6)), per cell:    */
+/* div_c = [(u_{i+1}-u_i) + (v_{j+1}-v_j) + (w_{k+1}-w_k)] / dx.            */
+/* ------------------------------------------------------------------------ */
+
+static double face_sum_difference(const orc_grid* g, const double* u, const double* v,
+                                  const double* w, int i, int j, int k)
+{
+    int du[3], dv[3], dw[3];
+    face_dims(g, 0, du);
+    face_dims(g, 1, dv);
+    face_dims(g, 2, dw);
+    return (u[face_index(du, i + 1, j, k)] - u[face_index(du, i, j, k)]) +
+           (v[face_index(dv, i, j + 1, k)] - v[face_index(dv, i, j, k)]) +
+           (w[face_index(dw, i, j, k + 1)] - w[face_index(dw, i, j, k)]);
+}
+
+void orc_divergence(const orc_grid* g, const double* u, const double* v, const double* w,
+                    double* div)
+{
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i)
+                div[cell_index(g, i, j, k)] = face_sum_difference(g, u, v, w, i, j, k) / g->dx;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Right-hand side of A p = b (paper Sec. 3.1.7). Multiplying the discrete  */
+/* Poisson equation by dx^2 rho / dt gives integer stencil coefficients and */
+/* b_c = -(rho dx / dt) * [sum of face differences] on fluid cells.         */
+/* ------------------------------------------------------------------------ */
+
+void orc_rhs(const orc_grid* g, const uint8_t* fluid, const double* u, const double* v,
+             const double* w, double density, double dt, double* b)
+{
+    const double scale = -density * g->dx / dt;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                int64_t c = cell_index(g, i, j, k);
+                b[c] = fluid[c] ? scale * face_sum_difference(g, u, v, w, i, j, k) : 0.0;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Seven-point operator (paper Sec. 3.1.7), restricted to fluid cells:      */
+/* (A p)_c = n_c p_c - sum over fluid neighbours p_nb, where n_c counts the */
+/* neighbours inside the domain (fluid or air; air carries p = 0, the free- */
+/* surface condition) and neighbours across a solid wall are left out.      */
+/* Non-fluid rows are zero.                                                 */
+/* ------------------------------------------------------------------------ */
+
+static const int NB[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+
+static int in_domain(const orc_grid* g, int i, int j, int k)
+{
+    return i >= 0 && i < g->nx && j >= 0 && j < g->ny && k >= 0 && k < g->nz;
+}
+
+static int neighbour_count(const orc_grid* g, int i, int j, int k)
+{
+    int n = 0;
+    for (int t = 0; t < 6; ++t) n += in_domain(g, i + NB[t][0], j + NB[t][1], k + NB[t][2]);
+    return n;
+}
+
+void orc_apply_A(const orc_grid* g, const uint8_t* fluid, const double* x, double* y)
+{
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                int64_t c = cell_index(g, i, j, k);
+                if (!fluid[c]) {
+                    y[c] = 0.0;
+                    continue;
+                }
+                double acc = neighbour_count(g, i, j, k) * x[c];
+                for (int t = 0; t < 6; ++t) {
+                    int ii = i + NB[t][0], jj = j + NB[t][1], kk = k + NB[t][2];
+                    if (!in_domain(g, ii, jj, kk)) continue;
+                    int64_t nb = cell_index(g, ii, jj, kk);
+                    if (fluid[nb]) acc -= x[nb];
+                }
+                y[c] = acc;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioners.                                                         */
+/* Jacobi: z = r / n_c.                                                     */
+/* MIC(0): modified incomplete Cholesky with zero fill-in, A ~ L L^T with   */
+/* L's sparsity that of A's lower triangle in x-fastest order. The diagonal */
+/* factor of each cell is built from its already-factored -x, -y, -z        */
+/* neighbours; the "modified" part adds tau times the fill-in that plain    */
+/* IC(0) would drop back onto the diagonal, and a pivot falling below      */
+/* sigma * n_c is replaced by n_c (tau = 0.97, sigma = 0.25, the values     */
+/* Bridson's book uses).                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* coupling of cell (i,j,k) to its +axis neighbour: -1 if both are fluid    */
+static double offdiag(const orc_grid* g, const uint8_t* fluid, int i, int j, int k, int axis)
+{
+    int ii = i + (axis == 0), jj = j + (axis == 1), kk = k + (axis == 2);
+    if (!in_domain(g, i, j, k) || !in_domain(g, ii, jj, kk)) return 0.0;
+    if (!fluid[cell_index(g, i, j, k)] || !fluid[cell_index(g, ii, jj, kk)]) return 0.0;
+    return -1.0;
+}
+
+static double precon_at(const orc_grid* g, const double* pc, int i, int j, int k)
+{
+    return in_domain(g, i, j, k) ? pc[cell_index(g, i, j, k)] : 0.0;
+}
+
+static void mic0_factor(const orc_grid* g, const uint8_t* fluid, double* pc)
+{
+    const double tau = 0.97, sigma = 0.25;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                int64_t c = cell_index(g, i, j, k);
+                pc[c] = 0.0;
+                if (!fluid[c]) continue;
+                double diag = neighbour_count(g, i, j, k);
+                double ax_m = offdiag(g, fluid, i - 1, j, k, 0);   /* (i-1) <-> i */
+                double ay_m = offdiag(g, fluid, i, j - 1, k, 1);
+                double az_m = offdiag(g, fluid, i, j, k - 1, 2);
+                double p_xm = precon_at(g, pc, i - 1, j, k);
+                double p_ym = precon_at(g, pc, i, j - 1, k);
+                double p_zm = precon_at(g, pc, i, j, k - 1);
+                double e = diag - (ax_m * p_xm) * (ax_m * p_xm) - (ay_m * p_ym) * (ay_m * p_ym) -
+                           (az_m * p_zm) * (az_m * p_zm);
+                double fill =
+                    ax_m * (offdiag(g, fluid, i - 1, j, k, 1) + offdiag(g, fluid, i - 1, j, k, 2)) * p_xm * p_xm +
+                    ay_m * (offdiag(g, fluid, i, j - 1, k, 0) + offdiag(g, fluid, i, j - 1, k, 2)) * p_ym * p_ym +
+                    az_m * (offdiag(g, fluid, i, j, k - 1, 0) + offdiag(g, fluid, i, j, k - 1, 1)) * p_zm * p_zm;
+                e -= tau * fill;
+                if (e < sigma * diag) e = diag;
+                pc[c] = 1.0 / sqrt(e);
+            }
+}
+
+static void mic0_apply(const orc_grid* g, const uint8_t* fluid, const double* pc,
+                       const double* r, double* tmp, double* z)
+{
+    /* solve L q = r (forward, increasing index) */
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                int64_t c = cell_index(g, i, j, k);
+                tmp[c] = 0.0;
+                if (!fluid[c]) continue;
+                double t = r[c];
+                if (i > 0) t -= offdiag(g, fluid, i - 1, j, k, 0) * pc[cell_index(g, i - 1, j, k)] * tmp[cell_index(g, i - 1, j, k)];
+                if (j > 0) t -= offdiag(g, fluid, i, j - 1, k, 1) * pc[cell_index(g, i, j - 1, k)] * tmp[cell_index(g, i, j - 1, k)];
+                if (k > 0) t -= offdiag(g, fluid, i, j, k - 1, 2) * pc[cell_index(g, i, j, k - 1)] * tmp[cell_index(g, i, j, k - 1)];
+                tmp[c] = t * pc[c];
+            }
+    /* solve L^T z = q (backward, decreasing index) */
+    for (int k = g->nz - 1; k >= 0; --k)
+        for (int j = g->ny - 1; j >= 0; --j)
+            for (int i = g->nx - 1; i >= 0; --i) {
+                int64_t c = cell_index(g, i, j, k);
+                z[c] = 0.0;
+                if (!fluid[c]) continue;
+                double t = tmp[c];
+                if (i + 1 < g->nx) t -= offdiag(g, fluid, i, j, k, 0) * pc[c] * z[cell_index(g, i + 1, j, k)];
+                if (j + 1 < g->ny) t -= offdiag(g, fluid, i, j, k, 1) * pc[c] * z[cell_index(g, i, j + 1, k)];
+                if (k + 1 < g->nz) t -= offdiag(g, fluid, i, j, k, 2) * pc[c] * z[cell_index(g, i, j, k + 1)];
+                z[c] = t * pc[c];
+            }
+}
+
+static void jacobi_apply(const orc_grid* g, const uint8_t* fluid, const double* r, double* z)
+{
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                int64_t c = cell_index(g, i, j, k);
+                z[c] = fluid[c] ? r[c] / neighbour_count(g, i, j, k) : 0.0;
+            }
+}
+
+static double dot_fluid(int64_t C, const uint8_t* fluid, const double* a, const double* b)
+{
+    double s = 0.0;
+    for (int64_t c = 0; c < C; ++c)
+        if (fluid[c]) s += a[c] * b[c];
+    return s;
+}
+
+static double maxabs_fluid(int64_t C, const uint8_t* fluid, const double* a)
+{
+    double m = 0.0;
+    for (int64_t c = 0; c < C; ++c)
+        if (fluid[c] && fabs(a[c]) > m) m = fabs(a[c]);
+    return m;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioned conjugate gradient (paper Sec. 3.1.7, CPU solver).        */
+/* Starts from p = 0. Stops when max|r| <= tol * max|b| over fluid cells    */
+/* (r the recursively updated residual). Returns 0 on convergence, 1 when   */
+/* max_iters is reached first, 2 on a breakdown (non-positive or non-finite */
+/* curvature).                                                              */
+/* ------------------------------------------------------------------------ */
+
+int orc_pcg(const orc_grid* g, const uint8_t* fluid, const double* b, double* p, double tol,
+            int max_iters, int precond, int* iters_out, double* max_r_out, double* max_b_out)
+{
+    const int64_t C = n_cells(g);
+    double* r = (double*)malloc(sizeof(double) * (size_t)C);
+    double* z = (double*)malloc(sizeof(double) * (size_t)C);
+    double* s = (double*)malloc(sizeof(double) * (size_t)C);
+    double* q = (double*)malloc(sizeof(double) * (size_t)C);
+    double* tmp = (double*)malloc(sizeof(double) * (size_t)C);
+    double* pc = NULL;
+    int status = 1, it = 0;
+
+    for (int64_t c = 0; c < C; ++c) {
+        p[c] = 0.0;
+        r[c] = fluid[c] ? b[c] : 0.0;
+    }
+    double max_b = maxabs_fluid(C, fluid, r);
+    double max_r = max_b;
+    if (max_b == 0.0) {
+        status = 0;
+        goto done;
+    }
+    if (precond == ORC_PRECOND_MIC0) {
+        pc = (double*)malloc(sizeof(double) * (size_t)C);
+        mic0_factor(g, fluid, pc);
+        mic0_apply(g, fluid, pc, r, tmp, z);
+    } else {
+        jacobi_apply(g, fluid, r, z);
+    }
+    memcpy(s, z, sizeof(double) * (size_t)C);
+    double rho = dot_fluid(C, fluid, r, z);
+    for (it = 1; it <= max_iters; ++it) {
+        orc_apply_A(g, fluid, s, q);
+        double sq = dot_fluid(C, fluid, s, q);
+        if (!(sq > 0.0) || !isfinite(sq)) {
+            status = 2;
+            break;
+        }
+        double alpha = rho / sq;
+        for (int64_t c = 0; c < C; ++c) {
+            if (!fluid[c]) continue;
+            p[c] += alpha * s[c];
+            r[c] -= alpha * q[c];
+        }
+        max_r = maxabs_fluid(C, fluid, r);
+        if (max_r <= tol * max_b) {
+            status = 0;
+            break;
+        }
+        if (precond == ORC_PRECOND_MIC0)
+            mic0_apply(g, fluid, pc, r, tmp, z);
+        else
+            jacobi_apply(g, fluid, r, z);
+        double rho_new = dot_fluid(C, fluid, r, z);
+        double beta = rho_new / rho;
+        rho = rho_new;
+        for (int64_t c = 0; c < C; ++c) s[c] = fluid[c] ? z[c] + beta * s[c] : 0.0;
+    }
+    if (it > max_iters) it = max_iters;
+done:
+    if (iters_out) *iters_out = it;
+    if (max_r_out) *max_r_out = max_r;
+    if (max_b_out) *max_b_out = max_b;
+    free(r);
+    free(z);
+    free(s);
+    free(q);
+    free(tmp);
+    free(pc);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Projection (paper Sec. 3.1.7, Eq. (5)): every face that is not a domain  */
+/* wall and touches at least one fluid cell gets                            */
+/*   u_f = u*_f - (dt / rho) (p_plus - p_minus) / dx,                       */
+/* with p = 0 in air cells (free surface). Wall faces and faces between two */
+/* air cells keep u*.                                                       */
+/* ------------------------------------------------------------------------ */
+
+void orc_project(const orc_grid* g, int a, const uint8_t* fluid, const double* p, double density,
+                 double dt, const double* star, double* out)
+{
+    int d[3];
+    face_dims(g, a, d);
+    const double scale = dt / (density * g->dx);
+    for (int k = 0; k < d[2]; ++k)
+        for (int j = 0; j < d[1]; ++j)
+            for (int i = 0; i < d[0]; ++i) {
+                int64_t f = face_index(d, i, j, k);
+                out[f] = star[f];
+                int idx = (a == 0) ? i : (a == 1) ? j : k;
+                int lim = (a == 0) ? g->nx : (a == 1) ? g->ny : g->nz;
+                if (idx == 0 || idx == lim) continue;
+                int64_t cp = cell_index(g, i, j, k);
+                int64_t cm = cell_index(g, i - (a == 0), j - (a == 1), k - (a == 2));
+                if (!fluid[cp] && !fluid[cm]) continue;
+                double pp = fluid[cp] ? p[cp] : 0.0;
+                double pm = fluid[cm] ? p[cm] : 0.0;
+                out[f] = star[f] - scale * (pp - pm);
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid-to-particle and advection (paper Sec. 3.1.8 and Sec. 3.1.3).        */
+/* Trilinear interpolation of a face field at a particle: the eight sample  */
+/* points around it, indices clamped to the valid range at the domain edge, */
+/* blended by nested linear interpolations a + t (b - a) along x, y, z.     */
+/* PIC = interp(u_new); change = interp(u_new - u_old); FLIP = v + change;  */
+/* v <- PIC + alpha (FLIP - PIC). Forward Euler moves the particle with the */
+/* grid velocity PIC (or with the blended velocity when the flag asks for   */
+/* it), then each coordinate is clamped into [s, L - s] with s = dx/1000.   */
+/* ------------------------------------------------------------------------ */
+
+static double lerp(double a, double b, double t) { return a + t * (b - a); }
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+double orc_interp(const orc_grid* g, int a, const double* f, double x, double y, double z)
+{
+    int d[3];
+    face_dims(g, a, d);
+    const double pos[3] = {x, y, z};
+    int i0[3], i1[3];
+    double t[3];
+    for (int ax = 0; ax < 3; ++ax) {
+        double gc = pos[ax] / g->dx - ((ax == a) ? 0.0 : 0.5);
+        double fl = floor(gc);
+        t[ax] = gc - fl;
+        i0[ax] = clampi((int)fl, 0, d[ax] - 1);
+        i1[ax] = clampi((int)fl + 1, 0, d[ax] - 1);
+    }
+#define F(I, J, K) f[face_index(d, (I), (J), (K))]
+    double c00 = lerp(F(i0[0], i0[1], i0[2]), F(i1[0], i0[1], i0[2]), t[0]);
+    double c10 = lerp(F(i0[0], i1[1], i0[2]), F(i1[0], i1[1], i0[2]), t[0]);
+    double c01 = lerp(F(i0[0], i0[1], i1[2]), F(i1[0], i0[1], i1[2]), t[0]);
+    double c11 = lerp(F(i0[0], i1[1], i1[2]), F(i1[0], i1[1], i1[2]), t[0]);
+#undef F
+    double c0 = lerp(c00, c10, t[1]);
+    double c1 = lerp(c01, c11, t[1]);
+    return lerp(c0, c1, t[2]);
+}
+
+void orc_g2p_advect(const orc_grid* g, int64_t n, double* px, double* py, double* pz,
+                    double* vx, double* vy, double* vz, const double* const unew[3],
+                    const double* const uold[3], double flip_ratio, double dt, unsigned flags)
+{
+    double* delta[3];
+    for (int a = 0; a < 3; ++a) {
+        int64_t F = orc_face_count(g, a);
+        delta[a] = (double*)malloc(sizeof(double) * (size_t)F);
+        for (int64_t f = 0; f < F; ++f) delta[a][f] = unew[a][f] - uold[a][f];
+    }
+    const double skin = 1e-3 * g->dx;
+    const double L[3] = {g->nx * g->dx, g->ny * g->dx, g->nz * g->dx};
+    for (int64_t p = 0; p < n; ++p) {
+        double* pos[3] = {&px[p], &py[p], &pz[p]};
+        double* vel[3] = {&vx[p], &vy[p], &vz[p]};
+        double pic[3], vnew[3];
+        for (int a = 0; a < 3; ++a) {
+            pic[a] = orc_interp(g, a, unew[a], px[p], py[p], pz[p]);
+            double change = orc_interp(g, a, delta[a], px[p], py[p], pz[p]);
+            double flip = *vel[a] + change;
+            vnew[a] = pic[a] + flip_ratio * (flip - pic[a]);
+        }
+        for (int a = 0; a < 3; ++a) {
+            double adv = (flags & ORC_ADVECT_PARTICLE_VEL) ? vnew[a] : pic[a];
+            double x = *pos[a] + dt * adv;
+            if (x < skin) x = skin;
+            if (x > L[a] - skin) x = L[a] - skin;
+            *pos[a] = x;
+            *vel[a] = vnew[a];
+        }
+    }
+    for (int a = 0; a < 3; ++a) free(delta[a]);
+}

@@ -1,0 +1,404 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests re-types the oracle's own formula: each checks it against
+a closed form, a textbook/library routine, a published test vector, an exact
+special case, or a brute-force evaluation of the paper's definition on a tiny
+input. Each pin is chosen so a plausible slip in the oracle (a dropped term,
+a wrong sign, offset or index, a transposed operand) fails it.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_01931_amd import inputs
+from tests.scenes_util import oracle_grid, oracle_params, oracle_regions
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# Seeding (paper Sec. 3.1.2, Fig. 3)
+# --------------------------------------------------------------------------
+
+def test_seed_generator_matches_published_splitmix64(orc):
+    with open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt")) as f:
+        vals = [int(l) for l in f.read().split("\n") if l.strip() and not l.startswith("#")]
+    assert len(vals) == 5
+    for c, v in enumerate(vals):
+        assert orc.uniform01(1234567, c) == (v >> 11) * 2.0 ** -53
+
+
+def _centres_inside(sc):
+    """Vectorised centre test over all cells, written independently of the C loop."""
+    n = sc.n
+    c = (np.arange(n) + 0.5) * sc.dx
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    inside = np.zeros((n, n, n), bool)
+    for r in sc.regions:
+        if r.kind == "box":
+            m = np.ones_like(inside)
+            for a, q in enumerate((x, y, z)):
+                m &= (r.lo[a] <= q) & (q < r.hi[a])
+        else:
+            m = (x - r.center[0]) ** 2 + (y - r.center[1]) ** 2 + (z - r.center[2]) ** 2 < r.radius ** 2
+        inside |= m
+    return inside
+
+
+@pytest.mark.parametrize("name,expected", [("dam32", 65536), ("drop64", 652192)])
+def test_seed_counts_and_subcell_coverage(orc, name, expected):
+    sc = inputs.scene(name)
+    g = oracle_grid(sc)
+    pos, vel = orc.seed(g, oracle_regions(sc), sc.sub, sc.seed)
+    inside = _centres_inside(sc)
+    n = pos.shape[1]
+    # rho = 2 gives eight subcells per fluid cell, one particle in each (Fig. 3)
+    assert n == 8 * int(inside.sum()) == expected
+    sub = np.floor(pos / (sc.dx / 2)).astype(np.int64)  # subcell coordinates
+    cell = sub // 2
+    lin = cell[0] + sc.n * (cell[1] + sc.n * cell[2])
+    assert np.array_equal(np.unique(lin), np.flatnonzero(inside.reshape(-1)))
+    sid = (sub[0] % 2) + 2 * ((sub[1] % 2) + 2 * (sub[2] % 2))
+    pair = lin * 8 + sid
+    assert np.unique(pair).size == n  # every subcell holds exactly one particle
+    if name == "drop64":
+        in_sphere = np.sum((pos - np.array([[0.5], [0.7], [0.5]])) ** 2, axis=0) < 0.2 ** 2
+        assert np.all(vel[1][in_sphere & (pos[1] > 0.45)] == -1.0)
+        assert np.all(vel[:, pos[1] < 0.3] == 0.0)
+
+
+# --------------------------------------------------------------------------
+# Binning (paper Sec. 3.1.5, Sec. 3.2.2)
+# --------------------------------------------------------------------------
+
+def _exact_keys(pos, shape, dx):
+    out = []
+    fdx = Fraction(dx)
+    for p in range(pos.shape[1]):
+        idx = []
+        for a in range(3):
+            q = math.floor(Fraction(float(pos[a, p])) / fdx)
+            idx.append(min(max(q, 0), shape[a] - 1))
+        out.append(idx[0] + shape[0] * (idx[1] + shape[1] * idx[2]))
+    return np.array(out, np.uint32)
+
+
+@pytest.mark.parametrize("shape,dx", [((7, 5, 6), 1 / 6), ((48, 48, 48), 1 / 48), ((4, 4, 4), 0.25)])
+def test_binning_is_exact_floor_and_stable_counting_sort(orc, shape, dx):
+    rng = np.random.default_rng(11)
+    g = O.Grid(*shape, dx)
+    L = np.array(shape) * dx
+    n = 3000
+    pos = rng.random((3, n)) * L[:, None]
+    # particles exactly on, just below and just above cell planes (dx non-dyadic for 1/6, 1/48)
+    m = rng.integers(0, min(shape), size=(3, 600))
+    on = m * dx
+    pos[:, :600] = on
+    pos[:, 600:1200] = np.nextafter(on, -np.inf)
+    pos[:, 1200:1800] = np.nextafter(on, np.inf)
+    pos = np.clip(pos, 0.0, L[:, None])
+    pos[:, 1800:2400] = pos[:, :600][:, rng.permutation(600)]  # duplicates -> ties
+    key, count, start, perm = orc.bin_particles(g, pos)
+    assert np.array_equal(key, _exact_keys(pos, shape, dx))
+    assert np.array_equal(perm, np.argsort(key, kind="stable"))
+    C = g.ncells
+    assert np.array_equal(count, np.bincount(key, minlength=C).astype(np.uint32))
+    # scan with identity: [I, a0, a0+a1, ...] (Sec. 3.2.2)
+    assert start[0] == 0
+    assert np.array_equal(start[1:], np.cumsum(count, dtype=np.uint64)[:-1].astype(np.uint32))
+    assert int(count.sum()) == n
+
+
+# --------------------------------------------------------------------------
+# Particle-to-grid (paper Sec. 3.1.6, Eq. (4))
+# --------------------------------------------------------------------------
+
+def _hat(r):
+    # Eq. (4b), case by case
+    if 0 <= r <= 1:
+        return 1 - r
+    if -1 <= r < 0:
+        return 1 + r
+    return 0.0
+
+
+def _brute_p2g(shape, dx, pos, vel, a):
+    nx, ny, nz = shape
+    d = [nx, ny, nz]
+    d[a] += 1
+    out = np.zeros(d[0] * d[1] * d[2])
+    for k in range(d[2]):
+        for j in range(d[1]):
+            for i in range(d[0]):
+                xf = [(i + (0 if a == 0 else 0.5)) * dx, (j + (0 if a == 1 else 0.5)) * dx,
+                      (k + (0 if a == 2 else 0.5)) * dx]
+                num = den = 0.0
+                for p in range(pos.shape[1]):
+                    kk = (_hat((pos[0, p] - xf[0]) / dx) * _hat((pos[1, p] - xf[1]) / dx)
+                          * _hat((pos[2, p] - xf[2]) / dx))
+                    num += vel[a, p] * kk
+                    den += kk
+                out[i + d[0] * (j + d[1] * k)] = num / den if den > 0 else 0.0
+    return out
+
+
+def test_p2g_matches_brute_force_definition(orc):
+    shape, dx = (4, 3, 5), 0.25
+    g = O.Grid(*shape, dx)
+    rng = np.random.default_rng(5)
+    L = np.array(shape) * dx
+    pos = rng.random((3, 25)) * L[:, None]
+    vel = rng.standard_normal((3, 25))
+    got = orc.p2g(g, pos, vel)
+    for a in range(3):
+        np.testing.assert_allclose(got[a], _brute_p2g(shape, dx, pos, vel, a), rtol=1e-13, atol=1e-14)
+
+
+def test_hat_weights_partition_of_unity_and_node_values(orc):
+    g = O.Grid(6, 6, 6, 1 / 6)
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        p = (1.2 + 3.5 * rng.random((3, 1))) / 6
+        _, w = orc.p2g(g, p, np.ones((3, 1)), return_weights=True)
+        for a in range(3):
+            assert abs(w[a].sum() - 1.0) < 1e-14
+            assert (w[a] > 0).sum() <= 8
+    # a particle sitting exactly on a u sample point: h(0) = 1 there, h(+-1) = 0 elsewhere
+    # (dyadic spacing so that the sample point is exactly representable)
+    g8 = O.Grid(8, 8, 8, 1 / 8)
+    p = np.array([[2 / 8], [2.5 / 8], [3.5 / 8]])
+    _, w = orc.p2g(g8, p, np.ones((3, 1)), return_weights=True)
+    nz = np.flatnonzero(w[0])
+    assert nz.tolist() == [2 + 9 * (2 + 8 * 3)] and w[0][nz[0]] == 1.0
+
+
+def test_uniform_dyadic_velocity_round_trip_is_bit_exact(orc):
+    g = O.Grid(16, 16, 16, 1 / 16)
+    pos, _ = inputs.random_particles((16, 16, 16), 4000, seed=3, lo=(4 / 16,) * 3, hi=(12 / 16,) * 3)
+    U = np.array([0.5, -2.0, 0.25])
+    vel = np.repeat(U[:, None], pos.shape[1], axis=1)
+    faces, w = orc.p2g(g, pos, vel, return_weights=True)
+    for a in range(3):
+        assert np.all(faces[a][w[a] > 0] == U[a])
+        assert np.all(faces[a][w[a] == 0] == 0.0)
+    dt = 1 / 240
+    pos_n, vel_n = orc.g2p_advect(g, pos, vel, faces, faces, 0.95, dt)
+    assert np.array_equal(vel_n, vel)
+    assert np.array_equal(pos_n, pos + dt * U[:, None])
+
+
+# --------------------------------------------------------------------------
+# Grid-to-particle (paper Sec. 3.1.8)
+# --------------------------------------------------------------------------
+
+def test_interpolation_reproduces_trilinear_fields(orc):
+    shape, dx = (8, 6, 7), 0.125
+    g = O.Grid(*shape, dx)
+    rng = np.random.default_rng(9)
+    coef = rng.standard_normal((3, 8))
+
+    def field(a, x, y, z):
+        c = coef[a]
+        return c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * y * z + c[6] * x * z + c[7] * x * y * z
+
+    for a in range(3):
+        d = [shape[0], shape[1], shape[2]]
+        d[a] += 1
+        k, j, i = np.meshgrid(np.arange(d[2]), np.arange(d[1]), np.arange(d[0]), indexing="ij")
+        off = [0.5, 0.5, 0.5]
+        off[a] = 0.0
+        f = field(a, (i + off[0]) * dx, (j + off[1]) * dx, (k + off[2]) * dx).reshape(-1)
+        for _ in range(50):
+            p = (1.0 + (np.array(shape) - 2.0) * rng.random(3)) * dx
+            assert abs(orc.interp(g, a, f, *p) - field(a, *p)) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# Operator and solve (paper Sec. 3.1.7)
+# --------------------------------------------------------------------------
+
+def _probe(orc, g, fluid):
+    idx = np.flatnonzero(fluid)
+    A = np.zeros((idx.size, idx.size))
+    for col, c in enumerate(idx):
+        e = np.zeros(g.ncells)
+        e[c] = 1.0
+        A[:, col] = orc.apply_A(g, fluid, e)[idx]
+    return A, idx
+
+
+def _random_mask(rng, g, frac=0.6):
+    fluid = (rng.random(g.ncells) < frac).astype(np.uint8)
+    fluid[rng.integers(0, g.ncells)] = 0  # at least one air cell
+    return fluid
+
+
+def test_operator_symmetric_positive_definite_and_kills_constants(orc):
+    rng = np.random.default_rng(4)
+    g = O.Grid(5, 4, 6, 0.2)
+    for _ in range(5):
+        fluid = _random_mask(rng, g)
+        A, idx = _probe(orc, g, fluid)
+        assert np.array_equal(A, A.T)
+        np.linalg.cholesky(A)  # raises unless SPD
+    # an all-fluid box with one air cell: the Laplacian annihilates constants
+    # in every row whose cell does not touch the air cell
+    fluid = np.ones(g.ncells, np.uint8)
+    air = 2 + 5 * (1 + 4 * 3)
+    fluid[air] = 0
+    y = orc.apply_A(g, fluid, np.ones(g.ncells))
+    i, j, k = 2, 1, 3
+    touching = {air + s for s in (1, -1, 5, -5, 20, -20)}
+    for c in range(g.ncells):
+        if fluid[c] and c not in touching:
+            assert y[c] == 0.0
+        if fluid[c] and c in touching:
+            assert y[c] == 1.0
+
+
+@pytest.mark.parametrize("precond", [O.PRECOND_MIC0, O.PRECOND_JACOBI])
+def test_pcg_matches_dense_direct_solve(orc, precond):
+    rng = np.random.default_rng(7 + precond)
+    for n in (4, 6, 8):
+        g = O.Grid(n, n, n, 1.0 / n)
+        fluid = _random_mask(rng, g, 0.55)
+        b = rng.standard_normal(g.ncells) * fluid
+        A, idx = _probe(orc, g, fluid)
+        ref = np.linalg.solve(A, b[idx])
+        res = orc.pcg(g, fluid, b, 1e-13, 10000, precond)
+        assert res.status == O.STATUS_CONVERGED
+        np.testing.assert_allclose(res.p[idx], ref, rtol=0, atol=1e-9 * np.abs(ref).max())
+        assert np.all(res.p[fluid == 0] == 0.0)
+
+
+def test_mic0_converges_in_fewer_iterations_than_jacobi(orc):
+    n = 24
+    g = O.Grid(n, n, n, 1.0 / n)
+    fluid = np.zeros((n, n, n), np.uint8)
+    fluid[: n // 2] = 1
+    b = np.random.default_rng(1).standard_normal(g.ncells) * fluid.reshape(-1)
+    fl = fluid.reshape(-1)
+    mic = orc.pcg(g, fl, b, 1e-8, 5000, O.PRECOND_MIC0)
+    jac = orc.pcg(g, fl, b, 1e-8, 5000, O.PRECOND_JACOBI)
+    assert mic.status == jac.status == O.STATUS_CONVERGED
+    assert mic.iterations < jac.iterations
+
+
+def _mms_error(orc, n):
+    g = O.Grid(n, n, n, 1.0 / n)
+    dx = g.dx
+    c = (np.arange(n) + 0.5) * dx
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    fluid = (np.arange(n)[None, :, None] < n // 2) * np.ones((n, n, n), np.uint8)
+    ys = (n // 2 + 0.5) * dx  # centre of the first air row: p = 0 there
+    p_ex = np.cos(np.pi * x) * np.cos(np.pi * z) * np.cos(np.pi * y / (2 * ys))
+    # -lap p = pi^2 (2 + 1/(4 ys^2)) p ; the integer stencil carries a factor dx^2
+    b = dx * dx * np.pi ** 2 * (2 + 1 / (4 * ys * ys)) * p_ex * fluid
+    res = orc.pcg(g, fluid.reshape(-1), b.reshape(-1), 1e-12, 20000, O.PRECOND_MIC0)
+    assert res.status == O.STATUS_CONVERGED
+    m = fluid.reshape(-1) == 1
+    return np.abs(res.p - p_ex.reshape(-1))[m].max()
+
+
+def test_poisson_discretisation_is_second_order(orc):
+    errs = [_mms_error(orc, n) for n in (16, 32, 64)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(1.9 < o < 2.1 for o in orders), (errs, orders)
+
+
+# --------------------------------------------------------------------------
+# Whole step: closed forms and invariants
+# --------------------------------------------------------------------------
+
+def test_hydrostatic_pool_is_at_rest(orc):
+    n, J = 16, 6
+    sc = inputs.Scene(name="pool", n=n, regions=(inputs.RegionSpec("box", hi=(9, J / n, 9)),), seed=9,
+                      precision="fp64", dt=1 / 240, flip_ratio=0.95, tol=1e-12, steps=1)
+    g = oracle_grid(sc)
+    pos, vel = orc.seed(g, oracle_regions(sc), 2, sc.seed)
+    r = orc.step(oracle_params(sc), pos, vel)
+    assert r.solve.status == O.STATUS_CONVERGED
+    jj = (np.arange(g.ncells) // n) % n
+    fl = r.fluid == 1
+    assert np.array_equal(fl, jj < J)
+    expected = 1.0 * 9.81 * g.dx * (J - jj)
+    np.testing.assert_allclose(r.solve.p[fl], expected[fl], rtol=1e-9)
+    # velocities on faces touching fluid vanish; the particles do not move
+    for a in range(3):
+        assert np.abs(r.u_new[a]).reshape(g.face_shape(a))[:, : J + 1 if a == 1 else J].max() < 1e-10
+    assert np.abs(r.vel).max() < 1e-10
+    skin = 1e-3 * g.dx  # seeded particles closer to a wall than the skin width are pushed out
+    assert np.abs(r.pos - np.clip(r.pos_sorted, skin, 1.0 - skin)).max() < 1e-12
+
+
+@pytest.mark.parametrize("gy,dt", [(-8.0, 1 / 256), (-9.81, 1 / 240)])
+def test_ballistic_blob_closed_form(orc, gy, dt):
+    n = 32
+    v0 = (0.5, 0.25, -0.5)
+    sc = inputs.Scene(name="blob", n=n, regions=(inputs.RegionSpec("sphere", center=(0.5, 0.5, 0.5),
+                                                                   radius=0.15, vel=v0),),
+                      seed=4, precision="fp64", dt=dt, flip_ratio=0.95, tol=1e-10, steps=4,
+                      gravity=(0.0, gy, 0.0))
+    g = oracle_grid(sc)
+    pos0, vel = orc.seed(g, oracle_regions(sc), 2, sc.seed)
+    pos, ids = pos0.copy(), np.arange(pos0.shape[1], dtype=np.uint32)
+    prm = oracle_params(sc)
+    steps = 4
+    for s in range(steps):
+        r = orc.step(prm, pos, vel, ids)
+        if s == 0:
+            # power-of-two velocities are transferred exactly, so the first
+            # right-hand side vanishes identically and the solve is skipped
+            assert r.solve.max_b == 0.0 and r.solve.iterations == 0
+        else:
+            # later velocities are not powers of two: only rounding is left
+            assert r.solve.max_b < 1e-9
+        pos, vel, ids = r.pos, r.vel, r.ids
+    gvec = np.array([0.0, gy, 0.0])
+    v_exp = np.array(v0) + steps * gvec * dt
+    np.testing.assert_allclose(vel, np.repeat(v_exp[:, None], vel.shape[1], 1), rtol=0, atol=1e-13)
+    # semi-implicit Euler: x_n = x_0 + n dt v0 + g dt^2 n (n + 1) / 2
+    shift = steps * dt * np.array(v0) + gvec * dt * dt * steps * (steps + 1) / 2
+    np.testing.assert_allclose(pos, pos0[:, ids] + shift[:, None], rtol=0, atol=1e-13)
+
+
+def test_projection_leaves_divergence_equal_to_scaled_residual(orc):
+    sc = inputs.Scene(name="dam16", n=16, regions=(inputs.RegionSpec("box", hi=(0.5, 0.5, 9)),), seed=2,
+                      precision="fp64", dt=1 / 240, flip_ratio=0.95, tol=1e-6, steps=1)
+    g = oracle_grid(sc)
+    pos, vel = orc.seed(g, oracle_regions(sc), 2, sc.seed)
+    vel = vel + np.random.default_rng(3).standard_normal(vel.shape)  # a divergent start
+    r = orc.step(oracle_params(sc), pos, vel)
+    fl = r.fluid == 1
+    r_true = r.b - orc.apply_A(g, r.fluid, r.solve.p)
+    div_new = orc.divergence(g, r.u_new)
+    div_star = orc.divergence(g, r.u_star)
+    # Eq. (5) applied to Eq. (6): div(u_new) = -(dt / (rho dx^2)) (b - A p) on fluid cells
+    scale = sc.dt / (sc.density * g.dx * g.dx)
+    np.testing.assert_allclose(div_new[fl], -scale * r_true[fl], rtol=0,
+                               atol=1e-9 * np.abs(div_star[fl]).max())
+    np.testing.assert_allclose(div_star[fl], -scale * r.b[fl], rtol=1e-12, atol=0)
+    ratio = np.abs(div_new[fl]).max() / np.abs(div_star[fl]).max()
+    assert ratio <= 1.0001e-6
+
+
+def test_particle_count_ids_and_bounds_are_conserved(orc):
+    sc = inputs.Scene(name="dam16", n=16, regions=(inputs.RegionSpec("box", hi=(0.5, 0.5, 9)),), seed=2,
+                      precision="fp64", dt=1 / 120, flip_ratio=0.95, tol=1e-6, steps=8)
+    g = oracle_grid(sc)
+    pos, vel = orc.seed(g, oracle_regions(sc), 2, sc.seed)
+    n = pos.shape[1]
+    ids = np.arange(n, dtype=np.uint32)
+    prm = oracle_params(sc)
+    skin = 1e-3 * g.dx
+    for _ in range(sc.steps):
+        r = orc.step(prm, pos, vel, ids)
+        pos, vel, ids = r.pos, r.vel, r.ids
+        assert pos.shape[1] == n
+        assert np.array_equal(np.sort(ids), np.arange(n, dtype=np.uint32))
+        assert pos.min() >= skin and pos.max() <= 1.0 - skin
+        assert r.solve.status == O.STATUS_CONVERGED
