@@ -1,0 +1,215 @@
+"""Benchmark: FLIP timestep throughput on one MI355X.
+
+Workload: the 256^3 drop-into-pool scene (pool y < 0.3 plus a sphere of radius
+0.15 at (0.5, 0.7, 0.5) falling at 1 m/s; 8 jittered particles per fluid cell,
+42,266,944 particles; FP32; dt = 1/960; FLIP ratio 0.97; PCG tolerance 1e-6).
+Inputs are synthetic and seeded and already resident in HBM when timing starts.
+
+A step is one full pass of the hot path (binning, particle-to-grid, forces and
+walls, right-hand side, PCG solve, projection, grid-to-particle and advection).
+Prints ONE JSON line with particle-steps/s, the roofline figures of the
+dominant kernel (algorithmic bytes per launch over its HIP-event-timed average
+duration), and the FP64 oracle timed on the host as a CPU baseline.
+
+Usage: python bench.py [--gpus 1] [--steps 30] [--warmup 3] [--scene drop256]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kind: str, rb: int, n: int, cells: int, faces: list, fluid: float) -> float:
+    """Bytes the method must move per launch of each kernel (no cache re-reads).
+
+    rb: bytes of the real type; n: particles; cells: grid cells; faces: face
+    counts per component; fluid: fluid cells of the solve.
+    """
+    F = sum(faces)
+    return {
+        "bin_keys": n * (3 * rb + 8) + 12 * cells,     # positions in; key, rank out; count fill + RMW
+        "bin_scan": 8 * cells,                          # counts in, starts out
+        "bin_scatter": 16 * n,                          # key, rank, start in; slot out
+        "bin_gather": n * (12 * rb + 20),               # slot, key, start, count, state in; state out
+        "tiles": 4 * cells,                             # counts in
+        "p2g": n * 4 * rb + 8 * cells + 2 * rb * F / 3,  # one component: particles, hash in; 2 faces out
+        "rhs": 3 * rb * F / 3 + fluid * (1 + 5 * rb),   # face differences in; diag, b, z, x, s out
+        "pcg_direction": fluid * (3 * rb + 1),          # z, s_old, diag in; s out
+        "pcg_update": fluid * (5 * rb + 1),             # x, s, z, diag in; x, z out
+        "project": 2 * rb * F / 3 + 4 * cells + rb * fluid / 3,  # one component
+        "g2p": n * 12 * rb + 6 * rb * F,                # particle state in/out; 6 face arrays in
+    }[kind]
+
+
+def traffic_for(kernel: str, scene: str):
+    """HBM bytes per launch measured with rocprofv3 counters, if the summary in
+    profiles/ was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{scene}.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2404_01931_amd", "csrc", vals.get("source", ""))
+    if not os.path.exists(src):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if digest != vals.get("source_sha256"):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(sample_scene: str):
+    """Time the FP64 oracle (plain serial C) for one step of a bounded sample."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2404_01931_amd import inputs
+
+    O.build(force=False)
+    sc = inputs.scene(sample_scene)
+    g = O.Grid(sc.n, sc.n, sc.n, sc.dx)
+    regs = [O.Region(kind=r.kind, lo=r.lo, hi=r.hi, center=r.center, radius=r.radius, vel=r.vel)
+            for r in sc.regions]
+    pos, vel = O.seed(g, regs, sc.sub, sc.seed)
+    pos = pos.astype(np.float32).astype(np.float64)
+    prm = O.Params(grid=g, gravity=sc.gravity, dt=sc.dt, flip_ratio=sc.flip_ratio, density=sc.density,
+                   tol=sc.tol)
+    t0 = time.perf_counter()
+    res = O.step(prm, pos, vel)
+    t = time.perf_counter() - t0
+    n = pos.shape[1]
+    return {
+        "value": n / t,
+        "unit": "particle-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one FP64 oracle step (serial C, MIC(0)-PCG to {sc.tol:g}, {res.solve.iterations} "
+                   f"iterations) of the drop-into-pool scene at {sc.n}^3 ({n} particles), {t:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scene", default="drop256")
+    ap.add_argument("--cpu-sample", default="drop128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the timestep has no multi-GPU "
+              f"path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2404_01931_amd import flip, inputs
+
+    torch.cuda.set_device(0)
+    sc = inputs.scene(args.scene)
+    cfg, keep = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING)
+    progress(f"init {sc.name}")
+    t = time.perf_counter()
+    sim = flip.Simulation(cfg, keep)
+    progress(f"init done in {time.perf_counter() - t:.1f} s: {sim.n} particles, workspace "
+             f"{sim.ws_bytes / 2**30:.2f} GiB")
+    if args.warmup:
+        sim.step(args.warmup)
+    s0 = sim.stats()
+    progress(f"warmup done ({args.warmup} steps, last {s0.pcg_iterations} PCG iterations)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s1 = sim.stats()
+    elapsed = t1 - t0
+    n = s1.n_particles
+    progress(f"timed {args.steps} steps in {elapsed:.3f} s")
+
+    rb = 8 if cfg.precision == flip.FLIP_FP64 else 4
+    cells = cfg.nx * cfg.ny * cfg.nz
+    faces = [(cfg.nx + 1) * cfg.ny * cfg.nz, cfg.nx * (cfg.ny + 1) * cfg.nz, cfg.nx * cfg.ny * (cfg.nz + 1)]
+    d_iter = s1.pcg_iterations_total - s0.pcg_iterations_total
+    d_cell_iter = s1.pcg_cell_iterations_total - s0.pcg_cell_iterations_total
+    fluid_avg = d_cell_iter / d_iter if d_iter else 0.0
+    kernels = {}
+    for k, name in enumerate(flip.KERNEL_NAMES):
+        cnt = s1.kernel_launches[k] - s0.kernel_launches[k]
+        ms = s1.kernel_ms[k] - s0.kernel_ms[k]
+        if cnt <= 0:
+            continue
+        avg = ms / cnt
+        launches = d_iter if name.startswith("pcg_") else cnt
+        kernels[name] = {"avg_ms": avg, "launches": launches, "est_total_ms": avg * launches}
+    dominant = max(kernels, key=lambda k: kernels[k]["est_total_ms"])
+    kd = kernels[dominant]
+    abytes = algorithmic_bytes(dominant, rb, n, cells, faces, fluid_avg)
+    achieved = abytes / (kd["avg_ms"] * 1e-3) / 1e9
+    traffic = traffic_for(dominant, sc.name)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
+                "avg_launch_ms": round(kd["avg_ms"], 5), "bytes_per_launch": abytes}
+    pcg_ms = sum(kernels[k]["est_total_ms"] for k in ("pcg_direction", "pcg_update") if k in kernels)
+    pcg_bytes = d_cell_iter * (8 * rb + 2)
+    pcg = {"iterations_per_step": d_iter / args.steps, "fluid_cells": round(fluid_avg),
+           "algorithmic_GBps": round(pcg_bytes / (pcg_ms * 1e-3) / 1e9, 1) if pcg_ms else None,
+           "frac_of_hbm_peak": round(pcg_bytes / (pcg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if pcg_ms else None,
+           "ms_per_step": round(pcg_ms / args.steps, 3)}
+    stage_ms = {k: round(v["est_total_ms"] / args.steps, 3) for k, v in kernels.items()}
+    progress(f"per-step kernel ms: {stage_ms}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        progress(f"cpu baseline: oracle on {args.cpu_sample}")
+        cpu = cpu_baseline(args.cpu_sample)
+        progress(f"cpu baseline: {cpu['value']:.3e} particle-steps/s")
+
+    line = {
+        "metric": "particle-steps/s",
+        "value": n * args.steps / elapsed,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if rb == 4 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{sc.name}: drop into pool, {sc.n}^3 MAC grid, {n} particles, FP32, "
+                               f"dt=1/{round(1 / sc.dt)}, FLIP {sc.flip_ratio}, Jacobi-PCG tol {sc.tol:g}",
+                   "grid": sc.n, "particles": n, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "pcg": pcg,
+        "kernel_ms_per_step": stage_ms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * flip.h - C ABI of libflipmi, an MI355X (gfx950) implementation of one FLIP
+ * incompressible-fluid timestep as defined in Centeno & Pereira, "Fluid
+ * Implicit Particle Simulation for CPU and GPU" (arXiv 2404.01931).
+ *
+ * One step is, in this order:
+ *   1. particle binning by cell: raw cell index, stable counting sort, space
+ *      hash (start offset and count per cell), fluid flags  (Sec. 3.1.5, 3.2.2)
+ *   2. particle-to-grid transfer onto the staggered MAC grid with the
+ *      trilinear hat kernel                                   (Sec. 3.1.6, Eq. 4)
+ *   3. gravity on every face, zero normal velocity on the six domain walls,
+ *      right-hand side of the pressure Poisson system         (Sec. 3.1.7, Eq. 6)
+ *   4. matrix-free seven-point Poisson solve by preconditioned conjugate
+ *      gradient                                                (Sec. 3.1.7)
+ *   5. projection of the face velocities                       (Sec. 3.1.7, Eq. 5)
+ *   6. grid-to-particle PIC/FLIP blend, forward-Euler advection and the
+ *      skin-width clamp                                        (Sec. 3.1.8, 3.1.3)
+ *
+ * Conventions
+ *   Domain [0, nx dx] x [0, ny dx] x [0, nz dx]; solid walls on all six faces.
+ *   Cells are flattened x-fastest: c = i + nx (j + ny k) (Sec. 3.1.1, Fig. 2).
+ *   Face component a (0 = u, 1 = v, 2 = w) has dims (nx+[a==0], ny+[a==1],
+ *   nz+[a==2]), flattened x-fastest; the sample of face (i, j, k) sits at the
+ *   cell-centre offset 1/2 on the two other axes and at offset 0 on axis a.
+ *   Particle arrays are structure-of-arrays (Sec. 3.2.1): all x, then all y,
+ *   then all z.
+ *   The real type ("real") of particle and grid data is float for FLIP_FP32
+ *   and FLIP_MIXED, double for FLIP_FP64.
+ *
+ * Errors
+ *   Every call returns a flip_status; nothing throws or aborts. Argument
+ *   errors are reported synchronously. Solver outcomes (non-convergence,
+ *   non-finite values) are returned by the flip_step that met them and are
+ *   also latched in the handle, where flip_stats reports them.
+ *
+ * Memory and streams
+ *   The caller owns the device workspace (flip_workspace_bytes) and keeps it
+ *   alive until flip_destroy. The library allocates no device memory of its
+ *   own; it allocates a small host-side handle and a few bytes of pinned host
+ *   memory in flip_init. Work is enqueued on the caller's HIP stream
+ *   (hipStream_t passed as void*, NULL = the null stream).
+ */
+#ifndef FLIPMI_FLIP_H
+#define FLIPMI_FLIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct flip_handle flip_handle;
+
+typedef enum {
+    FLIP_OK = 0,
+    FLIP_E_INVALID = -1,       /* bad argument or configuration                         */
+    FLIP_E_WORKSPACE = -2,     /* workspace missing, too small or misaligned            */
+    FLIP_E_HIP = -3,           /* a HIP runtime call failed                             */
+    FLIP_E_NOT_CONVERGED = -4, /* PCG hit pcg_max_iters before the tolerance            */
+    FLIP_E_NONFINITE = -5,     /* PCG breakdown: non-positive or non-finite curvature   */
+    FLIP_E_STATE = -6          /* call not valid in the handle's current state          */
+} flip_status;
+
+typedef enum { FLIP_FP32 = 0, FLIP_FP64 = 1, FLIP_MIXED = 2 } flip_precision;
+
+enum { FLIP_REGION_BOX = 0, FLIP_REGION_SPHERE = 1 };
+
+/* Fluid region for seeding (Sec. 3.1.2): a box lo <= x < hi on every axis, or
+ * a sphere |x - center|^2 < radius^2. Seeded particles get velocity vel. */
+typedef struct {
+    int32_t kind;
+    double lo[3], hi[3];
+    double center[3], radius;
+    double vel[3];
+} flip_region;
+
+/* configuration flags */
+enum {
+    FLIP_FLAG_NO_GRAVITY = 1u,         /* skip the gravity term                            */
+    FLIP_FLAG_NO_PROJECTION = 2u,      /* skip solve and projection (transfer-only steps)  */
+    FLIP_FLAG_ADVECT_PARTICLE_VEL = 4u,/* advect with the blended particle velocity        */
+    FLIP_FLAG_KERNEL_TIMING = 8u       /* bracket kernel launches with HIP events           */
+};
+
+typedef struct {
+    int32_t nx, ny, nz;        /* cells per axis, each >= 1                                */
+    double dx;                 /* cell size (Delta tau), > 0                               */
+    double gravity[3];         /* external acceleration, e.g. (0, -9.81, 0)                */
+    double dt;                 /* fixed time step, > 0                                     */
+    double flip_ratio;         /* blending factor alpha in [0, 1]: v = PIC + alpha(FLIP-PIC)*/
+    double density;            /* rho > 0 (scales the pressure only)                       */
+    double pcg_tol;            /* stop when max|r| <= pcg_tol * max|b| over fluid cells     */
+    int32_t pcg_max_iters;     /* <= 0 selects 20 * max(nx, ny, nz)                        */
+    double ir_tol;             /* FLIP_MIXED: outer refinement tolerance (relative)        */
+    int32_t precision;         /* flip_precision                                           */
+    uint32_t flags;            /* FLIP_FLAG_*                                              */
+    /* initial particles: either seeded from regions ...                                  */
+    uint32_t n_regions;
+    const flip_region* regions;/* host array, read only during flip_init                   */
+    int32_t subcells_per_axis; /* jitter subcells per axis (2 -> 8 particles per cell)     */
+    uint64_t seed;             /* SplitMix64 seed of the jitter                            */
+    /* ... or given explicitly (used when pos0 != NULL)                                   */
+    int64_t n_particles;
+    const double* pos0;        /* host, 3 * n_particles doubles, SoA, inside the domain    */
+    const double* vel0;        /* host, 3 * n_particles doubles, SoA                       */
+} flip_config;
+
+/* fields for flip_readback / flip_field_bytes */
+enum {
+    FLIP_FIELD_POS = 0,        /* real[3n] SoA, binned order of the last step              */
+    FLIP_FIELD_VEL = 1,        /* real[3n] SoA                                             */
+    FLIP_FIELD_ID = 2,         /* uint32[n]: initial index of each particle                */
+    FLIP_FIELD_CELL_COUNT = 3, /* uint32[ncells]: particles per cell (space hash)          */
+    FLIP_FIELD_CELL_START = 4, /* uint32[ncells]: exclusive scan of the counts             */
+    FLIP_FIELD_FLAGS = 5,      /* uint8[ncells]: 1 = fluid (count > 0), 0 = air            */
+    FLIP_FIELD_U_OLD = 6,      /* real[Fu + Fv + Fw]: raw particle-to-grid result          */
+    FLIP_FIELD_U_STAR = 7,     /* real[Fu + Fv + Fw]: after gravity and walls              */
+    FLIP_FIELD_U_NEW = 8,      /* real[Fu + Fv + Fw]: after projection                     */
+    FLIP_FIELD_RHS = 9,        /* real[ncells]: b (0 off fluid)                            */
+    FLIP_FIELD_PRESSURE = 10,  /* real[ncells]: p (0 off fluid); double for FLIP_MIXED      */
+    FLIP_FIELD_COUNT_ = 11
+};
+
+/* kernels that FLIP_FLAG_KERNEL_TIMING measures */
+enum {
+    FLIP_KERNEL_BIN_KEYS = 0,
+    FLIP_KERNEL_BIN_SCAN = 1,
+    FLIP_KERNEL_BIN_SCATTER = 2,
+    FLIP_KERNEL_BIN_GATHER = 3,
+    FLIP_KERNEL_TILES = 4,
+    FLIP_KERNEL_P2G = 5,
+    FLIP_KERNEL_RHS = 6,
+    FLIP_KERNEL_PCG_DIRECTION = 7, /* s = z + beta s, q = A s, s.q                        */
+    FLIP_KERNEL_PCG_UPDATE = 8,    /* x += alpha s, r -= alpha A s, r.z, max|r|          */
+    FLIP_KERNEL_PROJECT = 9,
+    FLIP_KERNEL_G2P = 10,
+    FLIP_KERNEL_COUNT = 11
+};
+
+typedef struct {
+    int64_t steps;                 /* steps completed since flip_init                      */
+    int64_t n_particles;
+    int64_t n_fluid_cells;         /* last step                                            */
+    int64_t n_active_tiles;        /* last step: 8x8x8 tiles holding a fluid cell          */
+    int32_t pcg_iterations;        /* last step                                            */
+    int32_t pcg_status;            /* last step: 0 converged, 1 max iters, 2 breakdown     */
+    double max_b;                  /* last step: max |b| over fluid cells                  */
+    double max_r;                  /* last step: final max |r| (solver's residual)         */
+    int64_t pcg_iterations_total;  /* summed over all steps                                */
+    int64_t pcg_cell_iterations_total; /* sum over steps of fluid cells x PCG iterations      */
+    int32_t latched_status;        /* first solver error since init (flip_status), or 0    */
+    int32_t pad_;
+    double kernel_ms[FLIP_KERNEL_COUNT];      /* summed durations of timed launches        */
+    int64_t kernel_launches[FLIP_KERNEL_COUNT];/* number of timed launches                 */
+} flip_step_stats;
+
+/* Device workspace needed for cfg (pure; used for HBM admission). */
+flip_status flip_workspace_bytes(const flip_config* cfg, size_t* out_bytes);
+
+/* Validate cfg, carve the caller-owned device workspace d_ws (ws_bytes long,
+ * 256-byte aligned), seed or upload the particles and return a handle.
+ * Synchronises hip_stream before returning. */
+flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void* hip_stream,
+                      flip_handle** out);
+
+/* Run nsteps >= 0 steps on hip_stream. The PCG loop is controlled from the
+ * host, so this call waits for the stream at the solver's convergence checks;
+ * projection and grid-to-particle of the last step may still be in flight
+ * when it returns. Returns the first solver error met, if any, after
+ * completing every step. */
+flip_status flip_step(flip_handle* h, int nsteps, void* hip_stream);
+
+/* Size in bytes of a readback field. */
+flip_status flip_field_bytes(const flip_handle* h, int field, size_t* out_bytes);
+
+/* Copy a field into dst (dst_bytes >= flip_field_bytes). dst_is_device != 0:
+ * dst is device memory and the copy is stream-ordered; otherwise dst is host
+ * memory and the call synchronises hip_stream. */
+flip_status flip_readback(flip_handle* h, int field, void* dst, size_t dst_bytes, int dst_is_device,
+                          void* hip_stream);
+
+/* Statistics of the handle; synchronises the stream of the last step. */
+flip_status flip_stats(flip_handle* h, flip_step_stats* out);
+
+/* Release the handle (not the workspace). NULL is ignored. */
+void flip_destroy(flip_handle* h);
+
+const char* flip_status_string(flip_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLIPMI_FLIP_H */

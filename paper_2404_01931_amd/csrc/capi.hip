@@ -1,0 +1,698 @@
+// C ABI of libflipmi: configuration, workspace carving, seeding, the step
+// sequence and readback. See include/flip.h for the contract of each call.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/flip.h"
+#include "common.h"
+
+using namespace flipmi;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int TIMED_PCG_EVERY = 8;  // with kernel timing on, one PCG iteration in 8 is bracketed
+constexpr int EVENT_PAIRS = 2048;
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Computes the workspace layout; with base == nullptr it only sums sizes.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename P>
+    P* take(size_t bytes)
+    {
+        size_t o = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return base ? (P*)(base + o) : nullptr;
+    }
+};
+
+struct Sizes {
+    int64_t n = 0, C = 0, T = 0, cap = 0, F[3] = {0, 0, 0};
+    size_t rb = 4;  // bytes of the real type
+};
+
+// ---------------------------------------------------------------------------
+// seeding (paper Sec. 3.1.2): sub^3 jittered subcells per cell whose centre is
+// inside a region. Jitter: SplitMix64 output sequence (Steele, Lea & Flood
+// 2014) of `seed`, element 3 * (sub^3 * cell + subcell) + axis, top 53 bits.
+// ---------------------------------------------------------------------------
+
+uint64_t splitmix_element(uint64_t seed, uint64_t index)
+{
+    uint64_t z = seed + (index + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double jitter(uint64_t seed, uint64_t index)
+{
+    return (double)(splitmix_element(seed, index) >> 11) * 0x1.0p-53;
+}
+
+const flip_region* region_of_centre(const flip_config& c, int i, int j, int k)
+{
+#pragma clang fp contract(off)
+    const double p[3] = {(i + 0.5) * c.dx, (j + 0.5) * c.dx, (k + 0.5) * c.dx};
+    for (uint32_t r = 0; r < c.n_regions; ++r) {
+        const flip_region& g = c.regions[r];
+        if (g.kind == FLIP_REGION_BOX) {
+            bool in = true;
+            for (int a = 0; a < 3; ++a) in = in && (g.lo[a] <= p[a] && p[a] < g.hi[a]);
+            if (in) return &g;
+        } else {
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double d = p[a] - g.center[a];
+                const double dd = d * d;
+                d2 = d2 + dd;
+            }
+            if (d2 < g.radius * g.radius) return &g;
+        }
+    }
+    return nullptr;
+}
+
+int64_t seeded_count(const flip_config& c)
+{
+    const int64_t per = (int64_t)c.subcells_per_axis * c.subcells_per_axis * c.subcells_per_axis;
+    int64_t n = 0;
+    for (int k = 0; k < c.nz; ++k)
+        for (int j = 0; j < c.ny; ++j)
+            for (int i = 0; i < c.nx; ++i)
+                if (region_of_centre(c, i, j, k)) n += per;
+    return n;
+}
+
+template <typename T>
+void seed_particles(const flip_config& c, std::vector<T>& pos, std::vector<T>& vel, int64_t n)
+{
+#pragma clang fp contract(off)
+    const int sub = c.subcells_per_axis;
+    const int64_t per = (int64_t)sub * sub * sub;
+    int64_t q = 0;
+    for (int k = 0; k < c.nz; ++k)
+        for (int j = 0; j < c.ny; ++j)
+            for (int i = 0; i < c.nx; ++i) {
+                const flip_region* r = region_of_centre(c, i, j, k);
+                if (!r) continue;
+                const uint64_t cell = (uint64_t)i + (uint64_t)c.nx * ((uint64_t)j + (uint64_t)c.ny * k);
+                for (int sz = 0; sz < sub; ++sz)
+                    for (int sy = 0; sy < sub; ++sy)
+                        for (int sx = 0; sx < sub; ++sx) {
+                            const uint64_t s = (uint64_t)sx + (uint64_t)sub * ((uint64_t)sy + (uint64_t)sub * sz);
+                            const uint64_t base = 3u * (per * cell + s);
+                            const double x = (((double)sx + jitter(c.seed, base + 0)) / sub + i) * c.dx;
+                            const double y = (((double)sy + jitter(c.seed, base + 1)) / sub + j) * c.dx;
+                            const double z = (((double)sz + jitter(c.seed, base + 2)) / sub + k) * c.dx;
+                            pos[q] = (T)x;
+                            pos[n + q] = (T)y;
+                            pos[2 * n + q] = (T)z;
+                            for (int a = 0; a < 3; ++a) vel[a * n + q] = (T)r->vel[a];
+                            ++q;
+                        }
+            }
+}
+
+}  // namespace
+
+struct flip_handle {
+    flip_config cfg;  // copy; region / array pointers cleared after init
+    int prec = FLIP_FP32;
+    Geo geo{};
+    Sizes sz;
+    // particles (double-buffered)
+    void* pos[2] = {nullptr, nullptr};
+    void* vel[2] = {nullptr, nullptr};
+    uint32_t* id[2] = {nullptr, nullptr};
+    uint32_t *key = nullptr, *rank = nullptr, *perm = nullptr;
+    // cells
+    uint32_t *count = nullptr, *start = nullptr, *scan_tmp = nullptr;
+    // tiles
+    uint32_t *tile_flag = nullptr, *tile_excl = nullptr, *tile_list = nullptr, *d_nactive = nullptr;
+    int32_t *tile_slot = nullptr, *tile_nbr = nullptr;
+    // faces
+    void* f_old[3] = {};
+    void* f_star[3] = {};
+    void* f_new[3] = {};
+    // solver (compact tile storage)
+    uint8_t* diag = nullptr;
+    void *b = nullptr, *z = nullptr, *x = nullptr, *s[2] = {nullptr, nullptr};
+    double* partials = nullptr;
+    PcgState* ps = nullptr;
+    void* staging = nullptr;
+    // host side
+    int cur = 0;
+    int n_active = 0;
+    int prev_iters = 0;
+    PcgState* h_ps = nullptr;
+    uint32_t* h_nactive = nullptr;
+    hipStream_t last_stream = nullptr;
+    flip_step_stats stats{};
+    // kernel timing
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    std::vector<int> ev_iter;  // PCG iteration of a timed solver launch, -1 otherwise
+    int ev_used = 0;
+    int ev_iter_limit = 1 << 30;  // solver launches at or past this iteration did no work
+};
+
+namespace {
+
+size_t real_bytes(int prec) { return prec == FLIP_FP64 ? 8 : 4; }
+
+flip_status validate(const flip_config* c)
+{
+    if (!c) return FLIP_E_INVALID;
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return FLIP_E_INVALID;
+    if ((int64_t)c->nx * c->ny * c->nz >= (int64_t)1 << 31) return FLIP_E_INVALID;
+    if (!(c->dx > 0.0) || !std::isfinite(c->dx)) return FLIP_E_INVALID;
+    if (!(c->dt > 0.0) || !std::isfinite(c->dt)) return FLIP_E_INVALID;
+    if (!(c->density > 0.0) || !std::isfinite(c->density)) return FLIP_E_INVALID;
+    if (!(c->flip_ratio >= 0.0 && c->flip_ratio <= 1.0)) return FLIP_E_INVALID;
+    if (!(c->pcg_tol >= 0.0) || !std::isfinite(c->pcg_tol)) return FLIP_E_INVALID;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c->gravity[a])) return FLIP_E_INVALID;
+    if (c->precision != FLIP_FP32 && c->precision != FLIP_FP64) return FLIP_E_INVALID;
+    if (c->pos0) {
+        if (c->n_particles < 0 || c->n_particles >= ((int64_t)1 << 31) || !c->vel0) return FLIP_E_INVALID;
+    } else {
+        if (c->n_regions > 0 && !c->regions) return FLIP_E_INVALID;
+        if (c->n_regions > 4096) return FLIP_E_INVALID;
+        if (c->subcells_per_axis < 1 || c->subcells_per_axis > 16) return FLIP_E_INVALID;
+        for (uint32_t r = 0; r < c->n_regions; ++r)
+            if (c->regions[r].kind != FLIP_REGION_BOX && c->regions[r].kind != FLIP_REGION_SPHERE)
+                return FLIP_E_INVALID;
+    }
+    return FLIP_OK;
+}
+
+flip_status particle_count(const flip_config* c, int64_t* n)
+{
+    if (c->pos0) {
+        *n = c->n_particles;
+        return FLIP_OK;
+    }
+    int64_t m = seeded_count(*c);
+    if (m >= ((int64_t)1 << 31)) return FLIP_E_INVALID;
+    *n = m;
+    return FLIP_OK;
+}
+
+Geo make_geo(const flip_config* c)
+{
+    Geo g;
+    g.nx = c->nx;
+    g.ny = c->ny;
+    g.nz = c->nz;
+    g.tx = (c->nx + TILE - 1) / TILE;
+    g.ty = (c->ny + TILE - 1) / TILE;
+    g.tz = (c->nz + TILE - 1) / TILE;
+    g.dx = c->dx;
+    g.inv_dx = 1.0 / c->dx;
+    return g;
+}
+
+Sizes make_sizes(const flip_config* c, int64_t n)
+{
+    Sizes s;
+    s.n = n;
+    s.C = (int64_t)c->nx * c->ny * c->nz;
+    Geo g = make_geo(c);
+    s.T = tiles_of(g);
+    s.cap = s.T * TILE_CELLS;
+    s.F[0] = (int64_t)(c->nx + 1) * c->ny * c->nz;
+    s.F[1] = (int64_t)c->nx * (c->ny + 1) * c->nz;
+    s.F[2] = (int64_t)c->nx * c->ny * (c->nz + 1);
+    s.rb = real_bytes(c->precision);
+    return s;
+}
+
+// One layout for both sizing and carving.
+void carve(flip_handle* h, Carver& cv)
+{
+    const Sizes& s = h->sz;
+    const size_t rb = s.rb;
+    for (int q = 0; q < 2; ++q) {
+        h->pos[q] = cv.take<void>(3 * s.n * rb);
+        h->vel[q] = cv.take<void>(3 * s.n * rb);
+        h->id[q] = cv.take<uint32_t>(4 * s.n);
+    }
+    h->key = cv.take<uint32_t>(4 * s.n);
+    h->rank = cv.take<uint32_t>(4 * s.n);
+    h->perm = cv.take<uint32_t>(4 * s.n);
+    h->count = cv.take<uint32_t>(4 * s.C);
+    h->start = cv.take<uint32_t>(4 * s.C);
+    h->scan_tmp = cv.take<uint32_t>(4 * scan_tmp_words(s.C > s.T ? s.C : s.T));
+    h->tile_flag = cv.take<uint32_t>(4 * s.T);
+    h->tile_excl = cv.take<uint32_t>(4 * s.T);
+    h->tile_list = cv.take<uint32_t>(4 * s.T);
+    h->tile_slot = cv.take<int32_t>(4 * s.T);
+    h->tile_nbr = cv.take<int32_t>(24 * s.T);
+    h->d_nactive = cv.take<uint32_t>(4);
+    for (int a = 0; a < 3; ++a) {
+        h->f_old[a] = cv.take<void>(s.F[a] * rb);
+        h->f_star[a] = cv.take<void>(s.F[a] * rb);
+        h->f_new[a] = cv.take<void>(s.F[a] * rb);
+    }
+    h->diag = cv.take<uint8_t>(s.cap);
+    h->b = cv.take<void>(s.cap * rb);
+    h->z = cv.take<void>(s.cap * rb);
+    h->x = cv.take<void>(s.cap * rb);
+    h->s[0] = cv.take<void>(s.cap * rb);
+    h->s[1] = cv.take<void>(s.cap * rb);
+    h->partials = cv.take<double>(3 * sizeof(double) * s.T);
+    h->ps = cv.take<PcgState>(sizeof(PcgState));
+    h->staging = cv.take<void>(8 * s.C);
+}
+
+#define HIP_TRY(call)                              \
+    do {                                           \
+        if ((call) != hipSuccess) return FLIP_E_HIP; \
+    } while (0)
+
+// ---- kernel timing (FLIP_FLAG_KERNEL_TIMING) --------------------------------
+
+int timer_begin(flip_handle* h, int kind, hipStream_t st, int pcg_iter = -1)
+{
+    if (!(h->cfg.flags & FLIP_FLAG_KERNEL_TIMING) || h->ev_used + 1 >= (int)h->ev.size()) return -1;
+    const int q = h->ev_used;
+    h->ev_used += 2;
+    h->ev_kind[q / 2] = kind;
+    h->ev_iter[q / 2] = pcg_iter;
+    (void)hipEventRecord(h->ev[q], st);
+    return q;
+}
+
+void timer_end(flip_handle* h, int q, hipStream_t st)
+{
+    if (q >= 0) (void)hipEventRecord(h->ev[q + 1], st);
+}
+
+flip_status timer_collect(flip_handle* h, hipStream_t st)
+{
+    if (h->ev_used == 0) return FLIP_OK;
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int q = 0; q < h->ev_used; q += 2) {
+        if (h->ev_iter[q / 2] >= h->ev_iter_limit) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev[q], h->ev[q + 1]) == hipSuccess) {
+            h->stats.kernel_ms[h->ev_kind[q / 2]] += ms;
+            h->stats.kernel_launches[h->ev_kind[q / 2]] += 1;
+        }
+    }
+    h->ev_used = 0;
+    h->ev_iter_limit = 1 << 30;
+    return FLIP_OK;
+}
+
+// ---- one step -----------------------------------------------------------------
+
+template <typename T>
+flip_status run_step(flip_handle* h, hipStream_t st)
+{
+    const Geo& g = h->geo;
+    const Sizes& s = h->sz;
+    const int64_t n = s.n;
+    const int nxt = h->cur ^ 1;
+    const flip_config& c = h->cfg;
+
+    // 1. binning
+    int tq = timer_begin(h, FLIP_KERNEL_BIN_KEYS, st);
+    launch_fill_u32(h->count, s.C, 0u, st);
+    launch_bin_keys<T>(g, (const T*)h->pos[h->cur], n, h->key, h->rank, h->count, st);
+    timer_end(h, tq, st);
+    tq = timer_begin(h, FLIP_KERNEL_BIN_SCAN, st);
+    launch_exclusive_scan_u32(h->count, h->start, s.C, h->scan_tmp, st);
+    timer_end(h, tq, st);
+    tq = timer_begin(h, FLIP_KERNEL_BIN_SCATTER, st);
+    launch_bin_scatter(h->key, h->rank, h->start, n, h->perm, st);
+    timer_end(h, tq, st);
+    tq = timer_begin(h, FLIP_KERNEL_BIN_GATHER, st);
+    launch_bin_gather<T>(h->perm, h->key, h->start, h->count, n, (const T*)h->pos[h->cur],
+                         (const T*)h->vel[h->cur], h->id[h->cur], (T*)h->pos[nxt], (T*)h->vel[nxt],
+                         h->id[nxt], st);
+    timer_end(h, tq, st);
+    h->cur = nxt;
+    tq = timer_begin(h, FLIP_KERNEL_TILES, st);
+    launch_tiles(g, h->count, h->tile_flag, h->tile_excl, h->tile_slot, h->tile_list, h->tile_nbr,
+                 h->d_nactive, h->scan_tmp, st);
+    timer_end(h, tq, st);
+    HIP_TRY(hipMemcpyAsync(h->h_nactive, h->d_nactive, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int na = (int)*h->h_nactive;
+    h->n_active = na;
+
+    // 2. particle-to-grid, gravity, walls
+    const T* pos = (const T*)h->pos[h->cur];
+    const T* vel = (const T*)h->vel[h->cur];
+    const bool grav = !(c.flags & FLIP_FLAG_NO_GRAVITY);
+    for (int a = 0; a < 3; ++a) {
+        tq = timer_begin(h, FLIP_KERNEL_P2G, st);
+        launch_p2g<T>(g, a, pos, n, vel + a * n, h->start, h->count,
+                      (T)(grav ? c.gravity[a] * c.dt : 0.0), (T*)h->f_old[a], (T*)h->f_star[a], st);
+        timer_end(h, tq, st);
+    }
+
+    // 3. right-hand side and solver start
+    PcgState ps_host{};
+    flip_status ret = FLIP_OK;
+    const bool project = !(c.flags & FLIP_FLAG_NO_PROJECTION);
+    const int max_iters = c.pcg_max_iters > 0 ? c.pcg_max_iters : 20 * std::max(c.nx, std::max(c.ny, c.nz));
+    if (na > 0) {
+        tq = timer_begin(h, FLIP_KERNEL_RHS, st);
+        launch_rhs<T, T>(g, na, h->tile_list, h->count, (const T*)h->f_star[0], (const T*)h->f_star[1],
+                         (const T*)h->f_star[2], -c.density * c.dx / c.dt, h->diag, (T*)h->b, (T*)h->z,
+                         (T*)h->x, (T*)h->s[0], (T*)h->s[1], h->partials, s.T, h->ps,
+                         project ? c.pcg_tol : 0.0, project ? max_iters : 0, st);
+        timer_end(h, tq, st);
+    }
+
+    // 4. PCG, host-controlled in chunks of iterations; the kernels skip work
+    //    once the device-side state says the solve is over
+    if (na > 0 && project) {
+        int chunk = h->prev_iters > 2 ? h->prev_iters - 2 : 16;
+        int launched = 0, sc = 0;
+        for (;;) {
+            for (int it = 0; it < chunk; ++it) {
+                const bool timed = ((launched + it) % TIMED_PCG_EVERY) == 0;
+                int q1 = timed ? timer_begin(h, FLIP_KERNEL_PCG_DIRECTION, st, launched + it) : -1;
+                launch_pcg_direction<T>(na, h->tile_nbr, h->diag, (const T*)h->z, (const T*)h->s[sc],
+                                        (T*)h->s[sc ^ 1], h->partials, h->ps, st);
+                timer_end(h, q1, st);
+                int q2 = timed ? timer_begin(h, FLIP_KERNEL_PCG_UPDATE, st, launched + it) : -1;
+                launch_pcg_update<T>(na, h->tile_nbr, h->diag, (const T*)h->s[sc ^ 1], (T*)h->x,
+                                     (T*)h->z, h->partials, s.T, h->ps, st);
+                timer_end(h, q2, st);
+                sc ^= 1;
+            }
+            launched += chunk;
+            HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (h->h_ps->done != PCG_RUNNING || launched > max_iters + 8) break;
+            chunk = 8;
+        }
+        ps_host = *h->h_ps;
+        h->prev_iters = ps_host.iter;
+        h->ev_iter_limit = ps_host.iter;
+        if (ps_host.done == PCG_MAX_ITERS || ps_host.done == PCG_RUNNING) ret = FLIP_E_NOT_CONVERGED;
+        if (ps_host.done == PCG_BREAKDOWN) ret = FLIP_E_NONFINITE;
+        // 5. projection
+        const T scale = (T)(c.dt / (c.density * c.dx));
+        for (int a = 0; a < 3; ++a) {
+            tq = timer_begin(h, FLIP_KERNEL_PROJECT, st);
+            launch_project<T, T>(g, a, h->count, h->tile_slot, (const T*)h->x, (const T*)h->f_star[a],
+                                 (T*)h->f_new[a], scale, st);
+            timer_end(h, tq, st);
+        }
+    } else {
+        if (na > 0) {
+            HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            ps_host = *h->h_ps;
+            ps_host.iter = 0;
+        }
+        for (int a = 0; a < 3; ++a)
+            HIP_TRY(hipMemcpyAsync(h->f_new[a], h->f_star[a], s.F[a] * sizeof(T),
+                                   hipMemcpyDeviceToDevice, st));
+    }
+
+    // 6. grid-to-particle, blend, advect, clamp
+    tq = timer_begin(h, FLIP_KERNEL_G2P, st);
+    launch_g2p<T>(g, n, (T*)h->pos[h->cur], (T*)h->vel[h->cur], (const T*)h->f_new[0],
+                  (const T*)h->f_new[1], (const T*)h->f_new[2], (const T*)h->f_old[0],
+                  (const T*)h->f_old[1], (const T*)h->f_old[2], (T)c.flip_ratio, (T)c.dt,
+                  (c.flags & FLIP_FLAG_ADVECT_PARTICLE_VEL) ? 1 : 0, st);
+    timer_end(h, tq, st);
+    if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
+
+    flip_step_stats& S = h->stats;
+    S.steps += 1;
+    S.n_fluid_cells = na > 0 ? ps_host.nfluid : 0;
+    S.n_active_tiles = na;
+    S.pcg_iterations = ps_host.iter;
+    S.pcg_status = ps_host.done == PCG_CONVERGED ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : (na > 0 && project ? 1 : 0));
+    S.max_b = ps_host.max_b;
+    S.max_r = ps_host.max_r;
+    S.pcg_iterations_total += ps_host.iter;
+    S.pcg_cell_iterations_total += (int64_t)ps_host.iter * (na > 0 ? ps_host.nfluid : 0);
+    if (ret != FLIP_OK && S.latched_status == 0) S.latched_status = ret;
+    flip_status tr = timer_collect(h, st);
+    return ret != FLIP_OK ? ret : tr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* flip_status_string(flip_status s)
+{
+    switch (s) {
+        case FLIP_OK: return "ok";
+        case FLIP_E_INVALID: return "invalid argument";
+        case FLIP_E_WORKSPACE: return "workspace missing, too small or misaligned";
+        case FLIP_E_HIP: return "HIP runtime error";
+        case FLIP_E_NOT_CONVERGED: return "PCG did not converge within pcg_max_iters";
+        case FLIP_E_NONFINITE: return "PCG breakdown (non-finite or non-positive curvature)";
+        case FLIP_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+flip_status flip_workspace_bytes(const flip_config* cfg, size_t* out_bytes)
+{
+    if (!out_bytes) return FLIP_E_INVALID;
+    flip_status v = validate(cfg);
+    if (v != FLIP_OK) return v;
+    int64_t n = 0;
+    v = particle_count(cfg, &n);
+    if (v != FLIP_OK) return v;
+    flip_handle tmp;
+    tmp.sz = make_sizes(cfg, n);
+    Carver cv(nullptr);
+    carve(&tmp, cv);
+    *out_bytes = cv.off;
+    return FLIP_OK;
+}
+
+flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void* hip_stream,
+                      flip_handle** out)
+{
+    if (!out) return FLIP_E_INVALID;
+    *out = nullptr;
+    flip_status v = validate(cfg);
+    if (v != FLIP_OK) return v;
+    int64_t n = 0;
+    v = particle_count(cfg, &n);
+    if (v != FLIP_OK) return v;
+    const double L[3] = {cfg->nx * cfg->dx, cfg->ny * cfg->dx, cfg->nz * cfg->dx};
+    if (cfg->pos0) {
+        for (int a = 0; a < 3; ++a)
+            for (int64_t p = 0; p < n; ++p) {
+                const double q = cfg->pos0[a * n + p], w = cfg->vel0[a * n + p];
+                if (!(q >= 0.0 && q <= L[a]) || !std::isfinite(w)) return FLIP_E_INVALID;
+            }
+    }
+    flip_handle* h = new (std::nothrow) flip_handle();
+    if (!h) return FLIP_E_INVALID;
+    h->cfg = *cfg;
+    h->prec = cfg->precision;
+    h->geo = make_geo(cfg);
+    h->sz = make_sizes(cfg, n);
+    Carver dry(nullptr);
+    carve(h, dry);
+    if (!d_ws || ws_bytes < dry.off || ((uintptr_t)d_ws & (ALIGN - 1))) {
+        delete h;
+        return FLIP_E_WORKSPACE;
+    }
+    Carver cv(d_ws);
+    carve(h, cv);
+    hipStream_t st = (hipStream_t)hip_stream;
+    h->last_stream = st;
+
+    // particles on the host, then one upload
+    const size_t rb = h->sz.rb;
+    std::vector<uint32_t> ids((size_t)n);
+    for (int64_t p = 0; p < n; ++p) ids[p] = (uint32_t)p;
+    flip_status rc = FLIP_OK;
+    auto upload = [&](auto tag) -> flip_status {
+        using T = decltype(tag);
+        std::vector<T> pos((size_t)(3 * n)), vel((size_t)(3 * n));
+        if (cfg->pos0) {
+            for (int64_t q = 0; q < 3 * n; ++q) {
+                pos[q] = (T)cfg->pos0[q];
+                vel[q] = (T)cfg->vel0[q];
+            }
+        } else {
+            seed_particles<T>(*cfg, pos, vel, n);
+        }
+        if (n > 0) {
+            HIP_TRY(hipMemcpyAsync(h->pos[0], pos.data(), 3 * n * rb, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(h->vel[0], vel.data(), 3 * n * rb, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(h->id[0], ids.data(), 4 * n, hipMemcpyHostToDevice, st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        return FLIP_OK;
+    };
+    rc = (h->prec == FLIP_FP64) ? upload(double{}) : upload(float{});
+    if (rc != FLIP_OK) {
+        delete h;
+        return rc;
+    }
+    h->cfg.regions = nullptr;
+    h->cfg.n_regions = 0;
+    h->cfg.pos0 = nullptr;
+    h->cfg.vel0 = nullptr;
+
+    // grid state readable before the first step
+    const Sizes& s = h->sz;
+    launch_fill_u32(h->count, s.C, 0u, st);
+    launch_fill_u32(h->start, s.C, 0u, st);
+    launch_fill_u32((uint32_t*)h->tile_slot, s.T, 0xFFFFFFFFu, st);
+    for (int a = 0; a < 3; ++a) {
+        launch_fill_bytes_zero(h->f_old[a], s.F[a] * rb, st);
+        launch_fill_bytes_zero(h->f_star[a], s.F[a] * rb, st);
+        launch_fill_bytes_zero(h->f_new[a], s.F[a] * rb, st);
+    }
+    launch_fill_bytes_zero(h->diag, s.cap, st);
+    launch_fill_bytes_zero(h->ps, sizeof(PcgState), st);
+    if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_nactive, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        flip_destroy(h);
+        return FLIP_E_HIP;
+    }
+    if (cfg->flags & FLIP_FLAG_KERNEL_TIMING) {
+        h->ev.resize(2 * EVENT_PAIRS);
+        h->ev_kind.resize(EVENT_PAIRS);
+        h->ev_iter.resize(EVENT_PAIRS);
+        for (auto& e : h->ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                flip_destroy(h);
+                return FLIP_E_HIP;
+            }
+    }
+    if (hipStreamSynchronize(st) != hipSuccess || hipGetLastError() != hipSuccess) {
+        flip_destroy(h);
+        return FLIP_E_HIP;
+    }
+    h->stats.n_particles = n;
+    *out = h;
+    return FLIP_OK;
+}
+
+flip_status flip_step(flip_handle* h, int nsteps, void* hip_stream)
+{
+    if (!h || nsteps < 0) return FLIP_E_INVALID;
+    hipStream_t st = (hipStream_t)hip_stream;
+    h->last_stream = st;
+    flip_status first = FLIP_OK;
+    for (int k = 0; k < nsteps; ++k) {
+        flip_status r = (h->prec == FLIP_FP64) ? run_step<double>(h, st) : run_step<float>(h, st);
+        if (r == FLIP_E_HIP) return r;
+        if (r != FLIP_OK && first == FLIP_OK) first = r;
+    }
+    return first;
+}
+
+flip_status flip_field_bytes(const flip_handle* h, int field, size_t* out_bytes)
+{
+    if (!h || !out_bytes) return FLIP_E_INVALID;
+    const Sizes& s = h->sz;
+    switch (field) {
+        case FLIP_FIELD_POS:
+        case FLIP_FIELD_VEL: *out_bytes = 3 * s.n * s.rb; break;
+        case FLIP_FIELD_ID: *out_bytes = 4 * s.n; break;
+        case FLIP_FIELD_CELL_COUNT:
+        case FLIP_FIELD_CELL_START: *out_bytes = 4 * s.C; break;
+        case FLIP_FIELD_FLAGS: *out_bytes = s.C; break;
+        case FLIP_FIELD_U_OLD:
+        case FLIP_FIELD_U_STAR:
+        case FLIP_FIELD_U_NEW: *out_bytes = (s.F[0] + s.F[1] + s.F[2]) * s.rb; break;
+        case FLIP_FIELD_RHS:
+        case FLIP_FIELD_PRESSURE: *out_bytes = s.C * s.rb; break;
+        default: return FLIP_E_INVALID;
+    }
+    return FLIP_OK;
+}
+
+flip_status flip_readback(flip_handle* h, int field, void* dst, size_t dst_bytes, int dst_is_device,
+                          void* hip_stream)
+{
+    if (!h || !dst) return FLIP_E_INVALID;
+    size_t need = 0;
+    flip_status v = flip_field_bytes(h, field, &need);
+    if (v != FLIP_OK) return v;
+    if (dst_bytes < need) return FLIP_E_INVALID;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const Sizes& s = h->sz;
+    char* d = (char*)dst;
+    switch (field) {
+        case FLIP_FIELD_POS: HIP_TRY(hipMemcpyAsync(d, h->pos[h->cur], need, kind, st)); break;
+        case FLIP_FIELD_VEL: HIP_TRY(hipMemcpyAsync(d, h->vel[h->cur], need, kind, st)); break;
+        case FLIP_FIELD_ID: HIP_TRY(hipMemcpyAsync(d, h->id[h->cur], need, kind, st)); break;
+        case FLIP_FIELD_CELL_COUNT: HIP_TRY(hipMemcpyAsync(d, h->count, need, kind, st)); break;
+        case FLIP_FIELD_CELL_START: HIP_TRY(hipMemcpyAsync(d, h->start, need, kind, st)); break;
+        case FLIP_FIELD_FLAGS:
+            launch_flags_from_count(h->count, s.C, (uint8_t*)h->staging, st);
+            HIP_TRY(hipMemcpyAsync(d, h->staging, need, kind, st));
+            break;
+        case FLIP_FIELD_U_OLD:
+        case FLIP_FIELD_U_STAR:
+        case FLIP_FIELD_U_NEW: {
+            void* const* f = field == FLIP_FIELD_U_OLD ? h->f_old : (field == FLIP_FIELD_U_STAR ? h->f_star : h->f_new);
+            size_t off = 0;
+            for (int a = 0; a < 3; ++a) {
+                HIP_TRY(hipMemcpyAsync(d + off, f[a], s.F[a] * s.rb, kind, st));
+                off += s.F[a] * s.rb;
+            }
+            break;
+        }
+        case FLIP_FIELD_RHS:
+        case FLIP_FIELD_PRESSURE: {
+            const void* src = field == FLIP_FIELD_RHS ? h->b : h->x;
+            if (h->prec == FLIP_FP64)
+                launch_densify<double, double>(h->geo, h->tile_slot, h->diag, (const double*)src,
+                                               (double*)h->staging, st);
+            else
+                launch_densify<float, float>(h->geo, h->tile_slot, h->diag, (const float*)src,
+                                             (float*)h->staging, st);
+            HIP_TRY(hipMemcpyAsync(d, h->staging, need, kind, st));
+            break;
+        }
+        default: return FLIP_E_INVALID;
+    }
+    if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
+    if (!dst_is_device) HIP_TRY(hipStreamSynchronize(st));
+    return FLIP_OK;
+}
+
+flip_status flip_stats(flip_handle* h, flip_step_stats* out)
+{
+    if (!h || !out) return FLIP_E_INVALID;
+    HIP_TRY(hipStreamSynchronize(h->last_stream));
+    *out = h->stats;
+    return FLIP_OK;
+}
+
+void flip_destroy(flip_handle* h)
+{
+    if (!h) return;
+    if (h->last_stream) (void)hipStreamSynchronize(h->last_stream);
+    for (auto& e : h->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (h->h_ps) (void)hipHostFree(h->h_ps);
+    if (h->h_nactive) (void)hipHostFree(h->h_nactive);
+    delete h;
+}
+
+}  // extern "C"

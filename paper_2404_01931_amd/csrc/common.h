@@ -1,0 +1,109 @@
+// Internal declarations shared by the library's translation units (not public).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flipmi {
+
+// PCG vectors live in 8x8x8 tiles of cells; only tiles holding a fluid cell
+// are stored ("active" tiles). Inside a tile, cells are x-fastest.
+constexpr int TILE = 8;
+constexpr int TILE_CELLS = TILE * TILE * TILE;
+
+// Grid geometry passed by value to every kernel.
+struct Geo {
+    int nx, ny, nz;     // cells per axis
+    int tx, ty, tz;     // tiles per axis (ceil(n / 8))
+    double dx, inv_dx;
+};
+
+// Solver state shared between the PCG kernels of one solve. Written only by
+// the last block of a reduction kernel; read by every block of the next one.
+struct PcgState {
+    double rho;        // r . z of the current residual
+    double alpha;      // step length of the current iteration
+    double beta;       // direction update factor for the next iteration
+    double max_b;      // max |b| over fluid cells
+    double max_r;      // max |r| after the last update
+    double tol;        // relative tolerance
+    int iter;          // completed iterations
+    int max_iters;
+    int done;          // 0 running, 1 converged, 2 max iterations, 3 breakdown
+    int nfluid;        // fluid cells of this solve
+    unsigned counter;  // blocks finished in the current reduction kernel
+    int n_active;      // active tiles
+};
+
+enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAX_ITERS = 2, PCG_BREAKDOWN = 3 };
+
+// Maximum number of blocks whose partial results one reduction kernel can
+// hold (one block per active tile).
+inline int64_t tiles_of(const Geo& g) { return (int64_t)g.tx * g.ty * g.tz; }
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files, explicit instantiations for float
+// and double). All are asynchronous on `st`.
+// ---------------------------------------------------------------------------
+
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+void launch_fill_bytes_zero(void* p, int64_t bytes, hipStream_t st);
+
+template <typename T>
+void launch_bin_keys(const Geo& g, const T* pos, int64_t n, uint32_t* key, uint32_t* rank,
+                     uint32_t* count, hipStream_t st);
+// exclusive scan of n u32 values; tmp needs scan_tmp_words(n) u32 words
+int64_t scan_tmp_words(int64_t n);
+void launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp,
+                               hipStream_t st);
+void launch_bin_scatter(const uint32_t* key, const uint32_t* rank, const uint32_t* start,
+                        int64_t n, uint32_t* perm, hipStream_t st);
+template <typename T>
+void launch_bin_gather(const uint32_t* perm, const uint32_t* key, const uint32_t* start,
+                       const uint32_t* count, int64_t n, const T* pos_in, const T* vel_in,
+                       const uint32_t* id_in, T* pos_out, T* vel_out, uint32_t* id_out,
+                       hipStream_t st);
+
+// tiles: flags -> scan -> compaction -> neighbour table; writes the active
+// count to *d_nactive
+void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint32_t* tile_excl,
+                  int32_t* tile_slot, uint32_t* tile_list, int32_t* tile_nbr, uint32_t* d_nactive,
+                  uint32_t* scan_tmp, hipStream_t st);
+
+template <typename T>
+void launch_p2g(const Geo& g, int axis, const T* pos, int64_t n, const T* vel_axis,
+                const uint32_t* start, const uint32_t* count, T accel_dt, T* out_old, T* out_star,
+                hipStream_t st);
+
+// right-hand side, solver start, and the two kernels of one PCG iteration;
+// grid = one 512-thread workgroup per active tile. `partials` holds
+// 3 * pstride doubles, pstride >= n_active.
+template <typename T, typename V>
+void launch_rhs(const Geo& g, int n_active, const uint32_t* tile_list, const uint32_t* count,
+                const T* u, const T* v, const T* w, double scale, uint8_t* diag, V* b, V* z, V* x,
+                V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev, double tol,
+                int max_iters, hipStream_t st);
+template <typename V>
+void launch_pcg_direction(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
+                          const V* s_old, V* s_new, double* partials, PcgState* st_dev,
+                          hipStream_t st);
+template <typename V>
+void launch_pcg_update(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
+                       V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st);
+
+template <typename T, typename V>
+void launch_project(const Geo& g, int axis, const uint32_t* count, const int32_t* tile_slot,
+                    const V* p, const T* star, T* out, T scale, hipStream_t st);
+
+template <typename T>
+void launch_g2p(const Geo& g, int64_t n, T* pos, T* vel, const T* u_new, const T* v_new,
+                const T* w_new, const T* u_old, const T* v_old, const T* w_old, T alpha, T dt,
+                int advect_particle_vel, hipStream_t st);
+
+template <typename V, typename O>
+void launch_densify(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const V* src,
+                    O* dst, hipStream_t st);
+void launch_flags_from_count(const uint32_t* count, int64_t ncells, uint8_t* flags,
+                             hipStream_t st);
+
+}  // namespace flipmi

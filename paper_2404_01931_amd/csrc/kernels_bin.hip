@@ -1,0 +1,383 @@
+// Particle binning by cell (paper Sec. 3.1.5, Fig. 4; GPU variant Sec. 3.2.2):
+// raw cell index per particle, per-cell counts, exclusive scan (the space
+// hash's start offsets), a stable counting sort of the particles, and the
+// list of active 8x8x8 tiles used by the pressure solve.
+//
+// Stability without a global order of atomics: each particle first takes a
+// provisional slot inside its cell's segment (an atomic rank, order
+// arbitrary), then its final slot is its rank by original index among the
+// particles of the same cell. The result equals a stable sort by key and is
+// the same on every run.
+#include "common.h"
+#include "device_util.h"
+
+namespace flipmi {
+
+// ---------------------------------------------------------------------------
+// fills
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
+__global__ __launch_bounds__(256) void k_zero_bytes(uint8_t* p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+void launch_fill_bytes_zero(void* p, int64_t bytes, hipStream_t st)
+{
+    if (bytes <= 0) return;
+    if ((bytes & 3) == 0 && ((uintptr_t)p & 3) == 0) {
+        launch_fill_u32((uint32_t*)p, bytes / 4, 0u, st);
+        return;
+    }
+    hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)((bytes + 255) / 256)), dim3(256), 0, st,
+                       (uint8_t*)p, bytes);
+}
+
+// ---------------------------------------------------------------------------
+// raw cell index and count (one thread per particle)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_keys(Geo g, const T* __restrict__ px,
+                                                  const T* __restrict__ py, const T* __restrict__ pz,
+                                                  int64_t n, uint32_t* __restrict__ key,
+                                                  uint32_t* __restrict__ rank,
+                                                  uint32_t* __restrict__ count)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const int i = exact_cell_floor((double)px[p], g.dx, g.inv_dx, g.nx);
+    const int j = exact_cell_floor((double)py[p], g.dx, g.inv_dx, g.ny);
+    const int k = exact_cell_floor((double)pz[p], g.dx, g.inv_dx, g.nz);
+    const uint32_t c = (uint32_t)(i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
+    key[p] = c;
+
+    // Lanes of a wave that share a cell take their provisional ranks from
+    // one atomic: particles arrive mostly sorted, so a wave touches few cells.
+    const int lane = lane_id();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    bool pending = true;
+    uint32_t my_rank = 0;
+    for (;;) {
+        const uint64_t pend = __ballot(pending);
+        if (pend == 0ull) break;
+        const int leader = __ffsll((unsigned long long)pend) - 1;
+        const uint32_t lc = __shfl(c, leader, WAVE);
+        const bool mine = pending && (c == lc);
+        const uint64_t same = __ballot(mine);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&count[lc], (uint32_t)__popcll(same));
+        base = __shfl(base, leader, WAVE);
+        if (mine) {
+            my_rank = base + (uint32_t)__popcll(same & below);
+            pending = false;
+        }
+    }
+    rank[p] = my_rank;
+}
+
+template <typename T>
+void launch_bin_keys(const Geo& g, const T* pos, int64_t n, uint32_t* key, uint32_t* rank,
+                     uint32_t* count, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_bin_keys<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, pos,
+                       pos + n, pos + 2 * n, n, key, rank, count);
+}
+
+template void launch_bin_keys<float>(const Geo&, const float*, int64_t, uint32_t*, uint32_t*,
+                                     uint32_t*, hipStream_t);
+template void launch_bin_keys<double>(const Geo&, const double*, int64_t, uint32_t*, uint32_t*,
+                                      uint32_t*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// exclusive scan of u32 (all-prefix-sums with identity 0, Sec. 3.2.2)
+// Three passes: per-block totals, a scan of the totals by one block, and a
+// rescan of each block with its offset. 256 threads x 16 items per block.
+// ---------------------------------------------------------------------------
+
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_NT * SCAN_ITEMS;
+
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, WAVE);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan across the block of one value per thread; returns the
+// thread's exclusive prefix and the block total in *total
+template <int NT>
+__device__ inline uint32_t block_excl_scan_u32(uint32_t v, uint32_t* sh, uint32_t* total)
+{
+    const int w = threadIdx.x / WAVE;
+    uint32_t incl = wave_incl_scan_u32(v);
+    __syncthreads();
+    if (lane_id() == WAVE - 1) sh[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int i = 0; i < NT / WAVE; ++i) {
+            uint32_t t = sh[i];
+            sh[i] = run;
+            run += t;
+        }
+        sh[NT / WAVE] = run;
+    }
+    __syncthreads();
+    *total = sh[NT / WAVE];
+    return incl - v + sh[w];
+}
+
+__global__ __launch_bounds__(SCAN_NT) void k_scan_totals(const uint32_t* __restrict__ in, int64_t n,
+                                                         uint32_t* __restrict__ totals)
+{
+    __shared__ uint32_t sh[SCAN_NT / WAVE + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    uint32_t s = 0;
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        int64_t i = base + it * SCAN_NT + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    uint32_t total;
+    block_excl_scan_u32<SCAN_NT>(s, sh, &total);
+    if (threadIdx.x == 0) totals[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of nb totals in place, chunk by chunk
+__global__ __launch_bounds__(1024) void k_scan_totals_scan(uint32_t* __restrict__ totals, int64_t nb)
+{
+    __shared__ uint32_t sh[1024 / WAVE + 1];
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        int64_t i = c0 + threadIdx.x;
+        uint32_t v = i < nb ? totals[i] : 0u;
+        uint32_t total;
+        uint32_t ex = block_excl_scan_u32<1024>(v, sh, &total);
+        if (i < nb) totals[i] = ex + carry;
+        carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const uint32_t* __restrict__ in,
+                                                        uint32_t* __restrict__ out, int64_t n,
+                                                        const uint32_t* __restrict__ offsets)
+{
+    // items of the tile staged in LDS; thread t owns items [16 t, 16 t + 16),
+    // padded by one word per 32 to spread LDS banks
+    __shared__ uint32_t tile[SCAN_TILE + SCAN_TILE / 32];
+    __shared__ uint32_t sh[SCAN_NT / WAVE + 1];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+#define PAD(i) ((i) + ((i) >> 5))
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        int li = it * SCAN_NT + threadIdx.x;
+        int64_t i = base + li;
+        tile[PAD(li)] = i < n ? in[i] : 0u;
+    }
+    __syncthreads();
+    uint32_t vals[SCAN_ITEMS];
+    uint32_t s = 0;
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        vals[it] = tile[PAD(threadIdx.x * SCAN_ITEMS + it)];
+        s += vals[it];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan_u32<SCAN_NT>(s, sh, &total) + offsets[blockIdx.x];
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        tile[PAD(threadIdx.x * SCAN_ITEMS + it)] = run;
+        run += vals[it];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SCAN_ITEMS; ++it) {
+        int li = it * SCAN_NT + threadIdx.x;
+        int64_t i = base + li;
+        if (i < n) out[i] = tile[PAD(li)];
+    }
+#undef PAD
+}
+
+int64_t scan_tmp_words(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+void launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp,
+                               hipStream_t st)
+{
+    if (n <= 0) return;
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_totals, dim3((unsigned)nb), dim3(SCAN_NT), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_totals_scan, dim3(1), dim3(1024), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_NT), 0, st, in, out, n, tmp);
+}
+
+// ---------------------------------------------------------------------------
+// stable counting sort
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t* __restrict__ key,
+                                                     const uint32_t* __restrict__ rank,
+                                                     const uint32_t* __restrict__ start, int64_t n,
+                                                     uint32_t* __restrict__ perm)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    perm[start[key[p]] + rank[p]] = (uint32_t)p;
+}
+
+void launch_bin_scatter(const uint32_t* key, const uint32_t* rank, const uint32_t* start,
+                        int64_t n, uint32_t* perm, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, key, rank,
+                       start, n, perm);
+}
+
+// Slot s of the provisional order holds particle p; p's final slot is the
+// start of its cell plus the number of particles of that cell with a smaller
+// original index. The particle's state moves there (double buffer, Sec. 3.2.2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_gather(
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ count, int64_t n,
+    const T* __restrict__ pos_in, const T* __restrict__ vel_in, const uint32_t* __restrict__ id_in,
+    T* __restrict__ pos_out, T* __restrict__ vel_out, uint32_t* __restrict__ id_out)
+{
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t p = perm[s];
+    const uint32_t c = key[p];
+    const uint32_t st = start[c];
+    const uint32_t cnt = count[c];
+    uint32_t r = 0;
+    for (uint32_t q = st; q < st + cnt; ++q) r += (perm[q] < p) ? 1u : 0u;
+    const int64_t d = (int64_t)st + r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        pos_out[a * n + d] = pos_in[a * n + p];
+        vel_out[a * n + d] = vel_in[a * n + p];
+    }
+    id_out[d] = id_in[p];
+}
+
+template <typename T>
+void launch_bin_gather(const uint32_t* perm, const uint32_t* key, const uint32_t* start,
+                       const uint32_t* count, int64_t n, const T* pos_in, const T* vel_in,
+                       const uint32_t* id_in, T* pos_out, T* vel_out, uint32_t* id_out,
+                       hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_bin_gather<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm,
+                       key, start, count, n, pos_in, vel_in, id_in, pos_out, vel_out, id_out);
+}
+
+template void launch_bin_gather<float>(const uint32_t*, const uint32_t*, const uint32_t*,
+                                       const uint32_t*, int64_t, const float*, const float*,
+                                       const uint32_t*, float*, float*, uint32_t*, hipStream_t);
+template void launch_bin_gather<double>(const uint32_t*, const uint32_t*, const uint32_t*,
+                                        const uint32_t*, int64_t, const double*, const double*,
+                                        const uint32_t*, double*, double*, uint32_t*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// active tiles (the fluid-cells vector of Sec. 3.1.5, at tile granularity)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_tile_flags(Geo g, const uint32_t* __restrict__ count,
+                                                    uint32_t* __restrict__ tile_flag)
+{
+    const int t = blockIdx.x;
+    const int ti = t % g.tx, tj = (t / g.tx) % g.ty, tk = t / (g.tx * g.ty);
+    int any = 0;
+    for (int l = threadIdx.x; l < TILE_CELLS; l += 256) {
+        const int i = ti * TILE + (l & 7), j = tj * TILE + ((l >> 3) & 7), k = tk * TILE + (l >> 6);
+        if (i < g.nx && j < g.ny && k < g.nz)
+            any |= count[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)] > 0;
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) tile_flag[t] = any ? 1u : 0u;
+}
+
+// slot of each tile (-1 when inactive), the active list, and for every
+// active tile the slots of its six face neighbours (-x,+x,-y,+y,-z,+z; -1 when
+// outside the domain or inactive)
+__global__ __launch_bounds__(256) void k_tile_compact(Geo g, const uint32_t* __restrict__ flag,
+                                                      const uint32_t* __restrict__ excl,
+                                                      int32_t* __restrict__ tile_slot,
+                                                      uint32_t* __restrict__ tile_list,
+                                                      int32_t* __restrict__ tile_nbr,
+                                                      uint32_t* __restrict__ d_nactive)
+{
+    const int64_t T = (int64_t)g.tx * g.ty * g.tz;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= T) return;
+    if (t == T - 1) *d_nactive = excl[t] + flag[t];
+    if (!flag[t]) {
+        tile_slot[t] = -1;
+        return;
+    }
+    const int32_t slot = (int32_t)excl[t];
+    tile_slot[t] = slot;
+    tile_list[slot] = (uint32_t)t;
+    const int ti = (int)(t % g.tx), tj = (int)((t / g.tx) % g.ty), tk = (int)(t / ((int64_t)g.tx * g.ty));
+    const int off[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const int a = ti + off[d][0], b = tj + off[d][1], c = tk + off[d][2];
+        int32_t ns = -1;
+        if (a >= 0 && a < g.tx && b >= 0 && b < g.ty && c >= 0 && c < g.tz) {
+            const int64_t tn = a + (int64_t)g.tx * (b + (int64_t)g.ty * c);
+            if (flag[tn]) ns = (int32_t)excl[tn];
+        }
+        tile_nbr[(int64_t)slot * 6 + d] = ns;
+    }
+}
+
+void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint32_t* tile_excl,
+                  int32_t* tile_slot, uint32_t* tile_list, int32_t* tile_nbr, uint32_t* d_nactive,
+                  uint32_t* scan_tmp, hipStream_t st)
+{
+    const int64_t T = tiles_of(g);
+    hipLaunchKernelGGL(k_tile_flags, dim3((unsigned)T), dim3(256), 0, st, g, count, tile_flag);
+    launch_exclusive_scan_u32(tile_flag, tile_excl, T, scan_tmp, st);
+    hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, g,
+                       tile_flag, tile_excl, tile_slot, tile_list, tile_nbr, d_nactive);
+}
+
+__global__ __launch_bounds__(256) void k_flags_from_count(const uint32_t* __restrict__ count,
+                                                          int64_t n, uint8_t* __restrict__ flags)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) flags[i] = count[i] > 0 ? 1 : 0;
+}
+
+void launch_flags_from_count(const uint32_t* count, int64_t ncells, uint8_t* flags,
+                             hipStream_t st)
+{
+    if (ncells <= 0) return;
+    hipLaunchKernelGGL(k_flags_from_count, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0,
+                       st, count, ncells, flags);
+}
+
+}  // namespace flipmi

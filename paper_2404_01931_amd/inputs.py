@@ -10,7 +10,8 @@ only by particle count and grid size:
 * ``drop256``    drop into a pool, 256^3: pool y < 0.3 plus a sphere of radius
                  0.15 at (0.5, 0.7, 0.5) moving at (0, -1, 0), FP32
 * ``drop256_mixed`` the same scene with the mixed-precision solver
-* ``drop64``     the drop scene downscaled to 64^3
+* ``drop64``     the drop scene downscaled to 64^3 (mixed-precision comparison size)
+* ``drop128``    the drop scene at 128^3 (bounded sample for the CPU baseline)
 
 Every scene uses 2 x 2 x 2 jittered subcells per fluid cell (paper Fig. 3),
 gravity (0, -9.81, 0) and solid walls on all six domain faces.
@@ -78,6 +79,8 @@ SCENES = {
                           flip_ratio=0.97, tol=1e-6, steps=30),
     "drop64": drop(64, name="drop64", seed=4, precision="fp32", dt=1 / 960,
                    flip_ratio=0.97, tol=1e-6, steps=30),
+    "drop128": drop(128, name="drop128", seed=3, precision="fp32", dt=1 / 960,
+                    flip_ratio=0.97, tol=1e-6, steps=30),
 }
 
 
