@@ -46,7 +46,7 @@ def algorithmic_bytes(kind: str, rb: int, n: int, cells: int, faces: list, fluid
         "bin_scatter": 16 * n,                          # key, rank, start in; slot out
         "bin_gather": n * (12 * rb + 20),               # slot, key, start, count, state in; state out
         "tiles": 4 * cells,                             # counts in
-        "p2g": n * 4 * rb + 8 * cells + 2 * rb * F / 3,  # one component: particles, hash in; 2 faces out
+        "p2g": n * 6 * rb + 8 * cells + 2 * rb * F,    # particles, hash in; raw and forced faces out
         "rhs": 3 * rb * F / 3 + fluid * (1 + 5 * rb),   # face differences in; diag, b, z, x, s out
         "pcg_direction": fluid * (3 * rb + 1),          # z, s_old, diag in; s out
         "pcg_update": fluid * (5 * rb + 1),             # x, s, z, diag in; x, z out

@@ -356,10 +356,13 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     const T* pos = (const T*)h->pos[h->cur];
     const T* vel = (const T*)h->vel[h->cur];
     const bool grav = !(c.flags & FLIP_FLAG_NO_GRAVITY);
-    for (int a = 0; a < 3; ++a) {
+    {
+        const T gdt[3] = {(T)(grav ? c.gravity[0] * c.dt : 0.0), (T)(grav ? c.gravity[1] * c.dt : 0.0),
+                          (T)(grav ? c.gravity[2] * c.dt : 0.0)};
+        T* const old[3] = {(T*)h->f_old[0], (T*)h->f_old[1], (T*)h->f_old[2]};
+        T* const star[3] = {(T*)h->f_star[0], (T*)h->f_star[1], (T*)h->f_star[2]};
         tq = timer_begin(h, FLIP_KERNEL_P2G, st);
-        launch_p2g<T>(g, a, pos, n, vel + a * n, h->start, h->count,
-                      (T)(grav ? c.gravity[a] * c.dt : 0.0), (T*)h->f_old[a], (T*)h->f_star[a], st);
+        launch_p2g<T>(g, pos, vel, n, h->start, h->count, gdt, old, star, st);
         timer_end(h, tq, st);
     }
 
@@ -405,7 +408,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
         h->prev_iters = ps_host.iter;
         h->ev_iter_limit = ps_host.iter;
         if (ps_host.done == PCG_MAX_ITERS || ps_host.done == PCG_RUNNING) ret = FLIP_E_NOT_CONVERGED;
-        if (ps_host.done == PCG_BREAKDOWN) ret = FLIP_E_NONFINITE;
+        if (ps_host.done == PCG_BREAKDOWN) ret = ps_host.sync_error ? FLIP_E_HIP : FLIP_E_NONFINITE;
         // 5. projection
         const T scale = (T)(c.dt / (c.density * c.dx));
         for (int a = 0; a < 3; ++a) {
@@ -565,6 +568,7 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
     }
     launch_fill_bytes_zero(h->diag, s.cap, st);
     launch_fill_bytes_zero(h->ps, sizeof(PcgState), st);
+    launch_fill_u64((uint64_t*)h->partials, 3 * s.T, SLOT_EMPTY_BITS, st);
     if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h->h_nactive, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
         flip_destroy(h);

@@ -33,12 +33,18 @@ struct PcgState {
     int nfluid;        // fluid cells of this solve
     unsigned counter;  // blocks finished in the current reduction kernel
     int n_active;      // active tiles
+    int sync_error;    // a partial result never became visible (reduction aborted)
+    int pad_;
 };
 
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAX_ITERS = 2, PCG_BREAKDOWN = 3 };
 
-// Maximum number of blocks whose partial results one reduction kernel can
-// hold (one block per active tile).
+// Upper bound on the workgroups of one PCG iteration kernel (8 per CU).
+constexpr int PCG_MAX_GROUPS = 2048;
+
+// Reduction slots hold this pattern when empty (see device_util.h).
+constexpr uint64_t SLOT_EMPTY_BITS = 0x7FF4DEADBEEF0001ull;
+
 inline int64_t tiles_of(const Geo& g) { return (int64_t)g.tx * g.ty * g.tz; }
 
 // ---------------------------------------------------------------------------
@@ -47,6 +53,7 @@ inline int64_t tiles_of(const Geo& g) { return (int64_t)g.tx * g.ty * g.tz; }
 // ---------------------------------------------------------------------------
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 void launch_fill_bytes_zero(void* p, int64_t bytes, hipStream_t st);
 
 template <typename T>
@@ -70,9 +77,10 @@ void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint
                   int32_t* tile_slot, uint32_t* tile_list, int32_t* tile_nbr, uint32_t* d_nactive,
                   uint32_t* scan_tmp, hipStream_t st);
 
+// particle-to-grid for all faces, with gravity (gdt = g * dt per axis) and walls
 template <typename T>
-void launch_p2g(const Geo& g, int axis, const T* pos, int64_t n, const T* vel_axis,
-                const uint32_t* start, const uint32_t* count, T accel_dt, T* out_old, T* out_star,
+void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint32_t* start,
+                const uint32_t* count, const T gdt[3], T* const old[3], T* const star[3],
                 hipStream_t st);
 
 // right-hand side, solver start, and the two kernels of one PCG iteration;

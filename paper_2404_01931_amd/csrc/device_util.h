@@ -85,39 +85,84 @@ __device__ inline double block_max(double v, double* sh)
     return s;
 }
 
-// Publish this block's partial results and report whether it is the last
-// block of the grid to do so. Called by every thread; the release fence
-// makes the partials visible device-wide (across XCDs) before the counter
-// increment, and the last block acquires before reading them.
-__device__ inline bool last_block_arrives(unsigned* counter, bool* sh_flag)
+// ---------------------------------------------------------------------------
+// Grid-wide reduction without a device-scope fence.
+//
+// A release fence at device scope makes the issuing CU write back its XCD's
+// whole L2, which costs far more than the kernel's own traffic when thousands
+// of workgroups each issue one. Instead, each workgroup publishes its partial
+// results into its own slots with relaxed device-scope atomic stores (coherent
+// across XCDs, nothing else is flushed) and counts itself in with a relaxed
+// atomic add. The workgroup that takes the count to the grid size reads every
+// slot; a slot whose store is not visible yet still holds the EMPTY pattern and
+// is re-read until it is (bounded; on exhaustion the error flag is set). Slots
+// are summed in index order, so the result is the same on every run, and are
+// reset to EMPTY for the next kernel.
+// ---------------------------------------------------------------------------
+
+// a signalling-NaN bit pattern: arithmetic never produces it
+constexpr unsigned long long SLOT_EMPTY = SLOT_EMPTY_BITS;
+constexpr int SLOT_MAX_POLLS = 1 << 20;
+
+__device__ inline void slot_store(double* slot, double v)
+{
+    __hip_atomic_store((unsigned long long*)slot, (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline unsigned long long slot_load(const double* slot)
+{
+    return __hip_atomic_load((unsigned long long*)slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 publishes vals[0..nq) into slots[q * stride + blockIdx.x]; returns
+// (in every thread) whether this workgroup is the last to arrive.
+__device__ inline bool publish_partials(double* slots, int64_t stride, const double* vals, int nq,
+                                        unsigned* counter, bool* sh_last)
 {
     if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        *sh_flag = (prev == gridDim.x - 1);
+        for (int q = 0; q < nq; ++q) slot_store(slots + q * stride + blockIdx.x, vals[q]);
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *sh_last = (prev == gridDim.x - 1);
     }
     __syncthreads();
-    bool last = *sh_flag;
-    if (last) __threadfence();
-    return last;
+    return *sh_last;
 }
 
-// Fixed-order reduction of nb partials by one block (sum or max). Callers
-// map non-finite magnitudes to +inf before a max so it cannot be lost.
-template <int NT>
-__device__ inline double reduce_partials_sum(const double* p, int nb, double* sh)
+// In the last workgroup: combine slots[0..nb) (sum, or max when MAX), reset
+// them to EMPTY. Loads are issued eight at a time per thread. *err is set
+// when a slot stayed EMPTY for SLOT_MAX_POLLS re-reads; after that the
+// thread stops waiting, so the block always finishes.
+template <int NT, bool MAX>
+__device__ inline double collect_slots(double* slots, int nb, double* sh, int* err)
 {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += NT) s += p[i];
-    return block_sum<NT>(s, sh);
-}
-
-template <int NT>
-__device__ inline double reduce_partials_max(const double* p, int nb, double* sh)
-{
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += NT) s = p[i] > s ? p[i] : s;
-    return block_max<NT>(s, sh);
+    double acc = 0.0;
+    for (int base = threadIdx.x; base < nb; base += 8 * NT) {
+        unsigned long long v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * NT;
+            v[u] = i < nb ? slot_load(slots + i) : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = base + u * NT;
+            if (i >= nb) continue;
+            for (int polls = 0; v[u] == SLOT_EMPTY && polls < SLOT_MAX_POLLS && !*err; ++polls) {
+                __builtin_amdgcn_s_sleep(1);
+                v[u] = slot_load(slots + i);
+            }
+            if (v[u] == SLOT_EMPTY) {
+                *err = 1;
+                v[u] = 0ull;
+            }
+            const double x = __longlong_as_double((long long)v[u]);
+            acc = MAX ? (x > acc ? x : acc) : acc + x;
+            __hip_atomic_store((unsigned long long*)(slots + i), SLOT_EMPTY, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    return MAX ? block_max<NT>(acc, sh) : block_sum<NT>(acc, sh);
 }
 
 }  // namespace flipmi

@@ -29,6 +29,18 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st)
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
 }
 
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, int64_t n, uint64_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
 __global__ __launch_bounds__(256) void k_zero_bytes(uint8_t* p, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;

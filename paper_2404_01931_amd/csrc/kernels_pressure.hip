@@ -111,16 +111,14 @@ __global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__
     const double rz = block_sum<PNT>((double)bq * (double)zq, red);
     const double mb = block_max<PNT>(finite_or_inf(fabs((double)bq)), red);
     const double nf = block_sum<PNT>(d ? 1.0 : 0.0, red);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = rz;
-        partials[pstride + blockIdx.x] = mb;
-        partials[2 * pstride + blockIdx.x] = nf;
-    }
-    if (!last_block_arrives(&ps->counter, &last)) return;
+    const double vals[3] = {rz, mb, nf};
+    if (!publish_partials(partials, pstride, vals, 3, &ps->counter, &last)) return;
     const int nb = gridDim.x;
-    const double rho = reduce_partials_sum<PNT>(partials, nb, red);
-    const double max_b = reduce_partials_max<PNT>(partials + pstride, nb, red);
-    const double nfl = reduce_partials_sum<PNT>(partials + 2 * pstride, nb, red);
+    int err = 0;
+    const double rho = collect_slots<PNT, false>(partials, nb, red, &err);
+    const double max_b = collect_slots<PNT, true>(partials + pstride, nb, red, &err);
+    const double nfl = collect_slots<PNT, false>(partials + 2 * pstride, nb, red, &err);
+    err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         ps->rho = rho;
         ps->alpha = 0.0;
@@ -136,7 +134,9 @@ __global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__
                    : (max_b == 0.0)    ? PCG_CONVERGED
                    : (max_iters <= 0)  ? PCG_MAX_ITERS
                                        : PCG_RUNNING;
-        ps->counter = 0u;
+        ps->sync_error = err;
+        if (err) ps->done = PCG_BREAKDOWN;
+        __hip_atomic_store(&ps->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -162,54 +162,106 @@ template void launch_rhs<double, double>(const Geo&, int, const uint32_t*, const
                                          double*, int64_t, PcgState*, double, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// direction kernel: s = z + beta s_old, q = A s, sigma = s.q
+// The two iteration kernels run a bounded number of 256-thread workgroups
+// (at most PCG_MAX_GROUPS); each walks a contiguous range of active tiles, so
+// that the workgroups of one XCD cover one spatial chunk of the tile list and
+// share its halos in L2. A thread owns cells tid and tid + 256 of the current
+// tile and stages up to two of its 384 halo cells. LDS is double-buffered
+// and the next tile's values are loaded into registers before the current
+// tile's stencil is evaluated, so loads overlap arithmetic and one barrier
+// per tile suffices.
 // ---------------------------------------------------------------------------
 
-template <typename V>
-__global__ __launch_bounds__(PNT) void k_pcg_direction(const int32_t* __restrict__ nbr,
-                                                       const uint8_t* __restrict__ diag,
-                                                       const V* __restrict__ z,
-                                                       const V* __restrict__ s_old,
-                                                       V* __restrict__ s_new,
-                                                       double* __restrict__ partials,
-                                                       PcgState* __restrict__ ps)
+constexpr int PCG_NT = 256;
+
+__device__ inline int64_t halo_elem(const int32_t* __restrict__ nbr, int slot, int h)
 {
-    __shared__ V stg[STAGE];
-    __shared__ double red[PNT / WAVE];
+    const int f = h >> 6;
+    const int32_t ns = nbr[(int64_t)slot * 6 + f];
+    return ns >= 0 ? (int64_t)ns * TILE_CELLS + halo_source(f, h & 63) : (int64_t)-1;
+}
+
+__device__ inline void tile_range(int n_tiles, int& t0, int& t1)
+{
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    t0 = (int)((int64_t)n_tiles * L / gridDim.x);
+    t1 = (int)((int64_t)n_tiles * (L + 1) / gridDim.x);
+}
+
+// direction kernel: s = z + beta s_old, q = A s, sigma = s.q
+template <typename V>
+__global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restrict__ nbr,
+                                                          const uint8_t* __restrict__ diag,
+                                                          const V* __restrict__ z,
+                                                          const V* __restrict__ s_old,
+                                                          V* __restrict__ s_new,
+                                                          double* __restrict__ partials,
+                                                          PcgState* __restrict__ ps, int n_tiles)
+{
+    __shared__ V stg[2][STAGE];
+    __shared__ double red[PCG_NT / WAVE];
     __shared__ bool last;
     if (ps->done != PCG_RUNNING) return;
     const V beta = (V)ps->beta;
-    const int slot = xcd_remap(blockIdx.x, gridDim.x);
-    const int l = threadIdx.x;
-    const int64_t e = (int64_t)slot * TILE_CELLS + l;
-    const V sc = fma(beta, s_old[e], z[e]);
-    const int d = diag[e];
-    s_new[e] = sc;
-    stg[l] = sc;
-    if (l < HALO) {
-        const int f = l >> 6;
-        const int32_t ns = nbr[(int64_t)slot * 6 + f];
-        V hv = V(0);
-        if (ns >= 0) {
-            const int64_t en = (int64_t)ns * TILE_CELLS + halo_source(f, l & 63);
-            hv = fma(beta, s_old[en], z[en]);
+    const int tid = threadIdx.x;
+    const bool two_halo = tid < HALO - PCG_NT;
+    int t0, t1;
+    tile_range(n_tiles, t0, t1);
+    // prefetched raw values of the next tile
+    V nz0 = 0, nz1 = 0, ns0 = 0, ns1 = 0, hz0 = 0, hs0 = 0, hz1 = 0, hs1 = 0;
+    int nd0 = 0, nd1 = 0;
+    auto fetch = [&](int slot) {
+        const int64_t e = (int64_t)slot * TILE_CELLS + tid;
+        nz0 = z[e];
+        ns0 = s_old[e];
+        nz1 = z[e + PCG_NT];
+        ns1 = s_old[e + PCG_NT];
+        nd0 = diag[e];
+        nd1 = diag[e + PCG_NT];
+        const int64_t h0 = halo_elem(nbr, slot, tid);
+        hz0 = h0 >= 0 ? z[h0] : V(0);
+        hs0 = h0 >= 0 ? s_old[h0] : V(0);
+        if (two_halo) {
+            const int64_t h1 = halo_elem(nbr, slot, tid + PCG_NT);
+            hz1 = h1 >= 0 ? z[h1] : V(0);
+            hs1 = h1 >= 0 ? s_old[h1] : V(0);
         }
-        stg[TILE_CELLS + l] = hv;
+    };
+    double acc = 0.0;
+    if (t0 < t1) fetch(t0);
+    for (int t = t0, buf = 0; t < t1; ++t, buf ^= 1) {
+        V* st = stg[buf];
+        const V sc0 = fma(beta, ns0, nz0), sc1 = fma(beta, ns1, nz1);
+        const int d0 = nd0, d1 = nd1;
+        st[tid] = sc0;
+        st[tid + PCG_NT] = sc1;
+        st[TILE_CELLS + tid] = fma(beta, hs0, hz0);
+        if (two_halo) st[TILE_CELLS + PCG_NT + tid] = fma(beta, hs1, hz1);
+        const int64_t e = (int64_t)t * TILE_CELLS + tid;
+        s_new[e] = sc0;
+        s_new[e + PCG_NT] = sc1;
+        if (t + 1 < t1) fetch(t + 1);
+        __syncthreads();
+        const V q0 = d0 ? fma((V)d0, sc0, -neighbour_sum(st, tid)) : V(0);
+        const V q1 = d1 ? fma((V)d1, sc1, -neighbour_sum(st, tid + PCG_NT)) : V(0);
+        acc += (double)sc0 * (double)q0 + (double)sc1 * (double)q1;
     }
-    __syncthreads();
-    const V q = d ? (V)d * sc - neighbour_sum(stg, l) : V(0);
-    const double part = block_sum<PNT>((double)sc * (double)q, red);
-    if (threadIdx.x == 0) partials[blockIdx.x] = part;
-    if (!last_block_arrives(&ps->counter, &last)) return;
-    const double sigma = reduce_partials_sum<PNT>(partials, gridDim.x, red);
+    const double part = block_sum<PCG_NT>(acc, red);
+    if (!publish_partials(partials, 0, &part, 1, &ps->counter, &last)) return;
+    int err = 0;
+    const double sigma = collect_slots<PCG_NT, false>(partials, gridDim.x, red, &err);
+    err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
-        if (!(sigma > 0.0) || !(sigma <= DBL_MAX))
+        if (!(sigma > 0.0) || !(sigma <= DBL_MAX) || err)
             ps->done = PCG_BREAKDOWN;
         else
             ps->alpha = ps->rho / sigma;
-        ps->counter = 0u;
+        if (err) ps->sync_error = 1;
+        __hip_atomic_store(&ps->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
+
+int pcg_groups(int n_active) { return n_active < PCG_MAX_GROUPS ? n_active : PCG_MAX_GROUPS; }
 
 template <typename V>
 void launch_pcg_direction(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
@@ -217,8 +269,8 @@ void launch_pcg_direction(int n_active, const int32_t* tile_nbr, const uint8_t* 
                           hipStream_t st)
 {
     if (n_active <= 0) return;
-    hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)n_active), dim3(PNT), 0, st, tile_nbr,
-                       diag, z, s_old, s_new, partials, st_dev);
+    hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)pcg_groups(n_active)), dim3(PCG_NT), 0, st,
+                       tile_nbr, diag, z, s_old, s_new, partials, st_dev, n_active);
 }
 
 template void launch_pcg_direction<float>(int, const int32_t*, const uint8_t*, const float*,
@@ -227,58 +279,88 @@ template void launch_pcg_direction<double>(int, const int32_t*, const uint8_t*, 
                                            const double*, double*, double*, PcgState*,
                                            hipStream_t);
 
-// ---------------------------------------------------------------------------
 // update kernel: x += alpha s; r = n z - alpha A s; z = r / n; r.z; max|r|
-// ---------------------------------------------------------------------------
-
 template <typename V>
-__global__ __launch_bounds__(PNT) void k_pcg_update(const int32_t* __restrict__ nbr,
-                                                    const uint8_t* __restrict__ diag,
-                                                    const V* __restrict__ s, V* __restrict__ x,
-                                                    V* __restrict__ z, double* __restrict__ partials,
-                                                    int64_t pstride, PcgState* __restrict__ ps)
+__global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict__ nbr,
+                                                       const uint8_t* __restrict__ diag,
+                                                       const V* __restrict__ s, V* __restrict__ x,
+                                                       V* __restrict__ z, double* __restrict__ partials,
+                                                       int64_t pstride, PcgState* __restrict__ ps,
+                                                       int n_tiles)
 {
-    __shared__ V stg[STAGE];
-    __shared__ double red[PNT / WAVE];
+    __shared__ V stg[2][STAGE];
+    __shared__ double red[PCG_NT / WAVE];
     __shared__ bool last;
     if (ps->done != PCG_RUNNING) return;
     const V alpha = (V)ps->alpha;
-    const int slot = xcd_remap(blockIdx.x, gridDim.x);
-    const int l = threadIdx.x;
-    const int64_t e = (int64_t)slot * TILE_CELLS + l;
-    const V sc = s[e];
-    const int d = diag[e];
-    stg[l] = sc;
-    if (l < HALO) {
-        const int f = l >> 6;
-        const int32_t ns = nbr[(int64_t)slot * 6 + f];
-        stg[TILE_CELLS + l] = ns >= 0 ? s[(int64_t)ns * TILE_CELLS + halo_source(f, l & 63)] : V(0);
-    }
-    __syncthreads();
+    const int tid = threadIdx.x;
+    const bool two_halo = tid < HALO - PCG_NT;
+    int t0, t1;
+    tile_range(n_tiles, t0, t1);
+    V ns0 = 0, ns1 = 0, nx0 = 0, nx1 = 0, nz0 = 0, nz1 = 0, h0v = 0, h1v = 0;
+    int nd0 = 0, nd1 = 0;
+    auto fetch = [&](int slot) {
+        const int64_t e = (int64_t)slot * TILE_CELLS + tid;
+        ns0 = s[e];
+        ns1 = s[e + PCG_NT];
+        nx0 = x[e];
+        nx1 = x[e + PCG_NT];
+        nz0 = z[e];
+        nz1 = z[e + PCG_NT];
+        nd0 = diag[e];
+        nd1 = diag[e + PCG_NT];
+        const int64_t h0 = halo_elem(nbr, slot, tid);
+        h0v = h0 >= 0 ? s[h0] : V(0);
+        if (two_halo) {
+            const int64_t h1 = halo_elem(nbr, slot, tid + PCG_NT);
+            h1v = h1 >= 0 ? s[h1] : V(0);
+        }
+    };
     double rz = 0.0, rmax = 0.0;
-    if (d) {
-        const V q = (V)d * sc - neighbour_sum(stg, l);
-        x[e] = fma(alpha, sc, x[e]);
-        const V r = fma((V)d, z[e], -alpha * q);
-        const V zn = r / (V)d;
-        z[e] = zn;
-        rz = (double)r * (double)zn;
-        rmax = finite_or_inf(fabs((double)r));
+    if (t0 < t1) fetch(t0);
+    for (int t = t0, buf = 0; t < t1; ++t, buf ^= 1) {
+        V* st = stg[buf];
+        const V sc0 = ns0, sc1 = ns1, xc0 = nx0, xc1 = nx1, zc0 = nz0, zc1 = nz1;
+        const int d0 = nd0, d1 = nd1;
+        st[tid] = sc0;
+        st[tid + PCG_NT] = sc1;
+        st[TILE_CELLS + tid] = h0v;
+        if (two_halo) st[TILE_CELLS + PCG_NT + tid] = h1v;
+        if (t + 1 < t1) fetch(t + 1);
+        __syncthreads();
+        const int64_t e = (int64_t)t * TILE_CELLS + tid;
+        if (d0) {
+            const V q = fma((V)d0, sc0, -neighbour_sum(st, tid));  // same rounding as the direction kernel
+            x[e] = fma(alpha, sc0, xc0);
+            const V r = fma((V)d0, zc0, -alpha * q);
+            const V zn = r / (V)d0;
+            z[e] = zn;
+            rz += (double)r * (double)zn;
+            rmax = fmax(rmax, finite_or_inf(fabs((double)r)));
+        }
+        if (d1) {
+            const V q = fma((V)d1, sc1, -neighbour_sum(st, tid + PCG_NT));
+            x[e + PCG_NT] = fma(alpha, sc1, xc1);
+            const V r = fma((V)d1, zc1, -alpha * q);
+            const V zn = r / (V)d1;
+            z[e + PCG_NT] = zn;
+            rz += (double)r * (double)zn;
+            rmax = fmax(rmax, finite_or_inf(fabs((double)r)));
+        }
     }
-    const double prz = block_sum<PNT>(rz, red);
-    const double pmx = block_max<PNT>(rmax, red);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = prz;
-        partials[pstride + blockIdx.x] = pmx;
-    }
-    if (!last_block_arrives(&ps->counter, &last)) return;
-    const double rho_new = reduce_partials_sum<PNT>(partials, gridDim.x, red);
-    const double max_r = reduce_partials_max<PNT>(partials + pstride, gridDim.x, red);
+    const double prz = block_sum<PCG_NT>(rz, red);
+    const double pmx = block_max<PCG_NT>(rmax, red);
+    const double vals[2] = {prz, pmx};
+    if (!publish_partials(partials, pstride, vals, 2, &ps->counter, &last)) return;
+    int err = 0;
+    const double rho_new = collect_slots<PCG_NT, false>(partials, gridDim.x, red, &err);
+    const double max_r = collect_slots<PCG_NT, true>(partials + pstride, gridDim.x, red, &err);
+    err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         const int it = ps->iter + 1;
         ps->iter = it;
         ps->max_r = max_r;
-        if (!(max_r <= DBL_MAX) || !(fabs(rho_new) <= DBL_MAX))
+        if (!(max_r <= DBL_MAX) || !(fabs(rho_new) <= DBL_MAX) || err)
             ps->done = PCG_BREAKDOWN;
         else if (max_r <= ps->tol * ps->max_b)
             ps->done = PCG_CONVERGED;
@@ -286,7 +368,8 @@ __global__ __launch_bounds__(PNT) void k_pcg_update(const int32_t* __restrict__ 
             ps->done = PCG_MAX_ITERS;
         ps->beta = rho_new / ps->rho;
         ps->rho = rho_new;
-        ps->counter = 0u;
+        if (err) ps->sync_error = 1;
+        __hip_atomic_store(&ps->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -295,8 +378,8 @@ void launch_pcg_update(int n_active, const int32_t* tile_nbr, const uint8_t* dia
                        V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st)
 {
     if (n_active <= 0) return;
-    hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)n_active), dim3(PNT), 0, st, tile_nbr, diag,
-                       s, x, z, partials, pstride, st_dev);
+    hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)pcg_groups(n_active)), dim3(PCG_NT), 0, st,
+                       tile_nbr, diag, s, x, z, partials, pstride, st_dev, n_active);
 }
 
 template void launch_pcg_update<float>(int, const int32_t*, const uint8_t*, const float*, float*,
