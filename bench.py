@@ -116,7 +116,21 @@ def main():
     ap.add_argument("--scene", default="drop256")
     ap.add_argument("--cpu-sample", default="drop128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (scales HBM counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        torch.cuda.set_device(0)
+        n = args.calibrate_copy * 2**20 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the timestep has no multi-GPU "
               f"path in this build", file=sys.stderr)

@@ -90,9 +90,12 @@ typedef struct {
     double dt;                 /* fixed time step, > 0                                     */
     double flip_ratio;         /* blending factor alpha in [0, 1]: v = PIC + alpha(FLIP-PIC)*/
     double density;            /* rho > 0 (scales the pressure only)                       */
-    double pcg_tol;            /* stop when max|r| <= pcg_tol * max|b| over fluid cells     */
+    double pcg_tol;            /* stop when max|r| <= pcg_tol * max|b| over fluid cells
+                                  (FLIP_MIXED: tolerance of each FP32 inner solve, relative
+                                  to the residual it starts from)                           */
     int32_t pcg_max_iters;     /* <= 0 selects 20 * max(nx, ny, nz)                        */
-    double ir_tol;             /* FLIP_MIXED: outer refinement tolerance (relative)        */
+    double ir_tol;             /* FLIP_MIXED: stop refining when the FP64 residual
+                                  max|b - A x| <= ir_tol * max|b| (at most 20 refinements)  */
     int32_t precision;         /* flip_precision                                           */
     uint32_t flags;            /* FLIP_FLAG_*                                              */
     /* initial particles: either seeded from regions ...                                  */
@@ -117,7 +120,7 @@ enum {
     FLIP_FIELD_U_OLD = 6,      /* real[Fu + Fv + Fw]: raw particle-to-grid result          */
     FLIP_FIELD_U_STAR = 7,     /* real[Fu + Fv + Fw]: after gravity and walls              */
     FLIP_FIELD_U_NEW = 8,      /* real[Fu + Fv + Fw]: after projection                     */
-    FLIP_FIELD_RHS = 9,        /* real[ncells]: b (0 off fluid)                            */
+    FLIP_FIELD_RHS = 9,        /* real[ncells]: b (0 off fluid); double for FLIP_MIXED      */
     FLIP_FIELD_PRESSURE = 10,  /* real[ncells]: p (0 off fluid); double for FLIP_MIXED      */
     FLIP_FIELD_COUNT_ = 11
 };
@@ -146,11 +149,12 @@ typedef struct {
     int32_t pcg_iterations;        /* last step                                            */
     int32_t pcg_status;            /* last step: 0 converged, 1 max iters, 2 breakdown     */
     double max_b;                  /* last step: max |b| over fluid cells                  */
-    double max_r;                  /* last step: final max |r| (solver's residual)         */
+    double max_r;                  /* last step: final max |r| (solver's recursive residual;
+                                      FLIP_MIXED: the FP64 residual |b - A x| of the result) */
     int64_t pcg_iterations_total;  /* summed over all steps                                */
     int64_t pcg_cell_iterations_total; /* sum over steps of fluid cells x PCG iterations      */
     int32_t latched_status;        /* first solver error since init (flip_status), or 0    */
-    int32_t pad_;
+    int32_t refinements;           /* last step, FLIP_MIXED: outer FP64 refinements        */
     double kernel_ms[FLIP_KERNEL_COUNT];      /* summed durations of timed launches        */
     int64_t kernel_launches[FLIP_KERNEL_COUNT];/* number of timed launches                 */
 } flip_step_stats;

@@ -18,6 +18,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 constexpr int TIMED_PCG_EVERY = 8;  // with kernel timing on, one PCG iteration in 8 is bracketed
 constexpr int EVENT_PAIRS = 2048;
+constexpr int MAX_REFINEMENTS = 20;  // FLIP_MIXED: outer refinements per step
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
 
@@ -146,7 +147,11 @@ struct flip_handle {
     void* f_new[3] = {};
     // solver (compact tile storage)
     uint8_t* diag = nullptr;
-    void *b = nullptr, *z = nullptr, *x = nullptr, *s[2] = {nullptr, nullptr};
+    void *b = nullptr, *z = nullptr, *xin[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
+    double* b64 = nullptr;                     // FLIP_MIXED only
+    double* x64[2] = {nullptr, nullptr};       // FLIP_MIXED only
+    int xi = 0;                                // current solution buffer
+    int scur = 0;                              // current direction buffer
     double* partials = nullptr;
     PcgState* ps = nullptr;
     void* staging = nullptr;
@@ -163,7 +168,6 @@ struct flip_handle {
     std::vector<int> ev_kind;
     std::vector<int> ev_iter;  // PCG iteration of a timed solver launch, -1 otherwise
     int ev_used = 0;
-    int ev_iter_limit = 1 << 30;  // solver launches at or past this iteration did no work
 };
 
 namespace {
@@ -182,7 +186,9 @@ flip_status validate(const flip_config* c)
     if (!(c->pcg_tol >= 0.0) || !std::isfinite(c->pcg_tol)) return FLIP_E_INVALID;
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(c->gravity[a])) return FLIP_E_INVALID;
-    if (c->precision != FLIP_FP32 && c->precision != FLIP_FP64) return FLIP_E_INVALID;
+    if (c->precision != FLIP_FP32 && c->precision != FLIP_FP64 && c->precision != FLIP_MIXED)
+        return FLIP_E_INVALID;
+    if (c->precision == FLIP_MIXED && (!(c->ir_tol > 0.0) || !std::isfinite(c->ir_tol))) return FLIP_E_INVALID;
     if (c->pos0) {
         if (c->n_particles < 0 || c->n_particles >= ((int64_t)1 << 31) || !c->vel0) return FLIP_E_INVALID;
     } else {
@@ -267,11 +273,17 @@ void carve(flip_handle* h, Carver& cv)
     h->diag = cv.take<uint8_t>(s.cap);
     h->b = cv.take<void>(s.cap * rb);
     h->z = cv.take<void>(s.cap * rb);
-    h->x = cv.take<void>(s.cap * rb);
+    h->xin[0] = cv.take<void>(s.cap * rb);
     h->s[0] = cv.take<void>(s.cap * rb);
     h->s[1] = cv.take<void>(s.cap * rb);
+    if (h->prec == FLIP_MIXED) {
+        h->xin[1] = cv.take<void>(s.cap * rb);
+        h->b64 = cv.take<double>(s.cap * 8);
+        h->x64[0] = cv.take<double>(s.cap * 8);
+        h->x64[1] = cv.take<double>(s.cap * 8);
+    }
     h->partials = cv.take<double>(3 * sizeof(double) * s.T);
-    h->ps = cv.take<PcgState>(sizeof(PcgState));
+    h->ps = cv.take<PcgState>(PCG_STATE_BYTES + SYNC_BYTES);
     h->staging = cv.take<void>(8 * s.C);
 }
 
@@ -303,7 +315,7 @@ flip_status timer_collect(flip_handle* h, hipStream_t st)
     if (h->ev_used == 0) return FLIP_OK;
     HIP_TRY(hipStreamSynchronize(st));
     for (int q = 0; q < h->ev_used; q += 2) {
-        if (h->ev_iter[q / 2] >= h->ev_iter_limit) continue;
+        if (h->ev_kind[q / 2] < 0) continue;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, h->ev[q], h->ev[q + 1]) == hipSuccess) {
             h->stats.kernel_ms[h->ev_kind[q / 2]] += ms;
@@ -311,13 +323,48 @@ flip_status timer_collect(flip_handle* h, hipStream_t st)
         }
     }
     h->ev_used = 0;
-    h->ev_iter_limit = 1 << 30;
     return FLIP_OK;
 }
 
 // ---- one step -----------------------------------------------------------------
 
-template <typename T>
+// Launch PCG iterations in chunks until the device-side state says the current
+// (inner) solve is over; returns the state read at the end.
+template <typename V>
+flip_status pcg_loop(flip_handle* h, int na, V* x, int max_iters, hipStream_t st, PcgState* out)
+{
+    int chunk = h->prev_iters > 2 ? h->prev_iters - 2 : 16;
+    int launched = 0;
+    const int first_sample = h->ev_used / 2;
+    for (;;) {
+        for (int it = 0; it < chunk; ++it) {
+            const int sc = h->scur;
+            const bool timed = ((launched + it) % TIMED_PCG_EVERY) == 0;
+            int q1 = timed ? timer_begin(h, FLIP_KERNEL_PCG_DIRECTION, st, launched + it) : -1;
+            launch_pcg_direction<V>(na, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
+                                    (V*)h->s[sc ^ 1], h->partials, h->ps, st);
+            timer_end(h, q1, st);
+            int q2 = timed ? timer_begin(h, FLIP_KERNEL_PCG_UPDATE, st, launched + it) : -1;
+            launch_pcg_update<V>(na, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
+                                 h->partials, h->sz.T, h->ps, st);
+            timer_end(h, q2, st);
+            h->scur = sc ^ 1;
+        }
+        launched += chunk;
+        HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (h->h_ps->done != PCG_RUNNING || launched > max_iters + 8) break;
+        chunk = 8;
+    }
+    *out = *h->h_ps;
+    h->prev_iters = out->iter;
+    // timed launches at or past the final iteration found the solve over and did no work
+    for (int q = first_sample; q < h->ev_used / 2; ++q)
+        if (h->ev_iter[q] >= out->iter) h->ev_kind[q] = -1;
+    return FLIP_OK;
+}
+
+template <typename T, bool MIXED>
 flip_status run_step(flip_handle* h, hipStream_t st)
 {
     const Geo& g = h->geo;
@@ -371,50 +418,64 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     flip_status ret = FLIP_OK;
     const bool project = !(c.flags & FLIP_FLAG_NO_PROJECTION);
     const int max_iters = c.pcg_max_iters > 0 ? c.pcg_max_iters : 20 * std::max(c.nx, std::max(c.ny, c.nz));
+    const double scale_b = -c.density * c.dx / c.dt;
+    h->scur = 0;
+    h->xi = 0;
     if (na > 0) {
         tq = timer_begin(h, FLIP_KERNEL_RHS, st);
-        launch_rhs<T, T>(g, na, h->tile_list, h->count, (const T*)h->f_star[0], (const T*)h->f_star[1],
-                         (const T*)h->f_star[2], -c.density * c.dx / c.dt, h->diag, (T*)h->b, (T*)h->z,
-                         (T*)h->x, (T*)h->s[0], (T*)h->s[1], h->partials, s.T, h->ps,
-                         project ? c.pcg_tol : 0.0, project ? max_iters : 0, st);
+        if (MIXED)
+            launch_rhs_mixed(g, na, h->tile_list, h->count, (const float*)h->f_star[0],
+                             (const float*)h->f_star[1], (const float*)h->f_star[2], scale_b, h->diag,
+                             h->b64, h->x64[0], (float*)h->z, (float*)h->xin[0], (float*)h->s[0],
+                             (float*)h->s[1], h->partials, s.T, h->ps, project ? c.pcg_tol : 0.0,
+                             project ? max_iters : 0, c.ir_tol, MAX_REFINEMENTS, st);
+        else
+            launch_rhs<T, T>(g, na, h->tile_list, h->count, (const T*)h->f_star[0], (const T*)h->f_star[1],
+                             (const T*)h->f_star[2], scale_b, h->diag, (T*)h->b, (T*)h->z, (T*)h->xin[0],
+                             (T*)h->s[0], (T*)h->s[1], h->partials, s.T, h->ps, project ? c.pcg_tol : 0.0,
+                             project ? max_iters : 0, st);
         timer_end(h, tq, st);
     }
 
-    // 4. PCG, host-controlled in chunks of iterations; the kernels skip work
-    //    once the device-side state says the solve is over
+    // 4. PCG (FP32 inner solves inside FP64 refinement when MIXED)
+    int iters = 0, refinements = 0;
     if (na > 0 && project) {
-        int chunk = h->prev_iters > 2 ? h->prev_iters - 2 : 16;
-        int launched = 0, sc = 0;
         for (;;) {
-            for (int it = 0; it < chunk; ++it) {
-                const bool timed = ((launched + it) % TIMED_PCG_EVERY) == 0;
-                int q1 = timed ? timer_begin(h, FLIP_KERNEL_PCG_DIRECTION, st, launched + it) : -1;
-                launch_pcg_direction<T>(na, h->tile_nbr, h->diag, (const T*)h->z, (const T*)h->s[sc],
-                                        (T*)h->s[sc ^ 1], h->partials, h->ps, st);
-                timer_end(h, q1, st);
-                int q2 = timed ? timer_begin(h, FLIP_KERNEL_PCG_UPDATE, st, launched + it) : -1;
-                launch_pcg_update<T>(na, h->tile_nbr, h->diag, (const T*)h->s[sc ^ 1], (T*)h->x,
-                                     (T*)h->z, h->partials, s.T, h->ps, st);
-                timer_end(h, q2, st);
-                sc ^= 1;
-            }
-            launched += chunk;
+            flip_status r = pcg_loop<T>(h, na, (T*)h->xin[h->xi], max_iters, st, &ps_host);
+            if (r != FLIP_OK) return r;
+            iters += ps_host.iter;
+            if (!MIXED || ps_host.done == PCG_BREAKDOWN) break;
+            const int xi = h->xi;
+            launch_ir_update(na, h->tile_nbr, h->diag, h->b64, h->x64[xi], h->x64[xi ^ 1],
+                             (const float*)h->xin[xi], (float*)h->xin[xi ^ 1], (float*)h->z,
+                             (float*)h->s[0], (float*)h->s[1], h->partials, s.T, h->ps, st);
+            h->xi = xi ^ 1;
+            h->scur = 0;
+            ++refinements;
             HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
-            if (h->h_ps->done != PCG_RUNNING || launched > max_iters + 8) break;
-            chunk = 8;
+            ps_host = *h->h_ps;
+            if (ps_host.outer_done != 0) break;
         }
-        ps_host = *h->h_ps;
-        h->prev_iters = ps_host.iter;
-        h->ev_iter_limit = ps_host.iter;
-        if (ps_host.done == PCG_MAX_ITERS || ps_host.done == PCG_RUNNING) ret = FLIP_E_NOT_CONVERGED;
-        if (ps_host.done == PCG_BREAKDOWN) ret = ps_host.sync_error ? FLIP_E_HIP : FLIP_E_NONFINITE;
-        // 5. projection
+        if (MIXED) {
+            if (ps_host.outer_done != 1) ret = (ps_host.done == PCG_BREAKDOWN)
+                                                  ? (ps_host.sync_error ? FLIP_E_HIP : FLIP_E_NONFINITE)
+                                                  : FLIP_E_NOT_CONVERGED;
+        } else {
+            if (ps_host.done == PCG_MAX_ITERS || ps_host.done == PCG_RUNNING) ret = FLIP_E_NOT_CONVERGED;
+            if (ps_host.done == PCG_BREAKDOWN) ret = ps_host.sync_error ? FLIP_E_HIP : FLIP_E_NONFINITE;
+        }
+        // 5. projection with the solution (FP64 when MIXED)
         const T scale = (T)(c.dt / (c.density * c.dx));
         for (int a = 0; a < 3; ++a) {
             tq = timer_begin(h, FLIP_KERNEL_PROJECT, st);
-            launch_project<T, T>(g, a, h->count, h->tile_slot, (const T*)h->x, (const T*)h->f_star[a],
-                                 (T*)h->f_new[a], scale, st);
+            if (MIXED)
+                launch_project<float, double>(g, a, h->count, h->tile_slot, h->x64[h->xi],
+                                              (const float*)h->f_star[a], (float*)h->f_new[a],
+                                              (float)scale, st);
+            else
+                launch_project<T, T>(g, a, h->count, h->tile_slot, (const T*)h->xin[h->xi],
+                                     (const T*)h->f_star[a], (T*)h->f_new[a], scale, st);
             timer_end(h, tq, st);
         }
     } else {
@@ -422,7 +483,6 @@ flip_status run_step(flip_handle* h, hipStream_t st)
             HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             ps_host = *h->h_ps;
-            ps_host.iter = 0;
         }
         for (int a = 0; a < 3; ++a)
             HIP_TRY(hipMemcpyAsync(h->f_new[a], h->f_star[a], s.F[a] * sizeof(T),
@@ -439,15 +499,22 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
 
     flip_step_stats& S = h->stats;
+    const bool solved = na > 0 && project;
     S.steps += 1;
     S.n_fluid_cells = na > 0 ? ps_host.nfluid : 0;
     S.n_active_tiles = na;
-    S.pcg_iterations = ps_host.iter;
-    S.pcg_status = ps_host.done == PCG_CONVERGED ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : (na > 0 && project ? 1 : 0));
-    S.max_b = ps_host.max_b;
-    S.max_r = ps_host.max_r;
-    S.pcg_iterations_total += ps_host.iter;
-    S.pcg_cell_iterations_total += (int64_t)ps_host.iter * (na > 0 ? ps_host.nfluid : 0);
+    S.pcg_iterations = iters;
+    S.refinements = refinements;
+    if (!solved)
+        S.pcg_status = 0;
+    else if (MIXED)
+        S.pcg_status = ps_host.outer_done == 1 ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : 1);
+    else
+        S.pcg_status = ps_host.done == PCG_CONVERGED ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : 1);
+    S.max_b = MIXED ? ps_host.max_b0 : ps_host.max_b;
+    S.max_r = MIXED ? ps_host.max_r64 : ps_host.max_r;
+    S.pcg_iterations_total += iters;
+    S.pcg_cell_iterations_total += (int64_t)iters * (na > 0 ? ps_host.nfluid : 0);
     if (ret != FLIP_OK && S.latched_status == 0) S.latched_status = ret;
     flip_status tr = timer_collect(h, st);
     return ret != FLIP_OK ? ret : tr;
@@ -480,6 +547,7 @@ flip_status flip_workspace_bytes(const flip_config* cfg, size_t* out_bytes)
     v = particle_count(cfg, &n);
     if (v != FLIP_OK) return v;
     flip_handle tmp;
+    tmp.prec = cfg->precision;
     tmp.sz = make_sizes(cfg, n);
     Carver cv(nullptr);
     carve(&tmp, cv);
@@ -567,7 +635,7 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
         launch_fill_bytes_zero(h->f_new[a], s.F[a] * rb, st);
     }
     launch_fill_bytes_zero(h->diag, s.cap, st);
-    launch_fill_bytes_zero(h->ps, sizeof(PcgState), st);
+    launch_fill_bytes_zero(h->ps, PCG_STATE_BYTES + SYNC_BYTES, st);
     launch_fill_u64((uint64_t*)h->partials, 3 * s.T, SLOT_EMPTY_BITS, st);
     if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h->h_nactive, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
@@ -600,7 +668,9 @@ flip_status flip_step(flip_handle* h, int nsteps, void* hip_stream)
     h->last_stream = st;
     flip_status first = FLIP_OK;
     for (int k = 0; k < nsteps; ++k) {
-        flip_status r = (h->prec == FLIP_FP64) ? run_step<double>(h, st) : run_step<float>(h, st);
+        flip_status r = (h->prec == FLIP_FP64)     ? run_step<double, false>(h, st)
+                        : (h->prec == FLIP_MIXED) ? run_step<float, true>(h, st)
+                                                  : run_step<float, false>(h, st);
         if (r == FLIP_E_HIP) return r;
         if (r != FLIP_OK && first == FLIP_OK) first = r;
     }
@@ -622,7 +692,7 @@ flip_status flip_field_bytes(const flip_handle* h, int field, size_t* out_bytes)
         case FLIP_FIELD_U_STAR:
         case FLIP_FIELD_U_NEW: *out_bytes = (s.F[0] + s.F[1] + s.F[2]) * s.rb; break;
         case FLIP_FIELD_RHS:
-        case FLIP_FIELD_PRESSURE: *out_bytes = s.C * s.rb; break;
+        case FLIP_FIELD_PRESSURE: *out_bytes = s.C * (h->prec == FLIP_MIXED ? 8 : s.rb); break;
         default: return FLIP_E_INVALID;
     }
     return FLIP_OK;
@@ -663,8 +733,12 @@ flip_status flip_readback(flip_handle* h, int field, void* dst, size_t dst_bytes
         }
         case FLIP_FIELD_RHS:
         case FLIP_FIELD_PRESSURE: {
-            const void* src = field == FLIP_FIELD_RHS ? h->b : h->x;
-            if (h->prec == FLIP_FP64)
+            const void* src = field == FLIP_FIELD_RHS ? h->b : h->xin[h->xi];
+            if (h->prec == FLIP_MIXED)
+                launch_densify<double, double>(h->geo, h->tile_slot, h->diag,
+                                               field == FLIP_FIELD_RHS ? h->b64 : h->x64[h->xi],
+                                               (double*)h->staging, st);
+            else if (h->prec == FLIP_FP64)
                 launch_densify<double, double>(h->geo, h->tile_slot, h->diag, (const double*)src,
                                                (double*)h->staging, st);
             else

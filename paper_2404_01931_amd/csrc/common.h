@@ -31,16 +31,35 @@ struct PcgState {
     int max_iters;
     int done;          // 0 running, 1 converged, 2 max iterations, 3 breakdown
     int nfluid;        // fluid cells of this solve
-    unsigned counter;  // blocks finished in the current reduction kernel
+    unsigned unused_;
     int n_active;      // active tiles
     int sync_error;    // a partial result never became visible (reduction aborted)
     int pad_;
+    // mixed precision: outer iterative refinement in FP64 around FP32 inner solves
+    double max_b0;     // max |b| of the FP64 right-hand side
+    double ir_tol;     // outer tolerance relative to max_b0
+    double max_r64;    // max |b - A x| of the FP64 solution after the last refinement
+    int outer;         // refinements done
+    int outer_done;    // 0 running, 1 converged, 2 out of refinements
+    int max_outer;
+    int pad2_;
 };
 
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAX_ITERS = 2, PCG_BREAKDOWN = 3 };
 
-// Upper bound on the workgroups of one PCG iteration kernel (8 per CU).
-constexpr int PCG_MAX_GROUPS = 2048;
+// The solver state is followed in device memory by the workgroup arrival
+// counters of the grid reductions (SYNC_BYTES, zero between kernels).
+constexpr int PCG_STATE_BYTES = 256;
+constexpr int SYNC_BYTES = 9 * 32 * 4;
+static_assert(sizeof(PcgState) <= PCG_STATE_BYTES, "solver state outgrew its slot");
+__host__ __device__ inline unsigned* pcg_sync(PcgState* ps)
+{
+    return (unsigned*)((char*)ps + PCG_STATE_BYTES);
+}
+
+// Upper bound on the workgroups of one PCG iteration kernel (4 per CU; a
+// sweep over 256..16384 on the 256^3 drop scene found 1024 fastest).
+constexpr int PCG_MAX_GROUPS = 1024;
 
 // Reduction slots hold this pattern when empty (see device_util.h).
 constexpr uint64_t SLOT_EMPTY_BITS = 0x7FF4DEADBEEF0001ull;
@@ -91,6 +110,19 @@ void launch_rhs(const Geo& g, int n_active, const uint32_t* tile_list, const uin
                 const T* u, const T* v, const T* w, double scale, uint8_t* diag, V* b, V* z, V* x,
                 V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev, double tol,
                 int max_iters, hipStream_t st);
+// mixed precision: right-hand side in FP64 (b64), FP64 solution x64 = 0 and the
+// start of the first FP32 inner solve (z = b64 / n rounded, x = 0, s = 0)
+void launch_rhs_mixed(const Geo& g, int n_active, const uint32_t* tile_list, const uint32_t* count,
+                      const float* u, const float* v, const float* w, double scale, uint8_t* diag,
+                      double* b64, double* x64, float* z, float* x, float* s0, float* s1,
+                      double* partials, int64_t pstride, PcgState* st_dev, double tol, int max_iters,
+                      double ir_tol, int max_outer, hipStream_t st);
+// one refinement: x64_out = x64_in + x_in; r64 = b64 - A x64_out; restart the
+// inner solve on r64 (z = r64 / n rounded, x_out = 0, s = 0) unless converged
+void launch_ir_update(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const double* b64,
+                      const double* x64_in, double* x64_out, const float* x_in, float* x_out,
+                      float* z, float* s0, float* s1, double* partials, int64_t pstride,
+                      PcgState* st_dev, hipStream_t st);
 template <typename V>
 void launch_pcg_direction(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
                           const V* s_old, V* s_new, double* partials, PcgState* st_dev,

@@ -115,18 +115,44 @@ __device__ inline unsigned long long slot_load(const double* slot)
     return __hip_atomic_load((unsigned long long*)slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Arrival counters: ctr[0] counts arriving sets, ctr[SYNC_STRIDE * (1 + x)]
+// counts the arriving workgroups of set x = blockIdx.x % 8. One counter per set
+// (each on its own 128-byte line) keeps the relaxed atomic adds from queueing
+// on a single address: a single counter cost microseconds per thousand
+// workgroups.
+constexpr int SYNC_SETS = 8;
+constexpr int SYNC_STRIDE = 32;
+static_assert(SYNC_STRIDE * (SYNC_SETS + 1) * 4 == SYNC_BYTES, "arrival counter layout");
+
 // Thread 0 publishes vals[0..nq) into slots[q * stride + blockIdx.x]; returns
-// (in every thread) whether this workgroup is the last to arrive.
+// (in every thread) whether this workgroup is the last of the grid to arrive.
 __device__ inline bool publish_partials(double* slots, int64_t stride, const double* vals, int nq,
-                                        unsigned* counter, bool* sh_last)
+                                        unsigned* ctr, bool* sh_last)
 {
     if (threadIdx.x == 0) {
         for (int q = 0; q < nq; ++q) slot_store(slots + q * stride + blockIdx.x, vals[q]);
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        *sh_last = (prev == gridDim.x - 1);
+        const unsigned nb = gridDim.x;
+        const unsigned set = blockIdx.x % SYNC_SETS;
+        const unsigned in_set = nb / SYNC_SETS + (set < nb % SYNC_SETS ? 1u : 0u);
+        const unsigned sets = nb < SYNC_SETS ? nb : SYNC_SETS;
+        bool last = false;
+        const unsigned prev = __hip_atomic_fetch_add(ctr + SYNC_STRIDE * (1 + set), 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == in_set - 1) {
+            const unsigned p2 = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = (p2 == sets - 1);
+        }
+        *sh_last = last;
     }
     __syncthreads();
     return *sh_last;
+}
+
+// In the last workgroup, after the slots are collected: zero the counters.
+__device__ inline void reset_arrivals(unsigned* ctr)
+{
+    if (threadIdx.x <= SYNC_SETS)
+        __hip_atomic_store(ctr + SYNC_STRIDE * threadIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // In the last workgroup: combine slots[0..nb) (sum, or max when MAX), reset

@@ -79,6 +79,7 @@ __global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__
 {
     __shared__ double red[PNT / WAVE];
     __shared__ bool last;
+    unsigned* const sync = pcg_sync(ps);
     const int slot = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t t = tile_list[slot];
     const int ti = (int)(t % g.tx), tj = (int)((t / g.tx) % g.ty), tk = (int)(t / ((uint32_t)g.tx * g.ty));
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__
     const double mb = block_max<PNT>(finite_or_inf(fabs((double)bq)), red);
     const double nf = block_sum<PNT>(d ? 1.0 : 0.0, red);
     const double vals[3] = {rz, mb, nf};
-    if (!publish_partials(partials, pstride, vals, 3, &ps->counter, &last)) return;
+    if (!publish_partials(partials, pstride, vals, 3, sync, &last)) return;
     const int nb = gridDim.x;
     int err = 0;
     const double rho = collect_slots<PNT, false>(partials, nb, red, &err);
@@ -136,8 +137,8 @@ __global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__
                                        : PCG_RUNNING;
         ps->sync_error = err;
         if (err) ps->done = PCG_BREAKDOWN;
-        __hip_atomic_store(&ps->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    reset_arrivals(sync);
 }
 
 template <typename T, typename V>
@@ -174,18 +175,84 @@ template void launch_rhs<double, double>(const Geo&, int, const uint32_t*, const
 
 constexpr int PCG_NT = 256;
 
-__device__ inline int64_t halo_elem(const int32_t* __restrict__ nbr, int slot, int h)
-{
-    const int f = h >> 6;
-    const int32_t ns = nbr[(int64_t)slot * 6 + f];
-    return ns >= 0 ? (int64_t)ns * TILE_CELLS + halo_source(f, h & 63) : (int64_t)-1;
-}
-
 __device__ inline void tile_range(int n_tiles, int& t0, int& t1)
 {
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     t0 = (int)((int64_t)n_tiles * L / gridDim.x);
     t1 = (int)((int64_t)n_tiles * (L + 1) / gridDim.x);
+}
+
+// Values of one tile that a thread stages: its two cells and up to two halo
+// cells, loaded into registers two tiles ahead of their use. Every load is
+// unconditional (a missing neighbour or a past-the-end tile reads a valid
+// address of the workgroup's own range and is masked where it is consumed),
+// so no control-flow merge makes the compiler wait for the loads early.
+template <typename V>
+struct DirRegs {
+    V z0, z1, s0, s1, hz0, hs0, hz1, hs1;
+    uint32_t d0, d1;
+    bool m0, m1;
+};
+
+template <typename V>
+__device__ inline void dir_fetch(DirRegs<V>& r, const V* __restrict__ z, const V* __restrict__ s_old,
+                                 const uint8_t* __restrict__ diag, int slot, int32_t n0, int32_t n1,
+                                 int tid, int hs0i, int hs1i)
+{
+    const int64_t e = (int64_t)slot * TILE_CELLS + tid;
+    const int64_t h0 = n0 >= 0 ? (int64_t)n0 * TILE_CELLS + hs0i : e;
+    const int64_t h1 = n1 >= 0 ? (int64_t)n1 * TILE_CELLS + hs1i : e;
+    r.z0 = z[e];
+    r.s0 = s_old[e];
+    r.z1 = z[e + PCG_NT];
+    r.s1 = s_old[e + PCG_NT];
+    r.d0 = diag[e];
+    r.d1 = diag[e + PCG_NT];
+    r.hz0 = z[h0];
+    r.hs0 = s_old[h0];
+    r.hz1 = z[h1];
+    r.hs1 = s_old[h1];
+    r.m0 = n0 >= 0;
+    r.m1 = n1 >= 0;
+}
+
+__device__ inline void next_nbr(const int32_t* __restrict__ nbr, int slot, int f0, int f1,
+                                bool two_halo, int32_t& n0, int32_t& n1)
+{
+    const int32_t a = nbr[(int64_t)slot * 6 + f0];
+    const int32_t b = nbr[(int64_t)slot * 6 + (two_halo ? f1 : f0)];
+    n0 = a;
+    n1 = two_halo ? b : -1;
+}
+
+// One tile of the direction kernel. The barrier makes the compiler wait for
+// every outstanding memory operation, so the LDS stores go before it and this
+// tile's global stores plus the loads two tiles ahead go after it, where they
+// overlap the stencil.
+template <typename V>
+__device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tlast, int32_t& nn0,
+                                  int32_t& nn1, const int32_t* __restrict__ nbr,
+                                  const uint8_t* __restrict__ diag, const V* __restrict__ z,
+                                  const V* __restrict__ s_old, V* __restrict__ s_new, int tid,
+                                  int f0, int f1, int hs0i, int hs1i, bool two_halo)
+{
+    const V sc0 = fma(beta, cur.s0, cur.z0), sc1 = fma(beta, cur.s1, cur.z1);
+    const V hv0 = cur.m0 ? fma(beta, cur.hs0, cur.hz0) : V(0);
+    const V hv1 = cur.m1 ? fma(beta, cur.hs1, cur.hz1) : V(0);
+    const int d0 = (int)cur.d0, d1 = (int)cur.d1;
+    st[tid] = sc0;
+    st[tid + PCG_NT] = sc1;
+    st[TILE_CELLS + tid] = hv0;
+    if (two_halo) st[TILE_CELLS + PCG_NT + tid] = hv1;
+    __syncthreads();
+    const int64_t e = (int64_t)t * TILE_CELLS + tid;
+    s_new[e] = sc0;
+    s_new[e + PCG_NT] = sc1;
+    dir_fetch(cur, z, s_old, diag, min(t + 2, tlast), nn0, nn1, tid, hs0i, hs1i);
+    next_nbr(nbr, min(t + 3, tlast), f0, f1, two_halo, nn0, nn1);
+    const V q0 = d0 ? fma((V)d0, sc0, -neighbour_sum(st, tid)) : V(0);
+    const V q1 = d1 ? fma((V)d1, sc1, -neighbour_sum(st, tid + PCG_NT)) : V(0);
+    return (double)sc0 * (double)q0 + (double)sc1 * (double)q1;
 }
 
 // direction kernel: s = z + beta s_old, q = A s, sigma = s.q
@@ -201,53 +268,35 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restr
     __shared__ V stg[2][STAGE];
     __shared__ double red[PCG_NT / WAVE];
     __shared__ bool last;
+    unsigned* const sync = pcg_sync(ps);
     if (ps->done != PCG_RUNNING) return;
     const V beta = (V)ps->beta;
     const int tid = threadIdx.x;
     const bool two_halo = tid < HALO - PCG_NT;
+    const int f0 = tid >> 6, f1 = (tid + PCG_NT) >> 6;
+    const int hs0i = halo_source(f0, tid & 63), hs1i = halo_source(f1, tid & 63);
     int t0, t1;
     tile_range(n_tiles, t0, t1);
-    // prefetched raw values of the next tile
-    V nz0 = 0, nz1 = 0, ns0 = 0, ns1 = 0, hz0 = 0, hs0 = 0, hz1 = 0, hs1 = 0;
-    int nd0 = 0, nd1 = 0;
-    auto fetch = [&](int slot) {
-        const int64_t e = (int64_t)slot * TILE_CELLS + tid;
-        nz0 = z[e];
-        ns0 = s_old[e];
-        nz1 = z[e + PCG_NT];
-        ns1 = s_old[e + PCG_NT];
-        nd0 = diag[e];
-        nd1 = diag[e + PCG_NT];
-        const int64_t h0 = halo_elem(nbr, slot, tid);
-        hz0 = h0 >= 0 ? z[h0] : V(0);
-        hs0 = h0 >= 0 ? s_old[h0] : V(0);
-        if (two_halo) {
-            const int64_t h1 = halo_elem(nbr, slot, tid + PCG_NT);
-            hz1 = h1 >= 0 ? z[h1] : V(0);
-            hs1 = h1 >= 0 ? s_old[h1] : V(0);
-        }
-    };
     double acc = 0.0;
-    if (t0 < t1) fetch(t0);
-    for (int t = t0, buf = 0; t < t1; ++t, buf ^= 1) {
-        V* st = stg[buf];
-        const V sc0 = fma(beta, ns0, nz0), sc1 = fma(beta, ns1, nz1);
-        const int d0 = nd0, d1 = nd1;
-        st[tid] = sc0;
-        st[tid + PCG_NT] = sc1;
-        st[TILE_CELLS + tid] = fma(beta, hs0, hz0);
-        if (two_halo) st[TILE_CELLS + PCG_NT + tid] = fma(beta, hs1, hz1);
-        const int64_t e = (int64_t)t * TILE_CELLS + tid;
-        s_new[e] = sc0;
-        s_new[e + PCG_NT] = sc1;
-        if (t + 1 < t1) fetch(t + 1);
-        __syncthreads();
-        const V q0 = d0 ? fma((V)d0, sc0, -neighbour_sum(st, tid)) : V(0);
-        const V q1 = d1 ? fma((V)d1, sc1, -neighbour_sum(st, tid + PCG_NT)) : V(0);
-        acc += (double)sc0 * (double)q0 + (double)sc1 * (double)q1;
+    if (t0 < t1) {
+        const int tlast = t1 - 1;
+        DirRegs<V> A, B;
+        int32_t nn0, nn1;
+        next_nbr(nbr, t0, f0, f1, two_halo, nn0, nn1);
+        dir_fetch(A, z, s_old, diag, t0, nn0, nn1, tid, hs0i, hs1i);
+        next_nbr(nbr, min(t0 + 1, tlast), f0, f1, two_halo, nn0, nn1);
+        dir_fetch(B, z, s_old, diag, min(t0 + 1, tlast), nn0, nn1, tid, hs0i, hs1i);
+        next_nbr(nbr, min(t0 + 2, tlast), f0, f1, two_halo, nn0, nn1);
+        for (int t = t0; t < t1; t += 2) {
+            acc += dir_tile(stg[0], A, beta, t, tlast, nn0, nn1, nbr, diag, z, s_old, s_new, tid, f0, f1,
+                            hs0i, hs1i, two_halo);
+            if (t + 1 < t1)
+                acc += dir_tile(stg[1], B, beta, t + 1, tlast, nn0, nn1, nbr, diag, z, s_old, s_new, tid,
+                                f0, f1, hs0i, hs1i, two_halo);
+        }
     }
     const double part = block_sum<PCG_NT>(acc, red);
-    if (!publish_partials(partials, 0, &part, 1, &ps->counter, &last)) return;
+    if (!publish_partials(partials, 0, &part, 1, sync, &last)) return;
     int err = 0;
     const double sigma = collect_slots<PCG_NT, false>(partials, gridDim.x, red, &err);
     err = __syncthreads_or(err);
@@ -257,8 +306,8 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restr
         else
             ps->alpha = ps->rho / sigma;
         if (err) ps->sync_error = 1;
-        __hip_atomic_store(&ps->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    reset_arrivals(sync);
 }
 
 int pcg_groups(int n_active) { return n_active < PCG_MAX_GROUPS ? n_active : PCG_MAX_GROUPS; }
@@ -279,6 +328,70 @@ template void launch_pcg_direction<double>(int, const int32_t*, const uint8_t*, 
                                            const double*, double*, double*, PcgState*,
                                            hipStream_t);
 
+template <typename V>
+struct UpdRegs {
+    V s0, s1, x0, x1, z0, z1, h0, h1;
+    uint32_t d0, d1;
+    bool m0, m1;
+};
+
+template <typename V>
+__device__ inline void upd_fetch(UpdRegs<V>& r, const V* __restrict__ s, const V* __restrict__ x,
+                                 const V* __restrict__ z, const uint8_t* __restrict__ diag, int slot,
+                                 int32_t n0, int32_t n1, int tid, int hs0i, int hs1i)
+{
+    const int64_t e = (int64_t)slot * TILE_CELLS + tid;
+    const int64_t h0 = n0 >= 0 ? (int64_t)n0 * TILE_CELLS + hs0i : e;
+    const int64_t h1 = n1 >= 0 ? (int64_t)n1 * TILE_CELLS + hs1i : e;
+    r.s0 = s[e];
+    r.s1 = s[e + PCG_NT];
+    r.x0 = x[e];
+    r.x1 = x[e + PCG_NT];
+    r.z0 = z[e];
+    r.z1 = z[e + PCG_NT];
+    r.d0 = diag[e];
+    r.d1 = diag[e + PCG_NT];
+    r.h0 = s[h0];
+    r.h1 = s[h1];
+    r.m0 = n0 >= 0;
+    r.m1 = n1 >= 0;
+}
+
+template <typename V>
+__device__ inline void upd_cell(const V* st, int l, int d, V sc, V xc, V zc, V alpha, int64_t e,
+                                V* __restrict__ x, V* __restrict__ z, double& rz, double& rmax)
+{
+    if (!d) return;
+    const V q = fma((V)d, sc, -neighbour_sum(st, l));  // same rounding as the direction kernel
+    x[e] = fma(alpha, sc, xc);
+    const V r = fma((V)d, zc, -alpha * q);
+    const V zn = r / (V)d;
+    z[e] = zn;
+    rz += (double)r * (double)zn;
+    rmax = fmax(rmax, finite_or_inf(fabs((double)r)));
+}
+
+template <typename V>
+__device__ inline void upd_tile(V* st, UpdRegs<V>& cur, V alpha, int t, int tlast, int32_t& nn0,
+                                int32_t& nn1, const int32_t* __restrict__ nbr,
+                                const uint8_t* __restrict__ diag, const V* __restrict__ s,
+                                V* __restrict__ x, V* __restrict__ z, int tid, int f0, int f1,
+                                int hs0i, int hs1i, bool two_halo, double& rz, double& rmax)
+{
+    const V sc0 = cur.s0, sc1 = cur.s1, xc0 = cur.x0, xc1 = cur.x1, zc0 = cur.z0, zc1 = cur.z1;
+    const int d0 = (int)cur.d0, d1 = (int)cur.d1;
+    st[tid] = sc0;
+    st[tid + PCG_NT] = sc1;
+    st[TILE_CELLS + tid] = cur.m0 ? cur.h0 : V(0);
+    if (two_halo) st[TILE_CELLS + PCG_NT + tid] = cur.m1 ? cur.h1 : V(0);
+    __syncthreads();  // loads two tiles ahead are issued after the barrier
+    upd_fetch(cur, s, x, z, diag, min(t + 2, tlast), nn0, nn1, tid, hs0i, hs1i);
+    next_nbr(nbr, min(t + 3, tlast), f0, f1, two_halo, nn0, nn1);
+    const int64_t e = (int64_t)t * TILE_CELLS + tid;
+    upd_cell(st, tid, d0, sc0, xc0, zc0, alpha, e, x, z, rz, rmax);
+    upd_cell(st, tid + PCG_NT, d1, sc1, xc1, zc1, alpha, e + PCG_NT, x, z, rz, rmax);
+}
+
 // update kernel: x += alpha s; r = n z - alpha A s; z = r / n; r.z; max|r|
 template <typename V>
 __global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict__ nbr,
@@ -291,67 +404,37 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict
     __shared__ V stg[2][STAGE];
     __shared__ double red[PCG_NT / WAVE];
     __shared__ bool last;
+    unsigned* const sync = pcg_sync(ps);
     if (ps->done != PCG_RUNNING) return;
     const V alpha = (V)ps->alpha;
     const int tid = threadIdx.x;
     const bool two_halo = tid < HALO - PCG_NT;
+    const int f0 = tid >> 6, f1 = (tid + PCG_NT) >> 6;
+    const int hs0i = halo_source(f0, tid & 63), hs1i = halo_source(f1, tid & 63);
     int t0, t1;
     tile_range(n_tiles, t0, t1);
-    V ns0 = 0, ns1 = 0, nx0 = 0, nx1 = 0, nz0 = 0, nz1 = 0, h0v = 0, h1v = 0;
-    int nd0 = 0, nd1 = 0;
-    auto fetch = [&](int slot) {
-        const int64_t e = (int64_t)slot * TILE_CELLS + tid;
-        ns0 = s[e];
-        ns1 = s[e + PCG_NT];
-        nx0 = x[e];
-        nx1 = x[e + PCG_NT];
-        nz0 = z[e];
-        nz1 = z[e + PCG_NT];
-        nd0 = diag[e];
-        nd1 = diag[e + PCG_NT];
-        const int64_t h0 = halo_elem(nbr, slot, tid);
-        h0v = h0 >= 0 ? s[h0] : V(0);
-        if (two_halo) {
-            const int64_t h1 = halo_elem(nbr, slot, tid + PCG_NT);
-            h1v = h1 >= 0 ? s[h1] : V(0);
-        }
-    };
     double rz = 0.0, rmax = 0.0;
-    if (t0 < t1) fetch(t0);
-    for (int t = t0, buf = 0; t < t1; ++t, buf ^= 1) {
-        V* st = stg[buf];
-        const V sc0 = ns0, sc1 = ns1, xc0 = nx0, xc1 = nx1, zc0 = nz0, zc1 = nz1;
-        const int d0 = nd0, d1 = nd1;
-        st[tid] = sc0;
-        st[tid + PCG_NT] = sc1;
-        st[TILE_CELLS + tid] = h0v;
-        if (two_halo) st[TILE_CELLS + PCG_NT + tid] = h1v;
-        if (t + 1 < t1) fetch(t + 1);
-        __syncthreads();
-        const int64_t e = (int64_t)t * TILE_CELLS + tid;
-        if (d0) {
-            const V q = fma((V)d0, sc0, -neighbour_sum(st, tid));  // same rounding as the direction kernel
-            x[e] = fma(alpha, sc0, xc0);
-            const V r = fma((V)d0, zc0, -alpha * q);
-            const V zn = r / (V)d0;
-            z[e] = zn;
-            rz += (double)r * (double)zn;
-            rmax = fmax(rmax, finite_or_inf(fabs((double)r)));
-        }
-        if (d1) {
-            const V q = fma((V)d1, sc1, -neighbour_sum(st, tid + PCG_NT));
-            x[e + PCG_NT] = fma(alpha, sc1, xc1);
-            const V r = fma((V)d1, zc1, -alpha * q);
-            const V zn = r / (V)d1;
-            z[e + PCG_NT] = zn;
-            rz += (double)r * (double)zn;
-            rmax = fmax(rmax, finite_or_inf(fabs((double)r)));
+    if (t0 < t1) {
+        const int tlast = t1 - 1;
+        UpdRegs<V> A, B;
+        int32_t nn0, nn1;
+        next_nbr(nbr, t0, f0, f1, two_halo, nn0, nn1);
+        upd_fetch(A, s, x, z, diag, t0, nn0, nn1, tid, hs0i, hs1i);
+        next_nbr(nbr, min(t0 + 1, tlast), f0, f1, two_halo, nn0, nn1);
+        upd_fetch(B, s, x, z, diag, min(t0 + 1, tlast), nn0, nn1, tid, hs0i, hs1i);
+        next_nbr(nbr, min(t0 + 2, tlast), f0, f1, two_halo, nn0, nn1);
+        for (int t = t0; t < t1; t += 2) {
+            upd_tile(stg[0], A, alpha, t, tlast, nn0, nn1, nbr, diag, s, x, z, tid, f0, f1, hs0i, hs1i,
+                     two_halo, rz, rmax);
+            if (t + 1 < t1)
+                upd_tile(stg[1], B, alpha, t + 1, tlast, nn0, nn1, nbr, diag, s, x, z, tid, f0, f1, hs0i,
+                         hs1i, two_halo, rz, rmax);
         }
     }
     const double prz = block_sum<PCG_NT>(rz, red);
     const double pmx = block_max<PCG_NT>(rmax, red);
     const double vals[2] = {prz, pmx};
-    if (!publish_partials(partials, pstride, vals, 2, &ps->counter, &last)) return;
+    if (!publish_partials(partials, pstride, vals, 2, sync, &last)) return;
     int err = 0;
     const double rho_new = collect_slots<PCG_NT, false>(partials, gridDim.x, red, &err);
     const double max_r = collect_slots<PCG_NT, true>(partials + pstride, gridDim.x, red, &err);
@@ -369,8 +452,8 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict
         ps->beta = rho_new / ps->rho;
         ps->rho = rho_new;
         if (err) ps->sync_error = 1;
-        __hip_atomic_store(&ps->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    reset_arrivals(sync);
 }
 
 template <typename V>
@@ -386,6 +469,201 @@ template void launch_pcg_update<float>(int, const int32_t*, const uint8_t*, cons
                                        float*, double*, int64_t, PcgState*, hipStream_t);
 template void launch_pcg_update<double>(int, const int32_t*, const uint8_t*, const double*, double*,
                                         double*, double*, int64_t, PcgState*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Mixed precision (FLIP_MIXED): FP32 inner Jacobi-PCG (FP32 vectors and
+// stencil, FP64 reductions, the kernels above) inside an outer iterative
+// refinement whose right-hand side, solution and residual are FP64.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __restrict__ tile_list,
+                                                   const uint32_t* __restrict__ count,
+                                                   const float* __restrict__ u,
+                                                   const float* __restrict__ v,
+                                                   const float* __restrict__ w, double scale,
+                                                   uint8_t* __restrict__ diag,
+                                                   double* __restrict__ b64,
+                                                   double* __restrict__ x64, float* __restrict__ z,
+                                                   float* __restrict__ x, float* __restrict__ s0,
+                                                   float* __restrict__ s1,
+                                                   double* __restrict__ partials, int64_t pstride,
+                                                   PcgState* __restrict__ ps, double tol,
+                                                   int max_iters, double ir_tol, int max_outer)
+{
+    __shared__ double red[PNT / WAVE];
+    __shared__ bool last;
+    unsigned* const sync = pcg_sync(ps);
+    const int slot = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t t = tile_list[slot];
+    const int ti = (int)(t % g.tx), tj = (int)((t / g.tx) % g.ty), tk = (int)(t / ((uint32_t)g.tx * g.ty));
+    const int l = threadIdx.x;
+    const int i = ti * TILE + (l & 7), j = tj * TILE + ((l >> 3) & 7), k = tk * TILE + (l >> 6);
+    int d = 0;
+    double bd = 0.0;
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        const int64_t c = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+        if (count[c] > 0) {
+            d = (i > 0) + (i < g.nx - 1) + (j > 0) + (j < g.ny - 1) + (k > 0) + (k < g.nz - 1);
+            const int64_t fu = i + (int64_t)(g.nx + 1) * (j + (int64_t)g.ny * k);
+            const int64_t fv = i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k);
+            const int64_t fw = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+            // face differences of float samples are exact in double
+            const double div = ((double)u[fu + 1] - (double)u[fu]) + ((double)v[fv + g.nx] - (double)v[fv]) +
+                               ((double)w[fw + (int64_t)g.nx * g.ny] - (double)w[fw]);
+            bd = scale * div;
+        }
+    }
+    const int64_t e = (int64_t)slot * TILE_CELLS + l;
+    const float zq = d ? (float)(bd / d) : 0.0f;
+    diag[e] = (uint8_t)d;
+    b64[e] = bd;
+    x64[e] = 0.0;
+    z[e] = zq;
+    x[e] = 0.0f;
+    s0[e] = 0.0f;
+    s1[e] = 0.0f;
+    const double rz = block_sum<PNT>((double)d * (double)zq * (double)zq, red);
+    const double mb = block_max<PNT>(finite_or_inf(fabs(bd)), red);
+    const double nf = block_sum<PNT>(d ? 1.0 : 0.0, red);
+    const double vals[3] = {rz, mb, nf};
+    if (!publish_partials(partials, pstride, vals, 3, sync, &last)) return;
+    const int nb = gridDim.x;
+    int err = 0;
+    const double rho = collect_slots<PNT, false>(partials, nb, red, &err);
+    const double max_b = collect_slots<PNT, true>(partials + pstride, nb, red, &err);
+    const double nfl = collect_slots<PNT, false>(partials + 2 * pstride, nb, red, &err);
+    err = __syncthreads_or(err);
+    if (threadIdx.x == 0) {
+        ps->rho = rho;
+        ps->alpha = 0.0;
+        ps->beta = 0.0;
+        ps->max_b = max_b;
+        ps->max_r = max_b;
+        ps->tol = tol;
+        ps->iter = 0;
+        ps->max_iters = max_iters;
+        ps->nfluid = (int)nfl;
+        ps->n_active = nb;
+        ps->max_b0 = max_b;
+        ps->ir_tol = ir_tol;
+        ps->max_r64 = max_b;
+        ps->outer = 0;
+        ps->max_outer = max_outer;
+        ps->outer_done = (max_b == 0.0) ? 1 : 0;
+        ps->done = !(max_b <= DBL_MAX) ? PCG_BREAKDOWN
+                   : (max_b == 0.0)    ? PCG_CONVERGED
+                   : (max_iters <= 0)  ? PCG_MAX_ITERS
+                                       : PCG_RUNNING;
+        ps->sync_error = err;
+        if (err) ps->done = PCG_BREAKDOWN;
+    }
+    reset_arrivals(sync);
+}
+
+void launch_rhs_mixed(const Geo& g, int n_active, const uint32_t* tile_list, const uint32_t* count,
+                      const float* u, const float* v, const float* w, double scale, uint8_t* diag,
+                      double* b64, double* x64, float* z, float* x, float* s0, float* s1,
+                      double* partials, int64_t pstride, PcgState* st_dev, double tol, int max_iters,
+                      double ir_tol, int max_outer, hipStream_t st)
+{
+    if (n_active <= 0) return;
+    hipLaunchKernelGGL(k_rhs_mixed, dim3((unsigned)n_active), dim3(PNT), 0, st, g, tile_list, count, u,
+                       v, w, scale, diag, b64, x64, z, x, s0, s1, partials, pstride, st_dev, tol,
+                       max_iters, ir_tol, max_outer);
+}
+
+// One workgroup of 512 threads per active tile. The updated FP64 solution of
+// the tile and its face halos is staged in LDS; the solution is double-buffered
+// (x64_in -> x64_out, x_in -> x_out) because other workgroups read this tile's
+// values as their halo.
+__global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ nbr,
+                                                   const uint8_t* __restrict__ diag,
+                                                   const double* __restrict__ b64,
+                                                   const double* __restrict__ x64_in,
+                                                   double* __restrict__ x64_out,
+                                                   const float* __restrict__ x_in,
+                                                   float* __restrict__ x_out, float* __restrict__ z,
+                                                   float* __restrict__ s0, float* __restrict__ s1,
+                                                   double* __restrict__ partials, int64_t pstride,
+                                                   PcgState* __restrict__ ps)
+{
+    __shared__ double stg[STAGE];
+    __shared__ double red[PNT / WAVE];
+    __shared__ bool last;
+    unsigned* const sync = pcg_sync(ps);
+    const int slot = xcd_remap(blockIdx.x, gridDim.x);
+    const int l = threadIdx.x;
+    const int64_t e = (int64_t)slot * TILE_CELLS + l;
+    const double xn = x64_in[e] + (double)x_in[e];
+    stg[l] = xn;
+    if (l < HALO) {
+        const int f = l >> 6;
+        const int32_t ns = nbr[(int64_t)slot * 6 + f];
+        double hv = 0.0;
+        if (ns >= 0) {
+            const int64_t en = (int64_t)ns * TILE_CELLS + halo_source(f, l & 63);
+            hv = x64_in[en] + (double)x_in[en];
+        }
+        stg[TILE_CELLS + l] = hv;
+    }
+    __syncthreads();
+    const int d = diag[e];
+    double r = 0.0;
+    float zq = 0.0f;
+    if (d) {
+        r = b64[e] - fma((double)d, xn, -neighbour_sum(stg, l));
+        zq = (float)(r / d);
+    }
+    x64_out[e] = xn;
+    x_out[e] = 0.0f;
+    z[e] = zq;
+    s0[e] = 0.0f;
+    s1[e] = 0.0f;
+    const double mr = block_max<PNT>(finite_or_inf(fabs(r)), red);
+    const double rz = block_sum<PNT>((double)d * (double)zq * (double)zq, red);
+    const double vals[2] = {rz, mr};
+    if (!publish_partials(partials, pstride, vals, 2, sync, &last)) return;
+    int err = 0;
+    const double rho = collect_slots<PNT, false>(partials, gridDim.x, red, &err);
+    const double max_r = collect_slots<PNT, true>(partials + pstride, gridDim.x, red, &err);
+    err = __syncthreads_or(err);
+    if (threadIdx.x == 0) {
+        const int outer = ps->outer + 1;
+        ps->outer = outer;
+        ps->max_r64 = max_r;
+        if (err || !(max_r <= DBL_MAX)) {
+            ps->done = PCG_BREAKDOWN;
+            ps->outer_done = 2;
+            if (err) ps->sync_error = 1;
+        } else if (max_r <= ps->ir_tol * ps->max_b0) {
+            ps->done = PCG_CONVERGED;
+            ps->outer_done = 1;
+        } else if (outer >= ps->max_outer) {
+            ps->done = PCG_MAX_ITERS;
+            ps->outer_done = 2;
+        } else {
+            // restart the inner solve on the new residual
+            ps->done = PCG_RUNNING;
+            ps->iter = 0;
+            ps->max_b = max_r;
+            ps->max_r = max_r;
+            ps->rho = rho;
+            ps->alpha = 0.0;
+            ps->beta = 0.0;
+        }
+    }
+    reset_arrivals(sync);
+}
+
+void launch_ir_update(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const double* b64,
+                      const double* x64_in, double* x64_out, const float* x_in, float* x_out,
+                      float* z, float* s0, float* s1, double* partials, int64_t pstride,
+                      PcgState* st_dev, hipStream_t st)
+{
+    if (n_active <= 0) return;
+    hipLaunchKernelGGL(k_ir_update, dim3((unsigned)n_active), dim3(PNT), 0, st, tile_nbr, diag, b64,
+                       x64_in, x64_out, x_in, x_out, z, s0, s1, partials, pstride, st_dev);
+}
 
 // ---------------------------------------------------------------------------
 // projection, Eq. (5): u = u* - (dt / (rho dx)) (p+ - p-) on every non-wall
@@ -447,6 +725,9 @@ template void launch_project<float, float>(const Geo&, int, const uint32_t*, con
 template void launch_project<double, double>(const Geo&, int, const uint32_t*, const int32_t*,
                                              const double*, const double*, double*, double,
                                              hipStream_t);
+template void launch_project<float, double>(const Geo&, int, const uint32_t*, const int32_t*,
+                                            const double*, const float*, float*, float,
+                                            hipStream_t);
 
 // ---------------------------------------------------------------------------
 // compact tile storage -> dense cell array (readback of b and p)

@@ -21,142 +21,119 @@ __device__ inline T hat(T r)
     return a > T(0) ? a : T(0);
 }
 
-// One thread per cell computes the three faces on the cell's low sides: u at
-// (i, j+1/2, k+1/2), v at (i+1/2, j, k+1/2), w at (i+1/2, j+1/2, k) (cell
-// units). Their hats can only reach particles of the 3x3x3 cells around the
-// cell; neighbour cell (i+di, j+dj, k+dk) can feed u only if di <= 0, v only if
-// dj <= 0 and w only if dk <= 0, which the unrolled loops resolve at compile
-// time. Each weight is rounded once and the same value enters both sums (no
-// contraction of products into the additions), so a uniform power-of-two
-// velocity comes back exactly. The faces on the domain's high sides
-// (i = nx, j = ny, k = nz) are done by k_p2g_high_faces.
-template <typename T>
-__global__ __launch_bounds__(256) void k_p2g_cells(Geo g, const T* __restrict__ px,
-                                                   const T* __restrict__ py, const T* __restrict__ pz,
-                                                   const T* __restrict__ vx, const T* __restrict__ vy,
-                                                   const T* __restrict__ vz,
-                                                   const uint32_t* __restrict__ start,
-                                                   const uint32_t* __restrict__ count, T gdt_x,
-                                                   T gdt_y, T gdt_z, T* __restrict__ u_old,
-                                                   T* __restrict__ v_old, T* __restrict__ w_old,
-                                                   T* __restrict__ u_star, T* __restrict__ v_star,
-                                                   T* __restrict__ w_star)
+// Particle-to-grid as an LDS splat, one wave per 8x8x8 tile of cells.
+//
+// The wave owns the tile's faces and accumulates their weight sums W and
+// weighted velocity sums M in LDS (u: 9x8x8 samples, v: 8x9x8, w: 8x8x9; the
+// ninth layer covers the domain's high side). It scatters every particle of
+// the tile and of the one-cell ring around it; samples outside the tile are
+// left to the neighbouring tile. A particle of cell c only reaches samples
+// within one index of c on each axis, so cells whose coordinates agree modulo
+// 3 never reach a common sample: the cells are visited in 27 phases, one per
+// residue class (at most 4 x 4 x 4 cells of the 10^3 ring box, one per lane),
+// and within a phase every lane updates its own samples with plain LDS
+// read-modify-writes. Each sample therefore sums its contributions in a fixed
+// order (phase, then particle order in the cell): the result is the same on
+// every run, needs no atomics, and - because each weight is rounded once and
+// enters W and M unchanged (no contraction) - a uniform power-of-two velocity
+// comes back exactly. Hat arguments are formed in double: in float, x / dx
+// carries an absolute error of ~1e-6 cells, a large relative error for the
+// small weights near the edge of a hat's support.
+constexpr int P2G_T = 8;
+constexpr int P2G_BOX = (P2G_T + 1) * P2G_T * P2G_T;  // 576 samples per component
+
+template <typename T, int A>
+__device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, double gy, double gz, T v)
 {
-    // block = 8 x 8 x 4 cells, one wave per z layer
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-    const int t = threadIdx.x;
-    const int i = bx * 8 + (t & 7), j = by * 8 + ((t >> 3) & 7), k = bz * 4 + (t >> 6);
-    if (i >= g.nx || j >= g.ny || k >= g.nz) return;
-    // hat arguments are formed in double: in float, x / dx carries an absolute
-    // error of ~1e-6 cells, which is a large relative error in the small
-    // weights of particles near the edge of a hat's support
-    const double inv = g.inv_dx;
-
-    uint32_t cs[27], cn[27];
+    // sample coordinates of this component (centre-aligned axes shifted by 1/2)
+    const double ax = A == 0 ? gx : gx - 0.5, ay = A == 1 ? gy : gy - 0.5, az = A == 2 ? gz : gz - 0.5;
+    const double fx = floor(ax), fy = floor(ay), fz = floor(az);
+    const int i0 = (int)fx - x0, j0 = (int)fy - y0, k0 = (int)fz - z0;
+    const double wx[2] = {hat(ax - fx), hat(ax - fx - 1.0)};
+    const double wy[2] = {hat(ay - fy), hat(ay - fy - 1.0)};
+    const double wz[2] = {hat(az - fz), hat(az - fz - 1.0)};
+    constexpr int DX = P2G_T + (A == 0), DY = P2G_T + (A == 1), DZ = P2G_T + (A == 2);
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-        const int ii = i + (q % 3) - 1, jj = j + ((q / 3) % 3) - 1, kk = k + (q / 9) - 1;
-        const bool in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
-        const int64_t c = in ? ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk) : 0;
-        cn[q] = in ? count[c] : 0u;
-        cs[q] = in ? start[c] : 0u;
-    }
-
-    T Wu = T(0), Mu = T(0), Wv = T(0), Mv = T(0), Ww = T(0), Mw = T(0);
-    {
-#pragma clang fp contract(off)
+    for (int dk = 0; dk < 2; ++dk)
 #pragma unroll
-        for (int q = 0; q < 27; ++q) {
-            const int di = (q % 3) - 1, dj = ((q / 3) % 3) - 1, dk = (q / 9) - 1;
-            const bool fu = di <= 0, fv = dj <= 0, fw = dk <= 0;
-            if (!(fu || fv || fw)) continue;
-            for (uint32_t p = cs[q]; p < cs[q] + cn[q]; ++p) {
-                const double gx = (double)px[p] * inv - i, gy = (double)py[p] * inv - j,
-                             gz = (double)pz[p] * inv - k;
-                // node-aligned and centre-aligned hats on each axis
-                const double xn = hat(gx), xc = hat(gx - 0.5);
-                const double yn = hat(gy), yc = hat(gy - 0.5);
-                const double zn = hat(gz), zc = hat(gz - 0.5);
-                if (fu) {
-                    const T w = (T)(xn * yc * zc);
-                    Wu = Wu + w;
-                    Mu = fma(vx[p], w, Mu);
-                }
-                if (fv) {
-                    const T w = (T)(xc * yn * zc);
-                    Wv = Wv + w;
-                    Mv = fma(vy[p], w, Mv);
-                }
-                if (fw) {
-                    const T w = (T)(xc * yc * zn);
-                    Ww = Ww + w;
-                    Mw = fma(vz[p], w, Mw);
-                }
+        for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+                const int li = i0 + di, lj = j0 + dj, lk = k0 + dk;
+                if (li < 0 || li >= DX || lj < 0 || lj >= DY || lk < 0 || lk >= DZ) continue;
+                const T w = (T)(wx[di] * wy[dj] * wz[dk]);
+                T* a = acc[li + DX * (lj + DY * lk)];
+                a[0] = a[0] + w;
+                a[1] = fma(v, w, a[1]);
             }
-        }
-    }
-    const T ru = Wu > T(0) ? Mu / Wu : T(0);
-    const T rv = Wv > T(0) ? Mv / Wv : T(0);
-    const T rw = Ww > T(0) ? Mw / Ww : T(0);
-    const int64_t fu = i + (int64_t)(g.nx + 1) * (j + (int64_t)g.ny * k);
-    const int64_t fv = i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k);
-    const int64_t fw = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-    u_old[fu] = ru;
-    v_old[fv] = rv;
-    w_old[fw] = rw;
-    // gravity on every face, then zero normal velocity on the walls
-    u_star[fu] = i == 0 ? T(0) : ru + gdt_x;
-    v_star[fv] = j == 0 ? T(0) : rv + gdt_y;
-    w_star[fw] = k == 0 ? T(0) : rw + gdt_z;
 }
 
-// Faces on the domain's high sides (u at i = nx, v at j = ny, w at k = nz):
-// one thread per face, gathering from the cells its hat can reach.
-template <typename T, int A>
-__global__ __launch_bounds__(256) void k_p2g_high_faces(Geo g, const T* __restrict__ px,
-                                                        const T* __restrict__ py,
-                                                        const T* __restrict__ pz,
-                                                        const T* __restrict__ vel,
-                                                        const uint32_t* __restrict__ start,
-                                                        const uint32_t* __restrict__ count,
-                                                        T* __restrict__ out_old,
-                                                        T* __restrict__ out_star)
+template <typename T>
+__global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, const T* __restrict__ px,
+                                                  const T* __restrict__ py, const T* __restrict__ pz,
+                                                  const T* __restrict__ vx, const T* __restrict__ vy,
+                                                  const T* __restrict__ vz,
+                                                  const uint32_t* __restrict__ start,
+                                                  const uint32_t* __restrict__ count, T gdt_x,
+                                                  T gdt_y, T gdt_z, T* __restrict__ u_old,
+                                                  T* __restrict__ v_old, T* __restrict__ w_old,
+                                                  T* __restrict__ u_star, T* __restrict__ v_star,
+                                                  T* __restrict__ w_star)
 {
-    // the plane is indexed by the two other axes (a, b)
-    const int na = A == 0 ? g.ny : g.nx, nb = A == 2 ? g.ny : g.nz;
-    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (m >= (int64_t)na * nb) return;
-    const int a = (int)(m % na), b = (int)(m / na);
-    const int i = A == 0 ? g.nx : a;
-    const int j = A == 1 ? g.ny : (A == 0 ? a : b);
-    const int k = A == 2 ? g.nz : b;
-    const double fx = i + (A == 0 ? 0.0 : 0.5);
-    const double fy = j + (A == 1 ? 0.0 : 0.5);
-    const double fz = k + (A == 2 ? 0.0 : 0.5);
-    const double inv = g.inv_dx;
-    const int i0 = max(i - 1, 0), i1 = min(A == 0 ? i : i + 1, g.nx - 1);
-    const int j0 = max(j - 1, 0), j1 = min(A == 1 ? j : j + 1, g.ny - 1);
-    const int k0 = max(k - 1, 0), k1 = min(A == 2 ? k : k + 1, g.nz - 1);
-    T W = T(0), M = T(0);
-    {
 #pragma clang fp contract(off)
-        for (int kk = k0; kk <= k1; ++kk)
-            for (int jj = j0; jj <= j1; ++jj)
-                for (int ii = i0; ii <= i1; ++ii) {
-                    const int64_t c = ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk);
-                    const uint32_t s0 = start[c], n = count[c];
-                    for (uint32_t q = s0; q < s0 + n; ++q) {
-                        const T w = (T)(hat((double)px[q] * inv - fx) * hat((double)py[q] * inv - fy) *
-                                        hat((double)pz[q] * inv - fz));
-                        W = W + w;
-                        M = fma(vel[q], w, M);
-                    }
-                }
+    __shared__ T acc[3][P2G_BOX][2];
+    const int lane = threadIdx.x;
+    const int x0 = blockIdx.x * P2G_T, y0 = blockIdx.y * P2G_T, z0 = blockIdx.z * P2G_T;
+    for (int q = lane; q < 3 * P2G_BOX * 2; q += 64) (&acc[0][0][0])[q] = T(0);
+    __syncthreads();
+    // ring box of cells, clipped to the domain (inclusive bounds)
+    const int rx0 = max(x0 - 1, 0), rx1 = min(x0 + P2G_T, g.nx - 1);
+    const int ry0 = max(y0 - 1, 0), ry1 = min(y0 + P2G_T, g.ny - 1);
+    const int rz0 = max(z0 - 1, 0), rz1 = min(z0 + P2G_T, g.nz - 1);
+    const double inv = g.inv_dx;
+    for (int ph = 0; ph < 27; ++ph) {
+        const int cx = rx0 + ((ph % 3) - rx0 % 3 + 3) % 3 + 3 * (lane & 3);
+        const int cy = ry0 + (((ph / 3) % 3) - ry0 % 3 + 3) % 3 + 3 * ((lane >> 2) & 3);
+        const int cz = rz0 + ((ph / 9) - rz0 % 3 + 3) % 3 + 3 * (lane >> 4);
+        if (cx <= rx1 && cy <= ry1 && cz <= rz1) {
+            const int64_t c = cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
+            const uint32_t s0 = start[c], n = count[c];
+            for (uint32_t q = s0; q < s0 + n; ++q) {
+                const double gx = (double)px[q] * inv, gy = (double)py[q] * inv, gz = (double)pz[q] * inv;
+                splat<T, 0>(acc[0], x0, y0, z0, gx, gy, gz, vx[q]);
+                splat<T, 1>(acc[1], x0, y0, z0, gx, gy, gz, vy[q]);
+                splat<T, 2>(acc[2], x0, y0, z0, gx, gy, gz, vz[q]);
+            }
+        }
+        __syncthreads();
     }
-    const int dX = g.nx + (A == 0), dY = g.ny + (A == 1);
-    const int64_t f = i + (int64_t)dX * (j + (int64_t)dY * k);
-    out_old[f] = W > T(0) ? M / W : T(0);
-    out_star[f] = T(0);  // wall
+    // write the samples this tile owns: [x0, x0+8) on every axis, plus the
+    // domain's high side when the tile touches it
+    const int ex = min(x0 + P2G_T, g.nx), ey = min(y0 + P2G_T, g.ny), ez = min(z0 + P2G_T, g.nz);
+    const T gdt[3] = {gdt_x, gdt_y, gdt_z};
+    T* const olds[3] = {u_old, v_old, w_old};
+    T* const stars[3] = {u_star, v_star, w_star};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int DX = P2G_T + (a == 0), DY = P2G_T + (a == 1);
+        const int fX = g.nx + (a == 0), fY = g.ny + (a == 1);
+        for (int q = lane; q < P2G_BOX; q += 64) {
+            const int li = q % DX, lj = (q / DX) % DY, lk = q / (DX * DY);
+            const int i = x0 + li, j = y0 + lj, k = z0 + lk;
+            const bool own = (a == 0 ? (i < ex || i == g.nx) : i < ex) &&
+                             (a == 1 ? (j < ey || j == g.ny) : j < ey) &&
+                             (a == 2 ? (k < ez || k == g.nz) : k < ez) &&
+                             i <= g.nx && j <= g.ny && k <= g.nz;
+            if (!own) continue;
+            const T W = acc[a][q][0], M = acc[a][q][1];
+            const T raw = W > T(0) ? M / W : T(0);
+            const int idx = a == 0 ? i : (a == 1 ? j : k);
+            const int lim = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
+            const int64_t f = i + (int64_t)fX * (j + (int64_t)fY * k);
+            olds[a][f] = raw;
+            stars[a][f] = (idx == 0 || idx == lim) ? T(0) : raw + gdt[a];
+        }
+    }
 }
 
 template <typename T>
@@ -164,17 +141,10 @@ void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint3
                 const uint32_t* count, const T gdt[3], T* const old[3], T* const star[3],
                 hipStream_t st)
 {
-    const dim3 grid((unsigned)((g.nx + 7) / 8), (unsigned)((g.ny + 7) / 8), (unsigned)((g.nz + 3) / 4));
-    hipLaunchKernelGGL(k_p2g_cells<T>, grid, dim3(256), 0, st, g, pos, pos + n, pos + 2 * n, vel,
+    const dim3 grid((unsigned)g.tx, (unsigned)g.ty, (unsigned)g.tz);
+    hipLaunchKernelGGL(k_p2g_tiles<T>, grid, dim3(64), 0, st, g, pos, pos + n, pos + 2 * n, vel,
                        vel + n, vel + 2 * n, start, count, gdt[0], gdt[1], gdt[2], old[0], old[1],
                        old[2], star[0], star[1], star[2]);
-    const int64_t planes[3] = {(int64_t)g.ny * g.nz, (int64_t)g.nx * g.nz, (int64_t)g.nx * g.ny};
-    hipLaunchKernelGGL((k_p2g_high_faces<T, 0>), dim3((unsigned)((planes[0] + 255) / 256)), dim3(256),
-                       0, st, g, pos, pos + n, pos + 2 * n, vel, start, count, old[0], star[0]);
-    hipLaunchKernelGGL((k_p2g_high_faces<T, 1>), dim3((unsigned)((planes[1] + 255) / 256)), dim3(256),
-                       0, st, g, pos, pos + n, pos + 2 * n, vel + n, start, count, old[1], star[1]);
-    hipLaunchKernelGGL((k_p2g_high_faces<T, 2>), dim3((unsigned)((planes[2] + 255) / 256)), dim3(256),
-                       0, st, g, pos, pos + n, pos + 2 * n, vel + 2 * n, start, count, old[2], star[2]);
 }
 
 template void launch_p2g<float>(const Geo&, const float*, const float*, int64_t, const uint32_t*,

@@ -80,8 +80,7 @@ class flip_step_stats(ctypes.Structure):
                 ("pcg_iterations", ctypes.c_int32), ("pcg_status", ctypes.c_int32),
                 ("max_b", ctypes.c_double), ("max_r", ctypes.c_double),
                 ("pcg_iterations_total", ctypes.c_int64), ("pcg_cell_iterations_total", ctypes.c_int64),
-                ("latched_status", ctypes.c_int32),
-                ("pad_", ctypes.c_int32), ("kernel_ms", ctypes.c_double * FLIP_KERNEL_COUNT),
+                ("latched_status", ctypes.c_int32), ("refinements", ctypes.c_int32), ("kernel_ms", ctypes.c_double * FLIP_KERNEL_COUNT),
                 ("kernel_launches", ctypes.c_int64 * FLIP_KERNEL_COUNT)]
 
 
@@ -260,6 +259,8 @@ class Simulation:
             return np.uint32
         if field == FLIP_FIELD_FLAGS:
             return np.uint8
+        if field in (FLIP_FIELD_RHS, FLIP_FIELD_PRESSURE) and self.cfg.precision == FLIP_MIXED:
+            return np.float64
         return self.real
 
     def read(self, field: int) -> np.ndarray:

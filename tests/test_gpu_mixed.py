@@ -1,0 +1,115 @@
+"""Mixed-precision form of the solve (FLIP_MIXED): FP32 inner Jacobi-PCG with
+FP64 reductions inside an FP64 iterative refinement of b - A x.
+
+Checked on the drop scene at 64^3 against the FP64 oracle and against the plain
+FP32 and FP64 GPU paths, each started from its own seeded state:
+- the FP64 residual max|b - A p| / max|b| of the mixed result, evaluated by the
+  oracle on the GPU's own FP64 right-hand side, is at or below the refinement
+  tolerance (1e-8);
+- the mixed pressure matches the oracle's exact solve of that right-hand side
+  far more closely than the FP32 path's;
+- per-field errors (pressure, projected face velocity, particle velocity and
+  position after one step) against the oracle's step are printed as a table.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_01931_amd import flip, inputs
+from tests.gpu_util import grid_of, l2_rel, log, max_rel, params_of, state
+
+pytestmark = pytest.mark.gpu
+
+IR_TOL = 1e-8
+
+
+def _run(prec, inner_tol):
+    sc = inputs.scene("drop64")
+    cfg, keep = flip.scene_config(sc, precision=prec, pcg_tol=inner_tol)
+    cfg.ir_tol = IR_TOL
+    sim = flip.Simulation(cfg, keep)
+    pos0, vel0, ids0 = state(sim)
+    sim.step(1)
+    out = {
+        "sim": sim, "pos0": pos0, "vel0": vel0, "ids0": ids0, "stats": sim.stats(),
+        "b": sim.read(flip.FLIP_FIELD_RHS).astype(np.float64),
+        "p": sim.read(flip.FLIP_FIELD_PRESSURE).astype(np.float64),
+        "flags": sim.read(flip.FLIP_FIELD_FLAGS),
+        "u_new": [f.astype(np.float64) for f in sim.faces(flip.FLIP_FIELD_U_NEW)],
+    }
+    out["pos1"], out["vel1"], out["ids1"] = state(sim)
+    return out
+
+
+def test_mixed_precision_solve_reaches_fp64_residual_and_error_table(orc):
+    runs = {}
+    for name, prec, tol in [("fp32", flip.FLIP_FP32, 1e-6), ("mixed", flip.FLIP_MIXED, 1e-4),
+                            ("fp64", flip.FLIP_FP64, 1e-6)]:
+        log(f"[mixed] drop64 {name}")
+        runs[name] = _run(prec, tol)
+    rows = []
+    for name, r in runs.items():
+        sim = r["sim"]
+        g = grid_of(sim)
+        fl = r["flags"]
+        st = r["stats"]
+        # the solve alone: oracle's exact solution of the GPU's own system
+        exact = orc.pcg(g, fl, r["b"], 1e-13, 100000)
+        true_res = np.abs(r["b"] - orc.apply_A(g, fl, r["p"])).max() / np.abs(r["b"]).max()
+        p_err = l2_rel(r["p"], exact.p)
+        # the whole step: oracle's step (exact solve) from the same state
+        ref = orc.step(params_of(sim), r["pos0"], r["vel0"], r["ids0"])
+        assert np.array_equal(ref.ids, r["ids1"])
+        u_err = max(l2_rel(r["u_new"][a], ref.u_new[a]) for a in range(3))
+        v_err = l2_rel(r["vel1"], ref.vel)
+        x_err = float(np.abs(r["pos1"] - ref.pos).max())
+        p_step = l2_rel(r["p"], ref.solve.p)
+        rows.append((name, st.pcg_iterations, st.refinements, true_res, p_err, p_step, u_err, v_err, x_err))
+        r["true_res"], r["p_err"], r["v_err"] = true_res, p_err, v_err
+        sim.close()
+    log("[mixed] precision  iters refin  true_res    p(solve)    p(step)     u_new       v_particle  x_max_abs")
+    for row in rows:
+        log("[mixed] %-9s %6d %5d  %.3e   %.3e   %.3e   %.3e   %.3e   %.3e" % row)
+    m, f32, f64 = runs["mixed"], runs["fp32"], runs["fp64"]
+    assert m["stats"].pcg_status == 0 and m["stats"].refinements >= 1
+    assert m["stats"].max_r <= IR_TOL * m["stats"].max_b * (1 + 1e-9)
+    assert m["true_res"] <= 1.01 * IR_TOL            # independent FP64 check by the oracle
+    assert f64["true_res"] <= 1.01e-6
+    assert m["p_err"] < 0.1 * f32["p_err"]             # the refinement buys real accuracy
+    assert m["p_err"] <= 1e-6
+    for r in runs.values():
+        assert r["v_err"] <= 1e-4
+
+
+def test_mixed_precision_shadowed_steps(orc):
+    log("[mixed] shadow drop64 mixed x3")
+    sc = inputs.scene("drop64")
+    cfg, keep = flip.scene_config(sc, precision=flip.FLIP_MIXED, pcg_tol=1e-4)
+    cfg.ir_tol = IR_TOL
+    sim = flip.Simulation(cfg, keep)
+    prm = params_of(sim)
+    for s in range(3):
+        pos0, vel0, ids0 = state(sim)
+        sim.step(1)
+        pos1, vel1, ids1 = state(sim)
+        st = sim.stats()
+        assert st.pcg_status == 0 and st.max_r <= IR_TOL * st.max_b * (1 + 1e-9)
+        res = orc.step(prm, pos0, vel0, ids0)
+        assert np.array_equal(res.ids, ids1)
+        assert l2_rel(vel1, res.vel) <= 1e-4
+        assert max_rel(pos1, res.pos) <= 1e-5
+    sim.close()
+
+
+def test_mixed_refinement_limit_is_reported():
+    log("[mixed] refinement limit")
+    sc = inputs.scene("drop64")
+    # an unreachable outer tolerance: the step completes, reports non-convergence
+    cfg, keep = flip.scene_config(sc, precision=flip.FLIP_MIXED, pcg_tol=1e-4)
+    cfg.ir_tol = 1e-30
+    sim = flip.Simulation(cfg, keep)
+    status = sim.step(1, allow=(flip.FLIP_E_NOT_CONVERGED,))
+    st = sim.stats()
+    assert status == flip.FLIP_E_NOT_CONVERGED and st.pcg_status == 1 and st.refinements == 20
+    assert np.all(np.isfinite(sim.read(flip.FLIP_FIELD_VEL)))
+    sim.close()
