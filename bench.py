@@ -16,6 +16,7 @@ Usage: python bench.py [--gpus 1] [--steps 30] [--warmup 3] [--scene drop256]
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -108,14 +109,76 @@ def cpu_baseline(sample_scene: str):
     }
 
 
+def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plain_sample: int):
+    """The batched-serving form: a stream of independent dam-break and drop
+    scenes (sides 32/48/64/96, 8 particles per cell, 100 FP32 steps each at
+    dt = 1/240, Poisson arrivals at 200 / s) through the continuous-batching
+    server under an HBM budget, beside the plain path (flip_step, one scene at
+    a time) on the first scenes of the same stream."""
+    import torch
+
+    from paper_2404_01931_amd import flip, inputs
+    from paper_2404_01931_amd.serving import FlipBackend, Server, requests_from_scenes
+
+    stream = inputs.serving_scenes(count=n_scenes)
+    reqs = requests_from_scenes(stream)
+    be = FlipBackend(graphs=graphs)
+    # warm the kernels and the graph path on two tiny requests
+    warm = [(0.0, dataclasses.replace(sc, steps=3)) for _, sc in stream[:2]]
+    Server(be, budget_bytes=2**34, max_slots=4).run(requests_from_scenes(warm))
+    budget = int(budget_gib * 2**30)
+    progress(f"serving: {n_scenes} scenes, budget {budget_gib} GiB, {slots} slots, graphs={graphs}")
+    rep = Server(be, budget_bytes=budget, max_slots=slots).run(reqs)
+    s = rep.summary()
+    progress(f"serving: {s['completed']} scenes in {s['wall_s']:.2f} s, {s['particle_steps_per_s']:.3e} "
+             f"particle-steps/s, step p50 {s['step_latency_ms_p50']:.2f} ms p99 {s['step_latency_ms_p99']:.2f} ms")
+    # the plain path, one scene at a time, GPU stepping time only
+    ps_plain, t_plain = 0, 0.0
+    for _, sc in stream[:plain_sample]:
+        cfg, keep = flip.scene_config(sc)
+        sim = flip.Simulation(cfg, keep)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.step(sc.steps)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - t
+        ps_plain += sim.n * sc.steps
+        sim.close()
+    plain = ps_plain / t_plain if t_plain > 0 else None
+    # the batched path on the same sample, all admitted at once
+    sample = requests_from_scenes([(0.0, sc) for _, sc in stream[:plain_sample]])
+    rep_b = Server(be, budget_bytes=2**38, max_slots=max(plain_sample, 1)).run(sample)
+    sb = rep_b.summary()
+    progress(f"serving: plain {plain:.3e} vs batched {sb['particle_steps_per_s']:.3e} particle-steps/s "
+             f"on the first {plain_sample} scenes")
+    return {
+        "workload": f"{n_scenes} scenes of the serving stream (dam break / drop, sides 32-96, 8 ppc, "
+                    f"100 FP32 steps, dt 1/240, Poisson arrivals 200/s)",
+        "budget_GiB": budget_gib, "max_slots": slots, "graphs": graphs,
+        **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()},
+        "plain_sample_scenes": plain_sample,
+        "plain_particle_steps_per_s": plain,
+        "batched_sample_particle_steps_per_s": sb["particle_steps_per_s"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scene", default="drop256")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default=None,
+                    help="override the scene's precision")
     ap.add_argument("--cpu-sample", default="drop128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-scenes", type=int, default=128,
+                    help="scenes of the serving stream to serve after the main benchmark (0: skip)")
+    ap.add_argument("--serving-budget-gib", type=float, default=4.0)
+    ap.add_argument("--serving-slots", type=int, default=128)
+    ap.add_argument("--serving-no-graphs", action="store_true")
+    ap.add_argument("--serving-plain-sample", type=int, default=16)
+    ap.add_argument("--serving-only", action="store_true", help="skip the 256^3 benchmark")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scales HBM counters)")
     args = ap.parse_args()
@@ -141,7 +204,14 @@ def main():
     from paper_2404_01931_amd import flip, inputs
 
     torch.cuda.set_device(0)
+    if args.serving_only:
+        out = serving_leg(args.serving_scenes, args.serving_budget_gib, args.serving_slots,
+                          not args.serving_no_graphs, args.serving_plain_sample)
+        print(json.dumps({"serving": out}), flush=True)
+        return
     sc = inputs.scene(args.scene)
+    if args.precision:
+        sc = inputs.scene(args.scene, precision=args.precision)
     cfg, keep = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING)
     progress(f"init {sc.name}")
     t = time.perf_counter()
@@ -187,12 +257,21 @@ def main():
                 "avg_launch_ms": round(kd["avg_ms"], 5), "bytes_per_launch": abytes}
     pcg_ms = sum(kernels[k]["est_total_ms"] for k in ("pcg_direction", "pcg_update") if k in kernels)
     pcg_bytes = d_cell_iter * (8 * rb + 2)
+    s_last = sim.stats()
     pcg = {"iterations_per_step": d_iter / args.steps, "fluid_cells": round(fluid_avg),
+           "last_residual_rel": s_last.max_r / s_last.max_b if s_last.max_b else 0.0,
+           "refinements_last_step": s_last.refinements,
            "algorithmic_GBps": round(pcg_bytes / (pcg_ms * 1e-3) / 1e9, 1) if pcg_ms else None,
            "frac_of_hbm_peak": round(pcg_bytes / (pcg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if pcg_ms else None,
            "ms_per_step": round(pcg_ms / args.steps, 3)}
     stage_ms = {k: round(v["est_total_ms"] / args.steps, 3) for k, v in kernels.items()}
     progress(f"per-step kernel ms: {stage_ms}")
+
+    sim.close()
+    serving = None
+    if args.serving_scenes > 0:
+        serving = serving_leg(args.serving_scenes, args.serving_budget_gib, args.serving_slots,
+                              not args.serving_no_graphs, args.serving_plain_sample)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -211,18 +290,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if rb == 4 else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "f32+f64"}[sc.precision],
         "data": "synthetic",
-        "config": {"workload": f"{sc.name}: drop into pool, {sc.n}^3 MAC grid, {n} particles, FP32, "
-                               f"dt=1/{round(1 / sc.dt)}, FLIP {sc.flip_ratio}, Jacobi-PCG tol {sc.tol:g}",
+        "config": {"workload": f"{sc.name}: drop into pool, {sc.n}^3 MAC grid, {n} particles, "
+                               f"{sc.precision.upper()}, dt=1/{round(1 / sc.dt)}, FLIP {sc.flip_ratio}, "
+                               f"Jacobi-PCG tol {sc.tol:g}"
+                               + (f", FP64 refinement to {sc.ir_tol:g}" if sc.precision == "mixed" else ""),
                    "grid": sc.n, "particles": n, "parallelism": "single GPU"},
         "roofline": roofline,
         "pcg": pcg,
         "kernel_ms_per_step": stage_ms,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    sim.close()
 
 
 if __name__ == "__main__":

@@ -190,6 +190,53 @@ flip_status flip_stats(flip_handle* h, flip_step_stats* out);
 /* Release the handle (not the workspace). NULL is ignored. */
 void flip_destroy(flip_handle* h);
 
+/* ---- batched stepping (serving many independent scenes) -----------------
+ *
+ * A batch advances several scenes together: every kernel of the step is
+ * launched once for all scenes, each workgroup working on one scene, so a
+ * step of many small scenes costs about as many launches as a step of one.
+ * Each scene keeps its own state in its own workspace, its own reductions
+ * and its own convergence test (a converged scene's solver workgroups exit at
+ * once while the others iterate). A scene's results are bitwise those that
+ * flip_step gives for the same handle alone: the same kernels run with the
+ * same per-scene work split and reduction order.
+ *
+ * Requirements: 1 <= nscenes <= FLIP_BATCH_MAX_SCENES initialised handles,
+ * all FLIP_FP32 or all FLIP_FP64 (FLIP_MIXED is not batched), none with
+ * FLIP_FLAG_NO_PROJECTION or FLIP_FLAG_KERNEL_TIMING, no handle twice. The
+ * handles stay owned by the caller, must outlive the batch and must not be
+ * stepped by other calls while the batch steps.
+ *
+ * The launch tables live in a caller-owned device workspace
+ * (flip_batch_workspace_bytes, 256-byte aligned), written once by
+ * flip_batch_create. With FLIP_BATCH_GRAPHS the batch records its launch
+ * sequences as HIP graphs (before the solve, a chunk of solver iterations,
+ * after the solve) from its second step on and replays them; the graphs
+ * are released by flip_batch_destroy. */
+enum { FLIP_BATCH_MAX_SCENES = 256 };
+enum { FLIP_BATCH_GRAPHS = 1u };
+
+typedef struct flip_batch flip_batch;
+
+/* Device workspace needed by a batch of these handles. */
+flip_status flip_batch_workspace_bytes(flip_handle* const* handles, int nscenes, size_t* out_bytes);
+
+/* Build the launch tables of a batch into d_ws (enqueued on hip_stream and
+ * synchronised before returning) and return the batch. flags: FLIP_BATCH_*. */
+flip_status flip_batch_create(flip_handle* const* handles, int nscenes, uint32_t flags, void* d_ws,
+                              size_t ws_bytes, void* hip_stream, flip_batch** out);
+
+/* Run nsteps >= 0 steps of every scene of the batch on hip_stream. As with
+ * flip_step, the host waits at the solver's convergence checks. Each scene's
+ * statistics and latched status are updated as by flip_step; the call
+ * returns the first solver error met by any scene, after completing every
+ * step of every scene. */
+flip_status flip_batch_step(flip_batch* b, int nsteps, void* hip_stream);
+
+/* Release the batch and its graphs (not the workspace or the handles). NULL
+ * is ignored. */
+void flip_batch_destroy(flip_batch* b);
+
 const char* flip_status_string(flip_status s);
 
 #ifdef __cplusplus

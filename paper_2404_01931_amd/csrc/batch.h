@@ -1,0 +1,201 @@
+// Batched launches (internal): one launch runs the same kernel for several
+// scenes. Each scene contributes the grid its plain launch would use; the
+// grids are concatenated and every workgroup finds its scene in a table of
+// first-workgroup offsets. The per-scene arguments are the plain launch's
+// arguments, stored as one struct per scene in device memory.
+#pragma once
+
+#include "common.h"
+
+namespace flipmi {
+
+// Device tables of one batched launch: args[ns] (struct per scene) and
+// first[ns + 1] (first[0] = 0, first[ns] = blocks).
+struct BatchLaunch {
+    const void* args = nullptr;
+    const uint32_t* first = nullptr;
+    int ns = 0;
+    uint32_t blocks = 0;
+};
+
+// workgroups of the plain launches (the batched ones concatenate them)
+constexpr int ELEM_NT = 256;        // one thread per element
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_NT * SCAN_ITEMS;
+inline uint32_t elem_blocks(int64_t n) { return (uint32_t)((n + ELEM_NT - 1) / ELEM_NT); }
+inline uint32_t scan_blocks(int64_t n) { return (uint32_t)((n + SCAN_TILE - 1) / SCAN_TILE); }
+
+// ---- arguments, one struct per kernel --------------------------------------
+
+struct FillU32Args {
+    uint32_t* p;
+    int64_t n;
+    uint32_t v;
+};
+
+template <typename T>
+struct BinKeysArgs {
+    Geo g;
+    const T *px, *py, *pz;
+    int64_t n;
+    uint32_t *key, *rank, *count;
+};
+
+struct ScanTotalsArgs {
+    const uint32_t* in;
+    int64_t n;
+    uint32_t* totals;
+};
+
+struct ScanTotalsScanArgs {
+    uint32_t* totals;
+    int64_t nb;
+};
+
+struct ScanApplyArgs {
+    const uint32_t* in;
+    uint32_t* out;
+    int64_t n;
+    const uint32_t* offsets;
+};
+
+struct ScatterArgs {
+    const uint32_t *key, *rank, *start;
+    int64_t n;
+    uint32_t* perm;
+};
+
+template <typename T>
+struct GatherArgs {
+    const uint32_t *perm, *key, *start, *count;
+    int64_t n;
+    const T *pos_in, *vel_in;
+    const uint32_t* id_in;
+    T *pos_out, *vel_out;
+    uint32_t* id_out;
+};
+
+struct TileFlagsArgs {
+    Geo g;
+    const uint32_t* count;
+    uint32_t* tile_flag;
+};
+
+struct TileCompactArgs {
+    Geo g;
+    const uint32_t *flag, *excl;
+    int32_t* tile_slot;
+    uint32_t* tile_list;
+    int32_t* tile_nbr;
+    uint32_t* d_nactive;
+};
+
+template <typename T>
+struct P2GArgs {
+    Geo g;
+    const T *px, *py, *pz, *vx, *vy, *vz;
+    const uint32_t *start, *count;
+    T gdt[3];
+    T* old[3];
+    T* star[3];
+};
+
+template <typename T, typename V>
+struct RhsArgs {
+    Geo g;
+    const uint32_t *tile_list, *d_nactive, *count;
+    const T *u, *v, *w;
+    double scale;
+    uint8_t* diag;
+    V *b, *z, *x, *s0, *s1;
+    double* partials;
+    int64_t pstride;
+    PcgState* ps;
+    double tol;
+    int max_iters;
+};
+
+template <typename V>
+struct DirArgs {
+    const int32_t* nbr;
+    const uint8_t* diag;
+    const V *z, *s_old;
+    V* s_new;
+    double* partials;
+    PcgState* ps;
+};
+
+template <typename V>
+struct UpdArgs {
+    const int32_t* nbr;
+    const uint8_t* diag;
+    const V* s;
+    V *x, *z;
+    double* partials;
+    int64_t pstride;
+    PcgState* ps;
+};
+
+template <typename T, typename V>
+struct ProjectArgs {
+    Geo g;
+    const uint32_t* count;
+    const int32_t* tile_slot;
+    const V* p;
+    const T* star;
+    T* out;
+    T scale;
+};
+
+template <typename T>
+struct G2PArgs {
+    Geo g;
+    int64_t n;
+    T *px, *py, *pz, *vx, *vy, *vz;
+    const T *un, *vn, *wn, *uo, *vo, *wo;
+    T alpha, dt, skin, Lx, Ly, Lz;
+    int advect_particle_vel;
+};
+
+// Per-scene summary of the solver state after a batched step, gathered into
+// one array so the host reads every scene's state with one copy.
+struct SolveSummary {
+    double max_b, max_r;
+    int iter, done, nfluid, n_active, sync_error, pad_;
+};
+
+struct SummaryArgs {
+    const PcgState* ps;
+    SolveSummary* out;
+};
+
+// ---- batched launchers (asynchronous on st; nothing is launched when
+// L.blocks == 0) --------------------------------------------------------------
+
+void launch_b_fill_u32(const BatchLaunch& L, hipStream_t st);
+template <typename T>
+void launch_b_bin_keys(const BatchLaunch& L, hipStream_t st);
+void launch_b_scan_totals(const BatchLaunch& L, hipStream_t st);
+void launch_b_scan_totals_scan(const BatchLaunch& L, hipStream_t st);
+void launch_b_scan_apply(const BatchLaunch& L, hipStream_t st);
+void launch_b_bin_scatter(const BatchLaunch& L, hipStream_t st);
+template <typename T>
+void launch_b_bin_gather(const BatchLaunch& L, hipStream_t st);
+void launch_b_tile_flags(const BatchLaunch& L, hipStream_t st);
+void launch_b_tile_compact(const BatchLaunch& L, hipStream_t st);
+template <typename T>
+void launch_b_p2g(const BatchLaunch& L, hipStream_t st);
+template <typename T, typename V>
+void launch_b_rhs(const BatchLaunch& L, hipStream_t st);
+template <typename V>
+void launch_b_pcg_direction(const BatchLaunch& L, hipStream_t st);
+template <typename V>
+void launch_b_pcg_update(const BatchLaunch& L, hipStream_t st);
+template <typename T, typename V>
+void launch_b_project(int axis, const BatchLaunch& L, hipStream_t st);
+template <typename T>
+void launch_b_g2p(const BatchLaunch& L, hipStream_t st);
+void launch_b_summary(const BatchLaunch& L, hipStream_t st);
+
+}  // namespace flipmi

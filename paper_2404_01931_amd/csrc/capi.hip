@@ -10,6 +10,7 @@
 
 #include "../../include/flip.h"
 #include "common.h"
+#include "handle.h"
 
 using namespace flipmi;
 
@@ -36,10 +37,6 @@ struct Carver {
     }
 };
 
-struct Sizes {
-    int64_t n = 0, C = 0, T = 0, cap = 0, F[3] = {0, 0, 0};
-    size_t rb = 4;  // bytes of the real type
-};
 
 // ---------------------------------------------------------------------------
 // seeding (paper Sec. 3.1.2): sub^3 jittered subcells per cell whose centre is
@@ -126,49 +123,6 @@ void seed_particles(const flip_config& c, std::vector<T>& pos, std::vector<T>& v
 
 }  // namespace
 
-struct flip_handle {
-    flip_config cfg;  // copy; region / array pointers cleared after init
-    int prec = FLIP_FP32;
-    Geo geo{};
-    Sizes sz;
-    // particles (double-buffered)
-    void* pos[2] = {nullptr, nullptr};
-    void* vel[2] = {nullptr, nullptr};
-    uint32_t* id[2] = {nullptr, nullptr};
-    uint32_t *key = nullptr, *rank = nullptr, *perm = nullptr;
-    // cells
-    uint32_t *count = nullptr, *start = nullptr, *scan_tmp = nullptr;
-    // tiles
-    uint32_t *tile_flag = nullptr, *tile_excl = nullptr, *tile_list = nullptr, *d_nactive = nullptr;
-    int32_t *tile_slot = nullptr, *tile_nbr = nullptr;
-    // faces
-    void* f_old[3] = {};
-    void* f_star[3] = {};
-    void* f_new[3] = {};
-    // solver (compact tile storage)
-    uint8_t* diag = nullptr;
-    void *b = nullptr, *z = nullptr, *xin[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
-    double* b64 = nullptr;                     // FLIP_MIXED only
-    double* x64[2] = {nullptr, nullptr};       // FLIP_MIXED only
-    int xi = 0;                                // current solution buffer
-    int scur = 0;                              // current direction buffer
-    double* partials = nullptr;
-    PcgState* ps = nullptr;
-    void* staging = nullptr;
-    // host side
-    int cur = 0;
-    int n_active = 0;
-    int prev_iters = 0;
-    PcgState* h_ps = nullptr;
-    uint32_t* h_nactive = nullptr;
-    hipStream_t last_stream = nullptr;
-    flip_step_stats stats{};
-    // kernel timing
-    std::vector<hipEvent_t> ev;
-    std::vector<int> ev_kind;
-    std::vector<int> ev_iter;  // PCG iteration of a timed solver launch, -1 otherwise
-    int ev_used = 0;
-};
 
 namespace {
 
@@ -243,6 +197,9 @@ Sizes make_sizes(const flip_config* c, int64_t n)
     return s;
 }
 
+// Persistent workgroups of the solver kernels: one per tile up to the cap.
+int solver_groups(int64_t tiles) { return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, PCG_MAX_GROUPS)); }
+
 // One layout for both sizing and carving.
 void carve(flip_handle* h, Carver& cv)
 {
@@ -282,15 +239,11 @@ void carve(flip_handle* h, Carver& cv)
         h->x64[0] = cv.take<double>(s.cap * 8);
         h->x64[1] = cv.take<double>(s.cap * 8);
     }
-    h->partials = cv.take<double>(3 * sizeof(double) * s.T);
+    h->partials = cv.take<double>(3 * sizeof(double) * solver_groups(s.T));
     h->ps = cv.take<PcgState>(PCG_STATE_BYTES + SYNC_BYTES);
     h->staging = cv.take<void>(8 * s.C);
 }
 
-#define HIP_TRY(call)                              \
-    do {                                           \
-        if ((call) != hipSuccess) return FLIP_E_HIP; \
-    } while (0)
 
 // ---- kernel timing (FLIP_FLAG_KERNEL_TIMING) --------------------------------
 
@@ -331,7 +284,7 @@ flip_status timer_collect(flip_handle* h, hipStream_t st)
 // Launch PCG iterations in chunks until the device-side state says the current
 // (inner) solve is over; returns the state read at the end.
 template <typename V>
-flip_status pcg_loop(flip_handle* h, int na, V* x, int max_iters, hipStream_t st, PcgState* out)
+flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgState* out)
 {
     int chunk = h->prev_iters > 2 ? h->prev_iters - 2 : 16;
     int launched = 0;
@@ -341,12 +294,12 @@ flip_status pcg_loop(flip_handle* h, int na, V* x, int max_iters, hipStream_t st
             const int sc = h->scur;
             const bool timed = ((launched + it) % TIMED_PCG_EVERY) == 0;
             int q1 = timed ? timer_begin(h, FLIP_KERNEL_PCG_DIRECTION, st, launched + it) : -1;
-            launch_pcg_direction<V>(na, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
+            launch_pcg_direction<V>(h->groups, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
                                     (V*)h->s[sc ^ 1], h->partials, h->ps, st);
             timer_end(h, q1, st);
             int q2 = timed ? timer_begin(h, FLIP_KERNEL_PCG_UPDATE, st, launched + it) : -1;
-            launch_pcg_update<V>(na, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
-                                 h->partials, h->sz.T, h->ps, st);
+            launch_pcg_update<V>(h->groups, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
+                                 h->partials, h->groups, h->ps, st);
             timer_end(h, q2, st);
             h->scur = sc ^ 1;
         }
@@ -394,10 +347,6 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     launch_tiles(g, h->count, h->tile_flag, h->tile_excl, h->tile_slot, h->tile_list, h->tile_nbr,
                  h->d_nactive, h->scan_tmp, st);
     timer_end(h, tq, st);
-    HIP_TRY(hipMemcpyAsync(h->h_nactive, h->d_nactive, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const int na = (int)*h->h_nactive;
-    h->n_active = na;
 
     // 2. particle-to-grid, gravity, walls
     const T* pos = (const T*)h->pos[h->cur];
@@ -417,38 +366,39 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     PcgState ps_host{};
     flip_status ret = FLIP_OK;
     const bool project = !(c.flags & FLIP_FLAG_NO_PROJECTION);
-    const int max_iters = c.pcg_max_iters > 0 ? c.pcg_max_iters : 20 * std::max(c.nx, std::max(c.ny, c.nz));
+    const int max_iters = solve_iter_cap(c);
     const double scale_b = -c.density * c.dx / c.dt;
     h->scur = 0;
     h->xi = 0;
-    if (na > 0) {
-        tq = timer_begin(h, FLIP_KERNEL_RHS, st);
-        if (MIXED)
-            launch_rhs_mixed(g, na, h->tile_list, h->count, (const float*)h->f_star[0],
-                             (const float*)h->f_star[1], (const float*)h->f_star[2], scale_b, h->diag,
-                             h->b64, h->x64[0], (float*)h->z, (float*)h->xin[0], (float*)h->s[0],
-                             (float*)h->s[1], h->partials, s.T, h->ps, project ? c.pcg_tol : 0.0,
-                             project ? max_iters : 0, c.ir_tol, MAX_REFINEMENTS, st);
-        else
-            launch_rhs<T, T>(g, na, h->tile_list, h->count, (const T*)h->f_star[0], (const T*)h->f_star[1],
-                             (const T*)h->f_star[2], scale_b, h->diag, (T*)h->b, (T*)h->z, (T*)h->xin[0],
-                             (T*)h->s[0], (T*)h->s[1], h->partials, s.T, h->ps, project ? c.pcg_tol : 0.0,
-                             project ? max_iters : 0, st);
-        timer_end(h, tq, st);
-    }
+    // the solver kernels read the active-tile count from device memory: no
+    // host round trip between binning and the solve
+    const int G = h->groups;
+    tq = timer_begin(h, FLIP_KERNEL_RHS, st);
+    if (MIXED)
+        launch_rhs_mixed(g, G, h->tile_list, h->d_nactive, h->count, (const float*)h->f_star[0],
+                         (const float*)h->f_star[1], (const float*)h->f_star[2], scale_b, h->diag,
+                         h->b64, h->x64[0], (float*)h->z, (float*)h->xin[0], (float*)h->s[0],
+                         (float*)h->s[1], h->partials, G, h->ps, project ? c.pcg_tol : 0.0,
+                         project ? max_iters : 0, c.ir_tol, MAX_REFINEMENTS, st);
+    else
+        launch_rhs<T, T>(g, G, h->tile_list, h->d_nactive, h->count, (const T*)h->f_star[0],
+                         (const T*)h->f_star[1], (const T*)h->f_star[2], scale_b, h->diag, (T*)h->b,
+                         (T*)h->z, (T*)h->xin[0], (T*)h->s[0], (T*)h->s[1], h->partials, G, h->ps,
+                         project ? c.pcg_tol : 0.0, project ? max_iters : 0, st);
+    timer_end(h, tq, st);
 
     // 4. PCG (FP32 inner solves inside FP64 refinement when MIXED)
     int iters = 0, refinements = 0;
-    if (na > 0 && project) {
+    if (project) {
         for (;;) {
-            flip_status r = pcg_loop<T>(h, na, (T*)h->xin[h->xi], max_iters, st, &ps_host);
+            flip_status r = pcg_loop<T>(h, (T*)h->xin[h->xi], max_iters, st, &ps_host);
             if (r != FLIP_OK) return r;
             iters += ps_host.iter;
-            if (!MIXED || ps_host.done == PCG_BREAKDOWN) break;
+            if (!MIXED || ps_host.done == PCG_BREAKDOWN || ps_host.outer_done != 0) break;
             const int xi = h->xi;
-            launch_ir_update(na, h->tile_nbr, h->diag, h->b64, h->x64[xi], h->x64[xi ^ 1],
+            launch_ir_update(G, h->tile_nbr, h->diag, h->b64, h->x64[xi], h->x64[xi ^ 1],
                              (const float*)h->xin[xi], (float*)h->xin[xi ^ 1], (float*)h->z,
-                             (float*)h->s[0], (float*)h->s[1], h->partials, s.T, h->ps, st);
+                             (float*)h->s[0], (float*)h->s[1], h->partials, G, h->ps, st);
             h->xi = xi ^ 1;
             h->scur = 0;
             ++refinements;
@@ -479,11 +429,9 @@ flip_status run_step(flip_handle* h, hipStream_t st)
             timer_end(h, tq, st);
         }
     } else {
-        if (na > 0) {
-            HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            ps_host = *h->h_ps;
-        }
+        HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        ps_host = *h->h_ps;
         for (int a = 0; a < 3; ++a)
             HIP_TRY(hipMemcpyAsync(h->f_new[a], h->f_star[a], s.F[a] * sizeof(T),
                                    hipMemcpyDeviceToDevice, st));
@@ -498,29 +446,42 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     timer_end(h, tq, st);
     if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
 
-    flip_step_stats& S = h->stats;
-    const bool solved = na > 0 && project;
-    S.steps += 1;
-    S.n_fluid_cells = na > 0 ? ps_host.nfluid : 0;
-    S.n_active_tiles = na;
-    S.pcg_iterations = iters;
-    S.refinements = refinements;
-    if (!solved)
-        S.pcg_status = 0;
-    else if (MIXED)
-        S.pcg_status = ps_host.outer_done == 1 ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : 1);
-    else
-        S.pcg_status = ps_host.done == PCG_CONVERGED ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : 1);
-    S.max_b = MIXED ? ps_host.max_b0 : ps_host.max_b;
-    S.max_r = MIXED ? ps_host.max_r64 : ps_host.max_r;
-    S.pcg_iterations_total += iters;
-    S.pcg_cell_iterations_total += (int64_t)iters * (na > 0 ? ps_host.nfluid : 0);
-    if (ret != FLIP_OK && S.latched_status == 0) S.latched_status = ret;
+    const bool solved = ps_host.n_active > 0 && project;
+    const int status = MIXED ? (ps_host.outer_done == 1 ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : 1))
+                             : (ps_host.done == PCG_CONVERGED ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : 1));
+    record_step(h, solved, status, ps_host.n_active, ps_host.nfluid, MIXED ? ps_host.max_b0 : ps_host.max_b,
+                MIXED ? ps_host.max_r64 : ps_host.max_r, iters, refinements, ret);
     flip_status tr = timer_collect(h, st);
     return ret != FLIP_OK ? ret : tr;
 }
 
 }  // namespace
+
+namespace flipmi {
+
+int solve_iter_cap(const flip_config& c)
+{
+    return c.pcg_max_iters > 0 ? c.pcg_max_iters : 20 * std::max(c.nx, std::max(c.ny, c.nz));
+}
+
+void record_step(flip_handle* h, bool solved, int status, int n_active, int nfluid, double max_b,
+                 double max_r, int iters, int refinements, flip_status ret)
+{
+    flip_step_stats& S = h->stats;
+    S.steps += 1;
+    S.n_fluid_cells = nfluid;
+    S.n_active_tiles = n_active;
+    S.pcg_iterations = iters;
+    S.refinements = refinements;
+    S.pcg_status = solved ? status : 0;
+    S.max_b = max_b;
+    S.max_r = max_r;
+    S.pcg_iterations_total += iters;
+    S.pcg_cell_iterations_total += (int64_t)iters * nfluid;
+    if (ret != FLIP_OK && S.latched_status == 0) S.latched_status = ret;
+}
+
+}  // namespace flipmi
 
 extern "C" {
 
@@ -579,6 +540,7 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
     h->prec = cfg->precision;
     h->geo = make_geo(cfg);
     h->sz = make_sizes(cfg, n);
+    h->groups = solver_groups(h->sz.T);
     Carver dry(nullptr);
     carve(h, dry);
     if (!d_ws || ws_bytes < dry.off || ((uintptr_t)d_ws & (ALIGN - 1))) {
@@ -636,9 +598,8 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
     }
     launch_fill_bytes_zero(h->diag, s.cap, st);
     launch_fill_bytes_zero(h->ps, PCG_STATE_BYTES + SYNC_BYTES, st);
-    launch_fill_u64((uint64_t*)h->partials, 3 * s.T, SLOT_EMPTY_BITS, st);
-    if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&h->h_nactive, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    launch_fill_u64((uint64_t*)h->partials, 3 * h->groups, SLOT_EMPTY_BITS, st);
+    if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess) {
         flip_destroy(h);
         return FLIP_E_HIP;
     }
@@ -769,7 +730,6 @@ void flip_destroy(flip_handle* h)
     for (auto& e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_ps) (void)hipHostFree(h->h_ps);
-    if (h->h_nactive) (void)hipHostFree(h->h_nactive);
     delete h;
 }
 

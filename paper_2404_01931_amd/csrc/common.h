@@ -102,34 +102,36 @@ void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint3
                 const uint32_t* count, const T gdt[3], T* const old[3], T* const star[3],
                 hipStream_t st);
 
-// right-hand side, solver start, and the two kernels of one PCG iteration;
-// grid = one 512-thread workgroup per active tile. `partials` holds
-// 3 * pstride doubles, pstride >= n_active.
+// right-hand side, solver start, and the two kernels of one PCG iteration.
+// All run `groups` persistent workgroups that split the active tiles among
+// themselves; the active-tile count is read from device memory (d_nactive for
+// the start kernels, the solver state afterwards), so nothing depends on the
+// host knowing it. `partials` holds 3 * pstride doubles, pstride >= groups.
 template <typename T, typename V>
-void launch_rhs(const Geo& g, int n_active, const uint32_t* tile_list, const uint32_t* count,
-                const T* u, const T* v, const T* w, double scale, uint8_t* diag, V* b, V* z, V* x,
-                V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev, double tol,
-                int max_iters, hipStream_t st);
-// mixed precision: right-hand side in FP64 (b64), FP64 solution x64 = 0 and the
-// start of the first FP32 inner solve (z = b64 / n rounded, x = 0, s = 0)
-void launch_rhs_mixed(const Geo& g, int n_active, const uint32_t* tile_list, const uint32_t* count,
-                      const float* u, const float* v, const float* w, double scale, uint8_t* diag,
-                      double* b64, double* x64, float* z, float* x, float* s0, float* s1,
-                      double* partials, int64_t pstride, PcgState* st_dev, double tol, int max_iters,
-                      double ir_tol, int max_outer, hipStream_t st);
-// one refinement: x64_out = x64_in + x_in; r64 = b64 - A x64_out; restart the
-// inner solve on r64 (z = r64 / n rounded, x_out = 0, s = 0) unless converged
-void launch_ir_update(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const double* b64,
-                      const double* x64_in, double* x64_out, const float* x_in, float* x_out,
-                      float* z, float* s0, float* s1, double* partials, int64_t pstride,
-                      PcgState* st_dev, hipStream_t st);
+void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint32_t* d_nactive,
+                const uint32_t* count, const T* u, const T* v, const T* w, double scale, uint8_t* diag,
+                V* b, V* z, V* x, V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev,
+                double tol, int max_iters, hipStream_t st);
 template <typename V>
-void launch_pcg_direction(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
+void launch_pcg_direction(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
                           const V* s_old, V* s_new, double* partials, PcgState* st_dev,
                           hipStream_t st);
 template <typename V>
-void launch_pcg_update(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
+void launch_pcg_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
                        V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st);
+// mixed precision: right-hand side in FP64 (b64), FP64 solution x64 = 0 and the
+// start of the first FP32 inner solve (z = b64 / n rounded, x = 0, s = 0)
+void launch_rhs_mixed(const Geo& g, int groups, const uint32_t* tile_list, const uint32_t* d_nactive,
+                      const uint32_t* count, const float* u, const float* v, const float* w,
+                      double scale, uint8_t* diag, double* b64, double* x64, float* z, float* x,
+                      float* s0, float* s1, double* partials, int64_t pstride, PcgState* st_dev,
+                      double tol, int max_iters, double ir_tol, int max_outer, hipStream_t st);
+// one refinement: x64_out = x64_in + x_in; r64 = b64 - A x64_out; restart the
+// inner solve on r64 (z = r64 / n rounded, x_out = 0, s = 0) unless converged
+void launch_ir_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const double* b64,
+                      const double* x64_in, double* x64_out, const float* x_in, float* x_out,
+                      float* z, float* s0, float* s1, double* partials, int64_t pstride,
+                      PcgState* st_dev, hipStream_t st);
 
 template <typename T, typename V>
 void launch_project(const Geo& g, int axis, const uint32_t* count, const int32_t* tile_slot,

@@ -12,6 +12,45 @@ constexpr int WAVE = 64;
 
 __device__ inline int lane_id() { return threadIdx.x & (WAVE - 1); }
 
+// A workgroup's place in the grid of the scene it works on. A plain launch
+// covers one scene: id = blockIdx.x, n = gridDim.x. A batched launch
+// concatenates the grids of several scenes: scene s owns the workgroups
+// [first[s], first[s + 1]) of the launch.
+struct Blk {
+    int id;
+    int n;
+};
+
+__device__ inline Blk plain_blk() { return Blk{(int)blockIdx.x, (int)gridDim.x}; }
+
+// Scene of this workgroup in a batched launch of ns scenes (first[] is
+// non-decreasing, first[0] = 0; scenes with no workgroups are skipped). Each
+// wave counts, 64 entries at a time, the scenes that end at or before this
+// workgroup. The result is uniform across the workgroup.
+__device__ inline int batch_scene(const uint32_t* __restrict__ first, int ns, Blk& b)
+{
+    const uint32_t w = blockIdx.x;
+    int s = 0;
+    for (int base = 1; base <= ns; base += WAVE) {
+        const int i = base + lane_id();
+        const bool ended = i <= ns && first[i] <= w;
+        s += __popcll(__ballot(ended));
+    }
+    s = __builtin_amdgcn_readfirstlane(s);
+    const uint32_t f0 = first[s], f1 = first[s + 1];
+    b.id = (int)(w - f0);
+    b.n = (int)(f1 - f0);
+    return s;
+}
+
+// Arguments of this workgroup's scene in a batched launch (see batch.h).
+template <typename A>
+__device__ inline const A& batch_args(const A* __restrict__ tab, const uint32_t* __restrict__ first, int ns,
+                                      Blk& b)
+{
+    return tab[batch_scene(first, ns, b)];
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8). Remap block b to a work index so that each XCD receives one
 // contiguous range of the (spatially ordered) work list: neighbouring tiles
@@ -116,7 +155,7 @@ __device__ inline unsigned long long slot_load(const double* slot)
 }
 
 // Arrival counters: ctr[0] counts arriving sets, ctr[SYNC_STRIDE * (1 + x)]
-// counts the arriving workgroups of set x = blockIdx.x % 8. One counter per set
+// counts the arriving workgroups of set x = (workgroup index) % 8. One counter per set
 // (each on its own 128-byte line) keeps the relaxed atomic adds from queueing
 // on a single address: a single counter cost microseconds per thousand
 // workgroups.
@@ -124,15 +163,15 @@ constexpr int SYNC_SETS = 8;
 constexpr int SYNC_STRIDE = 32;
 static_assert(SYNC_STRIDE * (SYNC_SETS + 1) * 4 == SYNC_BYTES, "arrival counter layout");
 
-// Thread 0 publishes vals[0..nq) into slots[q * stride + blockIdx.x]; returns
-// (in every thread) whether this workgroup is the last of the grid to arrive.
-__device__ inline bool publish_partials(double* slots, int64_t stride, const double* vals, int nq,
+// Thread 0 publishes vals[0..nq) into slots[q * stride + b.id]; returns (in
+// every thread) whether this workgroup is the last of its scene's grid to arrive.
+__device__ inline bool publish_partials(Blk b, double* slots, int64_t stride, const double* vals, int nq,
                                         unsigned* ctr, bool* sh_last)
 {
     if (threadIdx.x == 0) {
-        for (int q = 0; q < nq; ++q) slot_store(slots + q * stride + blockIdx.x, vals[q]);
-        const unsigned nb = gridDim.x;
-        const unsigned set = blockIdx.x % SYNC_SETS;
+        for (int q = 0; q < nq; ++q) slot_store(slots + q * stride + b.id, vals[q]);
+        const unsigned nb = (unsigned)b.n;
+        const unsigned set = (unsigned)b.id % SYNC_SETS;
         const unsigned in_set = nb / SYNC_SETS + (set < nb % SYNC_SETS ? 1u : 0u);
         const unsigned sets = nb < SYNC_SETS ? nb : SYNC_SETS;
         bool last = false;

@@ -1,0 +1,78 @@
+// The library's handle and the pieces of the step shared by the plain and
+// the batched step (internal).
+#pragma once
+
+#include <vector>
+
+#include "../../include/flip.h"
+#include "common.h"
+
+namespace flipmi {
+
+struct Sizes {
+    int64_t n = 0, C = 0, T = 0, cap = 0, F[3] = {0, 0, 0};
+    size_t rb = 4;  // bytes of the real type
+};
+
+#define HIP_TRY(call)                              \
+    do {                                           \
+        if ((call) != hipSuccess) return FLIP_E_HIP; \
+    } while (0)
+
+}  // namespace flipmi
+
+struct flip_handle {
+    flip_config cfg;  // copy; region / array pointers cleared after init
+    int prec = FLIP_FP32;
+    flipmi::Geo geo{};
+    flipmi::Sizes sz;
+    // particles (double-buffered)
+    void* pos[2] = {nullptr, nullptr};
+    void* vel[2] = {nullptr, nullptr};
+    uint32_t* id[2] = {nullptr, nullptr};
+    uint32_t *key = nullptr, *rank = nullptr, *perm = nullptr;
+    // cells
+    uint32_t *count = nullptr, *start = nullptr, *scan_tmp = nullptr;
+    // tiles
+    uint32_t *tile_flag = nullptr, *tile_excl = nullptr, *tile_list = nullptr, *d_nactive = nullptr;
+    int32_t *tile_slot = nullptr, *tile_nbr = nullptr;
+    // faces
+    void* f_old[3] = {};
+    void* f_star[3] = {};
+    void* f_new[3] = {};
+    // solver (compact tile storage)
+    uint8_t* diag = nullptr;
+    void *b = nullptr, *z = nullptr, *xin[2] = {nullptr, nullptr}, *s[2] = {nullptr, nullptr};
+    double* b64 = nullptr;                     // FLIP_MIXED only
+    double* x64[2] = {nullptr, nullptr};       // FLIP_MIXED only
+    int xi = 0;                                // current solution buffer
+    int scur = 0;                              // current direction buffer
+    double* partials = nullptr;
+    flipmi::PcgState* ps = nullptr;
+    void* staging = nullptr;
+    // host side
+    int cur = 0;
+    int groups = 1;  // persistent workgroups of the solver kernels
+    int prev_iters = 0;
+    flipmi::PcgState* h_ps = nullptr;
+    hipStream_t last_stream = nullptr;
+    flip_step_stats stats{};
+    // kernel timing
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    std::vector<int> ev_iter;  // PCG iteration of a timed solver launch, -1 otherwise
+    int ev_used = 0;
+};
+
+namespace flipmi {
+
+// Per-step bookkeeping after the solve (stats, latched status), shared by the
+// plain and the batched step. `solved`: a projection ran; `status`: 0
+// converged, 1 not converged, 2 breakdown.
+void record_step(flip_handle* h, bool solved, int status, int n_active, int nfluid, double max_b,
+                 double max_r, int iters, int refinements, flip_status ret);
+
+// iteration cap of one solve
+int solve_iter_cap(const flip_config& c);
+
+}  // namespace flipmi

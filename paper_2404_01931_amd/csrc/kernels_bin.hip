@@ -8,6 +8,7 @@
 // arbitrary), then its final slot is its rank by original index among the
 // particles of the same cell. The result equals a stable sort by key and is
 // the same on every run.
+#include "batch.h"
 #include "common.h"
 #include "device_util.h"
 
@@ -17,10 +18,29 @@ namespace flipmi {
 // fills
 // ---------------------------------------------------------------------------
 
+__device__ __forceinline__ void fill_u32_body(Blk b, uint32_t* p, int64_t n, uint32_t v)
+{
+    int64_t i = (int64_t)b.id * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, int64_t n, uint32_t v)
 {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = v;
+    fill_u32_body(plain_blk(), p, n, v);
+}
+
+__global__ __launch_bounds__(256) void kb_fill_u32(const FillU32Args* __restrict__ tab,
+                                                   const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const FillU32Args& a = batch_args(tab, first, ns, b);
+    fill_u32_body(b, a.p, a.n, a.v);
+}
+
+void launch_b_fill_u32(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_fill_u32, dim3(L.blocks), dim3(256), 0, st, (const FillU32Args*)L.args, L.first, L.ns);
 }
 
 void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st)
@@ -63,13 +83,13 @@ void launch_fill_bytes_zero(void* p, int64_t bytes, hipStream_t st)
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_bin_keys(Geo g, const T* __restrict__ px,
-                                                  const T* __restrict__ py, const T* __restrict__ pz,
-                                                  int64_t n, uint32_t* __restrict__ key,
-                                                  uint32_t* __restrict__ rank,
-                                                  uint32_t* __restrict__ count)
+__device__ __forceinline__ void bin_keys_body(Blk b, Geo g, const T* __restrict__ px,
+                                              const T* __restrict__ py, const T* __restrict__ pz,
+                                              int64_t n, uint32_t* __restrict__ key,
+                                              uint32_t* __restrict__ rank,
+                                              uint32_t* __restrict__ count)
 {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = (int64_t)b.id * 256 + threadIdx.x;
     if (p >= n) return;
     const int i = exact_cell_floor((double)px[p], g.dx, g.inv_dx, g.nx);
     const int j = exact_cell_floor((double)py[p], g.dx, g.inv_dx, g.ny);
@@ -102,6 +122,35 @@ __global__ __launch_bounds__(256) void k_bin_keys(Geo g, const T* __restrict__ p
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_bin_keys(Geo g, const T* __restrict__ px,
+                                                  const T* __restrict__ py, const T* __restrict__ pz,
+                                                  int64_t n, uint32_t* __restrict__ key,
+                                                  uint32_t* __restrict__ rank,
+                                                  uint32_t* __restrict__ count)
+{
+    bin_keys_body<T>(plain_blk(), g, px, py, pz, n, key, rank, count);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_bin_keys(const BinKeysArgs<T>* __restrict__ tab,
+                                                   const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const BinKeysArgs<T>& a = batch_args(tab, first, ns, b);
+    bin_keys_body<T>(b, a.g, a.px, a.py, a.pz, a.n, a.key, a.rank, a.count);
+}
+
+template <typename T>
+void launch_b_bin_keys(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_bin_keys<T>, dim3(L.blocks), dim3(256), 0, st, (const BinKeysArgs<T>*)L.args,
+                       L.first, L.ns);
+}
+template void launch_b_bin_keys<float>(const BatchLaunch&, hipStream_t);
+template void launch_b_bin_keys<double>(const BatchLaunch&, hipStream_t);
+
+template <typename T>
 void launch_bin_keys(const Geo& g, const T* pos, int64_t n, uint32_t* key, uint32_t* rank,
                      uint32_t* count, hipStream_t st)
 {
@@ -120,10 +169,6 @@ template void launch_bin_keys<double>(const Geo&, const double*, int64_t, uint32
 // Three passes: per-block totals, a scan of the totals by one block, and a
 // rescan of each block with its offset. 256 threads x 16 items per block.
 // ---------------------------------------------------------------------------
-
-constexpr int SCAN_NT = 256;
-constexpr int SCAN_ITEMS = 16;
-constexpr int SCAN_TILE = SCAN_NT * SCAN_ITEMS;
 
 __device__ inline uint32_t wave_incl_scan_u32(uint32_t v)
 {
@@ -160,11 +205,11 @@ __device__ inline uint32_t block_excl_scan_u32(uint32_t v, uint32_t* sh, uint32_
     return incl - v + sh[w];
 }
 
-__global__ __launch_bounds__(SCAN_NT) void k_scan_totals(const uint32_t* __restrict__ in, int64_t n,
-                                                         uint32_t* __restrict__ totals)
+__device__ __forceinline__ void scan_totals_body(Blk b, const uint32_t* __restrict__ in, int64_t n,
+                                                 uint32_t* __restrict__ totals)
 {
     __shared__ uint32_t sh[SCAN_NT / WAVE + 1];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    const int64_t base = (int64_t)b.id * SCAN_TILE;
     uint32_t s = 0;
 #pragma unroll
     for (int it = 0; it < SCAN_ITEMS; ++it) {
@@ -173,11 +218,32 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_totals(const uint32_t* __restr
     }
     uint32_t total;
     block_excl_scan_u32<SCAN_NT>(s, sh, &total);
-    if (threadIdx.x == 0) totals[blockIdx.x] = total;
+    if (threadIdx.x == 0) totals[b.id] = total;
+}
+
+__global__ __launch_bounds__(SCAN_NT) void k_scan_totals(const uint32_t* __restrict__ in, int64_t n,
+                                                         uint32_t* __restrict__ totals)
+{
+    scan_totals_body(plain_blk(), in, n, totals);
+}
+
+__global__ __launch_bounds__(SCAN_NT) void kb_scan_totals(const ScanTotalsArgs* __restrict__ tab,
+                                                          const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const ScanTotalsArgs& a = batch_args(tab, first, ns, b);
+    scan_totals_body(b, a.in, a.n, a.totals);
+}
+
+void launch_b_scan_totals(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_scan_totals, dim3(L.blocks), dim3(SCAN_NT), 0, st, (const ScanTotalsArgs*)L.args,
+                       L.first, L.ns);
 }
 
 // single block: exclusive scan of nb totals in place, chunk by chunk
-__global__ __launch_bounds__(1024) void k_scan_totals_scan(uint32_t* __restrict__ totals, int64_t nb)
+__device__ __forceinline__ void scan_totals_scan_body(uint32_t* __restrict__ totals, int64_t nb)
 {
     __shared__ uint32_t sh[1024 / WAVE + 1];
     uint32_t carry = 0;
@@ -192,15 +258,35 @@ __global__ __launch_bounds__(1024) void k_scan_totals_scan(uint32_t* __restrict_
     }
 }
 
-__global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const uint32_t* __restrict__ in,
-                                                        uint32_t* __restrict__ out, int64_t n,
-                                                        const uint32_t* __restrict__ offsets)
+__global__ __launch_bounds__(1024) void k_scan_totals_scan(uint32_t* __restrict__ totals, int64_t nb)
+{
+    scan_totals_scan_body(totals, nb);
+}
+
+__global__ __launch_bounds__(1024) void kb_scan_totals_scan(const ScanTotalsScanArgs* __restrict__ tab,
+                                                            const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const ScanTotalsScanArgs& a = batch_args(tab, first, ns, b);
+    scan_totals_scan_body(a.totals, a.nb);
+}
+
+void launch_b_scan_totals_scan(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_scan_totals_scan, dim3(L.blocks), dim3(1024), 0, st,
+                       (const ScanTotalsScanArgs*)L.args, L.first, L.ns);
+}
+
+__device__ __forceinline__ void scan_apply_body(Blk b, const uint32_t* __restrict__ in,
+                                                uint32_t* __restrict__ out, int64_t n,
+                                                const uint32_t* __restrict__ offsets)
 {
     // items of the tile staged in LDS; thread t owns items [16 t, 16 t + 16),
     // padded by one word per 32 to spread LDS banks
     __shared__ uint32_t tile[SCAN_TILE + SCAN_TILE / 32];
     __shared__ uint32_t sh[SCAN_NT / WAVE + 1];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    const int64_t base = (int64_t)b.id * SCAN_TILE;
 #define PAD(i) ((i) + ((i) >> 5))
 #pragma unroll
     for (int it = 0; it < SCAN_ITEMS; ++it) {
@@ -217,7 +303,7 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const uint32_t* __restri
         s += vals[it];
     }
     uint32_t total;
-    uint32_t run = block_excl_scan_u32<SCAN_NT>(s, sh, &total) + offsets[blockIdx.x];
+    uint32_t run = block_excl_scan_u32<SCAN_NT>(s, sh, &total) + offsets[b.id];
 #pragma unroll
     for (int it = 0; it < SCAN_ITEMS; ++it) {
         tile[PAD(threadIdx.x * SCAN_ITEMS + it)] = run;
@@ -231,6 +317,28 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const uint32_t* __restri
         if (i < n) out[i] = tile[PAD(li)];
     }
 #undef PAD
+}
+
+__global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const uint32_t* __restrict__ in,
+                                                        uint32_t* __restrict__ out, int64_t n,
+                                                        const uint32_t* __restrict__ offsets)
+{
+    scan_apply_body(plain_blk(), in, out, n, offsets);
+}
+
+__global__ __launch_bounds__(SCAN_NT) void kb_scan_apply(const ScanApplyArgs* __restrict__ tab,
+                                                         const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const ScanApplyArgs& a = batch_args(tab, first, ns, b);
+    scan_apply_body(b, a.in, a.out, a.n, a.offsets);
+}
+
+void launch_b_scan_apply(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_scan_apply, dim3(L.blocks), dim3(SCAN_NT), 0, st, (const ScanApplyArgs*)L.args,
+                       L.first, L.ns);
 }
 
 int64_t scan_tmp_words(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
@@ -249,14 +357,37 @@ void launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uin
 // stable counting sort
 // ---------------------------------------------------------------------------
 
+__device__ __forceinline__ void bin_scatter_body(Blk b, const uint32_t* __restrict__ key,
+                                                 const uint32_t* __restrict__ rank,
+                                                 const uint32_t* __restrict__ start, int64_t n,
+                                                 uint32_t* __restrict__ perm)
+{
+    const int64_t p = (int64_t)b.id * 256 + threadIdx.x;
+    if (p >= n) return;
+    perm[start[key[p]] + rank[p]] = (uint32_t)p;
+}
+
 __global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t* __restrict__ key,
                                                      const uint32_t* __restrict__ rank,
                                                      const uint32_t* __restrict__ start, int64_t n,
                                                      uint32_t* __restrict__ perm)
 {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
-    perm[start[key[p]] + rank[p]] = (uint32_t)p;
+    bin_scatter_body(plain_blk(), key, rank, start, n, perm);
+}
+
+__global__ __launch_bounds__(256) void kb_bin_scatter(const ScatterArgs* __restrict__ tab,
+                                                      const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const ScatterArgs& a = batch_args(tab, first, ns, b);
+    bin_scatter_body(b, a.key, a.rank, a.start, a.n, a.perm);
+}
+
+void launch_b_bin_scatter(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_bin_scatter, dim3(L.blocks), dim3(256), 0, st, (const ScatterArgs*)L.args, L.first,
+                       L.ns);
 }
 
 void launch_bin_scatter(const uint32_t* key, const uint32_t* rank, const uint32_t* start,
@@ -271,13 +402,13 @@ void launch_bin_scatter(const uint32_t* key, const uint32_t* rank, const uint32_
 // start of its cell plus the number of particles of that cell with a smaller
 // original index. The particle's state moves there (double buffer, Sec. 3.2.2).
 template <typename T>
-__global__ __launch_bounds__(256) void k_bin_gather(
-    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ key,
+__device__ __forceinline__ void bin_gather_body(
+    Blk b, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ key,
     const uint32_t* __restrict__ start, const uint32_t* __restrict__ count, int64_t n,
     const T* __restrict__ pos_in, const T* __restrict__ vel_in, const uint32_t* __restrict__ id_in,
     T* __restrict__ pos_out, T* __restrict__ vel_out, uint32_t* __restrict__ id_out)
 {
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = (int64_t)b.id * 256 + threadIdx.x;
     if (s >= n) return;
     const uint32_t p = perm[s];
     const uint32_t c = key[p];
@@ -293,6 +424,37 @@ __global__ __launch_bounds__(256) void k_bin_gather(
     }
     id_out[d] = id_in[p];
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_gather(
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ count, int64_t n,
+    const T* __restrict__ pos_in, const T* __restrict__ vel_in, const uint32_t* __restrict__ id_in,
+    T* __restrict__ pos_out, T* __restrict__ vel_out, uint32_t* __restrict__ id_out)
+{
+    bin_gather_body<T>(plain_blk(), perm, key, start, count, n, pos_in, vel_in, id_in, pos_out, vel_out,
+                       id_out);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_bin_gather(const GatherArgs<T>* __restrict__ tab,
+                                                     const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const GatherArgs<T>& a = batch_args(tab, first, ns, b);
+    bin_gather_body<T>(b, a.perm, a.key, a.start, a.count, a.n, a.pos_in, a.vel_in, a.id_in, a.pos_out,
+                       a.vel_out, a.id_out);
+}
+
+template <typename T>
+void launch_b_bin_gather(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_bin_gather<T>, dim3(L.blocks), dim3(256), 0, st, (const GatherArgs<T>*)L.args,
+                       L.first, L.ns);
+}
+template void launch_b_bin_gather<float>(const BatchLaunch&, hipStream_t);
+template void launch_b_bin_gather<double>(const BatchLaunch&, hipStream_t);
 
 template <typename T>
 void launch_bin_gather(const uint32_t* perm, const uint32_t* key, const uint32_t* start,
@@ -316,10 +478,10 @@ template void launch_bin_gather<double>(const uint32_t*, const uint32_t*, const 
 // active tiles (the fluid-cells vector of Sec. 3.1.5, at tile granularity)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_tile_flags(Geo g, const uint32_t* __restrict__ count,
-                                                    uint32_t* __restrict__ tile_flag)
+__device__ __forceinline__ void tile_flags_body(Blk b, Geo g, const uint32_t* __restrict__ count,
+                                                uint32_t* __restrict__ tile_flag)
 {
-    const int t = blockIdx.x;
+    const int t = b.id;
     const int ti = t % g.tx, tj = (t / g.tx) % g.ty, tk = t / (g.tx * g.ty);
     int any = 0;
     for (int l = threadIdx.x; l < TILE_CELLS; l += 256) {
@@ -331,18 +493,39 @@ __global__ __launch_bounds__(256) void k_tile_flags(Geo g, const uint32_t* __res
     if (threadIdx.x == 0) tile_flag[t] = any ? 1u : 0u;
 }
 
+__global__ __launch_bounds__(256) void k_tile_flags(Geo g, const uint32_t* __restrict__ count,
+                                                    uint32_t* __restrict__ tile_flag)
+{
+    tile_flags_body(plain_blk(), g, count, tile_flag);
+}
+
+__global__ __launch_bounds__(256) void kb_tile_flags(const TileFlagsArgs* __restrict__ tab,
+                                                     const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const TileFlagsArgs& a = batch_args(tab, first, ns, b);
+    tile_flags_body(b, a.g, a.count, a.tile_flag);
+}
+
+void launch_b_tile_flags(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_tile_flags, dim3(L.blocks), dim3(256), 0, st, (const TileFlagsArgs*)L.args, L.first,
+                       L.ns);
+}
+
 // slot of each tile (-1 when inactive), the active list, and for every
 // active tile the slots of its six face neighbours (-x,+x,-y,+y,-z,+z; -1 when
 // outside the domain or inactive)
-__global__ __launch_bounds__(256) void k_tile_compact(Geo g, const uint32_t* __restrict__ flag,
-                                                      const uint32_t* __restrict__ excl,
-                                                      int32_t* __restrict__ tile_slot,
-                                                      uint32_t* __restrict__ tile_list,
-                                                      int32_t* __restrict__ tile_nbr,
-                                                      uint32_t* __restrict__ d_nactive)
+__device__ __forceinline__ void tile_compact_body(Blk b, Geo g, const uint32_t* __restrict__ flag,
+                                                  const uint32_t* __restrict__ excl,
+                                                  int32_t* __restrict__ tile_slot,
+                                                  uint32_t* __restrict__ tile_list,
+                                                  int32_t* __restrict__ tile_nbr,
+                                                  uint32_t* __restrict__ d_nactive)
 {
     const int64_t T = (int64_t)g.tx * g.ty * g.tz;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t t = (int64_t)b.id * 256 + threadIdx.x;
     if (t >= T) return;
     if (t == T - 1) *d_nactive = excl[t] + flag[t];
     if (!flag[t]) {
@@ -364,6 +547,31 @@ __global__ __launch_bounds__(256) void k_tile_compact(Geo g, const uint32_t* __r
         }
         tile_nbr[(int64_t)slot * 6 + d] = ns;
     }
+}
+
+__global__ __launch_bounds__(256) void k_tile_compact(Geo g, const uint32_t* __restrict__ flag,
+                                                      const uint32_t* __restrict__ excl,
+                                                      int32_t* __restrict__ tile_slot,
+                                                      uint32_t* __restrict__ tile_list,
+                                                      int32_t* __restrict__ tile_nbr,
+                                                      uint32_t* __restrict__ d_nactive)
+{
+    tile_compact_body(plain_blk(), g, flag, excl, tile_slot, tile_list, tile_nbr, d_nactive);
+}
+
+__global__ __launch_bounds__(256) void kb_tile_compact(const TileCompactArgs* __restrict__ tab,
+                                                       const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const TileCompactArgs& a = batch_args(tab, first, ns, b);
+    tile_compact_body(b, a.g, a.flag, a.excl, a.tile_slot, a.tile_list, a.tile_nbr, a.d_nactive);
+}
+
+void launch_b_tile_compact(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_tile_compact, dim3(L.blocks), dim3(256), 0, st, (const TileCompactArgs*)L.args,
+                       L.first, L.ns);
 }
 
 void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint32_t* tile_excl,

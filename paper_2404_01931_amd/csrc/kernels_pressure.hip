@@ -23,6 +23,7 @@
 // results are identical from run to run.
 #include <cfloat>
 
+#include "batch.h"
 #include "common.h"
 #include "device_util.h"
 
@@ -62,59 +63,72 @@ __device__ inline V neighbour_sum(const V* st, int l)
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
+// contiguous range [t0, t1) of the n_tiles active tiles for this workgroup; the
+// workgroups of one XCD get one contiguous chunk of the (spatially ordered) list
+__device__ inline void tile_range(Blk blk, int n_tiles, int& t0, int& t1)
+{
+    const int L = xcd_remap(blk.id, blk.n);
+    t0 = (int)((int64_t)n_tiles * L / blk.n);
+    t1 = (int)((int64_t)n_tiles * (L + 1) / blk.n);
+}
+
 // ---------------------------------------------------------------------------
 // right-hand side and solver start (x = 0, z = b / n, s = 0)
 // ---------------------------------------------------------------------------
 
 template <typename T, typename V>
-__global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__ tile_list,
-                                             const uint32_t* __restrict__ count,
-                                             const T* __restrict__ u, const T* __restrict__ v,
-                                             const T* __restrict__ w, T scale,
-                                             uint8_t* __restrict__ diag, V* __restrict__ b,
-                                             V* __restrict__ z, V* __restrict__ x,
-                                             V* __restrict__ s0, V* __restrict__ s1,
-                                             double* __restrict__ partials, int64_t pstride,
-                                             PcgState* __restrict__ ps, double tol, int max_iters)
+__device__ __forceinline__ void rhs_body(Blk blk, Geo g, const uint32_t* __restrict__ tile_list,
+                                         const uint32_t* __restrict__ d_nactive,
+                                         const uint32_t* __restrict__ count, const T* __restrict__ u,
+                                         const T* __restrict__ v, const T* __restrict__ w, T scale,
+                                         uint8_t* __restrict__ diag, V* __restrict__ b,
+                                         V* __restrict__ z, V* __restrict__ x, V* __restrict__ s0,
+                                         V* __restrict__ s1, double* __restrict__ partials,
+                                         int64_t pstride, PcgState* __restrict__ ps, double tol,
+                                         int max_iters)
 {
     __shared__ double red[PNT / WAVE];
     __shared__ bool last;
     unsigned* const sync = pcg_sync(ps);
-    const int slot = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t t = tile_list[slot];
-    const int ti = (int)(t % g.tx), tj = (int)((t / g.tx) % g.ty), tk = (int)(t / ((uint32_t)g.tx * g.ty));
+    const int na = (int)*d_nactive;
+    int t0, t1;
+    tile_range(blk, na, t0, t1);
     const int l = threadIdx.x;
-    const int i = ti * TILE + (l & 7), j = tj * TILE + ((l >> 3) & 7), k = tk * TILE + (l >> 6);
-    int d = 0;
-    T bv = T(0);
-    if (i < g.nx && j < g.ny && k < g.nz) {
-        const int64_t c = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-        if (count[c] > 0) {
-            d = (i > 0) + (i < g.nx - 1) + (j > 0) + (j < g.ny - 1) + (k > 0) + (k < g.nz - 1);
-            const int64_t uX = g.nx + 1, vY = g.ny + 1;
-            const int64_t fu = i + uX * (j + (int64_t)g.ny * k);
-            const int64_t fv = i + (int64_t)g.nx * (j + vY * k);
-            const int64_t fw = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-            const int64_t wZ = (int64_t)g.nx * g.ny;
-            const T div = (u[fu + 1] - u[fu]) + (v[fv + g.nx] - v[fv]) + (w[fw + wZ] - w[fw]);
-            bv = scale * div;
+    double rz = 0.0, mb = 0.0, nf = 0.0;
+    for (int slot = t0; slot < t1; ++slot) {
+        const uint32_t t = tile_list[slot];
+        const int ti = (int)(t % g.tx), tj = (int)((t / g.tx) % g.ty), tk = (int)(t / ((uint32_t)g.tx * g.ty));
+        const int i = ti * TILE + (l & 7), j = tj * TILE + ((l >> 3) & 7), k = tk * TILE + (l >> 6);
+        int d = 0;
+        T bv = T(0);
+        if (i < g.nx && j < g.ny && k < g.nz) {
+            const int64_t c = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+            if (count[c] > 0) {
+                d = (i > 0) + (i < g.nx - 1) + (j > 0) + (j < g.ny - 1) + (k > 0) + (k < g.nz - 1);
+                const int64_t fu = i + (int64_t)(g.nx + 1) * (j + (int64_t)g.ny * k);
+                const int64_t fv = i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k);
+                const int64_t fw = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+                const int64_t wZ = (int64_t)g.nx * g.ny;
+                const T div = (u[fu + 1] - u[fu]) + (v[fv + g.nx] - v[fv]) + (w[fw + wZ] - w[fw]);
+                bv = scale * div;
+            }
         }
+        const int64_t e = (int64_t)slot * TILE_CELLS + l;
+        const V bq = (V)bv;
+        const V zq = d ? bq / (V)d : V(0);
+        diag[e] = (uint8_t)d;
+        b[e] = bq;
+        z[e] = zq;
+        x[e] = V(0);
+        s0[e] = V(0);
+        s1[e] = V(0);
+        rz += (double)bq * (double)zq;
+        mb = fmax(mb, finite_or_inf(fabs((double)bq)));
+        nf += d ? 1.0 : 0.0;
     }
-    const int64_t e = (int64_t)slot * TILE_CELLS + l;
-    const V bq = (V)bv;
-    const V zq = d ? bq / (V)d : V(0);
-    diag[e] = (uint8_t)d;
-    b[e] = bq;
-    z[e] = zq;
-    x[e] = V(0);
-    s0[e] = V(0);
-    s1[e] = V(0);
-    const double rz = block_sum<PNT>((double)bq * (double)zq, red);
-    const double mb = block_max<PNT>(finite_or_inf(fabs((double)bq)), red);
-    const double nf = block_sum<PNT>(d ? 1.0 : 0.0, red);
-    const double vals[3] = {rz, mb, nf};
-    if (!publish_partials(partials, pstride, vals, 3, sync, &last)) return;
-    const int nb = gridDim.x;
+    const double vals[3] = {block_sum<PNT>(rz, red), block_max<PNT>(mb, red), block_sum<PNT>(nf, red)};
+    if (!publish_partials(blk, partials, pstride, vals, 3, sync, &last)) return;
+    const int nb = blk.n;
     int err = 0;
     const double rho = collect_slots<PNT, false>(partials, nb, red, &err);
     const double max_b = collect_slots<PNT, true>(partials + pstride, nb, red, &err);
@@ -130,7 +144,7 @@ __global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__
         ps->iter = 0;
         ps->max_iters = max_iters;
         ps->nfluid = (int)nfl;
-        ps->n_active = nb;
+        ps->n_active = na;
         ps->done = !(max_b <= DBL_MAX) ? PCG_BREAKDOWN
                    : (max_b == 0.0)    ? PCG_CONVERGED
                    : (max_iters <= 0)  ? PCG_MAX_ITERS
@@ -142,25 +156,61 @@ __global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__
 }
 
 template <typename T, typename V>
-void launch_rhs(const Geo& g, int n_active, const uint32_t* tile_list, const uint32_t* count,
-                const T* u, const T* v, const T* w, double scale, uint8_t* diag, V* b, V* z, V* x,
-                V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev, double tol,
-                int max_iters, hipStream_t st)
+__global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__ tile_list,
+                                             const uint32_t* __restrict__ d_nactive,
+                                             const uint32_t* __restrict__ count,
+                                             const T* __restrict__ u, const T* __restrict__ v,
+                                             const T* __restrict__ w, T scale,
+                                             uint8_t* __restrict__ diag, V* __restrict__ b,
+                                             V* __restrict__ z, V* __restrict__ x,
+                                             V* __restrict__ s0, V* __restrict__ s1,
+                                             double* __restrict__ partials, int64_t pstride,
+                                             PcgState* __restrict__ ps, double tol, int max_iters)
 {
-    if (n_active <= 0) return;
-    hipLaunchKernelGGL((k_rhs<T, V>), dim3((unsigned)n_active), dim3(PNT), 0, st, g, tile_list,
+    rhs_body<T, V>(plain_blk(), g, tile_list, d_nactive, count, u, v, w, scale, diag, b, z, x, s0, s1,
+                   partials, pstride, ps, tol, max_iters);
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(PNT) void kb_rhs(const RhsArgs<T, V>* __restrict__ tab,
+                                              const uint32_t* __restrict__ first, int ns)
+{
+    Blk blk;
+    const RhsArgs<T, V>& a = batch_args(tab, first, ns, blk);
+    rhs_body<T, V>(blk, a.g, a.tile_list, a.d_nactive, a.count, a.u, a.v, a.w, (T)a.scale, a.diag, a.b, a.z,
+                   a.x, a.s0, a.s1, a.partials, a.pstride, a.ps, a.tol, a.max_iters);
+}
+
+template <typename T, typename V>
+void launch_b_rhs(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL((kb_rhs<T, V>), dim3(L.blocks), dim3(PNT), 0, st, (const RhsArgs<T, V>*)L.args, L.first,
+                       L.ns);
+}
+template void launch_b_rhs<float, float>(const BatchLaunch&, hipStream_t);
+template void launch_b_rhs<double, double>(const BatchLaunch&, hipStream_t);
+
+template <typename T, typename V>
+void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint32_t* d_nactive,
+                const uint32_t* count, const T* u, const T* v, const T* w, double scale, uint8_t* diag,
+                V* b, V* z, V* x, V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev,
+                double tol, int max_iters, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rhs<T, V>), dim3((unsigned)groups), dim3(PNT), 0, st, g, tile_list, d_nactive,
                        count, u, v, w, (T)scale, diag, b, z, x, s0, s1, partials, pstride, st_dev,
                        tol, max_iters);
 }
 
 template void launch_rhs<float, float>(const Geo&, int, const uint32_t*, const uint32_t*,
-                                       const float*, const float*, const float*, double, uint8_t*,
-                                       float*, float*, float*, float*, float*, double*, int64_t,
-                                       PcgState*, double, int, hipStream_t);
+                                       const uint32_t*, const float*, const float*, const float*,
+                                       double, uint8_t*, float*, float*, float*, float*, float*,
+                                       double*, int64_t, PcgState*, double, int, hipStream_t);
 template void launch_rhs<double, double>(const Geo&, int, const uint32_t*, const uint32_t*,
-                                         const double*, const double*, const double*, double,
-                                         uint8_t*, double*, double*, double*, double*, double*,
-                                         double*, int64_t, PcgState*, double, int, hipStream_t);
+                                         const uint32_t*, const double*, const double*, const double*,
+                                         double, uint8_t*, double*, double*, double*, double*,
+                                         double*, double*, int64_t, PcgState*, double, int,
+                                         hipStream_t);
 
 // ---------------------------------------------------------------------------
 // The two iteration kernels run a bounded number of 256-thread workgroups
@@ -175,12 +225,6 @@ template void launch_rhs<double, double>(const Geo&, int, const uint32_t*, const
 
 constexpr int PCG_NT = 256;
 
-__device__ inline void tile_range(int n_tiles, int& t0, int& t1)
-{
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    t0 = (int)((int64_t)n_tiles * L / gridDim.x);
-    t1 = (int)((int64_t)n_tiles * (L + 1) / gridDim.x);
-}
 
 // Values of one tile that a thread stages: its two cells and up to two halo
 // cells, loaded into registers two tiles ahead of their use. Every load is
@@ -257,13 +301,11 @@ __device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tla
 
 // direction kernel: s = z + beta s_old, q = A s, sigma = s.q
 template <typename V>
-__global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restrict__ nbr,
-                                                          const uint8_t* __restrict__ diag,
-                                                          const V* __restrict__ z,
-                                                          const V* __restrict__ s_old,
-                                                          V* __restrict__ s_new,
-                                                          double* __restrict__ partials,
-                                                          PcgState* __restrict__ ps, int n_tiles)
+__device__ __forceinline__ void pcg_direction_body(Blk blk, const int32_t* __restrict__ nbr,
+                                                   const uint8_t* __restrict__ diag,
+                                                   const V* __restrict__ z, const V* __restrict__ s_old,
+                                                   V* __restrict__ s_new, double* __restrict__ partials,
+                                                   PcgState* __restrict__ ps)
 {
     __shared__ V stg[2][STAGE];
     __shared__ double red[PCG_NT / WAVE];
@@ -276,7 +318,7 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restr
     const int f0 = tid >> 6, f1 = (tid + PCG_NT) >> 6;
     const int hs0i = halo_source(f0, tid & 63), hs1i = halo_source(f1, tid & 63);
     int t0, t1;
-    tile_range(n_tiles, t0, t1);
+    tile_range(blk, ps->n_active, t0, t1);
     double acc = 0.0;
     if (t0 < t1) {
         const int tlast = t1 - 1;
@@ -296,9 +338,9 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restr
         }
     }
     const double part = block_sum<PCG_NT>(acc, red);
-    if (!publish_partials(partials, 0, &part, 1, sync, &last)) return;
+    if (!publish_partials(blk, partials, 0, &part, 1, sync, &last)) return;
     int err = 0;
-    const double sigma = collect_slots<PCG_NT, false>(partials, gridDim.x, red, &err);
+    const double sigma = collect_slots<PCG_NT, false>(partials, blk.n, red, &err);
     err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         if (!(sigma > 0.0) || !(sigma <= DBL_MAX) || err)
@@ -310,16 +352,44 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restr
     reset_arrivals(sync);
 }
 
-int pcg_groups(int n_active) { return n_active < PCG_MAX_GROUPS ? n_active : PCG_MAX_GROUPS; }
+template <typename V>
+__global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restrict__ nbr,
+                                                          const uint8_t* __restrict__ diag,
+                                                          const V* __restrict__ z,
+                                                          const V* __restrict__ s_old,
+                                                          V* __restrict__ s_new,
+                                                          double* __restrict__ partials,
+                                                          PcgState* __restrict__ ps)
+{
+    pcg_direction_body<V>(plain_blk(), nbr, diag, z, s_old, s_new, partials, ps);
+}
 
 template <typename V>
-void launch_pcg_direction(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
+__global__ __launch_bounds__(PCG_NT) void kb_pcg_direction(const DirArgs<V>* __restrict__ tab,
+                                                           const uint32_t* __restrict__ first, int ns)
+{
+    Blk blk;
+    const DirArgs<V>& a = batch_args(tab, first, ns, blk);
+    pcg_direction_body<V>(blk, a.nbr, a.diag, a.z, a.s_old, a.s_new, a.partials, a.ps);
+}
+
+template <typename V>
+void launch_b_pcg_direction(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_pcg_direction<V>, dim3(L.blocks), dim3(PCG_NT), 0, st, (const DirArgs<V>*)L.args,
+                       L.first, L.ns);
+}
+template void launch_b_pcg_direction<float>(const BatchLaunch&, hipStream_t);
+template void launch_b_pcg_direction<double>(const BatchLaunch&, hipStream_t);
+
+template <typename V>
+void launch_pcg_direction(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
                           const V* s_old, V* s_new, double* partials, PcgState* st_dev,
                           hipStream_t st)
 {
-    if (n_active <= 0) return;
-    hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)pcg_groups(n_active)), dim3(PCG_NT), 0, st,
-                       tile_nbr, diag, z, s_old, s_new, partials, st_dev, n_active);
+    hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, tile_nbr, diag, z,
+                       s_old, s_new, partials, st_dev);
 }
 
 template void launch_pcg_direction<float>(int, const int32_t*, const uint8_t*, const float*,
@@ -394,12 +464,11 @@ __device__ inline void upd_tile(V* st, UpdRegs<V>& cur, V alpha, int t, int tlas
 
 // update kernel: x += alpha s; r = n z - alpha A s; z = r / n; r.z; max|r|
 template <typename V>
-__global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict__ nbr,
-                                                       const uint8_t* __restrict__ diag,
-                                                       const V* __restrict__ s, V* __restrict__ x,
-                                                       V* __restrict__ z, double* __restrict__ partials,
-                                                       int64_t pstride, PcgState* __restrict__ ps,
-                                                       int n_tiles)
+__device__ __forceinline__ void pcg_update_body(Blk blk, const int32_t* __restrict__ nbr,
+                                                const uint8_t* __restrict__ diag, const V* __restrict__ s,
+                                                V* __restrict__ x, V* __restrict__ z,
+                                                double* __restrict__ partials, int64_t pstride,
+                                                PcgState* __restrict__ ps)
 {
     __shared__ V stg[2][STAGE];
     __shared__ double red[PCG_NT / WAVE];
@@ -412,7 +481,7 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict
     const int f0 = tid >> 6, f1 = (tid + PCG_NT) >> 6;
     const int hs0i = halo_source(f0, tid & 63), hs1i = halo_source(f1, tid & 63);
     int t0, t1;
-    tile_range(n_tiles, t0, t1);
+    tile_range(blk, ps->n_active, t0, t1);
     double rz = 0.0, rmax = 0.0;
     if (t0 < t1) {
         const int tlast = t1 - 1;
@@ -434,10 +503,10 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict
     const double prz = block_sum<PCG_NT>(rz, red);
     const double pmx = block_max<PCG_NT>(rmax, red);
     const double vals[2] = {prz, pmx};
-    if (!publish_partials(partials, pstride, vals, 2, sync, &last)) return;
+    if (!publish_partials(blk, partials, pstride, vals, 2, sync, &last)) return;
     int err = 0;
-    const double rho_new = collect_slots<PCG_NT, false>(partials, gridDim.x, red, &err);
-    const double max_r = collect_slots<PCG_NT, true>(partials + pstride, gridDim.x, red, &err);
+    const double rho_new = collect_slots<PCG_NT, false>(partials, blk.n, red, &err);
+    const double max_r = collect_slots<PCG_NT, true>(partials + pstride, blk.n, red, &err);
     err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         const int it = ps->iter + 1;
@@ -457,12 +526,40 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict
 }
 
 template <typename V>
-void launch_pcg_update(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
+__global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict__ nbr,
+                                                       const uint8_t* __restrict__ diag,
+                                                       const V* __restrict__ s, V* __restrict__ x,
+                                                       V* __restrict__ z, double* __restrict__ partials,
+                                                       int64_t pstride, PcgState* __restrict__ ps)
+{
+    pcg_update_body<V>(plain_blk(), nbr, diag, s, x, z, partials, pstride, ps);
+}
+
+template <typename V>
+__global__ __launch_bounds__(PCG_NT) void kb_pcg_update(const UpdArgs<V>* __restrict__ tab,
+                                                        const uint32_t* __restrict__ first, int ns)
+{
+    Blk blk;
+    const UpdArgs<V>& a = batch_args(tab, first, ns, blk);
+    pcg_update_body<V>(blk, a.nbr, a.diag, a.s, a.x, a.z, a.partials, a.pstride, a.ps);
+}
+
+template <typename V>
+void launch_b_pcg_update(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_pcg_update<V>, dim3(L.blocks), dim3(PCG_NT), 0, st, (const UpdArgs<V>*)L.args,
+                       L.first, L.ns);
+}
+template void launch_b_pcg_update<float>(const BatchLaunch&, hipStream_t);
+template void launch_b_pcg_update<double>(const BatchLaunch&, hipStream_t);
+
+template <typename V>
+void launch_pcg_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
                        V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st)
 {
-    if (n_active <= 0) return;
-    hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)pcg_groups(n_active)), dim3(PCG_NT), 0, st,
-                       tile_nbr, diag, s, x, z, partials, pstride, st_dev, n_active);
+    hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, tile_nbr, diag, s,
+                       x, z, partials, pstride, st_dev);
 }
 
 template void launch_pcg_update<float>(int, const int32_t*, const uint8_t*, const float*, float*,
@@ -477,6 +574,7 @@ template void launch_pcg_update<double>(int, const int32_t*, const uint8_t*, con
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __restrict__ tile_list,
+                                                   const uint32_t* __restrict__ d_nactive,
                                                    const uint32_t* __restrict__ count,
                                                    const float* __restrict__ u,
                                                    const float* __restrict__ v,
@@ -493,41 +591,47 @@ __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __rest
     __shared__ double red[PNT / WAVE];
     __shared__ bool last;
     unsigned* const sync = pcg_sync(ps);
-    const int slot = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t t = tile_list[slot];
-    const int ti = (int)(t % g.tx), tj = (int)((t / g.tx) % g.ty), tk = (int)(t / ((uint32_t)g.tx * g.ty));
+    const Blk blk = plain_blk();
+    const int na = (int)*d_nactive;
+    int t0, t1;
+    tile_range(blk, na, t0, t1);
     const int l = threadIdx.x;
-    const int i = ti * TILE + (l & 7), j = tj * TILE + ((l >> 3) & 7), k = tk * TILE + (l >> 6);
-    int d = 0;
-    double bd = 0.0;
-    if (i < g.nx && j < g.ny && k < g.nz) {
-        const int64_t c = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-        if (count[c] > 0) {
-            d = (i > 0) + (i < g.nx - 1) + (j > 0) + (j < g.ny - 1) + (k > 0) + (k < g.nz - 1);
-            const int64_t fu = i + (int64_t)(g.nx + 1) * (j + (int64_t)g.ny * k);
-            const int64_t fv = i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k);
-            const int64_t fw = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-            // face differences of float samples are exact in double
-            const double div = ((double)u[fu + 1] - (double)u[fu]) + ((double)v[fv + g.nx] - (double)v[fv]) +
-                               ((double)w[fw + (int64_t)g.nx * g.ny] - (double)w[fw]);
-            bd = scale * div;
+    double rz = 0.0, mb = 0.0, nf = 0.0;
+    for (int slot = t0; slot < t1; ++slot) {
+        const uint32_t t = tile_list[slot];
+        const int ti = (int)(t % g.tx), tj = (int)((t / g.tx) % g.ty), tk = (int)(t / ((uint32_t)g.tx * g.ty));
+        const int i = ti * TILE + (l & 7), j = tj * TILE + ((l >> 3) & 7), k = tk * TILE + (l >> 6);
+        int d = 0;
+        double bd = 0.0;
+        if (i < g.nx && j < g.ny && k < g.nz) {
+            const int64_t c = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+            if (count[c] > 0) {
+                d = (i > 0) + (i < g.nx - 1) + (j > 0) + (j < g.ny - 1) + (k > 0) + (k < g.nz - 1);
+                const int64_t fu = i + (int64_t)(g.nx + 1) * (j + (int64_t)g.ny * k);
+                const int64_t fv = i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k);
+                const int64_t fw = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+                // face differences of float samples are exact in double
+                const double div = ((double)u[fu + 1] - (double)u[fu]) + ((double)v[fv + g.nx] - (double)v[fv]) +
+                                   ((double)w[fw + (int64_t)g.nx * g.ny] - (double)w[fw]);
+                bd = scale * div;
+            }
         }
+        const int64_t e = (int64_t)slot * TILE_CELLS + l;
+        const float zq = d ? (float)(bd / d) : 0.0f;
+        diag[e] = (uint8_t)d;
+        b64[e] = bd;
+        x64[e] = 0.0;
+        z[e] = zq;
+        x[e] = 0.0f;
+        s0[e] = 0.0f;
+        s1[e] = 0.0f;
+        rz += (double)d * (double)zq * (double)zq;
+        mb = fmax(mb, finite_or_inf(fabs(bd)));
+        nf += d ? 1.0 : 0.0;
     }
-    const int64_t e = (int64_t)slot * TILE_CELLS + l;
-    const float zq = d ? (float)(bd / d) : 0.0f;
-    diag[e] = (uint8_t)d;
-    b64[e] = bd;
-    x64[e] = 0.0;
-    z[e] = zq;
-    x[e] = 0.0f;
-    s0[e] = 0.0f;
-    s1[e] = 0.0f;
-    const double rz = block_sum<PNT>((double)d * (double)zq * (double)zq, red);
-    const double mb = block_max<PNT>(finite_or_inf(fabs(bd)), red);
-    const double nf = block_sum<PNT>(d ? 1.0 : 0.0, red);
-    const double vals[3] = {rz, mb, nf};
-    if (!publish_partials(partials, pstride, vals, 3, sync, &last)) return;
-    const int nb = gridDim.x;
+    const double vals[3] = {block_sum<PNT>(rz, red), block_max<PNT>(mb, red), block_sum<PNT>(nf, red)};
+    if (!publish_partials(blk, partials, pstride, vals, 3, sync, &last)) return;
+    const int nb = blk.n;
     int err = 0;
     const double rho = collect_slots<PNT, false>(partials, nb, red, &err);
     const double max_b = collect_slots<PNT, true>(partials + pstride, nb, red, &err);
@@ -543,7 +647,7 @@ __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __rest
         ps->iter = 0;
         ps->max_iters = max_iters;
         ps->nfluid = (int)nfl;
-        ps->n_active = nb;
+        ps->n_active = na;
         ps->max_b0 = max_b;
         ps->ir_tol = ir_tol;
         ps->max_r64 = max_b;
@@ -560,22 +664,21 @@ __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __rest
     reset_arrivals(sync);
 }
 
-void launch_rhs_mixed(const Geo& g, int n_active, const uint32_t* tile_list, const uint32_t* count,
-                      const float* u, const float* v, const float* w, double scale, uint8_t* diag,
-                      double* b64, double* x64, float* z, float* x, float* s0, float* s1,
-                      double* partials, int64_t pstride, PcgState* st_dev, double tol, int max_iters,
-                      double ir_tol, int max_outer, hipStream_t st)
+void launch_rhs_mixed(const Geo& g, int groups, const uint32_t* tile_list, const uint32_t* d_nactive,
+                      const uint32_t* count, const float* u, const float* v, const float* w,
+                      double scale, uint8_t* diag, double* b64, double* x64, float* z, float* x,
+                      float* s0, float* s1, double* partials, int64_t pstride, PcgState* st_dev,
+                      double tol, int max_iters, double ir_tol, int max_outer, hipStream_t st)
 {
-    if (n_active <= 0) return;
-    hipLaunchKernelGGL(k_rhs_mixed, dim3((unsigned)n_active), dim3(PNT), 0, st, g, tile_list, count, u,
-                       v, w, scale, diag, b64, x64, z, x, s0, s1, partials, pstride, st_dev, tol,
-                       max_iters, ir_tol, max_outer);
+    hipLaunchKernelGGL(k_rhs_mixed, dim3((unsigned)groups), dim3(PNT), 0, st, g, tile_list, d_nactive,
+                       count, u, v, w, scale, diag, b64, x64, z, x, s0, s1, partials, pstride, st_dev,
+                       tol, max_iters, ir_tol, max_outer);
 }
 
-// One workgroup of 512 threads per active tile. The updated FP64 solution of
-// the tile and its face halos is staged in LDS; the solution is double-buffered
-// (x64_in -> x64_out, x_in -> x_out) because other workgroups read this tile's
-// values as their halo.
+// One refinement, 512 threads per workgroup, one tile at a time. The updated
+// FP64 solution of the tile and its face halos is staged in LDS; the solution
+// is double-buffered (x64_in -> x64_out, x_in -> x_out) because other
+// workgroups read this tile's values as their halo.
 __global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ nbr,
                                                    const uint8_t* __restrict__ diag,
                                                    const double* __restrict__ b64,
@@ -591,41 +694,47 @@ __global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ n
     __shared__ double red[PNT / WAVE];
     __shared__ bool last;
     unsigned* const sync = pcg_sync(ps);
-    const int slot = xcd_remap(blockIdx.x, gridDim.x);
+    const Blk blk = plain_blk();
+    int t0, t1;
+    tile_range(blk, ps->n_active, t0, t1);
     const int l = threadIdx.x;
-    const int64_t e = (int64_t)slot * TILE_CELLS + l;
-    const double xn = x64_in[e] + (double)x_in[e];
-    stg[l] = xn;
-    if (l < HALO) {
-        const int f = l >> 6;
-        const int32_t ns = nbr[(int64_t)slot * 6 + f];
-        double hv = 0.0;
-        if (ns >= 0) {
-            const int64_t en = (int64_t)ns * TILE_CELLS + halo_source(f, l & 63);
-            hv = x64_in[en] + (double)x_in[en];
+    double rz = 0.0, mr = 0.0;
+    for (int slot = t0; slot < t1; ++slot) {
+        const int64_t e = (int64_t)slot * TILE_CELLS + l;
+        const double xn = x64_in[e] + (double)x_in[e];
+        stg[l] = xn;
+        if (l < HALO) {
+            const int f = l >> 6;
+            const int32_t ns = nbr[(int64_t)slot * 6 + f];
+            double hv = 0.0;
+            if (ns >= 0) {
+                const int64_t en = (int64_t)ns * TILE_CELLS + halo_source(f, l & 63);
+                hv = x64_in[en] + (double)x_in[en];
+            }
+            stg[TILE_CELLS + l] = hv;
         }
-        stg[TILE_CELLS + l] = hv;
+        __syncthreads();
+        const int d = diag[e];
+        double r = 0.0;
+        float zq = 0.0f;
+        if (d) {
+            r = b64[e] - fma((double)d, xn, -neighbour_sum(stg, l));
+            zq = (float)(r / d);
+        }
+        x64_out[e] = xn;
+        x_out[e] = 0.0f;
+        z[e] = zq;
+        s0[e] = 0.0f;
+        s1[e] = 0.0f;
+        mr = fmax(mr, finite_or_inf(fabs(r)));
+        rz += (double)d * (double)zq * (double)zq;
+        __syncthreads();
     }
-    __syncthreads();
-    const int d = diag[e];
-    double r = 0.0;
-    float zq = 0.0f;
-    if (d) {
-        r = b64[e] - fma((double)d, xn, -neighbour_sum(stg, l));
-        zq = (float)(r / d);
-    }
-    x64_out[e] = xn;
-    x_out[e] = 0.0f;
-    z[e] = zq;
-    s0[e] = 0.0f;
-    s1[e] = 0.0f;
-    const double mr = block_max<PNT>(finite_or_inf(fabs(r)), red);
-    const double rz = block_sum<PNT>((double)d * (double)zq * (double)zq, red);
-    const double vals[2] = {rz, mr};
-    if (!publish_partials(partials, pstride, vals, 2, sync, &last)) return;
+    const double vals[2] = {block_sum<PNT>(rz, red), block_max<PNT>(mr, red)};
+    if (!publish_partials(blk, partials, pstride, vals, 2, sync, &last)) return;
     int err = 0;
-    const double rho = collect_slots<PNT, false>(partials, gridDim.x, red, &err);
-    const double max_r = collect_slots<PNT, true>(partials + pstride, gridDim.x, red, &err);
+    const double rho = collect_slots<PNT, false>(partials, blk.n, red, &err);
+    const double max_r = collect_slots<PNT, true>(partials + pstride, blk.n, red, &err);
     err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         const int outer = ps->outer + 1;
@@ -655,13 +764,12 @@ __global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ n
     reset_arrivals(sync);
 }
 
-void launch_ir_update(int n_active, const int32_t* tile_nbr, const uint8_t* diag, const double* b64,
+void launch_ir_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const double* b64,
                       const double* x64_in, double* x64_out, const float* x_in, float* x_out,
                       float* z, float* s0, float* s1, double* partials, int64_t pstride,
                       PcgState* st_dev, hipStream_t st)
 {
-    if (n_active <= 0) return;
-    hipLaunchKernelGGL(k_ir_update, dim3((unsigned)n_active), dim3(PNT), 0, st, tile_nbr, diag, b64,
+    hipLaunchKernelGGL(k_ir_update, dim3((unsigned)groups), dim3(PNT), 0, st, tile_nbr, diag, b64,
                        x64_in, x64_out, x_in, x_out, z, s0, s1, partials, pstride, st_dev);
 }
 
@@ -680,14 +788,14 @@ __device__ inline V tile_value(const Geo& g, const int32_t* __restrict__ tile_sl
 }
 
 template <typename T, typename V, int A>
-__global__ __launch_bounds__(256) void k_project(Geo g, const uint32_t* __restrict__ count,
-                                                 const int32_t* __restrict__ tile_slot,
-                                                 const V* __restrict__ p, const T* __restrict__ star,
-                                                 T* __restrict__ out, T scale)
+__device__ __forceinline__ void project_body(Blk blk, Geo g, const uint32_t* __restrict__ count,
+                                             const int32_t* __restrict__ tile_slot,
+                                             const V* __restrict__ p, const T* __restrict__ star,
+                                             T* __restrict__ out, T scale)
 {
     const int dX = g.nx + (A == 0), dY = g.ny + (A == 1), dZ = g.nz + (A == 2);
     const int64_t F = (int64_t)dX * dY * dZ;
-    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t f = (int64_t)blk.id * 256 + threadIdx.x;
     if (f >= F) return;
     const int i = (int)(f % dX), j = (int)((f / dX) % dY), k = (int)(f / ((int64_t)dX * dY));
     const int idx = A == 0 ? i : (A == 1 ? j : k);
@@ -704,6 +812,65 @@ __global__ __launch_bounds__(256) void k_project(Geo g, const uint32_t* __restri
         }
     }
     out[f] = o;
+}
+
+template <typename T, typename V, int A>
+__global__ __launch_bounds__(256) void k_project(Geo g, const uint32_t* __restrict__ count,
+                                                 const int32_t* __restrict__ tile_slot,
+                                                 const V* __restrict__ p, const T* __restrict__ star,
+                                                 T* __restrict__ out, T scale)
+{
+    project_body<T, V, A>(plain_blk(), g, count, tile_slot, p, star, out, scale);
+}
+
+template <typename T, typename V, int A>
+__global__ __launch_bounds__(256) void kb_project(const ProjectArgs<T, V>* __restrict__ tab,
+                                                  const uint32_t* __restrict__ first, int ns)
+{
+    Blk blk;
+    const ProjectArgs<T, V>& a = batch_args(tab, first, ns, blk);
+    project_body<T, V, A>(blk, a.g, a.count, a.tile_slot, a.p, a.star, a.out, a.scale);
+}
+
+template <typename T, typename V>
+void launch_b_project(int axis, const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    const ProjectArgs<T, V>* tab = (const ProjectArgs<T, V>*)L.args;
+    if (axis == 0)
+        hipLaunchKernelGGL((kb_project<T, V, 0>), dim3(L.blocks), dim3(256), 0, st, tab, L.first, L.ns);
+    else if (axis == 1)
+        hipLaunchKernelGGL((kb_project<T, V, 1>), dim3(L.blocks), dim3(256), 0, st, tab, L.first, L.ns);
+    else
+        hipLaunchKernelGGL((kb_project<T, V, 2>), dim3(L.blocks), dim3(256), 0, st, tab, L.first, L.ns);
+}
+template void launch_b_project<float, float>(int, const BatchLaunch&, hipStream_t);
+template void launch_b_project<double, double>(int, const BatchLaunch&, hipStream_t);
+
+// one thread per scene: copy the solver state a host poll needs
+__global__ __launch_bounds__(64) void kb_summary(const SummaryArgs* __restrict__ tab,
+                                                 const uint32_t* __restrict__ first, int ns)
+{
+    Blk blk;
+    const SummaryArgs& a = batch_args(tab, first, ns, blk);
+    if (threadIdx.x != 0) return;
+    const PcgState* ps = a.ps;
+    SolveSummary o;
+    o.max_b = ps->max_b;
+    o.max_r = ps->max_r;
+    o.iter = ps->iter;
+    o.done = ps->done;
+    o.nfluid = ps->nfluid;
+    o.n_active = ps->n_active;
+    o.sync_error = ps->sync_error;
+    o.pad_ = 0;
+    *a.out = o;
+}
+
+void launch_b_summary(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_summary, dim3(L.blocks), dim3(64), 0, st, (const SummaryArgs*)L.args, L.first, L.ns);
 }
 
 template <typename T, typename V>

@@ -9,6 +9,7 @@
 //
 // Grid-to-particle (Sec. 3.1.8) with forward-Euler advection and the skin-width
 // clamp (Sec. 3.1.3): one thread per particle in binned order.
+#include "batch.h"
 #include "common.h"
 #include "device_util.h"
 
@@ -68,22 +69,22 @@ __device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, dou
             }
 }
 
+// workgroup b.id handles tile (b.id % tx, (b.id / tx) % ty, b.id / (tx ty))
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, const T* __restrict__ px,
-                                                  const T* __restrict__ py, const T* __restrict__ pz,
-                                                  const T* __restrict__ vx, const T* __restrict__ vy,
-                                                  const T* __restrict__ vz,
-                                                  const uint32_t* __restrict__ start,
-                                                  const uint32_t* __restrict__ count, T gdt_x,
-                                                  T gdt_y, T gdt_z, T* __restrict__ u_old,
-                                                  T* __restrict__ v_old, T* __restrict__ w_old,
-                                                  T* __restrict__ u_star, T* __restrict__ v_star,
-                                                  T* __restrict__ w_star)
+__device__ __forceinline__ void p2g_body(Blk b, Geo g, const T* __restrict__ px, const T* __restrict__ py,
+                                         const T* __restrict__ pz, const T* __restrict__ vx,
+                                         const T* __restrict__ vy, const T* __restrict__ vz,
+                                         const uint32_t* __restrict__ start,
+                                         const uint32_t* __restrict__ count, T gdt_x, T gdt_y, T gdt_z,
+                                         T* __restrict__ u_old, T* __restrict__ v_old,
+                                         T* __restrict__ w_old, T* __restrict__ u_star,
+                                         T* __restrict__ v_star, T* __restrict__ w_star)
 {
 #pragma clang fp contract(off)
     __shared__ T acc[3][P2G_BOX][2];
     const int lane = threadIdx.x;
-    const int x0 = blockIdx.x * P2G_T, y0 = blockIdx.y * P2G_T, z0 = blockIdx.z * P2G_T;
+    const int bx = b.id % g.tx, by = (b.id / g.tx) % g.ty, bz = b.id / (g.tx * g.ty);
+    const int x0 = bx * P2G_T, y0 = by * P2G_T, z0 = bz * P2G_T;
     for (int q = lane; q < 3 * P2G_BOX * 2; q += 64) (&acc[0][0][0])[q] = T(0);
     __syncthreads();
     // ring box of cells, clipped to the domain (inclusive bounds)
@@ -137,15 +138,51 @@ __global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, const T* __restrict__ p
 }
 
 template <typename T>
+__global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, const T* __restrict__ px,
+                                                  const T* __restrict__ py, const T* __restrict__ pz,
+                                                  const T* __restrict__ vx, const T* __restrict__ vy,
+                                                  const T* __restrict__ vz,
+                                                  const uint32_t* __restrict__ start,
+                                                  const uint32_t* __restrict__ count, T gdt_x,
+                                                  T gdt_y, T gdt_z, T* __restrict__ u_old,
+                                                  T* __restrict__ v_old, T* __restrict__ w_old,
+                                                  T* __restrict__ u_star, T* __restrict__ v_star,
+                                                  T* __restrict__ w_star)
+{
+    p2g_body<T>(plain_blk(), g, px, py, pz, vx, vy, vz, start, count, gdt_x, gdt_y, gdt_z, u_old, v_old,
+                w_old, u_star, v_star, w_star);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void kb_p2g_tiles(const P2GArgs<T>* __restrict__ tab,
+                                                   const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const P2GArgs<T>& a = batch_args(tab, first, ns, b);
+    p2g_body<T>(b, a.g, a.px, a.py, a.pz, a.vx, a.vy, a.vz, a.start, a.count, a.gdt[0], a.gdt[1], a.gdt[2],
+                a.old[0], a.old[1], a.old[2], a.star[0], a.star[1], a.star[2]);
+}
+
+template <typename T>
 void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint32_t* start,
                 const uint32_t* count, const T gdt[3], T* const old[3], T* const star[3],
                 hipStream_t st)
 {
-    const dim3 grid((unsigned)g.tx, (unsigned)g.ty, (unsigned)g.tz);
-    hipLaunchKernelGGL(k_p2g_tiles<T>, grid, dim3(64), 0, st, g, pos, pos + n, pos + 2 * n, vel,
+    const unsigned tiles = (unsigned)tiles_of(g);
+    hipLaunchKernelGGL(k_p2g_tiles<T>, dim3(tiles), dim3(64), 0, st, g, pos, pos + n, pos + 2 * n, vel,
                        vel + n, vel + 2 * n, start, count, gdt[0], gdt[1], gdt[2], old[0], old[1],
                        old[2], star[0], star[1], star[2]);
 }
+
+template <typename T>
+void launch_b_p2g(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_p2g_tiles<T>, dim3(L.blocks), dim3(64), 0, st, (const P2GArgs<T>*)L.args, L.first,
+                       L.ns);
+}
+template void launch_b_p2g<float>(const BatchLaunch&, hipStream_t);
+template void launch_b_p2g<double>(const BatchLaunch&, hipStream_t);
 
 template void launch_p2g<float>(const Geo&, const float*, const float*, int64_t, const uint32_t*,
                                 const uint32_t*, const float[3], float* const[3], float* const[3],
@@ -223,16 +260,15 @@ __device__ inline void sample(const Geo& g, const T* __restrict__ fnew, const T*
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_g2p(Geo g, int64_t n, T* __restrict__ px,
-                                             T* __restrict__ py, T* __restrict__ pz,
-                                             T* __restrict__ vx, T* __restrict__ vy,
-                                             T* __restrict__ vz, const T* __restrict__ un,
-                                             const T* __restrict__ vn, const T* __restrict__ wn,
-                                             const T* __restrict__ uo, const T* __restrict__ vo,
-                                             const T* __restrict__ wo, T alpha, T dt, T skin,
-                                             T Lx, T Ly, T Lz, int advect_particle_vel)
+__device__ __forceinline__ void g2p_body(Blk b, Geo g, int64_t n, T* __restrict__ px, T* __restrict__ py,
+                                         T* __restrict__ pz, T* __restrict__ vx, T* __restrict__ vy,
+                                         T* __restrict__ vz, const T* __restrict__ un,
+                                         const T* __restrict__ vn, const T* __restrict__ wn,
+                                         const T* __restrict__ uo, const T* __restrict__ vo,
+                                         const T* __restrict__ wo, T alpha, T dt, T skin, T Lx, T Ly,
+                                         T Lz, int advect_particle_vel)
 {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = (int64_t)b.id * 256 + threadIdx.x;
     if (p >= n) return;
     const T x = px[p], y = py[p], z = pz[p];
     T pic[3], ch[3];
@@ -264,6 +300,39 @@ __global__ __launch_bounds__(256) void k_g2p(Geo g, int64_t n, T* __restrict__ p
     vy[p] = vnew[1];
     vz[p] = vnew[2];
 }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_g2p(Geo g, int64_t n, T* __restrict__ px,
+                                             T* __restrict__ py, T* __restrict__ pz,
+                                             T* __restrict__ vx, T* __restrict__ vy,
+                                             T* __restrict__ vz, const T* __restrict__ un,
+                                             const T* __restrict__ vn, const T* __restrict__ wn,
+                                             const T* __restrict__ uo, const T* __restrict__ vo,
+                                             const T* __restrict__ wo, T alpha, T dt, T skin,
+                                             T Lx, T Ly, T Lz, int advect_particle_vel)
+{
+    g2p_body<T>(plain_blk(), g, n, px, py, pz, vx, vy, vz, un, vn, wn, uo, vo, wo, alpha, dt, skin, Lx, Ly,
+                Lz, advect_particle_vel);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_g2p(const G2PArgs<T>* __restrict__ tab,
+                                              const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const G2PArgs<T>& a = batch_args(tab, first, ns, b);
+    g2p_body<T>(b, a.g, a.n, a.px, a.py, a.pz, a.vx, a.vy, a.vz, a.un, a.vn, a.wn, a.uo, a.vo, a.wo, a.alpha,
+                a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel);
+}
+
+template <typename T>
+void launch_b_g2p(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_g2p<T>, dim3(L.blocks), dim3(256), 0, st, (const G2PArgs<T>*)L.args, L.first, L.ns);
+}
+template void launch_b_g2p<float>(const BatchLaunch&, hipStream_t);
+template void launch_b_g2p<double>(const BatchLaunch&, hipStream_t);
 
 template <typename T>
 void launch_g2p(const Geo& g, int64_t n, T* pos, T* vel, const T* u_new, const T* v_new,

@@ -46,8 +46,12 @@ KERNEL_NAMES = ["bin_keys", "bin_scan", "bin_scatter", "bin_gather", "tiles", "p
                 "pcg_direction", "pcg_update", "project", "g2p"]
 FLIP_KERNEL_COUNT = len(KERNEL_NAMES)
 
+FLIP_BATCH_MAX_SCENES = 256
+FLIP_BATCH_GRAPHS = 1
+
 EXPORTED = ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes", "flip_readback",
-            "flip_stats", "flip_destroy", "flip_status_string"]
+            "flip_stats", "flip_destroy", "flip_status_string", "flip_batch_workspace_bytes",
+            "flip_batch_create", "flip_batch_step", "flip_batch_destroy"]
 
 
 class FlipError(RuntimeError):
@@ -106,8 +110,15 @@ def load():
         lib.flip_destroy.restype = None
         lib.flip_status_string.argtypes = [i32]
         lib.flip_status_string.restype = ctypes.c_char_p
+        vpp = ctypes.POINTER(vp)
+        lib.flip_batch_workspace_bytes.argtypes = [vpp, i32, ctypes.POINTER(sz)]
+        lib.flip_batch_create.argtypes = [vpp, i32, ctypes.c_uint32, vp, sz, vp, vpp]
+        lib.flip_batch_step.argtypes = [vp, i32, vp]
+        lib.flip_batch_destroy.argtypes = [vp]
+        lib.flip_batch_destroy.restype = None
         for name in ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes",
-                     "flip_readback", "flip_stats"]:
+                     "flip_readback", "flip_stats", "flip_batch_workspace_bytes", "flip_batch_create",
+                     "flip_batch_step"]:
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -222,6 +233,37 @@ def flip_destroy(h):
     load().flip_destroy(h)
 
 
+def _handle_array(handles):
+    arr = (ctypes.c_void_p * max(1, len(handles)))()
+    for i, h in enumerate(handles):
+        arr[i] = h.value if isinstance(h, ctypes.c_void_p) else h
+    return arr
+
+
+def flip_batch_workspace_bytes(handles) -> int:
+    out = ctypes.c_size_t(0)
+    arr = _handle_array(handles)
+    _check(load().flip_batch_workspace_bytes(arr, len(handles), ctypes.byref(out)),
+           "flip_batch_workspace_bytes")
+    return out.value
+
+
+def flip_batch_create(handles, flags: int, ws_ptr: int, ws_bytes: int, stream: int):
+    b = ctypes.c_void_p(0)
+    arr = _handle_array(handles)
+    _check(load().flip_batch_create(arr, len(handles), int(flags), ctypes.c_void_p(ws_ptr), ws_bytes,
+                                    ctypes.c_void_p(stream), ctypes.byref(b)), "flip_batch_create")
+    return b
+
+
+def flip_batch_step(b, nsteps: int, stream: int, allow=()) -> int:
+    return _check(load().flip_batch_step(b, int(nsteps), ctypes.c_void_p(stream)), "flip_batch_step", allow)
+
+
+def flip_batch_destroy(b):
+    load().flip_batch_destroy(b)
+
+
 # --------------------------------------------------------------------------
 # convenience wrapper used by the tests and the benchmark
 # --------------------------------------------------------------------------
@@ -289,6 +331,35 @@ class Simulation:
         if self.h is not None:
             flip_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A batch over several Simulations plus its torch-allocated table workspace."""
+
+    def __init__(self, sims, flags: int = 0, stream=None):
+        import torch
+
+        self.sims = list(sims)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        handles = [s.h for s in self.sims]
+        self.ws_bytes = flip_batch_workspace_bytes(handles)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.sims[0].ws.device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.b = flip_batch_create(handles, flags, ptr, self.ws_bytes, self.stream.cuda_stream)
+
+    def step(self, nsteps: int = 1, allow=()):
+        return flip_batch_step(self.b, nsteps, self.stream.cuda_stream, allow)
+
+    def close(self):
+        if self.b is not None:
+            flip_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

@@ -88,3 +88,22 @@ def test_init_rejects_missing_or_short_workspace_without_gpu():
     assert lib.flip_init(ctypes.byref(cfg), ctypes.c_void_p((1 << 20) + 8), need, None,
                          ctypes.byref(h)) == flip.FLIP_E_WORKSPACE
     assert not h.value
+
+
+def test_batch_calls_reject_bad_arguments_without_gpu():
+    from paper_2404_01931_amd import flip
+
+    lib = flip.load()
+    out = ctypes.c_size_t(0)
+    # no handles, too many scenes, null handle entries: rejected before any device work
+    assert lib.flip_batch_workspace_bytes(None, 0, ctypes.byref(out)) == flip.FLIP_E_INVALID
+    arr = (ctypes.c_void_p * 2)()
+    assert lib.flip_batch_workspace_bytes(arr, 2, ctypes.byref(out)) == flip.FLIP_E_INVALID
+    assert lib.flip_batch_workspace_bytes(arr, flip.FLIP_BATCH_MAX_SCENES + 1,
+                                          ctypes.byref(out)) == flip.FLIP_E_INVALID
+    b = ctypes.c_void_p(0)
+    assert lib.flip_batch_create(arr, 0, 0, None, 0, None, ctypes.byref(b)) == flip.FLIP_E_INVALID
+    assert lib.flip_batch_create(arr, 2, 0, None, 0, None, ctypes.byref(b)) == flip.FLIP_E_INVALID
+    assert b.value is None
+    assert lib.flip_batch_step(None, 1, None) == flip.FLIP_E_INVALID
+    lib.flip_batch_destroy(None)

@@ -60,7 +60,8 @@ def test_mixed_precision_solve_reaches_fp64_residual_and_error_table(orc):
         # the whole step: oracle's step (exact solve) from the same state
         ref = orc.step(params_of(sim), r["pos0"], r["vel0"], r["ids0"])
         assert np.array_equal(ref.ids, r["ids1"])
-        u_err = max(l2_rel(r["u_new"][a], ref.u_new[a]) for a in range(3))
+        # all three components together (some are near zero in this scene)
+        u_err = l2_rel(np.concatenate(r["u_new"]), np.concatenate(ref.u_new))
         v_err = l2_rel(r["vel1"], ref.vel)
         x_err = float(np.abs(r["pos1"] - ref.pos).max())
         p_step = l2_rel(r["p"], ref.solve.p)
