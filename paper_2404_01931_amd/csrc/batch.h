@@ -94,6 +94,7 @@ struct TileCompactArgs {
 template <typename T>
 struct P2GArgs {
     Geo g;
+    int64_t n;
     const T *px, *py, *pz, *vx, *vy, *vz;
     const uint32_t *start, *count;
     T gdt[3];

@@ -137,6 +137,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             const bool grav = !(c.flags & FLIP_FLAG_NO_GRAVITY);
             P2GArgs<T> p;
             p.g = g;
+            p.n = n;
             p.px = pn;
             p.py = pn + n;
             p.pz = pn + 2 * n;

@@ -43,12 +43,37 @@ __device__ inline int batch_scene(const uint32_t* __restrict__ first, int ns, Bl
     return s;
 }
 
+// A pointer read from memory (not a kernel argument) is generic to the
+// compiler, so its accesses become flat loads and stores, which count on the
+// LDS counter too and make every wait a full one. The tables of batched
+// launches hold global pointers only: passing one through an integer into
+// the global address space restores global accesses.
+template <typename T>
+__device__ inline T* as_global(T* p)
+{
+    typedef __attribute__((address_space(1))) T GT;
+    return (T*)(GT*)(uintptr_t)p;
+}
+
 // Arguments of this workgroup's scene in a batched launch (see batch.h).
 template <typename A>
 __device__ inline const A& batch_args(const A* __restrict__ tab, const uint32_t* __restrict__ first, int ns,
                                       Blk& b)
 {
     return tab[batch_scene(first, ns, b)];
+}
+
+// Workgroup barrier that orders LDS only. __syncthreads() fences every
+// address space, which makes the compiler wait for all outstanding global
+// loads (vmcnt(0)) before the barrier, including loads issued early for
+// later use. Where waves exchange data through LDS alone, this barrier
+// waits only for the wave's LDS operations, so prefetched global loads stay
+// in flight across it.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD

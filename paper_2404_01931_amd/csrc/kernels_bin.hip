@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void kb_fill_u32(const FillU32Args* __restrict
 {
     Blk b;
     const FillU32Args& a = batch_args(tab, first, ns, b);
-    fill_u32_body(b, a.p, a.n, a.v);
+    fill_u32_body(b, as_global(a.p), a.n, a.v);
 }
 
 void launch_b_fill_u32(const BatchLaunch& L, hipStream_t st)
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void kb_bin_keys(const BinKeysArgs<T>* __restr
 {
     Blk b;
     const BinKeysArgs<T>& a = batch_args(tab, first, ns, b);
-    bin_keys_body<T>(b, a.g, a.px, a.py, a.pz, a.n, a.key, a.rank, a.count);
+    bin_keys_body<T>(b, a.g, as_global(a.px), as_global(a.py), as_global(a.pz), a.n, as_global(a.key), as_global(a.rank), as_global(a.count));
 }
 
 template <typename T>
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(SCAN_NT) void kb_scan_totals(const ScanTotalsArgs* 
 {
     Blk b;
     const ScanTotalsArgs& a = batch_args(tab, first, ns, b);
-    scan_totals_body(b, a.in, a.n, a.totals);
+    scan_totals_body(b, as_global(a.in), a.n, as_global(a.totals));
 }
 
 void launch_b_scan_totals(const BatchLaunch& L, hipStream_t st)
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(1024) void kb_scan_totals_scan(const ScanTotalsScan
 {
     Blk b;
     const ScanTotalsScanArgs& a = batch_args(tab, first, ns, b);
-    scan_totals_scan_body(a.totals, a.nb);
+    scan_totals_scan_body(as_global(a.totals), a.nb);
 }
 
 void launch_b_scan_totals_scan(const BatchLaunch& L, hipStream_t st)
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(SCAN_NT) void kb_scan_apply(const ScanApplyArgs* __
 {
     Blk b;
     const ScanApplyArgs& a = batch_args(tab, first, ns, b);
-    scan_apply_body(b, a.in, a.out, a.n, a.offsets);
+    scan_apply_body(b, as_global(a.in), as_global(a.out), a.n, as_global(a.offsets));
 }
 
 void launch_b_scan_apply(const BatchLaunch& L, hipStream_t st)
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void kb_bin_scatter(const ScatterArgs* __restr
 {
     Blk b;
     const ScatterArgs& a = batch_args(tab, first, ns, b);
-    bin_scatter_body(b, a.key, a.rank, a.start, a.n, a.perm);
+    bin_scatter_body(b, as_global(a.key), as_global(a.rank), as_global(a.start), a.n, as_global(a.perm));
 }
 
 void launch_b_bin_scatter(const BatchLaunch& L, hipStream_t st)
@@ -442,8 +442,8 @@ __global__ __launch_bounds__(256) void kb_bin_gather(const GatherArgs<T>* __rest
 {
     Blk b;
     const GatherArgs<T>& a = batch_args(tab, first, ns, b);
-    bin_gather_body<T>(b, a.perm, a.key, a.start, a.count, a.n, a.pos_in, a.vel_in, a.id_in, a.pos_out,
-                       a.vel_out, a.id_out);
+    bin_gather_body<T>(b, as_global(a.perm), as_global(a.key), as_global(a.start), as_global(a.count), a.n, as_global(a.pos_in), as_global(a.vel_in), as_global(a.id_in), as_global(a.pos_out),
+                       as_global(a.vel_out), as_global(a.id_out));
 }
 
 template <typename T>
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void kb_tile_flags(const TileFlagsArgs* __rest
 {
     Blk b;
     const TileFlagsArgs& a = batch_args(tab, first, ns, b);
-    tile_flags_body(b, a.g, a.count, a.tile_flag);
+    tile_flags_body(b, a.g, as_global(a.count), as_global(a.tile_flag));
 }
 
 void launch_b_tile_flags(const BatchLaunch& L, hipStream_t st)
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void kb_tile_compact(const TileCompactArgs* __
 {
     Blk b;
     const TileCompactArgs& a = batch_args(tab, first, ns, b);
-    tile_compact_body(b, a.g, a.flag, a.excl, a.tile_slot, a.tile_list, a.tile_nbr, a.d_nactive);
+    tile_compact_body(b, a.g, as_global(a.flag), as_global(a.excl), as_global(a.tile_slot), as_global(a.tile_list), as_global(a.tile_nbr), as_global(a.d_nactive));
 }
 
 void launch_b_tile_compact(const BatchLaunch& L, hipStream_t st)

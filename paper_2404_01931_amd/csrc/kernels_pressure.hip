@@ -177,8 +177,8 @@ __global__ __launch_bounds__(PNT) void kb_rhs(const RhsArgs<T, V>* __restrict__ 
 {
     Blk blk;
     const RhsArgs<T, V>& a = batch_args(tab, first, ns, blk);
-    rhs_body<T, V>(blk, a.g, a.tile_list, a.d_nactive, a.count, a.u, a.v, a.w, (T)a.scale, a.diag, a.b, a.z,
-                   a.x, a.s0, a.s1, a.partials, a.pstride, a.ps, a.tol, a.max_iters);
+    rhs_body<T, V>(blk, a.g, as_global(a.tile_list), as_global(a.d_nactive), as_global(a.count), as_global(a.u), as_global(a.v), as_global(a.w), (T)a.scale, as_global(a.diag), as_global(a.b), as_global(a.z),
+                   as_global(a.x), as_global(a.s0), as_global(a.s1), as_global(a.partials), a.pstride, as_global(a.ps), a.tol, a.max_iters);
 }
 
 template <typename T, typename V>
@@ -216,86 +216,169 @@ template void launch_rhs<double, double>(const Geo&, int, const uint32_t*, const
 // The two iteration kernels run a bounded number of 256-thread workgroups
 // (at most PCG_MAX_GROUPS); each walks a contiguous range of active tiles, so
 // that the workgroups of one XCD cover one spatial chunk of the tile list and
-// share its halos in L2. A thread owns cells tid and tid + 256 of the current
-// tile and stages up to two of its 384 halo cells. LDS is double-buffered
-// and the next tile's values are loaded into registers before the current
-// tile's stencil is evaluated, so loads overlap arithmetic and one barrier
-// per tile suffices.
+// share its halos in L2. Thread t owns the x-adjacent cell pair (2t, 2t + 1)
+// of the current tile, read and written with one wide access per vector, and
+// stages one entry of the face halos: waves 0 and 1 the -x and +x faces (one
+// cell per lane), waves 2 and 3 the y and z faces (two adjacent cells per
+// lane). Every halo lane reads one aligned cell pair of the neighbouring
+// tile, so all lanes issue the same loads. LDS is double-buffered and the
+// tiles two ahead are loaded into registers before the current tile's
+// stencil is evaluated, so loads overlap arithmetic and one barrier per tile
+// suffices.
 // ---------------------------------------------------------------------------
 
 constexpr int PCG_NT = 256;
 
+// LDS image of one tile: its 512 cells, the -x and +x halos (one value in
+// every even slot of 128), then the -y, +y, -z and +z halos (64 values each)
+constexpr int LX_M = TILE_CELLS;
+constexpr int LX_P = LX_M + 128;
+constexpr int LY_M = LX_P + 128;
+constexpr int LY_P = LY_M + 64;
+constexpr int LZ_M = LY_P + 64;
+constexpr int LZ_P = LZ_M + 64;
+constexpr int STAGE2 = LZ_P + 64;
 
-// Values of one tile that a thread stages: its two cells and up to two halo
-// cells, loaded into registers two tiles ahead of their use. Every load is
+template <typename V>
+struct alignas(2 * sizeof(V)) Pair {
+    V a, b;
+};
+
+template <typename V>
+__device__ inline Pair<V> ld2(const V* __restrict__ p, int64_t i)
+{
+    return *(const Pair<V>*)(p + i);
+}
+
+template <typename V>
+__device__ inline void st2(V* __restrict__ p, int64_t i, V a, V b)
+{
+    *(Pair<V>*)(p + i) = Pair<V>{a, b};
+}
+
+// The halo entry a thread stages: face f of the tile (-x +x -y +y -z +z),
+// the even local index of the cell pair it reads in the neighbouring tile,
+// whether it keeps the pair's second cell (x faces keep one cell) and its
+// LDS slot. The faces of a wave's two half-waves (f_lo for lanes 0-31, f_hi
+// for lanes 32-63; equal in waves 0 and 1) are wave-uniform, so the
+// neighbour slots are read with scalar loads, which complete apart from the
+// vector loads of the data.
+struct HaloLane {
+    int f, f_lo, f_hi, src, dst;
+    bool hi, upper;
+};
+
+__device__ inline HaloLane halo_lane(int tid)
+{
+    HaloLane h;
+    if (tid < 128) {  // x faces: lane m stages cell (x, m & 7, m >> 3)
+        const int m = tid & 63, a = m & 7, b = m >> 3;
+        h.f = tid >> 6;
+        const int li = (h.f == 0 ? 7 : 0) + 8 * a + 64 * b;
+        h.src = li & ~1;
+        h.hi = (li & 1) != 0;
+        h.dst = (h.f == 0 ? LX_M : LX_P) + 2 * (a + 8 * b);
+    } else if (tid < 192) {  // y faces: lane m stages cells (2 (m & 3) + {0, 1}, y, m >> 2)
+        const int m = tid & 31, x = 2 * (m & 3), zz = m >> 2;
+        h.f = tid < 160 ? 2 : 3;
+        h.src = x + 8 * (h.f == 2 ? 7 : 0) + 64 * zz;
+        h.dst = (h.f == 2 ? LY_M : LY_P) + x + 8 * zz;
+        h.hi = false;
+    } else {  // z faces: lane m stages cells (2 (m & 3) + {0, 1}, m >> 2, z)
+        const int m = tid & 31, x = 2 * (m & 3), yy = m >> 2;
+        h.f = tid < 224 ? 4 : 5;
+        h.src = x + 8 * yy + 64 * (h.f == 4 ? 7 : 0);
+        h.dst = (h.f == 4 ? LZ_M : LZ_P) + x + 8 * yy;
+        h.hi = false;
+    }
+    h.f_lo = __builtin_amdgcn_readfirstlane(h.f);
+    h.f_hi = __builtin_amdgcn_readlane(h.f, 32);
+    h.upper = (tid & 63) >= 32;
+    return h;
+}
+
+// Neighbour sums of the cell pair (2t, 2t + 1) from the staged tile; c0, c1
+// are the pair's own staged values. Same summation order for every cell:
+// ((x- + x+) + (y- + y+)) + (z- + z+).
+template <typename V>
+__device__ inline void pair_neighbour_sums(const V* st, int t, V c0, V c1, V& n0, V& n1)
+{
+    const int l0 = 2 * t;
+    const int lx = l0 & 7, ly = (l0 >> 3) & 7, lz = l0 >> 6;
+    const V xm = st[lx > 0 ? l0 - 1 : LX_M + 2 * (ly + 8 * lz)];
+    const V xp = st[lx < 6 ? l0 + 2 : LX_P + 2 * (ly + 8 * lz)];
+    const Pair<V> ym = *(const Pair<V>*)(st + (ly > 0 ? l0 - 8 : LY_M + lx + 8 * lz));
+    const Pair<V> yp = *(const Pair<V>*)(st + (ly < 7 ? l0 + 8 : LY_P + lx + 8 * lz));
+    const Pair<V> zm = *(const Pair<V>*)(st + (lz > 0 ? l0 - 64 : LZ_M + lx + 8 * ly));
+    const Pair<V> zp = *(const Pair<V>*)(st + (lz < 7 ? l0 + 64 : LZ_P + lx + 8 * ly));
+    n0 = ((xm + c1) + (ym.a + yp.a)) + (zm.a + zp.a);
+    n1 = ((c0 + xp) + (ym.b + yp.b)) + (zm.b + zp.b);
+}
+
+// Values of one tile that a thread stages: its cell pair and its halo pair,
+// loaded into registers two tiles ahead of their use. Every load is
 // unconditional (a missing neighbour or a past-the-end tile reads a valid
 // address of the workgroup's own range and is masked where it is consumed),
 // so no control-flow merge makes the compiler wait for the loads early.
 template <typename V>
 struct DirRegs {
-    V z0, z1, s0, s1, hz0, hs0, hz1, hs1;
-    uint32_t d0, d1;
-    bool m0, m1;
+    Pair<V> z, s, hz, hs;
+    uint32_t d;  // the pair's two diagonal bytes
+    bool m;      // the halo's neighbour tile exists
 };
 
 template <typename V>
 __device__ inline void dir_fetch(DirRegs<V>& r, const V* __restrict__ z, const V* __restrict__ s_old,
-                                 const uint8_t* __restrict__ diag, int slot, int32_t n0, int32_t n1,
-                                 int tid, int hs0i, int hs1i)
+                                 const uint8_t* __restrict__ diag, int slot, int32_t nslot, int tid,
+                                 int hsrc)
 {
-    const int64_t e = (int64_t)slot * TILE_CELLS + tid;
-    const int64_t h0 = n0 >= 0 ? (int64_t)n0 * TILE_CELLS + hs0i : e;
-    const int64_t h1 = n1 >= 0 ? (int64_t)n1 * TILE_CELLS + hs1i : e;
-    r.z0 = z[e];
-    r.s0 = s_old[e];
-    r.z1 = z[e + PCG_NT];
-    r.s1 = s_old[e + PCG_NT];
-    r.d0 = diag[e];
-    r.d1 = diag[e + PCG_NT];
-    r.hz0 = z[h0];
-    r.hs0 = s_old[h0];
-    r.hz1 = z[h1];
-    r.hs1 = s_old[h1];
-    r.m0 = n0 >= 0;
-    r.m1 = n1 >= 0;
+    const int64_t e = (int64_t)slot * TILE_CELLS + 2 * tid;
+    const int64_t h = nslot >= 0 ? (int64_t)nslot * TILE_CELLS + hsrc : e;
+    r.z = ld2(z, e);
+    r.s = ld2(s_old, e);
+    r.d = *(const uint16_t*)(diag + e);
+    r.hz = ld2(z, h);
+    r.hs = ld2(s_old, h);
+    r.m = nslot >= 0;
 }
 
-__device__ inline void next_nbr(const int32_t* __restrict__ nbr, int slot, int f0, int f1,
-                                bool two_halo, int32_t& n0, int32_t& n1)
+// neighbour slot across this lane's halo face of tile `slot`
+__device__ inline int32_t next_nbr(const int32_t* __restrict__ nbr, int slot, const HaloLane& hl)
 {
-    const int32_t a = nbr[(int64_t)slot * 6 + f0];
-    const int32_t b = nbr[(int64_t)slot * 6 + (two_halo ? f1 : f0)];
-    n0 = a;
-    n1 = two_halo ? b : -1;
+    const int32_t a = nbr[(int64_t)slot * 6 + hl.f_lo];
+    const int32_t b = nbr[(int64_t)slot * 6 + hl.f_hi];
+    return hl.upper ? b : a;
 }
 
-// One tile of the direction kernel. The barrier makes the compiler wait for
-// every outstanding memory operation, so the LDS stores go before it and this
-// tile's global stores plus the loads two tiles ahead go after it, where they
-// overlap the stencil.
+// One tile of the direction kernel: stage the tile in LDS, then store it,
+// issue the loads two tiles ahead and evaluate the stencil. The barrier
+// orders LDS only, so those loads stay in flight across the next tile's
+// barrier.
 template <typename V>
-__device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tlast, int32_t& nn0,
-                                  int32_t& nn1, const int32_t* __restrict__ nbr,
-                                  const uint8_t* __restrict__ diag, const V* __restrict__ z,
-                                  const V* __restrict__ s_old, V* __restrict__ s_new, int tid,
-                                  int f0, int f1, int hs0i, int hs1i, bool two_halo)
+__device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tlast, int32_t& nn,
+                                  const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
+                                  const V* __restrict__ z, const V* __restrict__ s_old, V* __restrict__ s_new,
+                                  int tid, const HaloLane& hl)
 {
-    const V sc0 = fma(beta, cur.s0, cur.z0), sc1 = fma(beta, cur.s1, cur.z1);
-    const V hv0 = cur.m0 ? fma(beta, cur.hs0, cur.hz0) : V(0);
-    const V hv1 = cur.m1 ? fma(beta, cur.hs1, cur.hz1) : V(0);
-    const int d0 = (int)cur.d0, d1 = (int)cur.d1;
-    st[tid] = sc0;
-    st[tid + PCG_NT] = sc1;
-    st[TILE_CELLS + tid] = hv0;
-    if (two_halo) st[TILE_CELLS + PCG_NT + tid] = hv1;
-    __syncthreads();
-    const int64_t e = (int64_t)t * TILE_CELLS + tid;
-    s_new[e] = sc0;
-    s_new[e + PCG_NT] = sc1;
-    dir_fetch(cur, z, s_old, diag, min(t + 2, tlast), nn0, nn1, tid, hs0i, hs1i);
-    next_nbr(nbr, min(t + 3, tlast), f0, f1, two_halo, nn0, nn1);
-    const V q0 = d0 ? fma((V)d0, sc0, -neighbour_sum(st, tid)) : V(0);
-    const V q1 = d1 ? fma((V)d1, sc1, -neighbour_sum(st, tid + PCG_NT)) : V(0);
+    const V sc0 = fma(beta, cur.s.a, cur.z.a), sc1 = fma(beta, cur.s.b, cur.z.b);
+    const V hv0 = fma(beta, cur.hs.a, cur.hz.a), hv1 = fma(beta, cur.hs.b, cur.hz.b);
+    const V h0 = cur.m ? (hl.hi ? hv1 : hv0) : V(0);
+    const V h1 = cur.m ? hv1 : V(0);
+    const int d0 = (int)(cur.d & 0xFFu), d1 = (int)(cur.d >> 8);
+    st2(st, 2 * tid, sc0, sc1);
+    st2(st, hl.dst, h0, h1);  // x faces: the second slot is padding
+    lds_barrier();
+    st2(s_new, (int64_t)t * TILE_CELLS + 2 * tid, sc0, sc1);
+    const int32_t nn3 = next_nbr(nbr, min(t + 3, tlast), hl);
+    dir_fetch(cur, z, s_old, diag, min(t + 2, tlast), nn, tid, hl.src);
+    nn = nn3;
+    V n0, n1;
+    pair_neighbour_sums(st, tid, sc0, sc1, n0, n1);
+    const V q0 = d0 ? fma((V)d0, sc0, -n0) : V(0);
+    const V q1 = d1 ? fma((V)d1, sc1, -n1) : V(0);
+    // keep the next tile's LDS stores (which wait for its loads) after this
+    // tile's work
+    __builtin_amdgcn_sched_barrier(0);
     return (double)sc0 * (double)q0 + (double)sc1 * (double)q1;
 }
 
@@ -307,34 +390,36 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, const int32_t* __res
                                                    V* __restrict__ s_new, double* __restrict__ partials,
                                                    PcgState* __restrict__ ps)
 {
-    __shared__ V stg[2][STAGE];
+    __shared__ alignas(16) V stg[2][STAGE2];
     __shared__ double red[PCG_NT / WAVE];
     __shared__ bool last;
     unsigned* const sync = pcg_sync(ps);
     if (ps->done != PCG_RUNNING) return;
     const V beta = (V)ps->beta;
     const int tid = threadIdx.x;
-    const bool two_halo = tid < HALO - PCG_NT;
-    const int f0 = tid >> 6, f1 = (tid + PCG_NT) >> 6;
-    const int hs0i = halo_source(f0, tid & 63), hs1i = halo_source(f1, tid & 63);
+    const HaloLane hl = halo_lane(tid);
     int t0, t1;
     tile_range(blk, ps->n_active, t0, t1);
     double acc = 0.0;
     if (t0 < t1) {
         const int tlast = t1 - 1;
         DirRegs<V> A, B;
-        int32_t nn0, nn1;
-        next_nbr(nbr, t0, f0, f1, two_halo, nn0, nn1);
-        dir_fetch(A, z, s_old, diag, t0, nn0, nn1, tid, hs0i, hs1i);
-        next_nbr(nbr, min(t0 + 1, tlast), f0, f1, two_halo, nn0, nn1);
-        dir_fetch(B, z, s_old, diag, min(t0 + 1, tlast), nn0, nn1, tid, hs0i, hs1i);
-        next_nbr(nbr, min(t0 + 2, tlast), f0, f1, two_halo, nn0, nn1);
+        int32_t nn = next_nbr(nbr, t0, hl);
+        dir_fetch(A, z, s_old, diag, t0, nn, tid, hl.src);
+        nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
+        dir_fetch(B, z, s_old, diag, min(t0 + 1, tlast), nn, tid, hl.src);
+        nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+        // Tiles go in pairs, both halves unconditional: a branch around the
+        // second half would make the compiler wait for every outstanding
+        // load at the loop head. With an odd count the last pair's second
+        // half is the last tile again, from the values fetched before its
+        // update: it stores what the first half stored and its sum is dropped.
         for (int t = t0; t < t1; t += 2) {
-            acc += dir_tile(stg[0], A, beta, t, tlast, nn0, nn1, nbr, diag, z, s_old, s_new, tid, f0, f1,
-                            hs0i, hs1i, two_halo);
-            if (t + 1 < t1)
-                acc += dir_tile(stg[1], B, beta, t + 1, tlast, nn0, nn1, nbr, diag, z, s_old, s_new, tid,
-                                f0, f1, hs0i, hs1i, two_halo);
+            acc += dir_tile(stg[0], A, beta, t, tlast, nn, nbr, diag, z, s_old, s_new, tid, hl);
+            const bool real = t + 1 < t1;
+            const double v = dir_tile(stg[1], B, beta, real ? t + 1 : tlast, tlast, nn, nbr, diag, z, s_old,
+                                      s_new, tid, hl);
+            acc += real ? v : 0.0;
         }
     }
     const double part = block_sum<PCG_NT>(acc, red);
@@ -370,7 +455,7 @@ __global__ __launch_bounds__(PCG_NT) void kb_pcg_direction(const DirArgs<V>* __r
 {
     Blk blk;
     const DirArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_direction_body<V>(blk, a.nbr, a.diag, a.z, a.s_old, a.s_new, a.partials, a.ps);
+    pcg_direction_body<V>(blk, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old), as_global(a.s_new), as_global(a.partials), as_global(a.ps));
 }
 
 template <typename V>
@@ -400,66 +485,65 @@ template void launch_pcg_direction<double>(int, const int32_t*, const uint8_t*, 
 
 template <typename V>
 struct UpdRegs {
-    V s0, s1, x0, x1, z0, z1, h0, h1;
-    uint32_t d0, d1;
-    bool m0, m1;
+    Pair<V> s, x, z, h;
+    uint32_t d;  // the pair's two diagonal bytes
+    bool m;      // the halo's neighbour tile exists
 };
 
 template <typename V>
 __device__ inline void upd_fetch(UpdRegs<V>& r, const V* __restrict__ s, const V* __restrict__ x,
                                  const V* __restrict__ z, const uint8_t* __restrict__ diag, int slot,
-                                 int32_t n0, int32_t n1, int tid, int hs0i, int hs1i)
+                                 int32_t nslot, int tid, int hsrc)
 {
-    const int64_t e = (int64_t)slot * TILE_CELLS + tid;
-    const int64_t h0 = n0 >= 0 ? (int64_t)n0 * TILE_CELLS + hs0i : e;
-    const int64_t h1 = n1 >= 0 ? (int64_t)n1 * TILE_CELLS + hs1i : e;
-    r.s0 = s[e];
-    r.s1 = s[e + PCG_NT];
-    r.x0 = x[e];
-    r.x1 = x[e + PCG_NT];
-    r.z0 = z[e];
-    r.z1 = z[e + PCG_NT];
-    r.d0 = diag[e];
-    r.d1 = diag[e + PCG_NT];
-    r.h0 = s[h0];
-    r.h1 = s[h1];
-    r.m0 = n0 >= 0;
-    r.m1 = n1 >= 0;
+    const int64_t e = (int64_t)slot * TILE_CELLS + 2 * tid;
+    const int64_t h = nslot >= 0 ? (int64_t)nslot * TILE_CELLS + hsrc : e;
+    r.s = ld2(s, e);
+    r.x = ld2(x, e);
+    r.z = ld2(z, e);
+    r.d = *(const uint16_t*)(diag + e);
+    r.h = ld2(s, h);
+    r.m = nslot >= 0;
 }
 
+// x += alpha s; r = n z - alpha q; z = r / n for one cell (n = 0: not fluid,
+// x and z stay 0); accumulates r.z and max|r|
 template <typename V>
-__device__ inline void upd_cell(const V* st, int l, int d, V sc, V xc, V zc, V alpha, int64_t e,
-                                V* __restrict__ x, V* __restrict__ z, double& rz, double& rmax)
+__device__ inline void upd_cell(int d, V sc, V xc, V zc, V nsum, V alpha, V& xn, V& zn, double& rz,
+                                double& rmax)
 {
-    if (!d) return;
-    const V q = fma((V)d, sc, -neighbour_sum(st, l));  // same rounding as the direction kernel
-    x[e] = fma(alpha, sc, xc);
-    const V r = fma((V)d, zc, -alpha * q);
-    const V zn = r / (V)d;
-    z[e] = zn;
+    const V q = fma((V)d, sc, -nsum);  // same rounding as the direction kernel
+    xn = fma(alpha, sc, xc);
+    const V r = d ? fma((V)d, zc, -alpha * q) : V(0);
+    zn = d ? r / (V)d : V(0);
     rz += (double)r * (double)zn;
     rmax = fmax(rmax, finite_or_inf(fabs((double)r)));
 }
 
 template <typename V>
-__device__ inline void upd_tile(V* st, UpdRegs<V>& cur, V alpha, int t, int tlast, int32_t& nn0,
-                                int32_t& nn1, const int32_t* __restrict__ nbr,
-                                const uint8_t* __restrict__ diag, const V* __restrict__ s,
-                                V* __restrict__ x, V* __restrict__ z, int tid, int f0, int f1,
-                                int hs0i, int hs1i, bool two_halo, double& rz, double& rmax)
+__device__ inline void upd_tile(V* st, UpdRegs<V>& cur, V alpha, int t, int tlast, int32_t& nn,
+                                const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
+                                const V* __restrict__ s, V* __restrict__ x, V* __restrict__ z, int tid,
+                                const HaloLane& hl, double& rz, double& rmax)
 {
-    const V sc0 = cur.s0, sc1 = cur.s1, xc0 = cur.x0, xc1 = cur.x1, zc0 = cur.z0, zc1 = cur.z1;
-    const int d0 = (int)cur.d0, d1 = (int)cur.d1;
-    st[tid] = sc0;
-    st[tid + PCG_NT] = sc1;
-    st[TILE_CELLS + tid] = cur.m0 ? cur.h0 : V(0);
-    if (two_halo) st[TILE_CELLS + PCG_NT + tid] = cur.m1 ? cur.h1 : V(0);
-    __syncthreads();  // loads two tiles ahead are issued after the barrier
-    upd_fetch(cur, s, x, z, diag, min(t + 2, tlast), nn0, nn1, tid, hs0i, hs1i);
-    next_nbr(nbr, min(t + 3, tlast), f0, f1, two_halo, nn0, nn1);
-    const int64_t e = (int64_t)t * TILE_CELLS + tid;
-    upd_cell(st, tid, d0, sc0, xc0, zc0, alpha, e, x, z, rz, rmax);
-    upd_cell(st, tid + PCG_NT, d1, sc1, xc1, zc1, alpha, e + PCG_NT, x, z, rz, rmax);
+    const Pair<V> sc = cur.s, xc = cur.x, zc = cur.z;
+    const V h0 = cur.m ? (hl.hi ? cur.h.b : cur.h.a) : V(0);
+    const V h1 = cur.m ? cur.h.b : V(0);
+    const int d0 = (int)(cur.d & 0xFFu), d1 = (int)(cur.d >> 8);
+    st2(st, 2 * tid, sc.a, sc.b);
+    st2(st, hl.dst, h0, h1);  // x faces: the second slot is padding
+    lds_barrier();
+    const int32_t nn3 = next_nbr(nbr, min(t + 3, tlast), hl);
+    upd_fetch(cur, s, x, z, diag, min(t + 2, tlast), nn, tid, hl.src);
+    nn = nn3;
+    V n0, n1;
+    pair_neighbour_sums(st, tid, sc.a, sc.b, n0, n1);
+    V x0, x1, z0, z1;
+    upd_cell(d0, sc.a, xc.a, zc.a, n0, alpha, x0, z0, rz, rmax);
+    upd_cell(d1, sc.b, xc.b, zc.b, n1, alpha, x1, z1, rz, rmax);
+    const int64_t e = (int64_t)t * TILE_CELLS + 2 * tid;
+    st2(x, e, x0, x1);
+    st2(z, e, z0, z1);
+    __builtin_amdgcn_sched_barrier(0);  // see dir_tile
 }
 
 // update kernel: x += alpha s; r = n z - alpha A s; z = r / n; r.z; max|r|
@@ -470,34 +554,33 @@ __device__ __forceinline__ void pcg_update_body(Blk blk, const int32_t* __restri
                                                 double* __restrict__ partials, int64_t pstride,
                                                 PcgState* __restrict__ ps)
 {
-    __shared__ V stg[2][STAGE];
+    __shared__ alignas(16) V stg[2][STAGE2];
     __shared__ double red[PCG_NT / WAVE];
     __shared__ bool last;
     unsigned* const sync = pcg_sync(ps);
     if (ps->done != PCG_RUNNING) return;
     const V alpha = (V)ps->alpha;
     const int tid = threadIdx.x;
-    const bool two_halo = tid < HALO - PCG_NT;
-    const int f0 = tid >> 6, f1 = (tid + PCG_NT) >> 6;
-    const int hs0i = halo_source(f0, tid & 63), hs1i = halo_source(f1, tid & 63);
+    const HaloLane hl = halo_lane(tid);
     int t0, t1;
     tile_range(blk, ps->n_active, t0, t1);
     double rz = 0.0, rmax = 0.0;
     if (t0 < t1) {
         const int tlast = t1 - 1;
         UpdRegs<V> A, B;
-        int32_t nn0, nn1;
-        next_nbr(nbr, t0, f0, f1, two_halo, nn0, nn1);
-        upd_fetch(A, s, x, z, diag, t0, nn0, nn1, tid, hs0i, hs1i);
-        next_nbr(nbr, min(t0 + 1, tlast), f0, f1, two_halo, nn0, nn1);
-        upd_fetch(B, s, x, z, diag, min(t0 + 1, tlast), nn0, nn1, tid, hs0i, hs1i);
-        next_nbr(nbr, min(t0 + 2, tlast), f0, f1, two_halo, nn0, nn1);
+        int32_t nn = next_nbr(nbr, t0, hl);
+        upd_fetch(A, s, x, z, diag, t0, nn, tid, hl.src);
+        nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
+        upd_fetch(B, s, x, z, diag, min(t0 + 1, tlast), nn, tid, hl.src);
+        nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+        // tiles in unconditional pairs, as in the direction kernel
         for (int t = t0; t < t1; t += 2) {
-            upd_tile(stg[0], A, alpha, t, tlast, nn0, nn1, nbr, diag, s, x, z, tid, f0, f1, hs0i, hs1i,
-                     two_halo, rz, rmax);
-            if (t + 1 < t1)
-                upd_tile(stg[1], B, alpha, t + 1, tlast, nn0, nn1, nbr, diag, s, x, z, tid, f0, f1, hs0i,
-                         hs1i, two_halo, rz, rmax);
+            upd_tile(stg[0], A, alpha, t, tlast, nn, nbr, diag, s, x, z, tid, hl, rz, rmax);
+            const bool real = t + 1 < t1;
+            double rz2 = 0.0, rmax2 = 0.0;
+            upd_tile(stg[1], B, alpha, real ? t + 1 : tlast, tlast, nn, nbr, diag, s, x, z, tid, hl, rz2, rmax2);
+            rz += real ? rz2 : 0.0;
+            rmax = real ? fmax(rmax, rmax2) : rmax;
         }
     }
     const double prz = block_sum<PCG_NT>(rz, red);
@@ -541,7 +624,7 @@ __global__ __launch_bounds__(PCG_NT) void kb_pcg_update(const UpdArgs<V>* __rest
 {
     Blk blk;
     const UpdArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_update_body<V>(blk, a.nbr, a.diag, a.s, a.x, a.z, a.partials, a.pstride, a.ps);
+    pcg_update_body<V>(blk, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.partials), a.pstride, as_global(a.ps));
 }
 
 template <typename V>
@@ -679,6 +762,12 @@ void launch_rhs_mixed(const Geo& g, int groups, const uint32_t* tile_list, const
 // FP64 solution of the tile and its face halos is staged in LDS; the solution
 // is double-buffered (x64_in -> x64_out, x_in -> x_out) because other
 // workgroups read this tile's values as their halo.
+//
+// The inner solve restarts from the new residual (s = 0). Continuing the
+// FP32 iteration with its search direction instead (a residual replacement)
+// took more than twice the iterations on the drop scene: the FP32 recursion
+// drifts from the true residual by about 1e-4 of max|b| by the time of a
+// refinement, so the kept direction no longer fits the replaced residual.
 __global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ nbr,
                                                    const uint8_t* __restrict__ diag,
                                                    const double* __restrict__ b64,
@@ -829,7 +918,7 @@ __global__ __launch_bounds__(256) void kb_project(const ProjectArgs<T, V>* __res
 {
     Blk blk;
     const ProjectArgs<T, V>& a = batch_args(tab, first, ns, blk);
-    project_body<T, V, A>(blk, a.g, a.count, a.tile_slot, a.p, a.star, a.out, a.scale);
+    project_body<T, V, A>(blk, a.g, as_global(a.count), as_global(a.tile_slot), as_global(a.p), as_global(a.star), as_global(a.out), a.scale);
 }
 
 template <typename T, typename V>
@@ -854,7 +943,7 @@ __global__ __launch_bounds__(64) void kb_summary(const SummaryArgs* __restrict__
     Blk blk;
     const SummaryArgs& a = batch_args(tab, first, ns, blk);
     if (threadIdx.x != 0) return;
-    const PcgState* ps = a.ps;
+    const PcgState* ps = as_global(a.ps);
     SolveSummary o;
     o.max_b = ps->max_b;
     o.max_r = ps->max_r;
@@ -864,7 +953,7 @@ __global__ __launch_bounds__(64) void kb_summary(const SummaryArgs* __restrict__
     o.n_active = ps->n_active;
     o.sync_error = ps->sync_error;
     o.pad_ = 0;
-    *a.out = o;
+    *as_global(a.out) = o;
 }
 
 void launch_b_summary(const BatchLaunch& L, hipStream_t st)

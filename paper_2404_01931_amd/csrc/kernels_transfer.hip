@@ -70,8 +70,50 @@ __device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, dou
 }
 
 // workgroup b.id handles tile (b.id % tx, (b.id / tx) % ty, b.id / (tx ty))
+// Particles of one cell, up to P2G_BATCH of them, held in registers: the
+// loads of a whole cell are issued together, one colour phase ahead of their
+// use, instead of one particle at a time.
+constexpr int P2G_BATCH = 8;
+
 template <typename T>
-__device__ __forceinline__ void p2g_body(Blk b, Geo g, const T* __restrict__ px, const T* __restrict__ py,
+struct CellParticles {
+    T x[P2G_BATCH], y[P2G_BATCH], z[P2G_BATCH], u[P2G_BATCH], v[P2G_BATCH], w[P2G_BATCH];
+};
+
+// Load particles s .. s + min(cnt, P2G_BATCH) - 1 (n > 0 particles in all;
+// indices are clamped into range so that every load is unconditional).
+template <typename T>
+__device__ inline void load_cell(CellParticles<T>& r, const T* __restrict__ px, const T* __restrict__ py,
+                                 const T* __restrict__ pz, const T* __restrict__ vx, const T* __restrict__ vy,
+                                 const T* __restrict__ vz, uint32_t s, uint32_t cnt, uint32_t n)
+{
+    const uint32_t last = cnt ? s + min(cnt, (uint32_t)P2G_BATCH) - 1 : s;
+#pragma unroll
+    for (int k = 0; k < P2G_BATCH; ++k) {
+        const uint32_t q = min(min(s + (uint32_t)k, last), n - 1);
+        r.x[k] = px[q];
+        r.y[k] = py[q];
+        r.z[k] = pz[q];
+        r.u[k] = vx[q];
+        r.v[k] = vy[q];
+        r.w[k] = vz[q];
+    }
+}
+
+// the cell that lane handles in colour phase ph (ring box [r0, r1] per axis),
+// or -1 when that position is outside the box
+__device__ inline int64_t phase_cell(const Geo& g, int ph, int lane, int rx0, int ry0, int rz0, int rx1, int ry1,
+                                     int rz1)
+{
+    const int cx = rx0 + ((ph % 3) - rx0 % 3 + 3) % 3 + 3 * (lane & 3);
+    const int cy = ry0 + (((ph / 3) % 3) - ry0 % 3 + 3) % 3 + 3 * ((lane >> 2) & 3);
+    const int cz = rz0 + ((ph / 9) - rz0 % 3 + 3) % 3 + 3 * (lane >> 4);
+    if (cx > rx1 || cy > ry1 || cz > rz1) return -1;
+    return cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
+}
+
+template <typename T>
+__device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __restrict__ px, const T* __restrict__ py,
                                          const T* __restrict__ pz, const T* __restrict__ vx,
                                          const T* __restrict__ vy, const T* __restrict__ vz,
                                          const uint32_t* __restrict__ start,
@@ -92,21 +134,47 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, const T* __restrict__ px,
     const int ry0 = max(y0 - 1, 0), ry1 = min(y0 + P2G_T, g.ny - 1);
     const int rz0 = max(z0 - 1, 0), rz1 = min(z0 + P2G_T, g.nz - 1);
     const double inv = g.inv_dx;
-    for (int ph = 0; ph < 27; ++ph) {
-        const int cx = rx0 + ((ph % 3) - rx0 % 3 + 3) % 3 + 3 * (lane & 3);
-        const int cy = ry0 + (((ph / 3) % 3) - ry0 % 3 + 3) % 3 + 3 * ((lane >> 2) & 3);
-        const int cz = rz0 + ((ph / 9) - rz0 % 3 + 3) % 3 + 3 * (lane >> 4);
-        if (cx <= rx1 && cy <= ry1 && cz <= rz1) {
-            const int64_t c = cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
-            const uint32_t s0 = start[c], n = count[c];
-            for (uint32_t q = s0; q < s0 + n; ++q) {
+    if (n > 0) {
+        // Software pipeline over the 27 phases: the cell range of phase
+        // ph + 2 and the particles of phase ph + 1 are loaded while phase ph
+        // is splatted. Phases exchange data through LDS only, so the barrier
+        // between them leaves those loads in flight.
+        const uint32_t nn = (uint32_t)n;
+        int64_t c = phase_cell(g, 0, lane, rx0, ry0, rz0, rx1, ry1, rz1);
+        uint32_t s_a = start[c >= 0 ? c : 0], n_a = c >= 0 ? count[c] : 0u;
+        c = phase_cell(g, 1, lane, rx0, ry0, rz0, rx1, ry1, rz1);
+        uint32_t s_b = start[c >= 0 ? c : 0], n_b = c >= 0 ? count[c] : 0u;
+        CellParticles<T> A;
+        load_cell(A, px, py, pz, vx, vy, vz, s_a, n_a, nn);
+#pragma unroll 1
+        for (int ph = 0; ph < 27; ++ph) {
+            c = phase_cell(g, min(ph + 2, 26), lane, rx0, ry0, rz0, rx1, ry1, rz1);
+            const uint32_t s_c = start[c >= 0 ? c : 0], n_c = c >= 0 ? count[c] : 0u;
+            CellParticles<T> B;
+            load_cell(B, px, py, pz, vx, vy, vz, s_b, n_b, nn);
+#pragma unroll
+            for (int k = 0; k < P2G_BATCH; ++k) {
+                if ((uint32_t)k < n_a) {
+                    const double gx = (double)A.x[k] * inv, gy = (double)A.y[k] * inv, gz = (double)A.z[k] * inv;
+                    splat<T, 0>(acc[0], x0, y0, z0, gx, gy, gz, A.u[k]);
+                    splat<T, 1>(acc[1], x0, y0, z0, gx, gy, gz, A.v[k]);
+                    splat<T, 2>(acc[2], x0, y0, z0, gx, gy, gz, A.w[k]);
+                }
+            }
+            // cells holding more particles than a batch: the rest one by one
+            for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q) {
                 const double gx = (double)px[q] * inv, gy = (double)py[q] * inv, gz = (double)pz[q] * inv;
                 splat<T, 0>(acc[0], x0, y0, z0, gx, gy, gz, vx[q]);
                 splat<T, 1>(acc[1], x0, y0, z0, gx, gy, gz, vy[q]);
                 splat<T, 2>(acc[2], x0, y0, z0, gx, gy, gz, vz[q]);
             }
+            lds_barrier();
+            A = B;
+            s_a = s_b;
+            n_a = n_b;
+            s_b = s_c;
+            n_b = n_c;
         }
-        __syncthreads();
     }
     // write the samples this tile owns: [x0, x0+8) on every axis, plus the
     // domain's high side when the tile touches it
@@ -138,7 +206,7 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, const T* __restrict__ px,
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, const T* __restrict__ px,
+__global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, int64_t n, const T* __restrict__ px,
                                                   const T* __restrict__ py, const T* __restrict__ pz,
                                                   const T* __restrict__ vx, const T* __restrict__ vy,
                                                   const T* __restrict__ vz,
@@ -149,7 +217,7 @@ __global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, const T* __restrict__ p
                                                   T* __restrict__ u_star, T* __restrict__ v_star,
                                                   T* __restrict__ w_star)
 {
-    p2g_body<T>(plain_blk(), g, px, py, pz, vx, vy, vz, start, count, gdt_x, gdt_y, gdt_z, u_old, v_old,
+    p2g_body<T>(plain_blk(), g, n, px, py, pz, vx, vy, vz, start, count, gdt_x, gdt_y, gdt_z, u_old, v_old,
                 w_old, u_star, v_star, w_star);
 }
 
@@ -159,8 +227,8 @@ __global__ __launch_bounds__(64) void kb_p2g_tiles(const P2GArgs<T>* __restrict_
 {
     Blk b;
     const P2GArgs<T>& a = batch_args(tab, first, ns, b);
-    p2g_body<T>(b, a.g, a.px, a.py, a.pz, a.vx, a.vy, a.vz, a.start, a.count, a.gdt[0], a.gdt[1], a.gdt[2],
-                a.old[0], a.old[1], a.old[2], a.star[0], a.star[1], a.star[2]);
+    p2g_body<T>(b, a.g, a.n, as_global(a.px), as_global(a.py), as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.start), as_global(a.count), a.gdt[0], a.gdt[1], a.gdt[2],
+                as_global(a.old[0]), as_global(a.old[1]), as_global(a.old[2]), as_global(a.star[0]), as_global(a.star[1]), as_global(a.star[2]));
 }
 
 template <typename T>
@@ -169,7 +237,7 @@ void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint3
                 hipStream_t st)
 {
     const unsigned tiles = (unsigned)tiles_of(g);
-    hipLaunchKernelGGL(k_p2g_tiles<T>, dim3(tiles), dim3(64), 0, st, g, pos, pos + n, pos + 2 * n, vel,
+    hipLaunchKernelGGL(k_p2g_tiles<T>, dim3(tiles), dim3(64), 0, st, g, n, pos, pos + n, pos + 2 * n, vel,
                        vel + n, vel + 2 * n, start, count, gdt[0], gdt[1], gdt[2], old[0], old[1],
                        old[2], star[0], star[1], star[2]);
 }
@@ -321,7 +389,7 @@ __global__ __launch_bounds__(256) void kb_g2p(const G2PArgs<T>* __restrict__ tab
 {
     Blk b;
     const G2PArgs<T>& a = batch_args(tab, first, ns, b);
-    g2p_body<T>(b, a.g, a.n, a.px, a.py, a.pz, a.vx, a.vy, a.vz, a.un, a.vn, a.wn, a.uo, a.vo, a.wo, a.alpha,
+    g2p_body<T>(b, a.g, a.n, as_global(a.px), as_global(a.py), as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.un), as_global(a.vn), as_global(a.wn), as_global(a.uo), as_global(a.vo), as_global(a.wo), a.alpha,
                 a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel);
 }
 
