@@ -263,6 +263,19 @@ void timer_end(flip_handle* h, int q, hipStream_t st)
     if (q >= 0) (void)hipEventRecord(h->ev[q + 1], st);
 }
 
+// An event pair for a launch that records its own start and end (the solver
+// kernels: their launches are short, so the dispatch latency that separate
+// event records would include matters). Returns the pair's first index or -1.
+int timer_pair(flip_handle* h, int kind, int pcg_iter)
+{
+    if (!(h->cfg.flags & FLIP_FLAG_KERNEL_TIMING) || h->ev_used + 1 >= (int)h->ev.size()) return -1;
+    const int q = h->ev_used;
+    h->ev_used += 2;
+    h->ev_kind[q / 2] = kind;
+    h->ev_iter[q / 2] = pcg_iter;
+    return q;
+}
+
 flip_status timer_collect(flip_handle* h, hipStream_t st)
 {
     if (h->ev_used == 0) return FLIP_OK;
@@ -293,14 +306,14 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
         for (int it = 0; it < chunk; ++it) {
             const int sc = h->scur;
             const bool timed = ((launched + it) % TIMED_PCG_EVERY) == 0;
-            int q1 = timed ? timer_begin(h, FLIP_KERNEL_PCG_DIRECTION, st, launched + it) : -1;
+            const int q1 = timed ? timer_pair(h, FLIP_KERNEL_PCG_DIRECTION, launched + it) : -1;
             launch_pcg_direction<V>(h->groups, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
-                                    (V*)h->s[sc ^ 1], h->partials, h->ps, st);
-            timer_end(h, q1, st);
-            int q2 = timed ? timer_begin(h, FLIP_KERNEL_PCG_UPDATE, st, launched + it) : -1;
+                                    (V*)h->s[sc ^ 1], h->partials, h->ps, st, q1 >= 0 ? h->ev[q1] : nullptr,
+                                    q1 >= 0 ? h->ev[q1 + 1] : nullptr);
+            const int q2 = timed ? timer_pair(h, FLIP_KERNEL_PCG_UPDATE, launched + it) : -1;
             launch_pcg_update<V>(h->groups, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
-                                 h->partials, h->groups, h->ps, st);
-            timer_end(h, q2, st);
+                                 h->partials, h->groups, h->ps, st, q2 >= 0 ? h->ev[q2] : nullptr,
+                                 q2 >= 0 ? h->ev[q2 + 1] : nullptr);
             h->scur = sc ^ 1;
         }
         launched += chunk;

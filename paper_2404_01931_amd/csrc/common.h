@@ -58,8 +58,12 @@ __host__ __device__ inline unsigned* pcg_sync(PcgState* ps)
 }
 
 // Upper bound on the workgroups of one PCG iteration kernel (4 per CU; a
-// sweep over 256..16384 on the 256^3 drop scene found 1024 fastest).
-constexpr int PCG_MAX_GROUPS = 1024;
+// sweep over 256..16384 on the 256^3 drop scene found 1024 fastest). A build
+// may set another bound with -DFLIPMI_PCG_GROUPS=n.
+#ifndef FLIPMI_PCG_GROUPS
+#define FLIPMI_PCG_GROUPS 1024
+#endif
+constexpr int PCG_MAX_GROUPS = FLIPMI_PCG_GROUPS;
 
 // Reduction slots hold this pattern when empty (see device_util.h).
 constexpr uint64_t SLOT_EMPTY_BITS = 0x7FF4DEADBEEF0001ull;
@@ -112,13 +116,16 @@ void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint3
                 const uint32_t* count, const T* u, const T* v, const T* w, double scale, uint8_t* diag,
                 V* b, V* z, V* x, V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev,
                 double tol, int max_iters, hipStream_t st);
+// With ev_start/ev_stop non-null the launch records the kernel's own start
+// and end in those events (dispatch latency excluded).
 template <typename V>
 void launch_pcg_direction(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
                           const V* s_old, V* s_new, double* partials, PcgState* st_dev,
-                          hipStream_t st);
+                          hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 template <typename V>
 void launch_pcg_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
-                       V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st);
+                       V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st,
+                       hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // mixed precision: right-hand side in FP64 (b64), FP64 solution x64 = 0 and the
 // start of the first FP32 inner solve (z = b64 / n rounded, x = 0, s = 0)
 void launch_rhs_mixed(const Geo& g, int groups, const uint32_t* tile_list, const uint32_t* d_nactive,

@@ -219,40 +219,55 @@ __device__ inline void reset_arrivals(unsigned* ctr)
         __hip_atomic_store(ctr + SYNC_STRIDE * threadIdx.x, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// In the last workgroup: combine slots[0..nb) (sum, or max when MAX), reset
-// them to EMPTY. Loads are issued eight at a time per thread. *err is set
+// In the last workgroup: combine the slots of NQ quantities, quantity q in
+// slots[q * stride + 0 .. nb), by sum, or by max where MAXMASK has bit q set,
+// and reset them to EMPTY. Every quantity's loads are issued together, so
+// the combine costs one round trip to memory whatever NQ is. *err is set
 // when a slot stayed EMPTY for SLOT_MAX_POLLS re-reads; after that the
-// thread stops waiting, so the block always finishes.
-template <int NT, bool MAX>
-__device__ inline double collect_slots(double* slots, int nb, double* sh, int* err)
+// thread stops waiting, so the block always finishes. Within a thread slots
+// are taken in index order, then threads in a fixed tree: the result is the
+// same on every run.
+template <int NT, int NQ, unsigned MAXMASK>
+__device__ inline void collect_slots(double* slots, int64_t stride, int nb, double* sh, int* err,
+                                     double (&out)[NQ])
 {
-    double acc = 0.0;
-    for (int base = threadIdx.x; base < nb; base += 8 * NT) {
-        unsigned long long v[8];
+    constexpr int U = 8;
+    double acc[NQ];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = base + u * NT;
-            v[u] = i < nb ? slot_load(slots + i) : 0ull;
-        }
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int base = threadIdx.x; base < nb; base += U * NT) {
+        unsigned long long v[NQ][U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int i = base + u * NT;
-            if (i >= nb) continue;
-            for (int polls = 0; v[u] == SLOT_EMPTY && polls < SLOT_MAX_POLLS && !*err; ++polls) {
-                __builtin_amdgcn_s_sleep(1);
-                v[u] = slot_load(slots + i);
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = base + u * NT;
+                v[q][u] = i < nb ? slot_load(slots + q * stride + i) : 0ull;
             }
-            if (v[u] == SLOT_EMPTY) {
-                *err = 1;
-                v[u] = 0ull;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = base + u * NT;
+                if (i >= nb) continue;
+                double* slot = slots + q * stride + i;
+                for (int polls = 0; v[q][u] == SLOT_EMPTY && polls < SLOT_MAX_POLLS && !*err; ++polls) {
+                    __builtin_amdgcn_s_sleep(1);
+                    v[q][u] = slot_load(slot);
+                }
+                if (v[q][u] == SLOT_EMPTY) {
+                    *err = 1;
+                    v[q][u] = 0ull;
+                }
+                const double x = __longlong_as_double((long long)v[q][u]);
+                acc[q] = ((MAXMASK >> q) & 1u) ? (x > acc[q] ? x : acc[q]) : acc[q] + x;
+                __hip_atomic_store((unsigned long long*)slot, SLOT_EMPTY, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             }
-            const double x = __longlong_as_double((long long)v[u]);
-            acc = MAX ? (x > acc ? x : acc) : acc + x;
-            __hip_atomic_store((unsigned long long*)(slots + i), SLOT_EMPTY, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
     }
-    return MAX ? block_max<NT>(acc, sh) : block_sum<NT>(acc, sh);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        out[q] = ((MAXMASK >> q) & 1u) ? block_max<NT>(acc[q], sh) : block_sum<NT>(acc[q], sh);
 }
 
 }  // namespace flipmi

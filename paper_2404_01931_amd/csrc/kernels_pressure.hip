@@ -23,6 +23,8 @@
 // results are identical from run to run.
 #include <cfloat>
 
+#include <hip/hip_ext.h>
+
 #include "batch.h"
 #include "common.h"
 #include "device_util.h"
@@ -130,9 +132,9 @@ __device__ __forceinline__ void rhs_body(Blk blk, Geo g, const uint32_t* __restr
     if (!publish_partials(blk, partials, pstride, vals, 3, sync, &last)) return;
     const int nb = blk.n;
     int err = 0;
-    const double rho = collect_slots<PNT, false>(partials, nb, red, &err);
-    const double max_b = collect_slots<PNT, true>(partials + pstride, nb, red, &err);
-    const double nfl = collect_slots<PNT, false>(partials + 2 * pstride, nb, red, &err);
+    double tot[3];
+    collect_slots<PNT, 3, 2u>(partials, pstride, nb, red, &err, tot);
+    const double rho = tot[0], max_b = tot[1], nfl = tot[2];
     err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         ps->rho = rho;
@@ -425,7 +427,9 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, const int32_t* __res
     const double part = block_sum<PCG_NT>(acc, red);
     if (!publish_partials(blk, partials, 0, &part, 1, sync, &last)) return;
     int err = 0;
-    const double sigma = collect_slots<PCG_NT, false>(partials, blk.n, red, &err);
+    double tot[1];
+    collect_slots<PCG_NT, 1, 0u>(partials, 0, blk.n, red, &err, tot);
+    const double sigma = tot[0];
     err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         if (!(sigma > 0.0) || !(sigma <= DBL_MAX) || err)
@@ -471,17 +475,21 @@ template void launch_b_pcg_direction<double>(const BatchLaunch&, hipStream_t);
 template <typename V>
 void launch_pcg_direction(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
                           const V* s_old, V* s_new, double* partials, PcgState* st_dev,
-                          hipStream_t st)
+                          hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
 {
-    hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, tile_nbr, diag, z,
-                       s_old, s_new, partials, st_dev);
+    if (ev_start)
+        hipExtLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop,
+                              0, tile_nbr, diag, z, s_old, s_new, partials, st_dev);
+    else
+        hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, tile_nbr, diag, z,
+                           s_old, s_new, partials, st_dev);
 }
 
 template void launch_pcg_direction<float>(int, const int32_t*, const uint8_t*, const float*,
-                                          const float*, float*, double*, PcgState*, hipStream_t);
+                                          const float*, float*, double*, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_pcg_direction<double>(int, const int32_t*, const uint8_t*, const double*,
                                            const double*, double*, double*, PcgState*,
-                                           hipStream_t);
+                                           hipStream_t, hipEvent_t, hipEvent_t);
 
 template <typename V>
 struct UpdRegs {
@@ -588,8 +596,9 @@ __device__ __forceinline__ void pcg_update_body(Blk blk, const int32_t* __restri
     const double vals[2] = {prz, pmx};
     if (!publish_partials(blk, partials, pstride, vals, 2, sync, &last)) return;
     int err = 0;
-    const double rho_new = collect_slots<PCG_NT, false>(partials, blk.n, red, &err);
-    const double max_r = collect_slots<PCG_NT, true>(partials + pstride, blk.n, red, &err);
+    double tot[2];
+    collect_slots<PCG_NT, 2, 2u>(partials, pstride, blk.n, red, &err, tot);
+    const double rho_new = tot[0], max_r = tot[1];
     err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         const int it = ps->iter + 1;
@@ -639,16 +648,21 @@ template void launch_b_pcg_update<double>(const BatchLaunch&, hipStream_t);
 
 template <typename V>
 void launch_pcg_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
-                       V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st)
+                       V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st,
+                       hipEvent_t ev_start, hipEvent_t ev_stop)
 {
-    hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, tile_nbr, diag, s,
-                       x, z, partials, pstride, st_dev);
+    if (ev_start)
+        hipExtLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop, 0,
+                              tile_nbr, diag, s, x, z, partials, pstride, st_dev);
+    else
+        hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, tile_nbr, diag, s,
+                           x, z, partials, pstride, st_dev);
 }
 
 template void launch_pcg_update<float>(int, const int32_t*, const uint8_t*, const float*, float*,
-                                       float*, double*, int64_t, PcgState*, hipStream_t);
+                                       float*, double*, int64_t, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_pcg_update<double>(int, const int32_t*, const uint8_t*, const double*, double*,
-                                        double*, double*, int64_t, PcgState*, hipStream_t);
+                                        double*, double*, int64_t, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ---------------------------------------------------------------------------
 // Mixed precision (FLIP_MIXED): FP32 inner Jacobi-PCG (FP32 vectors and
@@ -716,9 +730,9 @@ __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __rest
     if (!publish_partials(blk, partials, pstride, vals, 3, sync, &last)) return;
     const int nb = blk.n;
     int err = 0;
-    const double rho = collect_slots<PNT, false>(partials, nb, red, &err);
-    const double max_b = collect_slots<PNT, true>(partials + pstride, nb, red, &err);
-    const double nfl = collect_slots<PNT, false>(partials + 2 * pstride, nb, red, &err);
+    double tot[3];
+    collect_slots<PNT, 3, 2u>(partials, pstride, nb, red, &err, tot);
+    const double rho = tot[0], max_b = tot[1], nfl = tot[2];
     err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         ps->rho = rho;
@@ -822,8 +836,9 @@ __global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ n
     const double vals[2] = {block_sum<PNT>(rz, red), block_max<PNT>(mr, red)};
     if (!publish_partials(blk, partials, pstride, vals, 2, sync, &last)) return;
     int err = 0;
-    const double rho = collect_slots<PNT, false>(partials, blk.n, red, &err);
-    const double max_r = collect_slots<PNT, true>(partials + pstride, blk.n, red, &err);
+    double tot[2];
+    collect_slots<PNT, 2, 2u>(partials, pstride, blk.n, red, &err, tot);
+    const double rho = tot[0], max_r = tot[1];
     err = __syncthreads_or(err);
     if (threadIdx.x == 0) {
         const int outer = ps->outer + 1;

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libflipmi.so")
+# the in-tree build; FLIPMI_LIB names another build of the same library
+LIB_PATH = os.environ.get("FLIPMI_LIB") or os.path.join(_PKG, "libflipmi.so")
 
 FLIP_OK = 0
 FLIP_E_INVALID = -1
