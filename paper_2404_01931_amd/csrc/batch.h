@@ -119,6 +119,7 @@ struct RhsArgs {
 
 template <typename V>
 struct DirArgs {
+    int na_hint;  // -1: the active-tile count is read from the solver state
     const int32_t* nbr;
     const uint8_t* diag;
     const V *z, *s_old;
@@ -129,6 +130,7 @@ struct DirArgs {
 
 template <typename V>
 struct UpdArgs {
+    int na_hint;  // -1: as in DirArgs
     const int32_t* nbr;
     const uint8_t* diag;
     const V* s;

@@ -253,9 +253,9 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             q.max_iters = solve_iter_cap(c);
             r[s] = q;
             for (int k = 0; k < 2; ++k) {
-                DirArgs<T> d{h->tile_nbr, h->diag, (const T*)h->z, (const T*)h->s[k], (T*)h->s[k ^ 1], h->partials,
+                DirArgs<T> d{-1, h->tile_nbr, h->diag, (const T*)h->z, (const T*)h->s[k], (T*)h->s[k ^ 1], h->partials,
                              h->ps};
-                UpdArgs<T> u{h->tile_nbr, h->diag, (const T*)h->s[k ^ 1], (T*)h->xin[0], (T*)h->z, h->partials,
+                UpdArgs<T> u{-1, h->tile_nbr, h->diag, (const T*)h->s[k ^ 1], (T*)h->xin[0], (T*)h->z, h->partials,
                              h->groups, h->ps};
                 (k ? d1 : d0)[s] = d;
                 (k ? u1 : u0)[s] = u;

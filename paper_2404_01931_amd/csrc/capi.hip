@@ -307,11 +307,11 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
             const int sc = h->scur;
             const bool timed = ((launched + it) % TIMED_PCG_EVERY) == 0;
             const int q1 = timed ? timer_pair(h, FLIP_KERNEL_PCG_DIRECTION, launched + it) : -1;
-            launch_pcg_direction<V>(h->groups, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
+            launch_pcg_direction<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
                                     (V*)h->s[sc ^ 1], h->partials, h->ps, st, q1 >= 0 ? h->ev[q1] : nullptr,
                                     q1 >= 0 ? h->ev[q1 + 1] : nullptr);
             const int q2 = timed ? timer_pair(h, FLIP_KERNEL_PCG_UPDATE, launched + it) : -1;
-            launch_pcg_update<V>(h->groups, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
+            launch_pcg_update<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
                                  h->partials, h->groups, h->ps, st, q2 >= 0 ? h->ev[q2] : nullptr,
                                  q2 >= 0 ? h->ev[q2 + 1] : nullptr);
             h->scur = sc ^ 1;
@@ -400,10 +400,17 @@ flip_status run_step(flip_handle* h, hipStream_t st)
                          project ? c.pcg_tol : 0.0, project ? max_iters : 0, st);
     timer_end(h, tq, st);
 
-    // 4. PCG (FP32 inner solves inside FP64 refinement when MIXED)
+    // 4. PCG (FP32 inner solves inside FP64 refinement when MIXED). One read
+    // of the solver state after its start gives the active-tile count (the
+    // iteration kernels then issue their first loads without waiting for the
+    // state) and skips the loop when the start already decided the solve.
+    HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    ps_host = *h->h_ps;
+    h->na = ps_host.n_active;
     int iters = 0, refinements = 0;
     if (project) {
-        for (;;) {
+        while (ps_host.done == PCG_RUNNING) {
             flip_status r = pcg_loop<T>(h, (T*)h->xin[h->xi], max_iters, st, &ps_host);
             if (r != FLIP_OK) return r;
             iters += ps_host.iter;
@@ -442,9 +449,6 @@ flip_status run_step(flip_handle* h, hipStream_t st)
             timer_end(h, tq, st);
         }
     } else {
-        HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        ps_host = *h->h_ps;
         for (int a = 0; a < 3; ++a)
             HIP_TRY(hipMemcpyAsync(h->f_new[a], h->f_star[a], s.F[a] * sizeof(T),
                                    hipMemcpyDeviceToDevice, st));

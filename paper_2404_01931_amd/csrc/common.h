@@ -116,14 +116,16 @@ void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint3
                 const uint32_t* count, const T* u, const T* v, const T* w, double scale, uint8_t* diag,
                 V* b, V* z, V* x, V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev,
                 double tol, int max_iters, hipStream_t st);
-// With ev_start/ev_stop non-null the launch records the kernel's own start
-// and end in those events (dispatch latency excluded).
+// na_hint: the active-tile count when the host knows it (its loads then start
+// before the solver state is read), else -1. With ev_start/ev_stop non-null
+// the launch records the kernel's own start and end in those events
+// (dispatch latency excluded).
 template <typename V>
-void launch_pcg_direction(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
+void launch_pcg_direction(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
                           const V* s_old, V* s_new, double* partials, PcgState* st_dev,
                           hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 template <typename V>
-void launch_pcg_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
+void launch_pcg_update(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
                        V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st,
                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // mixed precision: right-hand side in FP64 (b64), FP64 solution x64 = 0 and the

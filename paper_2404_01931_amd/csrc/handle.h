@@ -53,6 +53,7 @@ struct flip_handle {
     // host side
     int cur = 0;
     int groups = 1;  // persistent workgroups of the solver kernels
+    int na = -1;     // active tiles of the current solve, once read back
     int prev_iters = 0;
     flipmi::PcgState* h_ps = nullptr;
     hipStream_t last_stream = nullptr;

@@ -386,7 +386,7 @@ __device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tla
 
 // direction kernel: s = z + beta s_old, q = A s, sigma = s.q
 template <typename V>
-__device__ __forceinline__ void pcg_direction_body(Blk blk, const int32_t* __restrict__ nbr,
+__device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const int32_t* __restrict__ nbr,
                                                    const uint8_t* __restrict__ diag,
                                                    const V* __restrict__ z, const V* __restrict__ s_old,
                                                    V* __restrict__ s_new, double* __restrict__ partials,
@@ -396,21 +396,25 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, const int32_t* __res
     __shared__ double red[PCG_NT / WAVE];
     __shared__ bool last;
     unsigned* const sync = pcg_sync(ps);
-    if (ps->done != PCG_RUNNING) return;
-    const V beta = (V)ps->beta;
     const int tid = threadIdx.x;
     const HaloLane hl = halo_lane(tid);
+    // With the active-tile count known (na_hint >= 0) the first tiles' loads
+    // go out before the solver state arrives; a workgroup without tiles loads
+    // a valid tile it does not use.
+    const int na = na_hint >= 0 ? na_hint : ps->n_active;
     int t0, t1;
-    tile_range(blk, ps->n_active, t0, t1);
+    tile_range(blk, na, t0, t1);
+    const int tlast = t0 < t1 ? t1 - 1 : max(min(t0, na - 1), 0);
+    DirRegs<V> A, B;
+    int32_t nn = next_nbr(nbr, min(t0, tlast), hl);
+    dir_fetch(A, z, s_old, diag, min(t0, tlast), nn, tid, hl.src);
+    nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
+    dir_fetch(B, z, s_old, diag, min(t0 + 1, tlast), nn, tid, hl.src);
+    nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+    if (ps->done != PCG_RUNNING) return;
+    const V beta = (V)ps->beta;
     double acc = 0.0;
-    if (t0 < t1) {
-        const int tlast = t1 - 1;
-        DirRegs<V> A, B;
-        int32_t nn = next_nbr(nbr, t0, hl);
-        dir_fetch(A, z, s_old, diag, t0, nn, tid, hl.src);
-        nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
-        dir_fetch(B, z, s_old, diag, min(t0 + 1, tlast), nn, tid, hl.src);
-        nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+    {
         // Tiles go in pairs, both halves unconditional: a branch around the
         // second half would make the compiler wait for every outstanding
         // load at the loop head. With an odd count the last pair's second
@@ -442,7 +446,7 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, const int32_t* __res
 }
 
 template <typename V>
-__global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restrict__ nbr,
+__global__ __launch_bounds__(PCG_NT) void k_pcg_direction(int na_hint, const int32_t* __restrict__ nbr,
                                                           const uint8_t* __restrict__ diag,
                                                           const V* __restrict__ z,
                                                           const V* __restrict__ s_old,
@@ -450,7 +454,7 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_direction(const int32_t* __restr
                                                           double* __restrict__ partials,
                                                           PcgState* __restrict__ ps)
 {
-    pcg_direction_body<V>(plain_blk(), nbr, diag, z, s_old, s_new, partials, ps);
+    pcg_direction_body<V>(plain_blk(), na_hint, nbr, diag, z, s_old, s_new, partials, ps);
 }
 
 template <typename V>
@@ -459,7 +463,7 @@ __global__ __launch_bounds__(PCG_NT) void kb_pcg_direction(const DirArgs<V>* __r
 {
     Blk blk;
     const DirArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_direction_body<V>(blk, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old), as_global(a.s_new), as_global(a.partials), as_global(a.ps));
+    pcg_direction_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old), as_global(a.s_new), as_global(a.partials), as_global(a.ps));
 }
 
 template <typename V>
@@ -473,21 +477,21 @@ template void launch_b_pcg_direction<float>(const BatchLaunch&, hipStream_t);
 template void launch_b_pcg_direction<double>(const BatchLaunch&, hipStream_t);
 
 template <typename V>
-void launch_pcg_direction(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
+void launch_pcg_direction(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
                           const V* s_old, V* s_new, double* partials, PcgState* st_dev,
                           hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     if (ev_start)
         hipExtLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop,
-                              0, tile_nbr, diag, z, s_old, s_new, partials, st_dev);
+                              0, na_hint, tile_nbr, diag, z, s_old, s_new, partials, st_dev);
     else
-        hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, tile_nbr, diag, z,
-                           s_old, s_new, partials, st_dev);
+        hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, tile_nbr, diag,
+                           z, s_old, s_new, partials, st_dev);
 }
 
-template void launch_pcg_direction<float>(int, const int32_t*, const uint8_t*, const float*,
+template void launch_pcg_direction<float>(int, int, const int32_t*, const uint8_t*, const float*,
                                           const float*, float*, double*, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
-template void launch_pcg_direction<double>(int, const int32_t*, const uint8_t*, const double*,
+template void launch_pcg_direction<double>(int, int, const int32_t*, const uint8_t*, const double*,
                                            const double*, double*, double*, PcgState*,
                                            hipStream_t, hipEvent_t, hipEvent_t);
 
@@ -556,7 +560,7 @@ __device__ inline void upd_tile(V* st, UpdRegs<V>& cur, V alpha, int t, int tlas
 
 // update kernel: x += alpha s; r = n z - alpha A s; z = r / n; r.z; max|r|
 template <typename V>
-__device__ __forceinline__ void pcg_update_body(Blk blk, const int32_t* __restrict__ nbr,
+__device__ __forceinline__ void pcg_update_body(Blk blk, int na_hint, const int32_t* __restrict__ nbr,
                                                 const uint8_t* __restrict__ diag, const V* __restrict__ s,
                                                 V* __restrict__ x, V* __restrict__ z,
                                                 double* __restrict__ partials, int64_t pstride,
@@ -566,21 +570,22 @@ __device__ __forceinline__ void pcg_update_body(Blk blk, const int32_t* __restri
     __shared__ double red[PCG_NT / WAVE];
     __shared__ bool last;
     unsigned* const sync = pcg_sync(ps);
-    if (ps->done != PCG_RUNNING) return;
-    const V alpha = (V)ps->alpha;
     const int tid = threadIdx.x;
     const HaloLane hl = halo_lane(tid);
+    const int na = na_hint >= 0 ? na_hint : ps->n_active;  // as in the direction kernel
     int t0, t1;
-    tile_range(blk, ps->n_active, t0, t1);
+    tile_range(blk, na, t0, t1);
+    const int tlast = t0 < t1 ? t1 - 1 : max(min(t0, na - 1), 0);
+    UpdRegs<V> A, B;
+    int32_t nn = next_nbr(nbr, min(t0, tlast), hl);
+    upd_fetch(A, s, x, z, diag, min(t0, tlast), nn, tid, hl.src);
+    nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
+    upd_fetch(B, s, x, z, diag, min(t0 + 1, tlast), nn, tid, hl.src);
+    nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+    if (ps->done != PCG_RUNNING) return;
+    const V alpha = (V)ps->alpha;
     double rz = 0.0, rmax = 0.0;
-    if (t0 < t1) {
-        const int tlast = t1 - 1;
-        UpdRegs<V> A, B;
-        int32_t nn = next_nbr(nbr, t0, hl);
-        upd_fetch(A, s, x, z, diag, t0, nn, tid, hl.src);
-        nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
-        upd_fetch(B, s, x, z, diag, min(t0 + 1, tlast), nn, tid, hl.src);
-        nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+    {
         // tiles in unconditional pairs, as in the direction kernel
         for (int t = t0; t < t1; t += 2) {
             upd_tile(stg[0], A, alpha, t, tlast, nn, nbr, diag, s, x, z, tid, hl, rz, rmax);
@@ -618,13 +623,13 @@ __device__ __forceinline__ void pcg_update_body(Blk blk, const int32_t* __restri
 }
 
 template <typename V>
-__global__ __launch_bounds__(PCG_NT) void k_pcg_update(const int32_t* __restrict__ nbr,
+__global__ __launch_bounds__(PCG_NT) void k_pcg_update(int na_hint, const int32_t* __restrict__ nbr,
                                                        const uint8_t* __restrict__ diag,
                                                        const V* __restrict__ s, V* __restrict__ x,
                                                        V* __restrict__ z, double* __restrict__ partials,
                                                        int64_t pstride, PcgState* __restrict__ ps)
 {
-    pcg_update_body<V>(plain_blk(), nbr, diag, s, x, z, partials, pstride, ps);
+    pcg_update_body<V>(plain_blk(), na_hint, nbr, diag, s, x, z, partials, pstride, ps);
 }
 
 template <typename V>
@@ -633,7 +638,7 @@ __global__ __launch_bounds__(PCG_NT) void kb_pcg_update(const UpdArgs<V>* __rest
 {
     Blk blk;
     const UpdArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_update_body<V>(blk, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.partials), a.pstride, as_global(a.ps));
+    pcg_update_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.partials), a.pstride, as_global(a.ps));
 }
 
 template <typename V>
@@ -647,21 +652,21 @@ template void launch_b_pcg_update<float>(const BatchLaunch&, hipStream_t);
 template void launch_b_pcg_update<double>(const BatchLaunch&, hipStream_t);
 
 template <typename V>
-void launch_pcg_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
+void launch_pcg_update(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
                        V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st,
                        hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     if (ev_start)
         hipExtLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop, 0,
-                              tile_nbr, diag, s, x, z, partials, pstride, st_dev);
+                              na_hint, tile_nbr, diag, s, x, z, partials, pstride, st_dev);
     else
-        hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, tile_nbr, diag, s,
+        hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, tile_nbr, diag, s,
                            x, z, partials, pstride, st_dev);
 }
 
-template void launch_pcg_update<float>(int, const int32_t*, const uint8_t*, const float*, float*,
+template void launch_pcg_update<float>(int, int, const int32_t*, const uint8_t*, const float*, float*,
                                        float*, double*, int64_t, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
-template void launch_pcg_update<double>(int, const int32_t*, const uint8_t*, const double*, double*,
+template void launch_pcg_update<double>(int, int, const int32_t*, const uint8_t*, const double*, double*,
                                         double*, double*, int64_t, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ---------------------------------------------------------------------------
