@@ -124,7 +124,7 @@ struct DirArgs {
     const uint8_t* diag;
     const V *z, *s_old;
     V* s_new;
-    double* partials;
+    double* pslots;
     PcgState* ps;
 };
 
@@ -135,8 +135,7 @@ struct UpdArgs {
     const uint8_t* diag;
     const V* s;
     V *x, *z;
-    double* partials;
-    int64_t pstride;
+    double* pslots;
     PcgState* ps;
 };
 

@@ -253,10 +253,10 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             q.max_iters = solve_iter_cap(c);
             r[s] = q;
             for (int k = 0; k < 2; ++k) {
-                DirArgs<T> d{-1, h->tile_nbr, h->diag, (const T*)h->z, (const T*)h->s[k], (T*)h->s[k ^ 1], h->partials,
+                DirArgs<T> d{-1, h->tile_nbr, h->diag, (const T*)h->z, (const T*)h->s[k], (T*)h->s[k ^ 1], h->pslots,
                              h->ps};
-                UpdArgs<T> u{-1, h->tile_nbr, h->diag, (const T*)h->s[k ^ 1], (T*)h->xin[0], (T*)h->z, h->partials,
-                             h->groups, h->ps};
+                UpdArgs<T> u{-1, h->tile_nbr, h->diag, (const T*)h->s[k ^ 1], (T*)h->xin[0], (T*)h->z, h->pslots,
+                             h->ps};
                 (k ? d1 : d0)[s] = d;
                 (k ? u1 : u0)[s] = u;
             }
@@ -373,16 +373,19 @@ void enqueue_pre(const flip_batch* b, int ph, hipStream_t st)
     launch_b_tile_compact(L(b, S.tile_compact), st);
     launch_b_p2g<T>(L(b, S.ph[ph].p2g), st);
     launch_b_rhs<T, T>(L(b, S.rhs), st);
+    launch_b_pcg_direction<T>(L(b, S.dir[0]), st);  // D_0
 }
 
-// `iters` solver iterations (from an even iteration index), then the summaries
+// `iters` solver iterations from an even iteration index k: the pairs
+// (U_k, D_{k+1}) (each direction kernel tests the residual the update before
+// it left), then the summaries
 template <typename T>
 void enqueue_chunk(const flip_batch* b, int iters, hipStream_t st)
 {
     const Sites& S = b->S;
     for (int i = 0; i < iters; ++i) {
-        launch_b_pcg_direction<T>(L(b, S.dir[i & 1]), st);
         launch_b_pcg_update<T>(L(b, S.upd[i & 1]), st);
+        launch_b_pcg_direction<T>(L(b, S.dir[(i + 1) & 1]), st);
     }
     launch_b_summary(L(b, S.summary), st);
 }

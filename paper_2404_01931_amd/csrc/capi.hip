@@ -240,6 +240,7 @@ void carve(flip_handle* h, Carver& cv)
         h->x64[1] = cv.take<double>(s.cap * 8);
     }
     h->partials = cv.take<double>(3 * sizeof(double) * solver_groups(s.T));
+    h->pslots = cv.take<double>(PCG_SLOT_SETS * sizeof(double) * solver_groups(s.T));
     h->ps = cv.take<PcgState>(PCG_STATE_BYTES + SYNC_BYTES);
     h->staging = cv.take<void>(8 * s.C);
 }
@@ -295,26 +296,33 @@ flip_status timer_collect(flip_handle* h, hipStream_t st)
 // ---- one step -----------------------------------------------------------------
 
 // Launch PCG iterations in chunks until the device-side state says the current
-// (inner) solve is over; returns the state read at the end.
+// (inner) solve is over; returns the state read at the end. Iteration k is
+// D_k then U_k; the direction kernel tests convergence of the residual the
+// update before it left, so the sequence is D_0, then (U_k, D_{k+1}) pairs,
+// and every chunk ends with a test.
 template <typename V>
 flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgState* out)
 {
     int chunk = h->prev_iters > 2 ? h->prev_iters - 2 : 16;
     int launched = 0;
     const int first_sample = h->ev_used / 2;
+    auto direction = [&](int k) {
+        const int sc = h->scur;
+        const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_pair(h, FLIP_KERNEL_PCG_DIRECTION, k) : -1;
+        launch_pcg_direction<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
+                                (V*)h->s[sc ^ 1], h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
+                                q >= 0 ? h->ev[q + 1] : nullptr);
+    };
+    direction(0);
     for (;;) {
         for (int it = 0; it < chunk; ++it) {
+            const int k = launched + it;
             const int sc = h->scur;
-            const bool timed = ((launched + it) % TIMED_PCG_EVERY) == 0;
-            const int q1 = timed ? timer_pair(h, FLIP_KERNEL_PCG_DIRECTION, launched + it) : -1;
-            launch_pcg_direction<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
-                                    (V*)h->s[sc ^ 1], h->partials, h->ps, st, q1 >= 0 ? h->ev[q1] : nullptr,
-                                    q1 >= 0 ? h->ev[q1 + 1] : nullptr);
-            const int q2 = timed ? timer_pair(h, FLIP_KERNEL_PCG_UPDATE, launched + it) : -1;
+            const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_pair(h, FLIP_KERNEL_PCG_UPDATE, k) : -1;
             launch_pcg_update<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
-                                 h->partials, h->groups, h->ps, st, q2 >= 0 ? h->ev[q2] : nullptr,
-                                 q2 >= 0 ? h->ev[q2 + 1] : nullptr);
+                                 h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr, q >= 0 ? h->ev[q + 1] : nullptr);
             h->scur = sc ^ 1;
+            direction(k + 1);
         }
         launched += chunk;
         HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));

@@ -18,16 +18,28 @@ struct Geo {
     double dx, inv_dx;
 };
 
-// Solver state shared between the PCG kernels of one solve. Written only by
-// the last block of a reduction kernel; read by every block of the next one.
+// Solver state shared between the kernels of one solve. The start kernels
+// (right-hand side, refinement) complete their reductions in their last
+// workgroup, which writes the state.
+//
+// Iteration k is a direction kernel D_k then an update kernel U_k. Each
+// kernel's grid reduction is completed by the kernel after it: every
+// workgroup stores its partial sums (plain stores; the kernel boundary makes
+// them visible) and every workgroup of the next kernel sums all of them in
+// the same fixed order, so all take the same decision. D_k completes U_{k-1}'s
+// reduction (r.z, max|r|) and decides convergence; U_k completes D_k's
+// (s.q). A field read inside a kernel is never written by another workgroup
+// of the same kernel: D reads iter and rho_prev and writes rho, kd, max_r,
+// beta (and done when the solve ends); U reads rho and kd and writes
+// rho_prev, iter, alpha (and done on a breakdown).
 struct PcgState {
     double rho;        // r . z of the current residual
     double alpha;      // step length of the current iteration
     double beta;       // direction update factor for the next iteration
-    double max_b;      // max |b| over fluid cells
-    double max_r;      // max |r| after the last update
+    double max_b;      // max |b| over fluid cells (the inner solve's start)
+    double max_r;      // max |r| at the last convergence test
     double tol;        // relative tolerance
-    int iter;          // completed iterations
+    int iter;          // completed updates (written by U)
     int max_iters;
     int done;          // 0 running, 1 converged, 2 max iterations, 3 breakdown
     int nfluid;        // fluid cells of this solve
@@ -42,7 +54,8 @@ struct PcgState {
     int outer;         // refinements done
     int outer_done;    // 0 running, 1 converged, 2 out of refinements
     int max_outer;
-    int pad2_;
+    int kd;            // iteration of the last direction kernel (written by D)
+    double rho_prev;   // r . z of the iteration before (written by U)
 };
 
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_MAX_ITERS = 2, PCG_BREAKDOWN = 3 };
@@ -64,6 +77,13 @@ __host__ __device__ inline unsigned* pcg_sync(PcgState* ps)
 #define FLIPMI_PCG_GROUPS 1024
 #endif
 constexpr int PCG_MAX_GROUPS = FLIPMI_PCG_GROUPS;
+
+// Slots of the iteration kernels' partial sums, per solve: s.q, r.z and
+// max|r|, one double per workgroup each.
+constexpr int PCG_SLOT_SETS = 3;
+__host__ __device__ inline double* slot_sig(double* s, int) { return s; }
+__host__ __device__ inline double* slot_rho(double* s, int g) { return s + (int64_t)g; }
+__host__ __device__ inline double* slot_max(double* s, int g) { return s + 2 * (int64_t)g; }
 
 // Reduction slots hold this pattern when empty (see device_util.h).
 constexpr uint64_t SLOT_EMPTY_BITS = 0x7FF4DEADBEEF0001ull;
@@ -110,7 +130,8 @@ void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint3
 // All run `groups` persistent workgroups that split the active tiles among
 // themselves; the active-tile count is read from device memory (d_nactive for
 // the start kernels, the solver state afterwards), so nothing depends on the
-// host knowing it. `partials` holds 3 * pstride doubles, pstride >= groups.
+// host knowing it. `partials` holds 3 * pstride doubles, pstride >= groups;
+// the iteration kernels' `pslots` hold PCG_SLOT_SETS * groups doubles.
 template <typename T, typename V>
 void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint32_t* d_nactive,
                 const uint32_t* count, const T* u, const T* v, const T* w, double scale, uint8_t* diag,
@@ -122,11 +143,11 @@ void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint3
 // (dispatch latency excluded).
 template <typename V>
 void launch_pcg_direction(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
-                          const V* s_old, V* s_new, double* partials, PcgState* st_dev,
+                          const V* s_old, V* s_new, double* pslots, PcgState* st_dev,
                           hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 template <typename V>
 void launch_pcg_update(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
-                       V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st,
+                       V* z, double* pslots, PcgState* st_dev, hipStream_t st,
                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // mixed precision: right-hand side in FP64 (b64), FP64 solution x64 = 0 and the
 // start of the first FP32 inner solve (z = b64 / n rounded, x = 0, s = 0)

@@ -150,6 +150,80 @@ __device__ inline double block_max(double v, double* sh)
 }
 
 // ---------------------------------------------------------------------------
+// Completing a reduction in the next kernel. Each workgroup of a kernel
+// stores its partial sums with plain stores; the kernel boundary makes them
+// visible, and every workgroup of the next kernel combines all of them the
+// same way (each thread strides over the slots in index order, then a fixed
+// tree), so all workgroups hold the same value and no workgroup of the
+// producing kernel has to wait for the others. The result is in every thread;
+// `sh` holds 2 * NT / 64 doubles.
+// ---------------------------------------------------------------------------
+
+// Slots per thread loaded together (one round trip for up to 4 * NT slots).
+constexpr int SLOT_UNROLL = 4;
+
+template <int NT>
+__device__ inline double reduce_slots_all(const double* __restrict__ slots, int nb, double* sh)
+{
+    double acc = 0.0;
+    for (int base = threadIdx.x; base < nb; base += SLOT_UNROLL * NT) {
+        double v[SLOT_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SLOT_UNROLL; ++u) {
+            const int i = base + u * NT;
+            v[u] = i < nb ? slots[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SLOT_UNROLL; ++u) acc += v[u];
+    }
+    acc = wave_sum(acc);
+    __syncthreads();
+    if (lane_id() == 0) sh[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < NT / WAVE; ++i) s += sh[i];
+    return s;
+}
+
+// sum of sum_slots[0..nb) and max of max_slots[0..nb), loaded together
+template <int NT>
+__device__ inline void reduce_slots_all(const double* __restrict__ sum_slots, const double* __restrict__ max_slots,
+                                        int nb, double* sh, double& sum, double& mx)
+{
+    double a = 0.0, m = 0.0;
+    for (int base = threadIdx.x; base < nb; base += SLOT_UNROLL * NT) {
+        double v[SLOT_UNROLL], w[SLOT_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SLOT_UNROLL; ++u) {
+            const int i = base + u * NT;
+            v[u] = i < nb ? sum_slots[i] : 0.0;
+            w[u] = i < nb ? max_slots[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SLOT_UNROLL; ++u) {
+            a += v[u];
+            m = w[u] > m ? w[u] : m;
+        }
+    }
+    a = wave_sum(a);
+    m = wave_max(m);
+    __syncthreads();
+    if (lane_id() == 0) {
+        sh[threadIdx.x / WAVE] = a;
+        sh[NT / WAVE + threadIdx.x / WAVE] = m;
+    }
+    __syncthreads();
+    a = 0.0;
+    m = 0.0;
+    for (int i = 0; i < NT / WAVE; ++i) {
+        a += sh[i];
+        m = sh[NT / WAVE + i] > m ? sh[NT / WAVE + i] : m;
+    }
+    sum = a;
+    mx = m;
+}
+
+// ---------------------------------------------------------------------------
 // Grid-wide reduction without a device-scope fence.
 //
 // A release fence at device scope makes the issuing CU write back its XCD's

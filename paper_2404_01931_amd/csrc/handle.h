@@ -47,7 +47,8 @@ struct flip_handle {
     double* x64[2] = {nullptr, nullptr};       // FLIP_MIXED only
     int xi = 0;                                // current solution buffer
     int scur = 0;                              // current direction buffer
-    double* partials = nullptr;
+    double* partials = nullptr;  // reduction slots of the start kernels (EMPTY when idle)
+    double* pslots = nullptr;    // partial sums of the iteration kernels
     flipmi::PcgState* ps = nullptr;
     void* staging = nullptr;
     // host side

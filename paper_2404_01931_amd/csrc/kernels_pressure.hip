@@ -389,13 +389,11 @@ template <typename V>
 __device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const int32_t* __restrict__ nbr,
                                                    const uint8_t* __restrict__ diag,
                                                    const V* __restrict__ z, const V* __restrict__ s_old,
-                                                   V* __restrict__ s_new, double* __restrict__ partials,
+                                                   V* __restrict__ s_new, double* __restrict__ pslots,
                                                    PcgState* __restrict__ ps)
 {
     __shared__ alignas(16) V stg[2][STAGE2];
-    __shared__ double red[PCG_NT / WAVE];
-    __shared__ bool last;
-    unsigned* const sync = pcg_sync(ps);
+    __shared__ double red[2 * (PCG_NT / WAVE)];
     const int tid = threadIdx.x;
     const HaloLane hl = halo_lane(tid);
     // With the active-tile count known (na_hint >= 0) the first tiles' loads
@@ -411,8 +409,31 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const i
     nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
     dir_fetch(B, z, s_old, diag, min(t0 + 1, tlast), nn, tid, hl.src);
     nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+    // complete the previous update's reduction (the slots' addresses do not
+    // depend on the state, so their loads go out at once) and test its residual
+    double rho_s, max_s;
+    reduce_slots_all<PCG_NT>(slot_rho(pslots, blk.n), slot_max(pslots, blk.n), blk.n, red, rho_s, max_s);
     if (ps->done != PCG_RUNNING) return;
-    const V beta = (V)ps->beta;
+    const int k = ps->iter;
+    double rho = ps->rho, maxr = ps->max_b, beta_d = 0.0;  // k = 0: the solve's start
+    if (k > 0) {
+        rho = rho_s;
+        maxr = max_s;
+        beta_d = rho / ps->rho_prev;
+    }
+    const int state = !(maxr <= DBL_MAX) || !(fabs(rho) <= DBL_MAX) ? PCG_BREAKDOWN
+                      : maxr <= ps->tol * ps->max_b               ? PCG_CONVERGED
+                      : k >= ps->max_iters                          ? PCG_MAX_ITERS
+                                                                    : PCG_RUNNING;
+    if (blk.id == 0 && tid == 0) {
+        ps->kd = k;
+        ps->max_r = maxr;
+        ps->rho = rho;
+        ps->beta = beta_d;
+        if (state != PCG_RUNNING) ps->done = state;
+    }
+    if (state != PCG_RUNNING) return;
+    const V beta = (V)beta_d;
     double acc = 0.0;
     {
         // Tiles go in pairs, both halves unconditional: a branch around the
@@ -429,20 +450,7 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const i
         }
     }
     const double part = block_sum<PCG_NT>(acc, red);
-    if (!publish_partials(blk, partials, 0, &part, 1, sync, &last)) return;
-    int err = 0;
-    double tot[1];
-    collect_slots<PCG_NT, 1, 0u>(partials, 0, blk.n, red, &err, tot);
-    const double sigma = tot[0];
-    err = __syncthreads_or(err);
-    if (threadIdx.x == 0) {
-        if (!(sigma > 0.0) || !(sigma <= DBL_MAX) || err)
-            ps->done = PCG_BREAKDOWN;
-        else
-            ps->alpha = ps->rho / sigma;
-        if (err) ps->sync_error = 1;
-    }
-    reset_arrivals(sync);
+    if (tid == 0) slot_sig(pslots, blk.n)[blk.id] = part;  // completed by U_k
 }
 
 template <typename V>
@@ -451,10 +459,10 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_direction(int na_hint, const int
                                                           const V* __restrict__ z,
                                                           const V* __restrict__ s_old,
                                                           V* __restrict__ s_new,
-                                                          double* __restrict__ partials,
+                                                          double* __restrict__ pslots,
                                                           PcgState* __restrict__ ps)
 {
-    pcg_direction_body<V>(plain_blk(), na_hint, nbr, diag, z, s_old, s_new, partials, ps);
+    pcg_direction_body<V>(plain_blk(), na_hint, nbr, diag, z, s_old, s_new, pslots, ps);
 }
 
 template <typename V>
@@ -463,7 +471,7 @@ __global__ __launch_bounds__(PCG_NT) void kb_pcg_direction(const DirArgs<V>* __r
 {
     Blk blk;
     const DirArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_direction_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old), as_global(a.s_new), as_global(a.partials), as_global(a.ps));
+    pcg_direction_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old), as_global(a.s_new), as_global(a.pslots), as_global(a.ps));
 }
 
 template <typename V>
@@ -478,19 +486,20 @@ template void launch_b_pcg_direction<double>(const BatchLaunch&, hipStream_t);
 
 template <typename V>
 void launch_pcg_direction(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
-                          const V* s_old, V* s_new, double* partials, PcgState* st_dev,
+                          const V* s_old, V* s_new, double* pslots, PcgState* st_dev,
                           hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     if (ev_start)
         hipExtLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop,
-                              0, na_hint, tile_nbr, diag, z, s_old, s_new, partials, st_dev);
+                              0, na_hint, tile_nbr, diag, z, s_old, s_new, pslots, st_dev);
     else
         hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, tile_nbr, diag,
-                           z, s_old, s_new, partials, st_dev);
+                           z, s_old, s_new, pslots, st_dev);
 }
 
 template void launch_pcg_direction<float>(int, int, const int32_t*, const uint8_t*, const float*,
-                                          const float*, float*, double*, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
+                                          const float*, float*, double*, PcgState*, hipStream_t, hipEvent_t,
+                                          hipEvent_t);
 template void launch_pcg_direction<double>(int, int, const int32_t*, const uint8_t*, const double*,
                                            const double*, double*, double*, PcgState*,
                                            hipStream_t, hipEvent_t, hipEvent_t);
@@ -563,13 +572,10 @@ template <typename V>
 __device__ __forceinline__ void pcg_update_body(Blk blk, int na_hint, const int32_t* __restrict__ nbr,
                                                 const uint8_t* __restrict__ diag, const V* __restrict__ s,
                                                 V* __restrict__ x, V* __restrict__ z,
-                                                double* __restrict__ partials, int64_t pstride,
-                                                PcgState* __restrict__ ps)
+                                                double* __restrict__ pslots, PcgState* __restrict__ ps)
 {
     __shared__ alignas(16) V stg[2][STAGE2];
-    __shared__ double red[PCG_NT / WAVE];
-    __shared__ bool last;
-    unsigned* const sync = pcg_sync(ps);
+    __shared__ double red[2 * (PCG_NT / WAVE)];
     const int tid = threadIdx.x;
     const HaloLane hl = halo_lane(tid);
     const int na = na_hint >= 0 ? na_hint : ps->n_active;  // as in the direction kernel
@@ -582,8 +588,20 @@ __device__ __forceinline__ void pcg_update_body(Blk blk, int na_hint, const int3
     nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
     upd_fetch(B, s, x, z, diag, min(t0 + 1, tlast), nn, tid, hl.src);
     nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+    // complete the direction kernel's reduction: alpha = rho / s.q
+    const double sigma = reduce_slots_all<PCG_NT>(slot_sig(pslots, blk.n), blk.n, red);
     if (ps->done != PCG_RUNNING) return;
-    const V alpha = (V)ps->alpha;
+    const double rho = ps->rho;
+    const bool bad = !(sigma > 0.0) || !(sigma <= DBL_MAX);
+    const double alpha_d = rho / sigma;
+    if (blk.id == 0 && tid == 0) {
+        if (bad) ps->done = PCG_BREAKDOWN;
+        ps->alpha = alpha_d;
+        ps->rho_prev = rho;
+        ps->iter = ps->kd + 1;
+    }
+    if (bad) return;
+    const V alpha = (V)alpha_d;
     double rz = 0.0, rmax = 0.0;
     {
         // tiles in unconditional pairs, as in the direction kernel
@@ -598,38 +616,20 @@ __device__ __forceinline__ void pcg_update_body(Blk blk, int na_hint, const int3
     }
     const double prz = block_sum<PCG_NT>(rz, red);
     const double pmx = block_max<PCG_NT>(rmax, red);
-    const double vals[2] = {prz, pmx};
-    if (!publish_partials(blk, partials, pstride, vals, 2, sync, &last)) return;
-    int err = 0;
-    double tot[2];
-    collect_slots<PCG_NT, 2, 2u>(partials, pstride, blk.n, red, &err, tot);
-    const double rho_new = tot[0], max_r = tot[1];
-    err = __syncthreads_or(err);
-    if (threadIdx.x == 0) {
-        const int it = ps->iter + 1;
-        ps->iter = it;
-        ps->max_r = max_r;
-        if (!(max_r <= DBL_MAX) || !(fabs(rho_new) <= DBL_MAX) || err)
-            ps->done = PCG_BREAKDOWN;
-        else if (max_r <= ps->tol * ps->max_b)
-            ps->done = PCG_CONVERGED;
-        else if (it >= ps->max_iters)
-            ps->done = PCG_MAX_ITERS;
-        ps->beta = rho_new / ps->rho;
-        ps->rho = rho_new;
-        if (err) ps->sync_error = 1;
+    if (tid == 0) {  // completed by D_{k+1}
+        slot_rho(pslots, blk.n)[blk.id] = prz;
+        slot_max(pslots, blk.n)[blk.id] = pmx;
     }
-    reset_arrivals(sync);
 }
 
 template <typename V>
 __global__ __launch_bounds__(PCG_NT) void k_pcg_update(int na_hint, const int32_t* __restrict__ nbr,
                                                        const uint8_t* __restrict__ diag,
                                                        const V* __restrict__ s, V* __restrict__ x,
-                                                       V* __restrict__ z, double* __restrict__ partials,
-                                                       int64_t pstride, PcgState* __restrict__ ps)
+                                                       V* __restrict__ z, double* __restrict__ pslots,
+                                                       PcgState* __restrict__ ps)
 {
-    pcg_update_body<V>(plain_blk(), na_hint, nbr, diag, s, x, z, partials, pstride, ps);
+    pcg_update_body<V>(plain_blk(), na_hint, nbr, diag, s, x, z, pslots, ps);
 }
 
 template <typename V>
@@ -638,7 +638,7 @@ __global__ __launch_bounds__(PCG_NT) void kb_pcg_update(const UpdArgs<V>* __rest
 {
     Blk blk;
     const UpdArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_update_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.partials), a.pstride, as_global(a.ps));
+    pcg_update_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.pslots), as_global(a.ps));
 }
 
 template <typename V>
@@ -653,21 +653,21 @@ template void launch_b_pcg_update<double>(const BatchLaunch&, hipStream_t);
 
 template <typename V>
 void launch_pcg_update(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
-                       V* z, double* partials, int64_t pstride, PcgState* st_dev, hipStream_t st,
+                       V* z, double* pslots, PcgState* st_dev, hipStream_t st,
                        hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     if (ev_start)
         hipExtLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop, 0,
-                              na_hint, tile_nbr, diag, s, x, z, partials, pstride, st_dev);
+                              na_hint, tile_nbr, diag, s, x, z, pslots, st_dev);
     else
         hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, tile_nbr, diag, s,
-                           x, z, partials, pstride, st_dev);
+                           x, z, pslots, st_dev);
 }
 
 template void launch_pcg_update<float>(int, int, const int32_t*, const uint8_t*, const float*, float*,
-                                       float*, double*, int64_t, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
+                                       float*, double*, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_pcg_update<double>(int, int, const int32_t*, const uint8_t*, const double*, double*,
-                                        double*, double*, int64_t, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
+                                        double*, double*, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ---------------------------------------------------------------------------
 // Mixed precision (FLIP_MIXED): FP32 inner Jacobi-PCG (FP32 vectors and
