@@ -206,8 +206,8 @@ void carve(flip_handle* h, Carver& cv)
     const Sizes& s = h->sz;
     const size_t rb = s.rb;
     for (int q = 0; q < 2; ++q) {
-        h->pos[q] = cv.take<void>(3 * s.n * rb);
-        h->vel[q] = cv.take<void>(3 * s.n * rb);
+        h->pos[q] = cv.take<void>((3 * s.n + PARTICLE_PAD) * rb);
+        h->vel[q] = cv.take<void>((3 * s.n + PARTICLE_PAD) * rb);
         h->id[q] = cv.take<uint32_t>(4 * s.n);
     }
     h->key = cv.take<uint32_t>(4 * s.n);

@@ -90,6 +90,10 @@ constexpr uint64_t SLOT_EMPTY_BITS = 0x7FF4DEADBEEF0001ull;
 
 inline int64_t tiles_of(const Geo& g) { return (int64_t)g.tx * g.ty * g.tz; }
 
+// Elements of slack after each particle state array (x|y|z or u|v|w): the
+// particle-to-grid kernel reads eight consecutive particles from any start.
+constexpr int PARTICLE_PAD = 8;
+
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files, explicit instantiations for float
 // and double). All are asynchronous on `st`.

@@ -74,30 +74,56 @@ __device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, dou
 // loads of a whole cell are issued together, one colour phase ahead of their
 // use, instead of one particle at a time.
 constexpr int P2G_BATCH = 8;
+static_assert(P2G_BATCH <= PARTICLE_PAD, "particle reads past the last particle need slack");
 
 template <typename T>
 struct CellParticles {
     T x[P2G_BATCH], y[P2G_BATCH], z[P2G_BATCH], u[P2G_BATCH], v[P2G_BATCH], w[P2G_BATCH];
 };
 
-// Load particles s .. s + min(cnt, P2G_BATCH) - 1 (n > 0 particles in all;
-// indices are clamped into range so that every load is unconditional).
+// Eight consecutive values p[s .. s + 7] with 16-byte loads from any 4-byte
+// aligned start (a lane's particles are contiguous; one wide load per four
+// floats keeps the address unit from issuing one address per particle).
+typedef float P2GF4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef double P2GD2 __attribute__((ext_vector_type(2), aligned(8)));
+
+__device__ inline void load8(const float* __restrict__ p, uint32_t s, float (&o)[P2G_BATCH])
+{
+    const P2GF4 a = *(const P2GF4*)(p + s), b = *(const P2GF4*)(p + s + 4);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = a.z;
+    o[3] = a.w;
+    o[4] = b.x;
+    o[5] = b.y;
+    o[6] = b.z;
+    o[7] = b.w;
+}
+
+__device__ inline void load8(const double* __restrict__ p, uint32_t s, double (&o)[P2G_BATCH])
+{
+#pragma unroll
+    for (int k = 0; k < P2G_BATCH; k += 2) {
+        const P2GD2 a = *(const P2GD2*)(p + s + k);
+        o[k] = a.x;
+        o[k + 1] = a.y;
+    }
+}
+
+// Load particles s .. s + 7 of a cell's range (values past the cell's own
+// particles are not used). The state arrays are followed by PARTICLE_PAD
+// elements of slack, so the reads stay inside the workspace for any s <= n.
 template <typename T>
 __device__ inline void load_cell(CellParticles<T>& r, const T* __restrict__ px, const T* __restrict__ py,
                                  const T* __restrict__ pz, const T* __restrict__ vx, const T* __restrict__ vy,
-                                 const T* __restrict__ vz, uint32_t s, uint32_t cnt, uint32_t n)
+                                 const T* __restrict__ vz, uint32_t s)
 {
-    const uint32_t last = cnt ? s + min(cnt, (uint32_t)P2G_BATCH) - 1 : s;
-#pragma unroll
-    for (int k = 0; k < P2G_BATCH; ++k) {
-        const uint32_t q = min(min(s + (uint32_t)k, last), n - 1);
-        r.x[k] = px[q];
-        r.y[k] = py[q];
-        r.z[k] = pz[q];
-        r.u[k] = vx[q];
-        r.v[k] = vy[q];
-        r.w[k] = vz[q];
-    }
+    load8(px, s, r.x);
+    load8(py, s, r.y);
+    load8(pz, s, r.z);
+    load8(vx, s, r.u);
+    load8(vy, s, r.v);
+    load8(vz, s, r.w);
 }
 
 // the cell that lane handles in colour phase ph (ring box [r0, r1] per axis),
@@ -139,19 +165,18 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
         // ph + 2 and the particles of phase ph + 1 are loaded while phase ph
         // is splatted. Phases exchange data through LDS only, so the barrier
         // between them leaves those loads in flight.
-        const uint32_t nn = (uint32_t)n;
         int64_t c = phase_cell(g, 0, lane, rx0, ry0, rz0, rx1, ry1, rz1);
         uint32_t s_a = start[c >= 0 ? c : 0], n_a = c >= 0 ? count[c] : 0u;
         c = phase_cell(g, 1, lane, rx0, ry0, rz0, rx1, ry1, rz1);
         uint32_t s_b = start[c >= 0 ? c : 0], n_b = c >= 0 ? count[c] : 0u;
         CellParticles<T> A;
-        load_cell(A, px, py, pz, vx, vy, vz, s_a, n_a, nn);
+        load_cell(A, px, py, pz, vx, vy, vz, s_a);
 #pragma unroll 1
         for (int ph = 0; ph < 27; ++ph) {
             c = phase_cell(g, min(ph + 2, 26), lane, rx0, ry0, rz0, rx1, ry1, rz1);
             const uint32_t s_c = start[c >= 0 ? c : 0], n_c = c >= 0 ? count[c] : 0u;
             CellParticles<T> B;
-            load_cell(B, px, py, pz, vx, vy, vz, s_b, n_b, nn);
+            load_cell(B, px, py, pz, vx, vy, vz, s_b);
 #pragma unroll
             for (int k = 0; k < P2G_BATCH; ++k) {
                 if ((uint32_t)k < n_a) {
