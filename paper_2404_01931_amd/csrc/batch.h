@@ -154,6 +154,7 @@ template <typename T>
 struct G2PArgs {
     Geo g;
     int64_t n;
+    const uint32_t *start, *count;
     T *px, *py, *pz, *vx, *vy, *vz;
     const T *un, *vn, *wn, *uo, *vo, *wo;
     T alpha, dt, skin, Lx, Ly, Lz;

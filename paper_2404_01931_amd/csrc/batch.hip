@@ -155,6 +155,8 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             G2PArgs<T> q;
             q.g = g;
             q.n = n;
+            q.start = h->start;
+            q.count = h->count;
             q.px = pn;
             q.py = pn + n;
             q.pz = pn + 2 * n;
@@ -181,7 +183,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
         S.ph[ph].bin_keys = add_site(t, ak, bp, ELEM_NT);
         S.ph[ph].gather = add_site(t, ag, bp, ELEM_NT);
         S.ph[ph].p2g = add_site(t, ap, bt, 64);
-        S.ph[ph].g2p = add_site(t, a2, bp, ELEM_NT);
+        S.ph[ph].g2p = add_site(t, a2, bt, 256);
     }
     {
         std::vector<const uint32_t*> in(ns);

@@ -464,7 +464,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
 
     // 6. grid-to-particle, blend, advect, clamp
     tq = timer_begin(h, FLIP_KERNEL_G2P, st);
-    launch_g2p<T>(g, n, (T*)h->pos[h->cur], (T*)h->vel[h->cur], (const T*)h->f_new[0],
+    launch_g2p<T>(g, n, h->start, h->count, (T*)h->pos[h->cur], (T*)h->vel[h->cur], (const T*)h->f_new[0],
                   (const T*)h->f_new[1], (const T*)h->f_new[2], (const T*)h->f_old[0],
                   (const T*)h->f_old[1], (const T*)h->f_old[2], (T)c.flip_ratio, (T)c.dt,
                   (c.flags & FLIP_FLAG_ADVECT_PARTICLE_VEL) ? 1 : 0, st);

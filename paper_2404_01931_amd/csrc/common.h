@@ -172,10 +172,12 @@ template <typename T, typename V>
 void launch_project(const Geo& g, int axis, const uint32_t* count, const int32_t* tile_slot,
                     const V* p, const T* star, T* out, T scale, hipStream_t st);
 
+// grid-to-particle: one workgroup per tile; start/count is the cell hash of
+// the binned particles
 template <typename T>
-void launch_g2p(const Geo& g, int64_t n, T* pos, T* vel, const T* u_new, const T* v_new,
-                const T* w_new, const T* u_old, const T* v_old, const T* w_old, T alpha, T dt,
-                int advect_particle_vel, hipStream_t st);
+void launch_g2p(const Geo& g, int64_t n, const uint32_t* start, const uint32_t* count, T* pos, T* vel,
+                const T* u_new, const T* v_new, const T* w_new, const T* u_old, const T* v_old,
+                const T* w_old, T alpha, T dt, int advect_particle_vel, hipStream_t st);
 
 template <typename V, typename O>
 void launch_densify(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const V* src,

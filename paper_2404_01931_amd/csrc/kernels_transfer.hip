@@ -8,7 +8,7 @@
 // faces, Sec. 3.1.7), and keeps the raw transfer for the FLIP change.
 //
 // Grid-to-particle (Sec. 3.1.8) with forward-Euler advection and the skin-width
-// clamp (Sec. 3.1.3): one thread per particle in binned order.
+// clamp (Sec. 3.1.3): one workgroup per tile, face samples staged in LDS.
 #include "batch.h"
 #include "common.h"
 #include "device_util.h"
@@ -288,42 +288,45 @@ template void launch_p2g<double>(const Geo&, const double*, const double*, int64
 // grid-to-particle, blend, advect, clamp
 // ---------------------------------------------------------------------------
 
-template <typename T>
-struct Stencil8 {
-    int64_t idx[8];  // (x0,y0,z0) (x1,y0,z0) (x0,y1,z0) (x1,y1,z0) then z1
-    T tx, ty, tz;
-};
+// One 256-thread workgroup per 8x8x8 tile. The face samples the tile's
+// particles can reach are staged in LDS first, new and old values: the
+// tile's own samples plus the layer below on the two axes where samples sit
+// at cell-centre height (a particle of cell c reaches samples c and c + 1
+// along its component's axis and c - 1 .. c + 1 across it), i.e. a
+// 9 x 10 x 10 box for u, 10 x 9 x 10 for v and 10 x 10 x 9 for w, read in
+// rows. Box positions outside the domain hold the clamped edge samples, as
+// a stencil clamped at the domain edge reads. Then the tile's particles -
+// contiguous per x-row of the tile after binning - are processed with their
+// stencils read from LDS; the arithmetic is unchanged. A stencil index that
+// rounding of x / dx pushes one past the box (a particle within an ulp of a
+// cell face) carries weight 0 in FP32 and about 1e-16 in FP64; it is clamped
+// into the box.
+constexpr int G2P_NT = 256;
 
-// eight face samples around position (x, y, z) for component A, indices
-// clamped to the valid range at the domain edge
+template <int A>
+struct G2PBox {
+    static constexpr int EX = A == 0 ? 9 : 10, EY = A == 1 ? 9 : 10, EZ = A == 2 ? 9 : 10;
+    static constexpr int N = EX * EY * EZ;
+};
+constexpr int G2P_BOX = 900;  // samples per component box
+static_assert(G2PBox<0>::N == G2P_BOX && G2PBox<1>::N == G2P_BOX && G2PBox<2>::N == G2P_BOX, "box size");
+
 template <typename T, int A>
-__device__ inline Stencil8<T> stencil(const Geo& g, T x, T y, T z)
+__device__ inline void stage_box(const Geo& g, int x0, int y0, int z0, const T* __restrict__ fnew,
+                                 const T* __restrict__ fold, T* sn, T* so)
 {
+    using B = G2PBox<A>;
+    const int ox = x0 - (A != 0), oy = y0 - (A != 1), oz = z0 - (A != 2);
     const int dX = g.nx + (A == 0), dY = g.ny + (A == 1), dZ = g.nz + (A == 2);
-    // sample coordinates in double (see the particle-to-grid kernel)
-    const double gx = (double)x * g.inv_dx - (A == 0 ? 0.0 : 0.5);
-    const double gy = (double)y * g.inv_dx - (A == 1 ? 0.0 : 0.5);
-    const double gz = (double)z * g.inv_dx - (A == 2 ? 0.0 : 0.5);
-    const double fx = floor(gx), fy = floor(gy), fz = floor(gz);
-    Stencil8<T> s;
-    s.tx = (T)(gx - fx);
-    s.ty = (T)(gy - fy);
-    s.tz = (T)(gz - fz);
-    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-    const int x0 = min(max(ix, 0), dX - 1), x1 = min(max(ix + 1, 0), dX - 1);
-    const int y0 = min(max(iy, 0), dY - 1), y1 = min(max(iy + 1, 0), dY - 1);
-    const int z0 = min(max(iz, 0), dZ - 1), z1 = min(max(iz + 1, 0), dZ - 1);
-    const int64_t r00 = (int64_t)dX * (y0 + (int64_t)dY * z0), r10 = (int64_t)dX * (y1 + (int64_t)dY * z0);
-    const int64_t r01 = (int64_t)dX * (y0 + (int64_t)dY * z1), r11 = (int64_t)dX * (y1 + (int64_t)dY * z1);
-    s.idx[0] = r00 + x0;
-    s.idx[1] = r00 + x1;
-    s.idx[2] = r10 + x0;
-    s.idx[3] = r10 + x1;
-    s.idx[4] = r01 + x0;
-    s.idx[5] = r01 + x1;
-    s.idx[6] = r11 + x0;
-    s.idx[7] = r11 + x1;
-    return s;
+    for (int q = threadIdx.x; q < B::N; q += G2P_NT) {
+        const int lx = q % B::EX, ly = (q / B::EX) % B::EY, lz = q / (B::EX * B::EY);
+        const int X = min(max(ox + lx, 0), dX - 1);
+        const int Y = min(max(oy + ly, 0), dY - 1);
+        const int Z = min(max(oz + lz, 0), dZ - 1);
+        const int64_t fidx = X + (int64_t)dX * (Y + (int64_t)dY * Z);
+        sn[q] = fnew[fidx];
+        so[q] = fold[fidx];
+    }
 }
 
 template <typename T>
@@ -337,84 +340,140 @@ __device__ inline T trilerp(const T v[8], T tx, T ty, T tz)
     return lerp(lerp(c00, c10, ty), lerp(c01, c11, ty), tz);
 }
 
+// PIC value and FLIP change of component A at (x, y, z) from the staged box
 template <typename T, int A>
-__device__ inline void sample(const Geo& g, const T* __restrict__ fnew, const T* __restrict__ fold,
-                              T x, T y, T z, T& pic, T& change)
+__device__ inline void sample_box(const Geo& g, int x0, int y0, int z0, const T* sn, const T* so, T x, T y, T z,
+                                  T& pic, T& change)
 {
-    const Stencil8<T> s = stencil<T, A>(g, x, y, z);
+    using B = G2PBox<A>;
+    // sample coordinates in double (see the particle-to-grid kernel)
+    const double gx = (double)x * g.inv_dx - (A == 0 ? 0.0 : 0.5);
+    const double gy = (double)y * g.inv_dx - (A == 1 ? 0.0 : 0.5);
+    const double gz = (double)z * g.inv_dx - (A == 2 ? 0.0 : 0.5);
+    const double fx = floor(gx), fy = floor(gy), fz = floor(gz);
+    const T tx = (T)(gx - fx), ty = (T)(gy - fy), tz = (T)(gz - fz);
+    const int ix = (int)fx - (x0 - (A != 0)), iy = (int)fy - (y0 - (A != 1)), iz = (int)fz - (z0 - (A != 2));
+    const int xa = min(max(ix, 0), B::EX - 1), xb = min(max(ix + 1, 0), B::EX - 1);
+    const int ya = min(max(iy, 0), B::EY - 1), yb = min(max(iy + 1, 0), B::EY - 1);
+    const int za = min(max(iz, 0), B::EZ - 1), zb = min(max(iz + 1, 0), B::EZ - 1);
+    const int r00 = B::EX * (ya + B::EY * za), r10 = B::EX * (yb + B::EY * za);
+    const int r01 = B::EX * (ya + B::EY * zb), r11 = B::EX * (yb + B::EY * zb);
+    const int idx[8] = {r00 + xa, r00 + xb, r10 + xa, r10 + xb, r01 + xa, r01 + xb, r11 + xa, r11 + xb};
     T vn[8], dv[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        vn[q] = fnew[s.idx[q]];
-        dv[q] = vn[q] - fold[s.idx[q]];
+        vn[q] = sn[idx[q]];
+        dv[q] = vn[q] - so[idx[q]];
     }
-    pic = trilerp(vn, s.tx, s.ty, s.tz);
-    change = trilerp(dv, s.tx, s.ty, s.tz);
+    pic = trilerp(vn, tx, ty, tz);
+    change = trilerp(dv, tx, ty, tz);
 }
 
 template <typename T>
-__device__ __forceinline__ void g2p_body(Blk b, Geo g, int64_t n, T* __restrict__ px, T* __restrict__ py,
-                                         T* __restrict__ pz, T* __restrict__ vx, T* __restrict__ vy,
-                                         T* __restrict__ vz, const T* __restrict__ un,
+__device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restrict__ start,
+                                         const uint32_t* __restrict__ count, T* __restrict__ px,
+                                         T* __restrict__ py, T* __restrict__ pz, T* __restrict__ vx,
+                                         T* __restrict__ vy, T* __restrict__ vz, const T* __restrict__ un,
                                          const T* __restrict__ vn, const T* __restrict__ wn,
                                          const T* __restrict__ uo, const T* __restrict__ vo,
                                          const T* __restrict__ wo, T alpha, T dt, T skin, T Lx, T Ly,
                                          T Lz, int advect_particle_vel)
 {
-    const int64_t p = (int64_t)b.id * 256 + threadIdx.x;
-    if (p >= n) return;
-    const T x = px[p], y = py[p], z = pz[p];
-    T pic[3], ch[3];
-    sample<T, 0>(g, un, uo, x, y, z, pic[0], ch[0]);
-    sample<T, 1>(g, vn, vo, x, y, z, pic[1], ch[1]);
-    sample<T, 2>(g, wn, wo, x, y, z, pic[2], ch[2]);
-    const T v[3] = {vx[p], vy[p], vz[p]};
-    T vnew[3];
+    __shared__ T box[3][2][G2P_BOX];
+    __shared__ uint32_t row_start[64];
+    __shared__ uint32_t row_pre[65];
+    const int tid = threadIdx.x;
+    const int bx = b.id % g.tx, by = (b.id / g.tx) % g.ty, bz = b.id / (g.tx * g.ty);
+    const int x0 = bx * TILE, y0 = by * TILE, z0 = bz * TILE;
+    // the tile's particles: x-row r = (j, k) of the tile holds cells
+    // (x0 .. x0+7, y0+j, z0+k), whose particles are contiguous after binning
+    if (tid < 64) {
+        const int y = y0 + (tid & 7), zc = z0 + (tid >> 3);
+        uint32_t s0 = 0, cnt = 0;
+        if (y < g.ny && zc < g.nz) {
+            const int64_t c0 = x0 + (int64_t)g.nx * (y + (int64_t)g.ny * zc);
+            const int64_t c1 = c0 + (min(x0 + TILE, g.nx) - 1 - x0);
+            s0 = start[c0];
+            cnt = start[c1] + count[c1] - s0;
+        }
+        uint32_t incl = cnt;  // inclusive scan over the 64 rows (one wave)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const T flip = v[a] + ch[a];
-        vnew[a] = pic[a] + alpha * (flip - pic[a]);
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, WAVE);
+            if (tid >= o) incl += t;
+        }
+        row_start[tid] = s0;
+        row_pre[tid + 1] = incl;
+        if (tid == 0) row_pre[0] = 0;
     }
+    __syncthreads();
+    const uint32_t total = row_pre[64];
+    if (total == 0) return;
+    stage_box<T, 0>(g, x0, y0, z0, un, uo, box[0][0], box[0][1]);
+    stage_box<T, 1>(g, x0, y0, z0, vn, vo, box[1][0], box[1][1]);
+    stage_box<T, 2>(g, x0, y0, z0, wn, wo, box[2][0], box[2][1]);
+    __syncthreads();
     const T L[3] = {Lx, Ly, Lz};
-    const T pos[3] = {x, y, z};
-    T out[3];
+    for (uint32_t fi = tid; fi < total; fi += G2P_NT) {
+        int r = 0;  // the row holding the tile's fi-th particle
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const T adv = advect_particle_vel ? vnew[a] : pic[a];
-        T q = pos[a] + dt * adv;
-        q = q < skin ? skin : q;
-        q = q > L[a] - skin ? L[a] - skin : q;
-        out[a] = q;
+        for (int step = 32; step > 0; step >>= 1)
+            if (row_pre[r + step] <= fi) r += step;
+        const int64_t p = (int64_t)row_start[r] + (fi - row_pre[r]);
+        const T x = px[p], y = py[p], z = pz[p];
+        T pic[3], ch[3];
+        sample_box<T, 0>(g, x0, y0, z0, box[0][0], box[0][1], x, y, z, pic[0], ch[0]);
+        sample_box<T, 1>(g, x0, y0, z0, box[1][0], box[1][1], x, y, z, pic[1], ch[1]);
+        sample_box<T, 2>(g, x0, y0, z0, box[2][0], box[2][1], x, y, z, pic[2], ch[2]);
+        const T v[3] = {vx[p], vy[p], vz[p]};
+        T vnew[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T flip = v[a] + ch[a];
+            vnew[a] = pic[a] + alpha * (flip - pic[a]);
+        }
+        const T pos[3] = {x, y, z};
+        T out[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T adv = advect_particle_vel ? vnew[a] : pic[a];
+            T q = pos[a] + dt * adv;
+            q = q < skin ? skin : q;
+            q = q > L[a] - skin ? L[a] - skin : q;
+            out[a] = q;
+        }
+        px[p] = out[0];
+        py[p] = out[1];
+        pz[p] = out[2];
+        vx[p] = vnew[0];
+        vy[p] = vnew[1];
+        vz[p] = vnew[2];
     }
-    px[p] = out[0];
-    py[p] = out[1];
-    pz[p] = out[2];
-    vx[p] = vnew[0];
-    vy[p] = vnew[1];
-    vz[p] = vnew[2];
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_g2p(Geo g, int64_t n, T* __restrict__ px,
-                                             T* __restrict__ py, T* __restrict__ pz,
-                                             T* __restrict__ vx, T* __restrict__ vy,
-                                             T* __restrict__ vz, const T* __restrict__ un,
-                                             const T* __restrict__ vn, const T* __restrict__ wn,
-                                             const T* __restrict__ uo, const T* __restrict__ vo,
-                                             const T* __restrict__ wo, T alpha, T dt, T skin,
-                                             T Lx, T Ly, T Lz, int advect_particle_vel)
+__global__ __launch_bounds__(G2P_NT) void k_g2p(Geo g, const uint32_t* __restrict__ start,
+                                                const uint32_t* __restrict__ count, T* __restrict__ px,
+                                                T* __restrict__ py, T* __restrict__ pz, T* __restrict__ vx,
+                                                T* __restrict__ vy, T* __restrict__ vz,
+                                                const T* __restrict__ un, const T* __restrict__ vn,
+                                                const T* __restrict__ wn, const T* __restrict__ uo,
+                                                const T* __restrict__ vo, const T* __restrict__ wo, T alpha,
+                                                T dt, T skin, T Lx, T Ly, T Lz, int advect_particle_vel)
 {
-    g2p_body<T>(plain_blk(), g, n, px, py, pz, vx, vy, vz, un, vn, wn, uo, vo, wo, alpha, dt, skin, Lx, Ly,
-                Lz, advect_particle_vel);
+    g2p_body<T>(plain_blk(), g, start, count, px, py, pz, vx, vy, vz, un, vn, wn, uo, vo, wo, alpha, dt, skin,
+                Lx, Ly, Lz, advect_particle_vel);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void kb_g2p(const G2PArgs<T>* __restrict__ tab,
-                                              const uint32_t* __restrict__ first, int ns)
+__global__ __launch_bounds__(G2P_NT) void kb_g2p(const G2PArgs<T>* __restrict__ tab,
+                                                 const uint32_t* __restrict__ first, int ns)
 {
     Blk b;
     const G2PArgs<T>& a = batch_args(tab, first, ns, b);
-    g2p_body<T>(b, a.g, a.n, as_global(a.px), as_global(a.py), as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.un), as_global(a.vn), as_global(a.wn), as_global(a.uo), as_global(a.vo), as_global(a.wo), a.alpha,
+    g2p_body<T>(b, a.g, as_global(a.start), as_global(a.count), as_global(a.px), as_global(a.py),
+                as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.un),
+                as_global(a.vn), as_global(a.wn), as_global(a.uo), as_global(a.vo), as_global(a.wo), a.alpha,
                 a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel);
 }
 
@@ -422,29 +481,29 @@ template <typename T>
 void launch_b_g2p(const BatchLaunch& L, hipStream_t st)
 {
     if (L.blocks == 0) return;
-    hipLaunchKernelGGL(kb_g2p<T>, dim3(L.blocks), dim3(256), 0, st, (const G2PArgs<T>*)L.args, L.first, L.ns);
+    hipLaunchKernelGGL(kb_g2p<T>, dim3(L.blocks), dim3(G2P_NT), 0, st, (const G2PArgs<T>*)L.args, L.first, L.ns);
 }
 template void launch_b_g2p<float>(const BatchLaunch&, hipStream_t);
 template void launch_b_g2p<double>(const BatchLaunch&, hipStream_t);
 
 template <typename T>
-void launch_g2p(const Geo& g, int64_t n, T* pos, T* vel, const T* u_new, const T* v_new,
-                const T* w_new, const T* u_old, const T* v_old, const T* w_old, T alpha, T dt,
-                int advect_particle_vel, hipStream_t st)
+void launch_g2p(const Geo& g, int64_t n, const uint32_t* start, const uint32_t* count, T* pos, T* vel,
+                const T* u_new, const T* v_new, const T* w_new, const T* u_old, const T* v_old,
+                const T* w_old, T alpha, T dt, int advect_particle_vel, hipStream_t st)
 {
     if (n <= 0) return;
     const T skin = (T)(1e-3 * g.dx);
     const T Lx = (T)(g.nx * g.dx), Ly = (T)(g.ny * g.dx), Lz = (T)(g.nz * g.dx);
-    hipLaunchKernelGGL(k_g2p<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, n, pos,
-                       pos + n, pos + 2 * n, vel, vel + n, vel + 2 * n, u_new, v_new, w_new, u_old,
-                       v_old, w_old, alpha, dt, skin, Lx, Ly, Lz, advect_particle_vel);
+    hipLaunchKernelGGL(k_g2p<T>, dim3((unsigned)tiles_of(g)), dim3(G2P_NT), 0, st, g, start, count, pos,
+                       pos + n, pos + 2 * n, vel, vel + n, vel + 2 * n, u_new, v_new, w_new, u_old, v_old,
+                       w_old, alpha, dt, skin, Lx, Ly, Lz, advect_particle_vel);
 }
 
-template void launch_g2p<float>(const Geo&, int64_t, float*, float*, const float*, const float*,
-                                const float*, const float*, const float*, const float*, float,
-                                float, int, hipStream_t);
-template void launch_g2p<double>(const Geo&, int64_t, double*, double*, const double*,
-                                 const double*, const double*, const double*, const double*,
+template void launch_g2p<float>(const Geo&, int64_t, const uint32_t*, const uint32_t*, float*, float*,
+                                const float*, const float*, const float*, const float*, const float*,
+                                const float*, float, float, int, hipStream_t);
+template void launch_g2p<double>(const Geo&, int64_t, const uint32_t*, const uint32_t*, double*, double*,
+                                 const double*, const double*, const double*, const double*, const double*,
                                  const double*, double, double, int, hipStream_t);
 
 }  // namespace flipmi
