@@ -197,8 +197,14 @@ Sizes make_sizes(const flip_config* c, int64_t n)
     return s;
 }
 
-// Persistent workgroups of the solver kernels: one per tile up to the cap.
-int solver_groups(int64_t tiles) { return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, PCG_MAX_GROUPS)); }
+// Persistent workgroups of the solver kernels: one per PCG_TILES_PER_GROUP
+// grid tiles, at least one, at most PCG_MAX_GROUPS. A function of the grid
+// alone, so a scene's reductions run in the same order alone and in a batch.
+int solver_groups(int64_t tiles)
+{
+    const int64_t g = (tiles + PCG_TILES_PER_GROUP - 1) / PCG_TILES_PER_GROUP;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, PCG_MAX_GROUPS));
+}
 
 // One layout for both sizing and carving.
 void carve(flip_handle* h, Carver& cv)

@@ -78,6 +78,16 @@ __host__ __device__ inline unsigned* pcg_sync(PcgState* ps)
 #endif
 constexpr int PCG_MAX_GROUPS = FLIPMI_PCG_GROUPS;
 
+// Grid tiles per solver workgroup below that bound. Only a part of a scene's
+// tiles hold fluid, and every workgroup of an iteration kernel also reads the
+// partial sums of all workgroups of the kernel before it, so small scenes
+// (and batches of them) run with a few active tiles per workgroup rather
+// than one workgroup per grid tile.
+#ifndef FLIPMI_PCG_TILES_PER_GROUP
+#define FLIPMI_PCG_TILES_PER_GROUP 16
+#endif
+constexpr int PCG_TILES_PER_GROUP = FLIPMI_PCG_TILES_PER_GROUP;
+
 // Slots of the iteration kernels' partial sums, per solve: s.q, r.z and
 // max|r|, one double per workgroup each.
 constexpr int PCG_SLOT_SETS = 3;
