@@ -185,10 +185,18 @@ __device__ inline double reduce_slots_all(const double* __restrict__ slots, int 
     return s;
 }
 
-// sum of sum_slots[0..nb) and max of max_slots[0..nb), loaded together
+// sum of sum_slots[0..nb) and max of max_slots[0..nb), loaded together.
+// Returned by value: a result written through a reference to a local that a
+// caller then selects against a value from memory lets the compiler merge the
+// two into one load through a selected pointer, which moves the local to
+// scratch memory and makes that load a flat one.
+struct SumMax {
+    double sum, mx;
+};
+
 template <int NT>
-__device__ inline void reduce_slots_all(const double* __restrict__ sum_slots, const double* __restrict__ max_slots,
-                                        int nb, double* sh, double& sum, double& mx)
+__device__ inline SumMax reduce_slots_all(const double* __restrict__ sum_slots,
+                                          const double* __restrict__ max_slots, int nb, double* sh)
 {
     double a = 0.0, m = 0.0;
     for (int base = threadIdx.x; base < nb; base += SLOT_UNROLL * NT) {
@@ -219,8 +227,7 @@ __device__ inline void reduce_slots_all(const double* __restrict__ sum_slots, co
         a += sh[i];
         m = sh[NT / WAVE + i] > m ? sh[NT / WAVE + i] : m;
     }
-    sum = a;
-    mx = m;
+    return SumMax{a, m};
 }
 
 // ---------------------------------------------------------------------------

@@ -241,6 +241,17 @@ constexpr int LZ_M = LY_P + 64;
 constexpr int LZ_P = LZ_M + 64;
 constexpr int STAGE2 = LZ_P + 64;
 
+// Tiles whose loads are in flight while a direction-kernel tile is
+// evaluated (even). Each costs about ten VGPRs in FP32 and eighteen in FP64;
+// the kernel must stay within 128 VGPRs so that four workgroups fit on a CU.
+// Four or six measured no faster than two at 256^3.
+#ifndef FLIPMI_PCG_AHEAD_DIR
+#define FLIPMI_PCG_AHEAD_DIR 2
+#endif
+template <typename V>
+constexpr int pcg_ahead_dir = sizeof(V) == 4 ? FLIPMI_PCG_AHEAD_DIR : 2;
+static_assert(FLIPMI_PCG_AHEAD_DIR >= 2 && FLIPMI_PCG_AHEAD_DIR % 2 == 0, "tiles go in pairs");
+
 template <typename V>
 struct alignas(2 * sizeof(V)) Pair {
     V a, b;
@@ -353,10 +364,10 @@ __device__ inline int32_t next_nbr(const int32_t* __restrict__ nbr, int slot, co
 }
 
 // One tile of the direction kernel: stage the tile in LDS, then store it,
-// issue the loads two tiles ahead and evaluate the stencil. The barrier
-// orders LDS only, so those loads stay in flight across the next tile's
-// barrier.
-template <typename V>
+// issue the loads AH tiles ahead and evaluate the stencil. The barrier
+// orders LDS only, so those loads stay in flight across the next tiles'
+// barriers.
+template <typename V, int AH>
 __device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tlast, int32_t& nn,
                                   const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
                                   const V* __restrict__ z, const V* __restrict__ s_old, V* __restrict__ s_new,
@@ -371,17 +382,23 @@ __device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tla
     st2(st, hl.dst, h0, h1);  // x faces: the second slot is padding
     lds_barrier();
     st2(s_new, (int64_t)t * TILE_CELLS + 2 * tid, sc0, sc1);
-    const int32_t nn3 = next_nbr(nbr, min(t + 3, tlast), hl);
-    dir_fetch(cur, z, s_old, diag, min(t + 2, tlast), nn, tid, hl.src);
-    nn = nn3;
+    const int32_t nn3 = next_nbr(nbr, min(t + AH + 1, tlast), hl);
     V n0, n1;
     pair_neighbour_sums(st, tid, sc0, sc1, n0, n1);
     const V q0 = d0 ? fma((V)d0, sc0, -n0) : V(0);
     const V q1 = d1 ? fma((V)d1, sc1, -n1) : V(0);
+    const double dot = (double)sc0 * (double)q0 + (double)sc1 * (double)q1;
+    // The loads AH tiles ahead go out once nothing computed from cur's old
+    // values is live (the compiler computes s in place of the loaded z), so
+    // they can take cur's registers: a copy between registers at the loop's
+    // back edge would wait for the loads.
+    __builtin_amdgcn_sched_barrier(0);
+    dir_fetch(cur, z, s_old, diag, min(t + AH, tlast), nn, tid, hl.src);
+    nn = nn3;
     // keep the next tile's LDS stores (which wait for its loads) after this
     // tile's work
     __builtin_amdgcn_sched_barrier(0);
-    return (double)sc0 * (double)q0 + (double)sc1 * (double)q1;
+    return dot;
 }
 
 // direction kernel: s = z + beta s_old, q = A s, sigma = s.q
@@ -403,26 +420,26 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const i
     int t0, t1;
     tile_range(blk, na, t0, t1);
     const int tlast = t0 < t1 ? t1 - 1 : max(min(t0, na - 1), 0);
-    DirRegs<V> A, B;
+    constexpr int AH = pcg_ahead_dir<V>;
+    DirRegs<V> R[AH];
     int32_t nn = next_nbr(nbr, min(t0, tlast), hl);
-    dir_fetch(A, z, s_old, diag, min(t0, tlast), nn, tid, hl.src);
-    nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
-    dir_fetch(B, z, s_old, diag, min(t0 + 1, tlast), nn, tid, hl.src);
-    nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+#pragma unroll
+    for (int j = 0; j < AH; ++j) {
+        dir_fetch(R[j], z, s_old, diag, min(t0 + j, tlast), nn, tid, hl.src);
+        nn = next_nbr(nbr, min(t0 + j + 1, tlast), hl);
+    }
     // complete the previous update's reduction (the slots' addresses do not
     // depend on the state, so their loads go out at once) and test its residual
-    double rho_s, max_s;
-    reduce_slots_all<PCG_NT>(slot_rho(pslots, blk.n), slot_max(pslots, blk.n), blk.n, red, rho_s, max_s);
+    const SumMax rm = reduce_slots_all<PCG_NT>(slot_rho(pslots, blk.n), slot_max(pslots, blk.n), blk.n, red);
     if (ps->done != PCG_RUNNING) return;
     const int k = ps->iter;
-    double rho = ps->rho, maxr = ps->max_b, beta_d = 0.0;  // k = 0: the solve's start
-    if (k > 0) {
-        rho = rho_s;
-        maxr = max_s;
-        beta_d = rho / ps->rho_prev;
-    }
+    const double ps_rho = ps->rho, max_b = ps->max_b, rho_prev = ps->rho_prev;
+    // k = 0: the solve's start, from the RHS
+    const double rho = k > 0 ? rm.sum : ps_rho;
+    const double maxr = k > 0 ? rm.mx : max_b;
+    const double beta_d = k > 0 ? rho / rho_prev : 0.0;
     const int state = !(maxr <= DBL_MAX) || !(fabs(rho) <= DBL_MAX) ? PCG_BREAKDOWN
-                      : maxr <= ps->tol * ps->max_b               ? PCG_CONVERGED
+                      : maxr <= ps->tol * max_b                   ? PCG_CONVERGED
                       : k >= ps->max_iters                          ? PCG_MAX_ITERS
                                                                     : PCG_RUNNING;
     if (blk.id == 0 && tid == 0) {
@@ -435,19 +452,33 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const i
     if (state != PCG_RUNNING) return;
     const V beta = (V)beta_d;
     double acc = 0.0;
-    {
+    if (t0 < t1) {
         // Tiles go in pairs, both halves unconditional: a branch around the
         // second half would make the compiler wait for every outstanding
         // load at the loop head. With an odd count the last pair's second
         // half is the last tile again, from the values fetched before its
         // update: it stores what the first half stored and its sum is dropped.
-        for (int t = t0; t < t1; t += 2) {
-            acc += dir_tile(stg[0], A, beta, t, tlast, nn, nbr, diag, z, s_old, s_new, tid, hl);
+        // The loop body covers AH tiles so that every register set keeps its
+        // name (a copy between sets would wait for the copied loads), and has
+        // no branch inside (a merge of paths with different loads in flight
+        // makes the compiler wait for nearly all of them); the pairs left
+        // over, fewer than AH / 2, follow the loop.
+        auto pair = [&](DirRegs<V>& ra, DirRegs<V>& rb, int t) {
+            acc += dir_tile<V, AH>(stg[0], ra, beta, t, tlast, nn, nbr, diag, z, s_old, s_new, tid, hl);
             const bool real = t + 1 < t1;
-            const double v = dir_tile(stg[1], B, beta, real ? t + 1 : tlast, tlast, nn, nbr, diag, z, s_old,
-                                      s_new, tid, hl);
+            const double v = dir_tile<V, AH>(stg[1], rb, beta, real ? t + 1 : tlast, tlast, nn, nbr, diag, z,
+                                             s_old, s_new, tid, hl);
             acc += real ? v : 0.0;
+        };
+        const int pairs = (t1 - t0 + 1) >> 1;
+        int t = t0;
+        for (int q = 0; q < pairs / (AH / 2); ++q) {
+#pragma unroll
+            for (int r = 0; r < AH; r += 2, t += 2) pair(R[r], R[r + 1], t);
         }
+#pragma unroll
+        for (int r = 0; r + 2 < AH; r += 2, t += 2)
+            if (r / 2 < pairs % (AH / 2)) pair(R[r], R[r + 1], t);
     }
     const double part = block_sum<PCG_NT>(acc, red);
     if (tid == 0) slot_sig(pslots, blk.n)[blk.id] = part;  // completed by U_k
