@@ -38,14 +38,30 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kind: str, rb: int, n: int, cells: int, faces: list, fluid: float) -> float:
+def mg_coarse_cells(nx: int, ny: int, nz: int) -> int:
+    """Cells of the multigrid's coarse levels (each axis halved, ceil, until
+    no axis has more than 8 cells), stored dense."""
+    total = 0
+    while True:
+        nx, ny, nz = (nx + 1) // 2, (ny + 1) // 2, (nz + 1) // 2
+        total += nx * ny * nz
+        if max(nx, ny, nz) <= 8:
+            return total
+
+
+def algorithmic_bytes(kind: str, rb: int, n: int, cells: int, faces: list, fluid: float,
+                      coarse: int = 0) -> float:
     """Bytes the method must move per launch of each kernel (no cache re-reads).
 
     rb: bytes of the real type; n: particles; cells: grid cells; faces: face
-    counts per component; fluid: fluid cells of the solve.
+    counts per component; fluid: fluid cells of the solve; coarse: cells of the
+    multigrid's coarse levels.
     """
     F = sum(faces)
     return {
+        # one V-cycle: fine level r, n_c in (down); r, n_c in, z out (up);
+        # each coarse cell b, n_c in and b out below (down), b, n_c in and x out (up)
+        "pcg_precond": fluid * (3 * rb + 2) + coarse * (3 * rb + 2),
         "bin_keys": n * (3 * rb + 8) + 12 * cells,     # positions in; key, rank out; count fill + RMW
         "bin_scan": 8 * cells,                          # counts in, starts out
         "bin_scatter": 16 * n,                          # key, rank, start in; slot out
@@ -191,6 +207,8 @@ def main():
     ap.add_argument("--serving-no-graphs", action="store_true")
     ap.add_argument("--serving-plain-sample", type=int, default=16)
     ap.add_argument("--serving-only", action="store_true", help="skip the 256^3 benchmark")
+    ap.add_argument("--multigrid", action="store_true",
+                    help="precondition the pressure CG with the multigrid V-cycle instead of Jacobi")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scales HBM counters)")
     args = ap.parse_args()
@@ -224,8 +242,9 @@ def main():
     sc = inputs.scene(args.scene)
     if args.precision:
         sc = inputs.scene(args.scene, precision=args.precision)
+    mgflag = flip.FLIP_FLAG_MULTIGRID if args.multigrid else 0
     # throughput: a handle without kernel timing (timed launches cost extra work)
-    cfg, keep = flip.scene_config(sc)
+    cfg, keep = flip.scene_config(sc, flags=mgflag)
     progress(f"init {sc.name}")
     t = time.perf_counter()
     sim = flip.Simulation(cfg, keep)
@@ -249,7 +268,7 @@ def main():
     # kernel durations: a second handle of the same scene with kernel timing on
     # (HIP events; the solver kernels record their own start and end), stepped
     # through the same warm-up and a few more steps
-    cfg_t, keep_t = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING)
+    cfg_t, keep_t = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING | mgflag)
     sim = flip.Simulation(cfg_t, keep_t)
     if args.warmup:
         sim.step(args.warmup)
@@ -276,14 +295,18 @@ def main():
     ts = args.timing_steps
     dominant = max(kernels, key=lambda k: kernels[k]["est_total_ms"])
     kd = kernels[dominant]
-    abytes = algorithmic_bytes(dominant, rb, n, cells, faces, fluid_avg)
+    coarse = mg_coarse_cells(cfg.nx, cfg.ny, cfg.nz) if args.multigrid else 0
+    abytes = algorithmic_bytes(dominant, rb, n, cells, faces, fluid_avg, coarse)
     achieved = abytes / (kd["avg_ms"] * 1e-3) / 1e9
     traffic = traffic_for(dominant, sc.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
                 "avg_launch_ms": round(kd["avg_ms"], 5), "bytes_per_launch": abytes}
-    pcg_ms = sum(kernels[k]["est_total_ms"] for k in ("pcg_direction", "pcg_update") if k in kernels)
+    pcg_ms = sum(kernels[k]["est_total_ms"] for k in ("pcg_direction", "pcg_update", "pcg_precond")
+                 if k in kernels)
     pcg_bytes = d_cell_iter * (8 * rb + 2)
+    if args.multigrid:
+        pcg_bytes += d_cell_iter * (3 * rb + 2) + d_iter * coarse * (3 * rb + 2)
     pcg = {"iterations_per_step": (s_last.pcg_iterations_total - s_pre.pcg_iterations_total) / args.steps,
            "iterations_per_step_timing_run": d_iter / ts, "fluid_cells": round(fluid_avg),
            "last_residual_rel": s_last.max_r / s_last.max_b if s_last.max_b else 0.0,
@@ -322,7 +345,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{sc.name}: drop into pool, {sc.n}^3 MAC grid, {n} particles, "
                                f"{sc.precision.upper()}, dt=1/{round(1 / sc.dt)}, FLIP {sc.flip_ratio}, "
-                               f"Jacobi-PCG tol {sc.tol:g}"
+                               f"{'multigrid' if args.multigrid else 'Jacobi'}-PCG tol {sc.tol:g}"
                                + (f", FP64 refinement to {sc.ir_tol:g}" if sc.precision == "mixed" else ""),
                    "grid": sc.n, "particles": n, "parallelism": "single GPU"},
         "roofline": roofline,

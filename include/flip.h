@@ -80,7 +80,10 @@ enum {
     FLIP_FLAG_NO_GRAVITY = 1u,         /* skip the gravity term                            */
     FLIP_FLAG_NO_PROJECTION = 2u,      /* skip solve and projection (transfer-only steps)  */
     FLIP_FLAG_ADVECT_PARTICLE_VEL = 4u,/* advect with the blended particle velocity        */
-    FLIP_FLAG_KERNEL_TIMING = 8u       /* bracket kernel launches with HIP events           */
+    FLIP_FLAG_KERNEL_TIMING = 8u,      /* bracket kernel launches with HIP events           */
+    FLIP_FLAG_MULTIGRID = 16u          /* precondition the pressure CG with a multigrid
+                                          V-cycle instead of Jacobi (FLIP_FP32 / FLIP_FP64;
+                                          FLIP_MIXED and batches refuse it)                   */
 };
 
 typedef struct {
@@ -138,7 +141,8 @@ enum {
     FLIP_KERNEL_PCG_UPDATE = 8,    /* x += alpha s, r -= alpha A s, r.z, max|r|          */
     FLIP_KERNEL_PROJECT = 9,
     FLIP_KERNEL_G2P = 10,
-    FLIP_KERNEL_COUNT = 11
+    FLIP_KERNEL_PCG_PRECOND = 11,  /* FLIP_FLAG_MULTIGRID: one V-cycle z = M r (all levels) */
+    FLIP_KERNEL_COUNT = 12
 };
 
 typedef struct {
@@ -203,9 +207,9 @@ void flip_destroy(flip_handle* h);
  *
  * Requirements: 1 <= nscenes <= FLIP_BATCH_MAX_SCENES initialised handles,
  * all FLIP_FP32 or all FLIP_FP64 (FLIP_MIXED is not batched), none with
- * FLIP_FLAG_NO_PROJECTION or FLIP_FLAG_KERNEL_TIMING, no handle twice. The
- * handles stay owned by the caller, must outlive the batch and must not be
- * stepped by other calls while the batch steps.
+ * FLIP_FLAG_NO_PROJECTION, FLIP_FLAG_KERNEL_TIMING or FLIP_FLAG_MULTIGRID, no
+ * handle twice. The handles stay owned by the caller, must outlive the batch
+ * and must not be stepped by other calls while the batch steps.
  *
  * The launch tables live in a caller-owned device workspace
  * (flip_batch_workspace_bytes, 256-byte aligned), written once by

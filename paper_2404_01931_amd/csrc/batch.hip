@@ -307,7 +307,8 @@ flip_status check_handles(flip_handle* const* handles, int nscenes, int* prec)
         if (!h) return FLIP_E_INVALID;
         if (h->prec != FLIP_FP32 && h->prec != FLIP_FP64) return FLIP_E_INVALID;
         if (h->prec != handles[0]->prec) return FLIP_E_INVALID;
-        if (h->cfg.flags & (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING)) return FLIP_E_INVALID;
+        if (h->cfg.flags & (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING | FLIP_FLAG_MULTIGRID))
+            return FLIP_E_INVALID;
         for (int q = 0; q < s; ++q)
             if (handles[q] == h) return FLIP_E_INVALID;
     }

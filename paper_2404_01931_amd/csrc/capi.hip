@@ -143,6 +143,7 @@ flip_status validate(const flip_config* c)
     if (c->precision != FLIP_FP32 && c->precision != FLIP_FP64 && c->precision != FLIP_MIXED)
         return FLIP_E_INVALID;
     if (c->precision == FLIP_MIXED && (!(c->ir_tol > 0.0) || !std::isfinite(c->ir_tol))) return FLIP_E_INVALID;
+    if (c->precision == FLIP_MIXED && (c->flags & FLIP_FLAG_MULTIGRID)) return FLIP_E_INVALID;
     if (c->pos0) {
         if (c->n_particles < 0 || c->n_particles >= ((int64_t)1 << 31) || !c->vel0) return FLIP_E_INVALID;
     } else {
@@ -239,6 +240,26 @@ void carve(flip_handle* h, Carver& cv)
     h->xin[0] = cv.take<void>(s.cap * rb);
     h->s[0] = cv.take<void>(s.cap * rb);
     h->s[1] = cv.take<void>(s.cap * rb);
+    h->nmg = 0;
+    if (h->cfg.flags & FLIP_FLAG_MULTIGRID) {
+        // z = M r, then the coarse levels: every axis halved (ceil) until
+        // none has more than MG_BOTTOM_SIDE cells
+        h->mgz = cv.take<void>(s.cap * rb);
+        int nx = h->cfg.nx, ny = h->cfg.ny, nz = h->cfg.nz;
+        do {
+            nx = (nx + 1) / 2;
+            ny = (ny + 1) / 2;
+            nz = (nz + 1) / 2;
+            const int64_t cells = (int64_t)nx * ny * nz;
+            MgLevel& L = h->mg[h->nmg++];
+            L.nx = nx;
+            L.ny = ny;
+            L.nz = nz;
+            L.b = cv.take<void>(cells * rb);
+            L.x = cv.take<void>(cells * rb);
+            L.d = cv.take<uint8_t>(cells);
+        } while ((nx > MG_BOTTOM_SIDE || ny > MG_BOTTOM_SIDE || nz > MG_BOTTOM_SIDE) && h->nmg < MG_MAX_LEVELS);
+    }
     if (h->prec == FLIP_MIXED) {
         h->xin[1] = cv.take<void>(s.cap * rb);
         h->b64 = cv.take<double>(s.cap * 8);
@@ -315,10 +336,22 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
     auto direction = [&](int k) {
         const int sc = h->scur;
         const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_pair(h, FLIP_KERNEL_PCG_DIRECTION, k) : -1;
-        launch_pcg_direction<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->z, (const V*)h->s[sc],
+        launch_pcg_direction<V>(h->groups, h->na, h->tile_nbr, h->diag,
+                                (const V*)(h->nmg > 0 ? h->mgz : h->z), (const V*)h->s[sc],
                                 (V*)h->s[sc ^ 1], h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
                                 q >= 0 ? h->ev[q + 1] : nullptr);
     };
+    // FLIP_FLAG_MULTIGRID: h->z holds r, and z = M r goes to h->mgz; a
+    // V-cycle runs before every direction kernel
+    const bool mg = h->nmg > 0;
+    auto precondition = [&](int k) {
+        if (!mg) return;
+        const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_begin(h, FLIP_KERNEL_PCG_PRECOND, st, k) : -1;
+        launch_mg_vcycle<V>(h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag, (const V*)h->z,
+                            (V*)h->mgz, h->mg, h->nmg, h->pslots, h->ps, st);
+        timer_end(h, q, st);
+    };
+    precondition(0);
     direction(0);
     for (;;) {
         for (int it = 0; it < chunk; ++it) {
@@ -326,8 +359,10 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
             const int sc = h->scur;
             const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_pair(h, FLIP_KERNEL_PCG_UPDATE, k) : -1;
             launch_pcg_update<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
-                                 h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr, q >= 0 ? h->ev[q + 1] : nullptr);
+                                 h->pslots, h->ps, mg, st, q >= 0 ? h->ev[q] : nullptr,
+                                 q >= 0 ? h->ev[q + 1] : nullptr);
             h->scur = sc ^ 1;
+            precondition(k + 1);
             direction(k + 1);
         }
         launched += chunk;
@@ -411,8 +446,13 @@ flip_status run_step(flip_handle* h, hipStream_t st)
         launch_rhs<T, T>(g, G, h->tile_list, h->d_nactive, h->count, (const T*)h->f_star[0],
                          (const T*)h->f_star[1], (const T*)h->f_star[2], scale_b, h->diag, (T*)h->b,
                          (T*)h->z, (T*)h->xin[0], (T*)h->s[0], (T*)h->s[1], h->partials, G, h->ps,
-                         project ? c.pcg_tol : 0.0, project ? max_iters : 0, st);
+                         project ? c.pcg_tol : 0.0, project ? max_iters : 0, h->nmg > 0 ? 1 : 0, st);
     timer_end(h, tq, st);
+    // cell types of the multigrid levels, from this step's fluid cells
+    if (!MIXED && h->nmg > 0 && project) {
+        launch_mg_types_fine(g, h->tile_slot, h->diag, h->mg[0], st);
+        for (int l = 0; l + 1 < h->nmg; ++l) launch_mg_types(h->mg[l], h->mg[l + 1], st);
+    }
 
     // 4. PCG (FP32 inner solves inside FP64 refinement when MIXED). One read
     // of the solver state after its start gives the active-tile count (the
@@ -539,6 +579,7 @@ flip_status flip_workspace_bytes(const flip_config* cfg, size_t* out_bytes)
     v = particle_count(cfg, &n);
     if (v != FLIP_OK) return v;
     flip_handle tmp;
+    tmp.cfg = *cfg;
     tmp.prec = cfg->precision;
     tmp.sz = make_sizes(cfg, n);
     Carver cv(nullptr);

@@ -43,7 +43,8 @@ struct PcgState {
     int max_iters;
     int done;          // 0 running, 1 converged, 2 max iterations, 3 breakdown
     int nfluid;        // fluid cells of this solve
-    unsigned unused_;
+    int from_slots;    // 1: D_0 also takes r . z and max|r| from the slots (a
+                       // preconditioner application ran between the start and D_0)
     int n_active;      // active tiles
     int sync_error;    // a partial result never became visible (reduction aborted)
     int pad_;
@@ -150,7 +151,7 @@ template <typename T, typename V>
 void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint32_t* d_nactive,
                 const uint32_t* count, const T* u, const T* v, const T* w, double scale, uint8_t* diag,
                 V* b, V* z, V* x, V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev,
-                double tol, int max_iters, hipStream_t st);
+                double tol, int max_iters, int r_form, hipStream_t st);
 // na_hint: the active-tile count when the host knows it (its loads then start
 // before the solver state is read), else -1. With ev_start/ev_stop non-null
 // the launch records the kernel's own start and end in those events
@@ -161,7 +162,7 @@ void launch_pcg_direction(int groups, int na_hint, const int32_t* tile_nbr, cons
                           hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 template <typename V>
 void launch_pcg_update(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
-                       V* z, double* pslots, PcgState* st_dev, hipStream_t st,
+                       V* z, double* pslots, PcgState* st_dev, bool r_form, hipStream_t st,
                        hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // mixed precision: right-hand side in FP64 (b64), FP64 solution x64 = 0 and the
 // start of the first FP32 inner solve (z = b64 / n rounded, x = 0, s = 0)
@@ -177,6 +178,31 @@ void launch_ir_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, 
                       const double* x64_in, double* x64_out, const float* x_in, float* x_out,
                       float* z, float* s0, float* s1, double* partials, int64_t pstride,
                       PcgState* st_dev, hipStream_t st);
+
+// ---- multigrid preconditioner (FLIP_FLAG_MULTIGRID) --------------------------
+// One coarse level, dense with i fastest: right-hand side b and solution x of
+// its correction equation (the real type of the solve), and n_c of its fluid
+// cells (0 elsewhere).
+struct MgLevel {
+    int nx, ny, nz;
+    void* b;
+    void* x;
+    uint8_t* d;
+};
+constexpr int MG_MAX_LEVELS = 32;
+constexpr int MG_BOTTOM_SIDE = 8;      // coarsen until every axis has at most 8 cells
+constexpr int MG_BOTTOM_SWEEPS = 20;   // Jacobi sweeps on the coarsest level
+// cell types of the first coarse level from the fine n_c, and of each next one
+void launch_mg_types_fine(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const MgLevel& c,
+                          hipStream_t st);
+void launch_mg_types(const MgLevel& f, const MgLevel& c, hipStream_t st);
+// z = M r over levels lv[0..nlev) below the fine grid; the last fine kernel
+// writes the partial sums r . z and max |r| of its `groups` workgroups into
+// pslots for the next direction kernel
+template <typename V>
+void launch_mg_vcycle(int groups, int na_hint, const Geo& g, const uint32_t* tile_list, const int32_t* tile_nbr,
+                      const uint8_t* diag, const V* r, V* z, const MgLevel* lv, int nlev, double* pslots,
+                      const PcgState* ps, hipStream_t st);
 
 template <typename T, typename V>
 void launch_project(const Geo& g, int axis, const uint32_t* count, const int32_t* tile_slot,

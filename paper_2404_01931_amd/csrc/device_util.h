@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cfloat>
+#include <cmath>
+
 #include "common.h"
 
 namespace flipmi {
@@ -85,6 +88,18 @@ __device__ inline int xcd_remap(int b, int nb)
     const int q = nb >> 3, rem = nb & 7, x = b & 7, idx = b >> 3;
     return x * q + (x < rem ? x : rem) + idx;
 }
+
+// contiguous range [t0, t1) of the n_tiles active tiles for this workgroup; the
+// workgroups of one XCD get one contiguous chunk of the (spatially ordered) list
+__device__ inline void tile_range(Blk blk, int n_tiles, int& t0, int& t1)
+{
+    const int L = xcd_remap(blk.id, blk.n);
+    t0 = (int)((int64_t)n_tiles * L / blk.n);
+    t1 = (int)((int64_t)n_tiles * (L + 1) / blk.n);
+}
+
+// a finite value, or +inf for inf and NaN (so a max over values flags both)
+__device__ inline double finite_or_inf(double a) { return (a <= DBL_MAX) ? a : INFINITY; }
 
 // Floor of the exact real quotient x / dx, clamped to [0, n-1]. The first
 // estimate comes from a rounded product; it is then corrected until

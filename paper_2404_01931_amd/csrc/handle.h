@@ -47,6 +47,9 @@ struct flip_handle {
     double* x64[2] = {nullptr, nullptr};       // FLIP_MIXED only
     int xi = 0;                                // current solution buffer
     int scur = 0;                              // current direction buffer
+    void* mgz = nullptr;                       // FLIP_FLAG_MULTIGRID: z = M r
+    flipmi::MgLevel mg[flipmi::MG_MAX_LEVELS] = {};  // coarse levels below the fine grid
+    int nmg = 0;
     double* partials = nullptr;  // reduction slots of the start kernels (EMPTY when idle)
     double* pslots = nullptr;    // partial sums of the iteration kernels
     flipmi::PcgState* ps = nullptr;

@@ -35,7 +35,6 @@ constexpr int PNT = TILE_CELLS;          // threads per tile workgroup
 constexpr int HALO = 6 * TILE * TILE;    // 384 face-halo cells
 constexpr int STAGE = TILE_CELLS + HALO; // 896
 
-__device__ inline double finite_or_inf(double a) { return (a <= DBL_MAX) ? a : INFINITY; }
 
 // local index (in the neighbouring tile) of halo cell m of face f
 __device__ inline int halo_source(int f, int m)
@@ -65,14 +64,6 @@ __device__ inline V neighbour_sum(const V* st, int l)
     return ((xm + xp) + (ym + yp)) + (zm + zp);
 }
 
-// contiguous range [t0, t1) of the n_tiles active tiles for this workgroup; the
-// workgroups of one XCD get one contiguous chunk of the (spatially ordered) list
-__device__ inline void tile_range(Blk blk, int n_tiles, int& t0, int& t1)
-{
-    const int L = xcd_remap(blk.id, blk.n);
-    t0 = (int)((int64_t)n_tiles * L / blk.n);
-    t1 = (int)((int64_t)n_tiles * (L + 1) / blk.n);
-}
 
 // ---------------------------------------------------------------------------
 // right-hand side and solver start (x = 0, z = b / n, s = 0)
@@ -87,7 +78,7 @@ __device__ __forceinline__ void rhs_body(Blk blk, Geo g, const uint32_t* __restr
                                          V* __restrict__ z, V* __restrict__ x, V* __restrict__ s0,
                                          V* __restrict__ s1, double* __restrict__ partials,
                                          int64_t pstride, PcgState* __restrict__ ps, double tol,
-                                         int max_iters)
+                                         int max_iters, int r_form)
 {
     __shared__ double red[PNT / WAVE];
     __shared__ bool last;
@@ -117,7 +108,9 @@ __device__ __forceinline__ void rhs_body(Blk blk, Geo g, const uint32_t* __restr
         }
         const int64_t e = (int64_t)slot * TILE_CELLS + l;
         const V bq = (V)bv;
-        const V zq = d ? bq / (V)d : V(0);
+        // z = b / n for the Jacobi-preconditioned form; r = b when a
+        // preconditioner application follows (multigrid)
+        const V zq = r_form ? bq : (d ? bq / (V)d : V(0));
         diag[e] = (uint8_t)d;
         b[e] = bq;
         z[e] = zq;
@@ -152,6 +145,7 @@ __device__ __forceinline__ void rhs_body(Blk blk, Geo g, const uint32_t* __restr
                    : (max_iters <= 0)  ? PCG_MAX_ITERS
                                        : PCG_RUNNING;
         ps->sync_error = err;
+        ps->from_slots = r_form;
         if (err) ps->done = PCG_BREAKDOWN;
     }
     reset_arrivals(sync);
@@ -167,10 +161,11 @@ __global__ __launch_bounds__(PNT) void k_rhs(Geo g, const uint32_t* __restrict__
                                              V* __restrict__ z, V* __restrict__ x,
                                              V* __restrict__ s0, V* __restrict__ s1,
                                              double* __restrict__ partials, int64_t pstride,
-                                             PcgState* __restrict__ ps, double tol, int max_iters)
+                                             PcgState* __restrict__ ps, double tol, int max_iters,
+                                             int r_form)
 {
     rhs_body<T, V>(plain_blk(), g, tile_list, d_nactive, count, u, v, w, scale, diag, b, z, x, s0, s1,
-                   partials, pstride, ps, tol, max_iters);
+                   partials, pstride, ps, tol, max_iters, r_form);
 }
 
 template <typename T, typename V>
@@ -180,7 +175,7 @@ __global__ __launch_bounds__(PNT) void kb_rhs(const RhsArgs<T, V>* __restrict__ 
     Blk blk;
     const RhsArgs<T, V>& a = batch_args(tab, first, ns, blk);
     rhs_body<T, V>(blk, a.g, as_global(a.tile_list), as_global(a.d_nactive), as_global(a.count), as_global(a.u), as_global(a.v), as_global(a.w), (T)a.scale, as_global(a.diag), as_global(a.b), as_global(a.z),
-                   as_global(a.x), as_global(a.s0), as_global(a.s1), as_global(a.partials), a.pstride, as_global(a.ps), a.tol, a.max_iters);
+                   as_global(a.x), as_global(a.s0), as_global(a.s1), as_global(a.partials), a.pstride, as_global(a.ps), a.tol, a.max_iters, 0);
 }
 
 template <typename T, typename V>
@@ -197,21 +192,21 @@ template <typename T, typename V>
 void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint32_t* d_nactive,
                 const uint32_t* count, const T* u, const T* v, const T* w, double scale, uint8_t* diag,
                 V* b, V* z, V* x, V* s0, V* s1, double* partials, int64_t pstride, PcgState* st_dev,
-                double tol, int max_iters, hipStream_t st)
+                double tol, int max_iters, int r_form, hipStream_t st)
 {
     hipLaunchKernelGGL((k_rhs<T, V>), dim3((unsigned)groups), dim3(PNT), 0, st, g, tile_list, d_nactive,
                        count, u, v, w, (T)scale, diag, b, z, x, s0, s1, partials, pstride, st_dev,
-                       tol, max_iters);
+                       tol, max_iters, r_form);
 }
 
 template void launch_rhs<float, float>(const Geo&, int, const uint32_t*, const uint32_t*,
                                        const uint32_t*, const float*, const float*, const float*,
                                        double, uint8_t*, float*, float*, float*, float*, float*,
-                                       double*, int64_t, PcgState*, double, int, hipStream_t);
+                                       double*, int64_t, PcgState*, double, int, int, hipStream_t);
 template void launch_rhs<double, double>(const Geo&, int, const uint32_t*, const uint32_t*,
                                          const uint32_t*, const double*, const double*, const double*,
                                          double, uint8_t*, double*, double*, double*, double*,
-                                         double*, double*, int64_t, PcgState*, double, int,
+                                         double*, double*, int64_t, PcgState*, double, int, int,
                                          hipStream_t);
 
 // ---------------------------------------------------------------------------
@@ -434,9 +429,11 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const i
     if (ps->done != PCG_RUNNING) return;
     const int k = ps->iter;
     const double ps_rho = ps->rho, max_b = ps->max_b, rho_prev = ps->rho_prev;
-    // k = 0: the solve's start, from the RHS
-    const double rho = k > 0 ? rm.sum : ps_rho;
-    const double maxr = k > 0 ? rm.mx : max_b;
+    // k = 0: the solve's start, from the RHS (or, after a preconditioner
+    // application, from its slots)
+    const bool slots = k > 0 || ps->from_slots != 0;
+    const double rho = slots ? rm.sum : ps_rho;
+    const double maxr = slots ? rm.mx : max_b;
     const double beta_d = k > 0 ? rho / rho_prev : 0.0;
     const int state = !(maxr <= DBL_MAX) || !(fabs(rho) <= DBL_MAX) ? PCG_BREAKDOWN
                       : maxr <= ps->tol * max_b                   ? PCG_CONVERGED
@@ -558,20 +555,26 @@ __device__ inline void upd_fetch(UpdRegs<V>& r, const V* __restrict__ s, const V
 }
 
 // x += alpha s; r = n z - alpha q; z = r / n for one cell (n = 0: not fluid,
-// x and z stay 0); accumulates r.z and max|r|
-template <typename V>
+// x and z stay 0); accumulates r.z and max|r|. With RF the stored vector is
+// r itself (r -= alpha q; a preconditioner application follows, which also
+// forms the sums).
+template <typename V, bool RF>
 __device__ inline void upd_cell(int d, V sc, V xc, V zc, V nsum, V alpha, V& xn, V& zn, double& rz,
                                 double& rmax)
 {
     const V q = fma((V)d, sc, -nsum);  // same rounding as the direction kernel
     xn = fma(alpha, sc, xc);
+    if (RF) {
+        zn = d ? fma(-alpha, q, zc) : V(0);
+        return;
+    }
     const V r = d ? fma((V)d, zc, -alpha * q) : V(0);
     zn = d ? r / (V)d : V(0);
     rz += (double)r * (double)zn;
     rmax = fmax(rmax, finite_or_inf(fabs((double)r)));
 }
 
-template <typename V>
+template <typename V, bool RF>
 __device__ inline void upd_tile(V* st, UpdRegs<V>& cur, V alpha, int t, int tlast, int32_t& nn,
                                 const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
                                 const V* __restrict__ s, V* __restrict__ x, V* __restrict__ z, int tid,
@@ -590,8 +593,8 @@ __device__ inline void upd_tile(V* st, UpdRegs<V>& cur, V alpha, int t, int tlas
     V n0, n1;
     pair_neighbour_sums(st, tid, sc.a, sc.b, n0, n1);
     V x0, x1, z0, z1;
-    upd_cell(d0, sc.a, xc.a, zc.a, n0, alpha, x0, z0, rz, rmax);
-    upd_cell(d1, sc.b, xc.b, zc.b, n1, alpha, x1, z1, rz, rmax);
+    upd_cell<V, RF>(d0, sc.a, xc.a, zc.a, n0, alpha, x0, z0, rz, rmax);
+    upd_cell<V, RF>(d1, sc.b, xc.b, zc.b, n1, alpha, x1, z1, rz, rmax);
     const int64_t e = (int64_t)t * TILE_CELLS + 2 * tid;
     st2(x, e, x0, x1);
     st2(z, e, z0, z1);
@@ -599,7 +602,7 @@ __device__ inline void upd_tile(V* st, UpdRegs<V>& cur, V alpha, int t, int tlas
 }
 
 // update kernel: x += alpha s; r = n z - alpha A s; z = r / n; r.z; max|r|
-template <typename V>
+template <typename V, bool RF>
 __device__ __forceinline__ void pcg_update_body(Blk blk, int na_hint, const int32_t* __restrict__ nbr,
                                                 const uint8_t* __restrict__ diag, const V* __restrict__ s,
                                                 V* __restrict__ x, V* __restrict__ z,
@@ -637,14 +640,16 @@ __device__ __forceinline__ void pcg_update_body(Blk blk, int na_hint, const int3
     {
         // tiles in unconditional pairs, as in the direction kernel
         for (int t = t0; t < t1; t += 2) {
-            upd_tile(stg[0], A, alpha, t, tlast, nn, nbr, diag, s, x, z, tid, hl, rz, rmax);
+            upd_tile<V, RF>(stg[0], A, alpha, t, tlast, nn, nbr, diag, s, x, z, tid, hl, rz, rmax);
             const bool real = t + 1 < t1;
             double rz2 = 0.0, rmax2 = 0.0;
-            upd_tile(stg[1], B, alpha, real ? t + 1 : tlast, tlast, nn, nbr, diag, s, x, z, tid, hl, rz2, rmax2);
+            upd_tile<V, RF>(stg[1], B, alpha, real ? t + 1 : tlast, tlast, nn, nbr, diag, s, x, z, tid, hl, rz2,
+                            rmax2);
             rz += real ? rz2 : 0.0;
             rmax = real ? fmax(rmax, rmax2) : rmax;
         }
     }
+    if (RF) return;  // the preconditioner application forms the sums
     const double prz = block_sum<PCG_NT>(rz, red);
     const double pmx = block_max<PCG_NT>(rmax, red);
     if (tid == 0) {  // completed by D_{k+1}
@@ -653,14 +658,14 @@ __device__ __forceinline__ void pcg_update_body(Blk blk, int na_hint, const int3
     }
 }
 
-template <typename V>
+template <typename V, bool RF>
 __global__ __launch_bounds__(PCG_NT) void k_pcg_update(int na_hint, const int32_t* __restrict__ nbr,
                                                        const uint8_t* __restrict__ diag,
                                                        const V* __restrict__ s, V* __restrict__ x,
                                                        V* __restrict__ z, double* __restrict__ pslots,
                                                        PcgState* __restrict__ ps)
 {
-    pcg_update_body<V>(plain_blk(), na_hint, nbr, diag, s, x, z, pslots, ps);
+    pcg_update_body<V, RF>(plain_blk(), na_hint, nbr, diag, s, x, z, pslots, ps);
 }
 
 template <typename V>
@@ -669,7 +674,7 @@ __global__ __launch_bounds__(PCG_NT) void kb_pcg_update(const UpdArgs<V>* __rest
 {
     Blk blk;
     const UpdArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_update_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.pslots), as_global(a.ps));
+    pcg_update_body<V, false>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.pslots), as_global(a.ps));
 }
 
 template <typename V>
@@ -684,21 +689,22 @@ template void launch_b_pcg_update<double>(const BatchLaunch&, hipStream_t);
 
 template <typename V>
 void launch_pcg_update(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
-                       V* z, double* pslots, PcgState* st_dev, hipStream_t st,
+                       V* z, double* pslots, PcgState* st_dev, bool r_form, hipStream_t st,
                        hipEvent_t ev_start, hipEvent_t ev_stop)
 {
+    auto kern = r_form ? k_pcg_update<V, true> : k_pcg_update<V, false>;
     if (ev_start)
-        hipExtLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop, 0,
-                              na_hint, tile_nbr, diag, s, x, z, pslots, st_dev);
+        hipExtLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop, 0, na_hint,
+                              tile_nbr, diag, s, x, z, pslots, st_dev);
     else
-        hipLaunchKernelGGL(k_pcg_update<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, tile_nbr, diag, s,
-                           x, z, pslots, st_dev);
+        hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, tile_nbr, diag, s, x, z,
+                           pslots, st_dev);
 }
 
 template void launch_pcg_update<float>(int, int, const int32_t*, const uint8_t*, const float*, float*,
-                                       float*, double*, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
+                                       float*, double*, PcgState*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_pcg_update<double>(int, int, const int32_t*, const uint8_t*, const double*, double*,
-                                        double*, double*, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
+                                        double*, double*, PcgState*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 
 // ---------------------------------------------------------------------------
 // Mixed precision (FLIP_MIXED): FP32 inner Jacobi-PCG (FP32 vectors and
@@ -787,6 +793,7 @@ __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __rest
         ps->outer = 0;
         ps->max_outer = max_outer;
         ps->outer_done = (max_b == 0.0) ? 1 : 0;
+        ps->from_slots = 0;
         ps->done = !(max_b <= DBL_MAX) ? PCG_BREAKDOWN
                    : (max_b == 0.0)    ? PCG_CONVERGED
                    : (max_iters <= 0)  ? PCG_MAX_ITERS

@@ -30,6 +30,7 @@ FLIP_FLAG_NO_GRAVITY = 1
 FLIP_FLAG_NO_PROJECTION = 2
 FLIP_FLAG_ADVECT_PARTICLE_VEL = 4
 FLIP_FLAG_KERNEL_TIMING = 8
+FLIP_FLAG_MULTIGRID = 16
 
 FLIP_FIELD_POS = 0
 FLIP_FIELD_VEL = 1
@@ -44,7 +45,7 @@ FLIP_FIELD_RHS = 9
 FLIP_FIELD_PRESSURE = 10
 
 KERNEL_NAMES = ["bin_keys", "bin_scan", "bin_scatter", "bin_gather", "tiles", "p2g", "rhs",
-                "pcg_direction", "pcg_update", "project", "g2p"]
+                "pcg_direction", "pcg_update", "project", "g2p", "pcg_precond"]
 FLIP_KERNEL_COUNT = len(KERNEL_NAMES)
 
 FLIP_BATCH_MAX_SCENES = 256

@@ -58,6 +58,27 @@ def test_status_strings_and_argument_errors_without_gpu():
     cfg, keep = flip.make_config((8, 8, 8), 1 / 8, 1 / 240, flip_ratio=1.5)
     with pytest.raises(flip.FlipError):
         flip.flip_workspace_bytes(cfg)
+    # the multigrid preconditioner is not combined with mixed precision
+    cfg, keep = flip.make_config((8, 8, 8), 1 / 8, 1 / 240, precision=flip.FLIP_MIXED,
+                                 flags=flip.FLIP_FLAG_MULTIGRID)
+    with pytest.raises(flip.FlipError) as e:
+        flip.flip_workspace_bytes(cfg)
+    assert e.value.status == flip.FLIP_E_INVALID
+
+
+def test_multigrid_workspace_holds_the_coarse_levels():
+    from paper_2404_01931_amd import flip, inputs
+
+    sc = inputs.scene("drop64")
+    cfg, keep = flip.scene_config(sc)
+    plain = flip.flip_workspace_bytes(cfg)
+    cfg, keep = flip.scene_config(sc, flags=flip.FLIP_FLAG_MULTIGRID)
+    mg = flip.flip_workspace_bytes(cfg)
+    # z = M r over the fine tiles (64^3 cells, 4 B) plus levels 32^3, 16^3 and 8^3
+    # of b and x (4 B each) and n_c (1 B)
+    coarse = sum(n ** 3 for n in (32, 16, 8))
+    assert mg - plain >= 64 ** 3 * 4 + coarse * 9
+    assert mg - plain <= 64 ** 3 * 4 + coarse * 9 + 16 * 256
 
 
 def test_workspace_size_is_pure_and_grows_with_the_problem():

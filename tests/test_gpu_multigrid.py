@@ -1,0 +1,148 @@
+"""GPU: the pressure solve preconditioned by the multigrid V-cycle
+(FLIP_FLAG_MULTIGRID), through the C ABI, against the oracle.
+
+The preconditioner changes how the conjugate-gradient iteration reaches the
+solution, not the system it solves (paper Sec. 3.1.7), so the bar is the one
+the Jacobi path meets: the recursive residual within the configured tolerance,
+the true residual of the returned pressure evaluated in FP64 by the oracle,
+the pressure against the oracle's exact solve of the GPU's own system, and
+the whole step within 1e-4 (norm-wise relative) of the oracle's step with an
+exact solve. The iteration count must drop well below the Jacobi path's on
+the same state.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2404_01931_amd import flip, inputs
+from tests.gpu_util import grid_of, l2_rel, log, params_of, state
+
+pytestmark = pytest.mark.gpu
+
+MG = flip.FLIP_FLAG_MULTIGRID
+
+
+def _case(name, flags):
+    if name == "dam32_fp64":
+        return flip.scene_config(inputs.scene("dam32"), flags=flags)
+    if name == "drop64_fp32":
+        return flip.scene_config(inputs.scene("drop64"), flags=flags)
+    if name == "drop64_fp64":
+        return flip.scene_config(inputs.scene("drop64"), precision=flip.FLIP_FP64, flags=flags)
+    if name == "ragged_fp32":
+        # 20 x 12 x 17 cells: odd coarse levels (10x6x9, 5x3x5) and tiles past the domain
+        shape, dx = (20, 12, 17), 1.0 / 20
+        L = np.array(shape) * dx
+        pos, vel = inputs.random_particles(shape, 9000, seed=21, lo=(0.0, 0.0, 0.0), hi=(0.55, 0.4, L[2]), dx=dx)
+        pos = np.clip(pos, 0.0, L[:, None] * (1 - 1e-6)).astype(np.float32).astype(np.float64)
+        vel = (0.5 * vel).astype(np.float32).astype(np.float64)
+        return flip.make_config(shape, dx, 1 / 240, precision=flip.FLIP_FP32, pcg_tol=1e-6, pos0=pos, vel0=vel,
+                                flags=flags)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("case", ["dam32_fp64", "drop64_fp32", "drop64_fp64", "ragged_fp32"])
+def test_multigrid_solve_and_step_against_oracle(orc, case):
+    log(f"[mg] one step {case}")
+    # Jacobi on the same state, for the iteration count
+    cfg, keep = _case(case, 0)
+    jac = flip.Simulation(cfg, keep)
+    jac.step(1)
+    it_jacobi = jac.stats().pcg_iterations
+    jac.close()
+
+    cfg, keep = _case(case, MG)
+    sim = flip.Simulation(cfg, keep)
+    g = grid_of(sim)
+    pos0, vel0, ids0 = state(sim)
+    sim.step(1)
+    st = sim.stats()
+    fp64 = sim.cfg.precision == flip.FLIP_FP64
+    key, count, start, perm = O.bin_particles(g, pos0)
+    fluid = O.fluid_flags(g, count)
+    b = sim.read(flip.FLIP_FIELD_RHS).astype(np.float64)
+    p = sim.read(flip.FLIP_FIELD_PRESSURE).astype(np.float64)
+    assert st.pcg_status == 0
+    assert st.max_r <= cfg.pcg_tol * st.max_b * (1 + 1e-12)
+    assert np.all(p[fluid == 0] == 0)
+    true_rel = np.abs(b - orc.apply_A(g, fluid, p)).max() / np.abs(b).max()
+    exact = orc.pcg(g, fluid, b, 1e-13, 100000)
+    perr = l2_rel(p, exact.p)
+    log(f"[mg] {case}: iterations {st.pcg_iterations} (Jacobi {it_jacobi}), true residual {true_rel:.3e}, "
+        f"|p - p_exact| / |p_exact| = {perr:.3e}")
+    assert true_rel <= (1.01e-6 if fp64 else 1e-3)
+    assert perr <= (1e-6 if fp64 else 1e-4)
+    assert 3 * st.pcg_iterations <= it_jacobi
+
+    pos1, vel1, ids1 = state(sim)
+    res = orc.step(params_of(sim), pos0, vel0, ids0)
+    assert np.array_equal(res.ids, ids1)
+    ev = l2_rel(vel1, res.vel)
+    log(f"[mg] {case}: step velocity error l2 {ev:.3e}")
+    assert ev <= 1e-4
+    sim.close()
+
+
+@pytest.mark.parametrize("case,steps", [("drop64_fp32", 5), ("dam32_fp64", 10)])
+def test_multigrid_shadowed_steps(orc, case, steps):
+    """Every step, the oracle restarts from the GPU's state."""
+    log(f"[mg] shadow {case} x{steps}")
+    cfg, keep = _case(case, MG)
+    sim = flip.Simulation(cfg, keep)
+    prm = params_of(sim)
+    worst = 0.0
+    for s in range(steps):
+        pos0, vel0, ids0 = state(sim)
+        sim.step(1)
+        pos1, vel1, ids1 = state(sim)
+        res = orc.step(prm, pos0, vel0, ids0)
+        assert np.array_equal(res.ids, ids1)
+        e = l2_rel(vel1, res.vel)
+        worst = max(worst, e)
+        assert e <= 1e-4, (s, e)
+    log(f"[mg] shadow {case}: worst velocity l2 error {worst:.3e}")
+    sim.close()
+
+
+def test_multigrid_runs_are_bitwise_identical():
+    log("[mg] determinism")
+    outs = []
+    for _ in range(2):
+        cfg, keep = _case("drop64_fp32", MG)
+        sim = flip.Simulation(cfg, keep)
+        sim.step(3)
+        outs.append((sim.read(flip.FLIP_FIELD_POS), sim.read(flip.FLIP_FIELD_VEL),
+                     sim.read(flip.FLIP_FIELD_PRESSURE)))
+        sim.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_multigrid_degenerate_grids(orc):
+    log("[mg] degenerate inputs")
+    # no particles: nothing to solve
+    cfg, keep = flip.make_config((8, 8, 8), 1 / 8, 1 / 240, pos0=np.zeros((3, 0)), vel0=np.zeros((3, 0)), flags=MG)
+    sim = flip.Simulation(cfg, keep)
+    sim.step(2)
+    assert sim.stats().pcg_iterations == 0
+    sim.close()
+    # one particle on a 3 x 1 x 2 grid (a single coarse level of 2 x 1 x 1)
+    cfg, keep = flip.make_config((3, 1, 2), 1 / 3, 1 / 240, pos0=np.array([[0.5], [0.1], [0.3]]),
+                                 vel0=np.array([[0.1], [0.0], [-0.2]]), flags=MG)
+    sim = flip.Simulation(cfg, keep)
+    p0, v0, i0 = state(sim)
+    sim.step(1)
+    _, v1, _ = state(sim)
+    res = orc.step(params_of(sim), p0, v0, i0)
+    assert l2_rel(v1, res.vel) <= 1e-4
+    sim.close()
+
+
+def test_batch_refuses_multigrid_handles():
+    log("[mg] batch refusal")
+    cfg, keep = _case("drop64_fp32", MG)
+    sim = flip.Simulation(cfg, keep)
+    with pytest.raises(flip.FlipError) as e:
+        flip.Batch([sim])
+    assert e.value.status == flip.FLIP_E_INVALID
+    sim.close()
