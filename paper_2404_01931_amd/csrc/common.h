@@ -196,6 +196,13 @@ constexpr int MG_BOTTOM_SWEEPS = 20;   // Jacobi sweeps on the coarsest level
 void launch_mg_types_fine(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const MgLevel& c,
                           hipStream_t st);
 void launch_mg_types(const MgLevel& f, const MgLevel& c, hipStream_t st);
+// the fine-level kernels of the V-cycle (up = false: smoothing and
+// restriction of r into lv0.b; up = true: prolongation of lv0.x, smoothing
+// into z and the partial sums r . z, max |r| in pslots)
+template <typename V>
+void launch_mg_fine(bool up, int groups, int na_hint, const Geo& g, const uint32_t* tile_list,
+                    const int32_t* tile_nbr, const uint8_t* diag, const V* r, const MgLevel& lv0, V* z,
+                    double* pslots, const PcgState* ps, hipStream_t st);
 // z = M r over levels lv[0..nlev) below the fine grid; the last fine kernel
 // writes the partial sums r . z and max |r| of its `groups` workgroups into
 // pslots for the next direction kernel

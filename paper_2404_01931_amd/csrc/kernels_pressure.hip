@@ -273,6 +273,7 @@ __device__ inline void st2(V* __restrict__ p, int64_t i, V a, V b)
 // vector loads of the data.
 struct HaloLane {
     int f, f_lo, f_hi, src, dst;
+    int hx, hy, hz;  // position of the staged halo cell relative to the tile's first cell
     bool hi, upper;
 };
 
@@ -286,17 +287,26 @@ __device__ inline HaloLane halo_lane(int tid)
         h.src = li & ~1;
         h.hi = (li & 1) != 0;
         h.dst = (h.f == 0 ? LX_M : LX_P) + 2 * (a + 8 * b);
+        h.hx = h.f == 0 ? -1 : TILE;
+        h.hy = a;
+        h.hz = b;
     } else if (tid < 192) {  // y faces: lane m stages cells (2 (m & 3) + {0, 1}, y, m >> 2)
         const int m = tid & 31, x = 2 * (m & 3), zz = m >> 2;
         h.f = tid < 160 ? 2 : 3;
         h.src = x + 8 * (h.f == 2 ? 7 : 0) + 64 * zz;
         h.dst = (h.f == 2 ? LY_M : LY_P) + x + 8 * zz;
+        h.hx = x;
+        h.hy = h.f == 2 ? -1 : TILE;
+        h.hz = zz;
         h.hi = false;
     } else {  // z faces: lane m stages cells (2 (m & 3) + {0, 1}, m >> 2, z)
         const int m = tid & 31, x = 2 * (m & 3), yy = m >> 2;
         h.f = tid < 224 ? 4 : 5;
         h.src = x + 8 * yy + 64 * (h.f == 4 ? 7 : 0);
         h.dst = (h.f == 4 ? LZ_M : LZ_P) + x + 8 * yy;
+        h.hx = x;
+        h.hy = yy;
+        h.hz = h.f == 4 ? -1 : TILE;
         h.hi = false;
     }
     h.f_lo = __builtin_amdgcn_readfirstlane(h.f);
@@ -531,6 +541,219 @@ template void launch_pcg_direction<float>(int, int, const int32_t*, const uint8_
 template void launch_pcg_direction<double>(int, int, const int32_t*, const uint8_t*, const double*,
                                            const double*, double*, double*, PcgState*,
                                            hipStream_t, hipEvent_t, hipEvent_t);
+
+// ---------------------------------------------------------------------------
+// Multigrid V-cycle, fine level (FLIP_FLAG_MULTIGRID): the two kernels that
+// touch the solver's tile layout, built like the direction kernel (cell pair
+// per thread, one staged halo pair per lane, LDS-only barriers, the tiles two
+// ahead in registers, unconditional tile pairs). The V-cycle and its coarse
+// levels are described with the coarse kernels; here:
+//   down: u = w r / n;  t = r - A u = (1 - w) r + sum of u over the fluid
+//         neighbours;  level-1 b = (sum of t over the 2x2x2 children) / 2
+//   up:   y = w r / n + x1(parent);  z = y + w (r - A y) / n, with the
+//         partial sums r . z and max |r| for the next direction kernel.
+// A pair of x-adjacent cells (2t, 2t + 1) has one parent, and so has the
+// halo pair of a y or z face; an x-face halo lane keeps one cell.
+// ---------------------------------------------------------------------------
+
+template <typename V>
+struct MgRegs {
+    Pair<V> r, hr;   // the pair's and the halo pair's r
+    uint32_t d, hd;  // their n_c bytes
+    V e, he;         // up: level-1 solution at the pair's and the halo cell's parent
+    uint32_t tile;   // grid index of the tile these values belong to
+    bool m;          // the halo's neighbour tile exists
+};
+
+__device__ inline int mg_clamp(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+// tile index of the active tile in `slot` (scalar)
+__device__ inline uint32_t next_tile(const uint32_t* __restrict__ tile_list, int slot) { return tile_list[slot]; }
+
+template <typename V, bool UP>
+__device__ inline void mg_fetch(MgRegs<V>& q, const V* __restrict__ r, const uint8_t* __restrict__ diag,
+                                const V* __restrict__ cx, const Geo& g, const MgLevel& c, int slot, int32_t nslot,
+                                uint32_t tile, int tid, const HaloLane& hl)
+{
+    const int64_t e = (int64_t)slot * TILE_CELLS + 2 * tid;
+    const int64_t h = nslot >= 0 ? (int64_t)nslot * TILE_CELLS + hl.src : e;
+    q.r = ld2(r, e);
+    q.hr = ld2(r, h);
+    q.d = *(const uint16_t*)(diag + e);
+    q.hd = *(const uint16_t*)(diag + h);
+    q.m = nslot >= 0;
+    q.tile = tile;
+    if (UP) {
+        const int ti = (int)(tile % (uint32_t)g.tx), tj = (int)((tile / (uint32_t)g.tx) % (uint32_t)g.ty);
+        const int tk = (int)(tile / ((uint32_t)g.tx * (uint32_t)g.ty));
+        const int l0 = 2 * tid;
+        const int gi = TILE * ti + (l0 & 7), gj = TILE * tj + ((l0 >> 3) & 7), gk = TILE * tk + (l0 >> 6);
+        // coordinates past the domain (cells of a partial tile, a missing
+        // neighbour) are clamped: their values are not used
+        q.e = cx[mg_clamp(gi >> 1, c.nx) + (int64_t)c.nx * (mg_clamp(gj >> 1, c.ny) + (int64_t)c.ny * mg_clamp(gk >> 1, c.nz))];
+        const int hi_ = TILE * ti + hl.hx, hj = TILE * tj + hl.hy, hk = TILE * tk + hl.hz;
+        q.he = cx[mg_clamp(hi_ >> 1, c.nx) + (int64_t)c.nx * (mg_clamp(hj >> 1, c.ny) + (int64_t)c.ny * mg_clamp(hk >> 1, c.nz))];
+    }
+}
+
+template <typename V>
+__device__ inline V mg_recip(int d)
+{
+    return d ? V(1) / (V)d : V(0);
+}
+
+// one tile of the down kernel; returns nothing, writes level-1 b for the
+// tile's 4x4x4 parents (those inside level 1)
+template <typename V>
+__device__ inline void mg_down_tile(V* st, V* psum, MgRegs<V>& cur, int t, int tlast, int32_t& nn, uint32_t& tn,
+                                    const int32_t* __restrict__ nbr, const uint32_t* __restrict__ tile_list,
+                                    const uint8_t* __restrict__ diag, const V* __restrict__ r, const Geo& g,
+                                    const MgLevel& c, V* __restrict__ cb, int tid, const HaloLane& hl)
+{
+    const V w = V(6) / V(7);
+    const int d0 = (int)(cur.d & 0xFFu), d1 = (int)(cur.d >> 8);
+    const int hd0 = (int)(cur.hd & 0xFFu), hd1 = (int)(cur.hd >> 8);
+    const V r0 = cur.r.a, r1 = cur.r.b;
+    const V u0 = w * r0 * mg_recip<V>(d0), u1 = w * r1 * mg_recip<V>(d1);
+    const V hu0 = w * cur.hr.a * mg_recip<V>(hd0), hu1 = w * cur.hr.b * mg_recip<V>(hd1);
+    const V h0 = cur.m ? (hl.hi ? hu1 : hu0) : V(0);
+    const V h1 = cur.m ? hu1 : V(0);
+    const uint32_t tile_cur = cur.tile;
+    st2(st, 2 * tid, u0, u1);
+    st2(st, hl.dst, h0, h1);
+    lds_barrier();
+    const int32_t nn3 = next_nbr(nbr, min(t + 3, tlast), hl);
+    const uint32_t tn3 = next_tile(tile_list, min(t + 3, tlast));
+    V n0, n1;
+    pair_neighbour_sums(st, tid, u0, u1, n0, n1);
+    const V t0v = d0 ? (r0 - w * r0) + n0 : V(0);
+    const V t1v = d1 ? (r1 - w * r1) + n1 : V(0);
+    psum[tid] = t0v + t1v;
+    lds_barrier();
+    if (tid < 64) {
+        // parent p of the tile's 4x4x4 block: its children are the x-pairs
+        // px + 4 y + 32 z for y in {2py, 2py+1}, z in {2pz, 2pz+1}
+        const int px = tid & 3, py = (tid >> 2) & 3, pz = tid >> 4;
+        const int b0 = px + 4 * (2 * py) + 32 * (2 * pz);
+        const V sum = (psum[b0] + psum[b0 + 4]) + (psum[b0 + 32] + psum[b0 + 36]);
+        const int ti = (int)(tile_cur % (uint32_t)g.tx), tj = (int)((tile_cur / (uint32_t)g.tx) % (uint32_t)g.ty);
+        const int tk = (int)(tile_cur / ((uint32_t)g.tx * (uint32_t)g.ty));
+        const int ci = 4 * ti + px, cj = 4 * tj + py, ck = 4 * tk + pz;
+        if (ci < c.nx && cj < c.ny && ck < c.nz) cb[ci + (int64_t)c.nx * (cj + (int64_t)c.ny * ck)] = V(0.5) * sum;
+    }
+    // nn and tn belong to tile t + 2 (loaded one tile ahead, like nn)
+    __builtin_amdgcn_sched_barrier(0);
+    mg_fetch<V, false>(cur, r, diag, nullptr, g, c, min(t + 2, tlast), nn, tn, tid, hl);
+    nn = nn3;
+    tn = tn3;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename V>
+__device__ inline void mg_up_tile(V* st, MgRegs<V>& cur, int t, int tlast, int32_t& nn, uint32_t& tn,
+                                  const int32_t* __restrict__ nbr, const uint32_t* __restrict__ tile_list,
+                                  const uint8_t* __restrict__ diag, const V* __restrict__ r, const V* __restrict__ cx,
+                                  const Geo& g, const MgLevel& c, V* __restrict__ z, int tid, const HaloLane& hl,
+                                  double& rz, double& rmax)
+{
+    const V w = V(6) / V(7);
+    const int d0 = (int)(cur.d & 0xFFu), d1 = (int)(cur.d >> 8);
+    const int hd0 = (int)(cur.hd & 0xFFu), hd1 = (int)(cur.hd >> 8);
+    const V r0 = cur.r.a, r1 = cur.r.b;
+    const V i0 = mg_recip<V>(d0), i1 = mg_recip<V>(d1);
+    const V y0 = d0 ? w * r0 * i0 + cur.e : V(0), y1 = d1 ? w * r1 * i1 + cur.e : V(0);
+    const V hy0 = hd0 ? w * cur.hr.a * mg_recip<V>(hd0) + cur.he : V(0);
+    const V hy1 = hd1 ? w * cur.hr.b * mg_recip<V>(hd1) + cur.he : V(0);
+    const V h0 = cur.m ? (hl.hi ? hy1 : hy0) : V(0);
+    const V h1 = cur.m ? hy1 : V(0);
+    st2(st, 2 * tid, y0, y1);
+    st2(st, hl.dst, h0, h1);
+    lds_barrier();
+    const int32_t nn3 = next_nbr(nbr, min(t + 3, tlast), hl);
+    const uint32_t tn3 = next_tile(tile_list, min(t + 3, tlast));
+    V n0, n1;
+    pair_neighbour_sums(st, tid, y0, y1, n0, n1);
+    const V z0 = d0 ? y0 + w * ((r0 - (V)d0 * y0) + n0) * i0 : V(0);
+    const V z1 = d1 ? y1 + w * ((r1 - (V)d1 * y1) + n1) * i1 : V(0);
+    st2(z, (int64_t)t * TILE_CELLS + 2 * tid, z0, z1);
+    rz += (double)r0 * (double)z0 + (double)r1 * (double)z1;
+    rmax = fmax(rmax, fmax(finite_or_inf(fabs((double)r0)), finite_or_inf(fabs((double)r1))));
+    __builtin_amdgcn_sched_barrier(0);
+    mg_fetch<V, true>(cur, r, diag, cx, g, c, min(t + 2, tlast), nn, tn, tid, hl);
+    nn = nn3;
+    tn = tn3;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename V, bool UP>
+__global__ __launch_bounds__(PCG_NT) void k_mg_fine(int na_hint, Geo g, const uint32_t* __restrict__ tile_list,
+                                                    const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
+                                                    const V* __restrict__ r, MgLevel c, V* __restrict__ z,
+                                                    double* __restrict__ pslots, const PcgState* __restrict__ ps)
+{
+    __shared__ alignas(16) V stg[2][STAGE2];
+    __shared__ V psum[2][PCG_NT];
+    __shared__ double red[2 * (PCG_NT / WAVE)];
+    const Blk blk = plain_blk();
+    const int tid = threadIdx.x;
+    const HaloLane hl = halo_lane(tid);
+    const int na = na_hint >= 0 ? na_hint : ps->n_active;
+    int t0, t1;
+    tile_range(blk, na, t0, t1);
+    if (ps->done != PCG_RUNNING || na == 0) return;
+    const int tlast = t0 < t1 ? t1 - 1 : max(min(t0, na - 1), 0);
+    const V* const cx = (const V*)c.x;
+    V* const cb = (V*)c.b;
+    MgRegs<V> A, B;
+    // nn and tn: neighbour slot and tile index of the next tile to fetch
+    int32_t nn = next_nbr(nbr, min(t0, tlast), hl);
+    uint32_t tn = next_tile(tile_list, min(t0, tlast));
+    mg_fetch<V, UP>(A, r, diag, cx, g, c, min(t0, tlast), nn, tn, tid, hl);
+    nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
+    tn = next_tile(tile_list, min(t0 + 1, tlast));
+    mg_fetch<V, UP>(B, r, diag, cx, g, c, min(t0 + 1, tlast), nn, tn, tid, hl);
+    nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+    tn = next_tile(tile_list, min(t0 + 2, tlast));
+    double rz = 0.0, rmax = 0.0;
+    // unconditional tile pairs, as in the direction kernel; an odd count
+    // repeats the last tile, which rewrites the same values (its sums dropped)
+    for (int t = t0; t < t1; t += 2) {
+        const bool real = t + 1 < t1;
+        if (UP) {
+            mg_up_tile<V>(stg[0], A, t, tlast, nn, tn, nbr, tile_list, diag, r, cx, g, c, z, tid, hl, rz, rmax);
+            double rz2 = 0.0, rmax2 = 0.0;
+            mg_up_tile<V>(stg[1], B, real ? t + 1 : tlast, tlast, nn, tn, nbr, tile_list, diag, r, cx, g, c, z, tid,
+                          hl, rz2, rmax2);
+            rz += real ? rz2 : 0.0;
+            rmax = real ? fmax(rmax, rmax2) : rmax;
+        } else {
+            mg_down_tile<V>(stg[0], psum[0], A, t, tlast, nn, tn, nbr, tile_list, diag, r, g, c, cb, tid, hl);
+            mg_down_tile<V>(stg[1], psum[1], B, real ? t + 1 : tlast, tlast, nn, tn, nbr, tile_list, diag, r, g, c,
+                            cb, tid, hl);
+        }
+    }
+    if (!UP) return;
+    const double prz = block_sum<PCG_NT>(rz, red);
+    const double pmx = block_max<PCG_NT>(rmax, red);
+    if (tid == 0) {  // completed by the next direction kernel
+        slot_rho(pslots, blk.n)[blk.id] = prz;
+        slot_max(pslots, blk.n)[blk.id] = pmx;
+    }
+}
+
+template <typename V>
+void launch_mg_fine(bool up, int groups, int na_hint, const Geo& g, const uint32_t* tile_list,
+                    const int32_t* tile_nbr, const uint8_t* diag, const V* r, const MgLevel& c, V* z,
+                    double* pslots, const PcgState* ps, hipStream_t st)
+{
+    auto kern = up ? k_mg_fine<V, true> : k_mg_fine<V, false>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, g, tile_list, tile_nbr, diag, r,
+                       c, z, pslots, ps);
+}
+template void launch_mg_fine<float>(bool, int, int, const Geo&, const uint32_t*, const int32_t*, const uint8_t*,
+                                    const float*, const MgLevel&, float*, double*, const PcgState*, hipStream_t);
+template void launch_mg_fine<double>(bool, int, int, const Geo&, const uint32_t*, const int32_t*, const uint8_t*,
+                                     const double*, const MgLevel&, double*, double*, const PcgState*, hipStream_t);
 
 template <typename V>
 struct UpdRegs {
