@@ -12,9 +12,13 @@ timing), the roofline figures of the dominant kernel (algorithmic bytes per
 launch over its average duration, from HIP events on a second handle of the
 same scene), a serving leg (a stream of independent scenes through the
 continuous-batching server, beside the plain path on the same scenes), and
-the FP64 oracle timed on the host as a CPU baseline.
+the FP64 oracle timed on the host as a CPU baseline. The headline uses the
+multigrid-preconditioned CG; the Jacobi-preconditioned CG on the same scene
+is measured too and reported beside it (`jacobi_pcg_same_scene`), with the
+roofline of its dominant kernel.
 
 Usage: python bench.py [--gpus 1] [--steps 30] [--warmup 3] [--scene drop256]
+                       [--solver multigrid|jacobi] [--no-second-solver]
                        [--serving-scenes 128] [--serving-only] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -59,9 +63,12 @@ def algorithmic_bytes(kind: str, rb: int, n: int, cells: int, faces: list, fluid
     """
     F = sum(faces)
     return {
-        # one V-cycle: fine level r, n_c in (down); r, n_c in, z out (up);
-        # each coarse cell b, n_c in and b out below (down), b, n_c in and x out (up)
-        "pcg_precond": fluid * (3 * rb + 2) + coarse * (3 * rb + 2),
+        # multigrid V-cycle: fine level r, n_c in, level-1 b out (down); r, n_c,
+        # level-1 x in, z out (up); each coarse cell b, n_c in and b out below
+        # (down), b, n_c and x below in, x out (up)
+        "mg_down_fine": fluid * (rb + 1) + cells / 8 * rb,
+        "mg_up_fine": fluid * (2 * rb + 1) + cells / 8 * rb,
+        "mg_coarse": coarse * (3 * rb + 2),
         "bin_keys": n * (3 * rb + 8) + 12 * cells,     # positions in; key, rank out; count fill + RMW
         "bin_scan": 8 * cells,                          # counts in, starts out
         "bin_scatter": 16 * n,                          # key, rank, start in; slot out
@@ -187,65 +194,18 @@ def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plai
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--scene", default="drop256")
-    ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default=None,
-                    help="override the scene's precision")
-    ap.add_argument("--cpu-sample", default="drop128")
-    ap.add_argument("--cpu-steps", type=int, default=4)
-    ap.add_argument("--timing-steps", type=int, default=10,
-                    help="steps of the separate handle that times each kernel")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-scenes", type=int, default=128,
-                    help="scenes of the serving stream to serve after the main benchmark (0: skip)")
-    ap.add_argument("--serving-budget-gib", type=float, default=4.0)
-    ap.add_argument("--serving-slots", type=int, default=128)
-    ap.add_argument("--serving-no-graphs", action="store_true")
-    ap.add_argument("--serving-plain-sample", type=int, default=16)
-    ap.add_argument("--serving-only", action="store_true", help="skip the 256^3 benchmark")
-    ap.add_argument("--multigrid", action="store_true",
-                    help="precondition the pressure CG with the multigrid V-cycle instead of Jacobi")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of MIB MiB five times (scales HBM counters)")
-    args = ap.parse_args()
-    if args.calibrate_copy:
-        import torch
-
-        torch.cuda.set_device(0)
-        n = args.calibrate_copy * 2**20 // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 5}), flush=True)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the timestep has no multi-GPU "
-              f"path in this build", file=sys.stderr)
-        sys.exit(2)
-
+def measure(args, sc, solver: str) -> dict:
+    """Throughput of `args.steps` steps of scene sc on one handle (after
+    `args.warmup`), then per-kernel durations on a second handle with kernel
+    timing on. solver: "jacobi" or "multigrid" (FLIP_FLAG_MULTIGRID)."""
     import torch
 
-    from paper_2404_01931_amd import flip, inputs
+    from paper_2404_01931_amd import flip
 
-    torch.cuda.set_device(0)
-    if args.serving_only:
-        out = serving_leg(args.serving_scenes, args.serving_budget_gib, args.serving_slots,
-                          not args.serving_no_graphs, args.serving_plain_sample)
-        print(json.dumps({"serving": out}), flush=True)
-        return
-    sc = inputs.scene(args.scene)
-    if args.precision:
-        sc = inputs.scene(args.scene, precision=args.precision)
-    mgflag = flip.FLIP_FLAG_MULTIGRID if args.multigrid else 0
+    mgflag = flip.FLIP_FLAG_MULTIGRID if solver == "multigrid" else 0
     # throughput: a handle without kernel timing (timed launches cost extra work)
     cfg, keep = flip.scene_config(sc, flags=mgflag)
-    progress(f"init {sc.name}")
+    progress(f"init {sc.name} ({solver})")
     t = time.perf_counter()
     sim = flip.Simulation(cfg, keep)
     progress(f"init done in {time.perf_counter() - t:.1f} s: {sim.n} particles, workspace "
@@ -290,23 +250,23 @@ def main():
         if cnt <= 0:
             continue
         avg = ms / cnt
-        launches = d_iter if name.startswith("pcg_") else cnt
+        launches = d_iter if name.startswith(("pcg_", "mg_")) else cnt
         kernels[name] = {"avg_ms": avg, "launches": launches, "est_total_ms": avg * launches}
     ts = args.timing_steps
-    dominant = max(kernels, key=lambda k: kernels[k]["est_total_ms"])
+    # the dominant single kernel (mg_coarse times several launches together)
+    dominant = max((k for k in kernels if k != "mg_coarse"), key=lambda k: kernels[k]["est_total_ms"])
     kd = kernels[dominant]
-    coarse = mg_coarse_cells(cfg.nx, cfg.ny, cfg.nz) if args.multigrid else 0
+    coarse = mg_coarse_cells(cfg.nx, cfg.ny, cfg.nz) if mgflag else 0
     abytes = algorithmic_bytes(dominant, rb, n, cells, faces, fluid_avg, coarse)
     achieved = abytes / (kd["avg_ms"] * 1e-3) / 1e9
     traffic = traffic_for(dominant, sc.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
                 "avg_launch_ms": round(kd["avg_ms"], 5), "bytes_per_launch": abytes}
-    pcg_ms = sum(kernels[k]["est_total_ms"] for k in ("pcg_direction", "pcg_update", "pcg_precond")
-                 if k in kernels)
+    pcg_ms = sum(v["est_total_ms"] for k, v in kernels.items() if k.startswith(("pcg_", "mg_")))
     pcg_bytes = d_cell_iter * (8 * rb + 2)
-    if args.multigrid:
-        pcg_bytes += d_cell_iter * (3 * rb + 2) + d_iter * coarse * (3 * rb + 2)
+    if mgflag:
+        pcg_bytes += d_cell_iter * (3 * rb + 2) + d_iter * (cells / 4 * rb + coarse * (3 * rb + 2))
     pcg = {"iterations_per_step": (s_last.pcg_iterations_total - s_pre.pcg_iterations_total) / args.steps,
            "iterations_per_step_timing_run": d_iter / ts, "fluid_cells": round(fluid_avg),
            "last_residual_rel": s_last.max_r / s_last.max_b if s_last.max_b else 0.0,
@@ -319,6 +279,75 @@ def main():
 
     sim.close()
     del sim
+    return {"solver": solver, "n": n, "elapsed": elapsed, "roofline": roofline, "pcg": pcg,
+            "stage_ms": stage_ms}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scene", default="drop256")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default=None,
+                    help="override the scene's precision")
+    ap.add_argument("--cpu-sample", default="drop128")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--timing-steps", type=int, default=10,
+                    help="steps of the separate handle that times each kernel")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-scenes", type=int, default=128,
+                    help="scenes of the serving stream to serve after the main benchmark (0: skip)")
+    ap.add_argument("--serving-budget-gib", type=float, default=4.0)
+    ap.add_argument("--serving-slots", type=int, default=128)
+    ap.add_argument("--serving-no-graphs", action="store_true")
+    ap.add_argument("--serving-plain-sample", type=int, default=16)
+    ap.add_argument("--serving-only", action="store_true", help="skip the 256^3 benchmark")
+    ap.add_argument("--solver", choices=["multigrid", "jacobi"], default="multigrid",
+                    help="preconditioner of the pressure CG for the headline number (the other one is "
+                         "measured too and reported beside it)")
+    ap.add_argument("--no-second-solver", action="store_true", help="measure the headline solver only")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (scales HBM counters)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        torch.cuda.set_device(0)
+        n = args.calibrate_copy * 2**20 // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 5}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the timestep has no multi-GPU "
+              f"path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2404_01931_amd import flip, inputs
+
+    torch.cuda.set_device(0)
+    if args.serving_only:
+        out = serving_leg(args.serving_scenes, args.serving_budget_gib, args.serving_slots,
+                          not args.serving_no_graphs, args.serving_plain_sample)
+        print(json.dumps({"serving": out}), flush=True)
+        return
+    sc = inputs.scene(args.scene)
+    if args.precision:
+        sc = inputs.scene(args.scene, precision=args.precision)
+    # the headline solver, then the other one on the same scene for comparison
+    # (mixed precision runs Jacobi only: its inner solves are not multigrid-preconditioned)
+    solvers = ["jacobi"] if sc.precision == "mixed" else (["jacobi", "multigrid"] if args.solver == "jacobi"
+                                                           else ["multigrid", "jacobi"])
+    if args.no_second_solver:
+        solvers = solvers[:1]
+    runs = {name: measure(args, sc, name) for name in solvers}
+    main_run = runs[solvers[0]]
     serving = None
     if args.serving_scenes > 0:
         serving = serving_leg(args.serving_scenes, args.serving_budget_gib, args.serving_slots,
@@ -330,6 +359,8 @@ def main():
         cpu = cpu_baseline(args.cpu_sample, args.cpu_steps)
         progress(f"cpu baseline: {cpu['value']:.3e} particle-steps/s")
 
+    n, elapsed = main_run["n"], main_run["elapsed"]
+    solver_label = {"jacobi": "Jacobi", "multigrid": "multigrid"}
     line = {
         "metric": "particle-steps/s",
         "value": n * args.steps / elapsed,
@@ -345,15 +376,22 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{sc.name}: drop into pool, {sc.n}^3 MAC grid, {n} particles, "
                                f"{sc.precision.upper()}, dt=1/{round(1 / sc.dt)}, FLIP {sc.flip_ratio}, "
-                               f"{'multigrid' if args.multigrid else 'Jacobi'}-PCG tol {sc.tol:g}"
+                               f"{solver_label[main_run['solver']]}-PCG tol {sc.tol:g}"
                                + (f", FP64 refinement to {sc.ir_tol:g}" if sc.precision == "mixed" else ""),
                    "grid": sc.n, "particles": n, "parallelism": "single GPU"},
-        "roofline": roofline,
-        "pcg": pcg,
-        "kernel_ms_per_step": stage_ms,
-        "serving": serving,
-        "cpu_baseline": cpu,
+        "roofline": main_run["roofline"],
+        "pcg": main_run["pcg"],
+        "kernel_ms_per_step": main_run["stage_ms"],
     }
+    for name, r in runs.items():
+        if r is main_run:
+            continue
+        line[f"{name}_pcg_same_scene"] = {
+            "value": r["n"] * args.steps / r["elapsed"], "unit": "particle-steps/s",
+            "ms_per_step": r["elapsed"] / args.steps * 1e3, "roofline": r["roofline"], "pcg": r["pcg"],
+            "kernel_ms_per_step": r["stage_ms"]}
+    line["serving"] = serving
+    line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

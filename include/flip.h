@@ -141,8 +141,11 @@ enum {
     FLIP_KERNEL_PCG_UPDATE = 8,    /* x += alpha s, r -= alpha A s, r.z, max|r|          */
     FLIP_KERNEL_PROJECT = 9,
     FLIP_KERNEL_G2P = 10,
-    FLIP_KERNEL_PCG_PRECOND = 11,  /* FLIP_FLAG_MULTIGRID: one V-cycle z = M r (all levels) */
-    FLIP_KERNEL_COUNT = 12
+    FLIP_KERNEL_MG_DOWN_FINE = 11, /* FLIP_FLAG_MULTIGRID, fine level: smooth r, restrict  */
+    FLIP_KERNEL_MG_UP_FINE = 12,   /* FLIP_FLAG_MULTIGRID, fine level: prolong, smooth, r.z */
+    FLIP_KERNEL_MG_COARSE = 13,    /* FLIP_FLAG_MULTIGRID: all coarse levels of one V-cycle
+                                      (several launches, timed together)                    */
+    FLIP_KERNEL_COUNT = 14
 };
 
 typedef struct {

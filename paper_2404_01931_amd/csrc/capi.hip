@@ -346,10 +346,18 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
     const bool mg = h->nmg > 0;
     auto precondition = [&](int k) {
         if (!mg) return;
-        const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_begin(h, FLIP_KERNEL_PCG_PRECOND, st, k) : -1;
-        launch_mg_vcycle<V>(h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag, (const V*)h->z,
-                            (V*)h->mgz, h->mg, h->nmg, h->pslots, h->ps, st);
+        const bool timed = (k % TIMED_PCG_EVERY) == 0;
+        int q = timed ? timer_pair(h, FLIP_KERNEL_MG_DOWN_FINE, k) : -1;
+        launch_mg_fine<V>(false, h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag, (const V*)h->z,
+                          h->mg[0], nullptr, nullptr, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
+                          q >= 0 ? h->ev[q + 1] : nullptr);
+        q = timed ? timer_begin(h, FLIP_KERNEL_MG_COARSE, st, k) : -1;
+        launch_mg_coarse<V>(h->mg, h->nmg, h->ps, st);
         timer_end(h, q, st);
+        q = timed ? timer_pair(h, FLIP_KERNEL_MG_UP_FINE, k) : -1;
+        launch_mg_fine<V>(true, h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag, (const V*)h->z,
+                          h->mg[0], (V*)h->mgz, h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
+                          q >= 0 ? h->ev[q + 1] : nullptr);
     };
     precondition(0);
     direction(0);

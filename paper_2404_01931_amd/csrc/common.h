@@ -199,17 +199,17 @@ void launch_mg_types(const MgLevel& f, const MgLevel& c, hipStream_t st);
 // the fine-level kernels of the V-cycle (up = false: smoothing and
 // restriction of r into lv0.b; up = true: prolongation of lv0.x, smoothing
 // into z and the partial sums r . z, max |r| in pslots)
+// A V-cycle is launch_mg_fine(down), launch_mg_coarse, launch_mg_fine(up).
+// With ev_start/ev_stop non-null a fine launch records its own start and end.
 template <typename V>
 void launch_mg_fine(bool up, int groups, int na_hint, const Geo& g, const uint32_t* tile_list,
                     const int32_t* tile_nbr, const uint8_t* diag, const V* r, const MgLevel& lv0, V* z,
-                    double* pslots, const PcgState* ps, hipStream_t st);
-// z = M r over levels lv[0..nlev) below the fine grid; the last fine kernel
-// writes the partial sums r . z and max |r| of its `groups` workgroups into
-// pslots for the next direction kernel
+                    double* pslots, const PcgState* ps, hipStream_t st, hipEvent_t ev_start = nullptr,
+                    hipEvent_t ev_stop = nullptr);
+// the coarse part of a V-cycle over levels lv[0..nlev): restrictions down to
+// the coarsest level, its sweeps, prolongations and smoothing back up to lv[0]
 template <typename V>
-void launch_mg_vcycle(int groups, int na_hint, const Geo& g, const uint32_t* tile_list, const int32_t* tile_nbr,
-                      const uint8_t* diag, const V* r, V* z, const MgLevel* lv, int nlev, double* pslots,
-                      const PcgState* ps, hipStream_t st);
+void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st);
 
 template <typename T, typename V>
 void launch_project(const Geo& g, int axis, const uint32_t* count, const int32_t* tile_slot,

@@ -239,11 +239,8 @@ void launch_mg_types(const MgLevel& f, const MgLevel& c, hipStream_t st)
 }
 
 template <typename V>
-void launch_mg_vcycle(int groups, int na_hint, const Geo& g, const uint32_t* tile_list, const int32_t* tile_nbr,
-                      const uint8_t* diag, const V* r, V* z, const MgLevel* lv, int nlev, double* pslots,
-                      const PcgState* ps, hipStream_t st)
+void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st)
 {
-    launch_mg_fine<V>(false, groups, na_hint, g, tile_list, tile_nbr, diag, r, lv[0], nullptr, nullptr, ps, st);
     for (int l = 0; l + 1 < nlev; ++l) {
         const dim3 grid((unsigned)((lv[l].nx + MGD_X - 1) / MGD_X), (unsigned)((lv[l].ny + MGD_Y - 1) / MGD_Y),
                         (unsigned)((lv[l].nz + MGD_Z - 1) / MGD_Z));
@@ -254,14 +251,9 @@ void launch_mg_vcycle(int groups, int na_hint, const Geo& g, const uint32_t* til
         const int64_t n = (int64_t)lv[l].nx * lv[l].ny * lv[l].nz;
         hipLaunchKernelGGL(k_mg_up<V>, dim3(blocks_for(n)), dim3(256), 0, st, lv[l], lv[l + 1], ps);
     }
-    launch_mg_fine<V>(true, groups, na_hint, g, tile_list, tile_nbr, diag, r, lv[0], z, pslots, ps, st);
 }
 
-template void launch_mg_vcycle<float>(int, int, const Geo&, const uint32_t*, const int32_t*, const uint8_t*,
-                                      const float*, float*, const MgLevel*, int, double*, const PcgState*,
-                                      hipStream_t);
-template void launch_mg_vcycle<double>(int, int, const Geo&, const uint32_t*, const int32_t*, const uint8_t*,
-                                       const double*, double*, const MgLevel*, int, double*, const PcgState*,
-                                       hipStream_t);
+template void launch_mg_coarse<float>(const MgLevel*, int, const PcgState*, hipStream_t);
+template void launch_mg_coarse<double>(const MgLevel*, int, const PcgState*, hipStream_t);
 
 }  // namespace flipmi

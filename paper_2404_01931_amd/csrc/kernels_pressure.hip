@@ -744,16 +744,22 @@ __global__ __launch_bounds__(PCG_NT) void k_mg_fine(int na_hint, Geo g, const ui
 template <typename V>
 void launch_mg_fine(bool up, int groups, int na_hint, const Geo& g, const uint32_t* tile_list,
                     const int32_t* tile_nbr, const uint8_t* diag, const V* r, const MgLevel& c, V* z,
-                    double* pslots, const PcgState* ps, hipStream_t st)
+                    double* pslots, const PcgState* ps, hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     auto kern = up ? k_mg_fine<V, true> : k_mg_fine<V, false>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, g, tile_list, tile_nbr, diag, r,
-                       c, z, pslots, ps);
+    if (ev_start)
+        hipExtLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop, 0, na_hint, g,
+                              tile_list, tile_nbr, diag, r, c, z, pslots, ps);
+    else
+        hipLaunchKernelGGL(kern, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, g, tile_list, tile_nbr, diag,
+                           r, c, z, pslots, ps);
 }
 template void launch_mg_fine<float>(bool, int, int, const Geo&, const uint32_t*, const int32_t*, const uint8_t*,
-                                    const float*, const MgLevel&, float*, double*, const PcgState*, hipStream_t);
+                                    const float*, const MgLevel&, float*, double*, const PcgState*, hipStream_t,
+                                    hipEvent_t, hipEvent_t);
 template void launch_mg_fine<double>(bool, int, int, const Geo&, const uint32_t*, const int32_t*, const uint8_t*,
-                                     const double*, const MgLevel&, double*, double*, const PcgState*, hipStream_t);
+                                     const double*, const MgLevel&, double*, double*, const PcgState*, hipStream_t,
+                                     hipEvent_t, hipEvent_t);
 
 template <typename V>
 struct UpdRegs {

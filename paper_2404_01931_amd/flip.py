@@ -45,7 +45,8 @@ FLIP_FIELD_RHS = 9
 FLIP_FIELD_PRESSURE = 10
 
 KERNEL_NAMES = ["bin_keys", "bin_scan", "bin_scatter", "bin_gather", "tiles", "p2g", "rhs",
-                "pcg_direction", "pcg_update", "project", "g2p", "pcg_precond"]
+                "pcg_direction", "pcg_update", "project", "g2p", "mg_down_fine", "mg_up_fine",
+                "mg_coarse"]
 FLIP_KERNEL_COUNT = len(KERNEL_NAMES)
 
 FLIP_BATCH_MAX_SCENES = 256
