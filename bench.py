@@ -341,9 +341,7 @@ def main():
     if args.precision:
         sc = inputs.scene(args.scene, precision=args.precision)
     # the headline solver, then the other one on the same scene for comparison
-    # (mixed precision runs Jacobi only: its inner solves are not multigrid-preconditioned)
-    solvers = ["jacobi"] if sc.precision == "mixed" else (["jacobi", "multigrid"] if args.solver == "jacobi"
-                                                           else ["multigrid", "jacobi"])
+    solvers = ["jacobi", "multigrid"] if args.solver == "jacobi" else ["multigrid", "jacobi"]
     if args.no_second_solver:
         solvers = solvers[:1]
     runs = {name: measure(args, sc, name) for name in solvers}

@@ -81,9 +81,9 @@ enum {
     FLIP_FLAG_NO_PROJECTION = 2u,      /* skip solve and projection (transfer-only steps)  */
     FLIP_FLAG_ADVECT_PARTICLE_VEL = 4u,/* advect with the blended particle velocity        */
     FLIP_FLAG_KERNEL_TIMING = 8u,      /* bracket kernel launches with HIP events           */
-    FLIP_FLAG_MULTIGRID = 16u          /* precondition the pressure CG with a multigrid
-                                          V-cycle instead of Jacobi (FLIP_FP32 / FLIP_FP64;
-                                          FLIP_MIXED and batches refuse it)                   */
+    FLIP_FLAG_MULTIGRID = 16u          /* precondition the pressure CG (FLIP_MIXED: its FP32
+                                          inner solves) with a multigrid V-cycle instead of
+                                          Jacobi; batches refuse it                           */
 };
 
 typedef struct {

@@ -143,7 +143,6 @@ flip_status validate(const flip_config* c)
     if (c->precision != FLIP_FP32 && c->precision != FLIP_FP64 && c->precision != FLIP_MIXED)
         return FLIP_E_INVALID;
     if (c->precision == FLIP_MIXED && (!(c->ir_tol > 0.0) || !std::isfinite(c->ir_tol))) return FLIP_E_INVALID;
-    if (c->precision == FLIP_MIXED && (c->flags & FLIP_FLAG_MULTIGRID)) return FLIP_E_INVALID;
     if (c->pos0) {
         if (c->n_particles < 0 || c->n_particles >= ((int64_t)1 << 31) || !c->vel0) return FLIP_E_INVALID;
     } else {
@@ -449,7 +448,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
                          (const float*)h->f_star[1], (const float*)h->f_star[2], scale_b, h->diag,
                          h->b64, h->x64[0], (float*)h->z, (float*)h->xin[0], (float*)h->s[0],
                          (float*)h->s[1], h->partials, G, h->ps, project ? c.pcg_tol : 0.0,
-                         project ? max_iters : 0, c.ir_tol, MAX_REFINEMENTS, st);
+                         project ? max_iters : 0, c.ir_tol, MAX_REFINEMENTS, h->nmg > 0 ? 1 : 0, st);
     else
         launch_rhs<T, T>(g, G, h->tile_list, h->d_nactive, h->count, (const T*)h->f_star[0],
                          (const T*)h->f_star[1], (const T*)h->f_star[2], scale_b, h->diag, (T*)h->b,
@@ -457,7 +456,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
                          project ? c.pcg_tol : 0.0, project ? max_iters : 0, h->nmg > 0 ? 1 : 0, st);
     timer_end(h, tq, st);
     // cell types of the multigrid levels, from this step's fluid cells
-    if (!MIXED && h->nmg > 0 && project) {
+    if (h->nmg > 0 && project) {
         launch_mg_types_fine(g, h->tile_slot, h->diag, h->mg[0], st);
         for (int l = 0; l + 1 < h->nmg; ++l) launch_mg_types(h->mg[l], h->mg[l + 1], st);
     }
@@ -480,7 +479,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
             const int xi = h->xi;
             launch_ir_update(G, h->tile_nbr, h->diag, h->b64, h->x64[xi], h->x64[xi ^ 1],
                              (const float*)h->xin[xi], (float*)h->xin[xi ^ 1], (float*)h->z,
-                             (float*)h->s[0], (float*)h->s[1], h->partials, G, h->ps, st);
+                             (float*)h->s[0], (float*)h->s[1], h->partials, G, h->ps, h->nmg > 0 ? 1 : 0, st);
             h->xi = xi ^ 1;
             h->scur = 0;
             ++refinements;

@@ -170,14 +170,14 @@ void launch_rhs_mixed(const Geo& g, int groups, const uint32_t* tile_list, const
                       const uint32_t* count, const float* u, const float* v, const float* w,
                       double scale, uint8_t* diag, double* b64, double* x64, float* z, float* x,
                       float* s0, float* s1, double* partials, int64_t pstride, PcgState* st_dev,
-                      double tol, int max_iters, double ir_tol, int max_outer, hipStream_t st);
+                      double tol, int max_iters, double ir_tol, int max_outer, int r_form, hipStream_t st);
 // one refinement: x64_out = x64_in + x_in; r64 = b64 - A x64_out; unless
 // converged, the inner FP32 solve restarts on r64 (z = r64 / n rounded,
 // x_out = 0, s = 0)
 void launch_ir_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const double* b64,
                       const double* x64_in, double* x64_out, const float* x_in, float* x_out,
                       float* z, float* s0, float* s1, double* partials, int64_t pstride,
-                      PcgState* st_dev, hipStream_t st);
+                      PcgState* st_dev, int r_form, hipStream_t st);
 
 // ---- multigrid preconditioner (FLIP_FLAG_MULTIGRID) --------------------------
 // One coarse level, dense with i fastest: right-hand side b and solution x of

@@ -954,7 +954,7 @@ __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __rest
                                                    float* __restrict__ s1,
                                                    double* __restrict__ partials, int64_t pstride,
                                                    PcgState* __restrict__ ps, double tol,
-                                                   int max_iters, double ir_tol, int max_outer)
+                                                   int max_iters, double ir_tol, int max_outer, int r_form)
 {
     __shared__ double red[PNT / WAVE];
     __shared__ bool last;
@@ -985,7 +985,9 @@ __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __rest
             }
         }
         const int64_t e = (int64_t)slot * TILE_CELLS + l;
-        const float zq = d ? (float)(bd / d) : 0.0f;
+        // the first inner solve starts from z = b / n, or from r = b when a
+        // preconditioner application follows (multigrid)
+        const float zq = r_form ? (float)bd : (d ? (float)(bd / d) : 0.0f);
         diag[e] = (uint8_t)d;
         b64[e] = bd;
         x64[e] = 0.0;
@@ -1022,7 +1024,7 @@ __global__ __launch_bounds__(PNT) void k_rhs_mixed(Geo g, const uint32_t* __rest
         ps->outer = 0;
         ps->max_outer = max_outer;
         ps->outer_done = (max_b == 0.0) ? 1 : 0;
-        ps->from_slots = 0;
+        ps->from_slots = r_form;
         ps->done = !(max_b <= DBL_MAX) ? PCG_BREAKDOWN
                    : (max_b == 0.0)    ? PCG_CONVERGED
                    : (max_iters <= 0)  ? PCG_MAX_ITERS
@@ -1037,11 +1039,11 @@ void launch_rhs_mixed(const Geo& g, int groups, const uint32_t* tile_list, const
                       const uint32_t* count, const float* u, const float* v, const float* w,
                       double scale, uint8_t* diag, double* b64, double* x64, float* z, float* x,
                       float* s0, float* s1, double* partials, int64_t pstride, PcgState* st_dev,
-                      double tol, int max_iters, double ir_tol, int max_outer, hipStream_t st)
+                      double tol, int max_iters, double ir_tol, int max_outer, int r_form, hipStream_t st)
 {
     hipLaunchKernelGGL(k_rhs_mixed, dim3((unsigned)groups), dim3(PNT), 0, st, g, tile_list, d_nactive,
                        count, u, v, w, scale, diag, b64, x64, z, x, s0, s1, partials, pstride, st_dev,
-                       tol, max_iters, ir_tol, max_outer);
+                       tol, max_iters, ir_tol, max_outer, r_form);
 }
 
 // One refinement, 512 threads per workgroup, one tile at a time. The updated
@@ -1063,7 +1065,7 @@ __global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ n
                                                    float* __restrict__ x_out, float* __restrict__ z,
                                                    float* __restrict__ s0, float* __restrict__ s1,
                                                    double* __restrict__ partials, int64_t pstride,
-                                                   PcgState* __restrict__ ps)
+                                                   PcgState* __restrict__ ps, int r_form)
 {
     __shared__ double stg[STAGE];
     __shared__ double red[PNT / WAVE];
@@ -1094,7 +1096,7 @@ __global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ n
         float zq = 0.0f;
         if (d) {
             r = b64[e] - fma((double)d, xn, -neighbour_sum(stg, l));
-            zq = (float)(r / d);
+            zq = r_form ? (float)r : (float)(r / d);
         }
         x64_out[e] = xn;
         x_out[e] = 0.0f;
@@ -1143,10 +1145,10 @@ __global__ __launch_bounds__(PNT) void k_ir_update(const int32_t* __restrict__ n
 void launch_ir_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, const double* b64,
                       const double* x64_in, double* x64_out, const float* x_in, float* x_out,
                       float* z, float* s0, float* s1, double* partials, int64_t pstride,
-                      PcgState* st_dev, hipStream_t st)
+                      PcgState* st_dev, int r_form, hipStream_t st)
 {
     hipLaunchKernelGGL(k_ir_update, dim3((unsigned)groups), dim3(PNT), 0, st, tile_nbr, diag, b64,
-                       x64_in, x64_out, x_in, x_out, z, s0, s1, partials, pstride, st_dev);
+                       x64_in, x64_out, x_in, x_out, z, s0, s1, partials, pstride, st_dev, r_form);
 }
 
 // ---------------------------------------------------------------------------

@@ -58,12 +58,6 @@ def test_status_strings_and_argument_errors_without_gpu():
     cfg, keep = flip.make_config((8, 8, 8), 1 / 8, 1 / 240, flip_ratio=1.5)
     with pytest.raises(flip.FlipError):
         flip.flip_workspace_bytes(cfg)
-    # the multigrid preconditioner is not combined with mixed precision
-    cfg, keep = flip.make_config((8, 8, 8), 1 / 8, 1 / 240, precision=flip.FLIP_MIXED,
-                                 flags=flip.FLIP_FLAG_MULTIGRID)
-    with pytest.raises(flip.FlipError) as e:
-        flip.flip_workspace_bytes(cfg)
-    assert e.value.status == flip.FLIP_E_INVALID
 
 
 def test_multigrid_workspace_holds_the_coarse_levels():
@@ -79,6 +73,11 @@ def test_multigrid_workspace_holds_the_coarse_levels():
     coarse = sum(n ** 3 for n in (32, 16, 8))
     assert mg - plain >= 64 ** 3 * 4 + coarse * 9
     assert mg - plain <= 64 ** 3 * 4 + coarse * 9 + 16 * 256
+    # mixed precision: the inner FP32 solves take the same levels (4-byte reals)
+    cfg, keep = flip.scene_config(sc, precision=flip.FLIP_MIXED)
+    mixed = flip.flip_workspace_bytes(cfg)
+    cfg, keep = flip.scene_config(sc, precision=flip.FLIP_MIXED, flags=flip.FLIP_FLAG_MULTIGRID)
+    assert flip.flip_workspace_bytes(cfg) - mixed == mg - plain
 
 
 def test_workspace_size_is_pure_and_grows_with_the_problem():

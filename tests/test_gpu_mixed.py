@@ -23,9 +23,9 @@ pytestmark = pytest.mark.gpu
 IR_TOL = 1e-8
 
 
-def _run(prec, inner_tol):
+def _run(prec, inner_tol, flags=0):
     sc = inputs.scene("drop64")
-    cfg, keep = flip.scene_config(sc, precision=prec, pcg_tol=inner_tol)
+    cfg, keep = flip.scene_config(sc, precision=prec, pcg_tol=inner_tol, flags=flags)
     cfg.ir_tol = IR_TOL
     sim = flip.Simulation(cfg, keep)
     pos0, vel0, ids0 = state(sim)
@@ -80,6 +80,33 @@ def test_mixed_precision_solve_reaches_fp64_residual_and_error_table(orc):
     assert m["p_err"] <= 1e-6
     for r in runs.values():
         assert r["v_err"] <= 1e-4
+
+
+def test_mixed_precision_with_multigrid_inner_solves(orc):
+    """FLIP_MIXED with FLIP_FLAG_MULTIGRID: the FP32 inner solves are
+    multigrid-preconditioned; the FP64 refinement and its bar are unchanged."""
+    log("[mixed] drop64 mixed, Jacobi and multigrid inner solves")
+    jac = _run(flip.FLIP_MIXED, 1e-4)
+    mg = _run(flip.FLIP_MIXED, 1e-4, flip.FLIP_FLAG_MULTIGRID)
+    sim = mg["sim"]
+    g = grid_of(sim)
+    st = mg["stats"]
+    exact = orc.pcg(g, mg["flags"], mg["b"], 1e-13, 100000)
+    true_res = np.abs(mg["b"] - orc.apply_A(g, mg["flags"], mg["p"])).max() / np.abs(mg["b"]).max()
+    p_err = l2_rel(mg["p"], exact.p)
+    ref = orc.step(params_of(sim), mg["pos0"], mg["vel0"], mg["ids0"])
+    v_err = l2_rel(mg["vel1"], ref.vel)
+    log(f"[mixed] multigrid inner solves: {st.pcg_iterations} iterations, {st.refinements} refinements "
+        f"(Jacobi: {jac['stats'].pcg_iterations}, {jac['stats'].refinements}); true residual {true_res:.3e}, "
+        f"p(solve) {p_err:.3e}, v_particle {v_err:.3e}")
+    assert st.pcg_status == 0 and st.refinements >= 1
+    assert st.max_r <= IR_TOL * st.max_b * (1 + 1e-9)
+    assert true_res <= 1.01 * IR_TOL
+    assert p_err <= 1e-6
+    assert v_err <= 1e-4
+    assert 3 * st.pcg_iterations <= jac["stats"].pcg_iterations
+    sim.close()
+    jac["sim"].close()
 
 
 def test_mixed_precision_shadowed_steps(orc):
