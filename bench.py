@@ -141,7 +141,8 @@ def cpu_baseline(sample_scene: str, steps: int):
     }
 
 
-def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plain_sample: int):
+def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plain_sample: int,
+                multigrid: bool = True):
     """The batched-serving form: a stream of independent dam-break and drop
     scenes (sides 32/48/64/96, 8 particles per cell, 100 FP32 steps each at
     dt = 1/240, Poisson arrivals at 200 / s) through the continuous-batching
@@ -154,7 +155,8 @@ def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plai
 
     stream = inputs.serving_scenes(count=n_scenes)
     reqs = requests_from_scenes(stream)
-    be = FlipBackend(graphs=graphs)
+    be = FlipBackend(graphs=graphs, multigrid=multigrid)
+    cfg_flags = flip.FLIP_FLAG_MULTIGRID if multigrid else 0
     # warm the kernels and the graph path on two tiny requests
     warm = [(0.0, dataclasses.replace(sc, steps=3)) for _, sc in stream[:2]]
     Server(be, budget_bytes=2**34, max_slots=4).run(requests_from_scenes(warm))
@@ -167,7 +169,7 @@ def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plai
     # the plain path, one scene at a time, GPU stepping time only
     ps_plain, t_plain = 0, 0.0
     for _, sc in stream[:plain_sample]:
-        cfg, keep = flip.scene_config(sc)
+        cfg, keep = flip.scene_config(sc, flags=cfg_flags)
         sim = flip.Simulation(cfg, keep)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -185,7 +187,8 @@ def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plai
              f"on the first {plain_sample} scenes")
     return {
         "workload": f"{n_scenes} scenes of the serving stream (dam break / drop, sides 32-96, 8 ppc, "
-                    f"100 FP32 steps, dt 1/240, Poisson arrivals 200/s)",
+                    f"100 FP32 steps, dt 1/240, Poisson arrivals 200/s, "
+                    f"{'multigrid' if multigrid else 'Jacobi'}-PCG tol 1e-6)",
         "budget_GiB": budget_gib, "max_slots": slots, "graphs": graphs,
         **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in s.items()},
         "plain_sample_scenes": plain_sample,
@@ -334,7 +337,7 @@ def main():
     torch.cuda.set_device(0)
     if args.serving_only:
         out = serving_leg(args.serving_scenes, args.serving_budget_gib, args.serving_slots,
-                          not args.serving_no_graphs, args.serving_plain_sample)
+                          not args.serving_no_graphs, args.serving_plain_sample, args.solver == "multigrid")
         print(json.dumps({"serving": out}), flush=True)
         return
     sc = inputs.scene(args.scene)
@@ -349,7 +352,7 @@ def main():
     serving = None
     if args.serving_scenes > 0:
         serving = serving_leg(args.serving_scenes, args.serving_budget_gib, args.serving_slots,
-                              not args.serving_no_graphs, args.serving_plain_sample)
+                              not args.serving_no_graphs, args.serving_plain_sample, args.solver == "multigrid")
 
     cpu = None
     if not args.no_cpu_baseline:

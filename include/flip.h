@@ -83,7 +83,7 @@ enum {
     FLIP_FLAG_KERNEL_TIMING = 8u,      /* bracket kernel launches with HIP events           */
     FLIP_FLAG_MULTIGRID = 16u          /* precondition the pressure CG (FLIP_MIXED: its FP32
                                           inner solves) with a multigrid V-cycle instead of
-                                          Jacobi; batches refuse it                           */
+                                          Jacobi                                              */
 };
 
 typedef struct {
@@ -209,10 +209,11 @@ void flip_destroy(flip_handle* h);
  * same per-scene work split and reduction order.
  *
  * Requirements: 1 <= nscenes <= FLIP_BATCH_MAX_SCENES initialised handles,
- * all FLIP_FP32 or all FLIP_FP64 (FLIP_MIXED is not batched), none with
- * FLIP_FLAG_NO_PROJECTION, FLIP_FLAG_KERNEL_TIMING or FLIP_FLAG_MULTIGRID, no
- * handle twice. The handles stay owned by the caller, must outlive the batch
- * and must not be stepped by other calls while the batch steps.
+ * all FLIP_FP32 or all FLIP_FP64 (FLIP_MIXED is not batched), all with or
+ * all without FLIP_FLAG_MULTIGRID, none with FLIP_FLAG_NO_PROJECTION or
+ * FLIP_FLAG_KERNEL_TIMING, no handle twice. The handles stay owned by the
+ * caller, must outlive the batch and must not be stepped by other calls while
+ * the batch steps.
  *
  * The launch tables live in a caller-owned device workspace
  * (flip_batch_workspace_bytes, 256-byte aligned), written once by

@@ -115,6 +115,7 @@ struct RhsArgs {
     PcgState* ps;
     double tol;
     int max_iters;
+    int r_form;  // 1: start in residual form (a preconditioner application follows)
 };
 
 template <typename V>
@@ -161,6 +162,39 @@ struct G2PArgs {
     int advect_particle_vel;
 };
 
+// multigrid V-cycle (FLIP_FLAG_MULTIGRID)
+struct MgTypesFineArgs {
+    Geo g;
+    const int32_t* tile_slot;
+    const uint8_t* diag;
+    MgLevel c;
+};
+
+// a coarse level and the one below it: cell types, restriction (f -> c),
+// prolongation (c -> f); the coarsest level's sweeps use f alone
+struct MgPairArgs {
+    MgLevel f, c;
+    const PcgState* ps;
+};
+
+template <typename V>
+struct MgFineArgs {
+    int na_hint;
+    Geo g;
+    const uint32_t* tile_list;
+    const int32_t* nbr;
+    const uint8_t* diag;
+    const V* r;
+    MgLevel c;
+    V* z;
+    double* pslots;
+    const PcgState* ps;
+};
+
+enum { MG_B_TYPES = 0, MG_B_DOWN = 1, MG_B_BOTTOM = 2, MG_B_UP = 3 };
+// workgroups of one scene's plain launch of a coarse kernel of that kind
+int64_t mg_blocks(int kind, const MgLevel& f, const MgLevel& c);
+
 // Per-scene summary of the solver state after a batched step, gathered into
 // one array so the host reads every scene's state with one copy.
 struct SolveSummary {
@@ -194,11 +228,17 @@ void launch_b_rhs(const BatchLaunch& L, hipStream_t st);
 template <typename V>
 void launch_b_pcg_direction(const BatchLaunch& L, hipStream_t st);
 template <typename V>
-void launch_b_pcg_update(const BatchLaunch& L, hipStream_t st);
+void launch_b_pcg_update(bool r_form, const BatchLaunch& L, hipStream_t st);
 template <typename T, typename V>
 void launch_b_project(int axis, const BatchLaunch& L, hipStream_t st);
 template <typename T>
 void launch_b_g2p(const BatchLaunch& L, hipStream_t st);
 void launch_b_summary(const BatchLaunch& L, hipStream_t st);
+void launch_b_mg_types_fine(const BatchLaunch& L, hipStream_t st);
+void launch_b_mg_types(const BatchLaunch& L, hipStream_t st);
+template <typename V>
+void launch_b_mg_level(int kind, const BatchLaunch& L, hipStream_t st);
+template <typename V>
+void launch_b_mg_fine(bool up, const BatchLaunch& L, hipStream_t st);
 
 }  // namespace flipmi

@@ -76,6 +76,11 @@ struct Sites {
         summary;
     PhaseSites ph[2];
     size_t summary_off = 0;  // SolveSummary[ns]
+    // multigrid (all scenes or none): levels below the fine grid, deepest scene
+    bool mg = false;
+    int mg_levels = 0;
+    Site mg_types_fine, mg_fine_down, mg_fine_up, mg_bottom;
+    Site mg_types[MG_MAX_LEVELS], mg_down[MG_MAX_LEVELS], mg_up[MG_MAX_LEVELS];
 };
 
 template <typename T>
@@ -253,9 +258,12 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             q.ps = h->ps;
             q.tol = c.pcg_tol;
             q.max_iters = solve_iter_cap(c);
+            q.r_form = S.mg ? 1 : 0;
             r[s] = q;
+            // with multigrid the direction kernel reads z = M r (h->z holds r)
+            const T* zdir = (const T*)(S.mg ? h->mgz : h->z);
             for (int k = 0; k < 2; ++k) {
-                DirArgs<T> d{-1, h->tile_nbr, h->diag, (const T*)h->z, (const T*)h->s[k], (T*)h->s[k ^ 1], h->pslots,
+                DirArgs<T> d{-1, h->tile_nbr, h->diag, zdir, (const T*)h->s[k], (T*)h->s[k ^ 1], h->pslots,
                              h->ps};
                 UpdArgs<T> u{-1, h->tile_nbr, h->diag, (const T*)h->s[k ^ 1], (T*)h->xin[0], (T*)h->z, h->pslots,
                              h->ps};
@@ -277,6 +285,50 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
         S.upd[1] = add_site(t, u1, bg, 256);
         for (int a = 0; a < 3; ++a) S.project[a] = add_site(t, pr[a], bf[a], ELEM_NT);
     }
+    if (S.mg) {
+        int L = 0;
+        for (flip_handle* h : hs) L = std::max(L, h->nmg);
+        S.mg_levels = L;
+        std::vector<MgTypesFineArgs> tf(ns);
+        std::vector<MgFineArgs<T>> fd(ns), fu(ns);
+        std::vector<MgPairArgs> bo(ns);
+        std::vector<uint32_t> btf(ns), bfine(ns), bbot(ns, 1u);
+        for (size_t s = 0; s < ns; ++s) {
+            flip_handle* h = hs[s];
+            const MgLevel& l0 = h->mg[0];
+            tf[s] = MgTypesFineArgs{h->geo, h->tile_slot, h->diag, l0};
+            btf[s] = (uint32_t)mg_blocks(MG_B_TYPES, l0, l0);
+            fd[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, nullptr,
+                                  nullptr, h->ps};
+            fu[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, (T*)h->mgz,
+                                  h->pslots, h->ps};
+            bfine[s] = (uint32_t)h->groups;
+            bo[s] = MgPairArgs{h->mg[h->nmg - 1], h->mg[h->nmg - 1], h->ps};
+        }
+        S.mg_types_fine = add_site(t, tf, btf, 256);
+        S.mg_fine_down = add_site(t, fd, bfine, 256);
+        S.mg_fine_up = add_site(t, fu, bfine, 256);
+        S.mg_bottom = add_site(t, bo, bbot, 512);
+        for (int l = 0; l + 1 < L; ++l) {
+            // level l to l + 1, for the scenes that have both
+            std::vector<MgPairArgs> a(ns);
+            std::vector<uint32_t> bt(ns, 0u), bd(ns, 0u), bu(ns, 0u);
+            for (size_t s = 0; s < ns; ++s) {
+                flip_handle* h = hs[s];
+                const bool has = l + 1 < h->nmg;
+                const MgLevel& f = h->mg[has ? l : 0];
+                const MgLevel& c = h->mg[has ? l + 1 : 0];
+                a[s] = MgPairArgs{f, c, h->ps};
+                if (!has) continue;
+                bt[s] = (uint32_t)mg_blocks(MG_B_TYPES, f, c);
+                bd[s] = (uint32_t)mg_blocks(MG_B_DOWN, f, c);
+                bu[s] = (uint32_t)mg_blocks(MG_B_UP, f, c);
+            }
+            S.mg_types[l] = add_site(t, a, bt, 256);
+            S.mg_down[l] = add_site(t, a, bd, 256);
+            S.mg_up[l] = add_site(t, a, bu, 256);
+        }
+    }
     {
         // the summary array itself, then the summary launch that fills it
         S.summary_off = t.reserve(sizeof(SolveSummary) * ns);
@@ -296,10 +348,14 @@ bool sites_fit(const Sites& S)
     for (int k = 0; k < 2; ++k)
         r = r && ok(S.dir[k]) && ok(S.upd[k]) && ok(S.ph[k].bin_keys) && ok(S.ph[k].gather) && ok(S.ph[k].p2g) &&
             ok(S.ph[k].g2p);
+    if (S.mg) {
+        r = r && ok(S.mg_types_fine) && ok(S.mg_fine_down) && ok(S.mg_fine_up) && ok(S.mg_bottom);
+        for (int l = 0; l + 1 < S.mg_levels; ++l) r = r && ok(S.mg_types[l]) && ok(S.mg_down[l]) && ok(S.mg_up[l]);
+    }
     return r;
 }
 
-flip_status check_handles(flip_handle* const* handles, int nscenes, int* prec)
+flip_status check_handles(flip_handle* const* handles, int nscenes, int* prec, bool* mg)
 {
     if (!handles || nscenes < 1 || nscenes > FLIP_BATCH_MAX_SCENES) return FLIP_E_INVALID;
     for (int s = 0; s < nscenes; ++s) {
@@ -307,17 +363,21 @@ flip_status check_handles(flip_handle* const* handles, int nscenes, int* prec)
         if (!h) return FLIP_E_INVALID;
         if (h->prec != FLIP_FP32 && h->prec != FLIP_FP64) return FLIP_E_INVALID;
         if (h->prec != handles[0]->prec) return FLIP_E_INVALID;
-        if (h->cfg.flags & (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING | FLIP_FLAG_MULTIGRID))
+        if (h->cfg.flags & (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING)) return FLIP_E_INVALID;
+        // the preconditioner is the same for every scene of a batch
+        if ((h->cfg.flags & FLIP_FLAG_MULTIGRID) != (handles[0]->cfg.flags & FLIP_FLAG_MULTIGRID))
             return FLIP_E_INVALID;
         for (int q = 0; q < s; ++q)
             if (handles[q] == h) return FLIP_E_INVALID;
     }
     *prec = handles[0]->prec;
+    *mg = (handles[0]->cfg.flags & FLIP_FLAG_MULTIGRID) != 0;
     return FLIP_OK;
 }
 
-flip_status build_tables(const std::vector<flip_handle*>& hs, int prec, Tables& t, Sites& S)
+flip_status build_tables(const std::vector<flip_handle*>& hs, int prec, bool mg, Tables& t, Sites& S)
 {
+    S.mg = mg;
     if (prec == FLIP_FP64)
         build_sites<double>(hs, t, S);
     else
@@ -357,6 +417,21 @@ BatchLaunch L(const flip_batch* b, const Site& s)
     return l;
 }
 
+// one multigrid V-cycle z = M r of every scene: the restrictions level by
+// level down to the deepest scene's coarsest level, every scene's coarsest
+// sweeps, then the prolongations back up (a scene takes part in the level
+// launches it has, so its own order is down, bottom, up)
+template <typename T>
+void enqueue_vcycle(const flip_batch* b, hipStream_t st)
+{
+    const Sites& S = b->S;
+    launch_b_mg_fine<T>(false, L(b, S.mg_fine_down), st);
+    for (int l = 0; l + 1 < S.mg_levels; ++l) launch_b_mg_level<T>(MG_B_DOWN, L(b, S.mg_down[l]), st);
+    launch_b_mg_level<T>(MG_B_BOTTOM, L(b, S.mg_bottom), st);
+    for (int l = S.mg_levels - 2; l >= 0; --l) launch_b_mg_level<T>(MG_B_UP, L(b, S.mg_up[l]), st);
+    launch_b_mg_fine<T>(true, L(b, S.mg_fine_up), st);
+}
+
 // binning, tiles, particle-to-grid and the solver start of every scene
 template <typename T>
 void enqueue_pre(const flip_batch* b, int ph, hipStream_t st)
@@ -376,6 +451,11 @@ void enqueue_pre(const flip_batch* b, int ph, hipStream_t st)
     launch_b_tile_compact(L(b, S.tile_compact), st);
     launch_b_p2g<T>(L(b, S.ph[ph].p2g), st);
     launch_b_rhs<T, T>(L(b, S.rhs), st);
+    if (S.mg) {
+        launch_b_mg_types_fine(L(b, S.mg_types_fine), st);
+        for (int l = 0; l + 1 < S.mg_levels; ++l) launch_b_mg_types(L(b, S.mg_types[l]), st);
+        enqueue_vcycle<T>(b, st);
+    }
     launch_b_pcg_direction<T>(L(b, S.dir[0]), st);  // D_0
 }
 
@@ -387,7 +467,8 @@ void enqueue_chunk(const flip_batch* b, int iters, hipStream_t st)
 {
     const Sites& S = b->S;
     for (int i = 0; i < iters; ++i) {
-        launch_b_pcg_update<T>(L(b, S.upd[i & 1]), st);
+        launch_b_pcg_update<T>(S.mg, L(b, S.upd[i & 1]), st);
+        if (S.mg) enqueue_vcycle<T>(b, st);
         launch_b_pcg_direction<T>(L(b, S.dir[(i + 1) & 1]), st);
     }
     launch_b_summary(L(b, S.summary), st);
@@ -502,12 +583,13 @@ flip_status flip_batch_workspace_bytes(flip_handle* const* handles, int nscenes,
 {
     if (!out_bytes) return FLIP_E_INVALID;
     int prec = FLIP_FP32;
-    flip_status v = check_handles(handles, nscenes, &prec);
+    bool mg = false;
+    flip_status v = check_handles(handles, nscenes, &prec, &mg);
     if (v != FLIP_OK) return v;
     std::vector<flip_handle*> hs(handles, handles + nscenes);
     Tables t;
     Sites S;
-    v = build_tables(hs, prec, t, S);
+    v = build_tables(hs, prec, mg, t, S);
     if (v != FLIP_OK) return v;
     *out_bytes = t.bytes.size();
     return FLIP_OK;
@@ -520,7 +602,8 @@ flip_status flip_batch_create(flip_handle* const* handles, int nscenes, uint32_t
     *out = nullptr;
     if (flags & ~(uint32_t)FLIP_BATCH_GRAPHS) return FLIP_E_INVALID;
     int prec = FLIP_FP32;
-    flip_status v = check_handles(handles, nscenes, &prec);
+    bool mg = false;
+    flip_status v = check_handles(handles, nscenes, &prec, &mg);
     if (v != FLIP_OK) return v;
     flip_batch* b = new (std::nothrow) flip_batch();
     if (!b) return FLIP_E_INVALID;
@@ -528,7 +611,7 @@ flip_status flip_batch_create(flip_handle* const* handles, int nscenes, uint32_t
     b->prec = prec;
     b->flags = flags;
     Tables t;
-    v = build_tables(b->hs, prec, t, b->S);
+    v = build_tables(b->hs, prec, mg, t, b->S);
     if (v != FLIP_OK) {
         delete b;
         return v;

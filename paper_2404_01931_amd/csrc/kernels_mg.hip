@@ -23,6 +23,7 @@
 // partial sums r . z and max |r| that the next direction kernel completes.
 //
 // Every kernel first reads the solver state and exits when the solve is over.
+#include "batch.h"
 #include "common.h"
 #include "device_util.h"
 
@@ -48,15 +49,26 @@ __device__ inline int level_nc(const MgLevel& L, int i, int j, int k)
     return (i > 0) + (i < L.nx - 1) + (j > 0) + (j < L.ny - 1) + (k > 0) + (k < L.nz - 1);
 }
 
+// a level whose pointers came from a batched launch's table, marked global
+// (pointers loaded from memory are otherwise generic, and generic accesses
+// make every wait a full one)
+__device__ inline MgLevel glob(MgLevel L)
+{
+    L.b = as_global(L.b);
+    L.x = as_global(L.x);
+    L.d = as_global(L.d);
+    return L;
+}
+
 
 }  // namespace
 
 // ---- cell types of the coarse levels -----------------------------------------
 
-__global__ __launch_bounds__(256) void k_mg_types_fine(Geo g, const int32_t* __restrict__ tile_slot,
-                                                       const uint8_t* __restrict__ diag, MgLevel c)
+__device__ __forceinline__ void mg_types_fine_body(Blk b, const Geo& g, const int32_t* __restrict__ tile_slot,
+                                                   const uint8_t* __restrict__ diag, const MgLevel& c)
 {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t q = (int64_t)b.id * 256 + threadIdx.x;
     if (q >= level_count(c)) return;
     const int i = (int)(q % c.nx), j = (int)((q / c.nx) % c.ny), k = (int)(q / ((int64_t)c.nx * c.ny));
     bool fluid = false;
@@ -69,9 +81,23 @@ __global__ __launch_bounds__(256) void k_mg_types_fine(Geo g, const int32_t* __r
     c.d[q] = fluid ? (uint8_t)level_nc(c, i, j, k) : (uint8_t)0;
 }
 
-__global__ __launch_bounds__(256) void k_mg_types(MgLevel f, MgLevel c)
+__global__ __launch_bounds__(256) void k_mg_types_fine(Geo g, const int32_t* __restrict__ tile_slot,
+                                                       const uint8_t* __restrict__ diag, MgLevel c)
 {
-    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    mg_types_fine_body(plain_blk(), g, tile_slot, diag, c);
+}
+
+__global__ __launch_bounds__(256) void kb_mg_types_fine(const MgTypesFineArgs* __restrict__ tab,
+                                                        const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const MgTypesFineArgs& a = batch_args(tab, first, ns, b);
+    mg_types_fine_body(b, a.g, as_global(a.tile_slot), as_global(a.diag), glob(a.c));
+}
+
+__device__ __forceinline__ void mg_types_body(Blk b, const MgLevel& f, const MgLevel& c)
+{
+    const int64_t q = (int64_t)b.id * 256 + threadIdx.x;
     if (q >= level_count(c)) return;
     const int i = (int)(q % c.nx), j = (int)((q / c.nx) % c.ny), k = (int)(q / ((int64_t)c.nx * c.ny));
     bool fluid = false;
@@ -80,6 +106,16 @@ __global__ __launch_bounds__(256) void k_mg_types(MgLevel f, MgLevel c)
         if (fi < f.nx && fj < f.ny && fk < f.nz && f.d[level_index(f, fi, fj, fk)] > 0) fluid = true;
     }
     c.d[q] = fluid ? (uint8_t)level_nc(c, i, j, k) : (uint8_t)0;
+}
+
+__global__ __launch_bounds__(256) void k_mg_types(MgLevel f, MgLevel c) { mg_types_body(plain_blk(), f, c); }
+
+__global__ __launch_bounds__(256) void kb_mg_types(const MgPairArgs* __restrict__ tab,
+                                                   const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const MgPairArgs& a = batch_args(tab, first, ns, b);
+    mg_types_body(b, glob(a.f), glob(a.c));
 }
 
 // ---- down: dense level f to level c ---------------------------------------------
@@ -97,13 +133,24 @@ __device__ inline V recip_nc(int d)
     return d ? V(1) / (V)d : V(0);
 }
 
+// workgroups of a restriction from level f: one per 16 x 4 x 4 block, x fastest
+__host__ __device__ inline int mg_down_blocks_x(const MgLevel& f) { return (f.nx + MGD_X - 1) / MGD_X; }
+__host__ __device__ inline int mg_down_blocks_y(const MgLevel& f) { return (f.ny + MGD_Y - 1) / MGD_Y; }
+__host__ __device__ inline int64_t mg_down_blocks(const MgLevel& f)
+{
+    return (int64_t)mg_down_blocks_x(f) * mg_down_blocks_y(f) * ((f.nz + MGD_Z - 1) / MGD_Z);
+}
+
 template <typename V>
-__global__ __launch_bounds__(256) void k_mg_down(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
+__device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const MgLevel& c,
+                                             const PcgState* __restrict__ ps)
 {
     __shared__ V tv[MGD_Z][MGD_Y][MGD_X];
     if (ps->done != PCG_RUNNING) return;
+    const int gbx = mg_down_blocks_x(f), gby = mg_down_blocks_y(f);
+    const int bx = blk.id % gbx, by = (blk.id / gbx) % gby, bz = blk.id / (gbx * gby);
     const int lx = threadIdx.x & 15, ly = (threadIdx.x >> 4) & 3, lz = threadIdx.x >> 6;
-    const int i = blockIdx.x * MGD_X + lx, j = blockIdx.y * MGD_Y + ly, k = blockIdx.z * MGD_Z + lz;
+    const int i = bx * MGD_X + lx, j = by * MGD_Y + ly, k = bz * MGD_Z + lz;
     const bool in = i < f.nx && j < f.ny && k < f.nz;
     const int ic = min(i, f.nx - 1), jc = min(j, f.ny - 1), kc = min(k, f.nz - 1);
     const V* const fb = (const V*)f.b;
@@ -131,8 +178,7 @@ __global__ __launch_bounds__(256) void k_mg_down(MgLevel f, MgLevel c, const Pcg
     __syncthreads();
     if (threadIdx.x < 32) {
         const int px = threadIdx.x & 7, py = (threadIdx.x >> 3) & 1, pz = threadIdx.x >> 4;
-        const int ci = blockIdx.x * (MGD_X / 2) + px, cj = blockIdx.y * (MGD_Y / 2) + py,
-                  ck = blockIdx.z * (MGD_Z / 2) + pz;
+        const int ci = bx * (MGD_X / 2) + px, cj = by * (MGD_Y / 2) + py, ck = bz * (MGD_Z / 2) + pz;
         if (ci < c.nx && cj < c.ny && ck < c.nz) {
             const V sum = ((tv[2 * pz][2 * py][2 * px] + tv[2 * pz][2 * py][2 * px + 1]) +
                            (tv[2 * pz][2 * py + 1][2 * px] + tv[2 * pz][2 * py + 1][2 * px + 1])) +
@@ -143,10 +189,25 @@ __global__ __launch_bounds__(256) void k_mg_down(MgLevel f, MgLevel c, const Pcg
     }
 }
 
+template <typename V>
+__global__ __launch_bounds__(256) void k_mg_down(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
+{
+    mg_down_body<V>(plain_blk(), f, c, ps);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void kb_mg_down(const MgPairArgs* __restrict__ tab,
+                                                  const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const MgPairArgs& a = batch_args(tab, first, ns, b);
+    mg_down_body<V>(b, glob(a.f), glob(a.c), as_global(a.ps));
+}
+
 // ---- bottom: the coarsest level (at most 8^3 cells), one workgroup -------------
 
 template <typename V>
-__global__ __launch_bounds__(512) void k_mg_bottom(MgLevel L, const PcgState* __restrict__ ps)
+__device__ __forceinline__ void mg_bottom_body(const MgLevel& L, const PcgState* __restrict__ ps)
 {
     __shared__ V xs[2][512];
     if (ps->done != PCG_RUNNING) return;
@@ -178,14 +239,30 @@ __global__ __launch_bounds__(512) void k_mg_bottom(MgLevel L, const PcgState* __
     if (own) ((V*)L.x)[q] = xs[MG_BOTTOM_SWEEPS & 1][q];
 }
 
+template <typename V>
+__global__ __launch_bounds__(512) void k_mg_bottom(MgLevel L, const PcgState* __restrict__ ps)
+{
+    mg_bottom_body<V>(L, ps);
+}
+
+template <typename V>
+__global__ __launch_bounds__(512) void kb_mg_bottom(const MgPairArgs* __restrict__ tab,
+                                                    const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const MgPairArgs& a = batch_args(tab, first, ns, b);  // the coarsest level is f
+    mg_bottom_body<V>(glob(a.f), as_global(a.ps));
+}
+
 // ---- up: dense level f from level c --------------------------------------------
 
 // One thread per level-f cell; loads issued unconditionally as in k_mg_down.
 template <typename V>
-__global__ __launch_bounds__(256) void k_mg_up(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
+__device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLevel& c,
+                                           const PcgState* __restrict__ ps)
 {
     if (ps->done != PCG_RUNNING) return;
-    const int64_t q0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t q0 = (int64_t)blk.id * 256 + threadIdx.x;
     const int64_t ncell = level_count(f);
     const bool in = q0 < ncell;
     const int64_t e = in ? q0 : ncell - 1;
@@ -219,6 +296,21 @@ __global__ __launch_bounds__(256) void k_mg_up(MgLevel f, MgLevel c, const PcgSt
     if (in) ((V*)f.x)[e] = d ? yc + w * ((bc - (V)d * yc) + nsum) * rd : V(0);
 }
 
+template <typename V>
+__global__ __launch_bounds__(256) void k_mg_up(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
+{
+    mg_up_body<V>(plain_blk(), f, c, ps);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void kb_mg_up(const MgPairArgs* __restrict__ tab,
+                                                const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const MgPairArgs& a = batch_args(tab, first, ns, b);
+    mg_up_body<V>(b, glob(a.f), glob(a.c), as_global(a.ps));
+}
+
 // ---- launchers -----------------------------------------------------------------
 
 namespace {
@@ -241,11 +333,9 @@ void launch_mg_types(const MgLevel& f, const MgLevel& c, hipStream_t st)
 template <typename V>
 void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st)
 {
-    for (int l = 0; l + 1 < nlev; ++l) {
-        const dim3 grid((unsigned)((lv[l].nx + MGD_X - 1) / MGD_X), (unsigned)((lv[l].ny + MGD_Y - 1) / MGD_Y),
-                        (unsigned)((lv[l].nz + MGD_Z - 1) / MGD_Z));
-        hipLaunchKernelGGL(k_mg_down<V>, grid, dim3(256), 0, st, lv[l], lv[l + 1], ps);
-    }
+    for (int l = 0; l + 1 < nlev; ++l)
+        hipLaunchKernelGGL(k_mg_down<V>, dim3((unsigned)mg_down_blocks(lv[l])), dim3(256), 0, st, lv[l], lv[l + 1],
+                           ps);
     hipLaunchKernelGGL(k_mg_bottom<V>, dim3(1), dim3(512), 0, st, lv[nlev - 1], ps);
     for (int l = nlev - 2; l >= 0; --l) {
         const int64_t n = (int64_t)lv[l].nx * lv[l].ny * lv[l].nz;
@@ -255,5 +345,45 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
 
 template void launch_mg_coarse<float>(const MgLevel*, int, const PcgState*, hipStream_t);
 template void launch_mg_coarse<double>(const MgLevel*, int, const PcgState*, hipStream_t);
+
+// ---- batched launchers (grids: see mg_batch_blocks) ------------------------------
+
+int64_t mg_blocks(int kind, const MgLevel& f, const MgLevel& c)
+{
+    switch (kind) {
+    case MG_B_TYPES: return blocks_for((int64_t)c.nx * c.ny * c.nz);
+    case MG_B_DOWN: return mg_down_blocks(f);
+    case MG_B_BOTTOM: return 1;
+    default: return blocks_for((int64_t)f.nx * f.ny * f.nz);  // MG_B_UP
+    }
+}
+
+void launch_b_mg_types_fine(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_mg_types_fine, dim3(L.blocks), dim3(256), 0, st, (const MgTypesFineArgs*)L.args, L.first,
+                       L.ns);
+}
+
+void launch_b_mg_types(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_mg_types, dim3(L.blocks), dim3(256), 0, st, (const MgPairArgs*)L.args, L.first, L.ns);
+}
+
+template <typename V>
+void launch_b_mg_level(int kind, const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    const MgPairArgs* a = (const MgPairArgs*)L.args;
+    if (kind == MG_B_DOWN)
+        hipLaunchKernelGGL(kb_mg_down<V>, dim3(L.blocks), dim3(256), 0, st, a, L.first, L.ns);
+    else if (kind == MG_B_BOTTOM)
+        hipLaunchKernelGGL(kb_mg_bottom<V>, dim3(L.blocks), dim3(512), 0, st, a, L.first, L.ns);
+    else
+        hipLaunchKernelGGL(kb_mg_up<V>, dim3(L.blocks), dim3(256), 0, st, a, L.first, L.ns);
+}
+template void launch_b_mg_level<float>(int, const BatchLaunch&, hipStream_t);
+template void launch_b_mg_level<double>(int, const BatchLaunch&, hipStream_t);
 
 }  // namespace flipmi

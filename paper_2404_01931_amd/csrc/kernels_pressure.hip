@@ -175,7 +175,7 @@ __global__ __launch_bounds__(PNT) void kb_rhs(const RhsArgs<T, V>* __restrict__ 
     Blk blk;
     const RhsArgs<T, V>& a = batch_args(tab, first, ns, blk);
     rhs_body<T, V>(blk, a.g, as_global(a.tile_list), as_global(a.d_nactive), as_global(a.count), as_global(a.u), as_global(a.v), as_global(a.w), (T)a.scale, as_global(a.diag), as_global(a.b), as_global(a.z),
-                   as_global(a.x), as_global(a.s0), as_global(a.s1), as_global(a.partials), a.pstride, as_global(a.ps), a.tol, a.max_iters, 0);
+                   as_global(a.x), as_global(a.s0), as_global(a.s1), as_global(a.partials), a.pstride, as_global(a.ps), a.tol, a.max_iters, a.r_form);
 }
 
 template <typename T, typename V>
@@ -686,15 +686,15 @@ __device__ inline void mg_up_tile(V* st, MgRegs<V>& cur, int t, int tlast, int32
 }
 
 template <typename V, bool UP>
-__global__ __launch_bounds__(PCG_NT) void k_mg_fine(int na_hint, Geo g, const uint32_t* __restrict__ tile_list,
-                                                    const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
-                                                    const V* __restrict__ r, MgLevel c, V* __restrict__ z,
-                                                    double* __restrict__ pslots, const PcgState* __restrict__ ps)
+__device__ __forceinline__ void mg_fine_body(Blk blk, int na_hint, const Geo& g,
+                                             const uint32_t* __restrict__ tile_list, const int32_t* __restrict__ nbr,
+                                             const uint8_t* __restrict__ diag, const V* __restrict__ r,
+                                             const MgLevel& c, V* __restrict__ z, double* __restrict__ pslots,
+                                             const PcgState* __restrict__ ps)
 {
     __shared__ alignas(16) V stg[2][STAGE2];
     __shared__ V psum[2][PCG_NT];
     __shared__ double red[2 * (PCG_NT / WAVE)];
-    const Blk blk = plain_blk();
     const int tid = threadIdx.x;
     const HaloLane hl = halo_lane(tid);
     const int na = na_hint >= 0 ? na_hint : ps->n_active;
@@ -740,6 +740,38 @@ __global__ __launch_bounds__(PCG_NT) void k_mg_fine(int na_hint, Geo g, const ui
         slot_max(pslots, blk.n)[blk.id] = pmx;
     }
 }
+
+template <typename V, bool UP>
+__global__ __launch_bounds__(PCG_NT) void k_mg_fine(int na_hint, Geo g, const uint32_t* __restrict__ tile_list,
+                                                    const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
+                                                    const V* __restrict__ r, MgLevel c, V* __restrict__ z,
+                                                    double* __restrict__ pslots, const PcgState* __restrict__ ps)
+{
+    mg_fine_body<V, UP>(plain_blk(), na_hint, g, tile_list, nbr, diag, r, c, z, pslots, ps);
+}
+
+template <typename V, bool UP>
+__global__ __launch_bounds__(PCG_NT) void kb_mg_fine(const MgFineArgs<V>* __restrict__ tab,
+                                                     const uint32_t* __restrict__ first, int ns)
+{
+    Blk blk;
+    const MgFineArgs<V>& a = batch_args(tab, first, ns, blk);
+    MgLevel c = a.c;
+    c.b = as_global(c.b);
+    c.x = as_global(c.x);
+    mg_fine_body<V, UP>(blk, a.na_hint, a.g, as_global(a.tile_list), as_global(a.nbr), as_global(a.diag),
+                        as_global(a.r), c, as_global(a.z), as_global(a.pslots), as_global(a.ps));
+}
+
+template <typename V>
+void launch_b_mg_fine(bool up, const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    auto kern = up ? kb_mg_fine<V, true> : kb_mg_fine<V, false>;
+    hipLaunchKernelGGL(kern, dim3(L.blocks), dim3(PCG_NT), 0, st, (const MgFineArgs<V>*)L.args, L.first, L.ns);
+}
+template void launch_b_mg_fine<float>(bool, const BatchLaunch&, hipStream_t);
+template void launch_b_mg_fine<double>(bool, const BatchLaunch&, hipStream_t);
 
 template <typename V>
 void launch_mg_fine(bool up, int groups, int na_hint, const Geo& g, const uint32_t* tile_list,
@@ -897,24 +929,24 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_update(int na_hint, const int32_
     pcg_update_body<V, RF>(plain_blk(), na_hint, nbr, diag, s, x, z, pslots, ps);
 }
 
-template <typename V>
+template <typename V, bool RF>
 __global__ __launch_bounds__(PCG_NT) void kb_pcg_update(const UpdArgs<V>* __restrict__ tab,
                                                         const uint32_t* __restrict__ first, int ns)
 {
     Blk blk;
     const UpdArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_update_body<V, false>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.pslots), as_global(a.ps));
+    pcg_update_body<V, RF>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.pslots), as_global(a.ps));
 }
 
 template <typename V>
-void launch_b_pcg_update(const BatchLaunch& L, hipStream_t st)
+void launch_b_pcg_update(bool r_form, const BatchLaunch& L, hipStream_t st)
 {
     if (L.blocks == 0) return;
-    hipLaunchKernelGGL(kb_pcg_update<V>, dim3(L.blocks), dim3(PCG_NT), 0, st, (const UpdArgs<V>*)L.args,
-                       L.first, L.ns);
+    auto kern = r_form ? kb_pcg_update<V, true> : kb_pcg_update<V, false>;
+    hipLaunchKernelGGL(kern, dim3(L.blocks), dim3(PCG_NT), 0, st, (const UpdArgs<V>*)L.args, L.first, L.ns);
 }
-template void launch_b_pcg_update<float>(const BatchLaunch&, hipStream_t);
-template void launch_b_pcg_update<double>(const BatchLaunch&, hipStream_t);
+template void launch_b_pcg_update<float>(bool, const BatchLaunch&, hipStream_t);
+template void launch_b_pcg_update<double>(bool, const BatchLaunch&, hipStream_t);
 
 template <typename V>
 void launch_pcg_update(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,

@@ -187,7 +187,7 @@ class Server:
 class FlipBackend:
     """Scenes of paper_2404_01931_amd.inputs run by libflipmi on the current GPU."""
 
-    def __init__(self, graphs: bool = True, precision=None, keep_results: bool = False):
+    def __init__(self, graphs: bool = True, precision=None, keep_results: bool = False, multigrid: bool = False):
         import torch
 
         from . import flip
@@ -197,13 +197,14 @@ class FlipBackend:
         self.graphs = graphs
         self.precision = precision
         self.keep_results = keep_results
+        self.cfg_flags = flip.FLIP_FLAG_MULTIGRID if multigrid else 0
         self.results = {}   # scene name -> (pos, vel, ids) at completion, when keep_results
         self.stream = torch.cuda.Stream()   # default priority
         self._local = threading.local()
         self._bytes_cache = {}
 
     def _cfg(self, scene):
-        return self.flip.scene_config(scene, precision=self.precision)
+        return self.flip.scene_config(scene, precision=self.precision, flags=self.cfg_flags)
 
     def workspace_bytes(self, scene) -> int:
         k = scene.name

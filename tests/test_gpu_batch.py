@@ -22,8 +22,8 @@ def _scenes(count=5, seed=11):
     return [sc for _, sc in inputs.serving_scenes(count=count, seed=seed)]
 
 
-def _sim(sc, precision=None):
-    cfg, keep = flip.scene_config(sc, precision=precision)
+def _sim(sc, precision=None, cfg_flags=0):
+    cfg, keep = flip.scene_config(sc, precision=precision, flags=cfg_flags)
     return flip.Simulation(cfg, keep)
 
 
@@ -36,8 +36,8 @@ def _snapshot(sim):
     }
 
 
-def _alone(sc, steps, precision=None):
-    sim = _sim(sc, precision)
+def _alone(sc, steps, precision=None, cfg_flags=0):
+    sim = _sim(sc, precision, cfg_flags)
     sim.step(steps)
     snap = _snapshot(sim)
     sim.close()
@@ -52,13 +52,16 @@ def _assert_same(a, b, what):
         assert a[k] == b[k], (what, k, a[k], b[k])
 
 
-@pytest.mark.parametrize("flags", [0, flip.FLIP_BATCH_GRAPHS], ids=["direct", "graphs"])
-def test_batch_matches_alone_bitwise(flags):
+@pytest.mark.parametrize("flags,cfg_flags", [(0, 0), (flip.FLIP_BATCH_GRAPHS, 0),
+                                              (0, flip.FLIP_FLAG_MULTIGRID),
+                                              (flip.FLIP_BATCH_GRAPHS, flip.FLIP_FLAG_MULTIGRID)],
+                         ids=["direct", "graphs", "direct-multigrid", "graphs-multigrid"])
+def test_batch_matches_alone_bitwise(flags, cfg_flags):
     scs = _scenes(5)
     steps = 5
-    log(f"[batch] alone vs mix flags={flags}: " + ", ".join(s.name for s in scs))
-    ref = [_alone(sc, steps) for sc in scs]
-    sims = [_sim(sc) for sc in scs]
+    log(f"[batch] alone vs mix flags={flags} cfg_flags={cfg_flags}: " + ", ".join(s.name for s in scs))
+    ref = [_alone(sc, steps, cfg_flags=cfg_flags) for sc in scs]
+    sims = [_sim(sc, cfg_flags=cfg_flags) for sc in scs]
     batch = flip.Batch(sims, flags=flags)
     for _ in range(steps):
         assert batch.step(1) == flip.FLIP_OK

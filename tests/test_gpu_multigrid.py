@@ -138,11 +138,14 @@ def test_multigrid_degenerate_grids(orc):
     sim.close()
 
 
-def test_batch_refuses_multigrid_handles():
+def test_batch_refuses_mixed_preconditioners():
     log("[mg] batch refusal")
     cfg, keep = _case("drop64_fp32", MG)
-    sim = flip.Simulation(cfg, keep)
+    a = flip.Simulation(cfg, keep)
+    cfg, keep = _case("drop64_fp32", 0)
+    b = flip.Simulation(cfg, keep)
     with pytest.raises(flip.FlipError) as e:
-        flip.Batch([sim])
+        flip.Batch([a, b])
     assert e.value.status == flip.FLIP_E_INVALID
-    sim.close()
+    a.close()
+    b.close()

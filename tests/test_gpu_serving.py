@@ -14,13 +14,14 @@ from tests.gpu_util import log
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("graphs", [False, True], ids=["direct", "graphs"])
-def test_served_scenes_match_alone(graphs):
+@pytest.mark.parametrize("graphs,multigrid", [(False, False), (True, False), (True, True)],
+                         ids=["direct", "graphs", "graphs-multigrid"])
+def test_served_scenes_match_alone(graphs, multigrid):
     stream = inputs.serving_scenes(count=6, seed=21)
     # short requests of uneven length, arriving 5 ms apart
     stream = [(0.005 * i, dataclasses.replace(sc, steps=3 + (i % 3))) for i, (_, sc) in enumerate(stream)]
     reqs = requests_from_scenes(stream)
-    be = FlipBackend(graphs=graphs, keep_results=True)
+    be = FlipBackend(graphs=graphs, keep_results=True, multigrid=multigrid)
     sizes = sorted(be.workspace_bytes(r.scene) for r in reqs)
     budget = sizes[-1] + sizes[-2]          # at most two of the largest at once
     log(f"[serving] graphs={graphs} budget={budget} scenes=" + ",".join(r.scene.name for r in reqs))
@@ -30,7 +31,7 @@ def test_served_scenes_match_alone(graphs):
     assert rep.n_completed == len(reqs) and rep.n_rejected == 0 and rep.status_errors == 0
     assert rep.peak_bytes <= budget and rep.peak_scenes <= 3
     for r in reqs:
-        cfg, keep = flip.scene_config(r.scene)
+        cfg, keep = flip.scene_config(r.scene, flags=flip.FLIP_FLAG_MULTIGRID if multigrid else 0)
         sim = flip.Simulation(cfg, keep)
         sim.step(r.steps)
         ref = (sim.read(flip.FLIP_FIELD_POS), sim.read(flip.FLIP_FIELD_VEL), sim.read(flip.FLIP_FIELD_ID))
