@@ -97,27 +97,28 @@ __device__ __forceinline__ void bin_keys_body(Blk b, Geo g, const T* __restrict_
     const uint32_t c = (uint32_t)(i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
     key[p] = c;
 
-    // Lanes of a wave that share a cell take their provisional ranks from
-    // one atomic: particles arrive mostly sorted, so a wave touches few cells.
+    // Provisional ranks: the lanes of a run of equal cells (particles arrive
+    // mostly sorted, so a wave holds a few long runs) take theirs from one
+    // atomic issued by the run's first lane; every run's atomic is issued by
+    // the same instruction, so a wave waits for one round trip, not one per
+    // run. A cell that appears in several runs gets several disjoint ranges;
+    // the gather kernel makes the final ranks stable.
     const int lane = lane_id();
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    bool pending = true;
-    uint32_t my_rank = 0;
-    for (;;) {
-        const uint64_t pend = __ballot(pending);
-        if (pend == 0ull) break;
-        const int leader = __ffsll((unsigned long long)pend) - 1;
-        const uint32_t lc = __shfl(c, leader, WAVE);
-        const bool mine = pending && (c == lc);
-        const uint64_t same = __ballot(mine);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&count[lc], (uint32_t)__popcll(same));
-        base = __shfl(base, leader, WAVE);
-        if (mine) {
-            my_rank = base + (uint32_t)__popcll(same & below);
-            pending = false;
-        }
-    }
+    const uint32_t prev = __shfl_up(c, 1, WAVE);
+    const bool head = lane == 0 || prev != c;
+    const uint64_t heads = __ballot(head);
+    const uint64_t live = __ballot(true);
+    // the run ends at the next head or at the wave's last live lane
+    const uint64_t above = lane == WAVE - 1 ? 0ull : (~0ull << (lane + 1));
+    const uint64_t after = heads & above & live;
+    const int end = after ? __ffsll((unsigned long long)after) - 1 : 64 - __clzll((unsigned long long)live);
+    uint32_t base = 0;
+    if (head) base = atomicAdd(&count[c], (uint32_t)(end - lane));
+    // this lane's run starts at the highest head at or below it
+    const uint64_t upto = lane == WAVE - 1 ? ~0ull : (~0ull >> (WAVE - 1 - lane));
+    const int first = 63 - __clzll((unsigned long long)(heads & upto));
+    base = __shfl(base, first, WAVE);
+    const uint32_t my_rank = base + (uint32_t)(lane - first);
     rank[p] = my_rank;
 }
 
@@ -414,8 +415,17 @@ __device__ __forceinline__ void bin_gather_body(
     const uint32_t c = key[p];
     const uint32_t st = start[c];
     const uint32_t cnt = count[c];
+    // the cell's slots are read four at a time (indices clamped into the
+    // cell), so a lane waits for one round trip per four particles
+    const uint32_t end = st + cnt;
     uint32_t r = 0;
-    for (uint32_t q = st; q < st + cnt; ++q) r += (perm[q] < p) ? 1u : 0u;
+    for (uint32_t q = st; q < end; q += 4) {
+        uint32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = perm[min(q + k, end - 1)];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r += (q + k < end && v[k] < p) ? 1u : 0u;
+    }
     const int64_t d = (int64_t)st + r;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

@@ -69,7 +69,6 @@ __device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, dou
             }
 }
 
-// workgroup b.id handles tile (b.id % tx, (b.id / tx) % ty, b.id / (tx ty))
 // Particles of one cell, up to P2G_BATCH of them, held in registers: the
 // loads of a whole cell are issued together, one colour phase ahead of their
 // use, instead of one particle at a time.
@@ -151,6 +150,9 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
 #pragma clang fp contract(off)
     __shared__ T acc[3][P2G_BOX][2];
     const int lane = threadIdx.x;
+    // tiles in grid order across the XCDs (the work per tile varies widely:
+    // contiguous runs per XCD, which would keep a ring's particles in one L2,
+    // measured slower for the imbalance)
     const int bx = b.id % g.tx, by = (b.id / g.tx) % g.ty, bz = b.id / (g.tx * g.ty);
     const int x0 = bx * P2G_T, y0 = by * P2G_T, z0 = bz * P2G_T;
     for (int q = lane; q < 3 * P2G_BOX * 2; q += 64) (&acc[0][0][0])[q] = T(0);
@@ -383,7 +385,11 @@ __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restric
     __shared__ uint32_t row_start[64];
     __shared__ uint32_t row_pre[65];
     const int tid = threadIdx.x;
-    const int bx = b.id % g.tx, by = (b.id / g.tx) % g.ty, bz = b.id / (g.tx * g.ty);
+    // the workgroups of one XCD take one contiguous run of tiles, so the face
+    // samples a tile shares with its neighbours are mostly read from that
+    // XCD's L2 (measured 7% faster than grid order at 256^3)
+    const int tile = xcd_remap(b.id, b.n);
+    const int bx = tile % g.tx, by = (tile / g.tx) % g.ty, bz = tile / (g.tx * g.ty);
     const int x0 = bx * TILE, y0 = by * TILE, z0 = bz * TILE;
     // the tile's particles: x-row r = (j, k) of the tile holds cells
     // (x0 .. x0+7, y0+j, z0+k), whose particles are contiguous after binning
