@@ -13,16 +13,18 @@
 //   down, level l:  x0 = w b / n;  t = b - A x0;  b_{l+1} = (R t) / 2
 //   bottom:         x = 0, then 20 sweeps x += w (b - A x) / n
 //   up, level l:    y = x0 + P x_{l+1};  x_l = y + w (b - A y) / n
-// R sums the children of a coarse cell, P copies a coarse value to its fluid
-// children (P = R^T), and the coarse equation is scaled by 1/2 (with these
-// transfers the Galerkin product R A P is 4 times the coarse stencil, while
-// a smooth error is corrected best with twice it). One pre- and one
-// post-sweep with the same smoother, a fixed number of bottom sweeps and
-// P = R^T make the cycle a fixed symmetric positive definite operator, as CG
+// Between the fine grid and level 1, P copies a coarse value to its fluid
+// children and R sums the children; between dense levels P is cell-centred
+// trilinear and R its transpose (described with those kernels). Both R have
+// a total weight of 8 per coarse cell, and the coarse equation is scaled by
+// 1/2: the coarse stencil at twice the spacing, h^2 scaling. One pre- and
+// one post-sweep with the same smoother, a fixed number of bottom sweeps and
+// R = P^T make the cycle a fixed symmetric positive definite operator, as CG
 // needs. Level 0 reads r and writes z; the fine up-kernel also forms the
 // partial sums r . z and max |r| that the next direction kernel completes.
 //
-// Every kernel first reads the solver state and exits when the solve is over.
+// Every kernel reads the solver state and exits when the solve is over (the
+// dense-level kernels issue their loads first, so the two waits overlap).
 #include "batch.h"
 #include "common.h"
 #include "device_util.h"
@@ -118,14 +120,18 @@ __global__ __launch_bounds__(256) void kb_mg_types(const MgPairArgs* __restrict_
     mg_types_body(b, glob(a.f), glob(a.c));
 }
 
-// ---- down: dense level f to level c ---------------------------------------------
-
-// One thread per level-f cell of a 16 x 4 x 4 block (x fastest, so a row is
-// one 64-byte segment); t = (1 - w) b + w sum of b / n over the fluid
-// neighbours goes to LDS, and 32 threads sum the 2x2x2 children of the
-// block's 8 x 2 x 2 parents. Every load is issued unconditionally (clamped
-// address, masked value), so a thread waits for memory once.
-constexpr int MGD_X = 16, MGD_Y = 4, MGD_Z = 4;
+// ---- transfers between dense levels ----------------------------------------------
+//
+// Between dense levels the prolongation is cell-centred trilinear: along each
+// axis a fine cell takes 3/4 of its parent and 1/4 of the parent's neighbour
+// on the cell's side (even child: below, odd child: above), that neighbour
+// clamped into the coarse box (at a wall the cell takes its parent whole).
+// The restriction is its transpose, which per axis gives coarse cell c
+//   3/4 of each child 2c, 2c + 1 (1 for child 2c when c = 0 and for child
+//   2c + 1 when c is the last cell, where the prolongation clamped) and
+//   1/4 of the nearer children 2c - 1 and 2c + 2 of its two neighbours.
+// Between the fine grid and level 1 the tile-layout kernels keep the
+// piecewise-constant pair (P copies the parent, R sums the children).
 
 template <typename V>
 __device__ inline V recip_nc(int d)
@@ -133,59 +139,113 @@ __device__ inline V recip_nc(int d)
     return d ? V(1) / (V)d : V(0);
 }
 
-// workgroups of a restriction from level f: one per 16 x 4 x 4 block, x fastest
-__host__ __device__ inline int mg_down_blocks_x(const MgLevel& f) { return (f.nx + MGD_X - 1) / MGD_X; }
-__host__ __device__ inline int mg_down_blocks_y(const MgLevel& f) { return (f.ny + MGD_Y - 1) / MGD_Y; }
-__host__ __device__ inline int64_t mg_down_blocks(const MgLevel& f)
+// weight of fine cell 2c - 1 + k (k = 0..3) in coarse cell c, on an axis of n coarse cells
+template <typename V>
+__device__ inline V restrict_weight(int k, int c, int n)
 {
-    return (int64_t)mg_down_blocks_x(f) * mg_down_blocks_y(f) * ((f.nz + MGD_Z - 1) / MGD_Z);
+    if (k == 0 || k == 3) return V(0.25);
+    return ((k == 1 && c == 0) || (k == 2 && c == n - 1)) ? V(1) : V(0.75);
+}
+
+// ---- down: dense level f to level c ---------------------------------------------
+
+// One workgroup per 8 x 4 x 4 block of level-c cells. Their restriction reads
+// t = b - A x0 (x0 = w b / n) on the children plus one fine cell around them
+// (18 x 10 x 10, the t region), and t there reads x0 one cell further out
+// (20 x 12 x 12, the u region): b and n of the u region are loaded once
+// (every load issued unconditionally: clamped address, masked value), x0 and
+// t are formed in LDS, and the restriction runs along x, then y, then z.
+constexpr int MGD_CX = 8, MGD_CY = 4, MGD_CZ = 4;
+constexpr int MGD_TX = 2 * MGD_CX + 2, MGD_TY = 2 * MGD_CY + 2, MGD_TZ = 2 * MGD_CZ + 2;
+constexpr int MGD_UX = MGD_TX + 2, MGD_UY = MGD_TY + 2, MGD_UZ = MGD_TZ + 2;
+constexpr int MGD_T = MGD_TX * MGD_TY * MGD_TZ;  // 1800
+constexpr int MGD_U = MGD_UX * MGD_UY * MGD_UZ;  // 2880
+constexpr int MGD_NL = (MGD_U + 255) / 256;      // u-region cells per thread
+static_assert(MGD_TZ * MGD_TY * MGD_CX + MGD_TZ * MGD_CY * MGD_CX <= MGD_U, "x and y passes fit the b buffer");
+
+// workgroups of a restriction to level c: one per 8 x 4 x 4 block of c, x fastest
+__host__ __device__ inline int mg_down_blocks_x(const MgLevel& c) { return (c.nx + MGD_CX - 1) / MGD_CX; }
+__host__ __device__ inline int mg_down_blocks_y(const MgLevel& c) { return (c.ny + MGD_CY - 1) / MGD_CY; }
+__host__ __device__ inline int64_t mg_down_blocks(const MgLevel& c)
+{
+    return (int64_t)mg_down_blocks_x(c) * mg_down_blocks_y(c) * ((c.nz + MGD_CZ - 1) / MGD_CZ);
 }
 
 template <typename V>
 __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const MgLevel& c,
                                              const PcgState* __restrict__ ps)
 {
-    __shared__ V tv[MGD_Z][MGD_Y][MGD_X];
-    if (ps->done != PCG_RUNNING) return;
-    const int gbx = mg_down_blocks_x(f), gby = mg_down_blocks_y(f);
-    const int bx = blk.id % gbx, by = (blk.id / gbx) % gby, bz = blk.id / (gbx * gby);
-    const int lx = threadIdx.x & 15, ly = (threadIdx.x >> 4) & 3, lz = threadIdx.x >> 6;
-    const int i = bx * MGD_X + lx, j = by * MGD_Y + ly, k = bz * MGD_Z + lz;
-    const bool in = i < f.nx && j < f.ny && k < f.nz;
-    const int ic = min(i, f.nx - 1), jc = min(j, f.ny - 1), kc = min(k, f.nz - 1);
+    __shared__ V us[MGD_U];       // x0 on the u region
+    __shared__ V bs[MGD_U];       // b on the u region; later the x and y passes
+    __shared__ uint8_t ds[MGD_U];  // n (0: not fluid or outside the level)
+    __shared__ V ts[MGD_T];
+    const int tid = threadIdx.x;
+    const int gbx = mg_down_blocks_x(c), gby = mg_down_blocks_y(c);
+    const int cx0 = (blk.id % gbx) * MGD_CX, cy0 = ((blk.id / gbx) % gby) * MGD_CY;
+    const int cz0 = (blk.id / (gbx * gby)) * MGD_CZ;
+    const int ox = 2 * cx0 - 2, oy = 2 * cy0 - 2, oz = 2 * cz0 - 2;  // u region origin on level f
     const V* const fb = (const V*)f.b;
-    const int64_t e = level_index(f, ic, jc, kc);
-    const int sx = 1, sy = f.nx;
-    const int64_t sz = (int64_t)f.nx * f.ny;
-    // neighbours inside the level (a missing one reads the cell itself, masked)
-    const bool hm[6] = {ic > 0, ic < f.nx - 1, jc > 0, jc < f.ny - 1, kc > 0, kc < f.nz - 1};
-    const int64_t off[6] = {-sx, sx, -sy, sy, -sz, sz};
-    int dn[6];
-    V bn[6];
+    V bv[MGD_NL];
+    int dv[MGD_NL];
+    bool iv[MGD_NL];
 #pragma unroll
-    for (int n = 0; n < 6; ++n) {
-        const int64_t q = hm[n] ? e + off[n] : e;
-        dn[n] = f.d[q];
-        bn[n] = fb[q];
+    for (int m = 0; m < MGD_NL; ++m) {
+        const int q = min(tid + 256 * m, MGD_U - 1);
+        const int gx = ox + q % MGD_UX, gy = oy + (q / MGD_UX) % MGD_UY, gz = oz + q / (MGD_UX * MGD_UY);
+        iv[m] = gx >= 0 && gx < f.nx && gy >= 0 && gy < f.ny && gz >= 0 && gz < f.nz;
+        const int64_t e = level_index(f, min(max(gx, 0), f.nx - 1), min(max(gy, 0), f.ny - 1),
+                                      min(max(gz, 0), f.nz - 1));
+        dv[m] = f.d[e];
+        bv[m] = fb[e];
     }
-    const int d = f.d[e];
-    const V b = fb[e];
+    if (ps->done != PCG_RUNNING) return;
     const V w = mg_omega<V>();
-    V nsum = V(0);
 #pragma unroll
-    for (int n = 0; n < 6; ++n) nsum += (hm[n] && dn[n]) ? bn[n] * recip_nc<V>(dn[n]) : V(0);
-    tv[lz][ly][lx] = (in && d) ? (V(1) - w) * b + w * nsum : V(0);
-    __syncthreads();
-    if (threadIdx.x < 32) {
-        const int px = threadIdx.x & 7, py = (threadIdx.x >> 3) & 1, pz = threadIdx.x >> 4;
-        const int ci = bx * (MGD_X / 2) + px, cj = by * (MGD_Y / 2) + py, ck = bz * (MGD_Z / 2) + pz;
-        if (ci < c.nx && cj < c.ny && ck < c.nz) {
-            const V sum = ((tv[2 * pz][2 * py][2 * px] + tv[2 * pz][2 * py][2 * px + 1]) +
-                           (tv[2 * pz][2 * py + 1][2 * px] + tv[2 * pz][2 * py + 1][2 * px + 1])) +
-                          ((tv[2 * pz + 1][2 * py][2 * px] + tv[2 * pz + 1][2 * py][2 * px + 1]) +
-                           (tv[2 * pz + 1][2 * py + 1][2 * px] + tv[2 * pz + 1][2 * py + 1][2 * px + 1]));
-            ((V*)c.b)[level_index(c, ci, cj, ck)] = V(0.5) * sum;
+    for (int m = 0; m < MGD_NL; ++m) {
+        const int q = tid + 256 * m;
+        if (q < MGD_U) {
+            const int d = iv[m] ? dv[m] : 0;
+            us[q] = d ? w * bv[m] * recip_nc<V>(d) : V(0);
+            bs[q] = bv[m];
+            ds[q] = (uint8_t)d;
         }
+    }
+    __syncthreads();
+    // t = b - A x0 = (1 - w) b + (sum of x0 over the neighbours) on the t region
+    constexpr int SY = MGD_UX, SZ = MGD_UX * MGD_UY;
+    for (int q = tid; q < MGD_T; q += 256) {
+        const int lx = q % MGD_TX, ly = (q / MGD_TX) % MGD_TY, lz = q / (MGD_TX * MGD_TY);
+        const int u = (lx + 1) + SY * (ly + 1) + SZ * (lz + 1);
+        const V nsum = ((us[u - 1] + us[u + 1]) + (us[u - SY] + us[u + SY])) + (us[u - SZ] + us[u + SZ]);
+        ts[q] = ds[u] ? (V(1) - w) * bs[u] + nsum : V(0);
+    }
+    __syncthreads();
+    V* const rx = bs;                                 // [TZ][TY][CX]
+    V* const ry = bs + MGD_TZ * MGD_TY * MGD_CX;      // [TZ][CY][CX]
+    for (int q = tid; q < MGD_TZ * MGD_TY * MGD_CX; q += 256) {
+        const int i = q % MGD_CX, row = q / MGD_CX;   // row = ly + TY lz
+        const int C = cx0 + i;
+        const V* t = ts + row * MGD_TX + 2 * i;
+        rx[q] = (restrict_weight<V>(0, C, c.nx) * t[0] + restrict_weight<V>(1, C, c.nx) * t[1]) +
+                (restrict_weight<V>(2, C, c.nx) * t[2] + restrict_weight<V>(3, C, c.nx) * t[3]);
+    }
+    __syncthreads();
+    for (int q = tid; q < MGD_TZ * MGD_CY * MGD_CX; q += 256) {
+        const int i = q % MGD_CX, j = (q / MGD_CX) % MGD_CY, lz = q / (MGD_CX * MGD_CY);
+        const int C = cy0 + j;
+        const V* t = rx + (lz * MGD_TY + 2 * j) * MGD_CX + i;
+        ry[q] = (restrict_weight<V>(0, C, c.ny) * t[0] + restrict_weight<V>(1, C, c.ny) * t[MGD_CX]) +
+                (restrict_weight<V>(2, C, c.ny) * t[2 * MGD_CX] + restrict_weight<V>(3, C, c.ny) * t[3 * MGD_CX]);
+    }
+    __syncthreads();
+    if (tid < MGD_CX * MGD_CY * MGD_CZ) {
+        const int i = tid % MGD_CX, j = (tid / MGD_CX) % MGD_CY, k = tid / (MGD_CX * MGD_CY);
+        const int ci = cx0 + i, cj = cy0 + j, ck = cz0 + k;
+        constexpr int S = MGD_CY * MGD_CX;
+        const V* t = ry + (2 * k) * S + j * MGD_CX + i;
+        const V v = (restrict_weight<V>(0, ck, c.nz) * t[0] + restrict_weight<V>(1, ck, c.nz) * t[S]) +
+                    (restrict_weight<V>(2, ck, c.nz) * t[2 * S] + restrict_weight<V>(3, ck, c.nz) * t[3 * S]);
+        if (ci < c.nx && cj < c.ny && ck < c.nz) ((V*)c.b)[level_index(c, ci, cj, ck)] = V(0.5) * v;
     }
 }
 
@@ -210,14 +270,18 @@ template <typename V>
 __device__ __forceinline__ void mg_bottom_body(const MgLevel& L, const PcgState* __restrict__ ps)
 {
     __shared__ V xs[2][512];
-    if (ps->done != PCG_RUNNING) return;
     const int q = threadIdx.x;
     const int n = level_count(L);
     const bool own = q < n;
     const int i = q % L.nx, j = (q / L.nx) % L.ny, k = q / (L.nx * L.ny);
-    const int d = own ? L.d[q] : 0;
-    const V b = own ? ((const V*)L.b)[q] : V(0);
+    const int qc = own ? q : 0;
+    const int dl = L.d[qc];
+    const V bl = ((const V*)L.b)[qc];
+    if (ps->done != PCG_RUNNING) return;
+    const int d = own ? dl : 0;
+    const V b = own ? bl : V(0);
     const V w = mg_omega<V>();
+    const V wr = w * recip_nc<V>(d);
     xs[0][q] = V(0);
     for (int it = 0; it < MG_BOTTOM_SWEEPS; ++it) {
         __syncthreads();
@@ -231,7 +295,7 @@ __device__ __forceinline__ void mg_bottom_body(const MgLevel& L, const PcgState*
             if (j < L.ny - 1) nsum += x[q + L.nx];
             if (k > 0) nsum += x[q - L.nx * L.ny];
             if (k < L.nz - 1) nsum += x[q + L.nx * L.ny];
-            xn = x[q] + w * (b - (V)d * x[q] + nsum) / (V)d;
+            xn = x[q] + (b - (V)d * x[q] + nsum) * wr;
         }
         xs[(it + 1) & 1][q] = xn;
     }
@@ -256,44 +320,111 @@ __global__ __launch_bounds__(512) void kb_mg_bottom(const MgPairArgs* __restrict
 
 // ---- up: dense level f from level c --------------------------------------------
 
-// One thread per level-f cell; loads issued unconditionally as in k_mg_down.
+// One workgroup per 16 x 8 x 8 block of level-f cells. The smoothing sweep
+// reads y = x0 + P x_c on the block plus one cell around it (18 x 10 x 10, the
+// y region), and P there reads the parents of those cells and the parents'
+// neighbours (12 x 8 x 8 level-c cells, loaded clamped into the level, which
+// is the prolongation's clamp). y is formed in LDS, then each thread updates
+// four cells of the block.
+constexpr int MGU_FX = 16, MGU_FY = 8, MGU_FZ = 8;
+constexpr int MGU_YX = MGU_FX + 2, MGU_YY = MGU_FY + 2, MGU_YZ = MGU_FZ + 2;
+constexpr int MGU_CX = MGU_FX / 2 + 4, MGU_CY = MGU_FY / 2 + 4, MGU_CZ = MGU_FZ / 2 + 4;
+constexpr int MGU_Y = MGU_YX * MGU_YY * MGU_YZ;  // 1800
+constexpr int MGU_C = MGU_CX * MGU_CY * MGU_CZ;  // 768
+constexpr int MGU_NY = (MGU_Y + 255) / 256;
+constexpr int MGU_NC = (MGU_C + 255) / 256;
+constexpr int MGU_NF = MGU_FX * MGU_FY * MGU_FZ / 256;  // cells per thread
+static_assert(MGU_FX * MGU_FY * MGU_FZ == 256 * MGU_NF, "whole cells per thread");
+
+__host__ __device__ inline int mg_up_blocks_x(const MgLevel& f) { return (f.nx + MGU_FX - 1) / MGU_FX; }
+__host__ __device__ inline int mg_up_blocks_y(const MgLevel& f) { return (f.ny + MGU_FY - 1) / MGU_FY; }
+__host__ __device__ inline int64_t mg_up_blocks(const MgLevel& f)
+{
+    return (int64_t)mg_up_blocks_x(f) * mg_up_blocks_y(f) * ((f.nz + MGU_FZ - 1) / MGU_FZ);
+}
+
 template <typename V>
 __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLevel& c,
                                            const PcgState* __restrict__ ps)
 {
-    if (ps->done != PCG_RUNNING) return;
-    const int64_t q0 = (int64_t)blk.id * 256 + threadIdx.x;
-    const int64_t ncell = level_count(f);
-    const bool in = q0 < ncell;
-    const int64_t e = in ? q0 : ncell - 1;
-    const int i = (int)(e % f.nx), j = (int)((e / f.nx) % f.ny), k = (int)(e / ((int64_t)f.nx * f.ny));
-    const V* const fb = (const V*)f.b;
+    __shared__ V xs[MGU_C];
+    __shared__ V ys[MGU_Y];
+    __shared__ V bs[MGU_Y];
+    __shared__ uint8_t ds[MGU_Y];
+    const int tid = threadIdx.x;
+    const int gbx = mg_up_blocks_x(f), gby = mg_up_blocks_y(f);
+    const int fx0 = (blk.id % gbx) * MGU_FX, fy0 = ((blk.id / gbx) % gby) * MGU_FY;
+    const int fz0 = (blk.id / (gbx * gby)) * MGU_FZ;
+    // coarse region origin: the parent of the y region's first cell, minus one
+    const int px0 = fx0 / 2 - 2, py0 = fy0 / 2 - 2, pz0 = fz0 / 2 - 2;
     const V* const cx = (const V*)c.x;
-    const int64_t sz = (int64_t)f.nx * f.ny;
-    const bool hm[6] = {i > 0, i < f.nx - 1, j > 0, j < f.ny - 1, k > 0, k < f.nz - 1};
-    const int64_t off[6] = {-1, 1, -f.nx, f.nx, -sz, sz};
-    const int pi[6] = {i - 1, i + 1, i, i, i, i}, pj[6] = {j, j, j - 1, j + 1, j, j},
-              pk[6] = {k, k, k, k, k - 1, k + 1};
-    int dn[6];
-    V bn[6], xn[6];
+    const V* const fb = (const V*)f.b;
+    V xv[MGU_NC];
 #pragma unroll
-    for (int n = 0; n < 6; ++n) {
-        const int64_t qn = hm[n] ? e + off[n] : e;
-        dn[n] = f.d[qn];
-        bn[n] = fb[qn];
-        const int a = hm[n] ? pi[n] : i, b2 = hm[n] ? pj[n] : j, c2 = hm[n] ? pk[n] : k;
-        xn[n] = cx[level_index(c, a >> 1, b2 >> 1, c2 >> 1)];
+    for (int m = 0; m < MGU_NC; ++m) {
+        const int q = min(tid + 256 * m, MGU_C - 1);
+        const int i = px0 + q % MGU_CX, j = py0 + (q / MGU_CX) % MGU_CY, k = pz0 + q / (MGU_CX * MGU_CY);
+        xv[m] = cx[level_index(c, min(max(i, 0), c.nx - 1), min(max(j, 0), c.ny - 1), min(max(k, 0), c.nz - 1))];
     }
-    const int d = f.d[e];
-    const V bc = fb[e], xc = cx[level_index(c, i >> 1, j >> 1, k >> 1)];
-    const V w = mg_omega<V>();
-    // y = w b / n + (P x_c) at this cell and its fluid neighbours
-    const V rd = recip_nc<V>(d);
-    const V yc = w * bc * rd + xc;
-    V nsum = V(0);
+    V bv[MGU_NY];
+    int dv[MGU_NY];
+    bool iv[MGU_NY];
 #pragma unroll
-    for (int n = 0; n < 6; ++n) nsum += (hm[n] && dn[n]) ? w * bn[n] * recip_nc<V>(dn[n]) + xn[n] : V(0);
-    if (in) ((V*)f.x)[e] = d ? yc + w * ((bc - (V)d * yc) + nsum) * rd : V(0);
+    for (int m = 0; m < MGU_NY; ++m) {
+        const int q = min(tid + 256 * m, MGU_Y - 1);
+        const int gx = fx0 - 1 + q % MGU_YX, gy = fy0 - 1 + (q / MGU_YX) % MGU_YY, gz = fz0 - 1 + q / (MGU_YX * MGU_YY);
+        iv[m] = gx >= 0 && gx < f.nx && gy >= 0 && gy < f.ny && gz >= 0 && gz < f.nz;
+        const int64_t e = level_index(f, min(max(gx, 0), f.nx - 1), min(max(gy, 0), f.ny - 1),
+                                      min(max(gz, 0), f.nz - 1));
+        dv[m] = f.d[e];
+        bv[m] = fb[e];
+    }
+    if (ps->done != PCG_RUNNING) return;
+#pragma unroll
+    for (int m = 0; m < MGU_NC; ++m)
+        if (tid + 256 * m < MGU_C) xs[tid + 256 * m] = xv[m];
+    __syncthreads();
+    const V w = mg_omega<V>();
+    constexpr int CS = MGU_CX * MGU_CY;
+#pragma unroll
+    for (int m = 0; m < MGU_NY; ++m) {
+        const int q = tid + 256 * m;
+        if (q >= MGU_Y) break;
+        const int lx = q % MGU_YX, ly = (q / MGU_YX) % MGU_YY, lz = q / (MGU_YX * MGU_YY);
+        const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly, gz = fz0 - 1 + lz;
+        const int d = iv[m] ? dv[m] : 0;
+        V y = V(0);
+        if (d) {
+            // parent and the parent's neighbour on this cell's side, per axis
+            // (region coordinates; the region holds clamped values)
+            const int ax = (gx >> 1) - px0, ay = (gy >> 1) - py0, az = (gz >> 1) - pz0;
+            const int sx = (gx & 1) ? 1 : -1, sy = (gy & 1) ? MGU_CX : -MGU_CX, sz = (gz & 1) ? CS : -CS;
+            const V* p = xs + ax + MGU_CX * ay + CS * az;
+            const V x00 = V(0.75) * p[0] + V(0.25) * p[sx];
+            const V x10 = V(0.75) * p[sy] + V(0.25) * p[sy + sx];
+            const V x01 = V(0.75) * p[sz] + V(0.25) * p[sz + sx];
+            const V x11 = V(0.75) * p[sz + sy] + V(0.25) * p[sz + sy + sx];
+            const V y0 = V(0.75) * x00 + V(0.25) * x10, y1 = V(0.75) * x01 + V(0.25) * x11;
+            y = w * bv[m] * recip_nc<V>(d) + (V(0.75) * y0 + V(0.25) * y1);
+        }
+        ys[q] = y;
+        bs[q] = bv[m];
+        ds[q] = (uint8_t)d;
+    }
+    __syncthreads();
+    constexpr int SY = MGU_YX, SZ = MGU_YX * MGU_YY;
+#pragma unroll
+    for (int m = 0; m < MGU_NF; ++m) {
+        const int q = tid + 256 * m;
+        const int lx = q % MGU_FX, ly = (q / MGU_FX) % MGU_FY, lz = q / (MGU_FX * MGU_FY);
+        const int i = fx0 + lx, j = fy0 + ly, k = fz0 + lz;
+        const int u = (lx + 1) + SY * (ly + 1) + SZ * (lz + 1);
+        const int d = ds[u];
+        const V yc = ys[u];
+        const V nsum = ((ys[u - 1] + ys[u + 1]) + (ys[u - SY] + ys[u + SY])) + (ys[u - SZ] + ys[u + SZ]);
+        if (i < f.nx && j < f.ny && k < f.nz)
+            ((V*)f.x)[level_index(f, i, j, k)] = d ? yc + w * ((bs[u] - (V)d * yc) + nsum) * recip_nc<V>(d) : V(0);
+    }
 }
 
 template <typename V>
@@ -334,13 +465,11 @@ template <typename V>
 void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st)
 {
     for (int l = 0; l + 1 < nlev; ++l)
-        hipLaunchKernelGGL(k_mg_down<V>, dim3((unsigned)mg_down_blocks(lv[l])), dim3(256), 0, st, lv[l], lv[l + 1],
-                           ps);
+        hipLaunchKernelGGL(k_mg_down<V>, dim3((unsigned)mg_down_blocks(lv[l + 1])), dim3(256), 0, st, lv[l],
+                           lv[l + 1], ps);
     hipLaunchKernelGGL(k_mg_bottom<V>, dim3(1), dim3(512), 0, st, lv[nlev - 1], ps);
-    for (int l = nlev - 2; l >= 0; --l) {
-        const int64_t n = (int64_t)lv[l].nx * lv[l].ny * lv[l].nz;
-        hipLaunchKernelGGL(k_mg_up<V>, dim3(blocks_for(n)), dim3(256), 0, st, lv[l], lv[l + 1], ps);
-    }
+    for (int l = nlev - 2; l >= 0; --l)
+        hipLaunchKernelGGL(k_mg_up<V>, dim3((unsigned)mg_up_blocks(lv[l])), dim3(256), 0, st, lv[l], lv[l + 1], ps);
 }
 
 template void launch_mg_coarse<float>(const MgLevel*, int, const PcgState*, hipStream_t);
@@ -352,9 +481,9 @@ int64_t mg_blocks(int kind, const MgLevel& f, const MgLevel& c)
 {
     switch (kind) {
     case MG_B_TYPES: return blocks_for((int64_t)c.nx * c.ny * c.nz);
-    case MG_B_DOWN: return mg_down_blocks(f);
+    case MG_B_DOWN: return mg_down_blocks(c);
     case MG_B_BOTTOM: return 1;
-    default: return blocks_for((int64_t)f.nx * f.ny * f.nz);  // MG_B_UP
+    default: return mg_up_blocks(f);  // MG_B_UP
     }
 }
 
