@@ -125,7 +125,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
         std::vector<GatherArgs<T>> ag(ns);
         std::vector<P2GArgs<T>> ap(ns);
         std::vector<G2PArgs<T>> a2(ns);
-        std::vector<uint32_t> bp(ns), bt(ns);
+        std::vector<uint32_t> bp(ns), bt(ns), b2g(ns);
         for (size_t s = 0; s < ns; ++s) {
             flip_handle* h = hs[s];
             const Geo& g = h->geo;
@@ -184,10 +184,11 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             a2[s] = q;
             bp[s] = elem_blocks(n);
             bt[s] = (uint32_t)h->sz.T;
+            b2g[s] = (uint32_t)p2g_blocks(g);
         }
         S.ph[ph].bin_keys = add_site(t, ak, bp, ELEM_NT);
         S.ph[ph].gather = add_site(t, ag, bp, ELEM_NT);
-        S.ph[ph].p2g = add_site(t, ap, bt, 64);
+        S.ph[ph].p2g = add_site(t, ap, b2g, 64);
         S.ph[ph].g2p = add_site(t, a2, bt, 256);
     }
     {

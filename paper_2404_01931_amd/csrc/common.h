@@ -135,7 +135,9 @@ void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint
                   int32_t* tile_slot, uint32_t* tile_list, int32_t* tile_nbr, uint32_t* d_nactive,
                   uint32_t* scan_tmp, hipStream_t st);
 
-// particle-to-grid for all faces, with gravity (gdt = g * dt per axis) and walls
+// particle-to-grid for all faces, with gravity (gdt = g * dt per axis) and walls;
+// p2g_blocks: its workgroup count (one per 10^3 block of cells)
+int64_t p2g_blocks(const Geo& g);
 template <typename T>
 void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint32_t* start,
                 const uint32_t* count, const T gdt[3], T* const old[3], T* const star[3],

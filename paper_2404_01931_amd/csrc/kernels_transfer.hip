@@ -22,26 +22,47 @@ __device__ inline T hat(T r)
     return a > T(0) ? a : T(0);
 }
 
-// Particle-to-grid as an LDS splat, one wave per 8x8x8 tile of cells.
+// Particle-to-grid as an LDS splat, one wave per 10x10x10 block of cells.
 //
-// The wave owns the tile's faces and accumulates their weight sums W and
-// weighted velocity sums M in LDS (u: 9x8x8 samples, v: 8x9x8, w: 8x8x9; the
-// ninth layer covers the domain's high side). It scatters every particle of
-// the tile and of the one-cell ring around it; samples outside the tile are
-// left to the neighbouring tile. A particle of cell c only reaches samples
-// within one index of c on each axis, so cells whose coordinates agree modulo
-// 3 never reach a common sample: the cells are visited in 27 phases, one per
-// residue class (at most 4 x 4 x 4 cells of the 10^3 ring box, one per lane),
-// and within a phase every lane updates its own samples with plain LDS
-// read-modify-writes. Each sample therefore sums its contributions in a fixed
+// The wave owns the block's faces and accumulates their weight sums W and
+// weighted velocity sums M in LDS (u: 11x10x10 samples, v: 10x11x10, w:
+// 10x10x11; the eleventh layer covers the domain's high side). It scatters
+// every particle of the block and of the one-cell ring around it; samples
+// outside the block are left to the neighbouring block. A particle of cell c
+// only reaches samples within one index of c on each axis, so cells whose
+// coordinates agree modulo 3 never reach a common sample: the cells are
+// visited in 27 phases, one per residue class (4 x 4 x 4 cells of the 12^3
+// ring box, one per lane: the block side is chosen so that every lane has a
+// cell in every phase), and within a phase every lane adds to its own
+// samples only. Each sample therefore sums its contributions in a fixed
 // order (phase, then particle order in the cell): the result is the same on
-// every run, needs no atomics, and - because each weight is rounded once and
-// enters W and M unchanged (no contraction) - a uniform power-of-two velocity
-// comes back exactly. Hat arguments are formed in double: in float, x / dx
-// carries an absolute error of ~1e-6 cells, a large relative error for the
-// small weights near the edge of a hat's support.
-constexpr int P2G_T = 8;
-constexpr int P2G_BOX = (P2G_T + 1) * P2G_T * P2G_T;  // 576 samples per component
+// every run and - because each weight is rounded once and enters W and M
+// unchanged (no contraction) - a uniform power-of-two velocity comes back
+// exactly. Hat arguments are formed in double: in float, x / dx carries an
+// absolute error of ~1e-6 cells, a large relative error for the small
+// weights near the edge of a hat's support.
+constexpr int P2G_T = 10;
+constexpr int P2G_BOX = (P2G_T + 1) * P2G_T * P2G_T;  // 1100 samples per component
+
+// blocks of the particle-to-grid launch, x fastest
+__host__ __device__ inline int p2g_bx(const Geo& g) { return (g.nx + P2G_T - 1) / P2G_T; }
+__host__ __device__ inline int p2g_by(const Geo& g) { return (g.ny + P2G_T - 1) / P2G_T; }
+__host__ __device__ inline int p2g_bz(const Geo& g) { return (g.nz + P2G_T - 1) / P2G_T; }
+int64_t p2g_blocks(const Geo& g) { return (int64_t)p2g_bx(g) * p2g_by(g) * p2g_bz(g); }
+
+// Add to an LDS word without reading it back into the wave (the LDS unit's
+// float add, rounded to nearest like the VALU's). Only one lane of a
+// workgroup adds to a given sample between two barriers, and a lane's adds
+// are applied in its program order, so each sum is still formed in a fixed
+// order. Used for FP64 sums (at 256^3: 2.86 ms per step against 3.74 ms with
+// read-modify-writes); FP32 sums keep the read-modify-write, which measured
+// several times faster than the LDS unit's FP32 add (1.85 against 12.2 ms).
+template <typename T>
+struct P2GAdd {
+    static constexpr bool lds_unit = sizeof(T) == 8;
+};
+__device__ inline void lds_add(float* a, float v) { __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline void lds_add(double* a, double v) { __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 
 template <typename T, int A>
 __device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, double gy, double gz, T v)
@@ -64,8 +85,13 @@ __device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, dou
                 if (li < 0 || li >= DX || lj < 0 || lj >= DY || lk < 0 || lk >= DZ) continue;
                 const T w = (T)(wx[di] * wy[dj] * wz[dk]);
                 T* a = acc[li + DX * (lj + DY * lk)];
-                a[0] = a[0] + w;
-                a[1] = fma(v, w, a[1]);
+                if (P2GAdd<T>::lds_unit) {
+                    lds_add(a, w);
+                    lds_add(a + 1, v * w);
+                } else {
+                    a[0] = a[0] + w;
+                    a[1] = fma(v, w, a[1]);
+                }
             }
 }
 
@@ -153,7 +179,8 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
     // tiles in grid order across the XCDs (the work per tile varies widely:
     // contiguous runs per XCD, which would keep a ring's particles in one L2,
     // measured slower for the imbalance)
-    const int bx = b.id % g.tx, by = (b.id / g.tx) % g.ty, bz = b.id / (g.tx * g.ty);
+    const int nbx = p2g_bx(g), nby = p2g_by(g);
+    const int bx = b.id % nbx, by = (b.id / nbx) % nby, bz = b.id / (nbx * nby);
     const int x0 = bx * P2G_T, y0 = by * P2G_T, z0 = bz * P2G_T;
     for (int q = lane; q < 3 * P2G_BOX * 2; q += 64) (&acc[0][0][0])[q] = T(0);
     __syncthreads();
@@ -263,7 +290,7 @@ void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint3
                 const uint32_t* count, const T gdt[3], T* const old[3], T* const star[3],
                 hipStream_t st)
 {
-    const unsigned tiles = (unsigned)tiles_of(g);
+    const unsigned tiles = (unsigned)p2g_blocks(g);
     hipLaunchKernelGGL(k_p2g_tiles<T>, dim3(tiles), dim3(64), 0, st, g, n, pos, pos + n, pos + 2 * n, vel,
                        vel + n, vel + 2 * n, start, count, gdt[0], gdt[1], gdt[2], old[0], old[1],
                        old[2], star[0], star[1], star[2]);
