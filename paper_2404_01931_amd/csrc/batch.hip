@@ -188,7 +188,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
         }
         S.ph[ph].bin_keys = add_site(t, ak, bp, ELEM_NT);
         S.ph[ph].gather = add_site(t, ag, bp, ELEM_NT);
-        S.ph[ph].p2g = add_site(t, ap, b2g, 64);
+        S.ph[ph].p2g = add_site(t, ap, b2g, P2G_NT);
         S.ph[ph].g2p = add_site(t, a2, bt, 256);
     }
     {

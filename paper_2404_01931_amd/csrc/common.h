@@ -136,7 +136,8 @@ void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint
                   uint32_t* scan_tmp, hipStream_t st);
 
 // particle-to-grid for all faces, with gravity (gdt = g * dt per axis) and walls;
-// p2g_blocks: its workgroup count (one per 10^3 block of cells)
+// p2g_blocks: its workgroup count (one per 10^3 block of cells, P2G_NT threads)
+constexpr int P2G_NT = 192;
 int64_t p2g_blocks(const Geo& g);
 template <typename T>
 void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint32_t* start,

@@ -103,7 +103,7 @@ static_assert(P2G_BATCH <= PARTICLE_PAD, "particle reads past the last particle 
 
 template <typename T>
 struct CellParticles {
-    T x[P2G_BATCH], y[P2G_BATCH], z[P2G_BATCH], u[P2G_BATCH], v[P2G_BATCH], w[P2G_BATCH];
+    T x[P2G_BATCH], y[P2G_BATCH], z[P2G_BATCH], v[P2G_BATCH];  // position and one velocity component
 };
 
 // Eight consecutive values p[s .. s + 7] with 16-byte loads from any 4-byte
@@ -140,15 +140,12 @@ __device__ inline void load8(const double* __restrict__ p, uint32_t s, double (&
 // elements of slack, so the reads stay inside the workspace for any s <= n.
 template <typename T>
 __device__ inline void load_cell(CellParticles<T>& r, const T* __restrict__ px, const T* __restrict__ py,
-                                 const T* __restrict__ pz, const T* __restrict__ vx, const T* __restrict__ vy,
-                                 const T* __restrict__ vz, uint32_t s)
+                                 const T* __restrict__ pz, const T* __restrict__ vc, uint32_t s)
 {
     load8(px, s, r.x);
     load8(py, s, r.y);
     load8(pz, s, r.z);
-    load8(vx, s, r.u);
-    load8(vy, s, r.v);
-    load8(vz, s, r.w);
+    load8(vc, s, r.v);
 }
 
 // the cell that lane handles in colour phase ph (ring box [r0, r1] per axis),
@@ -163,6 +160,83 @@ __device__ inline int64_t phase_cell(const Geo& g, int ph, int lane, int rx0, in
     return cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
 }
 
+// One wave of the workgroup: component A of the block's faces.
+template <typename T, int A>
+__device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0, int y0, int z0,
+                                              const T* __restrict__ px, const T* __restrict__ py,
+                                              const T* __restrict__ pz, const T* __restrict__ vc,
+                                              const uint32_t* __restrict__ start,
+                                              const uint32_t* __restrict__ count, T gdt, T (*acc)[2],
+                                              T* __restrict__ f_old, T* __restrict__ f_star)
+{
+#pragma clang fp contract(off)
+    for (int q = lane; q < P2G_BOX * 2; q += 64) (&acc[0][0])[q] = T(0);
+    // ring box of cells, clipped to the domain (inclusive bounds)
+    const int rx0 = max(x0 - 1, 0), rx1 = min(x0 + P2G_T, g.nx - 1);
+    const int ry0 = max(y0 - 1, 0), ry1 = min(y0 + P2G_T, g.ny - 1);
+    const int rz0 = max(z0 - 1, 0), rz1 = min(z0 + P2G_T, g.nz - 1);
+    const double inv = g.inv_dx;
+    if (n > 0) {
+        // Software pipeline over the 27 phases: the cell range of phase
+        // ph + 2 and the particles of phase ph + 1 are loaded while phase ph
+        // is splatted. The wave's LDS operations run in issue order, so the
+        // adds of one phase are in place before the next phase reads them.
+        int64_t c = phase_cell(g, 0, lane, rx0, ry0, rz0, rx1, ry1, rz1);
+        uint32_t s_a = start[c >= 0 ? c : 0], n_a = c >= 0 ? count[c] : 0u;
+        c = phase_cell(g, 1, lane, rx0, ry0, rz0, rx1, ry1, rz1);
+        uint32_t s_b = start[c >= 0 ? c : 0], n_b = c >= 0 ? count[c] : 0u;
+        CellParticles<T> P;
+        load_cell(P, px, py, pz, vc, s_a);
+#pragma unroll 1
+        for (int ph = 0; ph < 27; ++ph) {
+            c = phase_cell(g, min(ph + 2, 26), lane, rx0, ry0, rz0, rx1, ry1, rz1);
+            const uint32_t s_c = start[c >= 0 ? c : 0], n_c = c >= 0 ? count[c] : 0u;
+            CellParticles<T> Q;
+            load_cell(Q, px, py, pz, vc, s_b);
+#pragma unroll
+            for (int k = 0; k < P2G_BATCH; ++k) {
+                if ((uint32_t)k < n_a)
+                    splat<T, A>(acc, x0, y0, z0, (double)P.x[k] * inv, (double)P.y[k] * inv, (double)P.z[k] * inv,
+                                P.v[k]);
+            }
+            // cells holding more particles than a batch: the rest one by one
+            for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
+                splat<T, A>(acc, x0, y0, z0, (double)px[q] * inv, (double)py[q] * inv, (double)pz[q] * inv, vc[q]);
+            __builtin_amdgcn_wave_barrier();
+            P = Q;
+            s_a = s_b;
+            n_a = n_b;
+            s_b = s_c;
+            n_b = n_c;
+        }
+    }
+    // write the samples this block owns: [x0, x0+T) on every axis, plus the
+    // domain's high side when the block touches it
+    const int ex = min(x0 + P2G_T, g.nx), ey = min(y0 + P2G_T, g.ny), ez = min(z0 + P2G_T, g.nz);
+    constexpr int DX = P2G_T + (A == 0), DY = P2G_T + (A == 1);
+    const int fX = g.nx + (A == 0), fY = g.ny + (A == 1);
+    const int lim = A == 0 ? g.nx : (A == 1 ? g.ny : g.nz);
+    for (int q = lane; q < P2G_BOX; q += 64) {
+        const int li = q % DX, lj = (q / DX) % DY, lk = q / (DX * DY);
+        const int i = x0 + li, j = y0 + lj, k = z0 + lk;
+        const bool own = (A == 0 ? (i < ex || i == g.nx) : i < ex) && (A == 1 ? (j < ey || j == g.ny) : j < ey) &&
+                         (A == 2 ? (k < ez || k == g.nz) : k < ez) && i <= g.nx && j <= g.ny && k <= g.nz;
+        if (!own) continue;
+        const T W = acc[q][0], M = acc[q][1];
+        const T raw = W > T(0) ? M / W : T(0);
+        const int idx = A == 0 ? i : (A == 1 ? j : k);
+        const int64_t f = i + (int64_t)fX * (j + (int64_t)fY * k);
+        f_old[f] = raw;
+        f_star[f] = (idx == 0 || idx == lim) ? T(0) : raw + gdt;
+    }
+}
+
+// Three waves per block, wave a for velocity component a: each wave owns its
+// component's samples, so the waves share no LDS word and need no barrier;
+// per wave the block's LDS and registers hold one component, which keeps
+// three times as many waves resident as one wave doing all three.
+static_assert(P2G_NT == 3 * 64, "one wave per velocity component");
+
 template <typename T>
 __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __restrict__ px, const T* __restrict__ py,
                                          const T* __restrict__ pz, const T* __restrict__ vx,
@@ -173,94 +247,24 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
                                          T* __restrict__ w_old, T* __restrict__ u_star,
                                          T* __restrict__ v_star, T* __restrict__ w_star)
 {
-#pragma clang fp contract(off)
     __shared__ T acc[3][P2G_BOX][2];
-    const int lane = threadIdx.x;
-    // tiles in grid order across the XCDs (the work per tile varies widely:
-    // contiguous runs per XCD, which would keep a ring's particles in one L2,
-    // measured slower for the imbalance)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // blocks in grid order across the XCDs (the work per block varies
+    // widely: contiguous runs per XCD, which would keep a ring's particles in
+    // one L2, measured slower for the imbalance)
     const int nbx = p2g_bx(g), nby = p2g_by(g);
     const int bx = b.id % nbx, by = (b.id / nbx) % nby, bz = b.id / (nbx * nby);
     const int x0 = bx * P2G_T, y0 = by * P2G_T, z0 = bz * P2G_T;
-    for (int q = lane; q < 3 * P2G_BOX * 2; q += 64) (&acc[0][0][0])[q] = T(0);
-    __syncthreads();
-    // ring box of cells, clipped to the domain (inclusive bounds)
-    const int rx0 = max(x0 - 1, 0), rx1 = min(x0 + P2G_T, g.nx - 1);
-    const int ry0 = max(y0 - 1, 0), ry1 = min(y0 + P2G_T, g.ny - 1);
-    const int rz0 = max(z0 - 1, 0), rz1 = min(z0 + P2G_T, g.nz - 1);
-    const double inv = g.inv_dx;
-    if (n > 0) {
-        // Software pipeline over the 27 phases: the cell range of phase
-        // ph + 2 and the particles of phase ph + 1 are loaded while phase ph
-        // is splatted. Phases exchange data through LDS only, so the barrier
-        // between them leaves those loads in flight.
-        int64_t c = phase_cell(g, 0, lane, rx0, ry0, rz0, rx1, ry1, rz1);
-        uint32_t s_a = start[c >= 0 ? c : 0], n_a = c >= 0 ? count[c] : 0u;
-        c = phase_cell(g, 1, lane, rx0, ry0, rz0, rx1, ry1, rz1);
-        uint32_t s_b = start[c >= 0 ? c : 0], n_b = c >= 0 ? count[c] : 0u;
-        CellParticles<T> A;
-        load_cell(A, px, py, pz, vx, vy, vz, s_a);
-#pragma unroll 1
-        for (int ph = 0; ph < 27; ++ph) {
-            c = phase_cell(g, min(ph + 2, 26), lane, rx0, ry0, rz0, rx1, ry1, rz1);
-            const uint32_t s_c = start[c >= 0 ? c : 0], n_c = c >= 0 ? count[c] : 0u;
-            CellParticles<T> B;
-            load_cell(B, px, py, pz, vx, vy, vz, s_b);
-#pragma unroll
-            for (int k = 0; k < P2G_BATCH; ++k) {
-                if ((uint32_t)k < n_a) {
-                    const double gx = (double)A.x[k] * inv, gy = (double)A.y[k] * inv, gz = (double)A.z[k] * inv;
-                    splat<T, 0>(acc[0], x0, y0, z0, gx, gy, gz, A.u[k]);
-                    splat<T, 1>(acc[1], x0, y0, z0, gx, gy, gz, A.v[k]);
-                    splat<T, 2>(acc[2], x0, y0, z0, gx, gy, gz, A.w[k]);
-                }
-            }
-            // cells holding more particles than a batch: the rest one by one
-            for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q) {
-                const double gx = (double)px[q] * inv, gy = (double)py[q] * inv, gz = (double)pz[q] * inv;
-                splat<T, 0>(acc[0], x0, y0, z0, gx, gy, gz, vx[q]);
-                splat<T, 1>(acc[1], x0, y0, z0, gx, gy, gz, vy[q]);
-                splat<T, 2>(acc[2], x0, y0, z0, gx, gy, gz, vz[q]);
-            }
-            lds_barrier();
-            A = B;
-            s_a = s_b;
-            n_a = n_b;
-            s_b = s_c;
-            n_b = n_c;
-        }
-    }
-    // write the samples this tile owns: [x0, x0+8) on every axis, plus the
-    // domain's high side when the tile touches it
-    const int ex = min(x0 + P2G_T, g.nx), ey = min(y0 + P2G_T, g.ny), ez = min(z0 + P2G_T, g.nz);
-    const T gdt[3] = {gdt_x, gdt_y, gdt_z};
-    T* const olds[3] = {u_old, v_old, w_old};
-    T* const stars[3] = {u_star, v_star, w_star};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int DX = P2G_T + (a == 0), DY = P2G_T + (a == 1);
-        const int fX = g.nx + (a == 0), fY = g.ny + (a == 1);
-        for (int q = lane; q < P2G_BOX; q += 64) {
-            const int li = q % DX, lj = (q / DX) % DY, lk = q / (DX * DY);
-            const int i = x0 + li, j = y0 + lj, k = z0 + lk;
-            const bool own = (a == 0 ? (i < ex || i == g.nx) : i < ex) &&
-                             (a == 1 ? (j < ey || j == g.ny) : j < ey) &&
-                             (a == 2 ? (k < ez || k == g.nz) : k < ez) &&
-                             i <= g.nx && j <= g.ny && k <= g.nz;
-            if (!own) continue;
-            const T W = acc[a][q][0], M = acc[a][q][1];
-            const T raw = W > T(0) ? M / W : T(0);
-            const int idx = a == 0 ? i : (a == 1 ? j : k);
-            const int lim = a == 0 ? g.nx : (a == 1 ? g.ny : g.nz);
-            const int64_t f = i + (int64_t)fX * (j + (int64_t)fY * k);
-            olds[a][f] = raw;
-            stars[a][f] = (idx == 0 || idx == lim) ? T(0) : raw + gdt[a];
-        }
-    }
+    if (wv == 0)
+        p2g_component<T, 0>(g, n, lane, x0, y0, z0, px, py, pz, vx, start, count, gdt_x, acc[0], u_old, u_star);
+    else if (wv == 1)
+        p2g_component<T, 1>(g, n, lane, x0, y0, z0, px, py, pz, vy, start, count, gdt_y, acc[1], v_old, v_star);
+    else
+        p2g_component<T, 2>(g, n, lane, x0, y0, z0, px, py, pz, vz, start, count, gdt_z, acc[2], w_old, w_star);
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, int64_t n, const T* __restrict__ px,
+__global__ __launch_bounds__(P2G_NT) void k_p2g_tiles(Geo g, int64_t n, const T* __restrict__ px,
                                                   const T* __restrict__ py, const T* __restrict__ pz,
                                                   const T* __restrict__ vx, const T* __restrict__ vy,
                                                   const T* __restrict__ vz,
@@ -276,7 +280,7 @@ __global__ __launch_bounds__(64) void k_p2g_tiles(Geo g, int64_t n, const T* __r
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void kb_p2g_tiles(const P2GArgs<T>* __restrict__ tab,
+__global__ __launch_bounds__(P2G_NT) void kb_p2g_tiles(const P2GArgs<T>* __restrict__ tab,
                                                    const uint32_t* __restrict__ first, int ns)
 {
     Blk b;
@@ -291,7 +295,7 @@ void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint3
                 hipStream_t st)
 {
     const unsigned tiles = (unsigned)p2g_blocks(g);
-    hipLaunchKernelGGL(k_p2g_tiles<T>, dim3(tiles), dim3(64), 0, st, g, n, pos, pos + n, pos + 2 * n, vel,
+    hipLaunchKernelGGL(k_p2g_tiles<T>, dim3(tiles), dim3(P2G_NT), 0, st, g, n, pos, pos + n, pos + 2 * n, vel,
                        vel + n, vel + 2 * n, start, count, gdt[0], gdt[1], gdt[2], old[0], old[1],
                        old[2], star[0], star[1], star[2]);
 }
@@ -300,7 +304,7 @@ template <typename T>
 void launch_b_p2g(const BatchLaunch& L, hipStream_t st)
 {
     if (L.blocks == 0) return;
-    hipLaunchKernelGGL(kb_p2g_tiles<T>, dim3(L.blocks), dim3(64), 0, st, (const P2GArgs<T>*)L.args, L.first,
+    hipLaunchKernelGGL(kb_p2g_tiles<T>, dim3(L.blocks), dim3(P2G_NT), 0, st, (const P2GArgs<T>*)L.args, L.first,
                        L.ns);
 }
 template void launch_b_p2g<float>(const BatchLaunch&, hipStream_t);
