@@ -15,13 +15,6 @@
 
 namespace flipmi {
 
-template <typename T>
-__device__ inline T hat(T r)
-{
-    T a = T(1) - fabs(r);
-    return a > T(0) ? a : T(0);
-}
-
 // Particle-to-grid as an LDS splat, one wave per 10x10x10 block of cells.
 //
 // The wave owns the block's faces and accumulates their weight sums W and
@@ -71,20 +64,40 @@ __device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, dou
     const double ax = A == 0 ? gx : gx - 0.5, ay = A == 1 ? gy : gy - 0.5, az = A == 2 ? gz : gz - 0.5;
     const double fx = floor(ax), fy = floor(ay), fz = floor(az);
     const int i0 = (int)fx - x0, j0 = (int)fy - y0, k0 = (int)fz - z0;
-    const double wx[2] = {hat(ax - fx), hat(ax - fx - 1.0)};
-    const double wy[2] = {hat(ay - fy), hat(ay - fy - 1.0)};
-    const double wz[2] = {hat(az - fz), hat(az - fz - 1.0)};
     constexpr int DX = P2G_T + (A == 0), DY = P2G_T + (A == 1), DZ = P2G_T + (A == 2);
+    // FP32 (read-modify-write sums): samples outside the block's box get
+    // weight 0 and the index of the nearest sample inside it, which lies
+    // within one index of the particle's cell and is therefore touched by no
+    // other lane of the phase, so every update runs unconditionally (no
+    // branch per sample: 1.84 -> 1.77 ms at 256^3) and adding an exact zero
+    // leaves a sum unchanged. FP64 (LDS-unit adds) skips those samples
+    // instead: there the extra adds cost more than the branches.
+    constexpr bool masked = !P2GAdd<T>::lds_unit;
+    // with r = a - floor(a) in [0, 1) the two hats are 1 - r and r
+    const double rx = ax - fx, ry = ay - fy, rz = az - fz;
+    double wx[2] = {1.0 - rx, rx}, wy[2] = {1.0 - ry, ry}, wz[2] = {1.0 - rz, rz};
+    int li[2], lj[2], lk[2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+        const int i = i0 + d, j = j0 + d, k = k0 + d;
+        wx[d] = (i >= 0 && i < DX) ? wx[d] : 0.0;
+        wy[d] = (j >= 0 && j < DY) ? wy[d] : 0.0;
+        wz[d] = (k >= 0 && k < DZ) ? wz[d] : 0.0;
+        li[d] = min(max(i, 0), DX - 1);
+        lj[d] = min(max(j, 0), DY - 1);
+        lk[d] = min(max(k, 0), DZ - 1);
+    }
 #pragma unroll
     for (int dk = 0; dk < 2; ++dk)
 #pragma unroll
         for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
             for (int di = 0; di < 2; ++di) {
-                const int li = i0 + di, lj = j0 + dj, lk = k0 + dk;
-                if (li < 0 || li >= DX || lj < 0 || lj >= DY || lk < 0 || lk >= DZ) continue;
+                if (!masked && (i0 + di < 0 || i0 + di >= DX || j0 + dj < 0 || j0 + dj >= DY || k0 + dk < 0 ||
+                                k0 + dk >= DZ))
+                    continue;
                 const T w = (T)(wx[di] * wy[dj] * wz[dk]);
-                T* a = acc[li + DX * (lj + DY * lk)];
+                T* a = acc[li[di] + DX * (lj[dj] + DY * lk[dk])];
                 if (P2GAdd<T>::lds_unit) {
                     lds_add(a, w);
                     lds_add(a + 1, v * w);
@@ -148,14 +161,100 @@ __device__ inline void load_cell(CellParticles<T>& r, const T* __restrict__ px, 
     load8(vc, s, r.v);
 }
 
+// FP32: a lane sums its cell's particles in registers over the cell's
+// window of samples of component A (2 along A, where the samples sit on cell
+// faces; 3 across it, where they sit at cell-centre height: every particle of
+// the cell reaches only these), then adds the window to LDS once per cell.
+// Consecutive particles of a cell reach the same samples, and per-particle
+// LDS read-modify-writes made each particle wait for the previous one's
+// round trip.
+template <int A>
+struct Window {
+    static constexpr int NX = A == 0 ? 2 : 3, NY = A == 1 ? 2 : 3, NZ = A == 2 ? 2 : 3;
+    float W[NZ][NY][NX], M[NZ][NY][NX];
+};
+
+// the 1D weights of one axis over the window: 2 samples (face axis) or 3
+// (centre axis, the particle's pair at offset o = 0 or 1)
+// The hats are measured from the window's samples, not from floor(a): with a
+// spacing that is not a power of two, x * (1/dx) can land just below the
+// face a particle was binned across (the binning takes the exact floor of
+// x / dx), and the particle's weight then belongs to the window's sample.
+template <int N>
+__device__ inline void axis_weights(double a, int c, float (&w)[N])
+{
+    if (N == 2) {
+        // face axis: samples c and c + 1 of a particle in cell c
+        const double r = a - (double)c;
+        w[0] = (float)(1.0 - r);
+        w[1] = (float)r;
+    } else {
+        // centre axis, a = g - 1/2: the pair (c - 1, c) or (c, c + 1)
+        const bool up = floor(a) >= (double)c;
+        const double r = a - (double)(up ? c : c - 1);
+        const float lo = (float)(1.0 - r), hi = (float)r;
+        w[0] = up ? 0.0f : lo;
+        w[1] = up ? lo : hi;
+        w[N - 1] = up ? hi : 0.0f;
+    }
+}
+
+template <int A>
+__device__ inline void window_add(Window<A>& win, int cx, int cy, int cz, double gx, double gy, double gz, float v)
+{
+#pragma clang fp contract(off)
+    using Wn = Window<A>;
+    float wx[Wn::NX], wy[Wn::NY], wz[Wn::NZ];
+    axis_weights<Wn::NX>(A == 0 ? gx : gx - 0.5, cx, wx);
+    axis_weights<Wn::NY>(A == 1 ? gy : gy - 0.5, cy, wy);
+    axis_weights<Wn::NZ>(A == 2 ? gz : gz - 0.5, cz, wz);
+#pragma unroll
+    for (int k = 0; k < Wn::NZ; ++k)
+#pragma unroll
+        for (int j = 0; j < Wn::NY; ++j) {
+            const float wyz = wz[k] * wy[j];
+#pragma unroll
+            for (int i = 0; i < Wn::NX; ++i) {
+                const float w = wyz * wx[i];
+                win.W[k][j][i] = win.W[k][j][i] + w;
+                win.M[k][j][i] = fma(v, w, win.M[k][j][i]);
+            }
+        }
+}
+
+// add the window of cell (cx, cy, cz) to the block's samples; window samples
+// outside the box add 0 at the nearest sample inside it (within one index of
+// the cell, so touched by no other lane of the phase)
+template <int A>
+__device__ inline void window_flush(const Window<A>& win, float (*acc)[2], int cx, int cy, int cz, int x0, int y0,
+                                    int z0)
+{
+#pragma clang fp contract(off)
+    using Wn = Window<A>;
+    constexpr int DX = P2G_T + (A == 0), DY = P2G_T + (A == 1), DZ = P2G_T + (A == 2);
+    const int bi = cx - x0 - (A == 0 ? 0 : 1), bj = cy - y0 - (A == 1 ? 0 : 1), bk = cz - z0 - (A == 2 ? 0 : 1);
+#pragma unroll
+    for (int k = 0; k < Wn::NZ; ++k)
+#pragma unroll
+        for (int j = 0; j < Wn::NY; ++j)
+#pragma unroll
+            for (int i = 0; i < Wn::NX; ++i) {
+                const int li = bi + i, lj = bj + j, lk = bk + k;
+                const bool in = li >= 0 && li < DX && lj >= 0 && lj < DY && lk >= 0 && lk < DZ;
+                float* a = acc[min(max(li, 0), DX - 1) + DX * (min(max(lj, 0), DY - 1) + DY * min(max(lk, 0), DZ - 1))];
+                a[0] = a[0] + (in ? win.W[k][j][i] : 0.0f);
+                a[1] = a[1] + (in ? win.M[k][j][i] : 0.0f);
+            }
+}
+
 // the cell that lane handles in colour phase ph (ring box [r0, r1] per axis),
 // or -1 when that position is outside the box
 __device__ inline int64_t phase_cell(const Geo& g, int ph, int lane, int rx0, int ry0, int rz0, int rx1, int ry1,
-                                     int rz1)
+                                     int rz1, int& cx, int& cy, int& cz)
 {
-    const int cx = rx0 + ((ph % 3) - rx0 % 3 + 3) % 3 + 3 * (lane & 3);
-    const int cy = ry0 + (((ph / 3) % 3) - ry0 % 3 + 3) % 3 + 3 * ((lane >> 2) & 3);
-    const int cz = rz0 + ((ph / 9) - rz0 % 3 + 3) % 3 + 3 * (lane >> 4);
+    cx = rx0 + ((ph % 3) - rx0 % 3 + 3) % 3 + 3 * (lane & 3);
+    cy = ry0 + (((ph / 3) % 3) - ry0 % 3 + 3) % 3 + 3 * ((lane >> 2) & 3);
+    cz = rz0 + ((ph / 9) - rz0 % 3 + 3) % 3 + 3 * (lane >> 4);
     if (cx > rx1 || cy > ry1 || cz > rz1) return -1;
     return cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
 }
@@ -181,28 +280,54 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
         // ph + 2 and the particles of phase ph + 1 are loaded while phase ph
         // is splatted. The wave's LDS operations run in issue order, so the
         // adds of one phase are in place before the next phase reads them.
-        int64_t c = phase_cell(g, 0, lane, rx0, ry0, rz0, rx1, ry1, rz1);
+        int cxa, cya, cza, cxb, cyb, czb, cxc, cyc, czc;
+        int64_t c = phase_cell(g, 0, lane, rx0, ry0, rz0, rx1, ry1, rz1, cxa, cya, cza);
         uint32_t s_a = start[c >= 0 ? c : 0], n_a = c >= 0 ? count[c] : 0u;
-        c = phase_cell(g, 1, lane, rx0, ry0, rz0, rx1, ry1, rz1);
+        c = phase_cell(g, 1, lane, rx0, ry0, rz0, rx1, ry1, rz1, cxb, cyb, czb);
         uint32_t s_b = start[c >= 0 ? c : 0], n_b = c >= 0 ? count[c] : 0u;
         CellParticles<T> P;
         load_cell(P, px, py, pz, vc, s_a);
 #pragma unroll 1
         for (int ph = 0; ph < 27; ++ph) {
-            c = phase_cell(g, min(ph + 2, 26), lane, rx0, ry0, rz0, rx1, ry1, rz1);
+            c = phase_cell(g, min(ph + 2, 26), lane, rx0, ry0, rz0, rx1, ry1, rz1, cxc, cyc, czc);
             const uint32_t s_c = start[c >= 0 ? c : 0], n_c = c >= 0 ? count[c] : 0u;
             CellParticles<T> Q;
             load_cell(Q, px, py, pz, vc, s_b);
+            if constexpr (sizeof(T) == 4) {
+                Window<A> win;
 #pragma unroll
-            for (int k = 0; k < P2G_BATCH; ++k) {
-                if ((uint32_t)k < n_a)
-                    splat<T, A>(acc, x0, y0, z0, (double)P.x[k] * inv, (double)P.y[k] * inv, (double)P.z[k] * inv,
-                                P.v[k]);
+                for (int k = 0; k < Window<A>::NZ; ++k)
+#pragma unroll
+                    for (int j = 0; j < Window<A>::NY; ++j)
+#pragma unroll
+                        for (int i = 0; i < Window<A>::NX; ++i) win.W[k][j][i] = win.M[k][j][i] = 0.0f;
+#pragma unroll
+                for (int k = 0; k < P2G_BATCH; ++k) {
+                    if ((uint32_t)k < n_a)
+                        window_add<A>(win, cxa, cya, cza, (double)P.x[k] * inv, (double)P.y[k] * inv, (double)P.z[k] * inv, P.v[k]);
+                }
+                // cells holding more particles than a batch: the rest one by one
+                for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
+                    window_add<A>(win, cxa, cya, cza, (double)px[q] * inv, (double)py[q] * inv, (double)pz[q] * inv, vc[q]);
+                if (n_a > 0) window_flush<A>(win, acc, cxa, cya, cza, x0, y0, z0);
+            } else {
+#pragma unroll
+                for (int k = 0; k < P2G_BATCH; ++k) {
+                    if ((uint32_t)k < n_a)
+                        splat<T, A>(acc, x0, y0, z0, (double)P.x[k] * inv, (double)P.y[k] * inv,
+                                    (double)P.z[k] * inv, P.v[k]);
+                }
+                for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
+                    splat<T, A>(acc, x0, y0, z0, (double)px[q] * inv, (double)py[q] * inv, (double)pz[q] * inv,
+                                vc[q]);
             }
-            // cells holding more particles than a batch: the rest one by one
-            for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
-                splat<T, A>(acc, x0, y0, z0, (double)px[q] * inv, (double)py[q] * inv, (double)pz[q] * inv, vc[q]);
             __builtin_amdgcn_wave_barrier();
+            cxa = cxb;
+            cya = cyb;
+            cza = czb;
+            cxb = cxc;
+            cyb = cyc;
+            czb = czc;
             P = Q;
             s_a = s_b;
             n_a = n_b;
