@@ -194,7 +194,7 @@ struct MgLevel {
 };
 constexpr int MG_MAX_LEVELS = 32;
 constexpr int MG_BOTTOM_SIDE = 8;      // coarsen until every axis has at most 8 cells
-constexpr int MG_BOTTOM_SWEEPS = 20;   // Jacobi sweeps on the coarsest level
+constexpr int MG_BOTTOM_SWEEPS = 10;   // Jacobi sweeps on the coarsest level
 // cell types of the first coarse level from the fine n_c, and of each next one
 void launch_mg_types_fine(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const MgLevel& c,
                           hipStream_t st);

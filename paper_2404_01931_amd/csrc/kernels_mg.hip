@@ -11,7 +11,7 @@
 //
 // One V-cycle, with damped Jacobi (w = 6/7) as the smoother:
 //   down, level l:  x0 = w b / n;  t = b - A x0;  b_{l+1} = (R t) / 2
-//   bottom:         x = 0, then 20 sweeps x += w (b - A x) / n
+//   bottom:         x = 0, then 10 sweeps x += w (b - A x) / n
 //   up, level l:    y = x0 + P x_{l+1};  x_l = y + w (b - A y) / n
 // Between the fine grid and level 1, P copies a coarse value to its fluid
 // children and R sums the children; between dense levels P is cell-centred
