@@ -72,6 +72,20 @@ __device__ inline const A& batch_args(const A* __restrict__ tab, const uint32_t*
 // later use. Where waves exchange data through LDS alone, this barrier
 // waits only for the wave's LDS operations, so prefetched global loads stay
 // in flight across it.
+// 1/d for a cell's neighbour count d in 0..6 (0 for 0) in the multigrid
+// smoother. FP32 takes the hardware reciprocal (one instruction, within 1 ulp;
+// exact for 1, 2 and 4) instead of the correctly rounded division sequence:
+// the smoother only has to be the same linear operator every time it is
+// applied, which it is. FP64 divides.
+template <typename V>
+__device__ inline V smoother_recip(int d)
+{
+    if constexpr (sizeof(V) == 4)
+        return d ? __builtin_amdgcn_rcpf((float)d) : 0.0f;
+    else
+        return d ? V(1) / (V)d : V(0);
+}
+
 __device__ inline void lds_barrier()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");

@@ -41,10 +41,8 @@ __device__ inline V mg_omega()
 
 __device__ inline int level_count(const MgLevel& L) { return L.nx * L.ny * L.nz; }
 
-__device__ inline int64_t level_index(const MgLevel& L, int i, int j, int k)
-{
-    return i + (int64_t)L.nx * (j + (int64_t)L.ny * k);
-}
+// (a dense level has far fewer than 2^31 cells: 32-bit index arithmetic)
+__device__ inline int level_index(const MgLevel& L, int i, int j, int k) { return i + L.nx * (j + L.ny * k); }
 
 __device__ inline int level_nc(const MgLevel& L, int i, int j, int k)
 {
@@ -136,7 +134,7 @@ __global__ __launch_bounds__(256) void kb_mg_types(const MgPairArgs* __restrict_
 template <typename V>
 __device__ inline V recip_nc(int d)
 {
-    return d ? V(1) / (V)d : V(0);
+    return smoother_recip<V>(d);
 }
 
 // weight of fine cell 2c - 1 + k (k = 0..3) in coarse cell c, on an axis of n coarse cells

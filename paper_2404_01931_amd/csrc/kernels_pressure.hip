@@ -599,7 +599,7 @@ __device__ inline void mg_fetch(MgRegs<V>& q, const V* __restrict__ r, const uin
 template <typename V>
 __device__ inline V mg_recip(int d)
 {
-    return d ? V(1) / (V)d : V(0);
+    return smoother_recip<V>(d);
 }
 
 // one tile of the down kernel; returns nothing, writes level-1 b for the
