@@ -143,7 +143,7 @@ struct UpdArgs {
 template <typename T, typename V>
 struct ProjectArgs {
     Geo g;
-    const uint32_t* count;
+    const uint8_t* diag;
     const int32_t* tile_slot;
     const V* p;
     const T* star;

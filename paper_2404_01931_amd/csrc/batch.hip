@@ -273,7 +273,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             }
             const T scale = (T)(c.dt / (c.density * c.dx));
             for (int a = 0; a < 3; ++a) {
-                pr[a][s] = ProjectArgs<T, T>{h->geo, h->count, h->tile_slot, (const T*)h->xin[0],
+                pr[a][s] = ProjectArgs<T, T>{h->geo, h->diag, h->tile_slot, (const T*)h->xin[0],
                                              (const T*)h->f_star[a], (T*)h->f_new[a], scale};
                 bf[a][s] = elem_blocks(h->sz.F[a]);
             }

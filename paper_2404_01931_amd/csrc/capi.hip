@@ -501,11 +501,11 @@ flip_status run_step(flip_handle* h, hipStream_t st)
         for (int a = 0; a < 3; ++a) {
             tq = timer_begin(h, FLIP_KERNEL_PROJECT, st);
             if (MIXED)
-                launch_project<float, double>(g, a, h->count, h->tile_slot, h->x64[h->xi],
+                launch_project<float, double>(g, a, h->diag, h->tile_slot, h->x64[h->xi],
                                               (const float*)h->f_star[a], (float*)h->f_new[a],
                                               (float)scale, st);
             else
-                launch_project<T, T>(g, a, h->count, h->tile_slot, (const T*)h->xin[h->xi],
+                launch_project<T, T>(g, a, h->diag, h->tile_slot, (const T*)h->xin[h->xi],
                                      (const T*)h->f_star[a], (T*)h->f_new[a], scale, st);
             timer_end(h, tq, st);
         }

@@ -215,7 +215,7 @@ template <typename V>
 void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st);
 
 template <typename T, typename V>
-void launch_project(const Geo& g, int axis, const uint32_t* count, const int32_t* tile_slot,
+void launch_project(const Geo& g, int axis, const uint8_t* diag, const int32_t* tile_slot,
                     const V* p, const T* star, T* out, T scale, hipStream_t st);
 
 // grid-to-particle: one workgroup per tile; start/count is the cell hash of

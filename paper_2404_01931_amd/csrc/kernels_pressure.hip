@@ -1188,36 +1188,45 @@ void launch_ir_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, 
 // face touching a fluid cell; p = 0 in air
 // ---------------------------------------------------------------------------
 
+// Fluid status and pressure of cell (i, j, k), both from the tile layout: a
+// fluid cell of an active tile has a nonzero n_c byte (every cell of a grid
+// with more than one cell has a neighbour; a one-cell grid has no interior
+// face), every other cell is not fluid and holds p = 0.
 template <typename V>
-__device__ inline V tile_value(const Geo& g, const int32_t* __restrict__ tile_slot,
-                               const V* __restrict__ p, int i, int j, int k)
+__device__ inline bool tile_fluid(const Geo& g, const int32_t* __restrict__ tile_slot, const uint8_t* __restrict__ diag,
+                                  const V* __restrict__ p, int i, int j, int k, V& pv)
 {
-    const int64_t t = (i >> 3) + (int64_t)g.tx * ((j >> 3) + (int64_t)g.ty * (k >> 3));
-    const int32_t s = tile_slot[t];
-    return s >= 0 ? p[(int64_t)s * TILE_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7)] : V(0);
+    const int32_t s = tile_slot[(i >> 3) + g.tx * ((j >> 3) + g.ty * (k >> 3))];
+    const int64_t e = (int64_t)(s >= 0 ? s : 0) * TILE_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7);
+    const bool fl = s >= 0 && diag[e] > 0;
+    pv = fl ? p[e] : V(0);
+    return fl;
 }
 
 template <typename T, typename V, int A>
-__device__ __forceinline__ void project_body(Blk blk, Geo g, const uint32_t* __restrict__ count,
+__device__ __forceinline__ void project_body(Blk blk, Geo g, const uint8_t* __restrict__ diag,
                                              const int32_t* __restrict__ tile_slot,
                                              const V* __restrict__ p, const T* __restrict__ star,
                                              T* __restrict__ out, T scale)
 {
-    const int dX = g.nx + (A == 0), dY = g.ny + (A == 1), dZ = g.nz + (A == 2);
-    const int64_t F = (int64_t)dX * dY * dZ;
-    const int64_t f = (int64_t)blk.id * 256 + threadIdx.x;
+    // face counts stay below 2^32 (cells below 2^31): 32-bit index arithmetic
+    const uint32_t dX = g.nx + (A == 0), dY = g.ny + (A == 1), dZ = g.nz + (A == 2);
+    const uint32_t F = dX * dY * dZ;
+    const uint32_t f = (uint32_t)blk.id * 256u + threadIdx.x;
     if (f >= F) return;
-    const int i = (int)(f % dX), j = (int)((f / dX) % dY), k = (int)(f / ((int64_t)dX * dY));
+    const uint32_t row = f / dX;
+    const int i = (int)(f - row * dX), j = (int)(row % dY), k = (int)(row / dY);
     const int idx = A == 0 ? i : (A == 1 ? j : k);
     const int lim = A == 0 ? g.nx : (A == 1 ? g.ny : g.nz);
     T o = star[f];
     if (idx > 0 && idx < lim) {
         const int im = i - (A == 0), jm = j - (A == 1), km = k - (A == 2);
-        const bool fp = count[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)] > 0;
-        const bool fm = count[im + (int64_t)g.nx * (jm + (int64_t)g.ny * km)] > 0;
+        V vp, vm;
+        const bool fp = tile_fluid(g, tile_slot, diag, p, i, j, k, vp);
+        const bool fm = tile_fluid(g, tile_slot, diag, p, im, jm, km, vm);
         if (fp || fm) {
-            const T pp = fp ? (T)tile_value(g, tile_slot, p, i, j, k) : T(0);
-            const T pm = fm ? (T)tile_value(g, tile_slot, p, im, jm, km) : T(0);
+            const T pp = fp ? (T)vp : T(0);
+            const T pm = fm ? (T)vm : T(0);
             o = o - scale * (pp - pm);
         }
     }
@@ -1225,12 +1234,12 @@ __device__ __forceinline__ void project_body(Blk blk, Geo g, const uint32_t* __r
 }
 
 template <typename T, typename V, int A>
-__global__ __launch_bounds__(256) void k_project(Geo g, const uint32_t* __restrict__ count,
+__global__ __launch_bounds__(256) void k_project(Geo g, const uint8_t* __restrict__ diag,
                                                  const int32_t* __restrict__ tile_slot,
                                                  const V* __restrict__ p, const T* __restrict__ star,
                                                  T* __restrict__ out, T scale)
 {
-    project_body<T, V, A>(plain_blk(), g, count, tile_slot, p, star, out, scale);
+    project_body<T, V, A>(plain_blk(), g, diag, tile_slot, p, star, out, scale);
 }
 
 template <typename T, typename V, int A>
@@ -1239,7 +1248,7 @@ __global__ __launch_bounds__(256) void kb_project(const ProjectArgs<T, V>* __res
 {
     Blk blk;
     const ProjectArgs<T, V>& a = batch_args(tab, first, ns, blk);
-    project_body<T, V, A>(blk, a.g, as_global(a.count), as_global(a.tile_slot), as_global(a.p), as_global(a.star), as_global(a.out), a.scale);
+    project_body<T, V, A>(blk, a.g, as_global(a.diag), as_global(a.tile_slot), as_global(a.p), as_global(a.star), as_global(a.out), a.scale);
 }
 
 template <typename T, typename V>
@@ -1284,25 +1293,25 @@ void launch_b_summary(const BatchLaunch& L, hipStream_t st)
 }
 
 template <typename T, typename V>
-void launch_project(const Geo& g, int axis, const uint32_t* count, const int32_t* tile_slot,
+void launch_project(const Geo& g, int axis, const uint8_t* diag, const int32_t* tile_slot,
                     const V* p, const T* star, T* out, T scale, hipStream_t st)
 {
     const int64_t F = (int64_t)(g.nx + (axis == 0)) * (g.ny + (axis == 1)) * (g.nz + (axis == 2));
     const dim3 grid((unsigned)((F + 255) / 256)), block(256);
     if (axis == 0)
-        hipLaunchKernelGGL((k_project<T, V, 0>), grid, block, 0, st, g, count, tile_slot, p, star, out, scale);
+        hipLaunchKernelGGL((k_project<T, V, 0>), grid, block, 0, st, g, diag, tile_slot, p, star, out, scale);
     else if (axis == 1)
-        hipLaunchKernelGGL((k_project<T, V, 1>), grid, block, 0, st, g, count, tile_slot, p, star, out, scale);
+        hipLaunchKernelGGL((k_project<T, V, 1>), grid, block, 0, st, g, diag, tile_slot, p, star, out, scale);
     else
-        hipLaunchKernelGGL((k_project<T, V, 2>), grid, block, 0, st, g, count, tile_slot, p, star, out, scale);
+        hipLaunchKernelGGL((k_project<T, V, 2>), grid, block, 0, st, g, diag, tile_slot, p, star, out, scale);
 }
 
-template void launch_project<float, float>(const Geo&, int, const uint32_t*, const int32_t*,
+template void launch_project<float, float>(const Geo&, int, const uint8_t*, const int32_t*,
                                            const float*, const float*, float*, float, hipStream_t);
-template void launch_project<double, double>(const Geo&, int, const uint32_t*, const int32_t*,
+template void launch_project<double, double>(const Geo&, int, const uint8_t*, const int32_t*,
                                              const double*, const double*, double*, double,
                                              hipStream_t);
-template void launch_project<float, double>(const Geo&, int, const uint32_t*, const int32_t*,
+template void launch_project<float, double>(const Geo&, int, const uint8_t*, const int32_t*,
                                             const double*, const float*, float*, float,
                                             hipStream_t);
 
