@@ -158,7 +158,6 @@ constexpr int MGD_TX = 2 * MGD_CX + 2, MGD_TY = 2 * MGD_CY + 2, MGD_TZ = 2 * MGD
 constexpr int MGD_UX = MGD_TX + 2, MGD_UY = MGD_TY + 2, MGD_UZ = MGD_TZ + 2;
 constexpr int MGD_T = MGD_TX * MGD_TY * MGD_TZ;  // 1800
 constexpr int MGD_U = MGD_UX * MGD_UY * MGD_UZ;  // 2880
-constexpr int MGD_NL = (MGD_U + 255) / 256;      // u-region cells per thread
 static_assert(MGD_TZ * MGD_TY * MGD_CX + MGD_TZ * MGD_CY * MGD_CX <= MGD_U, "x and y passes fit the b buffer");
 
 // workgroups of a restriction to level c: one per 8 x 4 x 4 block of c, x fastest
@@ -169,10 +168,14 @@ __host__ __device__ inline int64_t mg_down_blocks(const MgLevel& c)
     return (int64_t)mg_down_blocks_x(c) * mg_down_blocks_y(c) * ((c.nz + MGD_CZ - 1) / MGD_CZ);
 }
 
-template <typename V>
+// NT threads per workgroup: 256, or 1024 on the small levels, where a
+// launch has fewer workgroups than the chip has CUs and the time is the
+// chain of each thread's serial work (the values are the same either way)
+template <typename V, int NT>
 __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const MgLevel& c,
                                              const PcgState* __restrict__ ps)
 {
+    constexpr int MGD_NL = (MGD_U + NT - 1) / NT;  // u-region cells per thread
     __shared__ V us[MGD_U];       // x0 on the u region
     __shared__ V bs[MGD_U];       // b on the u region; later the x and y passes
     __shared__ uint8_t ds[MGD_U];  // n (0: not fluid or outside the level)
@@ -188,7 +191,7 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
     bool iv[MGD_NL];
 #pragma unroll
     for (int m = 0; m < MGD_NL; ++m) {
-        const int q = min(tid + 256 * m, MGD_U - 1);
+        const int q = min(tid + NT * m, MGD_U - 1);
         const int gx = ox + q % MGD_UX, gy = oy + (q / MGD_UX) % MGD_UY, gz = oz + q / (MGD_UX * MGD_UY);
         iv[m] = gx >= 0 && gx < f.nx && gy >= 0 && gy < f.ny && gz >= 0 && gz < f.nz;
         const int64_t e = level_index(f, min(max(gx, 0), f.nx - 1), min(max(gy, 0), f.ny - 1),
@@ -200,7 +203,7 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
     const V w = mg_omega<V>();
 #pragma unroll
     for (int m = 0; m < MGD_NL; ++m) {
-        const int q = tid + 256 * m;
+        const int q = tid + NT * m;
         if (q < MGD_U) {
             const int d = iv[m] ? dv[m] : 0;
             us[q] = d ? w * bv[m] * recip_nc<V>(d) : V(0);
@@ -211,7 +214,7 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
     __syncthreads();
     // t = b - A x0 = (1 - w) b + (sum of x0 over the neighbours) on the t region
     constexpr int SY = MGD_UX, SZ = MGD_UX * MGD_UY;
-    for (int q = tid; q < MGD_T; q += 256) {
+    for (int q = tid; q < MGD_T; q += NT) {
         const int lx = q % MGD_TX, ly = (q / MGD_TX) % MGD_TY, lz = q / (MGD_TX * MGD_TY);
         const int u = (lx + 1) + SY * (ly + 1) + SZ * (lz + 1);
         const V nsum = ((us[u - 1] + us[u + 1]) + (us[u - SY] + us[u + SY])) + (us[u - SZ] + us[u + SZ]);
@@ -220,7 +223,7 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
     __syncthreads();
     V* const rx = bs;                                 // [TZ][TY][CX]
     V* const ry = bs + MGD_TZ * MGD_TY * MGD_CX;      // [TZ][CY][CX]
-    for (int q = tid; q < MGD_TZ * MGD_TY * MGD_CX; q += 256) {
+    for (int q = tid; q < MGD_TZ * MGD_TY * MGD_CX; q += NT) {
         const int i = q % MGD_CX, row = q / MGD_CX;   // row = ly + TY lz
         const int C = cx0 + i;
         const V* t = ts + row * MGD_TX + 2 * i;
@@ -228,7 +231,7 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
                 (restrict_weight<V>(2, C, c.nx) * t[2] + restrict_weight<V>(3, C, c.nx) * t[3]);
     }
     __syncthreads();
-    for (int q = tid; q < MGD_TZ * MGD_CY * MGD_CX; q += 256) {
+    for (int q = tid; q < MGD_TZ * MGD_CY * MGD_CX; q += NT) {
         const int i = q % MGD_CX, j = (q / MGD_CX) % MGD_CY, lz = q / (MGD_CX * MGD_CY);
         const int C = cy0 + j;
         const V* t = rx + (lz * MGD_TY + 2 * j) * MGD_CX + i;
@@ -247,10 +250,10 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
     }
 }
 
-template <typename V>
-__global__ __launch_bounds__(256) void k_mg_down(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
+template <typename V, int NT>
+__global__ __launch_bounds__(NT) void k_mg_down(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
 {
-    mg_down_body<V>(plain_blk(), f, c, ps);
+    mg_down_body<V, NT>(plain_blk(), f, c, ps);
 }
 
 template <typename V>
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(256) void kb_mg_down(const MgPairArgs* __restrict__
 {
     Blk b;
     const MgPairArgs& a = batch_args(tab, first, ns, b);
-    mg_down_body<V>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    mg_down_body<V, 256>(b, glob(a.f), glob(a.c), as_global(a.ps));
 }
 
 // ---- bottom: the coarsest level (at most 8^3 cells), one workgroup -------------
@@ -329,10 +332,6 @@ constexpr int MGU_YX = MGU_FX + 2, MGU_YY = MGU_FY + 2, MGU_YZ = MGU_FZ + 2;
 constexpr int MGU_CX = MGU_FX / 2 + 4, MGU_CY = MGU_FY / 2 + 4, MGU_CZ = MGU_FZ / 2 + 4;
 constexpr int MGU_Y = MGU_YX * MGU_YY * MGU_YZ;  // 1800
 constexpr int MGU_C = MGU_CX * MGU_CY * MGU_CZ;  // 768
-constexpr int MGU_NY = (MGU_Y + 255) / 256;
-constexpr int MGU_NC = (MGU_C + 255) / 256;
-constexpr int MGU_NF = MGU_FX * MGU_FY * MGU_FZ / 256;  // cells per thread
-static_assert(MGU_FX * MGU_FY * MGU_FZ == 256 * MGU_NF, "whole cells per thread");
 
 __host__ __device__ inline int mg_up_blocks_x(const MgLevel& f) { return (f.nx + MGU_FX - 1) / MGU_FX; }
 __host__ __device__ inline int mg_up_blocks_y(const MgLevel& f) { return (f.ny + MGU_FY - 1) / MGU_FY; }
@@ -341,10 +340,14 @@ __host__ __device__ inline int64_t mg_up_blocks(const MgLevel& f)
     return (int64_t)mg_up_blocks_x(f) * mg_up_blocks_y(f) * ((f.nz + MGU_FZ - 1) / MGU_FZ);
 }
 
-template <typename V>
+template <typename V, int NT>
 __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLevel& c,
                                            const PcgState* __restrict__ ps)
 {
+    constexpr int MGU_NY = (MGU_Y + NT - 1) / NT;
+    constexpr int MGU_NC = (MGU_C + NT - 1) / NT;
+    constexpr int MGU_NF = MGU_FX * MGU_FY * MGU_FZ / NT;  // cells per thread
+    static_assert(MGU_FX * MGU_FY * MGU_FZ == NT * MGU_NF, "whole cells per thread");
     __shared__ V xs[MGU_C];
     __shared__ V ys[MGU_Y];
     __shared__ V bs[MGU_Y];
@@ -360,7 +363,7 @@ __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLe
     V xv[MGU_NC];
 #pragma unroll
     for (int m = 0; m < MGU_NC; ++m) {
-        const int q = min(tid + 256 * m, MGU_C - 1);
+        const int q = min(tid + NT * m, MGU_C - 1);
         const int i = px0 + q % MGU_CX, j = py0 + (q / MGU_CX) % MGU_CY, k = pz0 + q / (MGU_CX * MGU_CY);
         xv[m] = cx[level_index(c, min(max(i, 0), c.nx - 1), min(max(j, 0), c.ny - 1), min(max(k, 0), c.nz - 1))];
     }
@@ -369,7 +372,7 @@ __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLe
     bool iv[MGU_NY];
 #pragma unroll
     for (int m = 0; m < MGU_NY; ++m) {
-        const int q = min(tid + 256 * m, MGU_Y - 1);
+        const int q = min(tid + NT * m, MGU_Y - 1);
         const int gx = fx0 - 1 + q % MGU_YX, gy = fy0 - 1 + (q / MGU_YX) % MGU_YY, gz = fz0 - 1 + q / (MGU_YX * MGU_YY);
         iv[m] = gx >= 0 && gx < f.nx && gy >= 0 && gy < f.ny && gz >= 0 && gz < f.nz;
         const int64_t e = level_index(f, min(max(gx, 0), f.nx - 1), min(max(gy, 0), f.ny - 1),
@@ -380,13 +383,13 @@ __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLe
     if (ps->done != PCG_RUNNING) return;
 #pragma unroll
     for (int m = 0; m < MGU_NC; ++m)
-        if (tid + 256 * m < MGU_C) xs[tid + 256 * m] = xv[m];
+        if (tid + NT * m < MGU_C) xs[tid + NT * m] = xv[m];
     __syncthreads();
     const V w = mg_omega<V>();
     constexpr int CS = MGU_CX * MGU_CY;
 #pragma unroll
     for (int m = 0; m < MGU_NY; ++m) {
-        const int q = tid + 256 * m;
+        const int q = tid + NT * m;
         if (q >= MGU_Y) break;
         const int lx = q % MGU_YX, ly = (q / MGU_YX) % MGU_YY, lz = q / (MGU_YX * MGU_YY);
         const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly, gz = fz0 - 1 + lz;
@@ -413,7 +416,7 @@ __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLe
     constexpr int SY = MGU_YX, SZ = MGU_YX * MGU_YY;
 #pragma unroll
     for (int m = 0; m < MGU_NF; ++m) {
-        const int q = tid + 256 * m;
+        const int q = tid + NT * m;
         const int lx = q % MGU_FX, ly = (q / MGU_FX) % MGU_FY, lz = q / (MGU_FX * MGU_FY);
         const int i = fx0 + lx, j = fy0 + ly, k = fz0 + lz;
         const int u = (lx + 1) + SY * (ly + 1) + SZ * (lz + 1);
@@ -425,10 +428,10 @@ __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLe
     }
 }
 
-template <typename V>
-__global__ __launch_bounds__(256) void k_mg_up(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
+template <typename V, int NT>
+__global__ __launch_bounds__(NT) void k_mg_up(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
 {
-    mg_up_body<V>(plain_blk(), f, c, ps);
+    mg_up_body<V, NT>(plain_blk(), f, c, ps);
 }
 
 template <typename V>
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(256) void kb_mg_up(const MgPairArgs* __restrict__ t
 {
     Blk b;
     const MgPairArgs& a = batch_args(tab, first, ns, b);
-    mg_up_body<V>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    mg_up_body<V, 256>(b, glob(a.f), glob(a.c), as_global(a.ps));
 }
 
 // ---- launchers -----------------------------------------------------------------
@@ -462,12 +465,23 @@ void launch_mg_types(const MgLevel& f, const MgLevel& c, hipStream_t st)
 template <typename V>
 void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st)
 {
-    for (int l = 0; l + 1 < nlev; ++l)
-        hipLaunchKernelGGL(k_mg_down<V>, dim3((unsigned)mg_down_blocks(lv[l + 1])), dim3(256), 0, st, lv[l],
-                           lv[l + 1], ps);
+    // levels whose launch has fewer workgroups than the chip has CUs run 1024-thread workgroups
+    constexpr int64_t SMALL = 128;
+    for (int l = 0; l + 1 < nlev; ++l) {
+        const int64_t nb = mg_down_blocks(lv[l + 1]);
+        if (nb < SMALL)
+            hipLaunchKernelGGL((k_mg_down<V, 1024>), dim3((unsigned)nb), dim3(1024), 0, st, lv[l], lv[l + 1], ps);
+        else
+            hipLaunchKernelGGL((k_mg_down<V, 256>), dim3((unsigned)nb), dim3(256), 0, st, lv[l], lv[l + 1], ps);
+    }
     hipLaunchKernelGGL(k_mg_bottom<V>, dim3(1), dim3(512), 0, st, lv[nlev - 1], ps);
-    for (int l = nlev - 2; l >= 0; --l)
-        hipLaunchKernelGGL(k_mg_up<V>, dim3((unsigned)mg_up_blocks(lv[l])), dim3(256), 0, st, lv[l], lv[l + 1], ps);
+    for (int l = nlev - 2; l >= 0; --l) {
+        const int64_t nb = mg_up_blocks(lv[l]);
+        if (nb < SMALL)
+            hipLaunchKernelGGL((k_mg_up<V, 1024>), dim3((unsigned)nb), dim3(1024), 0, st, lv[l], lv[l + 1], ps);
+        else
+            hipLaunchKernelGGL((k_mg_up<V, 256>), dim3((unsigned)nb), dim3(256), 0, st, lv[l], lv[l + 1], ps);
+    }
 }
 
 template void launch_mg_coarse<float>(const MgLevel*, int, const PcgState*, hipStream_t);
