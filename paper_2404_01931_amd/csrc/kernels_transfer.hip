@@ -374,11 +374,20 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
 {
     __shared__ T acc[3][P2G_BOX][2];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // blocks in grid order across the XCDs (the work per block varies
-    // widely: contiguous runs per XCD, which would keep a ring's particles in
-    // one L2, measured slower for the imbalance)
+    // Rows of blocks (fixed y, z) are dealt to the 8 XCDs in turn (workgroup
+    // b runs on XCD b % 8), and an XCD runs its row's blocks in x order, so
+    // the ring particles two x-neighbours share are read through one L2; the
+    // rows interleave, so the XCDs get a similar share of the work (whole
+    // slabs per XCD measured slower for the imbalance). Rows past the last
+    // full group of 8 keep the plain order.
     const int nbx = p2g_bx(g), nby = p2g_by(g);
-    const int bx = b.id % nbx, by = (b.id / nbx) % nby, bz = b.id / (nbx * nby);
+    const int nrows = nby * p2g_bz(g), full = (nrows / 8) * 8 * nbx;
+    int L = b.id;
+    if (b.id < full) {
+        const int x = b.id & 7, k = b.id >> 3;
+        L = (x + 8 * (k / nbx)) * nbx + k % nbx;
+    }
+    const int bx = L % nbx, by = (L / nbx) % nby, bz = L / (nbx * nby);
     const int x0 = bx * P2G_T, y0 = by * P2G_T, z0 = bz * P2G_T;
     if (wv == 0)
         p2g_component<T, 0>(g, n, lane, x0, y0, z0, px, py, pz, vx, start, count, gdt_x, acc[0], u_old, u_star);
