@@ -145,6 +145,18 @@ __device__ inline V restrict_weight(int k, int c, int n)
     return ((k == 1 && c == 0) || (k == 2 && c == n - 1)) ? V(1) : V(0.75);
 }
 
+// A box of NX x NY x NZ cells walked by NT threads a column at a time: a
+// thread keeps one (x, y) column (its index arithmetic done once) and steps
+// through z, P threads sharing a column when NT holds several copies of the
+// NX * NY columns.
+template <int NX, int NY, int NZ, int NT>
+struct Cols {
+    static constexpr int C = NX * NY;  // columns
+    static constexpr int P = NT / C;   // threads per column
+    static constexpr int J = (NZ + P - 1) / P;  // z steps per thread
+    static_assert(P >= 1, "a thread per column at least");
+};
+
 // ---- down: dense level f to level c ---------------------------------------------
 
 // One workgroup per 8 x 4 x 4 block of level-c cells. Their restriction reads
@@ -175,7 +187,8 @@ template <typename V, int NT>
 __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const MgLevel& c,
                                              const PcgState* __restrict__ ps)
 {
-    constexpr int MGD_NL = (MGD_U + NT - 1) / NT;  // u-region cells per thread
+    using CU = Cols<MGD_UX, MGD_UY, MGD_UZ, NT>;
+    using CT = Cols<MGD_TX, MGD_TY, MGD_TZ, NT>;
     __shared__ V us[MGD_U];       // x0 on the u region
     __shared__ V bs[MGD_U];       // b on the u region; later the x and y passes
     __shared__ uint8_t ds[MGD_U];  // n (0: not fluid or outside the level)
@@ -186,25 +199,31 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
     const int cz0 = (blk.id / (gbx * gby)) * MGD_CZ;
     const int ox = 2 * cx0 - 2, oy = 2 * cy0 - 2, oz = 2 * cz0 - 2;  // u region origin on level f
     const V* const fb = (const V*)f.b;
-    V bv[MGD_NL];
-    int dv[MGD_NL];
-    bool iv[MGD_NL];
+    // this thread's column of the u region
+    const int ucol = tid % CU::C, uzg = tid / CU::C;
+    const bool uact = tid < CU::C * CU::P;
+    const int ugx = ox + ucol % MGD_UX, ugy = oy + ucol / MGD_UX;
+    const bool uxy = ugx >= 0 && ugx < f.nx && ugy >= 0 && ugy < f.ny;
+    const int ubase = min(max(ugx, 0), f.nx - 1) + f.nx * min(max(ugy, 0), f.ny - 1);
+    const int sxy = f.nx * f.ny;
+    V bv[CU::J];
+    int dv[CU::J];
+    bool iv[CU::J];
 #pragma unroll
-    for (int m = 0; m < MGD_NL; ++m) {
-        const int q = min(tid + NT * m, MGD_U - 1);
-        const int gx = ox + q % MGD_UX, gy = oy + (q / MGD_UX) % MGD_UY, gz = oz + q / (MGD_UX * MGD_UY);
-        iv[m] = gx >= 0 && gx < f.nx && gy >= 0 && gy < f.ny && gz >= 0 && gz < f.nz;
-        const int64_t e = level_index(f, min(max(gx, 0), f.nx - 1), min(max(gy, 0), f.ny - 1),
-                                      min(max(gz, 0), f.nz - 1));
+    for (int m = 0; m < CU::J; ++m) {
+        const int lz = uzg + CU::P * m, gz = oz + lz;
+        iv[m] = uact && lz < MGD_UZ && uxy && gz >= 0 && gz < f.nz;
+        const int e = ubase + sxy * min(max(gz, 0), f.nz - 1);
         dv[m] = f.d[e];
         bv[m] = fb[e];
     }
     if (ps->done != PCG_RUNNING) return;
     const V w = mg_omega<V>();
 #pragma unroll
-    for (int m = 0; m < MGD_NL; ++m) {
-        const int q = tid + NT * m;
-        if (q < MGD_U) {
+    for (int m = 0; m < CU::J; ++m) {
+        const int lz = uzg + CU::P * m;
+        if (uact && lz < MGD_UZ) {
+            const int q = ucol + CU::C * lz;
             const int d = iv[m] ? dv[m] : 0;
             us[q] = d ? w * bv[m] * recip_nc<V>(d) : V(0);
             bs[q] = bv[m];
@@ -214,11 +233,14 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
     __syncthreads();
     // t = b - A x0 = (1 - w) b + (sum of x0 over the neighbours) on the t region
     constexpr int SY = MGD_UX, SZ = MGD_UX * MGD_UY;
-    for (int q = tid; q < MGD_T; q += NT) {
-        const int lx = q % MGD_TX, ly = (q / MGD_TX) % MGD_TY, lz = q / (MGD_TX * MGD_TY);
-        const int u = (lx + 1) + SY * (ly + 1) + SZ * (lz + 1);
-        const V nsum = ((us[u - 1] + us[u + 1]) + (us[u - SY] + us[u + SY])) + (us[u - SZ] + us[u + SZ]);
-        ts[q] = ds[u] ? (V(1) - w) * bs[u] + nsum : V(0);
+    if (tid < CT::C * CT::P) {
+        const int tcol = tid % CT::C;
+        const int ub = (tcol % MGD_TX + 1) + SY * (tcol / MGD_TX + 1);
+        for (int lz = tid / CT::C; lz < MGD_TZ; lz += CT::P) {
+            const int u = ub + SZ * (lz + 1);
+            const V nsum = ((us[u - 1] + us[u + 1]) + (us[u - SY] + us[u + SY])) + (us[u - SZ] + us[u + SZ]);
+            ts[tcol + CT::C * lz] = ds[u] ? (V(1) - w) * bs[u] + nsum : V(0);
+        }
     }
     __syncthreads();
     V* const rx = bs;                                 // [TZ][TY][CX]
@@ -344,10 +366,9 @@ template <typename V, int NT>
 __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLevel& c,
                                            const PcgState* __restrict__ ps)
 {
-    constexpr int MGU_NY = (MGU_Y + NT - 1) / NT;
-    constexpr int MGU_NC = (MGU_C + NT - 1) / NT;
-    constexpr int MGU_NF = MGU_FX * MGU_FY * MGU_FZ / NT;  // cells per thread
-    static_assert(MGU_FX * MGU_FY * MGU_FZ == NT * MGU_NF, "whole cells per thread");
+    using CC = Cols<MGU_CX, MGU_CY, MGU_CZ, NT>;
+    using CY = Cols<MGU_YX, MGU_YY, MGU_YZ, NT>;
+    using CF = Cols<MGU_FX, MGU_FY, MGU_FZ, NT>;
     __shared__ V xs[MGU_C];
     __shared__ V ys[MGU_Y];
     __shared__ V bs[MGU_Y];
@@ -360,46 +381,58 @@ __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLe
     const int px0 = fx0 / 2 - 2, py0 = fy0 / 2 - 2, pz0 = fz0 / 2 - 2;
     const V* const cx = (const V*)c.x;
     const V* const fb = (const V*)f.b;
-    V xv[MGU_NC];
+    // coarse region, a column per thread (loaded clamped into level c)
+    const int ccol = tid % CC::C, czg = tid / CC::C;
+    const bool cact = tid < CC::C * CC::P;
+    const int cbase = min(max(px0 + ccol % MGU_CX, 0), c.nx - 1) + c.nx * min(max(py0 + ccol / MGU_CX, 0), c.ny - 1);
+    V xv[CC::J];
 #pragma unroll
-    for (int m = 0; m < MGU_NC; ++m) {
-        const int q = min(tid + NT * m, MGU_C - 1);
-        const int i = px0 + q % MGU_CX, j = py0 + (q / MGU_CX) % MGU_CY, k = pz0 + q / (MGU_CX * MGU_CY);
-        xv[m] = cx[level_index(c, min(max(i, 0), c.nx - 1), min(max(j, 0), c.ny - 1), min(max(k, 0), c.nz - 1))];
+    for (int m = 0; m < CC::J; ++m) {
+        const int k = pz0 + czg + CC::P * m;
+        xv[m] = cx[cbase + c.nx * c.ny * min(max(k, 0), c.nz - 1)];
     }
-    V bv[MGU_NY];
-    int dv[MGU_NY];
-    bool iv[MGU_NY];
+    // y region, a column per thread
+    const int ycol = tid % CY::C, yzg = tid / CY::C;
+    const bool yact = tid < CY::C * CY::P;
+    const int ylx = ycol % MGU_YX, yly = ycol / MGU_YX;
+    const int gx = fx0 - 1 + ylx, gy = fy0 - 1 + yly;
+    const bool yxy = gx >= 0 && gx < f.nx && gy >= 0 && gy < f.ny;
+    const int ybase = min(max(gx, 0), f.nx - 1) + f.nx * min(max(gy, 0), f.ny - 1);
+    const int sxy = f.nx * f.ny;
+    V bv[CY::J];
+    int dv[CY::J];
+    bool iv[CY::J];
 #pragma unroll
-    for (int m = 0; m < MGU_NY; ++m) {
-        const int q = min(tid + NT * m, MGU_Y - 1);
-        const int gx = fx0 - 1 + q % MGU_YX, gy = fy0 - 1 + (q / MGU_YX) % MGU_YY, gz = fz0 - 1 + q / (MGU_YX * MGU_YY);
-        iv[m] = gx >= 0 && gx < f.nx && gy >= 0 && gy < f.ny && gz >= 0 && gz < f.nz;
-        const int64_t e = level_index(f, min(max(gx, 0), f.nx - 1), min(max(gy, 0), f.ny - 1),
-                                      min(max(gz, 0), f.nz - 1));
+    for (int m = 0; m < CY::J; ++m) {
+        const int lz = yzg + CY::P * m, gz = fz0 - 1 + lz;
+        iv[m] = yact && lz < MGU_YZ && yxy && gz >= 0 && gz < f.nz;
+        const int e = ybase + sxy * min(max(gz, 0), f.nz - 1);
         dv[m] = f.d[e];
         bv[m] = fb[e];
     }
     if (ps->done != PCG_RUNNING) return;
 #pragma unroll
-    for (int m = 0; m < MGU_NC; ++m)
-        if (tid + NT * m < MGU_C) xs[tid + NT * m] = xv[m];
+    for (int m = 0; m < CC::J; ++m) {
+        const int lz = czg + CC::P * m;
+        if (cact && lz < MGU_CZ) xs[ccol + CC::C * lz] = xv[m];
+    }
     __syncthreads();
     const V w = mg_omega<V>();
     constexpr int CS = MGU_CX * MGU_CY;
+    // parent and the parent's neighbour on this column's side in x and y
+    // (region coordinates; the region holds clamped values)
+    const int ax = (gx >> 1) - px0, ay = (gy >> 1) - py0;
+    const int sx = (gx & 1) ? 1 : -1, sy = (gy & 1) ? MGU_CX : -MGU_CX;
 #pragma unroll
-    for (int m = 0; m < MGU_NY; ++m) {
-        const int q = tid + NT * m;
-        if (q >= MGU_Y) break;
-        const int lx = q % MGU_YX, ly = (q / MGU_YX) % MGU_YY, lz = q / (MGU_YX * MGU_YY);
-        const int gx = fx0 - 1 + lx, gy = fy0 - 1 + ly, gz = fz0 - 1 + lz;
+    for (int m = 0; m < CY::J; ++m) {
+        const int lz = yzg + CY::P * m;
+        if (!yact || lz >= MGU_YZ) break;
+        const int q = ycol + CY::C * lz;
+        const int gz = fz0 - 1 + lz;
         const int d = iv[m] ? dv[m] : 0;
         V y = V(0);
         if (d) {
-            // parent and the parent's neighbour on this cell's side, per axis
-            // (region coordinates; the region holds clamped values)
-            const int ax = (gx >> 1) - px0, ay = (gy >> 1) - py0, az = (gz >> 1) - pz0;
-            const int sx = (gx & 1) ? 1 : -1, sy = (gy & 1) ? MGU_CX : -MGU_CX, sz = (gz & 1) ? CS : -CS;
+            const int az = (gz >> 1) - pz0, sz = (gz & 1) ? CS : -CS;
             const V* p = xs + ax + MGU_CX * ay + CS * az;
             const V x00 = V(0.75) * p[0] + V(0.25) * p[sx];
             const V x10 = V(0.75) * p[sy] + V(0.25) * p[sy + sx];
@@ -414,17 +447,21 @@ __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLe
     }
     __syncthreads();
     constexpr int SY = MGU_YX, SZ = MGU_YX * MGU_YY;
+    const int fcol = tid % CF::C, fzg = tid / CF::C;
+    const int lx = fcol % MGU_FX, ly = fcol / MGU_FX;
+    const int i = fx0 + lx, j = fy0 + ly;
+    const int ub = (lx + 1) + SY * (ly + 1);
+    if (tid < CF::C * CF::P && i < f.nx && j < f.ny) {
 #pragma unroll
-    for (int m = 0; m < MGU_NF; ++m) {
-        const int q = tid + NT * m;
-        const int lx = q % MGU_FX, ly = (q / MGU_FX) % MGU_FY, lz = q / (MGU_FX * MGU_FY);
-        const int i = fx0 + lx, j = fy0 + ly, k = fz0 + lz;
-        const int u = (lx + 1) + SY * (ly + 1) + SZ * (lz + 1);
-        const int d = ds[u];
-        const V yc = ys[u];
-        const V nsum = ((ys[u - 1] + ys[u + 1]) + (ys[u - SY] + ys[u + SY])) + (ys[u - SZ] + ys[u + SZ]);
-        if (i < f.nx && j < f.ny && k < f.nz)
+        for (int m = 0; m < CF::J; ++m) {
+            const int lz = fzg + CF::P * m, k = fz0 + lz;
+            if (lz >= MGU_FZ || k >= f.nz) break;
+            const int u = ub + SZ * (lz + 1);
+            const int d = ds[u];
+            const V yc = ys[u];
+            const V nsum = ((ys[u - 1] + ys[u + 1]) + (ys[u - SY] + ys[u + SY])) + (ys[u - SZ] + ys[u + SZ]);
             ((V*)f.x)[level_index(f, i, j, k)] = d ? yc + w * ((bs[u] - (V)d * yc) + nsum) * recip_nc<V>(d) : V(0);
+        }
     }
 }
 
