@@ -329,7 +329,14 @@ flip_status timer_collect(flip_handle* h, hipStream_t st)
 template <typename V>
 flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgState* out)
 {
-    int chunk = h->prev_iters > 2 ? h->prev_iters - 2 : 16;
+    // Chunk sizes: each host test idles the GPU for a round trip, and each
+    // iteration launched past convergence still costs its launches (two with
+    // Jacobi, fourteen with the V-cycle), so the multigrid solve starts with
+    // the previous step's count and then tests every two iterations, the
+    // Jacobi solve with two fewer than before and then every eight.
+    const bool mg_solve = h->nmg > 0;
+    int chunk = h->prev_iters > 2 ? (mg_solve ? h->prev_iters : h->prev_iters - 2) : 16;
+    const int next_chunk = mg_solve ? 2 : 8;
     int launched = 0;
     const int first_sample = h->ev_used / 2;
     auto direction = [&](int k) {
@@ -376,7 +383,7 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
         HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (h->h_ps->done != PCG_RUNNING || launched > max_iters + 8) break;
-        chunk = 8;
+        chunk = next_chunk;
     }
     *out = *h->h_ps;
     h->prev_iters = out->iter;

@@ -180,9 +180,9 @@ __host__ __device__ inline int64_t mg_down_blocks(const MgLevel& c)
     return (int64_t)mg_down_blocks_x(c) * mg_down_blocks_y(c) * ((c.nz + MGD_CZ - 1) / MGD_CZ);
 }
 
-// NT threads per workgroup: 256, or 1024 on the small levels, where a
+// NT threads per workgroup: 512, or 1024 on the small levels, where a
 // launch has few workgroups and the time is the chain of each thread's
-// serial work (the values are the same either way)
+// serial work (the values are the same either way; batched launches use 256)
 template <typename V, int NT>
 __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const MgLevel& c,
                                              const PcgState* __restrict__ ps)
@@ -503,15 +503,16 @@ template <typename V>
 void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st)
 {
     // launches of fewer than 512 workgroups (the levels below 128^3 cells at
-    // 256^3) run 1024-thread workgroups: 1.69 -> 1.44 ms per step for the
-    // coarse levels at 256^3; the 128^3 level measured faster with 256
+    // 256^3) run 1024-thread workgroups, larger ones 512 (256 threads for
+    // all: 1.69 ms per step for the coarse levels at 256^3; 1024 for the
+    // small ones: 1.44; 512 for the 128^3 level: 1.32, where 1024 was slower)
     constexpr int64_t SMALL = 512;
     for (int l = 0; l + 1 < nlev; ++l) {
         const int64_t nb = mg_down_blocks(lv[l + 1]);
         if (nb < SMALL)
             hipLaunchKernelGGL((k_mg_down<V, 1024>), dim3((unsigned)nb), dim3(1024), 0, st, lv[l], lv[l + 1], ps);
         else
-            hipLaunchKernelGGL((k_mg_down<V, 256>), dim3((unsigned)nb), dim3(256), 0, st, lv[l], lv[l + 1], ps);
+            hipLaunchKernelGGL((k_mg_down<V, 512>), dim3((unsigned)nb), dim3(512), 0, st, lv[l], lv[l + 1], ps);
     }
     hipLaunchKernelGGL(k_mg_bottom<V>, dim3(1), dim3(512), 0, st, lv[nlev - 1], ps);
     for (int l = nlev - 2; l >= 0; --l) {
@@ -519,7 +520,7 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
         if (nb < SMALL)
             hipLaunchKernelGGL((k_mg_up<V, 1024>), dim3((unsigned)nb), dim3(1024), 0, st, lv[l], lv[l + 1], ps);
         else
-            hipLaunchKernelGGL((k_mg_up<V, 256>), dim3((unsigned)nb), dim3(256), 0, st, lv[l], lv[l + 1], ps);
+            hipLaunchKernelGGL((k_mg_up<V, 512>), dim3((unsigned)nb), dim3(512), 0, st, lv[l], lv[l + 1], ps);
     }
 }
 
