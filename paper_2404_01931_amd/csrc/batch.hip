@@ -21,6 +21,10 @@ constexpr size_t TABLE_ALIGN = 256;
 constexpr int GRAPH_CHUNK = 8;  // solver iterations per recorded chunk (even: direction buffers alternate)
 constexpr int FIRST_CHUNK = 16; // solver iterations before the first convergence check, without history
 constexpr int NEXT_CHUNK = 8;   // solver iterations between later checks
+// Multigrid batches: an iteration launched past convergence costs fourteen
+// launches, so they start with the previous step's largest count and then
+// test every MG_NEXT_CHUNK iterations (a recorded chunk of that size too).
+constexpr int MG_NEXT_CHUNK = 2;
 
 // Host image of the launch tables, uploaded once into the batch workspace.
 struct Tables {
@@ -403,6 +407,7 @@ struct flip_batch {
     hipStream_t last_stream = nullptr;  // stream of the last step
     hipGraphExec_t g_pre[2] = {nullptr, nullptr};
     hipGraphExec_t g_chunk = nullptr;
+    hipGraphExec_t g_chunk_small = nullptr;  // MG_NEXT_CHUNK iterations (multigrid batches)
     hipGraphExec_t g_post[2] = {nullptr, nullptr};
 };
 
@@ -517,6 +522,11 @@ flip_status batch_step(flip_batch* b, hipStream_t st)
                                          &b->g_chunk);
             if (r != FLIP_OK) return r;
         }
+        if (b->S.mg && !b->g_chunk_small) {
+            flip_status r = record_graph(b, [&](hipStream_t cs) { enqueue_chunk<T>(b, MG_NEXT_CHUNK, cs); },
+                                         &b->g_chunk_small);
+            if (r != FLIP_OK) return r;
+        }
         if (!b->g_post[ph]) {
             flip_status r = record_graph(b, [&](hipStream_t cs) { enqueue_post<T>(b, ph, cs); }, &b->g_post[ph]);
             if (r != FLIP_OK) return r;
@@ -529,14 +539,17 @@ flip_status batch_step(flip_batch* b, hipStream_t st)
     // the solve: chunks of iterations until no scene is running
     int prev = 0;
     for (flip_handle* h : b->hs) prev = std::max(prev, h->prev_iters);
-    int chunk = prev > 2 ? prev - 2 : FIRST_CHUNK;
-    const int unit = graphs ? GRAPH_CHUNK : 2;
+    const bool mg = b->S.mg;
+    int chunk = prev > 2 ? (mg ? prev : prev - 2) : FIRST_CHUNK;
+    const int unit = graphs && !mg ? GRAPH_CHUNK : 2;
     chunk = (chunk + unit - 1) / unit * unit;
     int launched = 0;
     const size_t sum_bytes = sizeof(SolveSummary) * ns;
     for (;;) {
         if (graphs) {
             for (int q = 0; q < chunk / GRAPH_CHUNK; ++q) HIP_TRY(hipGraphLaunch(b->g_chunk, st));
+            for (int q = 0; q < (chunk % GRAPH_CHUNK) / MG_NEXT_CHUNK; ++q)
+                HIP_TRY(hipGraphLaunch(b->g_chunk_small, st));
         } else {
             enqueue_chunk<T>(b, chunk, st);
         }
@@ -546,7 +559,7 @@ flip_status batch_step(flip_batch* b, hipStream_t st)
         bool running = false;
         for (int s = 0; s < ns; ++s) running = running || b->h_sum[s].done == PCG_RUNNING;
         if (!running || launched > b->max_cap + 8) break;
-        chunk = graphs ? GRAPH_CHUNK : NEXT_CHUNK;
+        chunk = mg ? MG_NEXT_CHUNK : (graphs ? GRAPH_CHUNK : NEXT_CHUNK);
     }
 
     if (graphs)
@@ -659,7 +672,7 @@ void flip_batch_destroy(flip_batch* b)
     if (!b) return;
     // the handles may already be gone: only the batch's own streams are touched
     if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
-    for (hipGraphExec_t* g : {&b->g_pre[0], &b->g_pre[1], &b->g_chunk, &b->g_post[0], &b->g_post[1]})
+    for (hipGraphExec_t* g : {&b->g_pre[0], &b->g_pre[1], &b->g_chunk, &b->g_chunk_small, &b->g_post[0], &b->g_post[1]})
         if (*g) (void)hipGraphExecDestroy(*g);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->h_sum) (void)hipHostFree(b->h_sum);
