@@ -200,14 +200,16 @@ def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plai
 def measure(args, sc, solver: str) -> dict:
     """Throughput of `args.steps` steps of scene sc on one handle (after
     `args.warmup`), then per-kernel durations on a second handle with kernel
-    timing on. solver: "jacobi" or "multigrid" (FLIP_FLAG_MULTIGRID)."""
+    timing on. solver: "jacobi", "multigrid" (FLIP_FLAG_MULTIGRID) or "rbgs"
+    (FLIP_FLAG_RED_BLACK_GS: the paper's red-black Gauss-Seidel instead of CG)."""
     import torch
 
     from paper_2404_01931_amd import flip
 
     mgflag = flip.FLIP_FLAG_MULTIGRID if solver == "multigrid" else 0
+    sflag = mgflag | (flip.FLIP_FLAG_RED_BLACK_GS if solver == "rbgs" else 0)
     # throughput: a handle without kernel timing (timed launches cost extra work)
-    cfg, keep = flip.scene_config(sc, flags=mgflag)
+    cfg, keep = flip.scene_config(sc, flags=sflag)
     progress(f"init {sc.name} ({solver})")
     t = time.perf_counter()
     sim = flip.Simulation(cfg, keep)
@@ -231,7 +233,7 @@ def measure(args, sc, solver: str) -> dict:
     # kernel durations: a second handle of the same scene with kernel timing on
     # (HIP events; the solver kernels record their own start and end), stepped
     # through the same warm-up and a few more steps
-    cfg_t, keep_t = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING | mgflag)
+    cfg_t, keep_t = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING | sflag)
     sim = flip.Simulation(cfg_t, keep_t)
     if args.warmup:
         sim.step(args.warmup)
@@ -306,9 +308,10 @@ def main():
     ap.add_argument("--serving-no-graphs", action="store_true")
     ap.add_argument("--serving-plain-sample", type=int, default=16)
     ap.add_argument("--serving-only", action="store_true", help="skip the 256^3 benchmark")
-    ap.add_argument("--solver", choices=["multigrid", "jacobi"], default="multigrid",
+    ap.add_argument("--solver", choices=["multigrid", "jacobi", "rbgs"], default="multigrid",
                     help="preconditioner of the pressure CG for the headline number (the other one is "
-                         "measured too and reported beside it)")
+                         "measured too and reported beside it), or rbgs: the paper's red-black "
+                         "Gauss-Seidel solver alone")
     ap.add_argument("--no-second-solver", action="store_true", help="measure the headline solver only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scales HBM counters)")
@@ -345,6 +348,8 @@ def main():
         sc = inputs.scene(args.scene, precision=args.precision)
     # the headline solver, then the other one on the same scene for comparison
     solvers = ["jacobi", "multigrid"] if args.solver == "jacobi" else ["multigrid", "jacobi"]
+    if args.solver == "rbgs":
+        solvers = ["rbgs"]
     if args.no_second_solver:
         solvers = solvers[:1]
     runs = {name: measure(args, sc, name) for name in solvers}
@@ -361,7 +366,7 @@ def main():
         progress(f"cpu baseline: {cpu['value']:.3e} particle-steps/s")
 
     n, elapsed = main_run["n"], main_run["elapsed"]
-    solver_label = {"jacobi": "Jacobi", "multigrid": "multigrid"}
+    solver_label = {"jacobi": "Jacobi-PCG", "multigrid": "multigrid-PCG", "rbgs": "red-black Gauss-Seidel"}
     line = {
         "metric": "particle-steps/s",
         "value": n * args.steps / elapsed,
@@ -377,7 +382,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{sc.name}: drop into pool, {sc.n}^3 MAC grid, {n} particles, "
                                f"{sc.precision.upper()}, dt=1/{round(1 / sc.dt)}, FLIP {sc.flip_ratio}, "
-                               f"{solver_label[main_run['solver']]}-PCG tol {sc.tol:g}"
+                               f"{solver_label[main_run['solver']]} tol {sc.tol:g}"
                                + (f", FP64 refinement to {sc.ir_tol:g}" if sc.precision == "mixed" else ""),
                    "grid": sc.n, "particles": n, "parallelism": "single GPU"},
         "roofline": main_run["roofline"],

@@ -81,9 +81,21 @@ enum {
     FLIP_FLAG_NO_PROJECTION = 2u,      /* skip solve and projection (transfer-only steps)  */
     FLIP_FLAG_ADVECT_PARTICLE_VEL = 4u,/* advect with the blended particle velocity        */
     FLIP_FLAG_KERNEL_TIMING = 8u,      /* bracket kernel launches with HIP events           */
-    FLIP_FLAG_MULTIGRID = 16u          /* precondition the pressure CG (FLIP_MIXED: its FP32
+    FLIP_FLAG_MULTIGRID = 16u,         /* precondition the pressure CG (FLIP_MIXED: its FP32
                                           inner solves) with a multigrid V-cycle instead of
                                           Jacobi                                              */
+    FLIP_FLAG_RED_BLACK_GS = 32u       /* solve the pressure equation by red-black
+                                          Gauss-Seidel (the paper's GPU solver, Sec. 3.2.3)
+                                          instead of CG: same system and stopping rule, the
+                                          residual max |b - A p| (evaluated in FP64) tested
+                                          every 32 iterations (a red and a black pass each);
+                                          in FP32 it cannot fall much below 1e-5 max |b| on
+                                          grids of 32^3 and up, so FP32 runs need a tolerance
+                                          above that; pcg_max_iters then caps
+                                          those iterations (<= 0: 50 * max(nx, ny, nz)^2).
+                                          FLIP_FP32 and FLIP_FP64 only, not with
+                                          FLIP_FLAG_MULTIGRID, not in a batch
+                                          (FLIP_E_INVALID)                                    */
 };
 
 typedef struct {
@@ -210,8 +222,8 @@ void flip_destroy(flip_handle* h);
  *
  * Requirements: 1 <= nscenes <= FLIP_BATCH_MAX_SCENES initialised handles,
  * all FLIP_FP32 or all FLIP_FP64 (FLIP_MIXED is not batched), all with or
- * all without FLIP_FLAG_MULTIGRID, none with FLIP_FLAG_NO_PROJECTION or
- * FLIP_FLAG_KERNEL_TIMING, no handle twice. The handles stay owned by the
+ * all without FLIP_FLAG_MULTIGRID, none with FLIP_FLAG_NO_PROJECTION,
+ * FLIP_FLAG_KERNEL_TIMING or FLIP_FLAG_RED_BLACK_GS, no handle twice. The handles stay owned by the
  * caller, must outlive the batch and must not be stepped by other calls while
  * the batch steps.
  *

@@ -1,5 +1,6 @@
 // C ABI of libflipmi: configuration, workspace carving, seeding, the step
 // sequence and readback. See include/flip.h for the contract of each call.
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -143,6 +144,8 @@ flip_status validate(const flip_config* c)
     if (c->precision != FLIP_FP32 && c->precision != FLIP_FP64 && c->precision != FLIP_MIXED)
         return FLIP_E_INVALID;
     if (c->precision == FLIP_MIXED && (!(c->ir_tol > 0.0) || !std::isfinite(c->ir_tol))) return FLIP_E_INVALID;
+    if ((c->flags & FLIP_FLAG_RED_BLACK_GS) && (c->precision == FLIP_MIXED || (c->flags & FLIP_FLAG_MULTIGRID)))
+        return FLIP_E_INVALID;
     if (c->pos0) {
         if (c->n_particles < 0 || c->n_particles >= ((int64_t)1 << 31) || !c->vel0) return FLIP_E_INVALID;
     } else {
@@ -268,6 +271,7 @@ void carve(flip_handle* h, Carver& cv)
     h->partials = cv.take<double>(3 * sizeof(double) * solver_groups(s.T));
     h->pslots = cv.take<double>(PCG_SLOT_SETS * sizeof(double) * solver_groups(s.T));
     h->ps = cv.take<PcgState>(PCG_STATE_BYTES + SYNC_BYTES);
+    h->gs_rmax = cv.take<unsigned long long>(8);
     h->staging = cv.take<void>(8 * s.C);
 }
 
@@ -393,6 +397,51 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
     return FLIP_OK;
 }
 
+// Red-black Gauss-Seidel solve (FLIP_FLAG_RED_BLACK_GS, Sec. 3.2.3) from the
+// state the right-hand-side kernel left (p = 0, max |b|, tolerance): chunks of
+// GS_CHECK_EVERY iterations, each followed by the residual max |b - A p| over
+// the fluid cells, until it meets the tolerance or the cap.
+constexpr int GS_CHECK_EVERY = 32;
+
+int gs_iter_cap(const flip_config& c)
+{
+    const int64_t n = std::max(c.nx, std::max(c.ny, c.nz));
+    return c.pcg_max_iters > 0 ? c.pcg_max_iters : (int)std::min<int64_t>(50 * n * n, 1 << 30);
+}
+
+template <typename V>
+flip_status gs_loop(flip_handle* h, V* p, int max_iters, hipStream_t st, PcgState* state)
+{
+    unsigned long long* rmax = h->gs_rmax;
+    const double target = state->tol * state->max_b;
+    int iters = 0;
+    double max_r = 0.0;
+    for (;;) {
+        const int chunk = std::min(GS_CHECK_EVERY, max_iters - iters);
+        launch_gs_sweeps<V>(h->na, chunk, h->tile_nbr, h->diag, (const V*)h->b, p, st);
+        launch_gs_residual<V>(h->na, h->tile_nbr, h->diag, (const V*)h->b, p, rmax, st);
+        iters += chunk;
+        HIP_TRY(hipMemcpyAsync(&h->h_ps->max_r, rmax, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        max_r = h->h_ps->max_r;
+        if (!(max_r <= DBL_MAX)) {
+            state->done = PCG_BREAKDOWN;
+            break;
+        }
+        if (max_r <= target) {
+            state->done = PCG_CONVERGED;
+            break;
+        }
+        if (iters >= max_iters) {
+            state->done = PCG_MAX_ITERS;
+            break;
+        }
+    }
+    state->iter = iters;
+    state->max_r = max_r;
+    return FLIP_OK;
+}
+
 template <typename T, bool MIXED>
 flip_status run_step(flip_handle* h, hipStream_t st)
 {
@@ -477,8 +526,16 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     ps_host = *h->h_ps;
     h->na = ps_host.n_active;
     int iters = 0, refinements = 0;
+    const bool gs = (c.flags & FLIP_FLAG_RED_BLACK_GS) != 0;
+    if (project && gs) {
+        if (ps_host.done == PCG_RUNNING) {
+            flip_status r = gs_loop<T>(h, (T*)h->xin[0], gs_iter_cap(c), st, &ps_host);
+            if (r != FLIP_OK) return r;
+            iters = ps_host.iter;
+        }
+    }
     if (project) {
-        while (ps_host.done == PCG_RUNNING) {
+        while (!gs && ps_host.done == PCG_RUNNING) {
             flip_status r = pcg_loop<T>(h, (T*)h->xin[h->xi], max_iters, st, &ps_host);
             if (r != FLIP_OK) return r;
             iters += ps_host.iter;

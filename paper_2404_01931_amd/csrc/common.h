@@ -135,6 +135,16 @@ void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint
                   int32_t* tile_slot, uint32_t* tile_list, int32_t* tile_nbr, uint32_t* d_nactive,
                   uint32_t* scan_tmp, hipStream_t st);
 
+// red-black Gauss-Seidel (FLIP_FLAG_RED_BLACK_GS): `iters` iterations (a red
+// and a black pass each) over the n_active tiles, and max |b - A p| over the
+// fluid cells into *rmax (as the bits of a non-negative double)
+template <typename V>
+void launch_gs_sweeps(int n_active, int iters, const int32_t* nbr, const uint8_t* diag, const V* b, V* p,
+                      hipStream_t st);
+template <typename V>
+void launch_gs_residual(int n_active, const int32_t* nbr, const uint8_t* diag, const V* b, const V* p,
+                        unsigned long long* rmax, hipStream_t st);
+
 // particle-to-grid for all faces, with gravity (gdt = g * dt per axis) and walls;
 // p2g_blocks: its workgroup count (one per 10^3 block of cells, P2G_NT threads)
 constexpr int P2G_NT = 192;

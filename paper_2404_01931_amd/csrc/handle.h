@@ -52,6 +52,7 @@ struct flip_handle {
     int nmg = 0;
     double* partials = nullptr;  // reduction slots of the start kernels (EMPTY when idle)
     double* pslots = nullptr;    // partial sums of the iteration kernels
+    unsigned long long* gs_rmax = nullptr;  // FLIP_FLAG_RED_BLACK_GS: residual max (double bits)
     flipmi::PcgState* ps = nullptr;
     void* staging = nullptr;
     // host side

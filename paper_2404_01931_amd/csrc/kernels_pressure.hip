@@ -1352,4 +1352,124 @@ template void launch_densify<float, float>(const Geo&, const int32_t*, const uin
 template void launch_densify<double, double>(const Geo&, const int32_t*, const uint8_t*,
                                              const double*, double*, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Red-black Gauss-Seidel (FLIP_FLAG_RED_BLACK_GS): the paper's GPU pressure
+// solver (Sec. 3.2.3). The cells are split by the parity of i + j + k; every
+// neighbour of a cell has the other parity, so one colour is updated in
+// parallel from the other's values, p_c = (b_c + sum of p over the fluid
+// neighbours) / n_c, in two passes per iteration (red, then black). Air
+// neighbours hold 0; cells outside the box are not counted in n_c and add
+// nothing. One workgroup per active tile, one cell of the colour per thread.
+// A tile's origin is a multiple of 8, so local and global parity agree.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// value of p at local cell l of slot `slot` shifted one cell along direction
+// f (0..5: -x +x -y +y -z +z), from the neighbouring tile when it leaves the
+// tile (0 when that tile is not active)
+template <typename V>
+__device__ inline V gs_neighbour(const V* __restrict__ p, const int32_t* __restrict__ nbr, int slot, int lx, int ly,
+                                 int lz, int f)
+{
+    int x = lx, y = ly, z = lz, s = slot;
+    const int d = (f & 1) ? 1 : -1;
+    int* c = f < 2 ? &x : (f < 4 ? &y : &z);
+    *c += d;
+    if (*c < 0 || *c > 7) {
+        s = nbr[(int64_t)slot * 6 + f];
+        *c &= 7;
+    }
+    return s >= 0 ? p[(int64_t)s * TILE_CELLS + x + 8 * y + 64 * z] : V(0);
+}
+
+template <typename V>
+__device__ inline V gs_nsum(const V* __restrict__ p, const int32_t* __restrict__ nbr, int slot, int lx, int ly, int lz)
+{
+    return ((gs_neighbour(p, nbr, slot, lx, ly, lz, 0) + gs_neighbour(p, nbr, slot, lx, ly, lz, 1)) +
+            (gs_neighbour(p, nbr, slot, lx, ly, lz, 2) + gs_neighbour(p, nbr, slot, lx, ly, lz, 3))) +
+           (gs_neighbour(p, nbr, slot, lx, ly, lz, 4) + gs_neighbour(p, nbr, slot, lx, ly, lz, 5));
+}
+
+template <typename V>
+__device__ inline double gs_nsum_f64(const V* __restrict__ p, const int32_t* __restrict__ nbr, int slot, int lx, int ly,
+                                     int lz)
+{
+    double v[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) v[f] = (double)gs_neighbour(p, nbr, slot, lx, ly, lz, f);
+    return ((v[0] + v[1]) + (v[2] + v[3])) + (v[4] + v[5]);
+}
+
+}  // namespace
+
+template <typename V, int COLOR>
+__global__ __launch_bounds__(256) void k_gs_sweep(const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
+                                                  const V* __restrict__ b, V* __restrict__ p)
+{
+    const int slot = blockIdx.x, t = threadIdx.x;
+    // thread t: x-row t / 4 of the tile, the (t % 4)-th cell of the colour in it
+    const int ly = (t >> 2) & 7, lz = t >> 5;
+    const int lx = 2 * (t & 3) + ((ly + lz + COLOR) & 1);
+    const int64_t e = (int64_t)slot * TILE_CELLS + lx + 8 * ly + 64 * lz;
+    const int d = diag[e];
+    if (d == 0) return;
+    p[e] = (b[e] + gs_nsum(p, nbr, slot, lx, ly, lz)) / (V)d;
+}
+
+// max |b - A p| over the fluid cells (in FP64), folded into *rmax (the bits
+// of a non-negative double order like unsigned integers; *rmax starts at 0)
+template <typename V>
+__global__ __launch_bounds__(256) void k_gs_residual(const int32_t* __restrict__ nbr,
+                                                     const uint8_t* __restrict__ diag, const V* __restrict__ b,
+                                                     const V* __restrict__ p, unsigned long long* __restrict__ rmax)
+{
+    __shared__ double red[256 / WAVE];
+    const int slot = blockIdx.x, t = threadIdx.x;
+    double m = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int l = t + 256 * h;
+        const int lx = l & 7, ly = (l >> 3) & 7, lz = l >> 6;
+        const int64_t e = (int64_t)slot * TILE_CELLS + l;
+        const int d = diag[e];
+        if (d) {
+            // evaluated in FP64: in FP32 the rounding of this expression alone
+            // is of the order of the tolerances in use
+            const double r = (double)b[e] - ((double)d * (double)p[e] - gs_nsum_f64(p, nbr, slot, lx, ly, lz));
+            m = fmax(m, finite_or_inf(fabs(r)));
+        }
+    }
+    m = block_max<256>(m, red);
+    if (t == 0) atomicMax(rmax, (unsigned long long)__double_as_longlong(m));
+}
+
+template <typename V>
+void launch_gs_sweeps(int n_active, int iters, const int32_t* nbr, const uint8_t* diag, const V* b, V* p,
+                      hipStream_t st)
+{
+    if (n_active <= 0) return;
+    for (int i = 0; i < iters; ++i) {
+        hipLaunchKernelGGL((k_gs_sweep<V, 0>), dim3((unsigned)n_active), dim3(256), 0, st, nbr, diag, b, p);
+        hipLaunchKernelGGL((k_gs_sweep<V, 1>), dim3((unsigned)n_active), dim3(256), 0, st, nbr, diag, b, p);
+    }
+}
+
+template <typename V>
+void launch_gs_residual(int n_active, const int32_t* nbr, const uint8_t* diag, const V* b, const V* p,
+                        unsigned long long* rmax, hipStream_t st)
+{
+    launch_fill_u64((uint64_t*)rmax, 1, 0ull, st);
+    if (n_active <= 0) return;
+    hipLaunchKernelGGL(k_gs_residual<V>, dim3((unsigned)n_active), dim3(256), 0, st, nbr, diag, b, p, rmax);
+}
+
+template void launch_gs_sweeps<float>(int, int, const int32_t*, const uint8_t*, const float*, float*, hipStream_t);
+template void launch_gs_sweeps<double>(int, int, const int32_t*, const uint8_t*, const double*, double*,
+                                       hipStream_t);
+template void launch_gs_residual<float>(int, const int32_t*, const uint8_t*, const float*, const float*,
+                                        unsigned long long*, hipStream_t);
+template void launch_gs_residual<double>(int, const int32_t*, const uint8_t*, const double*, const double*,
+                                         unsigned long long*, hipStream_t);
+
 }  // namespace flipmi

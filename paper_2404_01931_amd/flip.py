@@ -31,6 +31,7 @@ FLIP_FLAG_NO_PROJECTION = 2
 FLIP_FLAG_ADVECT_PARTICLE_VEL = 4
 FLIP_FLAG_KERNEL_TIMING = 8
 FLIP_FLAG_MULTIGRID = 16
+FLIP_FLAG_RED_BLACK_GS = 32
 
 FLIP_FIELD_POS = 0
 FLIP_FIELD_VEL = 1
