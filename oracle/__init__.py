@@ -85,6 +85,7 @@ def _load():
             "orc_project": (None, [G, i32, P, P, dbl, dbl, P, P]),
             "orc_interp": (dbl, [G, i32, P, dbl, dbl, dbl]),
             "orc_g2p_advect": (None, [G, i64, P, P, P, P, P, P, P, P, dbl, dbl, ctypes.c_uint]),
+            "orc_cfl_dt": (dbl, [i64, P, P, P, dbl, dbl, dbl]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -296,6 +297,14 @@ def g2p_advect(grid: Grid, pos, vel, unew, uold, flip_ratio: float, dt: float, f
                            _ptr(vel[0]), _ptr(vel[1]), _ptr(vel[2]), arr_n, arr_o,
                            float(flip_ratio), float(dt), int(flags))
     return pos, vel
+
+
+def cfl_dt(vel, dx: float, alpha: float, dt_max: float) -> float:
+    """CFL time step (Sec. 3.1.4): min(dt_max, alpha dx / max |u_p|), dt_max when all rest."""
+    vel = _f64(vel)
+    n = vel.shape[1]
+    return float(_load().orc_cfl_dt(n, _ptr(vel[0]), _ptr(vel[1]), _ptr(vel[2]), float(dx), float(alpha),
+                                    float(dt_max)))
 
 
 @dataclass

@@ -662,3 +662,17 @@ void orc_g2p_advect(const orc_grid* g, int64_t n, double* px, double* py, double
     }
     for (int a = 0; a < 3; ++a) free(delta[a]);
 }
+
+/* Sec. 3.1.4: dt <= alpha dx / |u|, with |u| the speed of the fastest particle. */
+double orc_cfl_dt(int64_t n, const double* vx, const double* vy, const double* vz, double dx, double alpha,
+                  double dt_max)
+{
+    double umax = 0.0;
+    for (int64_t p = 0; p < n; ++p) {
+        const double speed = sqrt((vx[p] * vx[p] + vy[p] * vy[p]) + vz[p] * vz[p]);
+        if (speed > umax) umax = speed;
+    }
+    if (umax == 0.0) return dt_max;
+    const double dt = alpha * dx / umax;
+    return dt < dt_max ? dt : dt_max;
+}

@@ -68,6 +68,10 @@ double orc_interp(const orc_grid* g, int a, const double* f, double x, double y,
 void orc_g2p_advect(const orc_grid* g, int64_t n, double* px, double* py, double* pz,
                     double* vx, double* vy, double* vz, const double* const unew[3],
                     const double* const uold[3], double flip_ratio, double dt, unsigned flags);
+/* CFL time step (Sec. 3.1.4): the fastest particle's speed |u|max, and
+   dt = min(dt_max, alpha dx / |u|max) (dt_max when every particle is at rest) */
+double orc_cfl_dt(int64_t n, const double* vx, const double* vy, const double* vz, double dx, double alpha,
+                  double dt_max);
 
 #ifdef __cplusplus
 }

@@ -402,3 +402,22 @@ def test_particle_count_ids_and_bounds_are_conserved(orc):
         assert np.array_equal(np.sort(ids), np.arange(n, dtype=np.uint32))
         assert pos.min() >= skin and pos.max() <= 1.0 - skin
         assert r.solve.status == O.STATUS_CONVERGED
+
+
+def test_cfl_time_step(orc):
+    """Sec. 3.1.4: dt = min(dt_max, alpha dx / |u|max) over particle speeds."""
+    # the fastest particle moves at |(3, 4, 0)| = 5, the others slower
+    vel = np.array([[1.0, -2.0, 3.0, 0.5], [0.0, 1.0, -4.0, 0.5], [0.0, 2.0, 0.0, -0.5]])
+    assert orc.cfl_dt(vel, dx=0.1, alpha=3.0, dt_max=1.0) == 3.0 * 0.1 / 5.0
+    # the cap: a slow field keeps dt_max
+    assert orc.cfl_dt(vel, dx=0.1, alpha=3.0, dt_max=0.05) == 0.05
+    # all at rest: dt_max
+    assert orc.cfl_dt(np.zeros((3, 7)), dx=0.1, alpha=3.0, dt_max=0.01) == 0.01
+    # the speed is the Euclidean norm of the whole velocity, not one component
+    v1 = np.array([[1.0], [1.0], [1.0]])
+    assert orc.cfl_dt(v1, dx=1.0, alpha=1.0, dt_max=10.0) == 1.0 / np.sqrt(3.0)
+    # a brute-force reading over random velocities
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=(3, 1000))
+    umax = max(np.sqrt((v[0, p] * v[0, p] + v[1, p] * v[1, p]) + v[2, p] * v[2, p]) for p in range(1000))
+    assert orc.cfl_dt(v, dx=1 / 64, alpha=3.0, dt_max=1.0) == 3.0 * (1 / 64) / umax
