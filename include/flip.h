@@ -84,7 +84,7 @@ enum {
     FLIP_FLAG_MULTIGRID = 16u,         /* precondition the pressure CG (FLIP_MIXED: its FP32
                                           inner solves) with a multigrid V-cycle instead of
                                           Jacobi                                              */
-    FLIP_FLAG_RED_BLACK_GS = 32u       /* solve the pressure equation by red-black
+    FLIP_FLAG_RED_BLACK_GS = 32u,      /* solve the pressure equation by red-black
                                           Gauss-Seidel (the paper's GPU solver, Sec. 3.2.3)
                                           instead of CG: same system and stopping rule, the
                                           residual max |b - A p| (evaluated in FP64) tested
@@ -96,6 +96,12 @@ enum {
                                           FLIP_FP32 and FLIP_FP64 only, not with
                                           FLIP_FLAG_MULTIGRID, not in a batch
                                           (FLIP_E_INVALID)                                    */
+    FLIP_FLAG_ADAPTIVE_DT = 64u        /* CFL time step (Sec. 3.1.4): each step takes
+                                          dt = min(flip_config.dt, cfl * dx / |u|max), |u|max
+                                          the speed of the fastest particle at the step's
+                                          start (one 8-byte readback per step); the step's dt
+                                          is reported in flip_step_stats.dt. Needs cfl > 0;
+                                          not in a batch (FLIP_E_INVALID)                     */
 };
 
 typedef struct {
@@ -122,6 +128,8 @@ typedef struct {
     int64_t n_particles;
     const double* pos0;        /* host, 3 * n_particles doubles, SoA, inside the domain    */
     const double* vel0;        /* host, 3 * n_particles doubles, SoA                       */
+    double cfl;                /* FLIP_FLAG_ADAPTIVE_DT: the CFL number alpha (the paper
+                                  uses 3); ignored otherwise                               */
 } flip_config;
 
 /* fields for flip_readback / flip_field_bytes */
@@ -176,6 +184,7 @@ typedef struct {
     int32_t refinements;           /* last step, FLIP_MIXED: outer FP64 refinements        */
     double kernel_ms[FLIP_KERNEL_COUNT];      /* summed durations of timed launches        */
     int64_t kernel_launches[FLIP_KERNEL_COUNT];/* number of timed launches                 */
+    double dt;                     /* last step: the time step it took                     */
 } flip_step_stats;
 
 /* Device workspace needed for cfg (pure; used for HBM admission). */

@@ -146,6 +146,7 @@ flip_status validate(const flip_config* c)
     if (c->precision == FLIP_MIXED && (!(c->ir_tol > 0.0) || !std::isfinite(c->ir_tol))) return FLIP_E_INVALID;
     if ((c->flags & FLIP_FLAG_RED_BLACK_GS) && (c->precision == FLIP_MIXED || (c->flags & FLIP_FLAG_MULTIGRID)))
         return FLIP_E_INVALID;
+    if ((c->flags & FLIP_FLAG_ADAPTIVE_DT) && (!(c->cfl > 0.0) || !std::isfinite(c->cfl))) return FLIP_E_INVALID;
     if (c->pos0) {
         if (c->n_particles < 0 || c->n_particles >= ((int64_t)1 << 31) || !c->vel0) return FLIP_E_INVALID;
     } else {
@@ -451,6 +452,18 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     const int nxt = h->cur ^ 1;
     const flip_config& c = h->cfg;
 
+    // 0. the step's dt: fixed, or the CFL rule of Sec. 3.1.4 on the particles'
+    // speeds at the step's start
+    double dt = c.dt;
+    if (c.flags & FLIP_FLAG_ADAPTIVE_DT) {
+        launch_max_speed2<T>((const T*)h->vel[h->cur], n, h->gs_rmax, st);
+        HIP_TRY(hipMemcpyAsync(&h->h_ps->max_r, h->gs_rmax, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const double umax = std::sqrt(h->h_ps->max_r);
+        if (umax > 0.0) dt = std::min(c.dt, c.cfl * c.dx / umax);
+    }
+    h->stats.dt = dt;
+
     // 1. binning
     int tq = timer_begin(h, FLIP_KERNEL_BIN_KEYS, st);
     launch_fill_u32(h->count, s.C, 0u, st);
@@ -478,8 +491,8 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     const T* vel = (const T*)h->vel[h->cur];
     const bool grav = !(c.flags & FLIP_FLAG_NO_GRAVITY);
     {
-        const T gdt[3] = {(T)(grav ? c.gravity[0] * c.dt : 0.0), (T)(grav ? c.gravity[1] * c.dt : 0.0),
-                          (T)(grav ? c.gravity[2] * c.dt : 0.0)};
+        const T gdt[3] = {(T)(grav ? c.gravity[0] * dt : 0.0), (T)(grav ? c.gravity[1] * dt : 0.0),
+                          (T)(grav ? c.gravity[2] * dt : 0.0)};
         T* const old[3] = {(T*)h->f_old[0], (T*)h->f_old[1], (T*)h->f_old[2]};
         T* const star[3] = {(T*)h->f_star[0], (T*)h->f_star[1], (T*)h->f_star[2]};
         tq = timer_begin(h, FLIP_KERNEL_P2G, st);
@@ -492,7 +505,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     flip_status ret = FLIP_OK;
     const bool project = !(c.flags & FLIP_FLAG_NO_PROJECTION);
     const int max_iters = solve_iter_cap(c);
-    const double scale_b = -c.density * c.dx / c.dt;
+    const double scale_b = -c.density * c.dx / dt;
     h->scur = 0;
     h->xi = 0;
     // the solver kernels read the active-tile count from device memory: no
@@ -561,7 +574,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
             if (ps_host.done == PCG_BREAKDOWN) ret = ps_host.sync_error ? FLIP_E_HIP : FLIP_E_NONFINITE;
         }
         // 5. projection with the solution (FP64 when MIXED)
-        const T scale = (T)(c.dt / (c.density * c.dx));
+        const T scale = (T)(dt / (c.density * c.dx));
         for (int a = 0; a < 3; ++a) {
             tq = timer_begin(h, FLIP_KERNEL_PROJECT, st);
             if (MIXED)
@@ -583,7 +596,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     tq = timer_begin(h, FLIP_KERNEL_G2P, st);
     launch_g2p<T>(g, n, h->start, h->count, (T*)h->pos[h->cur], (T*)h->vel[h->cur], (const T*)h->f_new[0],
                   (const T*)h->f_new[1], (const T*)h->f_new[2], (const T*)h->f_old[0],
-                  (const T*)h->f_old[1], (const T*)h->f_old[2], (T)c.flip_ratio, (T)c.dt,
+                  (const T*)h->f_old[1], (const T*)h->f_old[2], (T)c.flip_ratio, (T)dt,
                   (c.flags & FLIP_FLAG_ADVECT_PARTICLE_VEL) ? 1 : 0, st);
     timer_end(h, tq, st);
     if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;

@@ -145,6 +145,11 @@ template <typename V>
 void launch_gs_residual(int n_active, const int32_t* nbr, const uint8_t* diag, const V* b, const V* p,
                         unsigned long long* rmax, hipStream_t st);
 
+// FLIP_FLAG_ADAPTIVE_DT: max over particles of (u^2 + v^2) + w^2 (FP64) into
+// *out, as the bits of a non-negative double
+template <typename T>
+void launch_max_speed2(const T* vel, int64_t n, unsigned long long* out, hipStream_t st);
+
 // particle-to-grid for all faces, with gravity (gdt = g * dt per axis) and walls;
 // p2g_blocks: its workgroup count (one per 10^3 block of cells, P2G_NT threads)
 constexpr int P2G_NT = 192;

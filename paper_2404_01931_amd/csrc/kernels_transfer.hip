@@ -9,6 +9,8 @@
 //
 // Grid-to-particle (Sec. 3.1.8) with forward-Euler advection and the skin-width
 // clamp (Sec. 3.1.3): one workgroup per tile, face samples staged in LDS.
+#include <algorithm>
+
 #include "batch.h"
 #include "common.h"
 #include "device_util.h"
@@ -676,5 +678,38 @@ template void launch_g2p<float>(const Geo&, int64_t, const uint32_t*, const uint
 template void launch_g2p<double>(const Geo&, int64_t, const uint32_t*, const uint32_t*, double*, double*,
                                  const double*, const double*, const double*, const double*, const double*,
                                  const double*, double, double, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// CFL time step (FLIP_FLAG_ADAPTIVE_DT, Sec. 3.1.4): the largest squared
+// particle speed, (u^2 + v^2) + w^2 in FP64, folded into *out as the bits of
+// a non-negative double (*out cleared first); the host takes the square root.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_max_speed2(const T* __restrict__ vx, const T* __restrict__ vy,
+                                                    const T* __restrict__ vz, int64_t n,
+                                                    unsigned long long* __restrict__ out)
+{
+#pragma clang fp contract(off)
+    __shared__ double red[256 / WAVE];
+    double m = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const double u = vx[p], v = vy[p], w = vz[p];
+        m = fmax(m, (u * u + v * v) + w * w);
+    }
+    m = block_max<256>(m, red);
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+template <typename T>
+void launch_max_speed2(const T* vel, int64_t n, unsigned long long* out, hipStream_t st)
+{
+    launch_fill_u64((uint64_t*)out, 1, 0ull, st);
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_max_speed2<T>, dim3((unsigned)blocks), dim3(256), 0, st, vel, vel + n, vel + 2 * n, n, out);
+}
+template void launch_max_speed2<float>(const float*, int64_t, unsigned long long*, hipStream_t);
+template void launch_max_speed2<double>(const double*, int64_t, unsigned long long*, hipStream_t);
 
 }  // namespace flipmi
