@@ -25,6 +25,7 @@
  *   grid-to-particle   paper Sec. 3.1.8 (trilinear interpolation of the new
  *                      field and of the change, PIC/FLIP blend)
  *   advection / clamp  paper Sec. 3.1.3 (forward Euler, skin-width clamp)
+ *   CFL time step      paper Sec. 3.1.4 (dt <= alpha dx / fastest speed)
  *
  * Readings of points the paper leaves open are stated where they are used.
  */
