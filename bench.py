@@ -380,7 +380,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "f32+f64"}[sc.precision],
         "data": "synthetic",
-        "config": {"workload": f"{sc.name}: drop into pool, {sc.n}^3 MAC grid, {n} particles, "
+        "config": {"workload": f"{sc.name}: {inputs.describe(sc)}, {sc.n}^3 MAC grid, {n} particles, "
                                f"{sc.precision.upper()}, dt=1/{round(1 / sc.dt)}, FLIP {sc.flip_ratio}, "
                                f"{solver_label[main_run['solver']]} tol {sc.tol:g}"
                                + (f", FP64 refinement to {sc.ir_tol:g}" if sc.precision == "mixed" else ""),

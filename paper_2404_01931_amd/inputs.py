@@ -62,6 +62,15 @@ def dam(n: int, x_hi: float, y_hi: float, **kw) -> Scene:
     return Scene(regions=reg, n=n, **kw)
 
 
+def double_dam(n: int, width: float, height: float, **kw) -> Scene:
+    """Two water columns against opposite walls (the paper's double dam break,
+    Table 1; its geometry is not given: columns x < width and x >= 1 - width,
+    y < height, all z)."""
+    reg = (RegionSpec("box", hi=(width, height, INF)), RegionSpec("box", lo=(1.0 - width, -INF, -INF),
+                                                                  hi=(INF, height, INF)))
+    return Scene(regions=reg, n=n, **kw)
+
+
 def drop(n: int, **kw) -> Scene:
     reg = (RegionSpec("box", hi=(INF, 0.3, INF)),
            RegionSpec("sphere", center=(0.5, 0.7, 0.5), radius=0.15, vel=(0.0, -1.0, 0.0)))
@@ -83,7 +92,19 @@ SCENES = {
                    flip_ratio=0.97, tol=1e-6, steps=30),
     "drop128": drop(128, name="drop128", seed=3, precision="fp32", dt=1 / 960,
                     flip_ratio=0.97, tol=1e-6, steps=30),
+    "ddam32": double_dam(32, 0.25, 0.5, name="ddam32", seed=6, precision="fp64", dt=1 / 240,
+                         flip_ratio=0.95, tol=1e-6, steps=20),
+    "ddam128": double_dam(128, 0.25, 0.5, name="ddam128", seed=6, precision="fp32", dt=1 / 480,
+                          flip_ratio=0.95, tol=1e-6, steps=50),
 }
+
+
+def describe(sc: Scene) -> str:
+    """Short description of a scene's layout."""
+    kinds = [r.kind for r in sc.regions]
+    if "sphere" in kinds:
+        return "drop into pool"
+    return "double dam break" if len(kinds) == 2 else "dam break"
 
 
 def scene(name: str, **overrides) -> Scene:

@@ -46,10 +46,12 @@ def make_case(name):
         return _ragged_case(flip.FLIP_FP64)
     if name == "drop64_fp32":
         return flip.scene_config(inputs.scene("drop64"))
+    if name == "ddam32_fp64":
+        return flip.scene_config(inputs.scene("ddam32"))
     raise KeyError(name)
 
 
-CASES = ["dam32_fp64", "dam32_fp32", "ragged_fp32", "ragged_fp64", "drop64_fp32"]
+CASES = ["dam32_fp64", "dam32_fp32", "ragged_fp32", "ragged_fp64", "drop64_fp32", "ddam32_fp64"]
 
 
 def _tol(sim):
