@@ -71,7 +71,7 @@ def test_seeded_or_uploaded_state_matches_oracle(orc, case):
     assert np.array_equal(ids, np.arange(pos.shape[1], dtype=np.uint32))
     if cfg.pos0:
         return
-    sc = {"dam32_fp64": "dam32", "dam32_fp32": "dam32", "drop64_fp32": "drop64"}[case]
+    sc = {"dam32_fp64": "dam32", "dam32_fp32": "dam32", "drop64_fp32": "drop64", "ddam32_fp64": "ddam32"}[case]
     s = inputs.scene(sc)
     from tests.scenes_util import oracle_grid, oracle_regions
 
