@@ -145,6 +145,11 @@ __device__ inline V restrict_weight(int k, int c, int n)
     return ((k == 1 && c == 0) || (k == 2 && c == n - 1)) ? V(1) : V(0.75);
 }
 
+// threads per workgroup of the batched dense-level kernels (the scenes of a
+// serving batch are 32^3 to 96^3, all their dense levels small; on the
+// serving stream 512 measured 1% above 256 and 1024)
+constexpr int MG_BATCH_NT = 512;
+
 // A box of NX x NY x NZ cells walked by NT threads a column at a time: a
 // thread keeps one (x, y) column (its index arithmetic done once) and steps
 // through z, P threads sharing a column when NT holds several copies of the
@@ -279,12 +284,12 @@ __global__ __launch_bounds__(NT) void k_mg_down(MgLevel f, MgLevel c, const PcgS
 }
 
 template <typename V>
-__global__ __launch_bounds__(256) void kb_mg_down(const MgPairArgs* __restrict__ tab,
+__global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_down(const MgPairArgs* __restrict__ tab,
                                                   const uint32_t* __restrict__ first, int ns)
 {
     Blk b;
     const MgPairArgs& a = batch_args(tab, first, ns, b);
-    mg_down_body<V, 256>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    mg_down_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
 }
 
 // ---- bottom: the coarsest level (at most 8^3 cells), one workgroup -------------
@@ -472,12 +477,12 @@ __global__ __launch_bounds__(NT) void k_mg_up(MgLevel f, MgLevel c, const PcgSta
 }
 
 template <typename V>
-__global__ __launch_bounds__(256) void kb_mg_up(const MgPairArgs* __restrict__ tab,
+__global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_up(const MgPairArgs* __restrict__ tab,
                                                 const uint32_t* __restrict__ first, int ns)
 {
     Blk b;
     const MgPairArgs& a = batch_args(tab, first, ns, b);
-    mg_up_body<V, 256>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    mg_up_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
 }
 
 // ---- launchers -----------------------------------------------------------------
@@ -558,11 +563,11 @@ void launch_b_mg_level(int kind, const BatchLaunch& L, hipStream_t st)
     if (L.blocks == 0) return;
     const MgPairArgs* a = (const MgPairArgs*)L.args;
     if (kind == MG_B_DOWN)
-        hipLaunchKernelGGL(kb_mg_down<V>, dim3(L.blocks), dim3(256), 0, st, a, L.first, L.ns);
+        hipLaunchKernelGGL(kb_mg_down<V>, dim3(L.blocks), dim3(MG_BATCH_NT), 0, st, a, L.first, L.ns);
     else if (kind == MG_B_BOTTOM)
         hipLaunchKernelGGL(kb_mg_bottom<V>, dim3(L.blocks), dim3(512), 0, st, a, L.first, L.ns);
     else
-        hipLaunchKernelGGL(kb_mg_up<V>, dim3(L.blocks), dim3(256), 0, st, a, L.first, L.ns);
+        hipLaunchKernelGGL(kb_mg_up<V>, dim3(L.blocks), dim3(MG_BATCH_NT), 0, st, a, L.first, L.ns);
 }
 template void launch_b_mg_level<float>(int, const BatchLaunch&, hipStream_t);
 template void launch_b_mg_level<double>(int, const BatchLaunch&, hipStream_t);
