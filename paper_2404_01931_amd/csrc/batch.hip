@@ -330,8 +330,8 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
                 bu[s] = (uint32_t)mg_blocks(MG_B_UP, f, c);
             }
             S.mg_types[l] = add_site(t, a, bt, 256);
-            S.mg_down[l] = add_site(t, a, bd, 512);
-            S.mg_up[l] = add_site(t, a, bu, 512);
+            S.mg_down[l] = add_site(t, a, bd, MG_BATCH_NT);
+            S.mg_up[l] = add_site(t, a, bu, MG_BATCH_NT);
         }
     }
     {

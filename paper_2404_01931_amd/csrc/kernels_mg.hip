@@ -145,11 +145,6 @@ __device__ inline V restrict_weight(int k, int c, int n)
     return ((k == 1 && c == 0) || (k == 2 && c == n - 1)) ? V(1) : V(0.75);
 }
 
-// threads per workgroup of the batched dense-level kernels (the scenes of a
-// serving batch are 32^3 to 96^3, all their dense levels small; on the
-// serving stream 512 measured 1% above 256 and 1024)
-constexpr int MG_BATCH_NT = 512;
-
 // A box of NX x NY x NZ cells walked by NT threads a column at a time: a
 // thread keeps one (x, y) column (its index arithmetic done once) and steps
 // through z, P threads sharing a column when NT holds several copies of the
