@@ -182,7 +182,8 @@ __host__ __device__ inline int64_t mg_down_blocks(const MgLevel& c)
 
 // NT threads per workgroup: 512, or 1024 on the small levels, where a
 // launch has few workgroups and the time is the chain of each thread's
-// serial work (the values are the same either way; batched launches use 256)
+// serial work (the values are the same either way; batched launches use
+// MG_BATCH_NT)
 template <typename V, int NT>
 __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const MgLevel& c,
                                              const PcgState* __restrict__ ps)
