@@ -86,6 +86,7 @@ def _load():
             "orc_interp": (dbl, [G, i32, P, dbl, dbl, dbl]),
             "orc_g2p_advect": (None, [G, i64, P, P, P, P, P, P, P, P, dbl, dbl, ctypes.c_uint]),
             "orc_cfl_dt": (dbl, [i64, P, P, P, dbl, dbl, dbl]),
+            "orc_reseed": (i64, [G, i32, u64, i64, i32, P, P, P, P, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -307,6 +308,26 @@ def cfl_dt(vel, dx: float, alpha: float, dt_max: float) -> float:
                                     float(dt_max)))
 
 
+def reseed(grid: Grid, sub: int, seed_value: int, step_index: int, round_fp32: bool, count, start, vel_sorted):
+    """Reseeding (Sec. 3.1.2): the particles added to fluid cells holding fewer
+    than sub^3 binned particles, in cell order: (pos 3 x m, vel 3 x m, cell m)."""
+    count = np.ascontiguousarray(count, dtype=np.uint32)
+    start = np.ascontiguousarray(start, dtype=np.uint32)
+    vel = _f64(vel_sorted)
+    lib = _load()
+    null = ctypes.c_void_p(0)
+    args = (grid.c(), int(sub), int(seed_value) & (2**64 - 1), int(step_index), int(bool(round_fp32)),
+            _ptr(count), _ptr(start), _ptr(vel[0]), _ptr(vel[1]), _ptr(vel[2]))
+    m = lib.orc_reseed(*args, null, null, null, null, null, null, null)
+    pos_new = np.zeros((3, m))
+    vel_new = np.zeros((3, m))
+    cell_new = np.zeros(m, dtype=np.uint32)
+    if m:
+        lib.orc_reseed(*args, _ptr(pos_new[0]), _ptr(pos_new[1]), _ptr(pos_new[2]), _ptr(vel_new[0]),
+                       _ptr(vel_new[1]), _ptr(vel_new[2]), _ptr(cell_new))
+    return pos_new, vel_new, cell_new
+
+
 @dataclass
 class Params:
     grid: Grid
@@ -319,6 +340,12 @@ class Params:
     precond: int = PRECOND_MIC0
     no_projection: bool = False
     advect_particle_vel: bool = False
+    # reseeding (Sec. 3.1.2): sub > 0 turns it on; seed, the number of steps
+    # done before this one, and whether positions are FP32 values
+    reseed_sub: int = 0
+    reseed_seed: int = 0
+    reseed_step: int = 0
+    reseed_fp32: bool = False
 
     def iters_cap(self):
         g = self.grid
@@ -357,6 +384,19 @@ def step(prm: Params, pos, vel, ids=None) -> StepResult:
     vel_s = np.ascontiguousarray(vel[:, perm])
     ids_s = np.ascontiguousarray(np.asarray(ids)[perm])
     fluid = fluid_flags(g, count)
+    n_new = 0
+    if prm.reseed_sub > 0:
+        # new particles follow the existing ones of their cell; ids continue from n
+        pos_r, vel_r, cell_r = reseed(g, prm.reseed_sub, prm.reseed_seed, prm.reseed_step, prm.reseed_fp32,
+                                      count, start, vel_s)
+        n_new = pos_r.shape[1]
+        if n_new:
+            order = np.argsort(np.concatenate([key[perm], cell_r]), kind="stable")
+            pos_s = np.ascontiguousarray(np.concatenate([pos_s, pos_r], axis=1)[:, order])
+            vel_s = np.ascontiguousarray(np.concatenate([vel_s, vel_r], axis=1)[:, order])
+            ids_s = np.ascontiguousarray(np.concatenate([ids_s, n + np.arange(n_new, dtype=np.uint32)])[order])
+            count = count + np.bincount(cell_r, minlength=g.ncells).astype(np.uint32)
+            start = (np.cumsum(count, dtype=np.uint64) - count).astype(np.uint32)
     u_old = p2g(g, pos_s, vel_s)
     u_star = forces_walls(g, u_old, prm.gravity, prm.dt)
     b = rhs(g, fluid, u_star, prm.density, prm.dt)
@@ -369,4 +409,4 @@ def step(prm: Params, pos, vel, ids=None) -> StepResult:
     flags = ADVECT_PARTICLE_VEL if prm.advect_particle_vel else 0
     pos_n, vel_n = g2p_advect(g, pos_s, vel_s, u_new, u_old, prm.flip_ratio, prm.dt, flags)
     return StepResult(key, count, start, perm, fluid, pos_s, vel_s, ids_s, u_old, u_star, b, sol,
-                      u_new, pos_n, vel_n)
+                      u_new, pos_n, vel_n, {"n_reseeded": n_new})

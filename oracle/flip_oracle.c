@@ -26,6 +26,8 @@
  *                      field and of the change, PIC/FLIP blend)
  *   advection / clamp  paper Sec. 3.1.3 (forward Euler, skin-width clamp)
  *   CFL time step      paper Sec. 3.1.4 (dt <= alpha dx / fastest speed)
+ *   reseeding          paper Sec. 3.1.2, closing paragraph (refill sparse
+ *                      fluid cells up to the seeding density)
  *
  * Readings of points the paper leaves open are stated where they are used.
  */
@@ -676,4 +678,84 @@ double orc_cfl_dt(int64_t n, const double* vx, const double* vy, const double* v
     if (umax == 0.0) return dt_max;
     const double dt = alpha * dx / umax;
     return dt < dt_max ? dt : dt_max;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reseeding (paper Sec. 3.1.2, closing paragraph): a fluid cell holding     */
+/* fewer particles than the seeding density asks for (sub^3 per cell) is     */
+/* refilled up to that number. The paper gives no further detail; readings:  */
+/*  - a cell with k particles, 0 < k < sub^3, gets sub^3 - k new particles,  */
+/*    one in each of its jitter subcells k .. sub^3 - 1 (x-fastest order),   */
+/*    at the same jittered point rule as the initial seeding;                */
+/*  - the jitter is element 3 (sub^3 (C (step + 1) + cell) + subcell) + axis */
+/*    of the seed's SplitMix64 sequence (C cells), so no step reuses the     */
+/*    numbers of the initial seeding or of another step;                     */
+/*  - a point that rounding (FP64, or FP32 when round_fp32) puts outside its */
+/*    cell, by the exact floor of the binning, is moved one representable    */
+/*    value at a time back into the cell;                                    */
+/*  - its velocity is the mean of the k particles already in the cell        */
+/*    (summed in FP64 in their binned order, then divided by k);             */
+/*  - cells with no particle (air) and cells at or above the density are     */
+/*    left alone.                                                            */
+/* count/start describe the binned particles, whose velocities vx, vy, vz    */
+/* are given in binned order. With px_new == NULL only the number of new     */
+/* particles is returned. New particles come out in cell order.              */
+/* ------------------------------------------------------------------------ */
+
+static double move_into_cell(double x, int i, double dx, int n, int round_fp32)
+{
+    if (round_fp32) {
+        float f = (float)x;
+        while (exact_floor_div((double)f, dx, n) < i) f = nextafterf(f, INFINITY);
+        while (exact_floor_div((double)f, dx, n) > i) f = nextafterf(f, -INFINITY);
+        return (double)f;
+    }
+    while (exact_floor_div(x, dx, n) < i) x = nextafter(x, INFINITY);
+    while (exact_floor_div(x, dx, n) > i) x = nextafter(x, -INFINITY);
+    return x;
+}
+
+int64_t orc_reseed(const orc_grid* g, int sub, uint64_t seed, int64_t step, int round_fp32,
+                   const uint32_t* count, const uint32_t* start, const double* vx, const double* vy,
+                   const double* vz, double* px_new, double* py_new, double* pz_new, double* vx_new,
+                   double* vy_new, double* vz_new, uint32_t* cell_new)
+{
+    const int64_t C = n_cells(g);
+    const int64_t per_cell = (int64_t)sub * sub * sub;
+    int64_t m = 0;
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                const int64_t c = cell_index(g, i, j, k);
+                const int64_t have = count[c];
+                if (have == 0 || have >= per_cell) continue;
+                double mean[3] = {0.0, 0.0, 0.0};
+                if (px_new) {
+                    const double* v[3] = {vx, vy, vz};
+                    for (int a = 0; a < 3; ++a) {
+                        double sum = 0.0;
+                        for (int64_t q = 0; q < have; ++q) sum += v[a][start[c] + q];
+                        mean[a] = sum / (double)have;
+                        if (round_fp32) mean[a] = (double)(float)mean[a];
+                    }
+                }
+                for (int64_t s = have; s < per_cell; ++s) {
+                    if (px_new) {
+                        const int sx = (int)(s % sub), sy = (int)((s / sub) % sub), sz = (int)(s / ((int64_t)sub * sub));
+                        const uint64_t ctr = 3u * (uint64_t)(per_cell * (C * (step + 1) + c) + s);
+                        const double x = ((sx + orc_uniform01(seed, ctr + 0)) / sub + i) * g->dx;
+                        const double y = ((sy + orc_uniform01(seed, ctr + 1)) / sub + j) * g->dx;
+                        const double z = ((sz + orc_uniform01(seed, ctr + 2)) / sub + k) * g->dx;
+                        px_new[m] = move_into_cell(x, i, g->dx, g->nx, round_fp32);
+                        py_new[m] = move_into_cell(y, j, g->dx, g->ny, round_fp32);
+                        pz_new[m] = move_into_cell(z, k, g->dx, g->nz, round_fp32);
+                        vx_new[m] = mean[0];
+                        vy_new[m] = mean[1];
+                        vz_new[m] = mean[2];
+                        cell_new[m] = (uint32_t)c;
+                    }
+                    ++m;
+                }
+            }
+    return m;
 }

@@ -72,6 +72,14 @@ void orc_g2p_advect(const orc_grid* g, int64_t n, double* px, double* py, double
    dt = min(dt_max, alpha dx / |u|max) (dt_max when every particle is at rest) */
 double orc_cfl_dt(int64_t n, const double* vx, const double* vy, const double* vz, double dx, double alpha,
                   double dt_max);
+/* Reseeding (Sec. 3.1.2): new particles for every fluid cell holding fewer
+   than sub^3 binned particles (count/start of the binning, velocities in
+   binned order); returns their number, written in cell order when px_new is
+   not NULL. Readings at the definition. */
+int64_t orc_reseed(const orc_grid* g, int sub, uint64_t seed, int64_t step, int round_fp32,
+                   const uint32_t* count, const uint32_t* start, const double* vx, const double* vy,
+                   const double* vz, double* px_new, double* py_new, double* pz_new, double* vx_new,
+                   double* vy_new, double* vz_new, uint32_t* cell_new);
 
 #ifdef __cplusplus
 }
