@@ -96,12 +96,27 @@ enum {
                                           FLIP_FP32 and FLIP_FP64 only, not with
                                           FLIP_FLAG_MULTIGRID, not in a batch
                                           (FLIP_E_INVALID)                                    */
-    FLIP_FLAG_ADAPTIVE_DT = 64u        /* CFL time step (Sec. 3.1.4): each step takes
+    FLIP_FLAG_ADAPTIVE_DT = 64u,       /* CFL time step (Sec. 3.1.4): each step takes
                                           dt = min(flip_config.dt, cfl * dx / |u|max), |u|max
                                           the speed of the fastest particle at the step's
                                           start (one 8-byte readback per step); the step's dt
                                           is reported in flip_step_stats.dt. Needs cfl > 0;
                                           not in a batch (FLIP_E_INVALID)                     */
+    FLIP_FLAG_RESEED = 128u            /* particle reseeding (Sec. 3.1.2): after binning, each
+                                          fluid cell holding k < sub^3 particles (sub =
+                                          subcells_per_axis, which must be in [1, 16] also
+                                          when pos0 is given) gets sub^3 - k new ones, one in
+                                          each of its jitter subcells k .. sub^3 - 1 (x-fastest
+                                          order), at the jittered point of the subcell moved
+                                          into the cell if rounding put it outside; velocity:
+                                          the mean of the cell's k particles; ids continue
+                                          from the current count in cell order. Jitter:
+                                          SplitMix64 of `seed`, element 3 * (sub^3 * (ncells *
+                                          (step + 1) + cell) + subcell) + axis, step the number
+                                          of steps done before. One 8-byte readback per step.
+                                          A step that would exceed particle_capacity returns
+                                          FLIP_E_WORKSPACE before moving any particle. Not in
+                                          a batch (FLIP_E_INVALID)                            */
 };
 
 typedef struct {
@@ -130,6 +145,8 @@ typedef struct {
     const double* vel0;        /* host, 3 * n_particles doubles, SoA                       */
     double cfl;                /* FLIP_FLAG_ADAPTIVE_DT: the CFL number alpha (the paper
                                   uses 3); ignored otherwise                               */
+    int64_t particle_capacity; /* particles the workspace holds (FLIP_FLAG_RESEED adds
+                                  particles); <= the initial count means that count        */
 } flip_config;
 
 /* fields for flip_readback / flip_field_bytes */
@@ -185,6 +202,7 @@ typedef struct {
     double kernel_ms[FLIP_KERNEL_COUNT];      /* summed durations of timed launches        */
     int64_t kernel_launches[FLIP_KERNEL_COUNT];/* number of timed launches                 */
     double dt;                     /* last step: the time step it took                     */
+    int64_t n_reseeded;            /* last step: particles FLIP_FLAG_RESEED added          */
 } flip_step_stats;
 
 /* Device workspace needed for cfg (pure; used for HBM admission). */
@@ -232,7 +250,8 @@ void flip_destroy(flip_handle* h);
  * Requirements: 1 <= nscenes <= FLIP_BATCH_MAX_SCENES initialised handles,
  * all FLIP_FP32 or all FLIP_FP64 (FLIP_MIXED is not batched), all with or
  * all without FLIP_FLAG_MULTIGRID, none with FLIP_FLAG_NO_PROJECTION,
- * FLIP_FLAG_KERNEL_TIMING or FLIP_FLAG_RED_BLACK_GS, no handle twice. The handles stay owned by the
+ * FLIP_FLAG_KERNEL_TIMING, FLIP_FLAG_RED_BLACK_GS, FLIP_FLAG_ADAPTIVE_DT or
+ * FLIP_FLAG_RESEED, no handle twice. The handles stay owned by the
  * caller, must outlive the batch and must not be stepped by other calls while
  * the batch steps.
  *

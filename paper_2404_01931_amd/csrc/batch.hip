@@ -369,7 +369,8 @@ flip_status check_handles(flip_handle* const* handles, int nscenes, int* prec, b
         if (h->prec != FLIP_FP32 && h->prec != FLIP_FP64) return FLIP_E_INVALID;
         if (h->prec != handles[0]->prec) return FLIP_E_INVALID;
         if (h->cfg.flags &
-            (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING | FLIP_FLAG_RED_BLACK_GS | FLIP_FLAG_ADAPTIVE_DT))
+            (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING | FLIP_FLAG_RED_BLACK_GS | FLIP_FLAG_ADAPTIVE_DT |
+             FLIP_FLAG_RESEED))
             return FLIP_E_INVALID;
         // the preconditioner is the same for every scene of a batch
         if ((h->cfg.flags & FLIP_FLAG_MULTIGRID) != (handles[0]->cfg.flags & FLIP_FLAG_MULTIGRID))

@@ -147,6 +147,9 @@ flip_status validate(const flip_config* c)
     if ((c->flags & FLIP_FLAG_RED_BLACK_GS) && (c->precision == FLIP_MIXED || (c->flags & FLIP_FLAG_MULTIGRID)))
         return FLIP_E_INVALID;
     if ((c->flags & FLIP_FLAG_ADAPTIVE_DT) && (!(c->cfl > 0.0) || !std::isfinite(c->cfl))) return FLIP_E_INVALID;
+    if ((c->flags & FLIP_FLAG_RESEED) && (c->subcells_per_axis < 1 || c->subcells_per_axis > 16))
+        return FLIP_E_INVALID;
+    if (c->particle_capacity >= ((int64_t)1 << 31)) return FLIP_E_INVALID;
     if (c->pos0) {
         if (c->n_particles < 0 || c->n_particles >= ((int64_t)1 << 31) || !c->vel0) return FLIP_E_INVALID;
     } else {
@@ -190,6 +193,7 @@ Sizes make_sizes(const flip_config* c, int64_t n)
 {
     Sizes s;
     s.n = n;
+    s.pcap = std::max<int64_t>(n, c->particle_capacity);
     s.C = (int64_t)c->nx * c->ny * c->nz;
     Geo g = make_geo(c);
     s.T = tiles_of(g);
@@ -216,13 +220,13 @@ void carve(flip_handle* h, Carver& cv)
     const Sizes& s = h->sz;
     const size_t rb = s.rb;
     for (int q = 0; q < 2; ++q) {
-        h->pos[q] = cv.take<void>((3 * s.n + PARTICLE_PAD) * rb);
-        h->vel[q] = cv.take<void>((3 * s.n + PARTICLE_PAD) * rb);
-        h->id[q] = cv.take<uint32_t>(4 * s.n);
+        h->pos[q] = cv.take<void>((3 * s.pcap + PARTICLE_PAD) * rb);
+        h->vel[q] = cv.take<void>((3 * s.pcap + PARTICLE_PAD) * rb);
+        h->id[q] = cv.take<uint32_t>(4 * s.pcap);
     }
-    h->key = cv.take<uint32_t>(4 * s.n);
-    h->rank = cv.take<uint32_t>(4 * s.n);
-    h->perm = cv.take<uint32_t>(4 * s.n);
+    h->key = cv.take<uint32_t>(4 * s.pcap);
+    h->rank = cv.take<uint32_t>(4 * s.pcap);
+    h->perm = cv.take<uint32_t>(4 * s.pcap);
     h->count = cv.take<uint32_t>(4 * s.C);
     h->start = cv.take<uint32_t>(4 * s.C);
     h->scan_tmp = cv.take<uint32_t>(4 * scan_tmp_words(s.C > s.T ? s.C : s.T));
@@ -273,6 +277,7 @@ void carve(flip_handle* h, Carver& cv)
     h->pslots = cv.take<double>(PCG_SLOT_SETS * sizeof(double) * solver_groups(s.T));
     h->ps = cv.take<PcgState>(PCG_STATE_BYTES + SYNC_BYTES);
     h->gs_rmax = cv.take<unsigned long long>(8);
+    h->d_reseeded = cv.take<uint32_t>(4);
     h->staging = cv.take<void>(8 * s.C);
 }
 
@@ -448,7 +453,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
 {
     const Geo& g = h->geo;
     const Sizes& s = h->sz;
-    const int64_t n = s.n;
+    int64_t n = s.n;
     const int nxt = h->cur ^ 1;
     const flip_config& c = h->cfg;
 
@@ -475,11 +480,36 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     tq = timer_begin(h, FLIP_KERNEL_BIN_SCATTER, st);
     launch_bin_scatter(h->key, h->rank, h->start, n, h->perm, st);
     timer_end(h, tq, st);
-    tq = timer_begin(h, FLIP_KERNEL_BIN_GATHER, st);
-    launch_bin_gather<T>(h->perm, h->key, h->start, h->count, n, (const T*)h->pos[h->cur],
-                         (const T*)h->vel[h->cur], h->id[h->cur], (T*)h->pos[nxt], (T*)h->vel[nxt],
-                         h->id[nxt], st);
-    timer_end(h, tq, st);
+    h->stats.n_reseeded = 0;
+    if (c.flags & FLIP_FLAG_RESEED) {
+        // Sec. 3.1.2: refill sparse fluid cells. The new total sets the
+        // particle arrays' stride, so it is read back before the move.
+        uint32_t* add = (uint32_t*)h->staging;
+        uint32_t* off = add + s.C;
+        const int sub = c.subcells_per_axis;
+        tq = timer_begin(h, FLIP_KERNEL_BIN_GATHER, st);
+        launch_reseed_plan(h->count, s.C, (uint32_t)(sub * sub * sub), add, st);
+        launch_exclusive_scan_u32(add, off, s.C, h->scan_tmp, st);
+        launch_reseed_total(add, off, s.C, h->d_reseeded, st);
+        HIP_TRY(hipMemcpyAsync(h->h_reseeded, h->d_reseeded, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const int64_t added = *h->h_reseeded;
+        if (n + added > s.pcap) return FLIP_E_WORKSPACE;  // nothing moved yet
+        launch_reseed_move<T>(g, sub, c.seed, (uint64_t)h->stats.steps, h->perm, h->key, h->start, h->count,
+                              add, off, n, n + added, (const T*)h->pos[h->cur], (const T*)h->vel[h->cur],
+                              h->id[h->cur], (T*)h->pos[nxt], (T*)h->vel[nxt], h->id[nxt], st);
+        timer_end(h, tq, st);
+        n += added;
+        h->sz.n = n;
+        h->stats.n_particles = n;
+        h->stats.n_reseeded = added;
+    } else {
+        tq = timer_begin(h, FLIP_KERNEL_BIN_GATHER, st);
+        launch_bin_gather<T>(h->perm, h->key, h->start, h->count, n, (const T*)h->pos[h->cur],
+                             (const T*)h->vel[h->cur], h->id[h->cur], (T*)h->pos[nxt], (T*)h->vel[nxt],
+                             h->id[nxt], st);
+        timer_end(h, tq, st);
+    }
     h->cur = nxt;
     tq = timer_begin(h, FLIP_KERNEL_TILES, st);
     launch_tiles(g, h->count, h->tile_flag, h->tile_excl, h->tile_slot, h->tile_list, h->tile_nbr,
@@ -755,7 +785,8 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
     launch_fill_bytes_zero(h->diag, s.cap, st);
     launch_fill_bytes_zero(h->ps, PCG_STATE_BYTES + SYNC_BYTES, st);
     launch_fill_u64((uint64_t*)h->partials, 3 * h->groups, SLOT_EMPTY_BITS, st);
-    if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_reseeded, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
         flip_destroy(h);
         return FLIP_E_HIP;
     }
@@ -886,6 +917,7 @@ void flip_destroy(flip_handle* h)
     for (auto& e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_ps) (void)hipHostFree(h->h_ps);
+    if (h->h_reseeded) (void)hipHostFree(h->h_reseeded);
     delete h;
 }
 

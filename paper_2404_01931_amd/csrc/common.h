@@ -129,6 +129,18 @@ void launch_bin_gather(const uint32_t* perm, const uint32_t* key, const uint32_t
                        const uint32_t* id_in, T* pos_out, T* vel_out, uint32_t* id_out,
                        hipStream_t st);
 
+// reseeding (Sec. 3.1.2): add[c] = new particles of cell c (target - count
+// for 0 < count < target); total = off[C-1] + add[C-1] with off the exclusive
+// scan of add; move = the spread gather of the binned particles into n_out
+// slots, then the new particles, and count/start of the refilled cells
+void launch_reseed_plan(const uint32_t* count, int64_t C, uint32_t target, uint32_t* add, hipStream_t st);
+void launch_reseed_total(const uint32_t* add, const uint32_t* off, int64_t C, uint32_t* total, hipStream_t st);
+template <typename T>
+void launch_reseed_move(const Geo& g, int sub, uint64_t seed, uint64_t step, const uint32_t* perm,
+                        const uint32_t* key, uint32_t* start, uint32_t* count, const uint32_t* add,
+                        const uint32_t* off, int64_t n, int64_t n_out, const T* pos_in, const T* vel_in,
+                        const uint32_t* id_in, T* pos_out, T* vel_out, uint32_t* id_out, hipStream_t st);
+
 // tiles: flags -> scan -> compaction -> neighbour table; writes the active
 // count to *d_nactive
 void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint32_t* tile_excl,

@@ -11,6 +11,7 @@ namespace flipmi {
 
 struct Sizes {
     int64_t n = 0, C = 0, T = 0, cap = 0, F[3] = {0, 0, 0};
+    int64_t pcap = 0;  // particle slots of the workspace (>= n; reseeding adds particles)
     size_t rb = 4;  // bytes of the real type
 };
 
@@ -53,6 +54,7 @@ struct flip_handle {
     double* partials = nullptr;  // reduction slots of the start kernels (EMPTY when idle)
     double* pslots = nullptr;    // partial sums of the iteration kernels
     unsigned long long* gs_rmax = nullptr;  // FLIP_FLAG_RED_BLACK_GS: residual max (double bits)
+    uint32_t* d_reseeded = nullptr;         // FLIP_FLAG_RESEED: new particles of the step
     flipmi::PcgState* ps = nullptr;
     void* staging = nullptr;
     // host side
@@ -61,6 +63,7 @@ struct flip_handle {
     int na = -1;     // active tiles of the current solve, once read back
     int prev_iters = 0;
     flipmi::PcgState* h_ps = nullptr;
+    uint32_t* h_reseeded = nullptr;  // pinned copy of d_reseeded
     hipStream_t last_stream = nullptr;
     flip_step_stats stats{};
     // kernel timing

@@ -402,12 +402,15 @@ void launch_bin_scatter(const uint32_t* key, const uint32_t* rank, const uint32_
 // Slot s of the provisional order holds particle p; p's final slot is the
 // start of its cell plus the number of particles of that cell with a smaller
 // original index. The particle's state moves there (double buffer, Sec. 3.2.2).
-template <typename T>
+// SPREAD (reseeding): the output has n_out >= n slots and cell c's particles
+// move up by spread[c], the new particles of the cells before it.
+template <typename T, bool SPREAD = false>
 __device__ __forceinline__ void bin_gather_body(
     Blk b, const uint32_t* __restrict__ perm, const uint32_t* __restrict__ key,
     const uint32_t* __restrict__ start, const uint32_t* __restrict__ count, int64_t n,
     const T* __restrict__ pos_in, const T* __restrict__ vel_in, const uint32_t* __restrict__ id_in,
-    T* __restrict__ pos_out, T* __restrict__ vel_out, uint32_t* __restrict__ id_out)
+    T* __restrict__ pos_out, T* __restrict__ vel_out, uint32_t* __restrict__ id_out,
+    const uint32_t* __restrict__ spread = nullptr, int64_t n_out = 0)
 {
     const int64_t s = (int64_t)b.id * 256 + threadIdx.x;
     if (s >= n) return;
@@ -426,11 +429,12 @@ __device__ __forceinline__ void bin_gather_body(
 #pragma unroll
         for (int k = 0; k < 4; ++k) r += (q + k < end && v[k] < p) ? 1u : 0u;
     }
-    const int64_t d = (int64_t)st + r;
+    const int64_t d = (int64_t)st + r + (SPREAD ? spread[c] : 0u);
+    const int64_t m = SPREAD ? n_out : n;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        pos_out[a * n + d] = pos_in[a * n + p];
-        vel_out[a * n + d] = vel_in[a * n + p];
+        pos_out[a * m + d] = pos_in[a * n + p];
+        vel_out[a * m + d] = vel_in[a * n + p];
     }
     id_out[d] = id_in[p];
 }
@@ -483,6 +487,146 @@ template void launch_bin_gather<float>(const uint32_t*, const uint32_t*, const u
 template void launch_bin_gather<double>(const uint32_t*, const uint32_t*, const uint32_t*,
                                         const uint32_t*, int64_t, const double*, const double*,
                                         const uint32_t*, double*, double*, uint32_t*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// reseeding (paper Sec. 3.1.2, closing paragraph): a fluid cell holding k
+// particles, 0 < k < sub^3, is refilled to sub^3. Plan: the number of new
+// particles per cell; its exclusive scan spreads the binned particles apart
+// (the gather above) and numbers the new ones; fill: the new particles, in
+// jitter subcells k .. sub^3 - 1, with the mean velocity of the cell's k.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_reseed_plan(const uint32_t* __restrict__ count, int64_t C,
+                                                     uint32_t target, uint32_t* __restrict__ add)
+{
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= C) return;
+    const uint32_t k = count[c];
+    add[c] = (k > 0 && k < target) ? target - k : 0u;
+}
+
+void launch_reseed_plan(const uint32_t* count, int64_t C, uint32_t target, uint32_t* add, hipStream_t st)
+{
+    if (C <= 0) return;
+    hipLaunchKernelGGL(k_reseed_plan, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st, count, C, target,
+                       add);
+}
+
+// the last prefix plus the last count: the number of new particles
+__global__ void k_reseed_total(const uint32_t* __restrict__ add, const uint32_t* __restrict__ off, int64_t C,
+                               uint32_t* __restrict__ total)
+{
+    if (threadIdx.x == 0) total[0] = C > 0 ? off[C - 1] + add[C - 1] : 0u;
+}
+
+void launch_reseed_total(const uint32_t* add, const uint32_t* off, int64_t C, uint32_t* total, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reseed_total, dim3(1), dim3(64), 0, st, add, off, C, total);
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): element `index` of the sequence of
+// `seed`, top 53 bits as a double in [0, 1)
+__device__ inline double splitmix_unit(uint64_t seed, uint64_t index)
+{
+    uint64_t z = seed + (index + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (double)(z >> 11) * 0x1.0p-53;
+}
+
+// x rounded to T, then moved one representable value at a time until the
+// binning's exact floor puts it in cell i (rounding can land it on a face)
+template <typename T>
+__device__ inline T into_cell(double x, int i, double dx, double inv_dx, int n)
+{
+    T v = (T)x;
+    for (int it = 0; it < 8 && exact_cell_floor((double)v, dx, inv_dx, n) < i; ++it)
+        v = nextafter(v, (T)INFINITY);
+    for (int it = 0; it < 8 && exact_cell_floor((double)v, dx, inv_dx, n) > i; ++it)
+        v = nextafter(v, (T)-INFINITY);
+    return v;
+}
+
+// One thread per cell. count/start become those of the refilled cells; the
+// cell's binned particles already sit at start + off (the spread gather).
+template <typename T>
+__global__ __launch_bounds__(256) void k_reseed_fill(Geo g, int sub, uint64_t seed, uint64_t step,
+                                                     uint32_t* __restrict__ count, uint32_t* __restrict__ start,
+                                                     const uint32_t* __restrict__ add,
+                                                     const uint32_t* __restrict__ off, uint32_t n_old,
+                                                     int64_t n, T* __restrict__ pos, T* __restrict__ vel,
+                                                     uint32_t* __restrict__ id)
+{
+#pragma clang fp contract(off)
+    const int64_t C = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= C) return;
+    const uint32_t k = count[c], a = add[c], o = off[c];
+    const uint32_t s0 = start[c] + o;
+    start[c] = s0;
+    count[c] = k + a;
+    if (a == 0) return;
+    double mean[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        double sum = 0.0;
+        for (uint32_t q = 0; q < k; ++q) sum += (double)vel[ax * n + s0 + q];
+        mean[ax] = sum / (double)k;
+    }
+    const int i = (int)(c % g.nx), j = (int)((c / g.nx) % g.ny), kk = (int)(c / ((int64_t)g.nx * g.ny));
+    const uint64_t per = (uint64_t)sub * sub * sub;
+    for (uint32_t t = 0; t < a; ++t) {
+        const uint32_t s = k + t;
+        const int sx = (int)(s % sub), sy = (int)((s / sub) % sub), sz = (int)(s / (sub * sub));
+        const uint64_t ctr = 3u * (per * ((uint64_t)C * (step + 1) + (uint64_t)c) + s);
+        const double x = (((double)sx + splitmix_unit(seed, ctr + 0)) / sub + i) * g.dx;
+        const double y = (((double)sy + splitmix_unit(seed, ctr + 1)) / sub + j) * g.dx;
+        const double z = (((double)sz + splitmix_unit(seed, ctr + 2)) / sub + kk) * g.dx;
+        const int64_t d = (int64_t)s0 + s;
+        pos[d] = into_cell<T>(x, i, g.dx, g.inv_dx, g.nx);
+        pos[n + d] = into_cell<T>(y, j, g.dx, g.inv_dx, g.ny);
+        pos[2 * n + d] = into_cell<T>(z, kk, g.dx, g.inv_dx, g.nz);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) vel[ax * n + d] = (T)mean[ax];
+        id[d] = n_old + o + t;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_bin_gather_spread(
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ key,
+    const uint32_t* __restrict__ start, const uint32_t* __restrict__ count, int64_t n,
+    const T* __restrict__ pos_in, const T* __restrict__ vel_in, const uint32_t* __restrict__ id_in,
+    T* __restrict__ pos_out, T* __restrict__ vel_out, uint32_t* __restrict__ id_out,
+    const uint32_t* __restrict__ spread, int64_t n_out)
+{
+    bin_gather_body<T, true>(plain_blk(), perm, key, start, count, n, pos_in, vel_in, id_in, pos_out, vel_out,
+                             id_out, spread, n_out);
+}
+
+template <typename T>
+void launch_reseed_move(const Geo& g, int sub, uint64_t seed, uint64_t step, const uint32_t* perm,
+                        const uint32_t* key, uint32_t* start, uint32_t* count, const uint32_t* add,
+                        const uint32_t* off, int64_t n, int64_t n_out, const T* pos_in, const T* vel_in,
+                        const uint32_t* id_in, T* pos_out, T* vel_out, uint32_t* id_out, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_bin_gather_spread<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm,
+                           key, start, count, n, pos_in, vel_in, id_in, pos_out, vel_out, id_out, off, n_out);
+    const int64_t C = (int64_t)g.nx * g.ny * g.nz;
+    hipLaunchKernelGGL(k_reseed_fill<T>, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, st, g, sub, seed, step,
+                       count, start, add, off, (uint32_t)n, n_out, pos_out, vel_out, id_out);
+}
+
+template void launch_reseed_move<float>(const Geo&, int, uint64_t, uint64_t, const uint32_t*, const uint32_t*,
+                                        uint32_t*, uint32_t*, const uint32_t*, const uint32_t*, int64_t, int64_t,
+                                        const float*, const float*, const uint32_t*, float*, float*, uint32_t*,
+                                        hipStream_t);
+template void launch_reseed_move<double>(const Geo&, int, uint64_t, uint64_t, const uint32_t*, const uint32_t*,
+                                         uint32_t*, uint32_t*, const uint32_t*, const uint32_t*, int64_t,
+                                         int64_t, const double*, const double*, const uint32_t*, double*,
+                                         double*, uint32_t*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // active tiles (the fluid-cells vector of Sec. 3.1.5, at tile granularity)

@@ -33,6 +33,7 @@ FLIP_FLAG_KERNEL_TIMING = 8
 FLIP_FLAG_MULTIGRID = 16
 FLIP_FLAG_RED_BLACK_GS = 32
 FLIP_FLAG_ADAPTIVE_DT = 64
+FLIP_FLAG_RESEED = 128
 
 FLIP_FIELD_POS = 0
 FLIP_FIELD_VEL = 1
@@ -80,7 +81,8 @@ class flip_config(ctypes.Structure):
                 ("n_regions", ctypes.c_uint32), ("regions", ctypes.POINTER(flip_region)),
                 ("subcells_per_axis", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("n_particles", ctypes.c_int64), ("pos0", ctypes.POINTER(ctypes.c_double)),
-                ("vel0", ctypes.POINTER(ctypes.c_double)), ("cfl", ctypes.c_double)]
+                ("vel0", ctypes.POINTER(ctypes.c_double)), ("cfl", ctypes.c_double),
+                ("particle_capacity", ctypes.c_int64)]
 
 
 class flip_step_stats(ctypes.Structure):
@@ -90,7 +92,8 @@ class flip_step_stats(ctypes.Structure):
                 ("max_b", ctypes.c_double), ("max_r", ctypes.c_double),
                 ("pcg_iterations_total", ctypes.c_int64), ("pcg_cell_iterations_total", ctypes.c_int64),
                 ("latched_status", ctypes.c_int32), ("refinements", ctypes.c_int32), ("kernel_ms", ctypes.c_double * FLIP_KERNEL_COUNT),
-                ("kernel_launches", ctypes.c_int64 * FLIP_KERNEL_COUNT), ("dt", ctypes.c_double)]
+                ("kernel_launches", ctypes.c_int64 * FLIP_KERNEL_COUNT), ("dt", ctypes.c_double),
+                ("n_reseeded", ctypes.c_int64)]
 
 
 _lib = None
@@ -145,7 +148,7 @@ def _check(status: int, where: str, allow=()):
 
 def make_config(shape, dx, dt, *, gravity=(0.0, -9.81, 0.0), flip_ratio=0.95, density=1.0,
                 pcg_tol=1e-6, pcg_max_iters=0, ir_tol=1e-8, precision=FLIP_FP32, flags=0,
-                regions=(), subcells=2, seed=0, pos0=None, vel0=None, cfl=0.0):
+                regions=(), subcells=2, seed=0, pos0=None, vel0=None, cfl=0.0, capacity=0):
     """Build a flip_config. Returns (config, keepalive) - keep both alive while in use."""
     cfg = flip_config()
     cfg.nx, cfg.ny, cfg.nz = (int(v) for v in shape)
@@ -160,6 +163,7 @@ def make_config(shape, dx, dt, *, gravity=(0.0, -9.81, 0.0), flip_ratio=0.95, de
     cfg.precision = int(precision)
     cfg.flags = int(flags)
     cfg.cfl = float(cfl)
+    cfg.particle_capacity = int(capacity)
     keep = []
     if pos0 is not None:
         p = np.ascontiguousarray(pos0, dtype=np.float64).reshape(3, -1)
@@ -181,12 +185,14 @@ def make_config(shape, dx, dt, *, gravity=(0.0, -9.81, 0.0), flip_ratio=0.95, de
         keep.append(arr)
         cfg.n_regions = len(regions)
         cfg.regions = arr
-        cfg.subcells_per_axis = int(subcells)
-        cfg.seed = int(seed)
+    # the seeding density and jitter also drive reseeding
+    cfg.subcells_per_axis = int(subcells)
+    cfg.seed = int(seed)
     return cfg, keep
 
 
-def scene_config(sc, *, precision=None, flags=0, pcg_tol=None, pcg_max_iters=0, pos0=None, vel0=None, cfl=0.0):
+def scene_config(sc, *, precision=None, flags=0, pcg_tol=None, pcg_max_iters=0, pos0=None, vel0=None, cfl=0.0,
+                 capacity=0):
     """flip_config for a scene of ``paper_2404_01931_amd.inputs``."""
     prec = {"fp32": FLIP_FP32, "fp64": FLIP_FP64, "mixed": FLIP_MIXED}[sc.precision]
     if precision is not None:
@@ -194,7 +200,8 @@ def scene_config(sc, *, precision=None, flags=0, pcg_tol=None, pcg_max_iters=0, 
     return make_config((sc.n, sc.n, sc.n), sc.dx, sc.dt, gravity=sc.gravity, flip_ratio=sc.flip_ratio,
                        density=sc.density, pcg_tol=sc.tol if pcg_tol is None else pcg_tol,
                        pcg_max_iters=pcg_max_iters, ir_tol=sc.ir_tol, precision=prec, flags=flags,
-                       regions=sc.regions, subcells=sc.sub, seed=sc.seed, pos0=pos0, vel0=vel0, cfl=cfl)
+                       regions=sc.regions, subcells=sc.sub, seed=sc.seed, pos0=pos0, vel0=vel0, cfl=cfl,
+                       capacity=capacity)
 
 
 # --------------------------------------------------------------------------

@@ -24,7 +24,10 @@ def params_of(sim, tol=1e-12, precond=O.PRECOND_MIC0):
                     else (0.0, 0.0, 0.0), dt=c.dt, flip_ratio=c.flip_ratio, density=c.density, tol=tol,
                     max_iters=100000, precond=precond,
                     no_projection=bool(c.flags & flip.FLIP_FLAG_NO_PROJECTION),
-                    advect_particle_vel=bool(c.flags & flip.FLIP_FLAG_ADVECT_PARTICLE_VEL))
+                    advect_particle_vel=bool(c.flags & flip.FLIP_FLAG_ADVECT_PARTICLE_VEL),
+                    reseed_sub=c.subcells_per_axis if c.flags & flip.FLIP_FLAG_RESEED else 0,
+                    reseed_seed=c.seed, reseed_step=int(sim.stats().steps),
+                    reseed_fp32=c.precision != flip.FLIP_FP64)
 
 
 def state(sim):
