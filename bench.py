@@ -208,8 +208,13 @@ def measure(args, sc, solver: str) -> dict:
 
     mgflag = flip.FLIP_FLAG_MULTIGRID if solver == "multigrid" else 0
     sflag = mgflag | (flip.FLIP_FLAG_RED_BLACK_GS if solver == "rbgs" else 0)
+    # reseeding adds particles: room for 6 per cell (the scenes seed fewer than 3 per cell)
+    cap = 0
+    if args.reseed:
+        sflag |= flip.FLIP_FLAG_RESEED
+        cap = 6 * sc.n**3
     # throughput: a handle without kernel timing (timed launches cost extra work)
-    cfg, keep = flip.scene_config(sc, flags=sflag)
+    cfg, keep = flip.scene_config(sc, flags=sflag, capacity=cap)
     progress(f"init {sc.name} ({solver})")
     t = time.perf_counter()
     sim = flip.Simulation(cfg, keep)
@@ -221,19 +226,29 @@ def measure(args, sc, solver: str) -> dict:
     progress(f"warmup done ({args.warmup} steps, last {s_pre.pcg_iterations} PCG iterations)")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(args.steps)
+    if args.reseed:
+        # the particle count grows: sum each step's count (a reseeding step
+        # already waits for the device once, for its new total)
+        particle_steps = 0
+        for _ in range(args.steps):
+            sim.step(1)
+            particle_steps += sim.stats().n_particles
+    else:
+        sim.step(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
     s_last = sim.stats()
     n = s_last.n_particles
+    if not args.reseed:
+        particle_steps = n * args.steps
     progress(f"timed {args.steps} steps in {elapsed:.3f} s")
     sim.close()
     del sim
     # kernel durations: a second handle of the same scene with kernel timing on
     # (HIP events; the solver kernels record their own start and end), stepped
     # through the same warm-up and a few more steps
-    cfg_t, keep_t = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING | sflag)
+    cfg_t, keep_t = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING | sflag, capacity=cap)
     sim = flip.Simulation(cfg_t, keep_t)
     if args.warmup:
         sim.step(args.warmup)
@@ -284,8 +299,8 @@ def measure(args, sc, solver: str) -> dict:
 
     sim.close()
     del sim
-    return {"solver": solver, "n": n, "elapsed": elapsed, "roofline": roofline, "pcg": pcg,
-            "stage_ms": stage_ms}
+    return {"solver": solver, "n": n, "n0": s_pre.n_particles, "particle_steps": particle_steps,
+            "elapsed": elapsed, "roofline": roofline, "pcg": pcg, "stage_ms": stage_ms}
 
 
 def main():
@@ -313,6 +328,8 @@ def main():
                          "measured too and reported beside it), or rbgs: the paper's red-black "
                          "Gauss-Seidel solver alone")
     ap.add_argument("--no-second-solver", action="store_true", help="measure the headline solver only")
+    ap.add_argument("--reseed", action="store_true",
+                    help="particle reseeding on (Sec. 3.1.2): sparse fluid cells are refilled each step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scales HBM counters)")
     args = ap.parse_args()
@@ -369,7 +386,7 @@ def main():
     solver_label = {"jacobi": "Jacobi-PCG", "multigrid": "multigrid-PCG", "rbgs": "red-black Gauss-Seidel"}
     line = {
         "metric": "particle-steps/s",
-        "value": n * args.steps / elapsed,
+        "value": main_run["particle_steps"] / elapsed,
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -383,7 +400,9 @@ def main():
         "config": {"workload": f"{sc.name}: {inputs.describe(sc)}, {sc.n}^3 MAC grid, {n} particles, "
                                f"{sc.precision.upper()}, dt=1/{round(1 / sc.dt)}, FLIP {sc.flip_ratio}, "
                                f"{solver_label[main_run['solver']]} tol {sc.tol:g}"
-                               + (f", FP64 refinement to {sc.ir_tol:g}" if sc.precision == "mixed" else ""),
+                               + (f", FP64 refinement to {sc.ir_tol:g}" if sc.precision == "mixed" else "")
+                               + (f", particle reseeding ({main_run['n0']} particles after warmup)"
+                                  if args.reseed else ""),
                    "grid": sc.n, "particles": n, "parallelism": "single GPU"},
         "roofline": main_run["roofline"],
         "pcg": main_run["pcg"],
@@ -393,7 +412,7 @@ def main():
         if r is main_run:
             continue
         line[f"{name}_pcg_same_scene"] = {
-            "value": r["n"] * args.steps / r["elapsed"], "unit": "particle-steps/s",
+            "value": r["particle_steps"] / r["elapsed"], "unit": "particle-steps/s",
             "ms_per_step": r["elapsed"] / args.steps * 1e3, "roofline": r["roofline"], "pcg": r["pcg"],
             "kernel_ms_per_step": r["stage_ms"]}
     line["serving"] = serving
