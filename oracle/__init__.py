@@ -87,6 +87,7 @@ def _load():
             "orc_g2p_advect": (None, [G, i64, P, P, P, P, P, P, P, P, dbl, dbl, ctypes.c_uint]),
             "orc_cfl_dt": (dbl, [i64, P, P, P, dbl, dbl, dbl]),
             "orc_reseed": (i64, [G, i32, u64, i64, i32, P, P, P, P, P, P, P, P, P, P, P, P]),
+            "orc_surface_field": (None, [G, i32, dbl, dbl, i64, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -326,6 +327,17 @@ def reseed(grid: Grid, sub: int, seed_value: int, step_index: int, round_fp32: b
         lib.orc_reseed(*args, _ptr(pos_new[0]), _ptr(pos_new[1]), _ptr(pos_new[2]), _ptr(vel_new[0]),
                        _ptr(vel_new[1]), _ptr(vel_new[2]), _ptr(cell_new))
     return pos_new, vel_new, cell_new
+
+
+def surface_field(grid: Grid, pos, radius: float, search: float, refine: int = 1) -> np.ndarray:
+    """Improved-blobby signed distance (Sec. 3.3.1) at the corners of the
+    sampling grid (spacing dx / refine), shape (nz*refine+1, ny*refine+1, nx*refine+1)."""
+    pos = _f64(pos)
+    shape = (grid.nz * refine + 1, grid.ny * refine + 1, grid.nx * refine + 1)
+    phi = np.zeros(shape)
+    _load().orc_surface_field(grid.c(), int(refine), float(radius), float(search), pos.shape[1],
+                              _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]), _ptr(phi))
+    return phi
 
 
 @dataclass

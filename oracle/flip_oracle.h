@@ -80,6 +80,11 @@ int64_t orc_reseed(const orc_grid* g, int sub, uint64_t seed, int64_t step, int 
                    const uint32_t* count, const uint32_t* start, const double* vx, const double* vy,
                    const double* vz, double* px_new, double* py_new, double* pz_new, double* vx_new,
                    double* vy_new, double* vz_new, uint32_t* cell_new);
+/* Surface scalar field (Sec. 3.3.1): improved-blobby signed distance at the
+   (nx*refine+1) x (ny*refine+1) x (nz*refine+1) corners of the sampling grid,
+   x fastest; phi = search where no particle is closer than search. */
+void orc_surface_field(const orc_grid* g, int refine, double radius, double search, int64_t n,
+                       const double* px, const double* py, const double* pz, double* phi);
 
 #ifdef __cplusplus
 }
