@@ -230,6 +230,29 @@ flip_status flip_field_bytes(const flip_handle* h, int field, size_t* out_bytes)
 flip_status flip_readback(flip_handle* h, int field, void* dst, size_t dst_bytes, int dst_is_device,
                           void* hip_stream);
 
+/* ---- surface reconstruction: scalar field (Sec. 3.3.1) -------------------
+ *
+ * The improved-blobby signed distance of the particles' current positions at
+ * the corners of a sampling grid of spacing dx / refine (1 <= refine <= 16):
+ *   phi(x) = |x - sum_i w_i x_i| - radius,
+ *   w_i = k(|x - x_i| / R) / sum_j k(|x - x_j| / R),  k(s) = max(0, (1 - s^2)^3),
+ * over the particles closer than R = search_radius (every particle has the
+ * same radius); a corner with no particle closer than R gets phi = R
+ * (outside). Negative inside the fluid, positive outside.
+ *
+ * Corners (I, J, K), I in 0 .. nx*refine (x fastest), at (I, J, K) * dx / refine.
+ * d_phi: caller-owned device memory of flip_surface_field_bytes bytes, reals
+ * of the particle precision (double for FLIP_FP64, float otherwise). The call
+ * bins the particles first (the binning of a step: their order, the ID field
+ * and the cell fields change as after a step's binning) and is stream-ordered
+ * on hip_stream; it does not synchronise. The search visits the cells within R
+ * of a corner, so its cost grows with (2 R / dx + 1)^3.
+ * Errors: FLIP_E_INVALID for a null pointer, refine out of range, radius or
+ * search_radius not positive and finite, or phi_bytes too small. */
+flip_status flip_surface_field_bytes(const flip_handle* h, int refine, size_t* out_bytes);
+flip_status flip_surface_field(flip_handle* h, double radius, double search_radius, int refine, void* d_phi,
+                               size_t phi_bytes, void* hip_stream);
+
 /* Statistics of the handle; synchronises the stream of the last step. */
 flip_status flip_stats(flip_handle* h, flip_step_stats* out);
 

@@ -14,8 +14,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libflipmi.so")
-SOURCES = ["kernels_bin.hip", "kernels_transfer.hip", "kernels_pressure.hip", "kernels_mg.hip", "capi.hip",
-           "batch.hip"]
+SOURCES = ["kernels_bin.hip", "kernels_transfer.hip", "kernels_pressure.hip", "kernels_mg.hip",
+           "kernels_surface.hip", "capi.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

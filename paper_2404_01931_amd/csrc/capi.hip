@@ -448,6 +448,25 @@ flip_status gs_loop(flip_handle* h, V* p, int max_iters, hipStream_t st, PcgStat
     return FLIP_OK;
 }
 
+// binning of the particles' current positions alone (keys, counts, starts,
+// the stable sort): the space hash for work outside a step
+template <typename T>
+void rebin(flip_handle* h, hipStream_t st)
+{
+    const Geo& g = h->geo;
+    const Sizes& s = h->sz;
+    const int64_t n = s.n;
+    const int nxt = h->cur ^ 1;
+    launch_fill_u32(h->count, s.C, 0u, st);
+    launch_bin_keys<T>(g, (const T*)h->pos[h->cur], n, h->key, h->rank, h->count, st);
+    launch_exclusive_scan_u32(h->count, h->start, s.C, h->scan_tmp, st);
+    launch_bin_scatter(h->key, h->rank, h->start, n, h->perm, st);
+    launch_bin_gather<T>(h->perm, h->key, h->start, h->count, n, (const T*)h->pos[h->cur],
+                         (const T*)h->vel[h->cur], h->id[h->cur], (T*)h->pos[nxt], (T*)h->vel[nxt], h->id[nxt],
+                         st);
+    h->cur = nxt;
+}
+
 template <typename T, bool MIXED>
 flip_status run_step(flip_handle* h, hipStream_t st)
 {
@@ -899,6 +918,39 @@ flip_status flip_readback(flip_handle* h, int field, void* dst, size_t dst_bytes
     }
     if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
     if (!dst_is_device) HIP_TRY(hipStreamSynchronize(st));
+    return FLIP_OK;
+}
+
+flip_status flip_surface_field_bytes(const flip_handle* h, int refine, size_t* out_bytes)
+{
+    if (!h || !out_bytes || refine < 1 || refine > 16) return FLIP_E_INVALID;
+    const flip_config& c = h->cfg;
+    *out_bytes = (size_t)(c.nx * refine + 1) * (c.ny * refine + 1) * (c.nz * refine + 1) * h->sz.rb;
+    return FLIP_OK;
+}
+
+flip_status flip_surface_field(flip_handle* h, double radius, double search_radius, int refine, void* d_phi,
+                               size_t phi_bytes, void* hip_stream)
+{
+    if (!h || !d_phi) return FLIP_E_INVALID;
+    if (!(radius > 0.0) || !std::isfinite(radius) || !(search_radius > 0.0) || !std::isfinite(search_radius))
+        return FLIP_E_INVALID;
+    size_t need = 0;
+    flip_status v = flip_surface_field_bytes(h, refine, &need);
+    if (v != FLIP_OK) return v;
+    if (phi_bytes < need) return FLIP_E_INVALID;
+    hipStream_t st = (hipStream_t)hip_stream;
+    h->last_stream = st;
+    if (h->prec == FLIP_FP64) {
+        rebin<double>(h, st);
+        launch_surface_field<double>(h->geo, refine, radius, search_radius, h->start, h->count,
+                                     (const double*)h->pos[h->cur], h->sz.n, (double*)d_phi, st);
+    } else {
+        rebin<float>(h, st);
+        launch_surface_field<float>(h->geo, refine, radius, search_radius, h->start, h->count,
+                                    (const float*)h->pos[h->cur], h->sz.n, (float*)d_phi, st);
+    }
+    if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
     return FLIP_OK;
 }
 

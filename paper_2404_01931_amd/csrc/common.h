@@ -141,6 +141,12 @@ void launch_reseed_move(const Geo& g, int sub, uint64_t seed, uint64_t step, con
                         const uint32_t* off, int64_t n, int64_t n_out, const T* pos_in, const T* vel_in,
                         const uint32_t* id_in, T* pos_out, T* vel_out, uint32_t* id_out, hipStream_t st);
 
+// surface scalar field (Sec. 3.3.1) at the (n*refine+1)^3 sampling corners,
+// from binned particles
+template <typename T>
+void launch_surface_field(const Geo& g, int refine, double radius, double search, const uint32_t* start,
+                          const uint32_t* count, const T* pos, int64_t n, T* phi, hipStream_t st);
+
 // tiles: flags -> scan -> compaction -> neighbour table; writes the active
 // count to *d_nactive
 void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint32_t* tile_excl,

@@ -57,7 +57,8 @@ FLIP_BATCH_GRAPHS = 1
 
 EXPORTED = ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes", "flip_readback",
             "flip_stats", "flip_destroy", "flip_status_string", "flip_batch_workspace_bytes",
-            "flip_batch_create", "flip_batch_step", "flip_batch_destroy"]
+            "flip_batch_create", "flip_batch_step", "flip_batch_destroy", "flip_surface_field_bytes",
+            "flip_surface_field"]
 
 
 class FlipError(RuntimeError):
@@ -124,9 +125,11 @@ def load():
         lib.flip_batch_step.argtypes = [vp, i32, vp]
         lib.flip_batch_destroy.argtypes = [vp]
         lib.flip_batch_destroy.restype = None
+        lib.flip_surface_field_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        lib.flip_surface_field.argtypes = [vp, ctypes.c_double, ctypes.c_double, i32, vp, sz, vp]
         for name in ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes",
                      "flip_readback", "flip_stats", "flip_batch_workspace_bytes", "flip_batch_create",
-                     "flip_batch_step"]:
+                     "flip_batch_step", "flip_surface_field_bytes", "flip_surface_field"]:
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -325,6 +328,28 @@ class Simulation:
         if field in (FLIP_FIELD_POS, FLIP_FIELD_VEL):
             out = out.reshape(3, -1)
         return out
+
+    def surface_field_device(self, radius: float, search: float, refine: int = 1):
+        """Surface scalar field (Sec. 3.3.1) into a new device tensor of shape
+        (nz*refine+1, ny*refine+1, nx*refine+1), stream-ordered."""
+        nbytes = ctypes.c_size_t(0)
+        _check(load().flip_surface_field_bytes(self.h, int(refine), ctypes.byref(nbytes)),
+               "flip_surface_field_bytes")
+        c = self.cfg
+        shape = (c.nz * refine + 1, c.ny * refine + 1, c.nx * refine + 1)
+        dt = self.torch.float64 if c.precision == FLIP_FP64 else self.torch.float32
+        phi = self.torch.empty(shape, dtype=dt, device=self.ws.device)
+        assert phi.numel() * phi.element_size() == nbytes.value
+        _check(load().flip_surface_field(self.h, float(radius), float(search), int(refine),
+                                         ctypes.c_void_p(phi.data_ptr()), nbytes.value,
+                                         ctypes.c_void_p(self.stream.cuda_stream)), "flip_surface_field")
+        return phi
+
+    def surface_field(self, radius: float, search: float, refine: int = 1) -> np.ndarray:
+        """Surface scalar field (Sec. 3.3.1) as a host array (synchronises)."""
+        phi = self.surface_field_device(radius, search, refine)
+        self.stream.synchronize()
+        return phi.cpu().numpy()
 
     def read_device(self, field: int):
         """Stream-ordered device-to-device readback into a new torch tensor of bytes."""
