@@ -88,6 +88,8 @@ def _load():
             "orc_cfl_dt": (dbl, [i64, P, P, P, dbl, dbl, dbl]),
             "orc_reseed": (i64, [G, i32, u64, i64, i32, P, P, P, P, P, P, P, P, P, P, P, P]),
             "orc_surface_field": (None, [G, i32, dbl, dbl, i64, P, P, P, P]),
+            "orc_surface_mesh": (i64, [G, i32, P, P, P, P, ctypes.POINTER(i64)]),
+            "orc_mc_case_triangles": (i32, [ctypes.c_uint, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -338,6 +340,29 @@ def surface_field(grid: Grid, pos, radius: float, search: float, refine: int = 1
     _load().orc_surface_field(grid.c(), int(refine), float(radius), float(search), pos.shape[1],
                               _ptr(pos[0]), _ptr(pos[1]), _ptr(pos[2]), _ptr(phi))
     return phi
+
+
+def surface_mesh(grid: Grid, phi, refine: int = 1):
+    """Marching cubes (Sec. 3.3.2) of the corner field phi: (vertices (nv, 3),
+    unit vertex normals (nv, 3), triangles (nt, 3) vertex indices)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    lib = _load()
+    nv = ctypes.c_int64(0)
+    null = ctypes.c_void_p(0)
+    nt = lib.orc_surface_mesh(grid.c(), int(refine), _ptr(phi), null, null, null, ctypes.byref(nv))
+    verts = np.zeros((nv.value, 3))
+    normals = np.zeros((nv.value, 3))
+    tris = np.zeros((nt, 3), dtype=np.int64)
+    lib.orc_surface_mesh(grid.c(), int(refine), _ptr(phi), _ptr(verts), _ptr(normals), _ptr(tris),
+                         ctypes.byref(nv))
+    return verts, normals, tris
+
+
+def mc_case_triangles(inside: int) -> np.ndarray:
+    """Local-edge triples of the triangles of one cube configuration."""
+    buf = np.zeros(48, dtype=np.int32)
+    nt = _load().orc_mc_case_triangles(int(inside), _ptr(buf))
+    return buf[:3 * nt].reshape(nt, 3)
 
 
 @dataclass

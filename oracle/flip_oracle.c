@@ -30,6 +30,8 @@
  *                      fluid cells up to the seeding density)
  *   surface field      paper Sec. 3.3.1 (improved-blobby signed distance at
  *                      the corners of a sampling grid)
+ *   surface mesh       paper Sec. 3.3.2 (marching cubes, inverse-area
+ *                      weighted vertex normals)
  *
  * Readings of points the paper leaves open are stated where they are used.
  */
@@ -814,4 +816,226 @@ void orc_surface_field(const orc_grid* g, int refine, double radius, double sear
                 phi[I + (int64_t)cx * (J + (int64_t)cy * K)] = out;
             }
     free(kv);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Marching cubes (paper Sec. 3.3.2). A corner is inside when phi < 0. Each   */
+/* grid edge whose two corners differ carries one vertex, at the linearly     */
+/* interpolated zero of phi; vertices are numbered in the order of their      */
+/* edges, edge id 3 * corner + axis (corner x-fastest, the edge running from  */
+/* it in +axis). The paper gives no case table; the triangles of a cube follow */
+/* from this rule, applied to each cube directly:                             */
+/*  - on each of the cube's six faces, a face with two crossing edges gets a  */
+/*    segment joining them; a face with four gets, for each of its inside     */
+/*    corners, a segment joining that corner's two edges (inside corners are  */
+/*    kept apart);                                                            */
+/*  - each segment runs so that the inside corners it cuts off lie on its     */
+/*    left seen from outside the cube: (Q - P) x (m - P) . n > 0 for the      */
+/*    points P -> Q at the edge midpoints of the unit cube, m the mean of     */
+/*    those corners and n the face's outward normal;                          */
+/*  - the segments close into loops, each taken from its lowest local edge;   */
+/*    local edges: 0-3 along x at (y, z) = (0,0), (1,0), (0,1), (1,1); 4-7    */
+/*    along y at (x, z); 8-11 along z at (x, y);                              */
+/*  - a loop v0, v1, ..., v(m-1) gives the triangles (v0, v(k+1), v(k)),      */
+/*    k = 1 .. m-2, whose normals then point out of the fluid.                */
+/* Cubes are taken x-fastest, loops in order of their first edge.             */
+/* Vertex normals: the unit normals of the triangles at a vertex, each        */
+/* weighted by the inverse of the triangle's area, summed and normalised      */
+/* (degenerate triangles skipped; a vertex with none keeps (0, 0, 0)).        */
+/* ------------------------------------------------------------------------ */
+
+/* local edge -> its two corners (corner = cx + 2 cy + 4 cz) */
+static void mc_edge_corners(int e, int* a, int* b)
+{
+    const int axis = e / 4, q = e % 4;
+    int c0[3];
+    if (axis == 0) { c0[0] = 0; c0[1] = q & 1; c0[2] = q >> 1; }
+    else if (axis == 1) { c0[0] = q & 1; c0[1] = 0; c0[2] = q >> 1; }
+    else { c0[0] = q & 1; c0[1] = q >> 1; c0[2] = 0; }
+    *a = c0[0] + 2 * c0[1] + 4 * c0[2];
+    c0[axis] = 1;
+    *b = c0[0] + 2 * c0[1] + 4 * c0[2];
+}
+
+static int mc_edge_of(int a, int b)
+{
+    for (int e = 0; e < 12; ++e) {
+        int p, q;
+        mc_edge_corners(e, &p, &q);
+        if ((p == a && q == b) || (p == b && q == a)) return e;
+    }
+    return -1;
+}
+
+/* triangles of one cube as local-edge triples; returns their number */
+static int mc_cube_triangles(unsigned inside, int tri[][3])
+{
+    int next[12];
+    for (int e = 0; e < 12; ++e) next[e] = -1;
+    for (int axis = 0; axis < 3; ++axis)
+        for (int side = 0; side < 2; ++side) {
+            /* the face's corners in cyclic order */
+            const int u = (axis + 1) % 3, v = (axis + 2) % 3;
+            int cyc[4];
+            const int uv[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+            for (int t = 0; t < 4; ++t) {
+                int c[3];
+                c[axis] = side;
+                c[u] = uv[t][0];
+                c[v] = uv[t][1];
+                cyc[t] = c[0] + 2 * c[1] + 4 * c[2];
+            }
+            int ncross = 0;
+            for (int t = 0; t < 4; ++t)
+                ncross += ((inside >> cyc[t]) & 1) != ((inside >> cyc[(t + 1) % 4]) & 1);
+            /* segments: (edge, edge, cut-off corners as a bit set) */
+            int seg[2][2], cut[2], nseg = 0;
+            if (ncross == 2) {
+                int ends[2], k = 0;
+                for (int t = 0; t < 4; ++t)
+                    if (((inside >> cyc[t]) & 1) != ((inside >> cyc[(t + 1) % 4]) & 1))
+                        ends[k++] = mc_edge_of(cyc[t], cyc[(t + 1) % 4]);
+                seg[0][0] = ends[0];
+                seg[0][1] = ends[1];
+                cut[0] = 0;
+                for (int t = 0; t < 4; ++t)
+                    if ((inside >> cyc[t]) & 1) cut[0] |= 1 << cyc[t];
+                nseg = 1;
+            } else if (ncross == 4) {
+                for (int t = 0; t < 4; ++t)
+                    if ((inside >> cyc[t]) & 1) {
+                        seg[nseg][0] = mc_edge_of(cyc[(t + 3) % 4], cyc[t]);
+                        seg[nseg][1] = mc_edge_of(cyc[t], cyc[(t + 1) % 4]);
+                        cut[nseg] = 1 << cyc[t];
+                        ++nseg;
+                    }
+            }
+            double n[3] = {0.0, 0.0, 0.0};
+            n[axis] = side ? 1.0 : -1.0;
+            for (int s = 0; s < nseg; ++s) {
+                double P[3], Q[3], m[3] = {0.0, 0.0, 0.0};
+                int a, b, cnt = 0;
+                mc_edge_corners(seg[s][0], &a, &b);
+                for (int d = 0; d < 3; ++d) P[d] = 0.5 * (((a >> d) & 1) + ((b >> d) & 1));
+                mc_edge_corners(seg[s][1], &a, &b);
+                for (int d = 0; d < 3; ++d) Q[d] = 0.5 * (((a >> d) & 1) + ((b >> d) & 1));
+                for (int c = 0; c < 8; ++c)
+                    if ((cut[s] >> c) & 1) {
+                        for (int d = 0; d < 3; ++d) m[d] += (c >> d) & 1;
+                        ++cnt;
+                    }
+                for (int d = 0; d < 3; ++d) m[d] /= cnt;
+                const double dq[3] = {Q[0] - P[0], Q[1] - P[1], Q[2] - P[2]};
+                const double dm[3] = {m[0] - P[0], m[1] - P[1], m[2] - P[2]};
+                const double cr[3] = {dq[1] * dm[2] - dq[2] * dm[1], dq[2] * dm[0] - dq[0] * dm[2],
+                                      dq[0] * dm[1] - dq[1] * dm[0]};
+                const double side_test = cr[0] * n[0] + cr[1] * n[1] + cr[2] * n[2];
+                if (side_test > 0) next[seg[s][0]] = seg[s][1];
+                else next[seg[s][1]] = seg[s][0];
+            }
+        }
+    int ntri = 0, seen[12] = {0};
+    for (int e = 0; e < 12; ++e) {
+        if (next[e] < 0 || seen[e]) continue;
+        int loop[12], m = 0, v = e;
+        do {
+            seen[v] = 1;
+            loop[m++] = v;
+            v = next[v];
+        } while (v != e && v >= 0 && m < 12);
+        for (int k = 1; k + 1 < m; ++k) {
+            tri[ntri][0] = loop[0];
+            tri[ntri][1] = loop[k + 1];
+            tri[ntri][2] = loop[k];
+            ++ntri;
+        }
+    }
+    return ntri;
+}
+
+int orc_mc_case_triangles(unsigned inside, int* tri_edges)
+{
+    int tri[16][3];
+    const int nt = mc_cube_triangles(inside & 255u, tri);
+    if (tri_edges)
+        for (int t = 0; t < nt; ++t)
+            for (int k = 0; k < 3; ++k) tri_edges[3 * t + k] = tri[t][k];
+    return nt;
+}
+
+/* phi on corners (cx = nx*refine+1 ...), spacing h = dx / refine. Returns the
+   vertex count through *nv and the triangle count; with verts == NULL only
+   counts. */
+int64_t orc_surface_mesh(const orc_grid* g, int refine, const double* phi, double* verts, double* normals,
+                         int64_t* tris, int64_t* nv)
+{
+    const int cx = g->nx * refine + 1, cy = g->ny * refine + 1, cz = g->nz * refine + 1;
+    const int64_t ncorner = (int64_t)cx * cy * cz;
+    const double h = g->dx / refine;
+    int64_t* vid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(3 * ncorner));
+    int64_t nvert = 0;
+    for (int64_t c = 0; c < ncorner; ++c) {
+        const int I = (int)(c % cx), J = (int)((c / cx) % cy), K = (int)(c / ((int64_t)cx * cy));
+        const int ijk[3] = {I, J, K}, lim[3] = {cx, cy, cz};
+        for (int a = 0; a < 3; ++a) {
+            vid[3 * c + a] = -1;
+            if (ijk[a] + 1 >= lim[a]) continue;
+            const int64_t step = a == 0 ? 1 : (a == 1 ? cx : (int64_t)cx * cy);
+            const double f0 = phi[c], f1 = phi[c + step];
+            if ((f0 < 0.0) == (f1 < 0.0)) continue;
+            if (verts) {
+                const double t = f0 / (f0 - f1);
+                for (int d = 0; d < 3; ++d) verts[3 * nvert + d] = ijk[d] * h;
+                verts[3 * nvert + a] = (ijk[a] + t) * h;
+            }
+            vid[3 * c + a] = nvert++;
+        }
+    }
+    int64_t ntri = 0;
+    for (int K = 0; K + 1 < cz; ++K)
+        for (int J = 0; J + 1 < cy; ++J)
+            for (int I = 0; I + 1 < cx; ++I) {
+                unsigned inside = 0;
+                for (int q = 0; q < 8; ++q) {
+                    const int64_t c = (I + (q & 1)) + (int64_t)cx * ((J + ((q >> 1) & 1)) + (int64_t)cy * (K + (q >> 2)));
+                    if (phi[c] < 0.0) inside |= 1u << q;
+                }
+                int tri[16][3];
+                const int nt = mc_cube_triangles(inside, tri);
+                for (int t = 0; t < nt; ++t) {
+                    if (tris)
+                        for (int k = 0; k < 3; ++k) {
+                            int a, b;
+                            mc_edge_corners(tri[t][k], &a, &b);
+                            const int64_t c = (I + (a & 1)) + (int64_t)cx * ((J + ((a >> 1) & 1)) + (int64_t)cy * (K + (a >> 2)));
+                            tris[3 * ntri + k] = vid[3 * c + tri[t][k] / 4];
+                        }
+                    ++ntri;
+                }
+            }
+    if (verts && normals) {
+        for (int64_t v = 0; v < 3 * nvert; ++v) normals[v] = 0.0;
+        for (int64_t t = 0; t < ntri; ++t) {
+            const double* A = verts + 3 * tris[3 * t];
+            const double* B = verts + 3 * tris[3 * t + 1];
+            const double* C = verts + 3 * tris[3 * t + 2];
+            const double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+            const double w[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+            const double cr[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+            const double len = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+            if (!(len > 0.0)) continue;
+            const double area = 0.5 * len;
+            for (int k = 0; k < 3; ++k)
+                for (int d = 0; d < 3; ++d) normals[3 * tris[3 * t + k] + d] += (cr[d] / len) / area;
+        }
+        for (int64_t v = 0; v < nvert; ++v) {
+            double* nn = normals + 3 * v;
+            const double len = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+            if (len > 0.0)
+                for (int d = 0; d < 3; ++d) nn[d] /= len;
+        }
+    }
+    free(vid);
+    *nv = nvert;
+    return ntri;
 }

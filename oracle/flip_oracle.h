@@ -85,6 +85,15 @@ int64_t orc_reseed(const orc_grid* g, int sub, uint64_t seed, int64_t step, int 
    x fastest; phi = search where no particle is closer than search. */
 void orc_surface_field(const orc_grid* g, int refine, double radius, double search, int64_t n,
                        const double* px, const double* py, const double* pz, double* phi);
+/* Marching cubes (Sec. 3.3.2) on the corner field phi of the sampling grid:
+   vertices (3 doubles each), unit vertex normals, triangles (3 vertex indices
+   each); counts only when verts == NULL. Returns the triangle count, the
+   vertex count in *nv. The triangulation rule is stated at the definition. */
+int64_t orc_surface_mesh(const orc_grid* g, int refine, const double* phi, double* verts, double* normals,
+                         int64_t* tris, int64_t* nv);
+/* the triangles of one cube configuration (bit q set: corner q inside) as
+   local-edge triples; returns their number */
+int orc_mc_case_triangles(unsigned inside, int* tri_edges);
 
 #ifdef __cplusplus
 }
