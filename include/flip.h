@@ -253,6 +253,41 @@ flip_status flip_surface_field_bytes(const flip_handle* h, int refine, size_t* o
 flip_status flip_surface_field(flip_handle* h, double radius, double search_radius, int refine, void* d_phi,
                                size_t phi_bytes, void* hip_stream);
 
+/* ---- surface reconstruction: marching cubes (Sec. 3.3.2) ------------------
+ *
+ * The triangle mesh of phi = 0 for a corner field d_phi as written by
+ * flip_surface_field with the same refine. A corner is inside when phi < 0;
+ * every grid edge whose corners differ carries one vertex at the linear zero
+ * of phi along it; vertices are numbered in the order of their edges (edge id
+ * 3 * corner + axis, corners x-fastest), triangles in cube order (x-fastest)
+ * and, within a cube, by a case table built from this rule: on each cube
+ * face two crossing edges are joined by a segment and a face with four joins
+ * each inside corner's two edges; segments run with the cut-off inside
+ * corners on their left seen from outside the cube; segments close into
+ * loops, each from its lowest local edge (0-3 along x, 4-7 along y, 8-11
+ * along z), and a loop v0 .. v(m-1) gives (v0, v(k+1), v(k)): normals point
+ * out of the fluid. Vertex normals (Sec. 3.3.2): the unit normals of the
+ * triangles at the vertex, each weighted by the inverse of its area, summed
+ * and normalised (summed with atomics: the last bits vary between runs).
+ *
+ * d_work: caller-owned device scratch of flip_surface_mesh_workspace_bytes
+ * bytes (256-byte aligned; about 32 bytes per corner). d_vertices and
+ * d_normals hold 3 reals per vertex (x, y, z; the particle precision),
+ * d_triangles 3 int32 vertex indices per triangle, all device memory with
+ * room for max_vertices / max_triangles. With all three output pointers NULL
+ * the call only counts. The counts are returned in *n_vertices and
+ * *n_triangles (host); the call synchronises hip_stream to read them, then
+ * enqueues the output kernels without waiting for them.
+ * Errors: FLIP_E_INVALID (null arguments, refine out of [1, 16], a grid of
+ * 2^31 / 3 corners or more, only some outputs given); FLIP_E_WORKSPACE
+ * (d_work too small or misaligned, or the mesh larger than max_vertices or
+ * max_triangles: counts set, nothing written). */
+flip_status flip_surface_mesh_workspace_bytes(const flip_handle* h, int refine, size_t* out_bytes);
+flip_status flip_surface_mesh(flip_handle* h, const void* d_phi, int refine, void* d_work, size_t work_bytes,
+                              void* d_vertices, void* d_normals, int64_t max_vertices, int32_t* d_triangles,
+                              int64_t max_triangles, int64_t* n_vertices, int64_t* n_triangles,
+                              void* hip_stream);
+
 /* Statistics of the handle; synchronises the stream of the last step. */
 flip_status flip_stats(flip_handle* h, flip_step_stats* out);
 

@@ -510,9 +510,9 @@ flip_status run_step(flip_handle* h, hipStream_t st)
         launch_reseed_plan(h->count, s.C, (uint32_t)(sub * sub * sub), add, st);
         launch_exclusive_scan_u32(add, off, s.C, h->scan_tmp, st);
         launch_reseed_total(add, off, s.C, h->d_reseeded, st);
-        HIP_TRY(hipMemcpyAsync(h->h_reseeded, h->d_reseeded, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h->h_words, h->d_reseeded, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        const int64_t added = *h->h_reseeded;
+        const int64_t added = h->h_words[0];
         if (n + added > s.pcap) return FLIP_E_WORKSPACE;  // nothing moved yet
         launch_reseed_move<T>(g, sub, c.seed, (uint64_t)h->stats.steps, h->perm, h->key, h->start, h->count,
                               add, off, n, n + added, (const T*)h->pos[h->cur], (const T*)h->vel[h->cur],
@@ -805,7 +805,7 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
     launch_fill_bytes_zero(h->ps, PCG_STATE_BYTES + SYNC_BYTES, st);
     launch_fill_u64((uint64_t*)h->partials, 3 * h->groups, SLOT_EMPTY_BITS, st);
     if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&h->h_reseeded, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&h->h_words, 2 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
         flip_destroy(h);
         return FLIP_E_HIP;
     }
@@ -954,6 +954,79 @@ flip_status flip_surface_field(flip_handle* h, double radius, double search_radi
     return FLIP_OK;
 }
 
+namespace {
+
+// the mesh scratch of a sampling grid, carved from the caller's workspace
+size_t mc_carve(const flip_config& c, int refine, void* base, McTable** tab, McWork* w)
+{
+    const int64_t nc = (int64_t)(c.nx * refine + 1) * (c.ny * refine + 1) * (c.nz * refine + 1);
+    const int64_t ncube = (int64_t)(c.nx * refine) * (c.ny * refine) * (c.nz * refine);
+    Carver cv(base);
+    *tab = cv.take<McTable>(sizeof(McTable));
+    w->flag = cv.take<uint32_t>(4 * 3 * nc);
+    w->vidx = cv.take<uint32_t>(4 * 3 * nc);
+    w->cnt = cv.take<uint32_t>(4 * ncube);
+    w->toff = cv.take<uint32_t>(4 * ncube);
+    w->scan_tmp = cv.take<uint32_t>(4 * scan_tmp_words(std::max<int64_t>(3 * nc, ncube)));
+    w->totals = cv.take<uint32_t>(8);
+    return cv.off;
+}
+
+}  // namespace
+
+flip_status flip_surface_mesh_workspace_bytes(const flip_handle* h, int refine, size_t* out_bytes)
+{
+    if (!h || !out_bytes || refine < 1 || refine > 16) return FLIP_E_INVALID;
+    const flip_config& c = h->cfg;
+    if ((int64_t)(c.nx * refine + 1) * (c.ny * refine + 1) * (c.nz * refine + 1) * 3 >= ((int64_t)1 << 31))
+        return FLIP_E_INVALID;
+    McTable* tab;
+    McWork w;
+    *out_bytes = mc_carve(c, refine, nullptr, &tab, &w);
+    return FLIP_OK;
+}
+
+flip_status flip_surface_mesh(flip_handle* h, const void* d_phi, int refine, void* d_work, size_t work_bytes,
+                              void* d_vertices, void* d_normals, int64_t max_vertices, int32_t* d_triangles,
+                              int64_t max_triangles, int64_t* n_vertices, int64_t* n_triangles, void* hip_stream)
+{
+    if (!h || !d_phi || !d_work || !n_vertices || !n_triangles) return FLIP_E_INVALID;
+    size_t need = 0;
+    flip_status v = flip_surface_mesh_workspace_bytes(h, refine, &need);
+    if (v != FLIP_OK) return v;
+    if (work_bytes < need || ((uintptr_t)d_work & (ALIGN - 1))) return FLIP_E_WORKSPACE;
+    const bool count_only = !d_vertices && !d_normals && !d_triangles;
+    if (!count_only && (!d_vertices || !d_normals || !d_triangles)) return FLIP_E_INVALID;
+    hipStream_t st = (hipStream_t)hip_stream;
+    h->last_stream = st;
+    McTable* tab;
+    McWork w;
+    mc_carve(h->cfg, refine, d_work, &tab, &w);
+    const flip_config& c = h->cfg;
+    const int cx = c.nx * refine + 1, cy = c.ny * refine + 1, cz = c.nz * refine + 1;
+    HIP_TRY(hipMemcpyAsync(tab, &mc_table(), sizeof(McTable), hipMemcpyHostToDevice, st));
+    const bool fp64 = h->prec == FLIP_FP64;
+    if (fp64) launch_mc_count<double>((const double*)d_phi, cx, cy, cz, tab, w, st);
+    else launch_mc_count<float>((const float*)d_phi, cx, cy, cz, tab, w, st);
+    HIP_TRY(hipMemcpyAsync(h->h_words, w.totals, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
+    const int64_t nv = h->h_words[0], nt = h->h_words[1];
+    *n_vertices = nv;
+    *n_triangles = nt;
+    if (count_only) return FLIP_OK;
+    if (nv > max_vertices || nt > max_triangles) return FLIP_E_WORKSPACE;
+    const double hs = c.dx / refine;
+    if (fp64)
+        launch_mc_emit<double>((const double*)d_phi, cx, cy, cz, hs, tab, w, nv, nt, (double*)d_vertices,
+                               (double*)d_normals, d_triangles, st);
+    else
+        launch_mc_emit<float>((const float*)d_phi, cx, cy, cz, hs, tab, w, nv, nt, (float*)d_vertices,
+                              (float*)d_normals, d_triangles, st);
+    if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
+    return FLIP_OK;
+}
+
 flip_status flip_stats(flip_handle* h, flip_step_stats* out)
 {
     if (!h || !out) return FLIP_E_INVALID;
@@ -969,7 +1042,7 @@ void flip_destroy(flip_handle* h)
     for (auto& e : h->ev)
         if (e) (void)hipEventDestroy(e);
     if (h->h_ps) (void)hipHostFree(h->h_ps);
-    if (h->h_reseeded) (void)hipHostFree(h->h_reseeded);
+    if (h->h_words) (void)hipHostFree(h->h_words);
     delete h;
 }
 

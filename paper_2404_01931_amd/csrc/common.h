@@ -147,6 +147,28 @@ template <typename T>
 void launch_surface_field(const Geo& g, int refine, double radius, double search, const uint32_t* start,
                           const uint32_t* count, const T* pos, int64_t n, T* phi, hipStream_t st);
 
+// marching cubes (Sec. 3.3.2): the case table (triangles per configuration as
+// local-edge triples) and the scratch arrays of one mesh extraction
+constexpr int MC_MAX_TRI = 12;
+struct McTable {
+    uint8_t ntri[256];
+    int8_t edge[256][3 * MC_MAX_TRI];
+};
+const McTable& mc_table();  // built once on the host
+struct McWork {
+    uint32_t* flag;      // 3 per corner: the edge crosses phi = 0
+    uint32_t* vidx;      // 3 per corner: vertex index of the edge (exclusive scan of flag)
+    uint32_t* cnt;       // per cube: triangles
+    uint32_t* toff;      // per cube: first triangle (exclusive scan of cnt)
+    uint32_t* scan_tmp;  // scan_tmp_words(max(3 corners, cubes))
+    uint32_t* totals;    // [vertices, triangles]
+};
+template <typename T>
+void launch_mc_count(const T* phi, int cx, int cy, int cz, const McTable* tab, const McWork& w, hipStream_t st);
+template <typename T>
+void launch_mc_emit(const T* phi, int cx, int cy, int cz, double h, const McTable* tab, const McWork& w,
+                    int64_t nv, int64_t nt, T* verts, T* normals, int32_t* tris, hipStream_t st);
+
 // tiles: flags -> scan -> compaction -> neighbour table; writes the active
 // count to *d_nactive
 void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint32_t* tile_excl,

@@ -63,7 +63,7 @@ struct flip_handle {
     int na = -1;     // active tiles of the current solve, once read back
     int prev_iters = 0;
     flipmi::PcgState* h_ps = nullptr;
-    uint32_t* h_reseeded = nullptr;  // pinned copy of d_reseeded
+    uint32_t* h_words = nullptr;  // pinned landing of small readbacks (2 words)
     hipStream_t last_stream = nullptr;
     flip_step_stats stats{};
     // kernel timing

@@ -58,7 +58,7 @@ FLIP_BATCH_GRAPHS = 1
 EXPORTED = ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes", "flip_readback",
             "flip_stats", "flip_destroy", "flip_status_string", "flip_batch_workspace_bytes",
             "flip_batch_create", "flip_batch_step", "flip_batch_destroy", "flip_surface_field_bytes",
-            "flip_surface_field"]
+            "flip_surface_field", "flip_surface_mesh_workspace_bytes", "flip_surface_mesh"]
 
 
 class FlipError(RuntimeError):
@@ -127,9 +127,14 @@ def load():
         lib.flip_batch_destroy.restype = None
         lib.flip_surface_field_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
         lib.flip_surface_field.argtypes = [vp, ctypes.c_double, ctypes.c_double, i32, vp, sz, vp]
+        lib.flip_surface_mesh_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.flip_surface_mesh.argtypes = [vp, vp, i32, vp, sz, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, i64p,
+                                          i64p, vp]
         for name in ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes",
                      "flip_readback", "flip_stats", "flip_batch_workspace_bytes", "flip_batch_create",
-                     "flip_batch_step", "flip_surface_field_bytes", "flip_surface_field"]:
+                     "flip_batch_step", "flip_surface_field_bytes", "flip_surface_field",
+                     "flip_surface_mesh_workspace_bytes", "flip_surface_mesh"]:
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -350,6 +355,32 @@ class Simulation:
         phi = self.surface_field_device(radius, search, refine)
         self.stream.synchronize()
         return phi.cpu().numpy()
+
+    def surface_mesh_device(self, phi, refine: int = 1):
+        """Marching cubes (Sec. 3.3.2) of a device corner field from
+        surface_field_device: (vertices (nv, 3), normals (nv, 3), triangles
+        (nt, 3) int32) as device tensors."""
+        lib = load()
+        wb = ctypes.c_size_t(0)
+        _check(lib.flip_surface_mesh_workspace_bytes(self.h, int(refine), ctypes.byref(wb)),
+               "flip_surface_mesh_workspace_bytes")
+        if getattr(self, "_mc_work", None) is None or self._mc_work.numel() < wb.value:
+            self._mc_work = self.torch.empty(wb.value, dtype=self.torch.uint8, device=self.ws.device)
+        work = ctypes.c_void_p(self._mc_work.data_ptr())
+        st = ctypes.c_void_p(self.stream.cuda_stream)
+        nv, nt = ctypes.c_int64(0), ctypes.c_int64(0)
+        null = ctypes.c_void_p(0)
+        _check(lib.flip_surface_mesh(self.h, ctypes.c_void_p(phi.data_ptr()), int(refine), work, wb.value, null,
+                                     null, 0, null, 0, ctypes.byref(nv), ctypes.byref(nt), st),
+               "flip_surface_mesh (count)")
+        verts = self.torch.empty((nv.value, 3), dtype=phi.dtype, device=self.ws.device)
+        normals = self.torch.empty((nv.value, 3), dtype=phi.dtype, device=self.ws.device)
+        tris = self.torch.empty((nt.value, 3), dtype=self.torch.int32, device=self.ws.device)
+        _check(lib.flip_surface_mesh(self.h, ctypes.c_void_p(phi.data_ptr()), int(refine), work, wb.value,
+                                     ctypes.c_void_p(verts.data_ptr()), ctypes.c_void_p(normals.data_ptr()),
+                                     nv.value, ctypes.c_void_p(tris.data_ptr()), nt.value, ctypes.byref(nv),
+                                     ctypes.byref(nt), st), "flip_surface_mesh")
+        return verts, normals, tris
 
     def read_device(self, field: int):
         """Stream-ordered device-to-device readback into a new torch tensor of bytes."""
