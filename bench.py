@@ -197,7 +197,34 @@ def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plai
     }
 
 
-def measure(args, sc, solver: str) -> dict:
+def surface_timing(sim, cfg, torch, reps: int = 5) -> dict:
+    """Surface reconstruction on the handle's final state (Sec. 3.3): the
+    improved-blobby field at the grid's corners (particle radius dx/2, search
+    radius 2 dx; the call bins first) and marching cubes with vertex normals
+    (the call reads its counts back), each timed with HIP events on the
+    handle's stream over `reps` calls."""
+    dx = cfg.dx
+    st = sim.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    phi = sim.surface_field_device(0.5 * dx, 2 * dx, 1)
+    mesh = sim.surface_mesh_device(phi, 1)
+    st.synchronize()
+    ev[0].record(st)
+    for _ in range(reps):
+        phi = sim.surface_field_device(0.5 * dx, 2 * dx, 1)
+    ev[1].record(st)
+    for _ in range(reps):
+        mesh = sim.surface_mesh_device(phi, 1)
+    ev[2].record(st)
+    st.synchronize()
+    out = {"corners": phi.numel(), "field_ms": round(ev[0].elapsed_time(ev[1]) / reps, 3),
+           "mesh_ms": round(ev[1].elapsed_time(ev[2]) / reps, 3), "vertices": int(mesh[0].shape[0]),
+           "triangles": int(mesh[2].shape[0]), "radius": "dx/2", "search": "2 dx", "refine": 1}
+    progress(f"surface: {out}")
+    return out
+
+
+def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
     """Throughput of `args.steps` steps of scene sc on one handle (after
     `args.warmup`), then per-kernel durations on a second handle with kernel
     timing on. solver: "jacobi", "multigrid" (FLIP_FLAG_MULTIGRID) or "rbgs"
@@ -243,6 +270,7 @@ def measure(args, sc, solver: str) -> dict:
     if not args.reseed:
         particle_steps = n * args.steps
     progress(f"timed {args.steps} steps in {elapsed:.3f} s")
+    surface = surface_timing(sim, cfg, torch) if with_surface else None
     sim.close()
     del sim
     # kernel durations: a second handle of the same scene with kernel timing on
@@ -300,7 +328,7 @@ def measure(args, sc, solver: str) -> dict:
     sim.close()
     del sim
     return {"solver": solver, "n": n, "n0": s_pre.n_particles, "particle_steps": particle_steps,
-            "elapsed": elapsed, "roofline": roofline, "pcg": pcg, "stage_ms": stage_ms}
+            "elapsed": elapsed, "roofline": roofline, "pcg": pcg, "stage_ms": stage_ms, "surface": surface}
 
 
 def main():
@@ -328,6 +356,7 @@ def main():
                          "measured too and reported beside it), or rbgs: the paper's red-black "
                          "Gauss-Seidel solver alone")
     ap.add_argument("--no-second-solver", action="store_true", help="measure the headline solver only")
+    ap.add_argument("--no-surface", action="store_true", help="skip the surface reconstruction timing")
     ap.add_argument("--reseed", action="store_true",
                     help="particle reseeding on (Sec. 3.1.2): sparse fluid cells are refilled each step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -369,7 +398,8 @@ def main():
         solvers = ["rbgs"]
     if args.no_second_solver:
         solvers = solvers[:1]
-    runs = {name: measure(args, sc, name) for name in solvers}
+    runs = {name: measure(args, sc, name, with_surface=(name == solvers[0] and not args.no_surface))
+            for name in solvers}
     main_run = runs[solvers[0]]
     serving = None
     if args.serving_scenes > 0:
@@ -415,6 +445,7 @@ def main():
             "value": r["particle_steps"] / r["elapsed"], "unit": "particle-steps/s",
             "ms_per_step": r["elapsed"] / args.steps * 1e3, "roofline": r["roofline"], "pcg": r["pcg"],
             "kernel_ms_per_step": r["stage_ms"]}
+    line["surface"] = main_run["surface"]
     line["serving"] = serving
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
