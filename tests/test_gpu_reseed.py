@@ -99,7 +99,8 @@ def test_reseed_transfer_step_velocities(orc, prec):
     sim.close()
 
 
-@pytest.mark.parametrize("prec,flags", [(flip.FLIP_FP64, 0), (flip.FLIP_FP32, flip.FLIP_FLAG_MULTIGRID)])
+@pytest.mark.parametrize("prec,flags", [(flip.FLIP_FP64, 0), (flip.FLIP_FP32, flip.FLIP_FLAG_MULTIGRID),
+                                        (flip.FLIP_MIXED, 0)])
 def test_reseed_shadowed_splash_steps(orc, prec, flags):
     """A sphere dropping into a pool: each step the oracle, restarted from the
     GPU's state, reseeds and steps; ids and counts exact, velocities to 1e-4."""
