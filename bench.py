@@ -197,7 +197,7 @@ def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plai
     }
 
 
-def surface_timing(sim, cfg, torch, reps: int = 5) -> dict:
+def surface_timing(sim, cfg, torch, reps: int = 5, refine: int = 1) -> dict:
     """Surface reconstruction on the handle's final state (Sec. 3.3): the
     improved-blobby field at the grid's corners (particle radius dx/2, search
     radius 2 dx; the call bins first) and marching cubes with vertex normals
@@ -206,21 +206,39 @@ def surface_timing(sim, cfg, torch, reps: int = 5) -> dict:
     dx = cfg.dx
     st = sim.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    phi = sim.surface_field_device(0.5 * dx, 2 * dx, 1)
-    mesh = sim.surface_mesh_device(phi, 1)
+    phi = sim.surface_field_device(0.5 * dx, 2 * dx, refine)
+    mesh = sim.surface_mesh_device(phi, refine)
     st.synchronize()
     ev[0].record(st)
     for _ in range(reps):
-        phi = sim.surface_field_device(0.5 * dx, 2 * dx, 1)
+        phi = sim.surface_field_device(0.5 * dx, 2 * dx, refine)
     ev[1].record(st)
     for _ in range(reps):
-        mesh = sim.surface_mesh_device(phi, 1)
+        mesh = sim.surface_mesh_device(phi, refine)
     ev[2].record(st)
     st.synchronize()
     out = {"corners": phi.numel(), "field_ms": round(ev[0].elapsed_time(ev[1]) / reps, 3),
            "mesh_ms": round(ev[1].elapsed_time(ev[2]) / reps, 3), "vertices": int(mesh[0].shape[0]),
-           "triangles": int(mesh[2].shape[0]), "radius": "dx/2", "search": "2 dx", "refine": 1}
+           "triangles": int(mesh[2].shape[0]), "radius": "dx/2", "search": "2 dx", "refine": refine}
     progress(f"surface: {out}")
+    return out
+
+
+def surface_paper_workload(torch) -> dict:
+    """The water drop of the paper's marching-cubes timings (about 300 k
+    particles meshed on a 104^3 grid): a drop scene on a 52^3 simulation grid,
+    10 steps in, field and mesh at refine 2 (104^3 sampling cells)."""
+    import dataclasses
+
+    from paper_2404_01931_amd import flip, inputs
+
+    sc = dataclasses.replace(inputs.scene("drop64"), n=52, name="drop52")
+    cfg, keep = flip.scene_config(sc, flags=flip.FLIP_FLAG_MULTIGRID)
+    sim = flip.Simulation(cfg, keep)
+    sim.step(10)
+    out = surface_timing(sim, cfg, torch, refine=2)
+    out.update({"workload": f"drop52: {sim.n} particles, 52^3 simulation grid, 104^3 sampling grid, FP32"})
+    sim.close()
     return out
 
 
@@ -446,6 +464,8 @@ def main():
             "ms_per_step": r["elapsed"] / args.steps * 1e3, "roofline": r["roofline"], "pcg": r["pcg"],
             "kernel_ms_per_step": r["stage_ms"]}
     line["surface"] = main_run["surface"]
+    if line["surface"] is not None:
+        line["surface"]["paper_mc_workload"] = surface_paper_workload(torch)
     line["serving"] = serving
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
