@@ -513,7 +513,11 @@ flip_status run_step(flip_handle* h, hipStream_t st)
         HIP_TRY(hipMemcpyAsync(h->h_words, h->d_reseeded, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         const int64_t added = h->h_words[0];
-        if (n + added > s.pcap) return FLIP_E_WORKSPACE;  // nothing moved yet
+        if (n + added > s.pcap) {  // nothing moved yet
+            timer_end(h, tq, st);
+            (void)timer_collect(h, st);
+            return FLIP_E_WORKSPACE;
+        }
         launch_reseed_move<T>(g, sub, c.seed, (uint64_t)h->stats.steps, h->perm, h->key, h->start, h->count,
                               add, off, n, n + added, (const T*)h->pos[h->cur], (const T*)h->vel[h->cur],
                               h->id[h->cur], (T*)h->pos[nxt], (T*)h->vel[nxt], h->id[nxt], st);

@@ -137,13 +137,17 @@ def test_reseed_capacity_and_refusals(orc):
     pos = _uneven_blob(shape, dx, 9)
     n = pos.shape[1]
     vel = np.zeros_like(pos)
-    # no room for new particles: the step fails before moving anything
-    cfg, keep = flip.make_config(shape, dx, 1 / 240, pos0=pos, vel0=vel, flags=RS)
+    # no room for new particles: the step fails before moving anything (with
+    # kernel timing on, its timed launches are still collected)
+    cfg, keep = flip.make_config(shape, dx, 1 / 240, pos0=pos, vel0=vel, flags=RS | flip.FLIP_FLAG_KERNEL_TIMING)
     sim = flip.Simulation(cfg, keep)
     before = state(sim)
     with pytest.raises(flip.FlipError) as e:
         sim.step(1)
     assert e.value.status == flip.FLIP_E_WORKSPACE
+    st = sim.stats()
+    assert st.steps == 0 and st.n_reseeded == 0
+    assert st.kernel_launches[flip.KERNEL_NAMES.index("bin_keys")] == 1
     after = state(sim)
     assert sim.n == n
     for a, b in zip(before, after):
