@@ -4,6 +4,10 @@ against the oracle.
 The GPU meshes its own scalar field; the oracle meshes the same field (read
 back). Inside/outside decisions are taken on the same values, so the vertex
 count, the triangle count and every triangle's vertex indices must be equal.
+In FP64 the GPU's mesh is also compared end to end with the oracle's mesh of
+the oracle's own field; in FP32 the inside/outside decisions (integers decided
+by floating point) are taken on the kernel's FP32 values, so the comparison is
+made on the GPU's field.
 Vertices are bit-exact in FP64 (same operations) and within 4 FP32 roundings
 of the largest coordinate in FP32; vertex normals (summed with atomics) within 1e-9 in FP64; in FP32
 within 1e-5 + 8 (max vertex error) / (smallest altitude of a triangle at the
@@ -43,6 +47,15 @@ def _mesh_and_compare(orc, sim, refine):
     if fp64:
         assert np.array_equal(v, v_ref)
         assert en <= 1e-9
+        # end to end: the oracle's own field from the particle positions, then
+        # its mesh (the two fields differ by rounding, far from any sign change)
+        pos = sim.read(flip.FLIP_FIELD_POS).astype(np.float64)
+        phi_o = orc.surface_field(grid_of(sim), pos, 0.5 * dx, 2 * dx, refine)
+        v_o, n_o, t_o = orc.surface_mesh(grid_of(sim), phi_o, refine)
+        assert np.array_equal(t, t_o)
+        e2v, e2n = np.abs(v - v_o).max() / h, np.abs(n - n_o).max()
+        log(f"[mesh] against the oracle's own field: vertices {e2v:.2e} h, normals {e2n:.2e}")
+        assert e2v <= 1e-10 and e2n <= 1e-6
     else:
         # (I + t) h in FP32: a few roundings at the coordinate's magnitude
         assert ev <= 4 * 2.0**-24 * (np.abs(v_ref).max() + h)
