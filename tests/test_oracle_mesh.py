@@ -98,6 +98,50 @@ def test_single_inside_corner_vertices_worked_by_hand():
     assert np.allclose(nrm, n / np.linalg.norm(n))
 
 
+def test_inverse_area_vertex_normals_worked_by_hand():
+    """Sec. 3.3.2 weights each face normal at a vertex by the inverse of the
+    face's area. Two inside corners joined along x give one quad of crossing
+    vertices, split into two triangles of different areas and normals; at the
+    two vertices they share, normalise(n1/A1 + n2/A2) differs from the
+    area-weighted and the unweighted sums, so either slip fails here."""
+    g = O.Grid(1, 1, 1, 1.0)
+    phi = np.ones((2, 2, 2))   # phi[K, J, I]
+    phi[0, 0, 0] = -1.0        # corner (0,0,0) inside
+    phi[0, 0, 1] = -1.0        # corner (1,0,0) inside
+    phi[0, 1, 0] = 1.0         # (0,0,0) -> (0,1,0): t = 1/2
+    phi[1, 0, 0] = 3.0         # (0,0,0) -> (0,0,1): t = 1/4
+    phi[0, 1, 1] = 0.25        # (1,0,0) -> (1,1,0): t = 4/5
+    phi[1, 0, 1] = 1.0         # (1,0,0) -> (1,0,1): t = 1/2
+    v, nrm, tri = O.surface_mesh(g, phi)
+    # vertices in edge order (y and z edges of corner 0, then of corner 1)
+    P = np.array([[0, 0.5, 0], [0, 0, 0.25], [1, 0.8, 0], [1, 0, 0.5]])
+    assert np.allclose(v, P, atol=1e-15)
+    assert tri.shape == (2, 3)
+    assert sorted(set(tri.ravel().tolist())) == [0, 1, 2, 3]
+    shared = sorted(set(tri[0].tolist()) & set(tri[1].tolist()))
+    assert len(shared) == 2
+    # each triangle's cross product: twice its area times its unit normal
+    cr = [np.cross(P[t[1]] - P[t[0]], P[t[2]] - P[t[0]]) for t in tri]
+    area = [0.5 * np.linalg.norm(c) for c in cr]
+    unit = [c / np.linalg.norm(c) for c in cr]
+    assert abs(area[0] - area[1]) > 0.05 * max(area)
+    assert np.dot(unit[0], unit[1]) < 0.999
+
+    def nz(w):
+        return w / np.linalg.norm(w)
+
+    inv = nz(unit[0] / area[0] + unit[1] / area[1])
+    for s in shared:
+        assert np.allclose(nrm[s], inv, atol=1e-14)
+        assert np.linalg.norm(nrm[s] - nz(unit[0] * area[0] + unit[1] * area[1])) > 1e-3
+        assert np.linalg.norm(nrm[s] - nz(unit[0] + unit[1])) > 1e-3
+    for t in range(2):
+        for q in set(tri[t].tolist()) - set(shared):
+            assert np.allclose(nrm[q], unit[t], atol=1e-14)
+    # out of the fluid: the inside corners sit on the edge y = z = 0
+    assert np.all(nrm[:, 1] > 0) and np.all(nrm[:, 2] > 0)
+
+
 def test_plane_vertices_lie_on_the_plane():
     g = O.Grid(6, 5, 4, 0.25)
     x = np.arange(7) * 0.25

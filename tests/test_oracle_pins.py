@@ -217,6 +217,84 @@ def test_interpolation_reproduces_trilinear_fields(orc):
             assert abs(orc.interp(g, a, f, *p) - field(a, *p)) < 1e-12
 
 
+def _linear_face_fields(shape, dx, c0, B):
+    """Face arrays of the linear field c0[a] + B[a] . x sampled at each component's
+    staggered sample points (x-fastest), and the closed form itself."""
+    out = []
+    for a in range(3):
+        d = list(shape)
+        d[a] += 1
+        k, j, i = np.meshgrid(np.arange(d[2]), np.arange(d[1]), np.arange(d[0]), indexing="ij")
+        off = [0.5, 0.5, 0.5]
+        off[a] = 0.0
+        pts = [(i + off[0]) * dx, (j + off[1]) * dx, (k + off[2]) * dx]
+        out.append((c0[a] + B[a][0] * pts[0] + B[a][1] * pts[1] + B[a][2] * pts[2]).reshape(-1))
+    return out, (lambda a, p: c0[a] + B[a] @ p)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 0.95, 1.0])
+def test_pic_flip_blend_with_pic_unequal_flip(orc, alpha):
+    """Sec. 3.1.8: the new particle velocity blends the interpolated grid velocity
+    (PIC) and the particle's own velocity plus the interpolated change of the grid
+    (FLIP), v = (1 - alpha) PIC + alpha FLIP. The new and old grids are two
+    different linear fields, so PIC, the change and FLIP are closed forms at each
+    particle (trilinear interpolation reproduces linear fields), and the particles'
+    velocities are random, so PIC != FLIP everywhere: swapping alpha and
+    1 - alpha, blending another pair, or dropping the particle's own velocity
+    fails at alpha in {0, 0.95, 1}. Positions move with PIC (Sec. 3.1.3)."""
+    shape, dx = (10, 9, 8), 0.125
+    g = O.Grid(*shape, dx)
+    rng = np.random.default_rng(21)
+    c_new, B_new = rng.standard_normal(3), rng.standard_normal((3, 3))
+    c_old, B_old = rng.standard_normal(3), rng.standard_normal((3, 3))
+    unew, f_new = _linear_face_fields(shape, dx, c_new, B_new)
+    uold, f_old = _linear_face_fields(shape, dx, c_old, B_old)
+    n = 300
+    # interior points: no clamped stencil index, no skin clamp
+    pos = (1.5 + (np.array(shape)[:, None] - 3.0) * rng.random((3, n))) * dx
+    vel = rng.standard_normal((3, n))
+    dt = 1 / 512
+    pos_n, vel_n = orc.g2p_advect(g, pos, vel, unew, uold, alpha, dt)
+    for p in range(n):
+        x = pos[:, p]
+        for a in range(3):
+            pic = f_new(a, x)
+            flip = vel[a, p] + (f_new(a, x) - f_old(a, x))
+            assert abs(vel_n[a, p] - ((1.0 - alpha) * pic + alpha * flip)) < 1e-11
+            assert abs(pos_n[a, p] - (x[a] + dt * pic)) < 1e-13
+    # the blend is not degenerate here: PIC - FLIP = u_old(x) - v is O(1) at most particles
+    diff = [abs(vel[a, p] - f_old(a, pos[:, p])) for p in range(n) for a in range(3)]
+    assert np.median(diff) > 0.1
+    if alpha == 0.0:
+        # pure PIC: the particle's own velocity and the old grid drop out
+        pic_all = np.array([[f_new(a, pos[:, p]) for p in range(n)] for a in range(3)])
+        assert np.abs(vel_n - pic_all).max() < 1e-12
+
+
+def test_advect_with_blended_velocity_flag(orc):
+    """With the flag (reading of Sec. 3.1.3's x <- x + u dt with u the particle's
+    new velocity) positions move by dt times the blended velocity, not by the
+    grid velocity; velocities are the same blend either way."""
+    shape, dx = (8, 8, 8), 0.125
+    g = O.Grid(*shape, dx)
+    rng = np.random.default_rng(22)
+    unew, f_new = _linear_face_fields(shape, dx, rng.standard_normal(3), rng.standard_normal((3, 3)))
+    uold, f_old = _linear_face_fields(shape, dx, rng.standard_normal(3), rng.standard_normal((3, 3)))
+    n, alpha, dt = 200, 0.9, 1 / 256
+    pos = (1.5 + 5.0 * rng.random((3, n))) * dx
+    vel = rng.standard_normal((3, n))
+    pos_p, vel_p = orc.g2p_advect(g, pos, vel, unew, uold, alpha, dt, flags=O.ADVECT_PARTICLE_VEL)
+    pos_g, vel_g = orc.g2p_advect(g, pos, vel, unew, uold, alpha, dt)
+    assert np.array_equal(vel_p, vel_g)
+    for p in range(n):
+        x = pos[:, p]
+        for a in range(3):
+            v = (1 - alpha) * f_new(a, x) + alpha * (vel[a, p] + f_new(a, x) - f_old(a, x))
+            assert abs(pos_p[a, p] - (x[a] + dt * v)) < 1e-13
+            assert abs(pos_g[a, p] - (x[a] + dt * f_new(a, x))) < 1e-13
+    assert np.abs(pos_p - pos_g).max() > 1e-4
+
+
 # --------------------------------------------------------------------------
 # Operator and solve (paper Sec. 3.1.7)
 # --------------------------------------------------------------------------
