@@ -213,17 +213,29 @@ void orc_fluid_flags(const orc_grid* g, const uint32_t* count, uint8_t* fluid)
 /* particle reaches; addition order does not change the definition.         */
 /* ------------------------------------------------------------------------ */
 
-static double hat(double r)
+/* The two sample planes of one axis that bracket a particle's coordinate   */
+/* x, given the particle's cell c on that axis (the binning's exact floor): */
+/* plane lo at (lo + off) dx and plane lo + 1 one spacing above, off = 0 on  */
+/* the component's own axis (samples on cell faces, lo = c) and 1/2 on the  */
+/* two others (samples at cell-centre height, lo = c - 1 below the centre   */
+/* of the cell, else c). Between the two planes the hat of Eq. (4b) is      */
+/* 1 - |x / dx - (lo + off)| for plane lo, which equals the distance from x */
+/* to the other plane over dx: ((lo + 1 + off) dx - x) / dx, and likewise   */
+/* (x - (lo + off) dx) / dx for plane lo + 1. Each distance is x minus the  */
+/* exact product plane * dx, rounded once (fma), so a weight is zero        */
+/* exactly when the particle lies on the other plane, never by cancellation */
+/* (the hat of a tiny distance is 1 - r with r rounded near 1). max(0, .)   */
+/* keeps the support at a domain edge that rounding of n dx moved. Returns  */
+/* lo; w[0] is the weight of plane lo, w[1] that of plane lo + 1.           */
+static int bracket(double x, int c, double off, double dx, double w[2])
 {
-    if (0.0 <= r && r <= 1.0) return 1.0 - r;
-    if (-1.0 <= r && r < 0.0) return 1.0 + r;
-    return 0.0;
-}
-
-static double face_coord(const orc_grid* g, int a, int axis, int idx)
-{
-    double off = (axis == a) ? 0.0 : 0.5;
-    return (idx + off) * g->dx;
+    int lo = c;
+    if (off != 0.0 && fma(-((double)c + 0.5), dx, x) < 0.0) lo = c - 1;
+    const double below = fma(-((double)lo + off), dx, x);     /* x - plane lo     */
+    const double above = fma((double)lo + 1.0 + off, dx, -x); /* plane lo + 1 - x */
+    w[0] = above > 0.0 ? above / dx : 0.0;
+    w[1] = below > 0.0 ? below / dx : 0.0;
+    return lo;
 }
 
 void orc_p2g(const orc_grid* g, int a, int64_t n, const double* px, const double* py,
@@ -231,27 +243,25 @@ void orc_p2g(const orc_grid* g, int a, int64_t n, const double* px, const double
 {
     int d[3];
     face_dims(g, a, d);
+    const int nc[3] = {g->nx, g->ny, g->nz};
     const int64_t F = (int64_t)d[0] * d[1] * d[2];
     double* W = (double*)calloc((size_t)F, sizeof(double));
     double* M = (double*)calloc((size_t)F, sizeof(double));
     for (int64_t p = 0; p < n; ++p) {
         const double x[3] = {px[p], py[p], pz[p]};
+        /* the hat has support |r| < 1: only the two sample planes that     */
+        /* bracket the particle on each axis can receive a non-zero weight  */
         int base[3];
-        for (int ax = 0; ax < 3; ++ax) {
-            double off = (ax == a) ? 0.0 : 0.5;
-            base[ax] = (int)floor(x[ax] / g->dx - off);
-        }
-        /* the hat has support |r| < 1: only the two nearest sample planes on */
-        /* each axis can receive a non-zero weight                             */
+        double w[3][2];
+        for (int ax = 0; ax < 3; ++ax)
+            base[ax] = bracket(x[ax], exact_floor_div(x[ax], g->dx, nc[ax]), (ax == a) ? 0.0 : 0.5, g->dx, w[ax]);
         for (int dk = 0; dk <= 1; ++dk)
             for (int dj = 0; dj <= 1; ++dj)
                 for (int di = 0; di <= 1; ++di) {
                     int fi = base[0] + di, fj = base[1] + dj, fk = base[2] + dk;
                     if (fi < 0 || fi >= d[0] || fj < 0 || fj >= d[1] || fk < 0 || fk >= d[2])
                         continue;
-                    double k = hat((x[0] - face_coord(g, a, 0, fi)) / g->dx) *
-                               hat((x[1] - face_coord(g, a, 1, fj)) / g->dx) *
-                               hat((x[2] - face_coord(g, a, 2, fk)) / g->dx);
+                    double k = w[0][di] * w[1][dj] * w[2][dk];
                     int64_t f = face_index(d, fi, fj, fk);
                     W[f] += k;
                     M[f] += vel[p] * k;

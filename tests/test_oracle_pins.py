@@ -158,6 +158,60 @@ def test_p2g_matches_brute_force_definition(orc):
         np.testing.assert_allclose(got[a], _brute_p2g(shape, dx, pos, vel, a), rtol=1e-13, atol=1e-14)
 
 
+def test_p2g_support_decided_exactly_near_planes(orc):
+    """Eq. (4): a face receives weight from a particle iff the particle lies
+    strictly inside the hat's support, |x - x_f| < dx on every axis. Particles
+    on, one ulp below and one ulp above cell planes and cell-centre planes of a
+    non-dyadic spacing (1/20) are at rounding-level distances from the edge of
+    a support; the set of faces with W > 0 must still be the exact one (Python
+    Fractions), and where the exact weight sum is not tiny, W and the face
+    value must match it."""
+    shape, dx = (5, 4, 3), 1 / 20
+    g = O.Grid(*shape, dx)
+    rng = np.random.default_rng(31)
+    L = np.array(shape) * dx
+    n = 60
+    pos = np.empty((3, n))
+    for a in range(3):
+        planes = rng.integers(1, shape[a], n) * dx
+        centres = (rng.integers(0, shape[a], n) + 0.5) * dx
+        base = np.where(rng.random(n) < 0.5, planes, centres)
+        which = rng.integers(0, 3, n)
+        pos[a] = np.where(which == 0, base, np.where(which == 1, np.nextafter(base, -1), np.nextafter(base, 2)))
+        pos[a] = np.clip(pos[a], 0, L[a])
+    vel = rng.standard_normal((3, n))
+    faces, w = orc.p2g(g, pos, vel, return_weights=True)
+    fdx = Fraction(dx)
+    X = [[Fraction(float(pos[a, p])) for p in range(n)] for a in range(3)]
+
+    def hat(r):
+        return max(Fraction(0), 1 - abs(r))
+
+    for a in range(3):
+        d = list(shape)
+        d[a] += 1
+        for k in range(d[2]):
+            for j in range(d[1]):
+                for i in range(d[0]):
+                    off = [Fraction(1, 2)] * 3
+                    off[a] = Fraction(0)
+                    idx = (i, j, k)
+                    Wx = Mx = Fraction(0)
+                    for p in range(n):
+                        kk = Fraction(1)
+                        for b in range(3):
+                            kk *= hat(X[b][p] / fdx - (idx[b] + off[b]))
+                            if kk == 0:
+                                break
+                        Wx += kk
+                        Mx += Fraction(float(vel[a, p])) * kk
+                    f = i + d[0] * (j + d[1] * k)
+                    assert (w[a][f] > 0) == (Wx > 0), (a, i, j, k, float(Wx), w[a][f])
+                    if Wx > Fraction(1, 10**6):
+                        assert abs(w[a][f] - float(Wx)) <= 1e-14 * max(1.0, float(Wx))
+                        assert abs(faces[a][f] - float(Mx / Wx)) <= 1e-9 * max(1.0, abs(float(Mx / Wx)))
+
+
 def test_hat_weights_partition_of_unity_and_node_values(orc):
     g = O.Grid(6, 6, 6, 1 / 6)
     rng = np.random.default_rng(2)
