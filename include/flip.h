@@ -58,7 +58,11 @@ typedef enum {
     FLIP_E_WORKSPACE = -2,     /* workspace missing, too small or misaligned            */
     FLIP_E_HIP = -3,           /* a HIP runtime call failed                             */
     FLIP_E_NOT_CONVERGED = -4, /* PCG hit pcg_max_iters before the tolerance            */
-    FLIP_E_NONFINITE = -5,     /* PCG breakdown: non-positive or non-finite curvature   */
+    FLIP_E_NONFINITE = -5,     /* non-finite values: a solver breakdown (non-positive or
+                                  non-finite curvature, e.g. from a non-finite right-hand
+                                  side), or a particle position or velocity that became
+                                  NaN or infinite (latched by grid-to-particle, reported
+                                  by the next flip_step and by flip_stats)              */
     FLIP_E_STATE = -6          /* call not valid in the handle's current state          */
 } flip_status;
 
@@ -102,7 +106,7 @@ enum {
                                           start (one 8-byte readback per step); the step's dt
                                           is reported in flip_step_stats.dt. Needs cfl > 0;
                                           not in a batch (FLIP_E_INVALID)                     */
-    FLIP_FLAG_RESEED = 128u            /* particle reseeding (Sec. 3.1.2): after binning, each
+    FLIP_FLAG_RESEED = 128u,           /* particle reseeding (Sec. 3.1.2): after binning, each
                                           fluid cell holding k < sub^3 particles (sub =
                                           subcells_per_axis, which must be in [1, 16] also
                                           when pos0 is given) gets sub^3 - k new ones, one in
@@ -117,6 +121,16 @@ enum {
                                           A step that would exceed particle_capacity returns
                                           FLIP_E_WORKSPACE before moving any particle. Not in
                                           a batch (FLIP_E_INVALID)                            */
+    FLIP_FLAG_DIAGNOSTICS = 256u       /* after every step, evaluate in FP64 (whatever the
+                                          precision) and report in flip_step_stats: the true
+                                          residual max |b - A p| / max |b| of the pressure
+                                          solve (Sec. 3.1.7) from the b and p it used, the
+                                          divergence left by the projection max |div u_new| /
+                                          max |div u*| over fluid cells (Eq. (5)), the
+                                          particles' kinetic energy and largest speed (the
+                                          energy of Sec. 4; the CFL number of Sec. 3.1.4).
+                                          A few extra passes over the grid and the particles
+                                          per step; not in a batch (FLIP_E_INVALID)          */
 };
 
 typedef struct {
@@ -162,7 +176,10 @@ enum {
     FLIP_FIELD_U_NEW = 8,      /* real[Fu + Fv + Fw]: after projection                     */
     FLIP_FIELD_RHS = 9,        /* real[ncells]: b (0 off fluid); double for FLIP_MIXED      */
     FLIP_FIELD_PRESSURE = 10,  /* real[ncells]: p (0 off fluid); double for FLIP_MIXED      */
-    FLIP_FIELD_COUNT_ = 11
+    FLIP_FIELD_DIV = 11,       /* double[ncells]: divergence of u_new per fluid cell (sum of
+                                  its face differences over dx, Sec. 3.1.7), evaluated in
+                                  FP64 from the stored faces; 0 off fluid                   */
+    FLIP_FIELD_COUNT_ = 12
 };
 
 /* kernels that FLIP_FLAG_KERNEL_TIMING measures */
@@ -203,6 +220,16 @@ typedef struct {
     int64_t kernel_launches[FLIP_KERNEL_COUNT];/* number of timed launches                 */
     double dt;                     /* last step: the time step it took                     */
     int64_t n_reseeded;            /* last step: particles FLIP_FLAG_RESEED added          */
+    /* FLIP_FLAG_DIAGNOSTICS, last step (0 without the flag), evaluated in FP64:          */
+    double true_residual;          /* max |b - A p| / max |b| over fluid cells, b and p as
+                                      the solve left them (FLIP_MIXED: the FP64 ones)      */
+    double div_ratio;              /* max |div u_new| / max |div u*| over fluid cells       */
+    double kinetic_energy;         /* 1/2 sum |v|^2 over the particles (unit particle mass) */
+    double max_speed;              /* largest particle speed after the step                */
+    double cfl_number;             /* max_speed * dt / dx                                  */
+    int32_t nonfinite;             /* 1 once a particle position or velocity was not finite
+                                      (latched since init; with or without the flag)       */
+    int32_t pad_;
 } flip_step_stats;
 
 /* Device workspace needed for cfg (pure; used for HBM admission). */
@@ -210,7 +237,14 @@ flip_status flip_workspace_bytes(const flip_config* cfg, size_t* out_bytes);
 
 /* Validate cfg, carve the caller-owned device workspace d_ws (ws_bytes long,
  * 256-byte aligned), seed or upload the particles and return a handle.
- * Synchronises hip_stream before returning. */
+ * Seeding (Sec. 3.1.2, Fig. 3): every cell whose centre lies inside a region
+ * gets subcells_per_axis^3 particles, one at a uniformly random point of each
+ * of its jitter subcells (SplitMix64 of `seed`, element 3 * (sub^3 * cell +
+ * subcell) + axis, top 53 bits); or pos0 / vel0 give the particles (every
+ * position inside the domain, every velocity finite). Particle ids are the
+ * initial indices. Errors: FLIP_E_INVALID (configuration, or pos0 / vel0 out
+ * of range or not finite), FLIP_E_WORKSPACE (d_ws missing, too small or
+ * misaligned), FLIP_E_HIP. Synchronises hip_stream before returning. */
 flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void* hip_stream,
                       flip_handle** out);
 
@@ -226,7 +260,15 @@ flip_status flip_field_bytes(const flip_handle* h, int field, size_t* out_bytes)
 
 /* Copy a field into dst (dst_bytes >= flip_field_bytes). dst_is_device != 0:
  * dst is device memory and the copy is stream-ordered; otherwise dst is host
- * memory and the call synchronises hip_stream. */
+ * memory and the call synchronises hip_stream. Particles come in the binned
+ * order of the last step (the counting sort by cell of Sec. 3.1.5, stable:
+ * particles of a cell keep their previous order); FLIP_FIELD_ID maps them to
+ * their initial indices. Cell fields are the space hash of Sec. 3.1.5 (start
+ * offset and count per cell) and the fluid flags; face fields are the MAC
+ * grid samples of Sec. 3.1.1 before forces (U_OLD), after forces and walls
+ * (U_STAR) and after projection (U_NEW); RHS and PRESSURE the Poisson system
+ * of Sec. 3.1.7. The caller owns dst. Errors: FLIP_E_INVALID (null handle or
+ * dst, unknown field, dst_bytes too small), FLIP_E_HIP. */
 flip_status flip_readback(flip_handle* h, int field, void* dst, size_t dst_bytes, int dst_is_device,
                           void* hip_stream);
 
@@ -288,7 +330,10 @@ flip_status flip_surface_mesh(flip_handle* h, const void* d_phi, int refine, voi
                               int64_t max_triangles, int64_t* n_vertices, int64_t* n_triangles,
                               void* hip_stream);
 
-/* Statistics of the handle; synchronises the stream of the last step. */
+/* Statistics of the handle; synchronises the stream of the last step. A
+ * non-finite particle state latched on the device since the last check is
+ * reported here (nonfinite, and latched_status = FLIP_E_NONFINITE if no
+ * earlier error was latched). */
 flip_status flip_stats(flip_handle* h, flip_step_stats* out);
 
 /* Release the handle (not the workspace). NULL is ignored. */

@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libflipmi.so")
 SOURCES = ["kernels_bin.hip", "kernels_transfer.hip", "kernels_pressure.hip", "kernels_mg.hip",
-           "kernels_surface.hip", "capi.hip", "batch.hip"]
+           "kernels_surface.hip", "kernels_diag.hip", "capi.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

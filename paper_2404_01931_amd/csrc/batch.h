@@ -148,7 +148,7 @@ struct ProjectArgs {
     const V* p;
     const T* star;
     T* out;
-    T scale;
+    V scale;
 };
 
 template <typename T>
@@ -160,6 +160,7 @@ struct G2PArgs {
     const T *un, *vn, *wn, *uo, *vo, *wo;
     T alpha, dt, skin, Lx, Ly, Lz;
     int advect_particle_vel;
+    uint32_t* nonfinite;  // the scene's latch of non-finite particle state
 };
 
 // multigrid V-cycle (FLIP_FLAG_MULTIGRID)

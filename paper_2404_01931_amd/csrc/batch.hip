@@ -185,6 +185,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             q.Ly = (T)(g.ny * g.dx);
             q.Lz = (T)(g.nz * g.dx);
             q.advect_particle_vel = (c.flags & FLIP_FLAG_ADVECT_PARTICLE_VEL) ? 1 : 0;
+            q.nonfinite = &h->diagw->nonfinite;
             a2[s] = q;
             bp[s] = elem_blocks(n);
             bt[s] = (uint32_t)h->sz.T;
@@ -369,7 +370,7 @@ flip_status check_handles(flip_handle* const* handles, int nscenes, int* prec, b
         if (h->prec != FLIP_FP32 && h->prec != FLIP_FP64) return FLIP_E_INVALID;
         if (h->prec != handles[0]->prec) return FLIP_E_INVALID;
         if (h->cfg.flags &
-            (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING | FLIP_FLAG_RED_BLACK_GS | FLIP_FLAG_ADAPTIVE_DT |
+            (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING | FLIP_FLAG_DIAGNOSTICS | FLIP_FLAG_RED_BLACK_GS | FLIP_FLAG_ADAPTIVE_DT |
              FLIP_FLAG_RESEED))
             return FLIP_E_INVALID;
         // the preconditioner is the same for every scene of a batch

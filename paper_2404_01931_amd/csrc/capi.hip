@@ -277,6 +277,8 @@ void carve(flip_handle* h, Carver& cv)
     h->pslots = cv.take<double>(PCG_SLOT_SETS * sizeof(double) * solver_groups(s.T));
     h->ps = cv.take<PcgState>(PCG_STATE_BYTES + SYNC_BYTES);
     h->gs_rmax = cv.take<unsigned long long>(8);
+    h->diagw = cv.take<DiagWords>(sizeof(DiagWords));
+    h->diag_part = cv.take<double>(8 * DIAG_ENERGY_BLOCKS);
     h->d_reseeded = cv.take<uint32_t>(4);
     h->staging = cv.take<void>(8 * s.C);
 }
@@ -588,9 +590,13 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     // iteration kernels then issue their first loads without waiting for the
     // state) and skips the loop when the start already decided the solve.
     HIP_TRY(hipMemcpyAsync(h->h_ps, h->ps, sizeof(PcgState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&h->h_diag->nonfinite, &h->diagw->nonfinite, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           st));
     HIP_TRY(hipStreamSynchronize(st));
     ps_host = *h->h_ps;
     h->na = ps_host.n_active;
+    // particle state that an earlier step's grid-to-particle left non-finite
+    const bool nonfinite_before = h->h_diag->nonfinite != 0;
     int iters = 0, refinements = 0;
     const bool gs = (c.flags & FLIP_FLAG_RED_BLACK_GS) != 0;
     if (project && gs) {
@@ -633,7 +639,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
             if (MIXED)
                 launch_project<float, double>(g, a, h->diag, h->tile_slot, h->x64[h->xi],
                                               (const float*)h->f_star[a], (float*)h->f_new[a],
-                                              (float)scale, st);
+                                              dt / (c.density * c.dx), st);
             else
                 launch_project<T, T>(g, a, h->diag, h->tile_slot, (const T*)h->xin[h->xi],
                                      (const T*)h->f_star[a], (T*)h->f_new[a], scale, st);
@@ -650,10 +656,33 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     launch_g2p<T>(g, n, h->start, h->count, (T*)h->pos[h->cur], (T*)h->vel[h->cur], (const T*)h->f_new[0],
                   (const T*)h->f_new[1], (const T*)h->f_new[2], (const T*)h->f_old[0],
                   (const T*)h->f_old[1], (const T*)h->f_old[2], (T)c.flip_ratio, (T)dt,
-                  (c.flags & FLIP_FLAG_ADVECT_PARTICLE_VEL) ? 1 : 0, st);
+                  (c.flags & FLIP_FLAG_ADVECT_PARTICLE_VEL) ? 1 : 0, &h->diagw->nonfinite, st);
     timer_end(h, tq, st);
+
+    // 7. diagnostics, in FP64: the solve's true residual, the divergence the
+    // projection left, the particles' energy and largest speed
+    if (c.flags & FLIP_FLAG_DIAGNOSTICS) {
+        DiagWords* dw = h->diagw;
+        if (project && ps_host.n_active > 0) {
+            if (MIXED)
+                launch_gs_residual<double>(ps_host.n_active, h->tile_nbr, h->diag, h->b64, h->x64[h->xi], &dw->rmax,
+                                           st);
+            else
+                launch_gs_residual<T>(ps_host.n_active, h->tile_nbr, h->diag, (const T*)h->b,
+                                      (const T*)h->xin[h->xi], &dw->rmax, st);
+        } else {
+            launch_fill_u64((uint64_t*)&dw->rmax, 1, 0ull, st);
+        }
+        const T* fn[3] = {(const T*)h->f_new[0], (const T*)h->f_new[1], (const T*)h->f_new[2]};
+        const T* fs[3] = {(const T*)h->f_star[0], (const T*)h->f_star[1], (const T*)h->f_star[2]};
+        launch_div_max<T>(g, h->count, fn, fs, nullptr, dw->div_max, st);
+        launch_particle_energy<T>((const T*)h->vel[h->cur], n, h->diag_part, &dw->energy, &dw->speed2, st);
+        h->diag_dt = dt;
+        h->diag_valid = true;
+    }
     if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
 
+    if (nonfinite_before && ret == FLIP_OK) ret = FLIP_E_NONFINITE;
     const bool solved = ps_host.n_active > 0 && project;
     const int status = MIXED ? (ps_host.outer_done == 1 ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : 1))
                              : (ps_host.done == PCG_CONVERGED ? 0 : (ps_host.done == PCG_BREAKDOWN ? 2 : 1));
@@ -701,7 +730,7 @@ const char* flip_status_string(flip_status s)
         case FLIP_E_WORKSPACE: return "workspace missing, too small or misaligned";
         case FLIP_E_HIP: return "HIP runtime error";
         case FLIP_E_NOT_CONVERGED: return "PCG did not converge within pcg_max_iters";
-        case FLIP_E_NONFINITE: return "PCG breakdown (non-finite or non-positive curvature)";
+        case FLIP_E_NONFINITE: return "non-finite values (solver breakdown or non-finite particle state)";
         case FLIP_E_STATE: return "invalid state";
     }
     return "unknown status";
@@ -807,9 +836,11 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
     }
     launch_fill_bytes_zero(h->diag, s.cap, st);
     launch_fill_bytes_zero(h->ps, PCG_STATE_BYTES + SYNC_BYTES, st);
+    launch_fill_bytes_zero(h->diagw, sizeof(DiagWords), st);
     launch_fill_u64((uint64_t*)h->partials, 3 * h->groups, SLOT_EMPTY_BITS, st);
     if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&h->h_words, 2 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&h->h_words, 2 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_diag, sizeof(DiagWords), hipHostMallocDefault) != hipSuccess) {
         flip_destroy(h);
         return FLIP_E_HIP;
     }
@@ -864,6 +895,7 @@ flip_status flip_field_bytes(const flip_handle* h, int field, size_t* out_bytes)
         case FLIP_FIELD_U_NEW: *out_bytes = (s.F[0] + s.F[1] + s.F[2]) * s.rb; break;
         case FLIP_FIELD_RHS:
         case FLIP_FIELD_PRESSURE: *out_bytes = s.C * (h->prec == FLIP_MIXED ? 8 : s.rb); break;
+        case FLIP_FIELD_DIV: *out_bytes = s.C * 8; break;
         default: return FLIP_E_INVALID;
     }
     return FLIP_OK;
@@ -915,6 +947,19 @@ flip_status flip_readback(flip_handle* h, int field, void* dst, size_t dst_bytes
             else
                 launch_densify<float, float>(h->geo, h->tile_slot, h->diag, (const float*)src,
                                              (float*)h->staging, st);
+            HIP_TRY(hipMemcpyAsync(d, h->staging, need, kind, st));
+            break;
+        }
+        case FLIP_FIELD_DIV: {
+            if (h->prec == FLIP_FP64) {
+                const double* fn[3] = {(const double*)h->f_new[0], (const double*)h->f_new[1],
+                                       (const double*)h->f_new[2]};
+                launch_div_max<double>(h->geo, h->count, fn, fn, (double*)h->staging, nullptr, st);
+            } else {
+                const float* fn[3] = {(const float*)h->f_new[0], (const float*)h->f_new[1],
+                                      (const float*)h->f_new[2]};
+                launch_div_max<float>(h->geo, h->count, fn, fn, (double*)h->staging, nullptr, st);
+            }
             HIP_TRY(hipMemcpyAsync(d, h->staging, need, kind, st));
             break;
         }
@@ -1034,8 +1079,26 @@ flip_status flip_surface_mesh(flip_handle* h, const void* d_phi, int refine, voi
 flip_status flip_stats(flip_handle* h, flip_step_stats* out)
 {
     if (!h || !out) return FLIP_E_INVALID;
-    HIP_TRY(hipStreamSynchronize(h->last_stream));
-    *out = h->stats;
+    hipStream_t st = h->last_stream;
+    HIP_TRY(hipMemcpyAsync(h->h_diag, h->diagw, sizeof(DiagWords), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const DiagWords& d = *h->h_diag;
+    flip_step_stats& S = h->stats;
+    if (d.nonfinite) {
+        S.nonfinite = 1;
+        if (S.latched_status == 0) S.latched_status = FLIP_E_NONFINITE;
+    }
+    if (h->diag_valid) {
+        const double rmax = __builtin_bit_cast(double, d.rmax);
+        const double dn = __builtin_bit_cast(double, d.div_max[0]);
+        const double ds = __builtin_bit_cast(double, d.div_max[1]);
+        S.true_residual = S.max_b > 0.0 ? rmax / S.max_b : 0.0;
+        S.div_ratio = ds > 0.0 ? dn / ds : 0.0;
+        S.kinetic_energy = d.energy;
+        S.max_speed = std::sqrt(__builtin_bit_cast(double, d.speed2));
+        S.cfl_number = S.max_speed * h->diag_dt / h->cfg.dx;
+    }
+    *out = S;
     return FLIP_OK;
 }
 
@@ -1047,6 +1110,7 @@ void flip_destroy(flip_handle* h)
         if (e) (void)hipEventDestroy(e);
     if (h->h_ps) (void)hipHostFree(h->h_ps);
     if (h->h_words) (void)hipHostFree(h->h_words);
+    if (h->h_diag) (void)hipHostFree(h->h_diag);
     delete h;
 }
 

@@ -271,14 +271,14 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
 
 template <typename T, typename V>
 void launch_project(const Geo& g, int axis, const uint8_t* diag, const int32_t* tile_slot,
-                    const V* p, const T* star, T* out, T scale, hipStream_t st);
+                    const V* p, const T* star, T* out, V scale, hipStream_t st);
 
 // grid-to-particle: one workgroup per tile; start/count is the cell hash of
 // the binned particles
 template <typename T>
 void launch_g2p(const Geo& g, int64_t n, const uint32_t* start, const uint32_t* count, T* pos, T* vel,
                 const T* u_new, const T* v_new, const T* w_new, const T* u_old, const T* v_old,
-                const T* w_old, T alpha, T dt, int advect_particle_vel, hipStream_t st);
+                const T* w_old, T alpha, T dt, int advect_particle_vel, uint32_t* nonfinite, hipStream_t st);
 
 template <typename V, typename O>
 void launch_densify(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const V* src,
@@ -286,4 +286,30 @@ void launch_densify(const Geo& g, const int32_t* tile_slot, const uint8_t* diag,
 void launch_flags_from_count(const uint32_t* count, int64_t ncells, uint8_t* flags,
                              hipStream_t st);
 
+// ---- per-step diagnostics (FLIP_FLAG_DIAGNOSTICS), evaluated in FP64 ----
+
+// Device words of a handle's diagnostics: maxima as bits of non-negative
+// doubles, the energy sum, and the latch of non-finite particle state that
+// grid-to-particle sets (never cleared).
+struct DiagWords {
+    unsigned long long rmax;      // max |b - A p| over fluid cells
+    unsigned long long div_max[2];// max |div u_new|, max |div u*| over fluid cells
+    unsigned long long speed2;    // max |v|^2 over the particles
+    double energy;                // 1/2 sum |v|^2 over the particles
+    uint32_t nonfinite;           // 1 once a particle's state was not finite
+    uint32_t pad_;
+};
+constexpr int DIAG_ENERGY_BLOCKS = 512;  // workgroups (and partials) of the energy sum
+
+// the divergence of f_new per cell (over dx, 0 off fluid) into div_out when
+// non-null, and max |div| of f_new and f_star over fluid cells into
+// maxbits[0..1] when non-null
+template <typename T>
+void launch_div_max(const Geo& g, const uint32_t* count, const T* const f_new[3], const T* const f_star[3],
+                    double* div_out, unsigned long long* maxbits, hipStream_t st);
+// 1/2 sum |v|^2 into *energy (part: DIAG_ENERGY_BLOCKS doubles of scratch) and
+// max |v|^2 into *speed2
+template <typename T>
+void launch_particle_energy(const T* vel, int64_t n, double* part, double* energy, unsigned long long* speed2,
+                            hipStream_t st);
 }  // namespace flipmi

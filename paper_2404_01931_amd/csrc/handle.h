@@ -56,6 +56,8 @@ struct flip_handle {
     unsigned long long* gs_rmax = nullptr;  // FLIP_FLAG_RED_BLACK_GS: residual max (double bits)
     uint32_t* d_reseeded = nullptr;         // FLIP_FLAG_RESEED: new particles of the step
     flipmi::PcgState* ps = nullptr;
+    flipmi::DiagWords* diagw = nullptr;  // diagnostics and the non-finite latch
+    double* diag_part = nullptr;          // partial sums of the energy (DIAG_ENERGY_BLOCKS)
     void* staging = nullptr;
     // host side
     int cur = 0;
@@ -64,6 +66,9 @@ struct flip_handle {
     int prev_iters = 0;
     flipmi::PcgState* h_ps = nullptr;
     uint32_t* h_words = nullptr;  // pinned landing of small readbacks (2 words)
+    flipmi::DiagWords* h_diag = nullptr;  // pinned landing of the diagnostics
+    double diag_dt = 0.0;                 // dt of the step the diagnostics describe
+    bool diag_valid = false;              // diagnostics enqueued since init
     hipStream_t last_stream = nullptr;
     flip_step_stats stats{};
     // kernel timing

@@ -1207,7 +1207,7 @@ template <typename T, typename V, int A>
 __device__ __forceinline__ void project_body(Blk blk, Geo g, const uint8_t* __restrict__ diag,
                                              const int32_t* __restrict__ tile_slot,
                                              const V* __restrict__ p, const T* __restrict__ star,
-                                             T* __restrict__ out, T scale)
+                                             T* __restrict__ out, V scale)
 {
     // face counts stay below 2^32 (cells below 2^31): 32-bit index arithmetic
     const uint32_t dX = g.nx + (A == 0), dY = g.ny + (A == 1), dZ = g.nz + (A == 2);
@@ -1225,9 +1225,12 @@ __device__ __forceinline__ void project_body(Blk blk, Geo g, const uint8_t* __re
         const bool fp = tile_fluid(g, tile_slot, diag, p, i, j, k, vp);
         const bool fm = tile_fluid(g, tile_slot, diag, p, im, jm, km, vm);
         if (fp || fm) {
-            const T pp = fp ? (T)vp : T(0);
-            const T pm = fm ? (T)vm : T(0);
-            o = o - scale * (pp - pm);
+            // the pressure difference and its scaling in the solution's
+            // precision, rounded to the face precision once (mixed: the FP64
+            // solution's difference is not cut to FP32 before it cancels)
+            const V pp = fp ? vp : V(0);
+            const V pm = fm ? vm : V(0);
+            o = o - (T)(scale * (pp - pm));
         }
     }
     out[f] = o;
@@ -1237,7 +1240,7 @@ template <typename T, typename V, int A>
 __global__ __launch_bounds__(256) void k_project(Geo g, const uint8_t* __restrict__ diag,
                                                  const int32_t* __restrict__ tile_slot,
                                                  const V* __restrict__ p, const T* __restrict__ star,
-                                                 T* __restrict__ out, T scale)
+                                                 T* __restrict__ out, V scale)
 {
     project_body<T, V, A>(plain_blk(), g, diag, tile_slot, p, star, out, scale);
 }
@@ -1294,7 +1297,7 @@ void launch_b_summary(const BatchLaunch& L, hipStream_t st)
 
 template <typename T, typename V>
 void launch_project(const Geo& g, int axis, const uint8_t* diag, const int32_t* tile_slot,
-                    const V* p, const T* star, T* out, T scale, hipStream_t st)
+                    const V* p, const T* star, T* out, V scale, hipStream_t st)
 {
     const int64_t F = (int64_t)(g.nx + (axis == 0)) * (g.ny + (axis == 1)) * (g.nz + (axis == 2));
     const dim3 grid((unsigned)((F + 255) / 256)), block(256);
@@ -1312,7 +1315,7 @@ template void launch_project<double, double>(const Geo&, int, const uint8_t*, co
                                              const double*, const double*, double*, double,
                                              hipStream_t);
 template void launch_project<float, double>(const Geo&, int, const uint8_t*, const int32_t*,
-                                            const double*, const float*, float*, float,
+                                            const double*, const float*, float*, double,
                                             hipStream_t);
 
 // ---------------------------------------------------------------------------

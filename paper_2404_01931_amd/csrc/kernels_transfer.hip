@@ -1,11 +1,12 @@
 // Particle <-> grid transfers on the staggered MAC grid.
 //
-// Particle-to-grid (paper Sec. 3.1.6, Eq. (4)), in the gather form the paper
-// uses: one thread per face sample sums over the particles of the cells its
-// trilinear hat can reach, in a fixed order, so the result is deterministic and
-// needs no atomics. The kernel also applies the force step (gravity, Sec.
-// 2.1.3) and the solid-wall condition (zero normal velocity on the six domain
-// faces, Sec. 3.1.7), and keeps the raw transfer for the FLIP change.
+// Particle-to-grid (paper Sec. 3.1.6, Eq. (4)) as an LDS splat: the particles
+// of a block of cells and its one-cell ring are added into the block's face
+// samples in colour phases, so every sample sums its contributions in a fixed
+// order (deterministic, no atomics). The kernel also applies the force step
+// (gravity, Sec. 2.1.3) and the solid-wall condition (zero normal velocity on
+// the six domain faces, Sec. 3.1.7), and keeps the raw transfer for the FLIP
+// change.
 //
 // Grid-to-particle (Sec. 3.1.8) with forward-Euler advection and the skin-width
 // clamp (Sec. 3.1.3): one workgroup per tile, face samples staged in LDS.
@@ -59,13 +60,35 @@ struct P2GAdd {
 __device__ inline void lds_add(float* a, float v) { __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 __device__ inline void lds_add(double* a, double v) { __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 
-template <typename T, int A>
-__device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, double gy, double gz, T v)
+// The two sample planes of one axis that bracket coordinate x of a particle
+// in cell c (the binning's exact floor of x / dx) and their hat weights
+// (Eq. (4b)). Face axis (CENTRE false, samples on cell faces): planes c and
+// c + 1. Centre axis (samples at cell-centre height, plane p at (p + 1/2) dx):
+// planes c - 1 and c below the cell's centre, else c and c + 1. The weight
+// of a plane is the distance from x to the other plane of the pair over dx,
+// each distance x minus the exact product plane * dx rounded once (fma): a
+// weight is zero exactly when the particle lies on the other plane, so every
+// face receives a weight exactly when the exact hat is positive, whatever
+// the rounding of x / dx (a hat formed as 1 - r with r rounded near 1 could
+// vanish, and a face reached only by that particle would flip between 0 and
+// the particle's velocity in Eq. (4)). Returns the lower plane.
+template <bool CENTRE>
+__device__ inline int bracket(double x, int c, double dx, double inv_dx, double& w0, double& w1)
 {
-    // sample coordinates of this component (centre-aligned axes shifted by 1/2)
-    const double ax = A == 0 ? gx : gx - 0.5, ay = A == 1 ? gy : gy - 0.5, az = A == 2 ? gz : gz - 0.5;
-    const double fx = floor(ax), fy = floor(ay), fz = floor(az);
-    const int i0 = (int)fx - x0, j0 = (int)fy - y0, k0 = (int)fz - z0;
+    int lo = c;
+    if (CENTRE && fma(-((double)c + 0.5), dx, x) < 0.0) lo = c - 1;
+    const double off = CENTRE ? 0.5 : 0.0;
+    const double below = fma(-((double)lo + off), dx, x);       // x - plane lo
+    const double above = fma((double)lo + (1.0 + off), dx, -x);  // plane lo + 1 - x
+    w0 = above > 0.0 ? above * inv_dx : 0.0;
+    w1 = below > 0.0 ? below * inv_dx : 0.0;
+    return lo;
+}
+
+template <typename T, int A>
+__device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, int cx, int cy, int cz, double x, double y,
+                             double z, double dx, double inv_dx, T v)
+{
     constexpr int DX = P2G_T + (A == 0), DY = P2G_T + (A == 1), DZ = P2G_T + (A == 2);
     // FP32 (read-modify-write sums): samples outside the block's box get
     // weight 0 and the index of the nearest sample inside it, which lies
@@ -75,9 +98,10 @@ __device__ inline void splat(T (*acc)[2], int x0, int y0, int z0, double gx, dou
     // leaves a sum unchanged. FP64 (LDS-unit adds) skips those samples
     // instead: there the extra adds cost more than the branches.
     constexpr bool masked = !P2GAdd<T>::lds_unit;
-    // with r = a - floor(a) in [0, 1) the two hats are 1 - r and r
-    const double rx = ax - fx, ry = ay - fy, rz = az - fz;
-    double wx[2] = {1.0 - rx, rx}, wy[2] = {1.0 - ry, ry}, wz[2] = {1.0 - rz, rz};
+    double wx[2], wy[2], wz[2];
+    const int i0 = bracket<A != 0>(x, cx, dx, inv_dx, wx[0], wx[1]) - x0;
+    const int j0 = bracket<A != 1>(y, cy, dx, inv_dx, wy[0], wy[1]) - y0;
+    const int k0 = bracket<A != 2>(z, cz, dx, inv_dx, wz[0], wz[1]) - z0;
     int li[2], lj[2], lk[2];
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
@@ -176,40 +200,37 @@ struct Window {
     float W[NZ][NY][NX], M[NZ][NY][NX];
 };
 
-// the 1D weights of one axis over the window: 2 samples (face axis) or 3
-// (centre axis, the particle's pair at offset o = 0 or 1)
-// The hats are measured from the window's samples, not from floor(a): with a
-// spacing that is not a power of two, x * (1/dx) can land just below the
-// face a particle was binned across (the binning takes the exact floor of
-// x / dx), and the particle's weight then belongs to the window's sample.
+// the 1D weights of one axis over the window: 2 samples (face axis: c and
+// c + 1) or 3 (centre axis: c - 1 .. c + 1, of which the bracketing pair
+// gets the weights and the third sample 0). The planes come from the binned
+// cell, not from floor(x / dx): with a spacing that is not a power of two,
+// x * (1/dx) can land just below the face a particle was binned across.
 template <int N>
-__device__ inline void axis_weights(double a, int c, float (&w)[N])
+__device__ inline void axis_weights(double x, int c, double dx, double inv_dx, float (&w)[N])
 {
+    double w0, w1;
     if (N == 2) {
-        // face axis: samples c and c + 1 of a particle in cell c
-        const double r = a - (double)c;
-        w[0] = (float)(1.0 - r);
-        w[1] = (float)r;
+        (void)bracket<false>(x, c, dx, inv_dx, w0, w1);
+        w[0] = (float)w0;
+        w[1] = (float)w1;
     } else {
-        // centre axis, a = g - 1/2: the pair (c - 1, c) or (c, c + 1)
-        const bool up = floor(a) >= (double)c;
-        const double r = a - (double)(up ? c : c - 1);
-        const float lo = (float)(1.0 - r), hi = (float)r;
-        w[0] = up ? 0.0f : lo;
-        w[1] = up ? lo : hi;
-        w[N - 1] = up ? hi : 0.0f;
+        const bool up = bracket<true>(x, c, dx, inv_dx, w0, w1) == c;
+        w[0] = up ? 0.0f : (float)w0;
+        w[1] = up ? (float)w0 : (float)w1;
+        w[N - 1] = up ? (float)w1 : 0.0f;
     }
 }
 
 template <int A>
-__device__ inline void window_add(Window<A>& win, int cx, int cy, int cz, double gx, double gy, double gz, float v)
+__device__ inline void window_add(Window<A>& win, int cx, int cy, int cz, double x, double y, double z, double dx,
+                                  double inv_dx, float v)
 {
 #pragma clang fp contract(off)
     using Wn = Window<A>;
     float wx[Wn::NX], wy[Wn::NY], wz[Wn::NZ];
-    axis_weights<Wn::NX>(A == 0 ? gx : gx - 0.5, cx, wx);
-    axis_weights<Wn::NY>(A == 1 ? gy : gy - 0.5, cy, wy);
-    axis_weights<Wn::NZ>(A == 2 ? gz : gz - 0.5, cz, wz);
+    axis_weights<Wn::NX>(x, cx, dx, inv_dx, wx);
+    axis_weights<Wn::NY>(y, cy, dx, inv_dx, wy);
+    axis_weights<Wn::NZ>(z, cz, dx, inv_dx, wz);
 #pragma unroll
     for (int k = 0; k < Wn::NZ; ++k)
 #pragma unroll
@@ -276,7 +297,7 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
     const int rx0 = max(x0 - 1, 0), rx1 = min(x0 + P2G_T, g.nx - 1);
     const int ry0 = max(y0 - 1, 0), ry1 = min(y0 + P2G_T, g.ny - 1);
     const int rz0 = max(z0 - 1, 0), rz1 = min(z0 + P2G_T, g.nz - 1);
-    const double inv = g.inv_dx;
+    const double inv = g.inv_dx, dx = g.dx;
     if (n > 0) {
         // Software pipeline over the 27 phases: the cell range of phase
         // ph + 2 and the particles of phase ph + 1 are loaded while phase ph
@@ -306,22 +327,23 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
 #pragma unroll
                 for (int k = 0; k < P2G_BATCH; ++k) {
                     if ((uint32_t)k < n_a)
-                        window_add<A>(win, cxa, cya, cza, (double)P.x[k] * inv, (double)P.y[k] * inv, (double)P.z[k] * inv, P.v[k]);
+                        window_add<A>(win, cxa, cya, cza, (double)P.x[k], (double)P.y[k], (double)P.z[k], dx, inv,
+                                      P.v[k]);
                 }
                 // cells holding more particles than a batch: the rest one by one
                 for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
-                    window_add<A>(win, cxa, cya, cza, (double)px[q] * inv, (double)py[q] * inv, (double)pz[q] * inv, vc[q]);
+                    window_add<A>(win, cxa, cya, cza, (double)px[q], (double)py[q], (double)pz[q], dx, inv, vc[q]);
                 if (n_a > 0) window_flush<A>(win, acc, cxa, cya, cza, x0, y0, z0);
             } else {
 #pragma unroll
                 for (int k = 0; k < P2G_BATCH; ++k) {
                     if ((uint32_t)k < n_a)
-                        splat<T, A>(acc, x0, y0, z0, (double)P.x[k] * inv, (double)P.y[k] * inv,
-                                    (double)P.z[k] * inv, P.v[k]);
+                        splat<T, A>(acc, x0, y0, z0, cxa, cya, cza, (double)P.x[k], (double)P.y[k], (double)P.z[k],
+                                    dx, inv, P.v[k]);
                 }
                 for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
-                    splat<T, A>(acc, x0, y0, z0, (double)px[q] * inv, (double)py[q] * inv, (double)pz[q] * inv,
-                                vc[q]);
+                    splat<T, A>(acc, x0, y0, z0, cxa, cya, cza, (double)px[q], (double)py[q], (double)pz[q], dx,
+                                inv, vc[q]);
             }
             __builtin_amdgcn_wave_barrier();
             cxa = cxb;
@@ -546,7 +568,7 @@ __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restric
                                          const T* __restrict__ vn, const T* __restrict__ wn,
                                          const T* __restrict__ uo, const T* __restrict__ vo,
                                          const T* __restrict__ wo, T alpha, T dt, T skin, T Lx, T Ly,
-                                         T Lz, int advect_particle_vel)
+                                         T Lz, int advect_particle_vel, uint32_t* __restrict__ nonfinite)
 {
     __shared__ T box[3][2][G2P_BOX];
     __shared__ uint32_t row_start[64];
@@ -621,6 +643,12 @@ __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restric
         vx[p] = vnew[0];
         vy[p] = vnew[1];
         vz[p] = vnew[2];
+        // latch non-finite particle state for the host (a NaN or an infinity
+        // is never clamped back into the domain)
+        bool bad = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) bad = bad || !(fabs(out[a]) <= L[a]) || !isfinite(vnew[a]);
+        if (bad) atomicOr(nonfinite, 1u);
     }
 }
 
@@ -632,10 +660,11 @@ __global__ __launch_bounds__(G2P_NT) void k_g2p(Geo g, const uint32_t* __restric
                                                 const T* __restrict__ un, const T* __restrict__ vn,
                                                 const T* __restrict__ wn, const T* __restrict__ uo,
                                                 const T* __restrict__ vo, const T* __restrict__ wo, T alpha,
-                                                T dt, T skin, T Lx, T Ly, T Lz, int advect_particle_vel)
+                                                T dt, T skin, T Lx, T Ly, T Lz, int advect_particle_vel,
+                                                uint32_t* __restrict__ nonfinite)
 {
     g2p_body<T>(plain_blk(), g, start, count, px, py, pz, vx, vy, vz, un, vn, wn, uo, vo, wo, alpha, dt, skin,
-                Lx, Ly, Lz, advect_particle_vel);
+                Lx, Ly, Lz, advect_particle_vel, nonfinite);
 }
 
 template <typename T>
@@ -647,7 +676,7 @@ __global__ __launch_bounds__(G2P_NT) void kb_g2p(const G2PArgs<T>* __restrict__ 
     g2p_body<T>(b, a.g, as_global(a.start), as_global(a.count), as_global(a.px), as_global(a.py),
                 as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.un),
                 as_global(a.vn), as_global(a.wn), as_global(a.uo), as_global(a.vo), as_global(a.wo), a.alpha,
-                a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel);
+                a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel, as_global(a.nonfinite));
 }
 
 template <typename T>
@@ -662,22 +691,22 @@ template void launch_b_g2p<double>(const BatchLaunch&, hipStream_t);
 template <typename T>
 void launch_g2p(const Geo& g, int64_t n, const uint32_t* start, const uint32_t* count, T* pos, T* vel,
                 const T* u_new, const T* v_new, const T* w_new, const T* u_old, const T* v_old,
-                const T* w_old, T alpha, T dt, int advect_particle_vel, hipStream_t st)
+                const T* w_old, T alpha, T dt, int advect_particle_vel, uint32_t* nonfinite, hipStream_t st)
 {
     if (n <= 0) return;
     const T skin = (T)(1e-3 * g.dx);
     const T Lx = (T)(g.nx * g.dx), Ly = (T)(g.ny * g.dx), Lz = (T)(g.nz * g.dx);
     hipLaunchKernelGGL(k_g2p<T>, dim3((unsigned)tiles_of(g)), dim3(G2P_NT), 0, st, g, start, count, pos,
                        pos + n, pos + 2 * n, vel, vel + n, vel + 2 * n, u_new, v_new, w_new, u_old, v_old,
-                       w_old, alpha, dt, skin, Lx, Ly, Lz, advect_particle_vel);
+                       w_old, alpha, dt, skin, Lx, Ly, Lz, advect_particle_vel, nonfinite);
 }
 
 template void launch_g2p<float>(const Geo&, int64_t, const uint32_t*, const uint32_t*, float*, float*,
                                 const float*, const float*, const float*, const float*, const float*,
-                                const float*, float, float, int, hipStream_t);
+                                const float*, float, float, int, uint32_t*, hipStream_t);
 template void launch_g2p<double>(const Geo&, int64_t, const uint32_t*, const uint32_t*, double*, double*,
                                  const double*, const double*, const double*, const double*, const double*,
-                                 const double*, double, double, int, hipStream_t);
+                                 const double*, double, double, int, uint32_t*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // CFL time step (FLIP_FLAG_ADAPTIVE_DT, Sec. 3.1.4): the largest squared

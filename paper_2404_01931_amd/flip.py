@@ -34,6 +34,7 @@ FLIP_FLAG_MULTIGRID = 16
 FLIP_FLAG_RED_BLACK_GS = 32
 FLIP_FLAG_ADAPTIVE_DT = 64
 FLIP_FLAG_RESEED = 128
+FLIP_FLAG_DIAGNOSTICS = 256
 
 FLIP_FIELD_POS = 0
 FLIP_FIELD_VEL = 1
@@ -46,6 +47,7 @@ FLIP_FIELD_U_STAR = 7
 FLIP_FIELD_U_NEW = 8
 FLIP_FIELD_RHS = 9
 FLIP_FIELD_PRESSURE = 10
+FLIP_FIELD_DIV = 11
 
 KERNEL_NAMES = ["bin_keys", "bin_scan", "bin_scatter", "bin_gather", "tiles", "p2g", "rhs",
                 "pcg_direction", "pcg_update", "project", "g2p", "mg_down_fine", "mg_up_fine",
@@ -94,7 +96,10 @@ class flip_step_stats(ctypes.Structure):
                 ("pcg_iterations_total", ctypes.c_int64), ("pcg_cell_iterations_total", ctypes.c_int64),
                 ("latched_status", ctypes.c_int32), ("refinements", ctypes.c_int32), ("kernel_ms", ctypes.c_double * FLIP_KERNEL_COUNT),
                 ("kernel_launches", ctypes.c_int64 * FLIP_KERNEL_COUNT), ("dt", ctypes.c_double),
-                ("n_reseeded", ctypes.c_int64)]
+                ("n_reseeded", ctypes.c_int64), ("true_residual", ctypes.c_double),
+                ("div_ratio", ctypes.c_double), ("kinetic_energy", ctypes.c_double),
+                ("max_speed", ctypes.c_double), ("cfl_number", ctypes.c_double),
+                ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _lib = None
@@ -323,6 +328,8 @@ class Simulation:
         if field == FLIP_FIELD_FLAGS:
             return np.uint8
         if field in (FLIP_FIELD_RHS, FLIP_FIELD_PRESSURE) and self.cfg.precision == FLIP_MIXED:
+            return np.float64
+        if field == FLIP_FIELD_DIV:
             return np.float64
         return self.real
 

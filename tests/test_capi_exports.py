@@ -127,3 +127,26 @@ def test_batch_calls_reject_bad_arguments_without_gpu():
     assert b.value is None
     assert lib.flip_batch_step(None, 1, None) == flip.FLIP_E_INVALID
     lib.flip_batch_destroy(None)
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C layout (size and
+    the offset of the last field), checked by compiling the header with gcc."""
+    import shutil
+    import subprocess
+
+    from paper_2404_01931_amd import flip
+
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "flip.h"\nint main(void){'
+                   'printf("%zu %zu %zu %zu %zu\\n", sizeof(flip_config), sizeof(flip_step_stats), '
+                   'offsetof(flip_step_stats, nonfinite), sizeof(flip_region), '
+                   'offsetof(flip_config, particle_capacity));return 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert out == [ctypes.sizeof(flip.flip_config), ctypes.sizeof(flip.flip_step_stats),
+                   flip.flip_step_stats.nonfinite.offset, ctypes.sizeof(flip.flip_region),
+                   flip.flip_config.particle_capacity.offset]

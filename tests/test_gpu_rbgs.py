@@ -75,7 +75,7 @@ def test_red_black_gauss_seidel_solve_and_step_against_oracle(orc, case):
     assert np.array_equal(res.ids, ids1)
     ev = l2_rel(vel1, res.vel)
     log(f"[gs] {case}: step velocity error l2 {ev:.3e}")
-    assert ev <= (1e-8 if fp64 else 1e-3)
+    assert ev <= (1e-8 if fp64 else 1e-4)
     sim.close()
 
 
