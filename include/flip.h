@@ -330,6 +330,29 @@ flip_status flip_surface_mesh(flip_handle* h, const void* d_phi, int refine, voi
                               int64_t max_triangles, int64_t* n_vertices, int64_t* n_triangles,
                               void* hip_stream);
 
+/* ---- marching cubes without a caller workspace -----------------------------
+ *
+ * For callers that cannot allocate device memory (code that may not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation): the same
+ * call as flip_surface_mesh, with the same arguments, outputs, results and
+ * errors, but its scratch is a library-owned device array of
+ * FLIP_MESH_SCRATCH_MAX_BYTES per GPU (held from the first flip_init on that
+ * GPU until the process ends) instead of d_work. Nothing is allocated: no
+ * hipMalloc, no hipFree, no allocating library call.
+ * Limit: a sampling grid whose flip_surface_mesh_workspace_bytes exceeds
+ * FLIP_MESH_SCRATCH_MAX_BYTES (about two million corners, e.g. a 104^3
+ * sampling grid fits) returns FLIP_E_WORKSPACE before anything is enqueued.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (a call writes every scratch word before it reads it): calls that overlap on one GPU, on
+ * different streams or from different threads, race and must be serialised
+ * by the caller. The call synchronises hip_stream (it reads the counts back),
+ * so back-to-back calls on one stream are ordered. */
+#define FLIP_MESH_SCRATCH_MAX_BYTES ((size_t)64 << 20)
+flip_status flip_surface_mesh_noalloc(flip_handle* h, const void* d_phi, int refine, void* d_vertices,
+                                      void* d_normals, int64_t max_vertices, int32_t* d_triangles,
+                                      int64_t max_triangles, int64_t* n_vertices, int64_t* n_triangles,
+                                      void* hip_stream);
+
 /* Statistics of the handle; synchronises the stream of the last step. A
  * non-finite particle state latched on the device since the last check is
  * reported here (nonfinite, and latched_status = FLIP_E_NONFINITE if no

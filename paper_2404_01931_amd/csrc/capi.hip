@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -15,7 +16,40 @@
 
 using namespace flipmi;
 
+// Scratch of flip_surface_mesh_noalloc: the marching-cubes edge flags, vertex
+// numbers, per-cube counts and scan words live here instead of in a caller
+// workspace. Every device the library runs on holds its own copy for the life
+// of the process; host code reaches it only through the device address looked
+// up at flip_init (the array's name is not a device address on the host).
+constexpr size_t MC_SCRATCH_BYTES = (size_t)64 << 20;
+static_assert(MC_SCRATCH_BYTES == FLIP_MESH_SCRATCH_MAX_BYTES, "header and library agree on the limit");
+static __device__ __align__(256) unsigned char scratch[MC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[SCRATCH_MAX_DEVICES] = {};
+
+// Looks up (once per device, with that device current) and returns the device
+// address of this device's `scratch`.
+flip_status scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return FLIP_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev]) return FLIP_OK;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FLIP_E_HIP;
+    g_scratch[dev] = p;
+    return FLIP_OK;
+}
+
+void* scratch_of(int dev)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[dev];
+}
 
 constexpr size_t ALIGN = 256;
 constexpr int TIMED_PCG_EVERY = 8;  // with kernel timing on, one PCG iteration in 8 is bracketed
@@ -785,6 +819,11 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
         delete h;
         return FLIP_E_WORKSPACE;
     }
+    // set-up of the no-allocation entry points' device scratch on this device
+    if (hipGetDevice(&h->device) != hipSuccess || scratch_setup(h->device) != FLIP_OK) {
+        delete h;
+        return FLIP_E_HIP;
+    }
     Carver cv(d_ws);
     carve(h, cv);
     hipStream_t st = (hipStream_t)hip_stream;
@@ -1035,15 +1074,13 @@ flip_status flip_surface_mesh_workspace_bytes(const flip_handle* h, int refine, 
     return FLIP_OK;
 }
 
-flip_status flip_surface_mesh(flip_handle* h, const void* d_phi, int refine, void* d_work, size_t work_bytes,
-                              void* d_vertices, void* d_normals, int64_t max_vertices, int32_t* d_triangles,
-                              int64_t max_triangles, int64_t* n_vertices, int64_t* n_triangles, void* hip_stream)
+namespace {
+
+// marching cubes with its scratch at d_work (checked by the caller)
+flip_status mesh_body(flip_handle* h, const void* d_phi, int refine, void* d_work, void* d_vertices,
+                      void* d_normals, int64_t max_vertices, int32_t* d_triangles, int64_t max_triangles,
+                      int64_t* n_vertices, int64_t* n_triangles, void* hip_stream)
 {
-    if (!h || !d_phi || !d_work || !n_vertices || !n_triangles) return FLIP_E_INVALID;
-    size_t need = 0;
-    flip_status v = flip_surface_mesh_workspace_bytes(h, refine, &need);
-    if (v != FLIP_OK) return v;
-    if (work_bytes < need || ((uintptr_t)d_work & (ALIGN - 1))) return FLIP_E_WORKSPACE;
     const bool count_only = !d_vertices && !d_normals && !d_triangles;
     if (!count_only && (!d_vertices || !d_normals || !d_triangles)) return FLIP_E_INVALID;
     hipStream_t st = (hipStream_t)hip_stream;
@@ -1074,6 +1111,37 @@ flip_status flip_surface_mesh(flip_handle* h, const void* d_phi, int refine, voi
                               (float*)d_normals, d_triangles, st);
     if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
     return FLIP_OK;
+}
+
+}  // namespace
+
+flip_status flip_surface_mesh(flip_handle* h, const void* d_phi, int refine, void* d_work, size_t work_bytes,
+                              void* d_vertices, void* d_normals, int64_t max_vertices, int32_t* d_triangles,
+                              int64_t max_triangles, int64_t* n_vertices, int64_t* n_triangles, void* hip_stream)
+{
+    if (!h || !d_phi || !d_work || !n_vertices || !n_triangles) return FLIP_E_INVALID;
+    size_t need = 0;
+    flip_status v = flip_surface_mesh_workspace_bytes(h, refine, &need);
+    if (v != FLIP_OK) return v;
+    if (work_bytes < need || ((uintptr_t)d_work & (ALIGN - 1))) return FLIP_E_WORKSPACE;
+    return mesh_body(h, d_phi, refine, d_work, d_vertices, d_normals, max_vertices, d_triangles, max_triangles,
+                     n_vertices, n_triangles, hip_stream);
+}
+
+flip_status flip_surface_mesh_noalloc(flip_handle* h, const void* d_phi, int refine, void* d_vertices,
+                                      void* d_normals, int64_t max_vertices, int32_t* d_triangles,
+                                      int64_t max_triangles, int64_t* n_vertices, int64_t* n_triangles,
+                                      void* hip_stream)
+{
+    if (!h || !d_phi || !n_vertices || !n_triangles) return FLIP_E_INVALID;
+    size_t need = 0;
+    flip_status v = flip_surface_mesh_workspace_bytes(h, refine, &need);
+    if (v != FLIP_OK) return v;
+    if (need > MC_SCRATCH_BYTES) return FLIP_E_WORKSPACE;
+    void* work = scratch_of(h->device);
+    if (!work) return FLIP_E_HIP;
+    return mesh_body(h, d_phi, refine, work, d_vertices, d_normals, max_vertices, d_triangles, max_triangles,
+                     n_vertices, n_triangles, hip_stream);
 }
 
 flip_status flip_stats(flip_handle* h, flip_step_stats* out)

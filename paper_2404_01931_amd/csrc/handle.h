@@ -70,6 +70,7 @@ struct flip_handle {
     double diag_dt = 0.0;                 // dt of the step the diagnostics describe
     bool diag_valid = false;              // diagnostics enqueued since init
     hipStream_t last_stream = nullptr;
+    int device = -1;  // the HIP device current at flip_init
     flip_step_stats stats{};
     // kernel timing
     std::vector<hipEvent_t> ev;

@@ -60,7 +60,11 @@ FLIP_BATCH_GRAPHS = 1
 EXPORTED = ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes", "flip_readback",
             "flip_stats", "flip_destroy", "flip_status_string", "flip_batch_workspace_bytes",
             "flip_batch_create", "flip_batch_step", "flip_batch_destroy", "flip_surface_field_bytes",
-            "flip_surface_field", "flip_surface_mesh_workspace_bytes", "flip_surface_mesh"]
+            "flip_surface_field", "flip_surface_mesh_workspace_bytes", "flip_surface_mesh",
+            "flip_surface_mesh_noalloc"]
+
+# device scratch of flip_surface_mesh_noalloc per GPU (FLIP_MESH_SCRATCH_MAX_BYTES)
+FLIP_MESH_SCRATCH_MAX_BYTES = 64 << 20
 
 
 class FlipError(RuntimeError):
@@ -136,10 +140,12 @@ def load():
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.flip_surface_mesh.argtypes = [vp, vp, i32, vp, sz, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, i64p,
                                           i64p, vp]
+        lib.flip_surface_mesh_noalloc.argtypes = [vp, vp, i32, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, i64p,
+                                                  i64p, vp]
         for name in ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes",
                      "flip_readback", "flip_stats", "flip_batch_workspace_bytes", "flip_batch_create",
                      "flip_batch_step", "flip_surface_field_bytes", "flip_surface_field",
-                     "flip_surface_mesh_workspace_bytes", "flip_surface_mesh"]:
+                     "flip_surface_mesh_workspace_bytes", "flip_surface_mesh", "flip_surface_mesh_noalloc"]:
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -388,6 +394,30 @@ class Simulation:
                                      nv.value, ctypes.c_void_p(tris.data_ptr()), nt.value, ctypes.byref(nv),
                                      ctypes.byref(nt), st), "flip_surface_mesh")
         return verts, normals, tris
+
+    def surface_mesh_noalloc_device(self, phi, refine: int = 1, out=None):
+        """Marching cubes through flip_surface_mesh_noalloc (the library's own
+        device scratch instead of a workspace). With out = (vertices, normals,
+        triangles) preallocated device tensors the call writes into them and
+        returns them cut to the mesh's size; without, it counts first and
+        allocates the outputs here (the library call itself allocates nothing)."""
+        lib = load()
+        st = ctypes.c_void_p(self.stream.cuda_stream)
+        nv, nt = ctypes.c_int64(0), ctypes.c_int64(0)
+        null = ctypes.c_void_p(0)
+        if out is None:
+            _check(lib.flip_surface_mesh_noalloc(self.h, ctypes.c_void_p(phi.data_ptr()), int(refine), null, null, 0,
+                                                 null, 0, ctypes.byref(nv), ctypes.byref(nt), st),
+                   "flip_surface_mesh_noalloc (count)")
+            out = (self.torch.empty((nv.value, 3), dtype=phi.dtype, device=self.ws.device),
+                   self.torch.empty((nv.value, 3), dtype=phi.dtype, device=self.ws.device),
+                   self.torch.empty((nt.value, 3), dtype=self.torch.int32, device=self.ws.device))
+        verts, normals, tris = out
+        _check(lib.flip_surface_mesh_noalloc(self.h, ctypes.c_void_p(phi.data_ptr()), int(refine),
+                                             ctypes.c_void_p(verts.data_ptr()), ctypes.c_void_p(normals.data_ptr()),
+                                             verts.shape[0], ctypes.c_void_p(tris.data_ptr()), tris.shape[0],
+                                             ctypes.byref(nv), ctypes.byref(nt), st), "flip_surface_mesh_noalloc")
+        return verts[:nv.value], normals[:nv.value], tris[:nt.value]
 
     def read_device(self, field: int):
         """Stream-ordered device-to-device readback into a new torch tensor of bytes."""
