@@ -12,14 +12,19 @@ timing), the roofline figures of the dominant kernel (algorithmic bytes per
 launch over its average duration, from HIP events on a second handle of the
 same scene), a serving leg (a stream of independent scenes through the
 continuous-batching server, beside the plain path on the same scenes), and
-the FP64 oracle timed on the host as a CPU baseline. The headline uses the
-multigrid-preconditioned CG; the Jacobi-preconditioned CG on the same scene
-is measured too and reported beside it (`jacobi_pcg_same_scene`), with the
-roofline of its dominant kernel.
+the FP64 oracle timed on the host as a CPU baseline (one step of the same
+scene, one thread). The headline uses the multigrid-preconditioned CG; the
+Jacobi-preconditioned CG on the same scene is measured too and reported
+beside it (`jacobi_pcg_same_scene`), with the roofline of its dominant
+kernel. `precision_forms` reports the mixed-precision solve (FP32 vectors,
+FP64 reductions, refinement to 1e-8) against the FP64 solve to the same
+tolerance and the plain FP32 solve, each with its FP64 true residual and the
+divergence the projection leaves.
 
 Usage: python bench.py [--gpus 1] [--steps 30] [--warmup 3] [--scene drop256]
                        [--solver multigrid|jacobi] [--no-second-solver]
-                       [--serving-scenes 128] [--serving-only] [--no-cpu-baseline]
+                       [--serving-scenes 512] [--serving-only] [--no-cpu-baseline]
+                       [--no-precision-forms]
 """
 from __future__ import annotations
 
@@ -136,9 +141,23 @@ def cpu_baseline(sample_scene: str, steps: int):
         "unit": "particle-steps/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"{steps} FP64 oracle steps (serial C, MIC(0)-PCG to {sc.tol:g}, {iters} iterations) of "
-                   f"scene {sc.name} ({sc.n}^3, {n} particles) from its seeded start, {t:.1f} s"),
+        "sample": (f"{steps} FP64 oracle step{'s' if steps != 1 else ''} (serial C, one thread, MIC(0)-PCG to "
+                   f"{sc.tol:g}, {iters} iterations) of scene {sc.name} ({sc.n}^3, {n} particles) from its "
+                   f"seeded start, {t:.1f} s; the value is particles x steps / time"),
+        "host_cpu": host_cpu_model(),
+        "host_nproc": os.cpu_count(),
+        "threads": 1,
     }
+
+
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def serving_leg(n_scenes: int, budget_gib: float, slots: int, graphs: bool, plain_sample: int,
@@ -294,7 +313,10 @@ def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
     # kernel durations: a second handle of the same scene with kernel timing on
     # (HIP events; the solver kernels record their own start and end), stepped
     # through the same warm-up and a few more steps
-    cfg_t, keep_t = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING | sflag, capacity=cap)
+    # (diagnostics on: the solve's true residual and the divergence left, in
+    # FP64, by kernels outside the timed list)
+    cfg_t, keep_t = flip.scene_config(sc, flags=flip.FLIP_FLAG_KERNEL_TIMING | flip.FLIP_FLAG_DIAGNOSTICS | sflag,
+                                      capacity=cap)
     sim = flip.Simulation(cfg_t, keep_t)
     if args.warmup:
         sim.step(args.warmup)
@@ -337,6 +359,7 @@ def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
            "iterations_per_step_timing_run": d_iter / ts, "fluid_cells": round(fluid_avg),
            "last_residual_rel": s_last.max_r / s_last.max_b if s_last.max_b else 0.0,
            "refinements_last_step": s_last.refinements,
+           "true_residual_fp64": s1.true_residual, "div_ratio_fp64": s1.div_ratio,
            "algorithmic_GBps": round(pcg_bytes / (pcg_ms * 1e-3) / 1e9, 1) if pcg_ms else None,
            "frac_of_hbm_peak": round(pcg_bytes / (pcg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if pcg_ms else None,
            "ms_per_step": round(pcg_ms / ts, 3)}
@@ -349,6 +372,35 @@ def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
             "elapsed": elapsed, "roofline": roofline, "pcg": pcg, "stage_ms": stage_ms, "surface": surface}
 
 
+def precision_forms(args, headline: dict, sc) -> dict:
+    """The mixed-precision solve (FP32 vectors, FP64 reductions and residual,
+    iterative refinement to 1e-8) on the headline scene, against the plain FP64
+    solve to the same tolerance and the plain FP32 solve, each timed on the GPU
+    with its FP64 true residual and the divergence left after the projection."""
+    from paper_2404_01931_amd import inputs
+
+    def row(r, sc_r):
+        return {"value": r["particle_steps"] / r["elapsed"], "unit": "particle-steps/s",
+                "ms_per_step": r["elapsed"] / args.steps * 1e3,
+                "tolerance": sc_r.ir_tol if sc_r.precision == "mixed" else sc_r.tol,
+                "iterations_per_step": r["pcg"]["iterations_per_step"],
+                "refinements_last_step": r["pcg"]["refinements_last_step"],
+                "true_residual_fp64": r["pcg"]["true_residual_fp64"], "div_ratio_fp64": r["pcg"]["div_ratio_fp64"],
+                "pcg_ms_per_step": r["pcg"]["ms_per_step"]}
+
+    out = {"fp32": row(headline, sc)}
+    mixed = inputs.scene(sc.name + "_mixed") if sc.name + "_mixed" in inputs.SCENES else \
+        dataclasses.replace(sc, precision="mixed", tol=1e-4, ir_tol=1e-8)
+    progress(f"precision forms: {mixed.name} mixed")
+    out["mixed"] = row(measure(args, mixed, "multigrid"), mixed)
+    fp64 = dataclasses.replace(sc, name=sc.name + "_fp64", precision="fp64", tol=mixed.ir_tol)
+    progress(f"precision forms: {fp64.name} to {fp64.tol:g}")
+    out["fp64_same_tolerance"] = row(measure(args, fp64, "multigrid"), fp64)
+    out["note"] = ("mixed and fp64 solve to the same relative residual (1e-8); fp32 solves to 1e-6 on its "
+                   "recursive residual, its FP64 true residual is what FP32 vectors allow")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,12 +409,12 @@ def main():
     ap.add_argument("--scene", default="drop256")
     ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default=None,
                     help="override the scene's precision")
-    ap.add_argument("--cpu-sample", default="drop128")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-sample", default="drop256")
+    ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--timing-steps", type=int, default=10,
                     help="steps of the separate handle that times each kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-scenes", type=int, default=128,
+    ap.add_argument("--serving-scenes", type=int, default=512,
                     help="scenes of the serving stream to serve after the main benchmark (0: skip)")
     ap.add_argument("--serving-budget-gib", type=float, default=4.0)
     ap.add_argument("--serving-slots", type=int, default=128)
@@ -375,6 +427,8 @@ def main():
                          "Gauss-Seidel solver alone")
     ap.add_argument("--no-second-solver", action="store_true", help="measure the headline solver only")
     ap.add_argument("--no-surface", action="store_true", help="skip the surface reconstruction timing")
+    ap.add_argument("--no-precision-forms", action="store_true",
+                    help="skip the mixed-precision and FP64 solves of the headline scene")
     ap.add_argument("--reseed", action="store_true",
                     help="particle reseeding on (Sec. 3.1.2): sparse fluid cells are refilled each step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -419,6 +473,9 @@ def main():
     runs = {name: measure(args, sc, name, with_surface=(name == solvers[0] and not args.no_surface))
             for name in solvers}
     main_run = runs[solvers[0]]
+    forms = None
+    if not args.no_precision_forms and sc.precision == "fp32" and main_run["solver"] == "multigrid":
+        forms = precision_forms(args, main_run, sc)
     serving = None
     if args.serving_scenes > 0:
         serving = serving_leg(args.serving_scenes, args.serving_budget_gib, args.serving_slots,
@@ -466,6 +523,7 @@ def main():
     line["surface"] = main_run["surface"]
     if line["surface"] is not None:
         line["surface"]["paper_mc_workload"] = surface_paper_workload(torch)
+    line["precision_forms"] = forms
     line["serving"] = serving
     line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
