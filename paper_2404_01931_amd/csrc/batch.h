@@ -97,6 +97,7 @@ struct P2GArgs {
     int64_t n;
     const T *px, *py, *pz, *vx, *vy, *vz;
     const uint32_t *start, *count;
+    const uint32_t* tile_flag;  // the binning's 8^3 tiles holding a particle
     T gdt[3];
     T* old[3];
     T* star[3];

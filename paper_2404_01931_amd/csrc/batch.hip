@@ -155,6 +155,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             p.vz = vn + 2 * n;
             p.start = h->start;
             p.count = h->count;
+            p.tile_flag = h->tile_flag;
             for (int a = 0; a < 3; ++a) {
                 p.gdt[a] = (T)(grav ? c.gravity[a] * c.dt : 0.0);
                 p.old[a] = (T*)h->f_old[a];
@@ -292,6 +293,11 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
         for (int a = 0; a < 3; ++a) S.project[a] = add_site(t, pr[a], bf[a], ELEM_NT);
     }
     if (S.mg) {
+        // batched launches run every block of a level (no block lists)
+        auto unlisted = [](MgLevel lv) {
+            lv.uflag = lv.dlist = lv.ulist = lv.cnt = nullptr;
+            return lv;
+        };
         int L = 0;
         for (flip_handle* h : hs) L = std::max(L, h->nmg);
         S.mg_levels = L;
@@ -301,7 +307,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
         std::vector<uint32_t> btf(ns), bfine(ns), bbot(ns, 1u);
         for (size_t s = 0; s < ns; ++s) {
             flip_handle* h = hs[s];
-            const MgLevel& l0 = h->mg[0];
+            const MgLevel l0 = unlisted(h->mg[0]);
             tf[s] = MgTypesFineArgs{h->geo, h->tile_slot, h->diag, l0};
             btf[s] = (uint32_t)mg_blocks(MG_B_TYPES, l0, l0);
             fd[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, nullptr,
@@ -309,7 +315,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             fu[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, (T*)h->mgz,
                                   h->pslots, h->ps};
             bfine[s] = (uint32_t)h->groups;
-            bo[s] = MgPairArgs{h->mg[h->nmg - 1], h->mg[h->nmg - 1], h->ps};
+            bo[s] = MgPairArgs{unlisted(h->mg[h->nmg - 1]), unlisted(h->mg[h->nmg - 1]), h->ps};
         }
         S.mg_types_fine = add_site(t, tf, btf, 256);
         S.mg_fine_down = add_site(t, fd, bfine, 256);
@@ -322,8 +328,8 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             for (size_t s = 0; s < ns; ++s) {
                 flip_handle* h = hs[s];
                 const bool has = l + 1 < h->nmg;
-                const MgLevel& f = h->mg[has ? l : 0];
-                const MgLevel& c = h->mg[has ? l + 1 : 0];
+                const MgLevel f = unlisted(h->mg[has ? l : 0]);
+                const MgLevel c = unlisted(h->mg[has ? l + 1 : 0]);
                 a[s] = MgPairArgs{f, c, h->ps};
                 if (!has) continue;
                 bt[s] = (uint32_t)mg_blocks(MG_B_TYPES, f, c);

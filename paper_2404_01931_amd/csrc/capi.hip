@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/flip.h"
+#include "batch.h"
 #include "common.h"
 #include "handle.h"
 
@@ -220,6 +221,8 @@ Geo make_geo(const flip_config* c)
     g.tz = (c->nz + TILE - 1) / TILE;
     g.dx = c->dx;
     g.inv_dx = 1.0 / c->dx;
+    int e = 0;
+    g.dyadic = std::frexp(c->dx, &e) == 0.5 && e > -120 && e < 120;
     return g;
 }
 
@@ -293,13 +296,34 @@ void carve(flip_handle* h, Carver& cv)
             nz = (nz + 1) / 2;
             const int64_t cells = (int64_t)nx * ny * nz;
             MgLevel& L = h->mg[h->nmg++];
+            L = MgLevel{};
             L.nx = nx;
             L.ny = ny;
             L.nz = nz;
             L.b = cv.take<void>(cells * rb);
-            L.x = cv.take<void>(cells * rb);
             L.d = cv.take<uint8_t>(cells);
         } while ((nx > MG_BOTTOM_SIDE || ny > MG_BOTTOM_SIDE || nz > MG_BOTTOM_SIDE) && h->nmg < MG_MAX_LEVELS);
+        // cleared at every step, in one range: the solutions x (air cells
+        // hold 0; the blocks a plain launch skips are not written), the
+        // block marks and the block counts
+        const size_t zero_from = cv.off;
+        for (int l = 0; l < h->nmg; ++l) {
+            MgLevel& L = h->mg[l];
+            L.x = cv.take<void>((int64_t)L.nx * L.ny * L.nz * rb);
+        }
+        for (int l = 0; l < h->nmg; ++l) {
+            MgLevel& L = h->mg[l];
+            L.uflag = cv.take<uint32_t>(4 * mg_blocks(MG_B_UP, L, L));
+        }
+        h->mg_cnt = cv.take<uint32_t>(4 * 2 * MG_MAX_LEVELS);
+        h->mg_zero = cv.base ? cv.base + zero_from : nullptr;
+        h->mg_zero_bytes = cv.off - zero_from;
+        for (int l = 0; l < h->nmg; ++l) {
+            MgLevel& L = h->mg[l];
+            L.dlist = cv.take<uint32_t>(4 * mg_blocks(MG_B_DOWN, L, L));
+            L.ulist = cv.take<uint32_t>(4 * mg_blocks(MG_B_UP, L, L));
+            L.cnt = h->mg_cnt ? h->mg_cnt + 2 * l : nullptr;
+        }
     }
     if (h->prec == FLIP_MIXED) {
         h->xin[1] = cv.take<void>(s.cap * rb);
@@ -585,7 +609,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
         T* const old[3] = {(T*)h->f_old[0], (T*)h->f_old[1], (T*)h->f_old[2]};
         T* const star[3] = {(T*)h->f_star[0], (T*)h->f_star[1], (T*)h->f_star[2]};
         tq = timer_begin(h, FLIP_KERNEL_P2G, st);
-        launch_p2g<T>(g, pos, vel, n, h->start, h->count, gdt, old, star, st);
+        launch_p2g<T>(g, pos, vel, n, h->start, h->count, h->tile_flag, gdt, old, star, st);
         timer_end(h, tq, st);
     }
 
@@ -613,10 +637,13 @@ flip_status run_step(flip_handle* h, hipStream_t st)
                          (T*)h->z, (T*)h->xin[0], (T*)h->s[0], (T*)h->s[1], h->partials, G, h->ps,
                          project ? c.pcg_tol : 0.0, project ? max_iters : 0, h->nmg > 0 ? 1 : 0, st);
     timer_end(h, tq, st);
-    // cell types of the multigrid levels, from this step's fluid cells
+    // cell types of the multigrid levels, from this step's fluid cells, and
+    // the blocks of each level that hold a fluid cell
     if (h->nmg > 0 && project) {
+        launch_fill_bytes_zero(h->mg_zero, (int64_t)h->mg_zero_bytes, st);
         launch_mg_types_fine(g, h->tile_slot, h->diag, h->mg[0], st);
         for (int l = 0; l + 1 < h->nmg; ++l) launch_mg_types(h->mg[l], h->mg[l + 1], st);
+        HIP_TRY(hipMemcpyAsync(h->h_mgcnt, h->mg_cnt, 4 * 2 * h->nmg, hipMemcpyDeviceToHost, st));
     }
 
     // 4. PCG (FP32 inner solves inside FP64 refinement when MIXED). One read
@@ -629,6 +656,11 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     HIP_TRY(hipStreamSynchronize(st));
     ps_host = *h->h_ps;
     h->na = ps_host.n_active;
+    if (h->nmg > 0 && project)
+        for (int l = 0; l < h->nmg; ++l) {
+            h->mg[l].nd = (int)h->h_mgcnt[2 * l];
+            h->mg[l].nu = (int)h->h_mgcnt[2 * l + 1];
+        }
     // particle state that an earlier step's grid-to-particle left non-finite
     const bool nonfinite_before = h->h_diag->nonfinite != 0;
     int iters = 0, refinements = 0;
@@ -879,6 +911,7 @@ flip_status flip_init(const flip_config* cfg, void* d_ws, size_t ws_bytes, void*
     launch_fill_u64((uint64_t*)h->partials, 3 * h->groups, SLOT_EMPTY_BITS, st);
     if (hipHostMalloc((void**)&h->h_ps, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h->h_words, 2 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_mgcnt, 4 * 2 * MG_MAX_LEVELS, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&h->h_diag, sizeof(DiagWords), hipHostMallocDefault) != hipSuccess) {
         flip_destroy(h);
         return FLIP_E_HIP;
@@ -1178,6 +1211,7 @@ void flip_destroy(flip_handle* h)
         if (e) (void)hipEventDestroy(e);
     if (h->h_ps) (void)hipHostFree(h->h_ps);
     if (h->h_words) (void)hipHostFree(h->h_words);
+    if (h->h_mgcnt) (void)hipHostFree(h->h_mgcnt);
     if (h->h_diag) (void)hipHostFree(h->h_diag);
     delete h;
 }

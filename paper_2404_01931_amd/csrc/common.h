@@ -16,6 +16,10 @@ struct Geo {
     int nx, ny, nz;     // cells per axis
     int tx, ty, tz;     // tiles per axis (ceil(n / 8))
     double dx, inv_dx;
+    // 1 when dx is a power of two: then x / dx of an FP32 coordinate is exact
+    // in FP32, and so is its offset from the binned cell (kernels use FP32
+    // sample coordinates instead of FP64 ones, with identical results)
+    int dyadic;
 };
 
 // Solver state shared between the kernels of one solve. The start kernels
@@ -196,8 +200,8 @@ constexpr int P2G_NT = 192;
 int64_t p2g_blocks(const Geo& g);
 template <typename T>
 void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint32_t* start,
-                const uint32_t* count, const T gdt[3], T* const old[3], T* const star[3],
-                hipStream_t st);
+                const uint32_t* count, const uint32_t* tile_flag, const T gdt[3], T* const old[3],
+                T* const star[3], hipStream_t st);
 
 // right-hand side, solver start, and the two kernels of one PCG iteration.
 // All run `groups` persistent workgroups that split the active tiles among
@@ -246,6 +250,16 @@ struct MgLevel {
     void* b;
     void* x;
     uint8_t* d;
+    // Active blocks of the plain launches (null in batched launches, which run
+    // every block): the blocks of the restriction into this level (8 x 4 x 4
+    // cells) and of the prolongation into it (16 x 8 x 8) that hold a fluid
+    // cell, listed by the cell-type kernel; a block of air cells only would
+    // write values no later kernel reads (b) or zeros the step already holds (x).
+    uint32_t* uflag;  // per prolongation block: 1 once listed
+    uint32_t* dlist;  // listed restriction blocks, in no particular order
+    uint32_t* ulist;  // listed prolongation blocks
+    uint32_t* cnt;    // [0] restriction blocks listed, [1] prolongation blocks listed
+    int nd, nu;       // the counts, read back by the host before the solve
 };
 constexpr int MG_MAX_LEVELS = 32;
 constexpr int MG_BOTTOM_SIDE = 8;      // coarsen until every axis has at most 8 cells

@@ -115,6 +115,15 @@ __device__ inline void tile_range(Blk blk, int n_tiles, int& t0, int& t1)
 // a finite value, or +inf for inf and NaN (so a max over values flags both)
 __device__ inline double finite_or_inf(double a) { return (a <= DBL_MAX) ? a : INFINITY; }
 
+// The cell index of an FP32 coordinate when dx is a power of two: x / dx is
+// then exact in FP32 and so is its floor, so this equals exact_cell_floor
+// below (NaN maps to 0 there too).
+__device__ inline int dyadic_cell_floor(float x, float inv_dx, int n)
+{
+    const float q = floorf(x * inv_dx);
+    return (int)fminf(fmaxf(q, 0.0f), (float)(n - 1));
+}
+
 // Floor of the exact real quotient x / dx, clamped to [0, n-1]. The first
 // estimate comes from a rounded product; it is then corrected until
 // q*dx <= x < (q+1)*dx, each test evaluated with one fused multiply-add whose

@@ -51,6 +51,9 @@ struct flip_handle {
     void* mgz = nullptr;                       // FLIP_FLAG_MULTIGRID: z = M r
     flipmi::MgLevel mg[flipmi::MG_MAX_LEVELS] = {};  // coarse levels below the fine grid
     int nmg = 0;
+    uint32_t* mg_cnt = nullptr;     // block counts of every level (2 per level)
+    char* mg_zero = nullptr;        // the range cleared at each step (solutions, block marks, counts)
+    size_t mg_zero_bytes = 0;
     double* partials = nullptr;  // reduction slots of the start kernels (EMPTY when idle)
     double* pslots = nullptr;    // partial sums of the iteration kernels
     unsigned long long* gs_rmax = nullptr;  // FLIP_FLAG_RED_BLACK_GS: residual max (double bits)
@@ -66,6 +69,7 @@ struct flip_handle {
     int prev_iters = 0;
     flipmi::PcgState* h_ps = nullptr;
     uint32_t* h_words = nullptr;  // pinned landing of small readbacks (2 words)
+    uint32_t* h_mgcnt = nullptr;  // pinned landing of the multigrid block counts
     flipmi::DiagWords* h_diag = nullptr;  // pinned landing of the diagnostics
     double diag_dt = 0.0;                 // dt of the step the diagnostics describe
     bool diag_valid = false;              // diagnostics enqueued since init

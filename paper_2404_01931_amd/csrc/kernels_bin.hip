@@ -91,9 +91,17 @@ __device__ __forceinline__ void bin_keys_body(Blk b, Geo g, const T* __restrict_
 {
     const int64_t p = (int64_t)b.id * 256 + threadIdx.x;
     if (p >= n) return;
-    const int i = exact_cell_floor((double)px[p], g.dx, g.inv_dx, g.nx);
-    const int j = exact_cell_floor((double)py[p], g.dx, g.inv_dx, g.ny);
-    const int k = exact_cell_floor((double)pz[p], g.dx, g.inv_dx, g.nz);
+    int i, j, k;
+    if (sizeof(T) == 4 && g.dyadic) {  // FP32 positions, power-of-two spacing: the same index in FP32
+        const float inv = (float)g.inv_dx;
+        i = dyadic_cell_floor((float)px[p], inv, g.nx);
+        j = dyadic_cell_floor((float)py[p], inv, g.ny);
+        k = dyadic_cell_floor((float)pz[p], inv, g.nz);
+    } else {
+        i = exact_cell_floor((double)px[p], g.dx, g.inv_dx, g.nx);
+        j = exact_cell_floor((double)py[p], g.dx, g.inv_dx, g.ny);
+        k = exact_cell_floor((double)pz[p], g.dx, g.inv_dx, g.nz);
+    }
     const uint32_t c = (uint32_t)(i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
     key[p] = c;
 

@@ -63,61 +63,6 @@ __device__ inline MgLevel glob(MgLevel L)
 
 }  // namespace
 
-// ---- cell types of the coarse levels -----------------------------------------
-
-__device__ __forceinline__ void mg_types_fine_body(Blk b, const Geo& g, const int32_t* __restrict__ tile_slot,
-                                                   const uint8_t* __restrict__ diag, const MgLevel& c)
-{
-    const int64_t q = (int64_t)b.id * 256 + threadIdx.x;
-    if (q >= level_count(c)) return;
-    const int i = (int)(q % c.nx), j = (int)((q / c.nx) % c.ny), k = (int)(q / ((int64_t)c.nx * c.ny));
-    bool fluid = false;
-    for (int o = 0; o < 8; ++o) {
-        const int gi = 2 * i + (o & 1), gj = 2 * j + ((o >> 1) & 1), gk = 2 * k + (o >> 2);
-        if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
-        const int32_t s = tile_slot[(gi >> 3) + (int64_t)g.tx * ((gj >> 3) + (int64_t)g.ty * (gk >> 3))];
-        if (s >= 0 && diag[(int64_t)s * TILE_CELLS + (gi & 7) + 8 * (gj & 7) + 64 * (gk & 7)] > 0) fluid = true;
-    }
-    c.d[q] = fluid ? (uint8_t)level_nc(c, i, j, k) : (uint8_t)0;
-}
-
-__global__ __launch_bounds__(256) void k_mg_types_fine(Geo g, const int32_t* __restrict__ tile_slot,
-                                                       const uint8_t* __restrict__ diag, MgLevel c)
-{
-    mg_types_fine_body(plain_blk(), g, tile_slot, diag, c);
-}
-
-__global__ __launch_bounds__(256) void kb_mg_types_fine(const MgTypesFineArgs* __restrict__ tab,
-                                                        const uint32_t* __restrict__ first, int ns)
-{
-    Blk b;
-    const MgTypesFineArgs& a = batch_args(tab, first, ns, b);
-    mg_types_fine_body(b, a.g, as_global(a.tile_slot), as_global(a.diag), glob(a.c));
-}
-
-__device__ __forceinline__ void mg_types_body(Blk b, const MgLevel& f, const MgLevel& c)
-{
-    const int64_t q = (int64_t)b.id * 256 + threadIdx.x;
-    if (q >= level_count(c)) return;
-    const int i = (int)(q % c.nx), j = (int)((q / c.nx) % c.ny), k = (int)(q / ((int64_t)c.nx * c.ny));
-    bool fluid = false;
-    for (int o = 0; o < 8; ++o) {
-        const int fi = 2 * i + (o & 1), fj = 2 * j + ((o >> 1) & 1), fk = 2 * k + (o >> 2);
-        if (fi < f.nx && fj < f.ny && fk < f.nz && f.d[level_index(f, fi, fj, fk)] > 0) fluid = true;
-    }
-    c.d[q] = fluid ? (uint8_t)level_nc(c, i, j, k) : (uint8_t)0;
-}
-
-__global__ __launch_bounds__(256) void k_mg_types(MgLevel f, MgLevel c) { mg_types_body(plain_blk(), f, c); }
-
-__global__ __launch_bounds__(256) void kb_mg_types(const MgPairArgs* __restrict__ tab,
-                                                   const uint32_t* __restrict__ first, int ns)
-{
-    Blk b;
-    const MgPairArgs& a = batch_args(tab, first, ns, b);
-    mg_types_body(b, glob(a.f), glob(a.c));
-}
-
 // ---- transfers between dense levels ----------------------------------------------
 //
 // Between dense levels the prolongation is cell-centred trilinear: along each
@@ -196,8 +141,9 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
     __shared__ V ts[MGD_T];
     const int tid = threadIdx.x;
     const int gbx = mg_down_blocks_x(c), gby = mg_down_blocks_y(c);
-    const int cx0 = (blk.id % gbx) * MGD_CX, cy0 = ((blk.id / gbx) % gby) * MGD_CY;
-    const int cz0 = (blk.id / (gbx * gby)) * MGD_CZ;
+    const int bid = c.dlist ? (int)c.dlist[blk.id] : blk.id;  // plain launches: the listed blocks
+    const int cx0 = (bid % gbx) * MGD_CX, cy0 = ((bid / gbx) % gby) * MGD_CY;
+    const int cz0 = (bid / (gbx * gby)) * MGD_CZ;
     const int ox = 2 * cx0 - 2, oy = 2 * cy0 - 2, oz = 2 * cz0 - 2;  // u region origin on level f
     const V* const fb = (const V*)f.b;
     // this thread's column of the u region
@@ -376,8 +322,9 @@ __device__ __forceinline__ void mg_up_body(Blk blk, const MgLevel& f, const MgLe
     __shared__ uint8_t ds[MGU_Y];
     const int tid = threadIdx.x;
     const int gbx = mg_up_blocks_x(f), gby = mg_up_blocks_y(f);
-    const int fx0 = (blk.id % gbx) * MGU_FX, fy0 = ((blk.id / gbx) % gby) * MGU_FY;
-    const int fz0 = (blk.id / (gbx * gby)) * MGU_FZ;
+    const int bid = f.ulist ? (int)f.ulist[blk.id] : blk.id;  // plain launches: the listed blocks
+    const int fx0 = (bid % gbx) * MGU_FX, fy0 = ((bid / gbx) % gby) * MGU_FY;
+    const int fz0 = (bid / (gbx * gby)) * MGU_FZ;
     // coarse region origin: the parent of the y region's first cell, minus one
     const int px0 = fx0 / 2 - 2, py0 = fy0 / 2 - 2, pz0 = fz0 / 2 - 2;
     const V* const cx = (const V*)c.x;
@@ -481,6 +428,103 @@ __global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_up(const MgPairArgs* __rest
     mg_up_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
 }
 
+// ---- cell types of the coarse levels -----------------------------------------
+//
+// One wave per restriction block of level c (8 x 4 x 4 cells, two per lane):
+// the wave writes the cells' types and, for the plain launches, lists the
+// block when it holds a fluid cell, and lists the prolongation block
+// (16 x 8 x 8) that contains it the first time one of its restriction blocks
+// is listed.
+constexpr int MGT_WAVES = 4;  // waves (restriction blocks) per workgroup
+
+__host__ __device__ inline int64_t mg_types_groups(const MgLevel& c)
+{
+    return (mg_down_blocks(c) + MGT_WAVES - 1) / MGT_WAVES;
+}
+
+template <typename Fluid>
+__device__ __forceinline__ void mg_types_block(Blk b, const MgLevel& c, Fluid is_fluid)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t db = (int64_t)b.id * MGT_WAVES + (threadIdx.x >> 6);
+    const int nbx = mg_down_blocks_x(c), nby = mg_down_blocks_y(c);
+    const bool live = db < mg_down_blocks(c);
+    const int bx = (int)(db % nbx), by = (int)((db / nbx) % nby), bz = (int)(db / ((int64_t)nbx * nby));
+    bool any = false;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = lane + 64 * h;  // x fastest within the block
+        const int i = bx * MGD_CX + (e & 7), j = by * MGD_CY + ((e >> 3) & 3), k = bz * MGD_CZ + (e >> 5);
+        if (!live || i >= c.nx || j >= c.ny || k >= c.nz) continue;
+        const bool fluid = is_fluid(i, j, k);
+        c.d[level_index(c, i, j, k)] = fluid ? (uint8_t)level_nc(c, i, j, k) : (uint8_t)0;
+        any = any || fluid;
+    }
+    if (!c.dlist) return;  // uniform: batched launches list nothing
+    if (__ballot(any) != 0 && lane == 0) {
+        c.dlist[atomicAdd(c.cnt, 1u)] = (uint32_t)db;
+        const int ub = (bx * MGD_CX) / MGU_FX +
+                       mg_up_blocks_x(c) * ((by * MGD_CY) / MGU_FY + mg_up_blocks_y(c) * ((bz * MGD_CZ) / MGU_FZ));
+        if (atomicOr(&c.uflag[ub], 1u) == 0u) c.ulist[atomicAdd(c.cnt + 1, 1u)] = (uint32_t)ub;
+    }
+}
+
+// level 1 from the fine grid's n_c (tile layout): fluid when a child is
+__device__ __forceinline__ void mg_types_fine_body(Blk b, const Geo& g, const int32_t* __restrict__ tile_slot,
+                                                   const uint8_t* __restrict__ diag, const MgLevel& c)
+{
+    mg_types_block(b, c, [&](int i, int j, int k) {
+        bool fluid = false;
+        for (int o = 0; o < 8; ++o) {
+            const int gi = 2 * i + (o & 1), gj = 2 * j + ((o >> 1) & 1), gk = 2 * k + (o >> 2);
+            if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
+            const int32_t s = tile_slot[(gi >> 3) + (int64_t)g.tx * ((gj >> 3) + (int64_t)g.ty * (gk >> 3))];
+            if (s >= 0 && diag[(int64_t)s * TILE_CELLS + (gi & 7) + 8 * (gj & 7) + 64 * (gk & 7)] > 0) fluid = true;
+        }
+        return fluid;
+    });
+}
+
+__global__ __launch_bounds__(64 * MGT_WAVES) void k_mg_types_fine(Geo g, const int32_t* __restrict__ tile_slot,
+                                                                 const uint8_t* __restrict__ diag, MgLevel c)
+{
+    mg_types_fine_body(plain_blk(), g, tile_slot, diag, c);
+}
+
+__global__ __launch_bounds__(64 * MGT_WAVES) void kb_mg_types_fine(const MgTypesFineArgs* __restrict__ tab,
+                                                                  const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const MgTypesFineArgs& a = batch_args(tab, first, ns, b);
+    mg_types_fine_body(b, a.g, as_global(a.tile_slot), as_global(a.diag), glob(a.c));
+}
+
+// level c from level f: fluid when a child is
+__device__ __forceinline__ void mg_types_body(Blk b, const MgLevel& f, const MgLevel& c)
+{
+    mg_types_block(b, c, [&](int i, int j, int k) {
+        bool fluid = false;
+        for (int o = 0; o < 8; ++o) {
+            const int fi = 2 * i + (o & 1), fj = 2 * j + ((o >> 1) & 1), fk = 2 * k + (o >> 2);
+            if (fi < f.nx && fj < f.ny && fk < f.nz && f.d[level_index(f, fi, fj, fk)] > 0) fluid = true;
+        }
+        return fluid;
+    });
+}
+
+__global__ __launch_bounds__(64 * MGT_WAVES) void k_mg_types(MgLevel f, MgLevel c)
+{
+    mg_types_body(plain_blk(), f, c);
+}
+
+__global__ __launch_bounds__(64 * MGT_WAVES) void kb_mg_types(const MgPairArgs* __restrict__ tab,
+                                                             const uint32_t* __restrict__ first, int ns)
+{
+    Blk b;
+    const MgPairArgs& a = batch_args(tab, first, ns, b);
+    mg_types_body(b, glob(a.f), glob(a.c));
+}
+
 // ---- launchers -----------------------------------------------------------------
 
 namespace {
@@ -490,14 +534,13 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 void launch_mg_types_fine(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const MgLevel& c,
                           hipStream_t st)
 {
-    const int64_t n = (int64_t)c.nx * c.ny * c.nz;
-    hipLaunchKernelGGL(k_mg_types_fine, dim3(blocks_for(n)), dim3(256), 0, st, g, tile_slot, diag, c);
+    hipLaunchKernelGGL(k_mg_types_fine, dim3((unsigned)mg_types_groups(c)), dim3(64 * MGT_WAVES), 0, st, g,
+                       tile_slot, diag, c);
 }
 
 void launch_mg_types(const MgLevel& f, const MgLevel& c, hipStream_t st)
 {
-    const int64_t n = (int64_t)c.nx * c.ny * c.nz;
-    hipLaunchKernelGGL(k_mg_types, dim3(blocks_for(n)), dim3(256), 0, st, f, c);
+    hipLaunchKernelGGL(k_mg_types, dim3((unsigned)mg_types_groups(c)), dim3(64 * MGT_WAVES), 0, st, f, c);
 }
 
 template <typename V>
@@ -507,21 +550,27 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
     // 256^3) run 1024-thread workgroups, larger ones 512 (256 threads for
     // all: 1.69 ms per step for the coarse levels at 256^3; 1024 for the
     // small ones: 1.44; 512 for the 128^3 level: 1.32, where 1024 was slower)
+    // (the shape is chosen by the level's whole block count; the grid runs the
+    // listed blocks only)
     constexpr int64_t SMALL = 512;
     for (int l = 0; l + 1 < nlev; ++l) {
-        const int64_t nb = mg_down_blocks(lv[l + 1]);
+        const MgLevel& c = lv[l + 1];
+        const int64_t nb = mg_down_blocks(c), grid = c.dlist ? c.nd : nb;
+        if (grid <= 0) continue;
         if (nb < SMALL)
-            hipLaunchKernelGGL((k_mg_down<V, 1024>), dim3((unsigned)nb), dim3(1024), 0, st, lv[l], lv[l + 1], ps);
+            hipLaunchKernelGGL((k_mg_down<V, 1024>), dim3((unsigned)grid), dim3(1024), 0, st, lv[l], c, ps);
         else
-            hipLaunchKernelGGL((k_mg_down<V, 512>), dim3((unsigned)nb), dim3(512), 0, st, lv[l], lv[l + 1], ps);
+            hipLaunchKernelGGL((k_mg_down<V, 512>), dim3((unsigned)grid), dim3(512), 0, st, lv[l], c, ps);
     }
     hipLaunchKernelGGL(k_mg_bottom<V>, dim3(1), dim3(512), 0, st, lv[nlev - 1], ps);
     for (int l = nlev - 2; l >= 0; --l) {
-        const int64_t nb = mg_up_blocks(lv[l]);
+        const MgLevel& f = lv[l];
+        const int64_t nb = mg_up_blocks(f), grid = f.ulist ? f.nu : nb;
+        if (grid <= 0) continue;
         if (nb < SMALL)
-            hipLaunchKernelGGL((k_mg_up<V, 1024>), dim3((unsigned)nb), dim3(1024), 0, st, lv[l], lv[l + 1], ps);
+            hipLaunchKernelGGL((k_mg_up<V, 1024>), dim3((unsigned)grid), dim3(1024), 0, st, f, lv[l + 1], ps);
         else
-            hipLaunchKernelGGL((k_mg_up<V, 512>), dim3((unsigned)nb), dim3(512), 0, st, lv[l], lv[l + 1], ps);
+            hipLaunchKernelGGL((k_mg_up<V, 512>), dim3((unsigned)grid), dim3(512), 0, st, f, lv[l + 1], ps);
     }
 }
 
@@ -533,7 +582,7 @@ template void launch_mg_coarse<double>(const MgLevel*, int, const PcgState*, hip
 int64_t mg_blocks(int kind, const MgLevel& f, const MgLevel& c)
 {
     switch (kind) {
-    case MG_B_TYPES: return blocks_for((int64_t)c.nx * c.ny * c.nz);
+    case MG_B_TYPES: return mg_types_groups(c);
     case MG_B_DOWN: return mg_down_blocks(c);
     case MG_B_BOTTOM: return 1;
     default: return mg_up_blocks(f);  // MG_B_UP

@@ -221,16 +221,35 @@ __device__ inline void axis_weights(double x, int c, double dx, double inv_dx, f
     }
 }
 
+// The same weights when dx is a power of two, from f = x / dx - c, the
+// particle's offset in its binned cell in cell units: x / dx is a scaling by a
+// power of two and c <= x / dx < c + 1, so f is exact in FP32, and each weight
+// below is its exact value or one rounding of it - the values the FP64
+// bracket gives, with FP32 operations. A weight is clamped at 0 as there (a
+// non-finite coordinate gets weight 0 everywhere).
+template <int N>
+__device__ inline void axis_weights_dyadic(float f, float (&w)[N])
+{
+    if (N == 2) {
+        w[0] = fmaxf(1.0f - f, 0.0f);
+        w[1] = fmaxf(f, 0.0f);
+    } else {
+        const bool below = f < 0.5f;  // below the cell's centre: planes c - 1 and c
+        w[0] = fmaxf(0.5f - f, 0.0f);
+        w[1] = fmaxf(below ? 0.5f + f : 1.5f - f, 0.0f);
+        w[N - 1] = fmaxf(f - 0.5f, 0.0f);
+    }
+}
+
+// the particle's contribution to the window: W += w, M += v w for each of the
+// window's samples, w the product of the three axis weights
 template <int A>
-__device__ inline void window_add(Window<A>& win, int cx, int cy, int cz, double x, double y, double z, double dx,
-                                  double inv_dx, float v)
+__device__ inline void window_accumulate(Window<A>& win, const float (&wx)[Window<A>::NX],
+                                         const float (&wy)[Window<A>::NY], const float (&wz)[Window<A>::NZ],
+                                         float v)
 {
 #pragma clang fp contract(off)
     using Wn = Window<A>;
-    float wx[Wn::NX], wy[Wn::NY], wz[Wn::NZ];
-    axis_weights<Wn::NX>(x, cx, dx, inv_dx, wx);
-    axis_weights<Wn::NY>(y, cy, dx, inv_dx, wy);
-    axis_weights<Wn::NZ>(z, cz, dx, inv_dx, wz);
 #pragma unroll
     for (int k = 0; k < Wn::NZ; ++k)
 #pragma unroll
@@ -243,6 +262,31 @@ __device__ inline void window_add(Window<A>& win, int cx, int cy, int cz, double
                 win.M[k][j][i] = fma(v, w, win.M[k][j][i]);
             }
         }
+}
+
+// dyadic form: fx, fy, fz are the exact in-cell offsets
+template <int A>
+__device__ inline void window_add_dyadic(Window<A>& win, float fx, float fy, float fz, float v)
+{
+    using Wn = Window<A>;
+    float wx[Wn::NX], wy[Wn::NY], wz[Wn::NZ];
+    axis_weights_dyadic<Wn::NX>(fx, wx);
+    axis_weights_dyadic<Wn::NY>(fy, wy);
+    axis_weights_dyadic<Wn::NZ>(fz, wz);
+    window_accumulate<A>(win, wx, wy, wz, v);
+}
+
+template <int A>
+__device__ inline void window_add(Window<A>& win, int cx, int cy, int cz, double x, double y, double z, double dx,
+                                  double inv_dx, float v)
+{
+#pragma clang fp contract(off)
+    using Wn = Window<A>;
+    float wx[Wn::NX], wy[Wn::NY], wz[Wn::NZ];
+    axis_weights<Wn::NX>(x, cx, dx, inv_dx, wx);
+    axis_weights<Wn::NY>(y, cy, dx, inv_dx, wy);
+    axis_weights<Wn::NZ>(z, cz, dx, inv_dx, wz);
+    window_accumulate<A>(win, wx, wy, wz, v);
 }
 
 // add the window of cell (cx, cy, cz) to the block's samples; window samples
@@ -282,13 +326,37 @@ __device__ inline int64_t phase_cell(const Geo& g, int ph, int lane, int rx0, in
     return cx + (int64_t)g.nx * (cy + (int64_t)g.ny * cz);
 }
 
-// One wave of the workgroup: component A of the block's faces.
-template <typename T, int A>
+// Whether any 8^3 tile of the binning's tile flags that meets the ring box
+// [r0, r1] holds a particle (a box of at most 12 cells per axis meets at most
+// 3 tiles per axis; lane t < 27 reads one flag). A block whose ring box holds
+// no particle adds nothing to its samples.
+__device__ inline bool ring_has_particles(const Geo& g, const uint32_t* __restrict__ tile_flag, int lane, int rx0,
+                                          int ry0, int rz0, int rx1, int ry1, int rz1)
+{
+    const int tx = rx0 / TILE + lane % 3, ty = ry0 / TILE + (lane / 3) % 3, tz = rz0 / TILE + lane / 9;
+    bool any = false;
+    if (lane < 27 && tx <= rx1 / TILE && ty <= ry1 / TILE && tz <= rz1 / TILE)
+        any = tile_flag[tx + (int64_t)g.tx * (ty + (int64_t)g.ty * tz)] != 0u;
+    return __ballot(any) != 0;
+}
+
+// a particle's offset in its binned cell along one axis, in cells (exact
+// when dx is a power of two; see axis_weights_dyadic)
+__device__ inline float cell_offset(float x, float inv_dx, int c)
+{
+#pragma clang fp contract(off)
+    return x * inv_dx - (float)c;
+}
+
+// One wave of the workgroup: component A of the block's faces. DYADIC: dx is
+// a power of two (FP32 hat weights from exact in-cell offsets).
+template <typename T, int A, bool DYADIC>
 __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0, int y0, int z0,
                                               const T* __restrict__ px, const T* __restrict__ py,
                                               const T* __restrict__ pz, const T* __restrict__ vc,
                                               const uint32_t* __restrict__ start,
-                                              const uint32_t* __restrict__ count, T gdt, T (*acc)[2],
+                                              const uint32_t* __restrict__ count,
+                                              const uint32_t* __restrict__ tile_flag, T gdt, T (*acc)[2],
                                               T* __restrict__ f_old, T* __restrict__ f_star)
 {
 #pragma clang fp contract(off)
@@ -298,7 +366,7 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
     const int ry0 = max(y0 - 1, 0), ry1 = min(y0 + P2G_T, g.ny - 1);
     const int rz0 = max(z0 - 1, 0), rz1 = min(z0 + P2G_T, g.nz - 1);
     const double inv = g.inv_dx, dx = g.dx;
-    if (n > 0) {
+    if (n > 0 && ring_has_particles(g, tile_flag, lane, rx0, ry0, rz0, rx1, ry1, rz1)) {
         // Software pipeline over the 27 phases: the cell range of phase
         // ph + 2 and the particles of phase ph + 1 are loaded while phase ph
         // is splatted. The wave's LDS operations run in issue order, so the
@@ -324,15 +392,29 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
                     for (int j = 0; j < Window<A>::NY; ++j)
 #pragma unroll
                         for (int i = 0; i < Window<A>::NX; ++i) win.W[k][j][i] = win.M[k][j][i] = 0.0f;
+                if constexpr (DYADIC) {
+                    const float invf = (float)inv;
 #pragma unroll
-                for (int k = 0; k < P2G_BATCH; ++k) {
-                    if ((uint32_t)k < n_a)
-                        window_add<A>(win, cxa, cya, cza, (double)P.x[k], (double)P.y[k], (double)P.z[k], dx, inv,
-                                      P.v[k]);
+                    for (int k = 0; k < P2G_BATCH; ++k) {
+                        if ((uint32_t)k < n_a)
+                            window_add_dyadic<A>(win, cell_offset(P.x[k], invf, cxa), cell_offset(P.y[k], invf, cya),
+                                                 cell_offset(P.z[k], invf, cza), P.v[k]);
+                    }
+                    // cells holding more particles than a batch: the rest one by one
+                    for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
+                        window_add_dyadic<A>(win, cell_offset(px[q], invf, cxa), cell_offset(py[q], invf, cya),
+                                             cell_offset(pz[q], invf, cza), vc[q]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < P2G_BATCH; ++k) {
+                        if ((uint32_t)k < n_a)
+                            window_add<A>(win, cxa, cya, cza, (double)P.x[k], (double)P.y[k], (double)P.z[k], dx,
+                                          inv, P.v[k]);
+                    }
+                    for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
+                        window_add<A>(win, cxa, cya, cza, (double)px[q], (double)py[q], (double)pz[q], dx, inv,
+                                      vc[q]);
                 }
-                // cells holding more particles than a batch: the rest one by one
-                for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
-                    window_add<A>(win, cxa, cya, cza, (double)px[q], (double)py[q], (double)pz[q], dx, inv, vc[q]);
                 if (n_a > 0) window_flush<A>(win, acc, cxa, cya, cza, x0, y0, z0);
             } else {
 #pragma unroll
@@ -386,17 +468,17 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
 // three times as many waves resident as one wave doing all three.
 static_assert(P2G_NT == 3 * 64, "one wave per velocity component");
 
-template <typename T>
+template <typename T, bool DY>
 __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __restrict__ px, const T* __restrict__ py,
                                          const T* __restrict__ pz, const T* __restrict__ vx,
                                          const T* __restrict__ vy, const T* __restrict__ vz,
                                          const uint32_t* __restrict__ start,
-                                         const uint32_t* __restrict__ count, T gdt_x, T gdt_y, T gdt_z,
+                                         const uint32_t* __restrict__ count,
+                                         const uint32_t* __restrict__ tile_flag, T gdt_x, T gdt_y, T gdt_z,
                                          T* __restrict__ u_old, T* __restrict__ v_old,
                                          T* __restrict__ w_old, T* __restrict__ u_star,
-                                         T* __restrict__ v_star, T* __restrict__ w_star)
+                                         T* __restrict__ v_star, T* __restrict__ w_star, T (*acc)[P2G_BOX][2])
 {
-    __shared__ T acc[3][P2G_BOX][2];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // Rows of blocks (fixed y, z) are dealt to the 8 XCDs in turn (workgroup
     // b runs on XCD b % 8), and an XCD runs its row's blocks in x order, so
@@ -414,11 +496,22 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
     const int bx = L % nbx, by = (L / nbx) % nby, bz = L / (nbx * nby);
     const int x0 = bx * P2G_T, y0 = by * P2G_T, z0 = bz * P2G_T;
     if (wv == 0)
-        p2g_component<T, 0>(g, n, lane, x0, y0, z0, px, py, pz, vx, start, count, gdt_x, acc[0], u_old, u_star);
+        p2g_component<T, 0, DY>(g, n, lane, x0, y0, z0, px, py, pz, vx, start, count, tile_flag, gdt_x, acc[0], u_old, u_star);
     else if (wv == 1)
-        p2g_component<T, 1>(g, n, lane, x0, y0, z0, px, py, pz, vy, start, count, gdt_y, acc[1], v_old, v_star);
+        p2g_component<T, 1, DY>(g, n, lane, x0, y0, z0, px, py, pz, vy, start, count, tile_flag, gdt_y, acc[1], v_old, v_star);
     else
-        p2g_component<T, 2>(g, n, lane, x0, y0, z0, px, py, pz, vz, start, count, gdt_z, acc[2], w_old, w_star);
+        p2g_component<T, 2, DY>(g, n, lane, x0, y0, z0, px, py, pz, vz, start, count, tile_flag, gdt_z, acc[2], w_old, w_star);
+}
+
+// FP32 particles on a power-of-two spacing take the FP32 weights (the same values)
+template <typename T, typename... Args>
+__device__ __forceinline__ void p2g_dispatch(Blk b, const Geo& g, Args... args)
+{
+    __shared__ T acc[3][P2G_BOX][2];  // one LDS block for both forms
+    if (sizeof(T) == 4 && g.dyadic)
+        p2g_body<T, sizeof(T) == 4>(b, g, args..., acc);
+    else
+        p2g_body<T, false>(b, g, args..., acc);
 }
 
 template <typename T>
@@ -427,14 +520,15 @@ __global__ __launch_bounds__(P2G_NT) void k_p2g_tiles(Geo g, int64_t n, const T*
                                                   const T* __restrict__ vx, const T* __restrict__ vy,
                                                   const T* __restrict__ vz,
                                                   const uint32_t* __restrict__ start,
-                                                  const uint32_t* __restrict__ count, T gdt_x,
+                                                  const uint32_t* __restrict__ count,
+                                                  const uint32_t* __restrict__ tile_flag, T gdt_x,
                                                   T gdt_y, T gdt_z, T* __restrict__ u_old,
                                                   T* __restrict__ v_old, T* __restrict__ w_old,
                                                   T* __restrict__ u_star, T* __restrict__ v_star,
                                                   T* __restrict__ w_star)
 {
-    p2g_body<T>(plain_blk(), g, n, px, py, pz, vx, vy, vz, start, count, gdt_x, gdt_y, gdt_z, u_old, v_old,
-                w_old, u_star, v_star, w_star);
+    p2g_dispatch<T>(plain_blk(), g, n, px, py, pz, vx, vy, vz, start, count, tile_flag, gdt_x, gdt_y, gdt_z, u_old,
+                    v_old, w_old, u_star, v_star, w_star);
 }
 
 template <typename T>
@@ -443,18 +537,18 @@ __global__ __launch_bounds__(P2G_NT) void kb_p2g_tiles(const P2GArgs<T>* __restr
 {
     Blk b;
     const P2GArgs<T>& a = batch_args(tab, first, ns, b);
-    p2g_body<T>(b, a.g, a.n, as_global(a.px), as_global(a.py), as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.start), as_global(a.count), a.gdt[0], a.gdt[1], a.gdt[2],
+    p2g_dispatch<T>(b, a.g, a.n, as_global(a.px), as_global(a.py), as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.start), as_global(a.count), as_global(a.tile_flag), a.gdt[0], a.gdt[1], a.gdt[2],
                 as_global(a.old[0]), as_global(a.old[1]), as_global(a.old[2]), as_global(a.star[0]), as_global(a.star[1]), as_global(a.star[2]));
 }
 
 template <typename T>
 void launch_p2g(const Geo& g, const T* pos, const T* vel, int64_t n, const uint32_t* start,
-                const uint32_t* count, const T gdt[3], T* const old[3], T* const star[3],
-                hipStream_t st)
+                const uint32_t* count, const uint32_t* tile_flag, const T gdt[3], T* const old[3],
+                T* const star[3], hipStream_t st)
 {
     const unsigned tiles = (unsigned)p2g_blocks(g);
     hipLaunchKernelGGL(k_p2g_tiles<T>, dim3(tiles), dim3(P2G_NT), 0, st, g, n, pos, pos + n, pos + 2 * n, vel,
-                       vel + n, vel + 2 * n, start, count, gdt[0], gdt[1], gdt[2], old[0], old[1],
+                       vel + n, vel + 2 * n, start, count, tile_flag, gdt[0], gdt[1], gdt[2], old[0], old[1],
                        old[2], star[0], star[1], star[2]);
 }
 
@@ -469,10 +563,10 @@ template void launch_b_p2g<float>(const BatchLaunch&, hipStream_t);
 template void launch_b_p2g<double>(const BatchLaunch&, hipStream_t);
 
 template void launch_p2g<float>(const Geo&, const float*, const float*, int64_t, const uint32_t*,
-                                const uint32_t*, const float[3], float* const[3], float* const[3],
-                                hipStream_t);
+                                const uint32_t*, const uint32_t*, const float[3], float* const[3],
+                                float* const[3], hipStream_t);
 template void launch_p2g<double>(const Geo&, const double*, const double*, int64_t, const uint32_t*,
-                                 const uint32_t*, const double[3], double* const[3],
+                                 const uint32_t*, const uint32_t*, const double[3], double* const[3],
                                  double* const[3], hipStream_t);
 
 // ---------------------------------------------------------------------------
@@ -531,19 +625,44 @@ __device__ inline T trilerp(const T v[8], T tx, T ty, T tz)
     return lerp(lerp(c00, c10, ty), lerp(c01, c11, ty), tz);
 }
 
+// The lower sample index along one axis and the interpolation weight t of the
+// sample above it. CENTRE: samples at cell-centre height (plane p at
+// (p + 1/2) dx), else on cell faces. The sample coordinate x / dx - offset is
+// formed in double (see the particle-to-grid kernel). DYADIC (FP32, dx a power
+// of two): X = x / dx and its fraction f are exact in FP32, and t is f, f - 1/2
+// (exact) or f + 1/2 rounded once: the values the double form gives.
+template <typename T, bool CENTRE, bool DYADIC>
+__device__ inline int sample_coord(const Geo& g, T x, T& t)
+{
+    if constexpr (DYADIC) {
+        const float X = (float)x * (float)g.inv_dx;
+        const float c = floorf(X);
+        const float f = X - c;
+        if (!CENTRE) {
+            t = f;
+            return (int)c;
+        }
+        const bool above = f >= 0.5f;  // at or above the cell's centre
+        t = above ? f - 0.5f : f + 0.5f;
+        return (int)c - (above ? 0 : 1);
+    } else {
+        const double gx = (double)x * g.inv_dx - (CENTRE ? 0.5 : 0.0);
+        const double fx = floor(gx);
+        t = (T)(gx - fx);
+        return (int)fx;
+    }
+}
+
 // PIC value and FLIP change of component A at (x, y, z) from the staged box
-template <typename T, int A>
+template <typename T, int A, bool DYADIC>
 __device__ inline void sample_box(const Geo& g, int x0, int y0, int z0, const T* sn, const T* so, T x, T y, T z,
                                   T& pic, T& change)
 {
     using B = G2PBox<A>;
-    // sample coordinates in double (see the particle-to-grid kernel)
-    const double gx = (double)x * g.inv_dx - (A == 0 ? 0.0 : 0.5);
-    const double gy = (double)y * g.inv_dx - (A == 1 ? 0.0 : 0.5);
-    const double gz = (double)z * g.inv_dx - (A == 2 ? 0.0 : 0.5);
-    const double fx = floor(gx), fy = floor(gy), fz = floor(gz);
-    const T tx = (T)(gx - fx), ty = (T)(gy - fy), tz = (T)(gz - fz);
-    const int ix = (int)fx - (x0 - (A != 0)), iy = (int)fy - (y0 - (A != 1)), iz = (int)fz - (z0 - (A != 2));
+    T tx, ty, tz;
+    const int ix = sample_coord<T, A != 0, DYADIC>(g, x, tx) - (x0 - (A != 0));
+    const int iy = sample_coord<T, A != 1, DYADIC>(g, y, ty) - (y0 - (A != 1));
+    const int iz = sample_coord<T, A != 2, DYADIC>(g, z, tz) - (z0 - (A != 2));
     const int xa = min(max(ix, 0), B::EX - 1), xb = min(max(ix + 1, 0), B::EX - 1);
     const int ya = min(max(iy, 0), B::EY - 1), yb = min(max(iy + 1, 0), B::EY - 1);
     const int za = min(max(iz, 0), B::EZ - 1), zb = min(max(iz + 1, 0), B::EZ - 1);
@@ -560,7 +679,7 @@ __device__ inline void sample_box(const Geo& g, int x0, int y0, int z0, const T*
     change = trilerp(dv, tx, ty, tz);
 }
 
-template <typename T>
+template <typename T, bool DYADIC>
 __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restrict__ start,
                                          const uint32_t* __restrict__ count, T* __restrict__ px,
                                          T* __restrict__ py, T* __restrict__ pz, T* __restrict__ vx,
@@ -568,11 +687,9 @@ __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restric
                                          const T* __restrict__ vn, const T* __restrict__ wn,
                                          const T* __restrict__ uo, const T* __restrict__ vo,
                                          const T* __restrict__ wo, T alpha, T dt, T skin, T Lx, T Ly,
-                                         T Lz, int advect_particle_vel, uint32_t* __restrict__ nonfinite)
+                                         T Lz, int advect_particle_vel, uint32_t* __restrict__ nonfinite,
+                                         T (*box)[2][G2P_BOX], uint32_t* row_start, uint32_t* row_pre)
 {
-    __shared__ T box[3][2][G2P_BOX];
-    __shared__ uint32_t row_start[64];
-    __shared__ uint32_t row_pre[65];
     const int tid = threadIdx.x;
     // the workgroups of one XCD take one contiguous run of tiles, so the face
     // samples a tile shares with its neighbours are mostly read from that
@@ -617,9 +734,9 @@ __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restric
         const int64_t p = (int64_t)row_start[r] + (fi - row_pre[r]);
         const T x = px[p], y = py[p], z = pz[p];
         T pic[3], ch[3];
-        sample_box<T, 0>(g, x0, y0, z0, box[0][0], box[0][1], x, y, z, pic[0], ch[0]);
-        sample_box<T, 1>(g, x0, y0, z0, box[1][0], box[1][1], x, y, z, pic[1], ch[1]);
-        sample_box<T, 2>(g, x0, y0, z0, box[2][0], box[2][1], x, y, z, pic[2], ch[2]);
+        sample_box<T, 0, DYADIC>(g, x0, y0, z0, box[0][0], box[0][1], x, y, z, pic[0], ch[0]);
+        sample_box<T, 1, DYADIC>(g, x0, y0, z0, box[1][0], box[1][1], x, y, z, pic[1], ch[1]);
+        sample_box<T, 2, DYADIC>(g, x0, y0, z0, box[2][0], box[2][1], x, y, z, pic[2], ch[2]);
         const T v[3] = {vx[p], vy[p], vz[p]};
         T vnew[3];
 #pragma unroll
@@ -652,6 +769,20 @@ __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restric
     }
 }
 
+// FP32 particles on a power-of-two spacing take the FP32 sample coordinates
+// (the same values); one set of LDS buffers for both forms
+template <typename T, typename... Args>
+__device__ __forceinline__ void g2p_dispatch(Blk b, const Geo& g, Args... args)
+{
+    __shared__ T box[3][2][G2P_BOX];
+    __shared__ uint32_t row_start[64];
+    __shared__ uint32_t row_pre[65];
+    if (sizeof(T) == 4 && g.dyadic)
+        g2p_body<T, sizeof(T) == 4>(b, g, args..., box, row_start, row_pre);
+    else
+        g2p_body<T, false>(b, g, args..., box, row_start, row_pre);
+}
+
 template <typename T>
 __global__ __launch_bounds__(G2P_NT) void k_g2p(Geo g, const uint32_t* __restrict__ start,
                                                 const uint32_t* __restrict__ count, T* __restrict__ px,
@@ -663,8 +794,8 @@ __global__ __launch_bounds__(G2P_NT) void k_g2p(Geo g, const uint32_t* __restric
                                                 T dt, T skin, T Lx, T Ly, T Lz, int advect_particle_vel,
                                                 uint32_t* __restrict__ nonfinite)
 {
-    g2p_body<T>(plain_blk(), g, start, count, px, py, pz, vx, vy, vz, un, vn, wn, uo, vo, wo, alpha, dt, skin,
-                Lx, Ly, Lz, advect_particle_vel, nonfinite);
+    g2p_dispatch<T>(plain_blk(), g, start, count, px, py, pz, vx, vy, vz, un, vn, wn, uo, vo, wo, alpha, dt, skin,
+                    Lx, Ly, Lz, advect_particle_vel, nonfinite);
 }
 
 template <typename T>
@@ -673,7 +804,7 @@ __global__ __launch_bounds__(G2P_NT) void kb_g2p(const G2PArgs<T>* __restrict__ 
 {
     Blk b;
     const G2PArgs<T>& a = batch_args(tab, first, ns, b);
-    g2p_body<T>(b, a.g, as_global(a.start), as_global(a.count), as_global(a.px), as_global(a.py),
+    g2p_dispatch<T>(b, a.g, as_global(a.start), as_global(a.count), as_global(a.px), as_global(a.py),
                 as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.un),
                 as_global(a.vn), as_global(a.wn), as_global(a.uo), as_global(a.vo), as_global(a.wo), a.alpha,
                 a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel, as_global(a.nonfinite));
