@@ -386,11 +386,42 @@ void flip_destroy(flip_handle* h);
  * flip_batch_create. With FLIP_BATCH_GRAPHS the batch records its launch
  * sequences as HIP graphs (before the solve, a chunk of solver iterations,
  * after the solve) from its second step on and replays them; the graphs
- * are released by flip_batch_destroy. */
+ * are released by flip_batch_destroy.
+ *
+ * Slot batches (continuous batching): flip_batch_create_slots makes a batch
+ * of nslots empty slots; scenes join with flip_batch_attach and leave with
+ * flip_batch_detach between steps, and the batch is never rebuilt. Every
+ * launch of a slot batch runs a fixed grid whose workgroups loop over the
+ * workgroups of the scenes present (taken from the tables, which the next
+ * step rewrites with one host-to-device copy when the scenes changed), so the
+ * graphs recorded once are replayed whatever the scenes. A scene is stepped
+ * exactly as in a batch built for it (the same per-scene grid, work split and
+ * reduction order), so its results are again bitwise those of flip_step. */
 enum { FLIP_BATCH_MAX_SCENES = 256 };
-enum { FLIP_BATCH_GRAPHS = 1u };
+enum { FLIP_BATCH_GRAPHS = 1u, FLIP_BATCH_MULTIGRID = 2u };
 
 typedef struct flip_batch flip_batch;
+
+/* Shape of a slot batch: nslots in 1 .. FLIP_BATCH_MAX_SCENES; precision
+ * FLIP_FP32 or FLIP_FP64; flags FLIP_BATCH_GRAPHS and FLIP_BATCH_MULTIGRID
+ * (the scenes' preconditioner: set exactly when they use
+ * FLIP_FLAG_MULTIGRID); the largest grid a scene may have (it sets the
+ * multigrid levels the launch sequence covers). */
+typedef struct {
+    int nslots;
+    int precision;
+    uint32_t flags;
+    int max_nx, max_ny, max_nz;
+} flip_batch_slots;
+
+/* Counters of a batch since its creation. */
+typedef struct {
+    int64_t steps;           /* batched steps taken                                  */
+    int64_t graph_launches;  /* recorded graphs replayed                             */
+    int64_t graph_captures;  /* graphs recorded                                      */
+    int64_t table_uploads;   /* table copies (at creation, and after scene changes)   */
+    int nslots, occupied;    /* slots, and slots holding a scene                     */
+} flip_batch_info;
 
 /* Device workspace needed by a batch of these handles. */
 flip_status flip_batch_workspace_bytes(flip_handle* const* handles, int nscenes, size_t* out_bytes);
@@ -399,6 +430,33 @@ flip_status flip_batch_workspace_bytes(flip_handle* const* handles, int nscenes,
  * synchronised before returning) and return the batch. flags: FLIP_BATCH_*. */
 flip_status flip_batch_create(flip_handle* const* handles, int nscenes, uint32_t flags, void* d_ws,
                               size_t ws_bytes, void* hip_stream, flip_batch** out);
+
+/* Device workspace of a slot batch of this shape (FLIP_E_INVALID for a bad
+ * shape). */
+flip_status flip_batch_slots_workspace_bytes(const flip_batch_slots* spec, size_t* out_bytes);
+
+/* Make an empty slot batch whose tables live in d_ws (at least
+ * flip_batch_slots_workspace_bytes, 256-byte aligned, caller-owned, must
+ * outlive the batch). Nothing is enqueued. Errors: FLIP_E_INVALID (shape),
+ * FLIP_E_WORKSPACE (d_ws). */
+flip_status flip_batch_create_slots(const flip_batch_slots* spec, void* d_ws, size_t ws_bytes, void* hip_stream,
+                                    flip_batch** out);
+
+/* Put handle h into the empty slot `slot` of a slot batch, from the next
+ * step on. h must meet the requirements above, have the batch's precision
+ * and preconditioner, fit the batch's largest grid and not be in the batch
+ * already; it stays owned by the caller and must stay alive while attached.
+ * Errors (nothing changes): FLIP_E_INVALID. */
+flip_status flip_batch_attach(flip_batch* b, int slot, flip_handle* h);
+
+/* Empty slot `slot` (the handle may be destroyed afterwards, once the last
+ * step's work is complete, which flip_destroy waits for). FLIP_E_INVALID for
+ * an empty or out-of-range slot or a batch not made by
+ * flip_batch_create_slots. */
+flip_status flip_batch_detach(flip_batch* b, int slot);
+
+/* The batch's counters (host only). */
+flip_status flip_batch_get_info(const flip_batch* b, flip_batch_info* out);
 
 /* Run nsteps >= 0 steps of every scene of the batch on hip_stream. As with
  * flip_step, the host waits at the solver's convergence checks. Each scene's

@@ -26,9 +26,11 @@ constexpr int NEXT_CHUNK = 8;   // solver iterations between later checks
 // test every MG_NEXT_CHUNK iterations (a recorded chunk of that size too).
 constexpr int MG_NEXT_CHUNK = 2;
 
-// Host image of the launch tables, uploaded once into the batch workspace.
+// Host image of the launch tables, uploaded into the batch workspace (once,
+// or after each change of a slot batch's scenes).
 struct Tables {
     std::vector<char> bytes;
+    std::vector<char> live;  // per slot: holds a scene (an empty slot has no workgroups)
     // reserve n zeroed bytes, aligned
     size_t reserve(size_t n)
     {
@@ -48,16 +50,17 @@ struct Tables {
 struct Site {
     size_t args_off = 0, first_off = 0;
     int ns = 0;
-    uint32_t blocks = 0;
-    uint64_t items = 0;  // work-items of the launch
+    uint32_t blocks = 0;  // workgroups of the launch (the scenes' own grids, concatenated)
+    uint64_t items = 0;   // work-items of the launch
 };
 
 template <typename A>
-Site add_site(Tables& t, const std::vector<A>& args, const std::vector<uint32_t>& blocks, int threads)
+Site add_site(Tables& t, const std::vector<A>& args, std::vector<uint32_t> blocks, int threads)
 {
     std::vector<uint32_t> first(args.size() + 1, 0u);
     uint64_t total = 0;
     for (size_t i = 0; i < args.size(); ++i) {
+        if (i < t.live.size() && !t.live[i]) blocks[i] = 0;
         total += blocks[i];
         first[i + 1] = (uint32_t)std::min<uint64_t>(total, 0xFFFFFFFFull);
     }
@@ -110,11 +113,23 @@ void scan_sites(Tables& t, const std::vector<const uint32_t*>& in, const std::ve
 }
 
 // The tables of every launch of one step, with the same arguments and grids
-// as the plain step of each handle (capi.hip, run_step).
+// as the plain step of each handle (capi.hip, run_step). slots[s] is the
+// scene of slot s (null: empty; its entries stay zero and it has no
+// workgroups); cur0[s] its current particle buffer at an even batch step;
+// mg_levels the multigrid levels the launch sequence covers; dws the device
+// workspace (null when only sizing).
 template <typename T>
-void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
+void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>& cur0, int mg_levels,
+                 const char* dws, Tables& t, Sites& S)
 {
-    const size_t ns = hs.size();
+    const size_t ns = slots.size();
+    static flip_handle empty_slot;  // stands in for an empty slot (zero sizes, null pointers)
+    std::vector<flip_handle*> hs(ns);
+    t.live.assign(ns, 0);
+    for (size_t s = 0; s < ns; ++s) {
+        hs[s] = slots[s] ? slots[s] : &empty_slot;
+        t.live[s] = slots[s] != nullptr;
+    }
     std::vector<uint32_t> blk(ns);
     {
         std::vector<FillU32Args> a(ns);
@@ -135,7 +150,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             const Geo& g = h->geo;
             const flip_config& c = h->cfg;
             const int64_t n = h->sz.n;
-            const int cur = h->cur ^ ph, nxt = cur ^ 1;
+            const int cur = cur0[s] ^ ph, nxt = cur ^ 1;
             const T* pc = (const T*)h->pos[cur];
             ak[s] = BinKeysArgs<T>{g, pc, pc + n, pc + 2 * n, n, h->key, h->rank, h->count};
             ag[s] = GatherArgs<T>{h->perm, h->key, h->start, h->count, n,
@@ -298,8 +313,7 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             lv.uflag = lv.dlist = lv.ulist = lv.cnt = nullptr;
             return lv;
         };
-        int L = 0;
-        for (flip_handle* h : hs) L = std::max(L, h->nmg);
+        const int L = mg_levels;
         S.mg_levels = L;
         std::vector<MgTypesFineArgs> tf(ns);
         std::vector<MgFineArgs<T>> fd(ns), fu(ns);
@@ -315,7 +329,8 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
             fu[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, (T*)h->mgz,
                                   h->pslots, h->ps};
             bfine[s] = (uint32_t)h->groups;
-            bo[s] = MgPairArgs{unlisted(h->mg[h->nmg - 1]), unlisted(h->mg[h->nmg - 1]), h->ps};
+            const MgLevel bottom = unlisted(h->mg[h->nmg > 0 ? h->nmg - 1 : 0]);
+            bo[s] = MgPairArgs{bottom, bottom, h->ps};
         }
         S.mg_types_fine = add_site(t, tf, btf, 256);
         S.mg_fine_down = add_site(t, fd, bfine, 256);
@@ -344,10 +359,47 @@ void build_sites(const std::vector<flip_handle*>& hs, Tables& t, Sites& S)
     {
         // the summary array itself, then the summary launch that fills it
         S.summary_off = t.reserve(sizeof(SolveSummary) * ns);
+        SolveSummary* d_sum = dws ? (SolveSummary*)(dws + S.summary_off) : nullptr;
         std::vector<SummaryArgs> a(ns);
         std::vector<uint32_t> b1(ns, 1u);
-        for (size_t s = 0; s < ns; ++s) a[s] = SummaryArgs{hs[s]->ps, nullptr};  // rebased at create
+        for (size_t s = 0; s < ns; ++s) a[s] = SummaryArgs{hs[s]->ps, d_sum ? d_sum + s : nullptr};
         S.summary = add_site(t, a, b1, 64);
+    }
+}
+
+// every launch site of a step, in a fixed order
+template <typename S_, typename F>
+void for_each_site(S_& S, F&& f)
+{
+    f(S.fill_count);
+    f(S.scatter);
+    f(S.tile_flags);
+    f(S.tile_compact);
+    f(S.rhs);
+    f(S.summary);
+    for (int i = 0; i < 3; ++i) {
+        f(S.scan_c[i]);
+        f(S.scan_t[i]);
+        f(S.project[i]);
+    }
+    for (int k = 0; k < 2; ++k) {
+        f(S.dir[k]);
+        f(S.upd[k]);
+        f(S.ph[k].bin_keys);
+        f(S.ph[k].gather);
+        f(S.ph[k].p2g);
+        f(S.ph[k].g2p);
+    }
+    if (S.mg) {
+        f(S.mg_types_fine);
+        f(S.mg_fine_down);
+        f(S.mg_fine_up);
+        f(S.mg_bottom);
+        for (int l = 0; l + 1 < S.mg_levels; ++l) {
+            f(S.mg_types[l]);
+            f(S.mg_down[l]);
+            f(S.mg_up[l]);
+        }
     }
 }
 
@@ -367,69 +419,118 @@ bool sites_fit(const Sites& S)
     return r;
 }
 
-flip_status check_handles(flip_handle* const* handles, int nscenes, int* prec, bool* mg)
+// a handle a batch of this precision and preconditioner can step
+flip_status check_handle(const flip_handle* h, int prec, bool mg)
 {
-    if (!handles || nscenes < 1 || nscenes > FLIP_BATCH_MAX_SCENES) return FLIP_E_INVALID;
-    for (int s = 0; s < nscenes; ++s) {
-        const flip_handle* h = handles[s];
-        if (!h) return FLIP_E_INVALID;
-        if (h->prec != FLIP_FP32 && h->prec != FLIP_FP64) return FLIP_E_INVALID;
-        if (h->prec != handles[0]->prec) return FLIP_E_INVALID;
-        if (h->cfg.flags &
-            (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING | FLIP_FLAG_DIAGNOSTICS | FLIP_FLAG_RED_BLACK_GS | FLIP_FLAG_ADAPTIVE_DT |
-             FLIP_FLAG_RESEED))
-            return FLIP_E_INVALID;
-        // the preconditioner is the same for every scene of a batch
-        if ((h->cfg.flags & FLIP_FLAG_MULTIGRID) != (handles[0]->cfg.flags & FLIP_FLAG_MULTIGRID))
-            return FLIP_E_INVALID;
-        for (int q = 0; q < s; ++q)
-            if (handles[q] == h) return FLIP_E_INVALID;
-    }
-    *prec = handles[0]->prec;
-    *mg = (handles[0]->cfg.flags & FLIP_FLAG_MULTIGRID) != 0;
+    if (!h) return FLIP_E_INVALID;
+    if (h->prec != FLIP_FP32 && h->prec != FLIP_FP64) return FLIP_E_INVALID;
+    if (h->prec != prec) return FLIP_E_INVALID;
+    if (h->cfg.flags & (FLIP_FLAG_NO_PROJECTION | FLIP_FLAG_KERNEL_TIMING | FLIP_FLAG_DIAGNOSTICS |
+                        FLIP_FLAG_RED_BLACK_GS | FLIP_FLAG_ADAPTIVE_DT | FLIP_FLAG_RESEED))
+        return FLIP_E_INVALID;
+    // the preconditioner is the same for every scene of a batch
+    if (((h->cfg.flags & FLIP_FLAG_MULTIGRID) != 0) != mg) return FLIP_E_INVALID;
     return FLIP_OK;
 }
 
-flip_status build_tables(const std::vector<flip_handle*>& hs, int prec, bool mg, Tables& t, Sites& S)
+flip_status check_handles(flip_handle* const* handles, int nscenes, int* prec, bool* mg)
+{
+    if (!handles || nscenes < 1 || nscenes > FLIP_BATCH_MAX_SCENES) return FLIP_E_INVALID;
+    if (!handles[0]) return FLIP_E_INVALID;
+    *prec = handles[0]->prec;
+    *mg = (handles[0]->cfg.flags & FLIP_FLAG_MULTIGRID) != 0;
+    for (int s = 0; s < nscenes; ++s) {
+        flip_status v = check_handle(handles[s], *prec, *mg);
+        if (v != FLIP_OK) return v;
+        for (int q = 0; q < s; ++q)
+            if (handles[q] == handles[s]) return FLIP_E_INVALID;
+    }
+    return FLIP_OK;
+}
+
+// multigrid levels of a grid (each axis halved, ceil, until none exceeds the bottom side)
+int mg_levels_of(int nx, int ny, int nz)
+{
+    int l = 0;
+    do {
+        nx = (nx + 1) / 2;
+        ny = (ny + 1) / 2;
+        nz = (nz + 1) / 2;
+        ++l;
+    } while ((nx > MG_BOTTOM_SIDE || ny > MG_BOTTOM_SIDE || nz > MG_BOTTOM_SIDE) && l < MG_MAX_LEVELS);
+    return l;
+}
+
+flip_status build_tables(const std::vector<flip_handle*>& slots, const std::vector<int>& cur0, int prec, bool mg,
+                         int mg_levels, const char* dws, Tables& t, Sites& S)
 {
     S.mg = mg;
     if (prec == FLIP_FP64)
-        build_sites<double>(hs, t, S);
+        build_sites<double>(slots, cur0, mg_levels, dws, t, S);
     else
-        build_sites<float>(hs, t, S);
+        build_sites<float>(slots, cur0, mg_levels, dws, t, S);
     return sites_fit(S) ? FLIP_OK : FLIP_E_INVALID;
+}
+
+// A recorded graph keeps the grid each launch had when it was recorded, and
+// its workgroups loop over however many workgroups the scenes present need, so
+// it stays correct whatever the scenes; it is recorded again only when a
+// launch needs more than twice the workgroups it was recorded with (or had
+// none), or a quarter of them or fewer (idle workgroups).
+bool grids_drifted(const Sites& cur, const Sites& rec)
+{
+    std::vector<uint32_t> a, r;
+    for_each_site(cur, [&](const Site& x) { a.push_back(x.blocks); });
+    for_each_site(rec, [&](const Site& x) { r.push_back(std::max<uint32_t>(x.blocks, 1u)); });
+    if (a.size() != r.size()) return true;
+    for (size_t i = 0; i < a.size(); ++i) {
+        if (a[i] > 2ull * r[i]) return true;
+        if (a[i] > 0 && 4ull * a[i] <= r[i]) return true;
+    }
+    return false;
 }
 
 }  // namespace
 
 struct flip_batch {
-    std::vector<flip_handle*> hs;
-    std::vector<int> cur0;  // each scene's current particle buffer at creation
+    std::vector<flip_handle*> slot;  // scene of each slot (null: empty)
+    std::vector<int> cur0;           // per slot: the scene's current particle buffer at an even step
     int prec = FLIP_FP32;
+    bool mg = false;
+    int mg_levels = 0;               // levels the launch sequence covers
     uint32_t flags = 0;
+    bool slots_api = false;          // made by flip_batch_create_slots (fixed grids, attach / detach)
+    int max_dims[3] = {0, 0, 0};     // largest grid a slot batch takes
     char* dws = nullptr;
+    size_t table_bytes = 0;
     Sites S;
-    SolveSummary* h_sum = nullptr;  // pinned host copy of the summaries
-    int phase = 0;                  // steps taken, mod 2
+    Sites S_rec;                     // the launch grids the graphs were recorded with
+    char* h_table = nullptr;         // pinned image of the tables
+    bool dirty = true;               // the scenes changed since the tables were uploaded
+    SolveSummary* h_sum = nullptr;   // pinned host copy of the summaries
+    int phase = 0;                   // steps taken, mod 2
     int64_t steps = 0;
-    int max_cap = 0;                // largest iteration cap of the scenes
     hipStream_t cap_stream = nullptr;
     hipStream_t last_stream = nullptr;  // stream of the last step
     hipGraphExec_t g_pre[2] = {nullptr, nullptr};
     hipGraphExec_t g_chunk = nullptr;
     hipGraphExec_t g_chunk_small = nullptr;  // MG_NEXT_CHUNK iterations (multigrid batches)
     hipGraphExec_t g_post[2] = {nullptr, nullptr};
+    flip_batch_info info{};
 };
 
 namespace {
 
+// A slot batch launches every site, at least one workgroup: a recorded graph
+// then holds every launch, whatever the scenes at recording time (a launch
+// whose scenes need no workgroup exits at once).
 BatchLaunch L(const flip_batch* b, const Site& s)
 {
     BatchLaunch l;
     l.args = b->dws + s.args_off;
     l.first = (const uint32_t*)(b->dws + s.first_off);
     l.ns = s.ns;
-    l.blocks = s.blocks;
+    l.blocks = b->slots_api ? std::max<uint32_t>(s.blocks, 1u) : s.blocks;
     return l;
 }
 
@@ -510,19 +611,72 @@ flip_status record_graph(flip_batch* b, F&& enqueue, hipGraphExec_t* out)
     const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) return FLIP_E_HIP;
+    b->info.graph_captures += 1;
     return hipGetLastError() == hipSuccess ? FLIP_OK : FLIP_E_HIP;
+}
+
+flip_status launch_graph(flip_batch* b, hipGraphExec_t g, hipStream_t st)
+{
+    HIP_TRY(hipGraphLaunch(g, st));
+    b->info.graph_launches += 1;
+    return FLIP_OK;
+}
+
+// rebuild the tables for the current scenes and upload them (stream-ordered
+// before the step's launches)
+flip_status upload_tables(flip_batch* b, hipStream_t st)
+{
+    Tables t;
+    Sites S;
+    flip_status v = build_tables(b->slot, b->cur0, b->prec, b->mg, b->mg_levels, b->dws, t, S);
+    if (v != FLIP_OK) return v;
+    if (t.bytes.size() != b->table_bytes) return FLIP_E_STATE;  // the layout is fixed by the slot count
+    // the previous upload has completed: every step ends with a synchronised summary read
+    std::memcpy(b->h_table, t.bytes.data(), t.bytes.size());
+    HIP_TRY(hipMemcpyAsync(b->dws, b->h_table, t.bytes.size(), hipMemcpyHostToDevice, st));
+    b->S = S;
+    b->dirty = false;
+    b->info.table_uploads += 1;
+    return FLIP_OK;
+}
+
+void drop_graphs(flip_batch* b)
+{
+    for (hipGraphExec_t* g : {&b->g_pre[0], &b->g_pre[1], &b->g_chunk, &b->g_chunk_small, &b->g_post[0], &b->g_post[1]})
+        if (*g) {
+            (void)hipGraphExecDestroy(*g);
+            *g = nullptr;
+        }
 }
 
 template <typename T>
 flip_status batch_step(flip_batch* b, hipStream_t st)
 {
-    const int ns = (int)b->hs.size();
+    const int ns = (int)b->slot.size();
     const int ph = b->phase;
     b->last_stream = st;
-    for (int s = 0; s < ns; ++s)
-        if (b->hs[s]->cur != (b->cur0[s] ^ ph)) return FLIP_E_STATE;  // stepped outside the batch
+    bool any = false;
+    for (int s = 0; s < ns; ++s) {
+        const flip_handle* h = b->slot[s];
+        if (!h) continue;
+        any = true;
+        if (h->cur != (b->cur0[s] ^ ph)) return FLIP_E_STATE;  // stepped outside the batch
+    }
+    if (!any) return FLIP_OK;  // an empty slot batch: nothing to step
+    if (b->dirty) {
+        flip_status v = upload_tables(b, st);
+        if (v != FLIP_OK) return v;
+        // record the graphs again when launches outgrew the grids they were
+        // recorded with, or shrank far below them
+        if (b->g_chunk && grids_drifted(b->S, b->S_rec)) {
+            HIP_TRY(hipStreamSynchronize(st));  // no replay of the old graphs is still running
+            drop_graphs(b);
+        }
+    }
     const bool graphs = (b->flags & FLIP_BATCH_GRAPHS) && b->steps >= 1;
     if (graphs) {
+        const bool any = b->g_pre[0] || b->g_pre[1] || b->g_chunk || b->g_post[0] || b->g_post[1];
+        if (!any) b->S_rec = b->S;  // a new set of graphs: recorded with the current grids
         if (!b->g_pre[ph]) {
             flip_status r = record_graph(b, [&](hipStream_t cs) { enqueue_pre<T>(b, ph, cs); }, &b->g_pre[ph]);
             if (r != FLIP_OK) return r;
@@ -541,14 +695,19 @@ flip_status batch_step(flip_batch* b, hipStream_t st)
             flip_status r = record_graph(b, [&](hipStream_t cs) { enqueue_post<T>(b, ph, cs); }, &b->g_post[ph]);
             if (r != FLIP_OK) return r;
         }
-        HIP_TRY(hipGraphLaunch(b->g_pre[ph], st));
+        flip_status r = launch_graph(b, b->g_pre[ph], st);
+        if (r != FLIP_OK) return r;
     } else {
         enqueue_pre<T>(b, ph, st);
     }
 
     // the solve: chunks of iterations until no scene is running
-    int prev = 0;
-    for (flip_handle* h : b->hs) prev = std::max(prev, h->prev_iters);
+    int prev = 0, max_cap = 0;
+    for (const flip_handle* h : b->slot)
+        if (h) {
+            prev = std::max(prev, h->prev_iters);
+            max_cap = std::max(max_cap, solve_iter_cap(h->cfg));
+        }
     const bool mg = b->S.mg;
     int chunk = prev > 2 ? (mg ? prev : prev - 2) : FIRST_CHUNK;
     const int unit = graphs && !mg ? GRAPH_CHUNK : 2;
@@ -557,9 +716,14 @@ flip_status batch_step(flip_batch* b, hipStream_t st)
     const size_t sum_bytes = sizeof(SolveSummary) * ns;
     for (;;) {
         if (graphs) {
-            for (int q = 0; q < chunk / GRAPH_CHUNK; ++q) HIP_TRY(hipGraphLaunch(b->g_chunk, st));
-            for (int q = 0; q < (chunk % GRAPH_CHUNK) / MG_NEXT_CHUNK; ++q)
-                HIP_TRY(hipGraphLaunch(b->g_chunk_small, st));
+            for (int q = 0; q < chunk / GRAPH_CHUNK; ++q) {
+                flip_status r = launch_graph(b, b->g_chunk, st);
+                if (r != FLIP_OK) return r;
+            }
+            for (int q = 0; q < (chunk % GRAPH_CHUNK) / MG_NEXT_CHUNK; ++q) {
+                flip_status r = launch_graph(b, b->g_chunk_small, st);
+                if (r != FLIP_OK) return r;
+            }
         } else {
             enqueue_chunk<T>(b, chunk, st);
         }
@@ -567,20 +731,23 @@ flip_status batch_step(flip_batch* b, hipStream_t st)
         HIP_TRY(hipMemcpyAsync(b->h_sum, b->dws + b->S.summary_off, sum_bytes, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         bool running = false;
-        for (int s = 0; s < ns; ++s) running = running || b->h_sum[s].done == PCG_RUNNING;
-        if (!running || launched > b->max_cap + 8) break;
+        for (int s = 0; s < ns; ++s) running = running || (b->slot[s] && b->h_sum[s].done == PCG_RUNNING);
+        if (!running || launched > max_cap + 8) break;
         chunk = mg ? MG_NEXT_CHUNK : (graphs ? GRAPH_CHUNK : NEXT_CHUNK);
     }
 
-    if (graphs)
-        HIP_TRY(hipGraphLaunch(b->g_post[ph], st));
-    else
+    if (graphs) {
+        flip_status r = launch_graph(b, b->g_post[ph], st);
+        if (r != FLIP_OK) return r;
+    } else {
         enqueue_post<T>(b, ph, st);
+    }
     if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
 
     flip_status first = FLIP_OK;
     for (int s = 0; s < ns; ++s) {
-        flip_handle* h = b->hs[s];
+        flip_handle* h = b->slot[s];
+        if (!h) continue;
         const SolveSummary& q = b->h_sum[s];
         flip_status ret = FLIP_OK;
         if (q.done == PCG_MAX_ITERS || q.done == PCG_RUNNING) ret = FLIP_E_NOT_CONVERGED;
@@ -596,7 +763,53 @@ flip_status batch_step(flip_batch* b, hipStream_t st)
     }
     b->phase ^= 1;
     b->steps += 1;
+    b->info.steps += 1;
     return first;
+}
+
+// a batch object with its tables sized for `slots` (the entries filled by build_tables)
+flip_status new_batch(const std::vector<flip_handle*>& slots, int prec, bool mg, int mg_levels, uint32_t flags,
+                      bool slots_api, void* d_ws, size_t ws_bytes, flip_batch** out)
+{
+    flip_batch* b = new (std::nothrow) flip_batch();
+    if (!b) return FLIP_E_INVALID;
+    b->slot = slots;
+    b->cur0.assign(slots.size(), 0);
+    for (size_t s = 0; s < slots.size(); ++s)
+        if (slots[s]) b->cur0[s] = slots[s]->cur;
+    b->prec = prec;
+    b->mg = mg;
+    b->mg_levels = mg_levels;
+    b->flags = flags;
+    b->slots_api = slots_api;
+    Tables t;
+    Sites S;
+    flip_status v = build_tables(b->slot, b->cur0, prec, mg, mg_levels, nullptr, t, S);
+    if (v != FLIP_OK) {
+        delete b;
+        return v;
+    }
+    if (!d_ws || ws_bytes < t.bytes.size() || ((uintptr_t)d_ws & (TABLE_ALIGN - 1))) {
+        delete b;
+        return FLIP_E_WORKSPACE;
+    }
+    b->dws = (char*)d_ws;
+    b->table_bytes = t.bytes.size();
+    b->S = S;
+    b->info.nslots = (int)slots.size();
+    if (hipHostMalloc((void**)&b->h_sum, sizeof(SolveSummary) * slots.size(), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_table, b->table_bytes, hipHostMallocDefault) != hipSuccess) {
+        flip_batch_destroy(b);
+        return FLIP_E_HIP;
+    }
+    *out = b;
+    return FLIP_OK;
+}
+
+bool slot_batch_takes(const flip_batch* b, const flip_handle* h)
+{
+    return h->cfg.nx <= b->max_dims[0] && h->cfg.ny <= b->max_dims[1] && h->cfg.nz <= b->max_dims[2] &&
+           h->nmg <= b->mg_levels;
 }
 
 }  // namespace
@@ -611,9 +824,12 @@ flip_status flip_batch_workspace_bytes(flip_handle* const* handles, int nscenes,
     flip_status v = check_handles(handles, nscenes, &prec, &mg);
     if (v != FLIP_OK) return v;
     std::vector<flip_handle*> hs(handles, handles + nscenes);
+    std::vector<int> cur0(nscenes, 0);
+    int levels = 0;
+    for (flip_handle* h : hs) levels = std::max(levels, h->nmg);
     Tables t;
     Sites S;
-    v = build_tables(hs, prec, mg, t, S);
+    v = build_tables(hs, cur0, prec, mg, levels, nullptr, t, S);
     if (v != FLIP_OK) return v;
     *out_bytes = t.bytes.size();
     return FLIP_OK;
@@ -629,38 +845,98 @@ flip_status flip_batch_create(flip_handle* const* handles, int nscenes, uint32_t
     bool mg = false;
     flip_status v = check_handles(handles, nscenes, &prec, &mg);
     if (v != FLIP_OK) return v;
-    flip_batch* b = new (std::nothrow) flip_batch();
-    if (!b) return FLIP_E_INVALID;
-    b->hs.assign(handles, handles + nscenes);
-    b->prec = prec;
-    b->flags = flags;
-    Tables t;
-    v = build_tables(b->hs, prec, mg, t, b->S);
-    if (v != FLIP_OK) {
-        delete b;
-        return v;
+    std::vector<flip_handle*> hs(handles, handles + nscenes);
+    int levels = 0;
+    for (flip_handle* h : hs) levels = std::max(levels, h->nmg);
+    flip_batch* b = nullptr;
+    v = new_batch(hs, prec, mg, levels, flags, false, d_ws, ws_bytes, &b);
+    if (v != FLIP_OK) return v;
+    for (flip_handle* h : hs) {
+        b->max_dims[0] = std::max(b->max_dims[0], h->cfg.nx);
+        b->max_dims[1] = std::max(b->max_dims[1], h->cfg.ny);
+        b->max_dims[2] = std::max(b->max_dims[2], h->cfg.nz);
     }
-    if (!d_ws || ws_bytes < t.bytes.size() || ((uintptr_t)d_ws & (TABLE_ALIGN - 1))) {
-        delete b;
-        return FLIP_E_WORKSPACE;
-    }
-    b->dws = (char*)d_ws;
-    // the summary launch writes scene s's entry of the summary array
-    SummaryArgs* sa = (SummaryArgs*)(t.bytes.data() + b->S.summary.args_off);
-    SolveSummary* d_sum = (SolveSummary*)(b->dws + b->S.summary_off);
-    for (int s = 0; s < nscenes; ++s) sa[s].out = d_sum + s;
-    for (flip_handle* h : b->hs) {
-        b->cur0.push_back(h->cur);
-        b->max_cap = std::max(b->max_cap, solve_iter_cap(h->cfg));
-    }
+    b->info.occupied = nscenes;
     hipStream_t st = (hipStream_t)hip_stream;
-    if (hipHostMalloc((void**)&b->h_sum, sizeof(SolveSummary) * nscenes, hipHostMallocDefault) != hipSuccess ||
-        hipMemcpyAsync(b->dws, t.bytes.data(), t.bytes.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess) {
+    if (upload_tables(b, st) != FLIP_OK || hipStreamSynchronize(st) != hipSuccess) {
         flip_batch_destroy(b);
         return FLIP_E_HIP;
     }
     *out = b;
+    return FLIP_OK;
+}
+
+flip_status flip_batch_slots_workspace_bytes(const flip_batch_slots* spec, size_t* out_bytes)
+{
+    if (!spec || !out_bytes) return FLIP_E_INVALID;
+    if (spec->nslots < 1 || spec->nslots > FLIP_BATCH_MAX_SCENES) return FLIP_E_INVALID;
+    if (spec->precision != FLIP_FP32 && spec->precision != FLIP_FP64) return FLIP_E_INVALID;
+    if (spec->max_nx < 1 || spec->max_ny < 1 || spec->max_nz < 1) return FLIP_E_INVALID;
+    std::vector<flip_handle*> hs(spec->nslots, nullptr);
+    std::vector<int> cur0(spec->nslots, 0);
+    const bool mg = (spec->flags & FLIP_BATCH_MULTIGRID) != 0;
+    Tables t;
+    Sites S;
+    flip_status v = build_tables(hs, cur0, spec->precision, mg, mg ? mg_levels_of(spec->max_nx, spec->max_ny, spec->max_nz) : 0,
+                                 nullptr, t, S);
+    if (v != FLIP_OK) return v;
+    *out_bytes = t.bytes.size();
+    return FLIP_OK;
+}
+
+flip_status flip_batch_create_slots(const flip_batch_slots* spec, void* d_ws, size_t ws_bytes, void* hip_stream,
+                                    flip_batch** out)
+{
+    if (!out) return FLIP_E_INVALID;
+    *out = nullptr;
+    size_t need = 0;
+    flip_status v = flip_batch_slots_workspace_bytes(spec, &need);
+    if (v != FLIP_OK) return v;
+    if (spec->flags & ~(uint32_t)(FLIP_BATCH_GRAPHS | FLIP_BATCH_MULTIGRID)) return FLIP_E_INVALID;
+    const bool mg = (spec->flags & FLIP_BATCH_MULTIGRID) != 0;
+    std::vector<flip_handle*> hs(spec->nslots, nullptr);
+    flip_batch* b = nullptr;
+    v = new_batch(hs, spec->precision, mg, mg ? mg_levels_of(spec->max_nx, spec->max_ny, spec->max_nz) : 0,
+                  spec->flags & FLIP_BATCH_GRAPHS, true, d_ws, ws_bytes, &b);
+    if (v != FLIP_OK) return v;
+    b->max_dims[0] = spec->max_nx;
+    b->max_dims[1] = spec->max_ny;
+    b->max_dims[2] = spec->max_nz;
+    b->last_stream = (hipStream_t)hip_stream;
+    *out = b;
+    return FLIP_OK;
+}
+
+flip_status flip_batch_attach(flip_batch* b, int slot, flip_handle* h)
+{
+    if (!b || !h || !b->slots_api) return FLIP_E_INVALID;
+    if (slot < 0 || slot >= (int)b->slot.size() || b->slot[slot]) return FLIP_E_INVALID;
+    flip_status v = check_handle(h, b->prec, b->mg);
+    if (v != FLIP_OK) return v;
+    if (!slot_batch_takes(b, h)) return FLIP_E_INVALID;
+    for (const flip_handle* o : b->slot)
+        if (o == h) return FLIP_E_INVALID;
+    b->slot[slot] = h;
+    b->cur0[slot] = h->cur ^ b->phase;
+    b->dirty = true;
+    b->info.occupied += 1;
+    return FLIP_OK;
+}
+
+flip_status flip_batch_detach(flip_batch* b, int slot)
+{
+    if (!b || !b->slots_api) return FLIP_E_INVALID;
+    if (slot < 0 || slot >= (int)b->slot.size() || !b->slot[slot]) return FLIP_E_INVALID;
+    b->slot[slot] = nullptr;
+    b->dirty = true;
+    b->info.occupied -= 1;
+    return FLIP_OK;
+}
+
+flip_status flip_batch_get_info(const flip_batch* b, flip_batch_info* out)
+{
+    if (!b || !out) return FLIP_E_INVALID;
+    *out = b->info;
     return FLIP_OK;
 }
 
@@ -671,7 +947,7 @@ flip_status flip_batch_step(flip_batch* b, int nsteps, void* hip_stream)
     flip_status first = FLIP_OK;
     for (int k = 0; k < nsteps; ++k) {
         flip_status r = b->prec == FLIP_FP64 ? batch_step<double>(b, st) : batch_step<float>(b, st);
-        if (r == FLIP_E_HIP || r == FLIP_E_STATE) return r;
+        if (r == FLIP_E_HIP || r == FLIP_E_STATE || r == FLIP_E_INVALID) return r;
         if (r != FLIP_OK && first == FLIP_OK) first = r;
     }
     return first;
@@ -686,6 +962,7 @@ void flip_batch_destroy(flip_batch* b)
         if (*g) (void)hipGraphExecDestroy(*g);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->h_sum) (void)hipHostFree(b->h_sum);
+    if (b->h_table) (void)hipHostFree(b->h_table);
     delete b;
 }
 

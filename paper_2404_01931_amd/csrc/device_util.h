@@ -26,13 +26,12 @@ struct Blk {
 
 __device__ inline Blk plain_blk() { return Blk{(int)blockIdx.x, (int)gridDim.x}; }
 
-// Scene of this workgroup in a batched launch of ns scenes (first[] is
+// Scene of virtual workgroup w in a batched launch of ns scenes (first[] is
 // non-decreasing, first[0] = 0; scenes with no workgroups are skipped). Each
 // wave counts, 64 entries at a time, the scenes that end at or before this
 // workgroup. The result is uniform across the workgroup.
-__device__ inline int batch_scene(const uint32_t* __restrict__ first, int ns, Blk& b)
+__device__ inline int batch_scene(const uint32_t* __restrict__ first, int ns, uint32_t w, Blk& b)
 {
-    const uint32_t w = blockIdx.x;
     int s = 0;
     for (int base = 1; base <= ns; base += WAVE) {
         const int i = base + lane_id();
@@ -58,12 +57,23 @@ __device__ inline T* as_global(T* p)
     return (T*)(GT*)(uintptr_t)p;
 }
 
-// Arguments of this workgroup's scene in a batched launch (see batch.h).
-template <typename A>
-__device__ inline const A& batch_args(const A* __restrict__ tab, const uint32_t* __restrict__ first, int ns,
-                                      Blk& b)
+// Runs body(b, args) for each workgroup of a batched launch's virtual grid
+// (see batch.h): first[ns] workgroups in all, each with its scene's
+// arguments and its place b in that scene's own grid. This workgroup takes
+// virtual workgroups blockIdx.x, blockIdx.x + gridDim.x, ... (the physical
+// grid is fixed when the batch is built, whatever its scenes are later), with
+// a barrier between two of them, so each may use LDS from the start.
+template <typename A, typename F>
+__device__ __forceinline__ void batch_for_each(const A* __restrict__ tab, const uint32_t* __restrict__ first, int ns,
+                                               F&& body)
 {
-    return tab[batch_scene(first, ns, b)];
+    const uint32_t total = first[ns];
+    for (uint32_t w = blockIdx.x; w < total; w += gridDim.x) {
+        Blk b;
+        const int s = batch_scene(first, ns, w, b);
+        body(b, tab[s]);
+        __syncthreads();
+    }
 }
 
 // Workgroup barrier that orders LDS only. __syncthreads() fences every

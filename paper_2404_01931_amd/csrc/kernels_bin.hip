@@ -32,9 +32,9 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, int64_t n, uint32
 __global__ __launch_bounds__(256) void kb_fill_u32(const FillU32Args* __restrict__ tab,
                                                    const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const FillU32Args& a = batch_args(tab, first, ns, b);
-    fill_u32_body(b, as_global(a.p), a.n, a.v);
+    batch_for_each(tab, first, ns, [&](Blk b, const FillU32Args& a) {
+        fill_u32_body(b, as_global(a.p), a.n, a.v);
+    });
 }
 
 void launch_b_fill_u32(const BatchLaunch& L, hipStream_t st)
@@ -144,9 +144,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_bin_keys(const BinKeysArgs<T>* __restrict__ tab,
                                                    const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const BinKeysArgs<T>& a = batch_args(tab, first, ns, b);
-    bin_keys_body<T>(b, a.g, as_global(a.px), as_global(a.py), as_global(a.pz), a.n, as_global(a.key), as_global(a.rank), as_global(a.count));
+    batch_for_each(tab, first, ns, [&](Blk b, const BinKeysArgs<T>& a) {
+        bin_keys_body<T>(b, a.g, as_global(a.px), as_global(a.py), as_global(a.pz), a.n, as_global(a.key), as_global(a.rank), as_global(a.count));
+    });
 }
 
 template <typename T>
@@ -239,9 +239,9 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_totals(const uint32_t* __restr
 __global__ __launch_bounds__(SCAN_NT) void kb_scan_totals(const ScanTotalsArgs* __restrict__ tab,
                                                           const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const ScanTotalsArgs& a = batch_args(tab, first, ns, b);
-    scan_totals_body(b, as_global(a.in), a.n, as_global(a.totals));
+    batch_for_each(tab, first, ns, [&](Blk b, const ScanTotalsArgs& a) {
+        scan_totals_body(b, as_global(a.in), a.n, as_global(a.totals));
+    });
 }
 
 void launch_b_scan_totals(const BatchLaunch& L, hipStream_t st)
@@ -275,9 +275,9 @@ __global__ __launch_bounds__(1024) void k_scan_totals_scan(uint32_t* __restrict_
 __global__ __launch_bounds__(1024) void kb_scan_totals_scan(const ScanTotalsScanArgs* __restrict__ tab,
                                                             const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const ScanTotalsScanArgs& a = batch_args(tab, first, ns, b);
-    scan_totals_scan_body(as_global(a.totals), a.nb);
+    batch_for_each(tab, first, ns, [&](Blk b, const ScanTotalsScanArgs& a) {
+        scan_totals_scan_body(as_global(a.totals), a.nb);
+    });
 }
 
 void launch_b_scan_totals_scan(const BatchLaunch& L, hipStream_t st)
@@ -338,9 +338,9 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const uint32_t* __restri
 __global__ __launch_bounds__(SCAN_NT) void kb_scan_apply(const ScanApplyArgs* __restrict__ tab,
                                                          const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const ScanApplyArgs& a = batch_args(tab, first, ns, b);
-    scan_apply_body(b, as_global(a.in), as_global(a.out), a.n, as_global(a.offsets));
+    batch_for_each(tab, first, ns, [&](Blk b, const ScanApplyArgs& a) {
+        scan_apply_body(b, as_global(a.in), as_global(a.out), a.n, as_global(a.offsets));
+    });
 }
 
 void launch_b_scan_apply(const BatchLaunch& L, hipStream_t st)
@@ -387,9 +387,9 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t* __restrict_
 __global__ __launch_bounds__(256) void kb_bin_scatter(const ScatterArgs* __restrict__ tab,
                                                       const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const ScatterArgs& a = batch_args(tab, first, ns, b);
-    bin_scatter_body(b, as_global(a.key), as_global(a.rank), as_global(a.start), a.n, as_global(a.perm));
+    batch_for_each(tab, first, ns, [&](Blk b, const ScatterArgs& a) {
+        bin_scatter_body(b, as_global(a.key), as_global(a.rank), as_global(a.start), a.n, as_global(a.perm));
+    });
 }
 
 void launch_b_bin_scatter(const BatchLaunch& L, hipStream_t st)
@@ -462,10 +462,10 @@ template <typename T>
 __global__ __launch_bounds__(256) void kb_bin_gather(const GatherArgs<T>* __restrict__ tab,
                                                      const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const GatherArgs<T>& a = batch_args(tab, first, ns, b);
-    bin_gather_body<T>(b, as_global(a.perm), as_global(a.key), as_global(a.start), as_global(a.count), a.n, as_global(a.pos_in), as_global(a.vel_in), as_global(a.id_in), as_global(a.pos_out),
-                       as_global(a.vel_out), as_global(a.id_out));
+    batch_for_each(tab, first, ns, [&](Blk b, const GatherArgs<T>& a) {
+        bin_gather_body<T>(b, as_global(a.perm), as_global(a.key), as_global(a.start), as_global(a.count), a.n, as_global(a.pos_in), as_global(a.vel_in), as_global(a.id_in), as_global(a.pos_out),
+                           as_global(a.vel_out), as_global(a.id_out));
+    });
 }
 
 template <typename T>
@@ -664,9 +664,9 @@ __global__ __launch_bounds__(256) void k_tile_flags(Geo g, const uint32_t* __res
 __global__ __launch_bounds__(256) void kb_tile_flags(const TileFlagsArgs* __restrict__ tab,
                                                      const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const TileFlagsArgs& a = batch_args(tab, first, ns, b);
-    tile_flags_body(b, a.g, as_global(a.count), as_global(a.tile_flag));
+    batch_for_each(tab, first, ns, [&](Blk b, const TileFlagsArgs& a) {
+        tile_flags_body(b, a.g, as_global(a.count), as_global(a.tile_flag));
+    });
 }
 
 void launch_b_tile_flags(const BatchLaunch& L, hipStream_t st)
@@ -724,9 +724,9 @@ __global__ __launch_bounds__(256) void k_tile_compact(Geo g, const uint32_t* __r
 __global__ __launch_bounds__(256) void kb_tile_compact(const TileCompactArgs* __restrict__ tab,
                                                        const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const TileCompactArgs& a = batch_args(tab, first, ns, b);
-    tile_compact_body(b, a.g, as_global(a.flag), as_global(a.excl), as_global(a.tile_slot), as_global(a.tile_list), as_global(a.tile_nbr), as_global(a.d_nactive));
+    batch_for_each(tab, first, ns, [&](Blk b, const TileCompactArgs& a) {
+        tile_compact_body(b, a.g, as_global(a.flag), as_global(a.excl), as_global(a.tile_slot), as_global(a.tile_list), as_global(a.tile_nbr), as_global(a.d_nactive));
+    });
 }
 
 void launch_b_tile_compact(const BatchLaunch& L, hipStream_t st)

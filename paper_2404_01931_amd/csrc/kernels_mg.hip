@@ -229,9 +229,9 @@ template <typename V>
 __global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_down(const MgPairArgs* __restrict__ tab,
                                                   const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const MgPairArgs& a = batch_args(tab, first, ns, b);
-    mg_down_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {
+        mg_down_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    });
 }
 
 // ---- bottom: the coarsest level (at most 8^3 cells), one workgroup -------------
@@ -283,9 +283,9 @@ template <typename V>
 __global__ __launch_bounds__(512) void kb_mg_bottom(const MgPairArgs* __restrict__ tab,
                                                     const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const MgPairArgs& a = batch_args(tab, first, ns, b);  // the coarsest level is f
-    mg_bottom_body<V>(glob(a.f), as_global(a.ps));
+    batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {  // the coarsest level is f
+        mg_bottom_body<V>(glob(a.f), as_global(a.ps));
+    });
 }
 
 // ---- up: dense level f from level c --------------------------------------------
@@ -423,9 +423,9 @@ template <typename V>
 __global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_up(const MgPairArgs* __restrict__ tab,
                                                 const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const MgPairArgs& a = batch_args(tab, first, ns, b);
-    mg_up_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {
+        mg_up_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    });
 }
 
 // ---- cell types of the coarse levels -----------------------------------------
@@ -494,9 +494,9 @@ __global__ __launch_bounds__(64 * MGT_WAVES) void k_mg_types_fine(Geo g, const i
 __global__ __launch_bounds__(64 * MGT_WAVES) void kb_mg_types_fine(const MgTypesFineArgs* __restrict__ tab,
                                                                   const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const MgTypesFineArgs& a = batch_args(tab, first, ns, b);
-    mg_types_fine_body(b, a.g, as_global(a.tile_slot), as_global(a.diag), glob(a.c));
+    batch_for_each(tab, first, ns, [&](Blk b, const MgTypesFineArgs& a) {
+        mg_types_fine_body(b, a.g, as_global(a.tile_slot), as_global(a.diag), glob(a.c));
+    });
 }
 
 // level c from level f: fluid when a child is
@@ -520,9 +520,9 @@ __global__ __launch_bounds__(64 * MGT_WAVES) void k_mg_types(MgLevel f, MgLevel 
 __global__ __launch_bounds__(64 * MGT_WAVES) void kb_mg_types(const MgPairArgs* __restrict__ tab,
                                                              const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const MgPairArgs& a = batch_args(tab, first, ns, b);
-    mg_types_body(b, glob(a.f), glob(a.c));
+    batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {
+        mg_types_body(b, glob(a.f), glob(a.c));
+    });
 }
 
 // ---- launchers -----------------------------------------------------------------

@@ -1,6 +1,10 @@
 // Pressure projection (paper Sec. 3.1.7): right-hand side from the discrete
-// divergence (Eq. (6)), matrix-free seven-point operator, Jacobi-preconditioned
-// conjugate gradient, and the pressure-gradient update of the faces (Eq. (5)).
+// divergence (Eq. (6)), matrix-free seven-point operator, preconditioned
+// conjugate gradient (Jacobi, or the multigrid V-cycle whose fine-level kernels
+// live here and whose coarse levels are in kernels_mg.hip), the paper's
+// red-black Gauss-Seidel solver as an alternative, the FP64 refinement of the
+// mixed-precision solve, and the pressure-gradient update of the faces
+// (Eq. (5)).
 //
 // Layout: the solver's vectors are stored per active 8x8x8 tile (512 cells,
 // x-fastest), so a workgroup of 512 threads owns one tile and reads it with
@@ -19,8 +23,12 @@
 //   direction kernel: s = z + beta s_old; q = A s; sigma = s.q; alpha = rho/sigma
 //   update kernel:    x += alpha s; r = n z - alpha A s; z = r / n;
 //                     rho' = r.z; max|r|; beta = rho'/rho; convergence test
-// Each kernel finishes with a fixed-order grid reduction by its last block, so
-// results are identical from run to run.
+// The iteration kernels' grid reductions are completed by the kernel after
+// them (every workgroup stores its partial sums; every workgroup of the next
+// kernel sums all of them in workgroup order); the start kernels complete
+// theirs in their last workgroup. Either way the order is fixed, so results
+// are identical from run to run. With the multigrid preconditioner the update
+// kernel keeps r instead of z = r / n_c and the V-cycle forms z = M r.
 #include <cfloat>
 
 #include <hip/hip_ext.h>
@@ -172,10 +180,10 @@ template <typename T, typename V>
 __global__ __launch_bounds__(PNT) void kb_rhs(const RhsArgs<T, V>* __restrict__ tab,
                                               const uint32_t* __restrict__ first, int ns)
 {
-    Blk blk;
-    const RhsArgs<T, V>& a = batch_args(tab, first, ns, blk);
-    rhs_body<T, V>(blk, a.g, as_global(a.tile_list), as_global(a.d_nactive), as_global(a.count), as_global(a.u), as_global(a.v), as_global(a.w), (T)a.scale, as_global(a.diag), as_global(a.b), as_global(a.z),
-                   as_global(a.x), as_global(a.s0), as_global(a.s1), as_global(a.partials), a.pstride, as_global(a.ps), a.tol, a.max_iters, a.r_form);
+    batch_for_each(tab, first, ns, [&](Blk blk, const RhsArgs<T, V>& a) {
+        rhs_body<T, V>(blk, a.g, as_global(a.tile_list), as_global(a.d_nactive), as_global(a.count), as_global(a.u), as_global(a.v), as_global(a.w), (T)a.scale, as_global(a.diag), as_global(a.b), as_global(a.z),
+                       as_global(a.x), as_global(a.s0), as_global(a.s1), as_global(a.partials), a.pstride, as_global(a.ps), a.tol, a.max_iters, a.r_form);
+    });
 }
 
 template <typename T, typename V>
@@ -507,9 +515,9 @@ template <typename V>
 __global__ __launch_bounds__(PCG_NT) void kb_pcg_direction(const DirArgs<V>* __restrict__ tab,
                                                            const uint32_t* __restrict__ first, int ns)
 {
-    Blk blk;
-    const DirArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_direction_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old), as_global(a.s_new), as_global(a.pslots), as_global(a.ps));
+    batch_for_each(tab, first, ns, [&](Blk blk, const DirArgs<V>& a) {
+        pcg_direction_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old), as_global(a.s_new), as_global(a.pslots), as_global(a.ps));
+    });
 }
 
 template <typename V>
@@ -754,13 +762,13 @@ template <typename V, bool UP>
 __global__ __launch_bounds__(PCG_NT) void kb_mg_fine(const MgFineArgs<V>* __restrict__ tab,
                                                      const uint32_t* __restrict__ first, int ns)
 {
-    Blk blk;
-    const MgFineArgs<V>& a = batch_args(tab, first, ns, blk);
-    MgLevel c = a.c;
-    c.b = as_global(c.b);
-    c.x = as_global(c.x);
-    mg_fine_body<V, UP>(blk, a.na_hint, a.g, as_global(a.tile_list), as_global(a.nbr), as_global(a.diag),
-                        as_global(a.r), c, as_global(a.z), as_global(a.pslots), as_global(a.ps));
+    batch_for_each(tab, first, ns, [&](Blk blk, const MgFineArgs<V>& a) {
+        MgLevel c = a.c;
+        c.b = as_global(c.b);
+        c.x = as_global(c.x);
+        mg_fine_body<V, UP>(blk, a.na_hint, a.g, as_global(a.tile_list), as_global(a.nbr), as_global(a.diag),
+                            as_global(a.r), c, as_global(a.z), as_global(a.pslots), as_global(a.ps));
+    });
 }
 
 template <typename V>
@@ -933,9 +941,9 @@ template <typename V, bool RF>
 __global__ __launch_bounds__(PCG_NT) void kb_pcg_update(const UpdArgs<V>* __restrict__ tab,
                                                         const uint32_t* __restrict__ first, int ns)
 {
-    Blk blk;
-    const UpdArgs<V>& a = batch_args(tab, first, ns, blk);
-    pcg_update_body<V, RF>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.pslots), as_global(a.ps));
+    batch_for_each(tab, first, ns, [&](Blk blk, const UpdArgs<V>& a) {
+        pcg_update_body<V, RF>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.s), as_global(a.x), as_global(a.z), as_global(a.pslots), as_global(a.ps));
+    });
 }
 
 template <typename V>
@@ -1249,9 +1257,9 @@ template <typename T, typename V, int A>
 __global__ __launch_bounds__(256) void kb_project(const ProjectArgs<T, V>* __restrict__ tab,
                                                   const uint32_t* __restrict__ first, int ns)
 {
-    Blk blk;
-    const ProjectArgs<T, V>& a = batch_args(tab, first, ns, blk);
-    project_body<T, V, A>(blk, a.g, as_global(a.diag), as_global(a.tile_slot), as_global(a.p), as_global(a.star), as_global(a.out), a.scale);
+    batch_for_each(tab, first, ns, [&](Blk blk, const ProjectArgs<T, V>& a) {
+        project_body<T, V, A>(blk, a.g, as_global(a.diag), as_global(a.tile_slot), as_global(a.p), as_global(a.star), as_global(a.out), a.scale);
+    });
 }
 
 template <typename T, typename V>
@@ -1273,20 +1281,20 @@ template void launch_b_project<double, double>(int, const BatchLaunch&, hipStrea
 __global__ __launch_bounds__(64) void kb_summary(const SummaryArgs* __restrict__ tab,
                                                  const uint32_t* __restrict__ first, int ns)
 {
-    Blk blk;
-    const SummaryArgs& a = batch_args(tab, first, ns, blk);
-    if (threadIdx.x != 0) return;
-    const PcgState* ps = as_global(a.ps);
-    SolveSummary o;
-    o.max_b = ps->max_b;
-    o.max_r = ps->max_r;
-    o.iter = ps->iter;
-    o.done = ps->done;
-    o.nfluid = ps->nfluid;
-    o.n_active = ps->n_active;
-    o.sync_error = ps->sync_error;
-    o.pad_ = 0;
-    *as_global(a.out) = o;
+    batch_for_each(tab, first, ns, [&](Blk blk, const SummaryArgs& a) {
+        if (threadIdx.x != 0) return;
+        const PcgState* ps = as_global(a.ps);
+        SolveSummary o;
+        o.max_b = ps->max_b;
+        o.max_r = ps->max_r;
+        o.iter = ps->iter;
+        o.done = ps->done;
+        o.nfluid = ps->nfluid;
+        o.n_active = ps->n_active;
+        o.sync_error = ps->sync_error;
+        o.pad_ = 0;
+        *as_global(a.out) = o;
+    });
 }
 
 void launch_b_summary(const BatchLaunch& L, hipStream_t st)

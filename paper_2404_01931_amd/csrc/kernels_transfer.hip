@@ -241,8 +241,11 @@ __device__ inline void axis_weights_dyadic(float f, float (&w)[N])
     }
 }
 
-// the particle's contribution to the window: W += w, M += v w for each of the
-// window's samples, w the product of the three axis weights
+// the particle's contribution to the window: W += wz wy wx and M += wz wy (v wx)
+// for each of the window's samples, each with one fused multiply-add (the x
+// weights scaled by v once per particle). With v a power of two, v wx is exact
+// and every step of M is v times the same step of W, so M = v W exactly: a
+// uniform power-of-two velocity comes back unchanged.
 template <int A>
 __device__ inline void window_accumulate(Window<A>& win, const float (&wx)[Window<A>::NX],
                                          const float (&wy)[Window<A>::NY], const float (&wz)[Window<A>::NZ],
@@ -250,6 +253,9 @@ __device__ inline void window_accumulate(Window<A>& win, const float (&wx)[Windo
 {
 #pragma clang fp contract(off)
     using Wn = Window<A>;
+    float vwx[Wn::NX];
+#pragma unroll
+    for (int i = 0; i < Wn::NX; ++i) vwx[i] = v * wx[i];
 #pragma unroll
     for (int k = 0; k < Wn::NZ; ++k)
 #pragma unroll
@@ -257,9 +263,8 @@ __device__ inline void window_accumulate(Window<A>& win, const float (&wx)[Windo
             const float wyz = wz[k] * wy[j];
 #pragma unroll
             for (int i = 0; i < Wn::NX; ++i) {
-                const float w = wyz * wx[i];
-                win.W[k][j][i] = win.W[k][j][i] + w;
-                win.M[k][j][i] = fma(v, w, win.M[k][j][i]);
+                win.W[k][j][i] = fma(wyz, wx[i], win.W[k][j][i]);
+                win.M[k][j][i] = fma(wyz, vwx[i], win.M[k][j][i]);
             }
         }
 }
@@ -290,8 +295,9 @@ __device__ inline void window_add(Window<A>& win, int cx, int cy, int cz, double
 }
 
 // add the window of cell (cx, cy, cz) to the block's samples; window samples
-// outside the box add 0 at the nearest sample inside it (within one index of
-// the cell, so touched by no other lane of the phase)
+// outside the box go to the spare sample acc[P2G_BOX], which no output reads
+// (lanes of a phase may race on it; every sample inside the box is touched by
+// one lane of the phase only)
 template <int A>
 __device__ inline void window_flush(const Window<A>& win, float (*acc)[2], int cx, int cy, int cz, int x0, int y0,
                                     int z0)
@@ -300,18 +306,39 @@ __device__ inline void window_flush(const Window<A>& win, float (*acc)[2], int c
     using Wn = Window<A>;
     constexpr int DX = P2G_T + (A == 0), DY = P2G_T + (A == 1), DZ = P2G_T + (A == 2);
     const int bi = cx - x0 - (A == 0 ? 0 : 1), bj = cy - y0 - (A == 1 ? 0 : 1), bk = cz - z0 - (A == 2 ? 0 : 1);
+    const int base = bi + DX * (bj + DY * bk);
+    bool in_i[Wn::NX], in_j[Wn::NY], in_k[Wn::NZ];
 #pragma unroll
-    for (int k = 0; k < Wn::NZ; ++k)
+    for (int i = 0; i < Wn::NX; ++i) in_i[i] = (unsigned)(bi + i) < (unsigned)DX;
+#pragma unroll
+    for (int j = 0; j < Wn::NY; ++j) in_j[j] = (unsigned)(bj + j) < (unsigned)DY;
+#pragma unroll
+    for (int k = 0; k < Wn::NZ; ++k) in_k[k] = (unsigned)(bk + k) < (unsigned)DZ;
+    // all reads of a plane of the window, then all writes: samples inside the
+    // box are distinct, so only the spare sample can be read after a write
+    // of the same flush, and its value is never used
+    typedef float F2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int k = 0; k < Wn::NZ; ++k) {
+        F2* a[Wn::NY][Wn::NX];
+        F2 old[Wn::NY][Wn::NX];
 #pragma unroll
         for (int j = 0; j < Wn::NY; ++j)
 #pragma unroll
             for (int i = 0; i < Wn::NX; ++i) {
-                const int li = bi + i, lj = bj + j, lk = bk + k;
-                const bool in = li >= 0 && li < DX && lj >= 0 && lj < DY && lk >= 0 && lk < DZ;
-                float* a = acc[min(max(li, 0), DX - 1) + DX * (min(max(lj, 0), DY - 1) + DY * min(max(lk, 0), DZ - 1))];
-                a[0] = a[0] + (in ? win.W[k][j][i] : 0.0f);
-                a[1] = a[1] + (in ? win.M[k][j][i] : 0.0f);
+                a[j][i] = (F2*)acc[in_i[i] && in_j[j] && in_k[k] ? base + i + DX * (j + DY * k) : P2G_BOX];
+                old[j][i] = *a[j][i];
             }
+#pragma unroll
+        for (int j = 0; j < Wn::NY; ++j)
+#pragma unroll
+            for (int i = 0; i < Wn::NX; ++i) {
+                F2 v = old[j][i];
+                v.x = v.x + win.W[k][j][i];
+                v.y = v.y + win.M[k][j][i];
+                *a[j][i] = v;
+            }
+    }
 }
 
 // the cell that lane handles in colour phase ph (ring box [r0, r1] per axis),
@@ -477,7 +504,8 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
                                          const uint32_t* __restrict__ tile_flag, T gdt_x, T gdt_y, T gdt_z,
                                          T* __restrict__ u_old, T* __restrict__ v_old,
                                          T* __restrict__ w_old, T* __restrict__ u_star,
-                                         T* __restrict__ v_star, T* __restrict__ w_star, T (*acc)[P2G_BOX][2])
+                                         T* __restrict__ v_star, T* __restrict__ w_star,
+                                         T (*acc)[P2G_BOX + 1][2])
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // Rows of blocks (fixed y, z) are dealt to the 8 XCDs in turn (workgroup
@@ -507,7 +535,7 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
 template <typename T, typename... Args>
 __device__ __forceinline__ void p2g_dispatch(Blk b, const Geo& g, Args... args)
 {
-    __shared__ T acc[3][P2G_BOX][2];  // one LDS block for both forms
+    __shared__ T acc[3][P2G_BOX + 1][2];  // one LDS block for both forms; a spare sample per component
     if (sizeof(T) == 4 && g.dyadic)
         p2g_body<T, sizeof(T) == 4>(b, g, args..., acc);
     else
@@ -535,10 +563,10 @@ template <typename T>
 __global__ __launch_bounds__(P2G_NT) void kb_p2g_tiles(const P2GArgs<T>* __restrict__ tab,
                                                    const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const P2GArgs<T>& a = batch_args(tab, first, ns, b);
-    p2g_dispatch<T>(b, a.g, a.n, as_global(a.px), as_global(a.py), as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.start), as_global(a.count), as_global(a.tile_flag), a.gdt[0], a.gdt[1], a.gdt[2],
-                as_global(a.old[0]), as_global(a.old[1]), as_global(a.old[2]), as_global(a.star[0]), as_global(a.star[1]), as_global(a.star[2]));
+    batch_for_each(tab, first, ns, [&](Blk b, const P2GArgs<T>& a) {
+        p2g_dispatch<T>(b, a.g, a.n, as_global(a.px), as_global(a.py), as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.start), as_global(a.count), as_global(a.tile_flag), a.gdt[0], a.gdt[1], a.gdt[2],
+                    as_global(a.old[0]), as_global(a.old[1]), as_global(a.old[2]), as_global(a.star[0]), as_global(a.star[1]), as_global(a.star[2]));
+    });
 }
 
 template <typename T>
@@ -802,12 +830,12 @@ template <typename T>
 __global__ __launch_bounds__(G2P_NT) void kb_g2p(const G2PArgs<T>* __restrict__ tab,
                                                  const uint32_t* __restrict__ first, int ns)
 {
-    Blk b;
-    const G2PArgs<T>& a = batch_args(tab, first, ns, b);
-    g2p_dispatch<T>(b, a.g, as_global(a.start), as_global(a.count), as_global(a.px), as_global(a.py),
-                as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.un),
-                as_global(a.vn), as_global(a.wn), as_global(a.uo), as_global(a.vo), as_global(a.wo), a.alpha,
-                a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel, as_global(a.nonfinite));
+    batch_for_each(tab, first, ns, [&](Blk b, const G2PArgs<T>& a) {
+        g2p_dispatch<T>(b, a.g, as_global(a.start), as_global(a.count), as_global(a.px), as_global(a.py),
+                    as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.un),
+                    as_global(a.vn), as_global(a.wn), as_global(a.uo), as_global(a.vo), as_global(a.wo), a.alpha,
+                    a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel, as_global(a.nonfinite));
+    });
 }
 
 template <typename T>

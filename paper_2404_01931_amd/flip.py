@@ -56,12 +56,14 @@ FLIP_KERNEL_COUNT = len(KERNEL_NAMES)
 
 FLIP_BATCH_MAX_SCENES = 256
 FLIP_BATCH_GRAPHS = 1
+FLIP_BATCH_MULTIGRID = 2
 
 EXPORTED = ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes", "flip_readback",
             "flip_stats", "flip_destroy", "flip_status_string", "flip_batch_workspace_bytes",
             "flip_batch_create", "flip_batch_step", "flip_batch_destroy", "flip_surface_field_bytes",
             "flip_surface_field", "flip_surface_mesh_workspace_bytes", "flip_surface_mesh",
-            "flip_surface_mesh_noalloc"]
+            "flip_surface_mesh_noalloc", "flip_batch_slots_workspace_bytes", "flip_batch_create_slots",
+            "flip_batch_attach", "flip_batch_detach", "flip_batch_get_info"]
 
 # device scratch of flip_surface_mesh_noalloc per GPU (FLIP_MESH_SCRATCH_MAX_BYTES)
 FLIP_MESH_SCRATCH_MAX_BYTES = 64 << 20
@@ -106,6 +108,17 @@ class flip_step_stats(ctypes.Structure):
                 ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
+class flip_batch_slots(ctypes.Structure):
+    _fields_ = [("nslots", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("max_nx", ctypes.c_int32), ("max_ny", ctypes.c_int32), ("max_nz", ctypes.c_int32)]
+
+
+class flip_batch_info(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64), ("table_uploads", ctypes.c_int64),
+                ("nslots", ctypes.c_int32), ("occupied", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -142,10 +155,18 @@ def load():
                                           i64p, vp]
         lib.flip_surface_mesh_noalloc.argtypes = [vp, vp, i32, vp, vp, ctypes.c_int64, vp, ctypes.c_int64, i64p,
                                                   i64p, vp]
+        specp = ctypes.POINTER(flip_batch_slots)
+        lib.flip_batch_slots_workspace_bytes.argtypes = [specp, ctypes.POINTER(sz)]
+        lib.flip_batch_create_slots.argtypes = [specp, vp, sz, vp, vpp]
+        lib.flip_batch_attach.argtypes = [vp, i32, vp]
+        lib.flip_batch_detach.argtypes = [vp, i32]
+        lib.flip_batch_get_info.argtypes = [vp, ctypes.POINTER(flip_batch_info)]
         for name in ["flip_workspace_bytes", "flip_init", "flip_step", "flip_field_bytes",
                      "flip_readback", "flip_stats", "flip_batch_workspace_bytes", "flip_batch_create",
                      "flip_batch_step", "flip_surface_field_bytes", "flip_surface_field",
-                     "flip_surface_mesh_workspace_bytes", "flip_surface_mesh", "flip_surface_mesh_noalloc"]:
+                     "flip_surface_mesh_workspace_bytes", "flip_surface_mesh", "flip_surface_mesh_noalloc",
+                     "flip_batch_slots_workspace_bytes", "flip_batch_create_slots", "flip_batch_attach",
+                     "flip_batch_detach", "flip_batch_get_info"]:
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -296,6 +317,34 @@ def flip_batch_destroy(b):
     load().flip_batch_destroy(b)
 
 
+def flip_batch_slots_workspace_bytes(spec: flip_batch_slots) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().flip_batch_slots_workspace_bytes(ctypes.byref(spec), ctypes.byref(out)),
+           "flip_batch_slots_workspace_bytes")
+    return out.value
+
+
+def flip_batch_create_slots(spec: flip_batch_slots, ws_ptr: int, ws_bytes: int, stream: int):
+    b = ctypes.c_void_p(0)
+    _check(load().flip_batch_create_slots(ctypes.byref(spec), ctypes.c_void_p(ws_ptr), ws_bytes,
+                                          ctypes.c_void_p(stream), ctypes.byref(b)), "flip_batch_create_slots")
+    return b
+
+
+def flip_batch_attach(b, slot: int, h):
+    _check(load().flip_batch_attach(b, int(slot), h), "flip_batch_attach")
+
+
+def flip_batch_detach(b, slot: int):
+    _check(load().flip_batch_detach(b, int(slot)), "flip_batch_detach")
+
+
+def flip_batch_get_info(b) -> flip_batch_info:
+    out = flip_batch_info()
+    _check(load().flip_batch_get_info(b, ctypes.byref(out)), "flip_batch_get_info")
+    return out
+
+
 # --------------------------------------------------------------------------
 # convenience wrapper used by the tests and the benchmark
 # --------------------------------------------------------------------------
@@ -437,6 +486,52 @@ class Simulation:
         if self.h is not None:
             flip_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SlotBatch:
+    """A slot batch (continuous batching) plus its torch-allocated table workspace:
+    Simulations join with attach() and leave with detach() between steps."""
+
+    def __init__(self, nslots: int, precision: int = FLIP_FP32, multigrid: bool = False, graphs: bool = True,
+                 max_dims=(96, 96, 96), stream=None, device: str = "cuda"):
+        import torch
+
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        flags = (FLIP_BATCH_GRAPHS if graphs else 0) | (FLIP_BATCH_MULTIGRID if multigrid else 0)
+        self.spec = flip_batch_slots(int(nslots), int(precision), flags, *[int(d) for d in max_dims])
+        self.ws_bytes = flip_batch_slots_workspace_bytes(self.spec)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.b = flip_batch_create_slots(self.spec, ptr, self.ws_bytes, self.stream.cuda_stream)
+        self.sims = [None] * int(nslots)
+
+    def attach(self, slot: int, sim):
+        flip_batch_attach(self.b, slot, sim.h)
+        self.sims[slot] = sim
+
+    def detach(self, slot: int):
+        flip_batch_detach(self.b, slot)
+        self.sims[slot] = None
+
+    def free_slot(self) -> int:
+        return self.sims.index(None)
+
+    def step(self, nsteps: int = 1, allow=()):
+        return flip_batch_step(self.b, nsteps, self.stream.cuda_stream, allow)
+
+    def info(self) -> flip_batch_info:
+        return flip_batch_get_info(self.b)
+
+    def close(self):
+        if self.b is not None:
+            flip_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

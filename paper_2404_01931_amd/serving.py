@@ -6,14 +6,19 @@ workspace (flip_workspace_bytes) fits in what is left of the HBM budget; a
 request larger than the whole budget is rejected. Admitted scenes are
 initialised by a preparation thread on a stream of its own, so host-side
 seeding and upload overlap the steps of the scenes already on the GPU, and
-join the running batch at the next step boundary. Every step advances all
-resident scenes together with one batched step (flip_batch_step: one launch
-per kernel for all scenes); scenes that have taken their steps leave at the
-step boundary and return their memory to the budget.
+join the running batch at the next step boundary. The batch is one
+persistent slot batch (flip_batch_create_slots), made once: a scene joins by
+taking a free slot (flip_batch_attach) and leaves by freeing it
+(flip_batch_detach), so membership changes rebuild nothing and the batch's
+recorded graphs are replayed throughout. Every step advances all resident
+scenes together with one batched step (flip_batch_step: one launch per kernel
+for all scenes); scenes that have taken their steps leave at the step
+boundary and return their memory to the budget.
 
 Reported: per scene-step latency (the wall time of the batched step it took
 part in) p50 / p99, end-to-end scene latency (arrival to last step), queueing
-delay, aggregate particle-steps/s over the run, peak resident bytes and scenes.
+delay, aggregate particle-steps/s over the run, peak resident bytes and
+scenes, slot changes, and the batch's graph replays and table uploads.
 
 The GPU work is done by a backend: FlipBackend drives libflipmi through its C
 ABI; tests of the scheduling logic use a backend of their own.
@@ -61,8 +66,10 @@ class ServeReport:
     queue_delay_s: list = field(default_factory=list)     # arrival -> admission, per scene
     peak_bytes: int = 0
     peak_scenes: int = 0
-    batch_rebuilds: int = 0
+    batch_rebuilds: int = 0     # batches made (one persistent slot batch per run)
+    slot_changes: int = 0       # scenes attached to or detached from the batch
     status_errors: int = 0
+    batch_info: dict = field(default_factory=dict)
 
     def summary(self) -> dict:
         # every scene-step of a batched step waits for the whole step: weight by scenes
@@ -82,7 +89,8 @@ class ServeReport:
             "batched_steps": len(self.step_latency_ms),
             "mean_resident_scenes": float(np.mean(self.step_scenes)) if self.step_scenes else 0.0,
             "peak_resident_scenes": self.peak_scenes, "peak_resident_bytes": self.peak_bytes,
-            "batch_rebuilds": self.batch_rebuilds, "status_errors": self.status_errors,
+            "batch_rebuilds": self.batch_rebuilds, "slot_changes": self.slot_changes,
+            "status_errors": self.status_errors, **self.batch_info,
         }
 
 
@@ -108,7 +116,8 @@ class Server:
         used = 0
         rep = ServeReport(n_requests=len(reqs), n_completed=0, n_rejected=0, wall_s=0.0, particle_steps=0)
         batch = None
-        members: tuple = ()
+        slot_of: dict[int, int] = {}        # resident scene (rid) -> its slot in the batch
+        free_slots = list(range(self.max_slots - 1, -1, -1))
         pool = ThreadPoolExecutor(max_workers=self.prep_threads, initializer=be.prep_thread_init)
         t0 = self.clock()
         try:
@@ -146,13 +155,14 @@ class Server:
                     elif pending and not queue:
                         time.sleep(max(0.0, min(pending[0].arrival - (self.clock() - t0), 0.05)))
                     continue
-                key = tuple(id(s.state) for s in resident)
-                if batch is None or key != members:
-                    if batch is not None:
-                        be.close_batch(batch)
-                    batch = be.make_batch([s.state for s in resident])
-                    members = key
+                if batch is None:
+                    batch = be.open_batch(self.max_slots)
                     rep.batch_rebuilds += 1
+                for s in resident:
+                    if s.req.rid not in slot_of:
+                        slot_of[s.req.rid] = free_slots.pop()
+                        be.attach(batch, slot_of[s.req.rid], s.state)
+                        rep.slot_changes += 1
                 rep.peak_scenes = max(rep.peak_scenes, len(resident))
                 ts = self.clock()
                 ok = be.step(batch)
@@ -166,18 +176,20 @@ class Server:
                     s.done_steps += 1
                     rep.particle_steps += s.n_particles
                     (done if s.done_steps >= s.req.steps else left).append(s)
-                if done:
-                    # the batch goes before the handles it refers to
-                    be.close_batch(batch)
-                    batch = None
-                    for s in done:
-                        rep.n_completed += 1
-                        rep.scene_latency_s.append(te - t0 - s.req.arrival)
-                        be.finish(s.state)
-                        used -= s.nbytes
+                for s in done:
+                    # the scene leaves the batch before its handle goes
+                    slot = slot_of.pop(s.req.rid)
+                    be.detach(batch, slot)
+                    free_slots.append(slot)
+                    rep.slot_changes += 1
+                    rep.n_completed += 1
+                    rep.scene_latency_s.append(te - t0 - s.req.arrival)
+                    be.finish(s.state)
+                    used -= s.nbytes
                 resident = left
         finally:
             if batch is not None:
+                rep.batch_info = be.batch_info(batch)
                 be.close_batch(batch)
             pool.shutdown(wait=True)
         rep.wall_s = self.clock() - t0
@@ -187,7 +199,8 @@ class Server:
 class FlipBackend:
     """Scenes of paper_2404_01931_amd.inputs run by libflipmi on the current GPU."""
 
-    def __init__(self, graphs: bool = True, precision=None, keep_results: bool = False, multigrid: bool = False):
+    def __init__(self, graphs: bool = True, precision=None, keep_results: bool = False, multigrid: bool = False,
+                 max_dims=(96, 96, 96)):
         import torch
 
         from . import flip
@@ -197,6 +210,8 @@ class FlipBackend:
         self.graphs = graphs
         self.precision = precision
         self.keep_results = keep_results
+        self.multigrid = multigrid
+        self.max_dims = tuple(max_dims)   # the largest scene grid the batch takes
         self.cfg_flags = flip.FLIP_FLAG_MULTIGRID if multigrid else 0
         self.results = {}   # scene name -> (pos, vel, ids) at completion, when keep_results
         self.stream = torch.cuda.Stream()   # default priority
@@ -231,8 +246,22 @@ class FlipBackend:
     def n_particles(self, sim) -> int:
         return sim.n
 
-    def make_batch(self, sims):
-        return self.flip.Batch(sims, flags=self.flip.FLIP_BATCH_GRAPHS if self.graphs else 0, stream=self.stream)
+    def open_batch(self, nslots: int):
+        f = self.flip
+        prec = f.FLIP_FP64 if self.precision == f.FLIP_FP64 else f.FLIP_FP32
+        return f.SlotBatch(nslots, precision=prec, multigrid=self.multigrid, graphs=self.graphs,
+                           max_dims=self.max_dims, stream=self.stream)
+
+    def attach(self, batch, slot: int, sim):
+        batch.attach(slot, sim)
+
+    def detach(self, batch, slot: int):
+        batch.detach(slot)
+
+    def batch_info(self, batch) -> dict:
+        i = batch.info()
+        return {"batch_steps": i.steps, "graph_launches": i.graph_launches, "graph_captures": i.graph_captures,
+                "table_uploads": i.table_uploads}
 
     def step(self, batch) -> bool:
         st = batch.step(1, allow=(self.flip.FLIP_E_NOT_CONVERGED,))

@@ -18,7 +18,8 @@ class RecordingBackend:
         self.live = {}
         self.steps_of = {}
         self.admit_order = []
-        self.open_batches = []
+        self.opened = 0
+        self.slots = None          # slot -> scene name of the open batch
 
     def workspace_bytes(self, scene):
         return scene["bytes"]
@@ -35,27 +36,41 @@ class RecordingBackend:
     def n_particles(self, st):
         return st["n"]
 
-    def make_batch(self, states):
-        b = [s["name"] for s in states]
-        self.open_batches.append(b)
-        return b
+    def open_batch(self, nslots):
+        assert self.slots is None, "one persistent batch per run"
+        self.opened += 1
+        self.slots = [None] * nslots
+        return self.slots
+
+    def attach(self, batch, slot, st):
+        assert batch is self.slots and batch[slot] is None and st["name"] not in batch
+        batch[slot] = st["name"]
+
+    def detach(self, batch, slot):
+        assert batch is self.slots and batch[slot] is not None
+        batch[slot] = None
+
+    def batch_info(self, batch):
+        return {}
 
     def step(self, batch):
         if self.step_s:
             time.sleep(self.step_s)
+        names = tuple(sorted(n for n in batch if n is not None))
         with self.lock:
-            self.batches.append(tuple(batch))
+            self.batches.append(names)
             self.resident_bytes.append(sum(self.live.values()))
-        for name in batch:
+        for name in names:
             self.steps_of[name] = self.steps_of.get(name, 0) + 1
         return True
 
     def close_batch(self, batch):
-        self.open_batches.remove(batch)
+        assert batch is self.slots
+        self.slots = None
 
     def finish(self, st):
-        # a batch refers to its scenes' handles: it must be closed first
-        assert all(st["name"] not in b for b in self.open_batches)
+        # a batch refers to its scenes' handles: a scene leaves it first
+        assert self.slots is None or st["name"] not in self.slots
         with self.lock:
             del self.live[st["name"]]
 
@@ -75,7 +90,8 @@ def test_every_request_completes_with_its_steps():
     s = rep.summary()
     assert s["scene_steps"] == 13 and s["step_latency_ms_p99"] >= s["step_latency_ms_p50"] >= 0.0
     assert len(rep.scene_latency_s) == 4 and len(rep.queue_delay_s) == 4
-    assert be.open_batches == []
+    assert be.slots is None and be.opened == 1 and rep.batch_rebuilds == 1
+    assert rep.slot_changes == 8   # every scene attached once and detached once
 
 
 def test_budget_and_slots_are_never_exceeded():
@@ -113,7 +129,8 @@ def test_late_arrivals_join_running_batches():
     assert rep.n_completed == 2
     joint = [b for b in be.batches if set(b) == {"s0", "s1"}]
     assert len(joint) == 2           # s1 stepped inside s0's batch, then left
-    assert rep.batch_rebuilds >= 3   # s0 alone, s0+s1, s0 alone again
+    assert rep.batch_rebuilds == 1   # the one batch throughout: s1 took a slot and gave it back
+    assert rep.slot_changes == 4
 
 
 def test_serving_workload_recipe():
