@@ -375,6 +375,118 @@ __device__ inline float cell_offset(float x, float inv_dx, int c)
     return x * inv_dx - (float)c;
 }
 
+// Eight consecutive floats of a lane's row in LDS (two 16-byte reads)
+__device__ inline void lds_load8(const float* p, float (&o)[P2G_BATCH])
+{
+    const float4 a = *(const float4*)p, b = *(const float4*)(p + 4);
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = a.z;
+    o[3] = a.w;
+    o[4] = b.x;
+    o[5] = b.y;
+    o[6] = b.z;
+    o[7] = b.w;
+}
+
+__device__ inline void lds_store8(float* p, const float (&v)[P2G_BATCH])
+{
+    *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+    *(float4*)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+}
+
+// Coordinates of the phase's particles shared by the workgroup's three waves:
+// [buffer][axis][lane][particle]; wave A loads axis A of its cell's particles
+// (and its own velocity component) and the others read it from LDS, so each
+// particle's position is read from memory once per phase instead of three times.
+constexpr int P2G_CRD = 2 * 3 * 64 * P2G_BATCH;
+
+// FP32 form of the component wave (see p2g_component): the three waves of the
+// workgroup take the phases in step, with a workgroup barrier per phase for
+// the shared coordinates.
+template <int A, bool DYADIC>
+__device__ __forceinline__ void p2g_phases_f32(const Geo& g, int lane, int x0, int y0, int z0, int rx0, int ry0,
+                                               int rz0, int rx1, int ry1, int rz1, const float* __restrict__ px,
+                                               const float* __restrict__ py, const float* __restrict__ pz,
+                                               const float* __restrict__ vc, const uint32_t* __restrict__ start,
+                                               const uint32_t* __restrict__ count, float (*acc)[2], float* crd)
+{
+#pragma clang fp contract(off)
+    const float* const pa = A == 0 ? px : (A == 1 ? py : pz);  // the axis this wave loads
+    const double inv = g.inv_dx, dx = g.dx;
+    const float invf = (float)inv;
+    auto row = [&](int buf, int axis) { return crd + ((buf * 3 + axis) * 64 + lane) * P2G_BATCH; };
+    int cxa, cya, cza, cxb, cyb, czb, cxc, cyc, czc;
+    int64_t c = phase_cell(g, 0, lane, rx0, ry0, rz0, rx1, ry1, rz1, cxa, cya, cza);
+    uint32_t s_a = start[c >= 0 ? c : 0], n_a = c >= 0 ? count[c] : 0u;
+    c = phase_cell(g, 1, lane, rx0, ry0, rz0, rx1, ry1, rz1, cxb, cyb, czb);
+    uint32_t s_b = start[c >= 0 ? c : 0], n_b = c >= 0 ? count[c] : 0u;
+    float Pv[P2G_BATCH], La[P2G_BATCH];
+    load8(pa, s_a, La);
+    load8(vc, s_a, Pv);
+    lds_store8(row(0, A), La);
+    lds_barrier();
+#pragma unroll 1
+    for (int ph = 0; ph < 27; ++ph) {
+        c = phase_cell(g, min(ph + 2, 26), lane, rx0, ry0, rz0, rx1, ry1, rz1, cxc, cyc, czc);
+        const uint32_t s_c = start[c >= 0 ? c : 0], n_c = c >= 0 ? count[c] : 0u;
+        // the next phase's axis and velocity, in flight while this phase is splatted
+        float Qa[P2G_BATCH], Qv[P2G_BATCH];
+        load8(pa, s_b, Qa);
+        load8(vc, s_b, Qv);
+        Window<A> win;
+#pragma unroll
+        for (int k = 0; k < Window<A>::NZ; ++k)
+#pragma unroll
+            for (int j = 0; j < Window<A>::NY; ++j)
+#pragma unroll
+                for (int i = 0; i < Window<A>::NX; ++i) win.W[k][j][i] = win.M[k][j][i] = 0.0f;
+        if (n_a > 0) {
+            float X[P2G_BATCH], Y[P2G_BATCH], Z[P2G_BATCH];
+            lds_load8(row(ph & 1, 0), X);
+            lds_load8(row(ph & 1, 1), Y);
+            lds_load8(row(ph & 1, 2), Z);
+            if constexpr (DYADIC) {
+#pragma unroll
+                for (int k = 0; k < P2G_BATCH; ++k) {
+                    if ((uint32_t)k < n_a)
+                        window_add_dyadic<A>(win, cell_offset(X[k], invf, cxa), cell_offset(Y[k], invf, cya),
+                                             cell_offset(Z[k], invf, cza), Pv[k]);
+                }
+                // cells holding more particles than a batch: the rest one by one
+                for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
+                    window_add_dyadic<A>(win, cell_offset(px[q], invf, cxa), cell_offset(py[q], invf, cya),
+                                         cell_offset(pz[q], invf, cza), vc[q]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < P2G_BATCH; ++k) {
+                    if ((uint32_t)k < n_a)
+                        window_add<A>(win, cxa, cya, cza, (double)X[k], (double)Y[k], (double)Z[k], dx, inv, Pv[k]);
+                }
+                for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
+                    window_add<A>(win, cxa, cya, cza, (double)px[q], (double)py[q], (double)pz[q], dx, inv, vc[q]);
+            }
+            window_flush<A>(win, acc, cxa, cya, cza, x0, y0, z0);
+        }
+        // the next phase's axis goes to the other buffer, which every wave
+        // finished reading before the last barrier
+        lds_store8(row((ph + 1) & 1, A), Qa);
+        lds_barrier();
+        cxa = cxb;
+        cya = cyb;
+        cza = czb;
+        cxb = cxc;
+        cyb = cyc;
+        czb = czc;
+#pragma unroll
+        for (int k = 0; k < P2G_BATCH; ++k) Pv[k] = Qv[k];
+        s_a = s_b;
+        n_a = n_b;
+        s_b = s_c;
+        n_b = n_c;
+    }
+}
+
 // One wave of the workgroup: component A of the block's faces. DYADIC: dx is
 // a power of two (FP32 hat weights from exact in-cell offsets).
 template <typename T, int A, bool DYADIC>
@@ -384,7 +496,7 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
                                               const uint32_t* __restrict__ start,
                                               const uint32_t* __restrict__ count,
                                               const uint32_t* __restrict__ tile_flag, T gdt, T (*acc)[2],
-                                              T* __restrict__ f_old, T* __restrict__ f_star)
+                                              T* __restrict__ f_old, T* __restrict__ f_star, float* crd)
 {
 #pragma clang fp contract(off)
     for (int q = lane; q < P2G_BOX * 2; q += 64) (&acc[0][0])[q] = T(0);
@@ -393,7 +505,14 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
     const int ry0 = max(y0 - 1, 0), ry1 = min(y0 + P2G_T, g.ny - 1);
     const int rz0 = max(z0 - 1, 0), rz1 = min(z0 + P2G_T, g.nz - 1);
     const double inv = g.inv_dx, dx = g.dx;
-    if (n > 0 && ring_has_particles(g, tile_flag, lane, rx0, ry0, rz0, rx1, ry1, rz1)) {
+    // (the same decision in the workgroup's three waves: they share barriers)
+    const bool work = n > 0 && ring_has_particles(g, tile_flag, lane, rx0, ry0, rz0, rx1, ry1, rz1);
+    if constexpr (sizeof(T) == 4) {
+        if (work)
+            p2g_phases_f32<A, DYADIC>(g, lane, x0, y0, z0, rx0, ry0, rz0, rx1, ry1, rz1, (const float*)px,
+                                      (const float*)py, (const float*)pz, (const float*)vc, start, count,
+                                      (float (*)[2])acc, crd);
+    } else if (work) {
         // Software pipeline over the 27 phases: the cell range of phase
         // ph + 2 and the particles of phase ph + 1 are loaded while phase ph
         // is splatted. The wave's LDS operations run in issue order, so the
@@ -411,39 +530,7 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
             const uint32_t s_c = start[c >= 0 ? c : 0], n_c = c >= 0 ? count[c] : 0u;
             CellParticles<T> Q;
             load_cell(Q, px, py, pz, vc, s_b);
-            if constexpr (sizeof(T) == 4) {
-                Window<A> win;
-#pragma unroll
-                for (int k = 0; k < Window<A>::NZ; ++k)
-#pragma unroll
-                    for (int j = 0; j < Window<A>::NY; ++j)
-#pragma unroll
-                        for (int i = 0; i < Window<A>::NX; ++i) win.W[k][j][i] = win.M[k][j][i] = 0.0f;
-                if constexpr (DYADIC) {
-                    const float invf = (float)inv;
-#pragma unroll
-                    for (int k = 0; k < P2G_BATCH; ++k) {
-                        if ((uint32_t)k < n_a)
-                            window_add_dyadic<A>(win, cell_offset(P.x[k], invf, cxa), cell_offset(P.y[k], invf, cya),
-                                                 cell_offset(P.z[k], invf, cza), P.v[k]);
-                    }
-                    // cells holding more particles than a batch: the rest one by one
-                    for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
-                        window_add_dyadic<A>(win, cell_offset(px[q], invf, cxa), cell_offset(py[q], invf, cya),
-                                             cell_offset(pz[q], invf, cza), vc[q]);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < P2G_BATCH; ++k) {
-                        if ((uint32_t)k < n_a)
-                            window_add<A>(win, cxa, cya, cza, (double)P.x[k], (double)P.y[k], (double)P.z[k], dx,
-                                          inv, P.v[k]);
-                    }
-                    for (uint32_t q = s_a + P2G_BATCH; q < s_a + n_a; ++q)
-                        window_add<A>(win, cxa, cya, cza, (double)px[q], (double)py[q], (double)pz[q], dx, inv,
-                                      vc[q]);
-                }
-                if (n_a > 0) window_flush<A>(win, acc, cxa, cya, cza, x0, y0, z0);
-            } else {
+            {
 #pragma unroll
                 for (int k = 0; k < P2G_BATCH; ++k) {
                     if ((uint32_t)k < n_a)
@@ -490,9 +577,11 @@ __device__ __forceinline__ void p2g_component(Geo g, int64_t n, int lane, int x0
 }
 
 // Three waves per block, wave a for velocity component a: each wave owns its
-// component's samples, so the waves share no LDS word and need no barrier;
-// per wave the block's LDS and registers hold one component, which keeps
-// three times as many waves resident as one wave doing all three.
+// component's samples (no LDS word of the sums is shared), and per wave the
+// block's LDS and registers hold one component, which keeps three times as
+// many waves resident as one wave doing all three. In FP32 the waves share the
+// phase's particle coordinates through LDS (wave a loads axis a), with one
+// workgroup barrier per phase; in FP64 each wave loads all three itself.
 static_assert(P2G_NT == 3 * 64, "one wave per velocity component");
 
 template <typename T, bool DY>
@@ -505,7 +594,7 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
                                          T* __restrict__ u_old, T* __restrict__ v_old,
                                          T* __restrict__ w_old, T* __restrict__ u_star,
                                          T* __restrict__ v_star, T* __restrict__ w_star,
-                                         T (*acc)[P2G_BOX + 1][2])
+                                         T (*acc)[P2G_BOX + 1][2], float* crd)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // Rows of blocks (fixed y, z) are dealt to the 8 XCDs in turn (workgroup
@@ -524,11 +613,11 @@ __device__ __forceinline__ void p2g_body(Blk b, Geo g, int64_t n, const T* __res
     const int bx = L % nbx, by = (L / nbx) % nby, bz = L / (nbx * nby);
     const int x0 = bx * P2G_T, y0 = by * P2G_T, z0 = bz * P2G_T;
     if (wv == 0)
-        p2g_component<T, 0, DY>(g, n, lane, x0, y0, z0, px, py, pz, vx, start, count, tile_flag, gdt_x, acc[0], u_old, u_star);
+        p2g_component<T, 0, DY>(g, n, lane, x0, y0, z0, px, py, pz, vx, start, count, tile_flag, gdt_x, acc[0], u_old, u_star, crd);
     else if (wv == 1)
-        p2g_component<T, 1, DY>(g, n, lane, x0, y0, z0, px, py, pz, vy, start, count, tile_flag, gdt_y, acc[1], v_old, v_star);
+        p2g_component<T, 1, DY>(g, n, lane, x0, y0, z0, px, py, pz, vy, start, count, tile_flag, gdt_y, acc[1], v_old, v_star, crd);
     else
-        p2g_component<T, 2, DY>(g, n, lane, x0, y0, z0, px, py, pz, vz, start, count, tile_flag, gdt_z, acc[2], w_old, w_star);
+        p2g_component<T, 2, DY>(g, n, lane, x0, y0, z0, px, py, pz, vz, start, count, tile_flag, gdt_z, acc[2], w_old, w_star, crd);
 }
 
 // FP32 particles on a power-of-two spacing take the FP32 weights (the same values)
@@ -536,10 +625,11 @@ template <typename T, typename... Args>
 __device__ __forceinline__ void p2g_dispatch(Blk b, const Geo& g, Args... args)
 {
     __shared__ T acc[3][P2G_BOX + 1][2];  // one LDS block for both forms; a spare sample per component
+    __shared__ float crd[sizeof(T) == 4 ? P2G_CRD : 1];  // FP32: the phase's shared coordinates
     if (sizeof(T) == 4 && g.dyadic)
-        p2g_body<T, sizeof(T) == 4>(b, g, args..., acc);
+        p2g_body<T, sizeof(T) == 4>(b, g, args..., acc, crd);
     else
-        p2g_body<T, false>(b, g, args..., acc);
+        p2g_body<T, false>(b, g, args..., acc, crd);
 }
 
 template <typename T>
