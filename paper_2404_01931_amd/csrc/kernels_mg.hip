@@ -550,12 +550,16 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
     // 256^3) run 1024-thread workgroups, larger ones 512 (256 threads for
     // all: 1.69 ms per step for the coarse levels at 256^3; 1024 for the
     // small ones: 1.44; 512 for the 128^3 level: 1.32, where 1024 was slower)
-    // (the shape is chosen by the level's whole block count; the grid runs the
-    // listed blocks only)
+    // (the shape is chosen by the level's whole block count). Launches of
+    // 512 workgroups or more run the listed blocks only; the smaller ones run
+    // every block: there the list's extra dependent load cost more (about
+    // 0.2 us per launch) than the few air blocks it saved.
     constexpr int64_t SMALL = 512;
     for (int l = 0; l + 1 < nlev; ++l) {
-        const MgLevel& c = lv[l + 1];
-        const int64_t nb = mg_down_blocks(c), grid = c.dlist ? c.nd : nb;
+        MgLevel c = lv[l + 1];
+        const int64_t nb = mg_down_blocks(c);
+        if (nb < SMALL) c.dlist = nullptr;
+        const int64_t grid = c.dlist ? c.nd : nb;
         if (grid <= 0) continue;
         if (nb < SMALL)
             hipLaunchKernelGGL((k_mg_down<V, 1024>), dim3((unsigned)grid), dim3(1024), 0, st, lv[l], c, ps);
@@ -564,8 +568,10 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
     }
     hipLaunchKernelGGL(k_mg_bottom<V>, dim3(1), dim3(512), 0, st, lv[nlev - 1], ps);
     for (int l = nlev - 2; l >= 0; --l) {
-        const MgLevel& f = lv[l];
-        const int64_t nb = mg_up_blocks(f), grid = f.ulist ? f.nu : nb;
+        MgLevel f = lv[l];
+        const int64_t nb = mg_up_blocks(f);
+        if (nb < SMALL) f.ulist = nullptr;
+        const int64_t grid = f.ulist ? f.nu : nb;
         if (grid <= 0) continue;
         if (nb < SMALL)
             hipLaunchKernelGGL((k_mg_up<V, 1024>), dim3((unsigned)grid), dim3(1024), 0, st, f, lv[l + 1], ps);
