@@ -423,6 +423,15 @@ __device__ __forceinline__ void bin_gather_body(
     const int64_t s = (int64_t)b.id * 256 + threadIdx.x;
     if (s >= n) return;
     const uint32_t p = perm[s];
+    // the particle's state is read while its slot is worked out (those
+    // loads do not depend on the rank)
+    T pv[3], vv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        pv[a] = pos_in[a * n + p];
+        vv[a] = vel_in[a * n + p];
+    }
+    const uint32_t idv = id_in[p];
     const uint32_t c = key[p];
     const uint32_t st = start[c];
     const uint32_t cnt = count[c];
@@ -441,10 +450,10 @@ __device__ __forceinline__ void bin_gather_body(
     const int64_t m = SPREAD ? n_out : n;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        pos_out[a * m + d] = pos_in[a * n + p];
-        vel_out[a * m + d] = vel_in[a * n + p];
+        pos_out[a * m + d] = pv[a];
+        vel_out[a * m + d] = vv[a];
     }
-    id_out[d] = id_in[p];
+    id_out[d] = idv;
 }
 
 template <typename T>

@@ -375,10 +375,13 @@ __device__ inline float cell_offset(float x, float inv_dx, int c)
     return x * inv_dx - (float)c;
 }
 
-// Eight consecutive floats of a lane's row in LDS (two 16-byte reads)
+// A lane's eight floats in LDS, stored as two groups of four whose groups
+// for the 64 lanes are contiguous (lane l at p + 4 l and p + 256 + 4 l), so a
+// wave's 16-byte reads cover consecutive banks (a lane's eight floats side by
+// side would put lanes l and l + 4 on the same banks)
 __device__ inline void lds_load8(const float* p, float (&o)[P2G_BATCH])
 {
-    const float4 a = *(const float4*)p, b = *(const float4*)(p + 4);
+    const float4 a = *(const float4*)p, b = *(const float4*)(p + 4 * 64);
     o[0] = a.x;
     o[1] = a.y;
     o[2] = a.z;
@@ -392,11 +395,11 @@ __device__ inline void lds_load8(const float* p, float (&o)[P2G_BATCH])
 __device__ inline void lds_store8(float* p, const float (&v)[P2G_BATCH])
 {
     *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
-    *(float4*)(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+    *(float4*)(p + 4 * 64) = make_float4(v[4], v[5], v[6], v[7]);
 }
 
 // Coordinates of the phase's particles shared by the workgroup's three waves:
-// [buffer][axis][lane][particle]; wave A loads axis A of its cell's particles
+// [buffer][axis][particle group of four][lane][4]; wave A loads axis A of its cell's particles
 // (and its own velocity component) and the others read it from LDS, so each
 // particle's position is read from memory once per phase instead of three times.
 constexpr int P2G_CRD = 2 * 3 * 64 * P2G_BATCH;
@@ -415,7 +418,7 @@ __device__ __forceinline__ void p2g_phases_f32(const Geo& g, int lane, int x0, i
     const float* const pa = A == 0 ? px : (A == 1 ? py : pz);  // the axis this wave loads
     const double inv = g.inv_dx, dx = g.dx;
     const float invf = (float)inv;
-    auto row = [&](int buf, int axis) { return crd + ((buf * 3 + axis) * 64 + lane) * P2G_BATCH; };
+    auto row = [&](int buf, int axis) { return crd + (buf * 3 + axis) * 64 * P2G_BATCH + 4 * lane; };
     int cxa, cya, cza, cxb, cyb, czb, cxc, cyc, czc;
     int64_t c = phase_cell(g, 0, lane, rx0, ry0, rz0, rx1, ry1, rz1, cxa, cya, cza);
     uint32_t s_a = start[c >= 0 ? c : 0], n_a = c >= 0 ? count[c] : 0u;
