@@ -420,9 +420,17 @@ __device__ __forceinline__ void bin_gather_body(
     T* __restrict__ pos_out, T* __restrict__ vel_out, uint32_t* __restrict__ id_out,
     const uint32_t* __restrict__ spread = nullptr, int64_t n_out = 0)
 {
-    const int64_t s = (int64_t)b.id * 256 + threadIdx.x;
-    if (s >= n) return;
-    const uint32_t p = perm[s];
+    // the workgroup's 256 slots of the provisional order, staged in LDS: a
+    // cell's slots are mostly among them, and the rank below reads them from
+    // there (the few outside the workgroup's range from memory)
+    __shared__ uint32_t slots[256];
+    const int64_t s0 = (int64_t)b.id * 256;
+    const int64_t s = s0 + threadIdx.x;
+    const bool live = s < n;
+    const uint32_t p = live ? perm[s] : 0u;
+    slots[threadIdx.x] = p;
+    __syncthreads();
+    if (!live) return;
     // the particle's state is read while its slot is worked out (those
     // loads do not depend on the rank)
     T pv[3], vv[3];
@@ -435,14 +443,17 @@ __device__ __forceinline__ void bin_gather_body(
     const uint32_t c = key[p];
     const uint32_t st = start[c];
     const uint32_t cnt = count[c];
-    // the cell's slots are read four at a time (indices clamped into the
-    // cell), so a lane waits for one round trip per four particles
+    // the cell's slots four at a time (indices clamped into the cell)
     const uint32_t end = st + cnt;
+    const uint32_t base = (uint32_t)s0;
     uint32_t r = 0;
     for (uint32_t q = st; q < end; q += 4) {
         uint32_t v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = perm[min(q + k, end - 1)];
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t qq = min(q + k, end - 1);
+            v[k] = qq - base < 256u ? slots[qq - base] : perm[qq];
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) r += (q + k < end && v[k] < p) ? 1u : 0u;
     }
