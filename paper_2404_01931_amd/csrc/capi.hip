@@ -551,7 +551,8 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     // 1. binning
     int tq = timer_begin(h, FLIP_KERNEL_BIN_KEYS, st);
     launch_fill_u32(h->count, s.C, 0u, st);
-    launch_bin_keys<T>(g, (const T*)h->pos[h->cur], n, h->key, h->rank, h->count, st);
+    launch_fill_u32(h->tile_flag, s.T, 0u, st);
+    launch_bin_keys<T>(g, (const T*)h->pos[h->cur], n, h->key, h->rank, h->count, st, h->tile_flag);
     timer_end(h, tq, st);
     tq = timer_begin(h, FLIP_KERNEL_BIN_SCAN, st);
     launch_exclusive_scan_u32(h->count, h->start, s.C, h->scan_tmp, st);
@@ -596,7 +597,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
     h->cur = nxt;
     tq = timer_begin(h, FLIP_KERNEL_TILES, st);
     launch_tiles(g, h->count, h->tile_flag, h->tile_excl, h->tile_slot, h->tile_list, h->tile_nbr,
-                 h->d_nactive, h->scan_tmp, st);
+                 h->d_nactive, h->scan_tmp, st, true);
     timer_end(h, tq, st);
 
     // 2. particle-to-grid, gravity, walls

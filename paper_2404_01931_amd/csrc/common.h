@@ -118,9 +118,11 @@ void launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 void launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t st);
 void launch_fill_bytes_zero(void* p, int64_t bytes, hipStream_t st);
 
+// tile_flag (optional, cleared by the caller): set for every 8^3 tile that
+// receives a particle, the flags launch_tiles would otherwise derive from count
 template <typename T>
 void launch_bin_keys(const Geo& g, const T* pos, int64_t n, uint32_t* key, uint32_t* rank,
-                     uint32_t* count, hipStream_t st);
+                     uint32_t* count, hipStream_t st, uint32_t* tile_flag = nullptr);
 // exclusive scan of n u32 values; tmp needs scan_tmp_words(n) u32 words
 int64_t scan_tmp_words(int64_t n);
 void launch_exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp,
@@ -174,10 +176,10 @@ void launch_mc_emit(const T* phi, int cx, int cy, int cz, double h, const McTabl
                     int64_t nv, int64_t nt, T* verts, T* normals, int32_t* tris, hipStream_t st);
 
 // tiles: flags -> scan -> compaction -> neighbour table; writes the active
-// count to *d_nactive
+// count to *d_nactive (flags_set: the binning already set the flags)
 void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint32_t* tile_excl,
                   int32_t* tile_slot, uint32_t* tile_list, int32_t* tile_nbr, uint32_t* d_nactive,
-                  uint32_t* scan_tmp, hipStream_t st);
+                  uint32_t* scan_tmp, hipStream_t st, bool flags_set = false);
 
 // red-black Gauss-Seidel (FLIP_FLAG_RED_BLACK_GS): `iters` iterations (a red
 // and a black pass each) over the n_active tiles, and max |b - A p| over the

@@ -87,7 +87,8 @@ __device__ __forceinline__ void bin_keys_body(Blk b, Geo g, const T* __restrict_
                                               const T* __restrict__ py, const T* __restrict__ pz,
                                               int64_t n, uint32_t* __restrict__ key,
                                               uint32_t* __restrict__ rank,
-                                              uint32_t* __restrict__ count)
+                                              uint32_t* __restrict__ count,
+                                              uint32_t* __restrict__ tile_flag = nullptr)
 {
     const int64_t p = (int64_t)b.id * 256 + threadIdx.x;
     if (p >= n) return;
@@ -121,7 +122,12 @@ __device__ __forceinline__ void bin_keys_body(Blk b, Geo g, const T* __restrict_
     const uint64_t after = heads & above & live;
     const int end = after ? __ffsll((unsigned long long)after) - 1 : 64 - __clzll((unsigned long long)live);
     uint32_t base = 0;
-    if (head) base = atomicAdd(&count[c], (uint32_t)(end - lane));
+    if (head) {
+        base = atomicAdd(&count[c], (uint32_t)(end - lane));
+        // the 8^3 tile holds a particle (flags cleared before the launch; every
+        // writer stores the same value)
+        if (tile_flag) tile_flag[(i >> 3) + (int64_t)g.tx * ((j >> 3) + (int64_t)g.ty * (k >> 3))] = 1u;
+    }
     // this lane's run starts at the highest head at or below it
     const uint64_t upto = lane == WAVE - 1 ? ~0ull : (~0ull >> (WAVE - 1 - lane));
     const int first = 63 - __clzll((unsigned long long)(heads & upto));
@@ -135,9 +141,10 @@ __global__ __launch_bounds__(256) void k_bin_keys(Geo g, const T* __restrict__ p
                                                   const T* __restrict__ py, const T* __restrict__ pz,
                                                   int64_t n, uint32_t* __restrict__ key,
                                                   uint32_t* __restrict__ rank,
-                                                  uint32_t* __restrict__ count)
+                                                  uint32_t* __restrict__ count,
+                                                  uint32_t* __restrict__ tile_flag)
 {
-    bin_keys_body<T>(plain_blk(), g, px, py, pz, n, key, rank, count);
+    bin_keys_body<T>(plain_blk(), g, px, py, pz, n, key, rank, count, tile_flag);
 }
 
 template <typename T>
@@ -161,17 +168,17 @@ template void launch_b_bin_keys<double>(const BatchLaunch&, hipStream_t);
 
 template <typename T>
 void launch_bin_keys(const Geo& g, const T* pos, int64_t n, uint32_t* key, uint32_t* rank,
-                     uint32_t* count, hipStream_t st)
+                     uint32_t* count, hipStream_t st, uint32_t* tile_flag)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_bin_keys<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, pos,
-                       pos + n, pos + 2 * n, n, key, rank, count);
+                       pos + n, pos + 2 * n, n, key, rank, count, tile_flag);
 }
 
 template void launch_bin_keys<float>(const Geo&, const float*, int64_t, uint32_t*, uint32_t*,
-                                     uint32_t*, hipStream_t);
+                                     uint32_t*, hipStream_t, uint32_t*);
 template void launch_bin_keys<double>(const Geo&, const double*, int64_t, uint32_t*, uint32_t*,
-                                      uint32_t*, hipStream_t);
+                                      uint32_t*, hipStream_t, uint32_t*);
 
 // ---------------------------------------------------------------------------
 // exclusive scan of u32 (all-prefix-sums with identity 0, Sec. 3.2.2)
@@ -758,10 +765,10 @@ void launch_b_tile_compact(const BatchLaunch& L, hipStream_t st)
 
 void launch_tiles(const Geo& g, const uint32_t* count, uint32_t* tile_flag, uint32_t* tile_excl,
                   int32_t* tile_slot, uint32_t* tile_list, int32_t* tile_nbr, uint32_t* d_nactive,
-                  uint32_t* scan_tmp, hipStream_t st)
+                  uint32_t* scan_tmp, hipStream_t st, bool flags_set)
 {
     const int64_t T = tiles_of(g);
-    hipLaunchKernelGGL(k_tile_flags, dim3((unsigned)T), dim3(256), 0, st, g, count, tile_flag);
+    if (!flags_set) hipLaunchKernelGGL(k_tile_flags, dim3((unsigned)T), dim3(256), 0, st, g, count, tile_flag);
     launch_exclusive_scan_u32(tile_flag, tile_excl, T, scan_tmp, st);
     hipLaunchKernelGGL(k_tile_compact, dim3((unsigned)((T + 255) / 256)), dim3(256), 0, st, g,
                        tile_flag, tile_excl, tile_slot, tile_list, tile_nbr, d_nactive);

@@ -469,19 +469,21 @@ __device__ __forceinline__ void mg_types_block(Blk b, const MgLevel& c, Fluid is
     }
 }
 
-// level 1 from the fine grid's n_c (tile layout): fluid when a child is
+// level 1 from the fine grid's n_c (tile layout): fluid when a child is.
+// The 2x2x2 children of a level-1 cell lie in one 8^3 tile (even offsets),
+// where they are four x-adjacent byte pairs; cells of an active tile outside
+// the domain hold n_c = 0, and an inactive tile holds no fluid cell.
 __device__ __forceinline__ void mg_types_fine_body(Blk b, const Geo& g, const int32_t* __restrict__ tile_slot,
                                                    const uint8_t* __restrict__ diag, const MgLevel& c)
 {
     mg_types_block(b, c, [&](int i, int j, int k) {
-        bool fluid = false;
-        for (int o = 0; o < 8; ++o) {
-            const int gi = 2 * i + (o & 1), gj = 2 * j + ((o >> 1) & 1), gk = 2 * k + (o >> 2);
-            if (gi >= g.nx || gj >= g.ny || gk >= g.nz) continue;
-            const int32_t s = tile_slot[(gi >> 3) + (int64_t)g.tx * ((gj >> 3) + (int64_t)g.ty * (gk >> 3))];
-            if (s >= 0 && diag[(int64_t)s * TILE_CELLS + (gi & 7) + 8 * (gj & 7) + 64 * (gk & 7)] > 0) fluid = true;
-        }
-        return fluid;
+        const int gi = 2 * i, gj = 2 * j, gk = 2 * k;
+        const int32_t s = tile_slot[(gi >> 3) + (int64_t)g.tx * ((gj >> 3) + (int64_t)g.ty * (gk >> 3))];
+        if (s < 0) return false;
+        const uint8_t* d = diag + (int64_t)s * TILE_CELLS + (gi & 7) + 8 * (gj & 7) + 64 * (gk & 7);
+        const uint16_t p00 = *(const uint16_t*)d, p10 = *(const uint16_t*)(d + 8);
+        const uint16_t p01 = *(const uint16_t*)(d + 64), p11 = *(const uint16_t*)(d + 72);
+        return ((p00 | p10) | (p01 | p11)) != 0;
     });
 }
 
