@@ -701,17 +701,15 @@ flip_status run_step(flip_handle* h, hipStream_t st)
         }
         // 5. projection with the solution (FP64 when MIXED)
         const T scale = (T)(dt / (c.density * c.dx));
-        for (int a = 0; a < 3; ++a) {
-            tq = timer_begin(h, FLIP_KERNEL_PROJECT, st);
-            if (MIXED)
-                launch_project<float, double>(g, a, h->diag, h->tile_slot, h->x64[h->xi],
-                                              (const float*)h->f_star[a], (float*)h->f_new[a],
-                                              dt / (c.density * c.dx), st);
-            else
-                launch_project<T, T>(g, a, h->diag, h->tile_slot, (const T*)h->xin[h->xi],
-                                     (const T*)h->f_star[a], (T*)h->f_new[a], scale, st);
-            timer_end(h, tq, st);
-        }
+        T* const star[3] = {(T*)h->f_star[0], (T*)h->f_star[1], (T*)h->f_star[2]};
+        T* const fnew[3] = {(T*)h->f_new[0], (T*)h->f_new[1], (T*)h->f_new[2]};
+        tq = timer_begin(h, FLIP_KERNEL_PROJECT, st);
+        if (MIXED)
+            launch_project3<float, double>(g, h->diag, h->tile_slot, h->x64[h->xi], (float* const*)star,
+                                           (float* const*)fnew, dt / (c.density * c.dx), st);
+        else
+            launch_project3<T, T>(g, h->diag, h->tile_slot, (const T*)h->xin[h->xi], star, fnew, scale, st);
+        timer_end(h, tq, st);
     } else {
         for (int a = 0; a < 3; ++a)
             HIP_TRY(hipMemcpyAsync(h->f_new[a], h->f_star[a], s.F[a] * sizeof(T),

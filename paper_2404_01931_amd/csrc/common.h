@@ -288,6 +288,10 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
 template <typename T, typename V>
 void launch_project(const Geo& g, int axis, const uint8_t* diag, const int32_t* tile_slot,
                     const V* p, const T* star, T* out, V scale, hipStream_t st);
+// the three components in one launch (the same values)
+template <typename T, typename V>
+void launch_project3(const Geo& g, const uint8_t* diag, const int32_t* tile_slot, const V* p, T* const star[3],
+                     T* const out[3], V scale, hipStream_t st);
 
 // grid-to-particle: one workgroup per tile; start/count is the cell hash of
 // the binned particles

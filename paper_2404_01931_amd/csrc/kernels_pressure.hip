@@ -1253,6 +1253,46 @@ __global__ __launch_bounds__(256) void k_project(Geo g, const uint8_t* __restric
     project_body<T, V, A>(plain_blk(), g, diag, tile_slot, p, star, out, scale);
 }
 
+// All three components in one launch (plain steps): thread (i, j, k) updates
+// the u, v and w faces at that index that exist, looking up the fluid status
+// and pressure of cell (i, j, k) once for all three and of its three lower
+// neighbours; each face takes the same operations as in project_body, so the
+// result is the same bit for bit. Rows of faces are x-contiguous per thread
+// block (64 x 4 threads), with no index division.
+template <typename T, typename V>
+__global__ __launch_bounds__(256) void k_project3(Geo g, const uint8_t* __restrict__ diag,
+                                                  const int32_t* __restrict__ tile_slot, const V* __restrict__ p,
+                                                  const T* __restrict__ su, const T* __restrict__ sv,
+                                                  const T* __restrict__ sw, T* __restrict__ ou, T* __restrict__ ov,
+                                                  T* __restrict__ ow, V scale)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int j = (int)(blockIdx.y * blockDim.y + threadIdx.y);
+    const int k = (int)blockIdx.z;
+    if (i > g.nx || j > g.ny || k > g.nz) return;
+    const bool in_c = i < g.nx && j < g.ny && k < g.nz;
+    // faces that exist at this index, and those between two cells of the domain
+    const bool has_u = j < g.ny && k < g.nz, has_v = i < g.nx && k < g.nz, has_w = i < g.nx && j < g.ny;
+    const bool int_u = has_u && i > 0 && i < g.nx, int_v = has_v && j > 0 && j < g.ny;
+    const bool int_w = has_w && k > 0 && k < g.nz;
+    const int64_t fu = i + (int64_t)(g.nx + 1) * (j + (int64_t)g.ny * k);
+    const int64_t fv = i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k);
+    const int64_t fw = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
+    T o_u = has_u ? su[fu] : T(0), o_v = has_v ? sv[fv] : T(0), o_w = has_w ? sw[fw] : T(0);
+    V vc = V(0), vx = V(0), vy = V(0), vz = V(0);
+    const bool fc = (int_u || int_v || int_w) && in_c && tile_fluid(g, tile_slot, diag, p, i, j, k, vc);
+    const bool fx = int_u && tile_fluid(g, tile_slot, diag, p, i - 1, j, k, vx);
+    const bool fy = int_v && tile_fluid(g, tile_slot, diag, p, i, j - 1, k, vy);
+    const bool fz = int_w && tile_fluid(g, tile_slot, diag, p, i, j, k - 1, vz);
+    const V pp = fc ? vc : V(0);
+    if (int_u && (fc || fx)) o_u = o_u - (T)(scale * (pp - (fx ? vx : V(0))));
+    if (int_v && (fc || fy)) o_v = o_v - (T)(scale * (pp - (fy ? vy : V(0))));
+    if (int_w && (fc || fz)) o_w = o_w - (T)(scale * (pp - (fz ? vz : V(0))));
+    if (has_u) ou[fu] = o_u;
+    if (has_v) ov[fv] = o_v;
+    if (has_w) ow[fw] = o_w;
+}
+
 template <typename T, typename V, int A>
 __global__ __launch_bounds__(256) void kb_project(const ProjectArgs<T, V>* __restrict__ tab,
                                                   const uint32_t* __restrict__ first, int ns)
@@ -1316,6 +1356,22 @@ void launch_project(const Geo& g, int axis, const uint8_t* diag, const int32_t* 
     else
         hipLaunchKernelGGL((k_project<T, V, 2>), grid, block, 0, st, g, diag, tile_slot, p, star, out, scale);
 }
+
+template <typename T, typename V>
+void launch_project3(const Geo& g, const uint8_t* diag, const int32_t* tile_slot, const V* p, T* const star[3],
+                     T* const out[3], V scale, hipStream_t st)
+{
+    const dim3 block(64, 4), grid((unsigned)((g.nx + 1 + 63) / 64), (unsigned)((g.ny + 1 + 3) / 4),
+                                  (unsigned)(g.nz + 1));
+    hipLaunchKernelGGL((k_project3<T, V>), grid, block, 0, st, g, diag, tile_slot, p, star[0], star[1], star[2],
+                       out[0], out[1], out[2], scale);
+}
+template void launch_project3<float, float>(const Geo&, const uint8_t*, const int32_t*, const float*,
+                                            float* const[3], float* const[3], float, hipStream_t);
+template void launch_project3<double, double>(const Geo&, const uint8_t*, const int32_t*, const double*,
+                                              double* const[3], double* const[3], double, hipStream_t);
+template void launch_project3<float, double>(const Geo&, const uint8_t*, const int32_t*, const double*,
+                                             float* const[3], float* const[3], double, hipStream_t);
 
 template void launch_project<float, float>(const Geo&, int, const uint8_t*, const int32_t*,
                                            const float*, const float*, float*, float, hipStream_t);
