@@ -755,6 +755,7 @@ flip_status batch_step(flip_batch* b, hipStream_t st)
         const int status = q.done == PCG_CONVERGED ? 0 : (q.done == PCG_BREAKDOWN ? 2 : 1);
         record_step(h, q.n_active > 0, status, q.n_active, q.nfluid, q.max_b, q.max_r, q.iter, 0, ret);
         h->prev_iters = q.iter;
+        h->keys_ready = false;  // a batched step does not bin the positions it writes
         h->cur ^= 1;
         h->scur = (q.iter & 1);
         h->xi = 0;

@@ -265,9 +265,11 @@ void carve(flip_handle* h, Carver& cv)
     h->rank = cv.take<uint32_t>(4 * s.pcap);
     h->perm = cv.take<uint32_t>(4 * s.pcap);
     h->count = cv.take<uint32_t>(4 * s.C);
+    h->count_next = cv.take<uint32_t>(4 * s.C);
     h->start = cv.take<uint32_t>(4 * s.C);
     h->scan_tmp = cv.take<uint32_t>(4 * scan_tmp_words(s.C > s.T ? s.C : s.T));
     h->tile_flag = cv.take<uint32_t>(4 * s.T);
+    h->tile_next = cv.take<uint32_t>(4 * s.T);
     h->tile_excl = cv.take<uint32_t>(4 * s.T);
     h->tile_list = cv.take<uint32_t>(4 * s.T);
     h->tile_slot = cv.take<int32_t>(4 * s.T);
@@ -517,6 +519,7 @@ void rebin(flip_handle* h, hipStream_t st)
     const Sizes& s = h->sz;
     const int64_t n = s.n;
     const int nxt = h->cur ^ 1;
+    h->keys_ready = false;  // the sort moves the particles
     launch_fill_u32(h->count, s.C, 0u, st);
     launch_bin_keys<T>(g, (const T*)h->pos[h->cur], n, h->key, h->rank, h->count, st);
     launch_exclusive_scan_u32(h->count, h->start, s.C, h->scan_tmp, st);
@@ -550,9 +553,17 @@ flip_status run_step(flip_handle* h, hipStream_t st)
 
     // 1. binning
     int tq = timer_begin(h, FLIP_KERNEL_BIN_KEYS, st);
-    launch_fill_u32(h->count, s.C, 0u, st);
-    launch_fill_u32(h->tile_flag, s.T, 0u, st);
-    launch_bin_keys<T>(g, (const T*)h->pos[h->cur], n, h->key, h->rank, h->count, st, h->tile_flag);
+    if (h->keys_ready) {
+        // the previous step's grid-to-particle binned the positions it wrote
+        // (keys, provisional ranks, counts and tile flags)
+        HIP_TRY(hipMemcpyAsync(h->count, h->count_next, 4 * s.C, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(h->tile_flag, h->tile_next, 4 * s.T, hipMemcpyDeviceToDevice, st));
+    } else {
+        launch_fill_u32(h->count, s.C, 0u, st);
+        launch_fill_u32(h->tile_flag, s.T, 0u, st);
+        launch_bin_keys<T>(g, (const T*)h->pos[h->cur], n, h->key, h->rank, h->count, st, h->tile_flag);
+    }
+    h->keys_ready = false;
     timer_end(h, tq, st);
     tq = timer_begin(h, FLIP_KERNEL_BIN_SCAN, st);
     launch_exclusive_scan_u32(h->count, h->start, s.C, h->scan_tmp, st);
@@ -716,12 +727,16 @@ flip_status run_step(flip_handle* h, hipStream_t st)
                                    hipMemcpyDeviceToDevice, st));
     }
 
-    // 6. grid-to-particle, blend, advect, clamp
+    // 6. grid-to-particle, blend, advect, clamp; it also bins the positions
+    // it writes for the next step (keys, provisional ranks, counts, tile flags)
     tq = timer_begin(h, FLIP_KERNEL_G2P, st);
+    launch_fill_u32(h->count_next, s.C, 0u, st);
+    launch_fill_u32(h->tile_next, s.T, 0u, st);
     launch_g2p<T>(g, n, h->start, h->count, (T*)h->pos[h->cur], (T*)h->vel[h->cur], (const T*)h->f_new[0],
                   (const T*)h->f_new[1], (const T*)h->f_new[2], (const T*)h->f_old[0],
                   (const T*)h->f_old[1], (const T*)h->f_old[2], (T)c.flip_ratio, (T)dt,
-                  (c.flags & FLIP_FLAG_ADVECT_PARTICLE_VEL) ? 1 : 0, &h->diagw->nonfinite, st);
+                  (c.flags & FLIP_FLAG_ADVECT_PARTICLE_VEL) ? 1 : 0, &h->diagw->nonfinite, st,
+                  h->key, h->rank, h->count_next, h->tile_next);
     timer_end(h, tq, st);
 
     // 7. diagnostics, in FP64: the solve's true residual, the divergence the
@@ -746,6 +761,7 @@ flip_status run_step(flip_handle* h, hipStream_t st)
         h->diag_valid = true;
     }
     if (hipGetLastError() != hipSuccess) return FLIP_E_HIP;
+    h->keys_ready = true;
 
     if (nonfinite_before && ret == FLIP_OK) ret = FLIP_E_NONFINITE;
     const bool solved = ps_host.n_active > 0 && project;

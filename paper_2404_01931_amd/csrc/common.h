@@ -294,11 +294,15 @@ void launch_project3(const Geo& g, const uint8_t* diag, const int32_t* tile_slot
                      T* const out[3], V scale, hipStream_t st);
 
 // grid-to-particle: one workgroup per tile; start/count is the cell hash of
-// the binned particles
+// the binned particles. With key_out (optional) it also bins the positions it
+// writes, as launch_bin_keys would: key, provisional rank, counts into
+// count_next and tile flags into tile_next (both cleared by the caller)
 template <typename T>
 void launch_g2p(const Geo& g, int64_t n, const uint32_t* start, const uint32_t* count, T* pos, T* vel,
                 const T* u_new, const T* v_new, const T* w_new, const T* u_old, const T* v_old,
-                const T* w_old, T alpha, T dt, int advect_particle_vel, uint32_t* nonfinite, hipStream_t st);
+                const T* w_old, T alpha, T dt, int advect_particle_vel, uint32_t* nonfinite, hipStream_t st,
+                uint32_t* key_out = nullptr, uint32_t* rank_out = nullptr, uint32_t* count_next = nullptr,
+                uint32_t* tile_next = nullptr);
 
 template <typename V, typename O>
 void launch_densify(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const V* src,

@@ -148,6 +148,58 @@ __device__ inline int exact_cell_floor(double x, double dx, double inv_dx, int n
     return (int)q;
 }
 
+// The binning's cell of a position: the exact floor of x / dx per axis,
+// clamped into the grid (FP32 positions on a power-of-two spacing take the
+// FP32 floor, which is the same)
+template <typename T>
+__device__ inline void bin_cell(const Geo& g, T x, T y, T z, int& i, int& j, int& k)
+{
+    if (sizeof(T) == 4 && g.dyadic) {
+        const float inv = (float)g.inv_dx;
+        i = dyadic_cell_floor((float)x, inv, g.nx);
+        j = dyadic_cell_floor((float)y, inv, g.ny);
+        k = dyadic_cell_floor((float)z, inv, g.nz);
+    } else {
+        i = exact_cell_floor((double)x, g.dx, g.inv_dx, g.nx);
+        j = exact_cell_floor((double)y, g.dx, g.inv_dx, g.ny);
+        k = exact_cell_floor((double)z, g.dx, g.inv_dx, g.nz);
+    }
+}
+
+// Provisional rank of a particle in cell c (i, j, k), for the wave's live
+// lanes, which must be a prefix of the wave holding consecutive particles:
+// the lanes of a run of equal cells (particles arrive mostly sorted, so a
+// wave holds a few long runs) take theirs from one atomic on count[c] issued
+// by the run's first lane; every run's atomic is issued by the same
+// instruction, so a wave waits for one round trip, not one per run. A cell
+// that appears in several runs gets several disjoint ranges; the gather makes
+// the final ranks stable. tile_flag (optional): the run's first lane marks
+// the cell's 8^3 tile.
+__device__ inline uint32_t bin_rank(const Geo& g, uint32_t c, int i, int j, int k, uint32_t* __restrict__ count,
+                                    uint32_t* __restrict__ tile_flag)
+{
+    const int lane = lane_id();
+    const uint32_t prev = __shfl_up(c, 1, WAVE);
+    const bool head = lane == 0 || prev != c;
+    const uint64_t heads = __ballot(head);
+    const uint64_t live = __ballot(true);
+    // the run ends at the next head or at the wave's last live lane
+    const uint64_t above = lane == WAVE - 1 ? 0ull : (~0ull << (lane + 1));
+    const uint64_t after = heads & above & live;
+    const int end = after ? __ffsll((unsigned long long)after) - 1 : 64 - __clzll((unsigned long long)live);
+    uint32_t base = 0;
+    if (head) {
+        base = atomicAdd(&count[c], (uint32_t)(end - lane));
+        // every writer stores the same value (flags cleared before the launch)
+        if (tile_flag) tile_flag[(i >> 3) + (int64_t)g.tx * ((j >> 3) + (int64_t)g.ty * (k >> 3))] = 1u;
+    }
+    // this lane's run starts at the highest head at or below it
+    const uint64_t upto = lane == WAVE - 1 ? ~0ull : (~0ull >> (WAVE - 1 - lane));
+    const int first = 63 - __clzll((unsigned long long)(heads & upto));
+    base = __shfl(base, first, WAVE);
+    return base + (uint32_t)(lane - first);
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v)
 {

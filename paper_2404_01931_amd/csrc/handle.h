@@ -34,6 +34,11 @@ struct flip_handle {
     uint32_t *key = nullptr, *rank = nullptr, *perm = nullptr;
     // cells
     uint32_t *count = nullptr, *start = nullptr, *scan_tmp = nullptr;
+    // the next step's cell counts and 8^3 tile flags, accumulated by a plain
+    // step's grid-to-particle as it writes the positions (with key and rank);
+    // keys_ready says they belong to the current positions
+    uint32_t *count_next = nullptr, *tile_next = nullptr;
+    bool keys_ready = false;
     // tiles
     uint32_t *tile_flag = nullptr, *tile_excl = nullptr, *tile_list = nullptr, *d_nactive = nullptr;
     int32_t *tile_slot = nullptr, *tile_nbr = nullptr;

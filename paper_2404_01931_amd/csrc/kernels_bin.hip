@@ -93,47 +93,10 @@ __device__ __forceinline__ void bin_keys_body(Blk b, Geo g, const T* __restrict_
     const int64_t p = (int64_t)b.id * 256 + threadIdx.x;
     if (p >= n) return;
     int i, j, k;
-    if (sizeof(T) == 4 && g.dyadic) {  // FP32 positions, power-of-two spacing: the same index in FP32
-        const float inv = (float)g.inv_dx;
-        i = dyadic_cell_floor((float)px[p], inv, g.nx);
-        j = dyadic_cell_floor((float)py[p], inv, g.ny);
-        k = dyadic_cell_floor((float)pz[p], inv, g.nz);
-    } else {
-        i = exact_cell_floor((double)px[p], g.dx, g.inv_dx, g.nx);
-        j = exact_cell_floor((double)py[p], g.dx, g.inv_dx, g.ny);
-        k = exact_cell_floor((double)pz[p], g.dx, g.inv_dx, g.nz);
-    }
+    bin_cell<T>(g, px[p], py[p], pz[p], i, j, k);
     const uint32_t c = (uint32_t)(i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
     key[p] = c;
-
-    // Provisional ranks: the lanes of a run of equal cells (particles arrive
-    // mostly sorted, so a wave holds a few long runs) take theirs from one
-    // atomic issued by the run's first lane; every run's atomic is issued by
-    // the same instruction, so a wave waits for one round trip, not one per
-    // run. A cell that appears in several runs gets several disjoint ranges;
-    // the gather kernel makes the final ranks stable.
-    const int lane = lane_id();
-    const uint32_t prev = __shfl_up(c, 1, WAVE);
-    const bool head = lane == 0 || prev != c;
-    const uint64_t heads = __ballot(head);
-    const uint64_t live = __ballot(true);
-    // the run ends at the next head or at the wave's last live lane
-    const uint64_t above = lane == WAVE - 1 ? 0ull : (~0ull << (lane + 1));
-    const uint64_t after = heads & above & live;
-    const int end = after ? __ffsll((unsigned long long)after) - 1 : 64 - __clzll((unsigned long long)live);
-    uint32_t base = 0;
-    if (head) {
-        base = atomicAdd(&count[c], (uint32_t)(end - lane));
-        // the 8^3 tile holds a particle (flags cleared before the launch; every
-        // writer stores the same value)
-        if (tile_flag) tile_flag[(i >> 3) + (int64_t)g.tx * ((j >> 3) + (int64_t)g.ty * (k >> 3))] = 1u;
-    }
-    // this lane's run starts at the highest head at or below it
-    const uint64_t upto = lane == WAVE - 1 ? ~0ull : (~0ull >> (WAVE - 1 - lane));
-    const int first = 63 - __clzll((unsigned long long)(heads & upto));
-    base = __shfl(base, first, WAVE);
-    const uint32_t my_rank = base + (uint32_t)(lane - first);
-    rank[p] = my_rank;
+    rank[p] = bin_rank(g, c, i, j, k, count, tile_flag);
 }
 
 template <typename T>

@@ -809,6 +809,8 @@ __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restric
                                          const T* __restrict__ uo, const T* __restrict__ vo,
                                          const T* __restrict__ wo, T alpha, T dt, T skin, T Lx, T Ly,
                                          T Lz, int advect_particle_vel, uint32_t* __restrict__ nonfinite,
+                                         uint32_t* __restrict__ key_out, uint32_t* __restrict__ rank_out,
+                                         uint32_t* __restrict__ count_next, uint32_t* __restrict__ tile_next,
                                          T (*box)[2][G2P_BOX], uint32_t* row_start, uint32_t* row_pre)
 {
     const int tid = threadIdx.x;
@@ -887,6 +889,15 @@ __device__ __forceinline__ void g2p_body(Blk b, Geo g, const uint32_t* __restric
 #pragma unroll
         for (int a = 0; a < 3; ++a) bad = bad || !(fabs(out[a]) <= L[a]) || !isfinite(vnew[a]);
         if (bad) atomicOr(nonfinite, 1u);
+        // the next step's binning of the position just written (the live
+        // lanes of this round are a prefix of the wave, as bin_rank needs)
+        if (key_out) {
+            int ci, cj, ck;
+            bin_cell<T>(g, out[0], out[1], out[2], ci, cj, ck);
+            const uint32_t cell = (uint32_t)(ci + (int64_t)g.nx * (cj + (int64_t)g.ny * ck));
+            key_out[p] = cell;
+            rank_out[p] = bin_rank(g, cell, ci, cj, ck, count_next, tile_next);
+        }
     }
 }
 
@@ -913,10 +924,12 @@ __global__ __launch_bounds__(G2P_NT) void k_g2p(Geo g, const uint32_t* __restric
                                                 const T* __restrict__ wn, const T* __restrict__ uo,
                                                 const T* __restrict__ vo, const T* __restrict__ wo, T alpha,
                                                 T dt, T skin, T Lx, T Ly, T Lz, int advect_particle_vel,
-                                                uint32_t* __restrict__ nonfinite)
+                                                uint32_t* __restrict__ nonfinite, uint32_t* __restrict__ key_out,
+                                                uint32_t* __restrict__ rank_out, uint32_t* __restrict__ count_next,
+                                                uint32_t* __restrict__ tile_next)
 {
     g2p_dispatch<T>(plain_blk(), g, start, count, px, py, pz, vx, vy, vz, un, vn, wn, uo, vo, wo, alpha, dt, skin,
-                    Lx, Ly, Lz, advect_particle_vel, nonfinite);
+                    Lx, Ly, Lz, advect_particle_vel, nonfinite, key_out, rank_out, count_next, tile_next);
 }
 
 template <typename T>
@@ -927,7 +940,8 @@ __global__ __launch_bounds__(G2P_NT) void kb_g2p(const G2PArgs<T>* __restrict__ 
         g2p_dispatch<T>(b, a.g, as_global(a.start), as_global(a.count), as_global(a.px), as_global(a.py),
                     as_global(a.pz), as_global(a.vx), as_global(a.vy), as_global(a.vz), as_global(a.un),
                     as_global(a.vn), as_global(a.wn), as_global(a.uo), as_global(a.vo), as_global(a.wo), a.alpha,
-                    a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel, as_global(a.nonfinite));
+                    a.dt, a.skin, a.Lx, a.Ly, a.Lz, a.advect_particle_vel, as_global(a.nonfinite),
+                    (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr);
     });
 }
 
@@ -943,22 +957,26 @@ template void launch_b_g2p<double>(const BatchLaunch&, hipStream_t);
 template <typename T>
 void launch_g2p(const Geo& g, int64_t n, const uint32_t* start, const uint32_t* count, T* pos, T* vel,
                 const T* u_new, const T* v_new, const T* w_new, const T* u_old, const T* v_old,
-                const T* w_old, T alpha, T dt, int advect_particle_vel, uint32_t* nonfinite, hipStream_t st)
+                const T* w_old, T alpha, T dt, int advect_particle_vel, uint32_t* nonfinite, hipStream_t st,
+                uint32_t* key_out, uint32_t* rank_out, uint32_t* count_next, uint32_t* tile_next)
 {
     if (n <= 0) return;
     const T skin = (T)(1e-3 * g.dx);
     const T Lx = (T)(g.nx * g.dx), Ly = (T)(g.ny * g.dx), Lz = (T)(g.nz * g.dx);
     hipLaunchKernelGGL(k_g2p<T>, dim3((unsigned)tiles_of(g)), dim3(G2P_NT), 0, st, g, start, count, pos,
                        pos + n, pos + 2 * n, vel, vel + n, vel + 2 * n, u_new, v_new, w_new, u_old, v_old,
-                       w_old, alpha, dt, skin, Lx, Ly, Lz, advect_particle_vel, nonfinite);
+                       w_old, alpha, dt, skin, Lx, Ly, Lz, advect_particle_vel, nonfinite, key_out, rank_out,
+                       count_next, tile_next);
 }
 
 template void launch_g2p<float>(const Geo&, int64_t, const uint32_t*, const uint32_t*, float*, float*,
                                 const float*, const float*, const float*, const float*, const float*,
-                                const float*, float, float, int, uint32_t*, hipStream_t);
+                                const float*, float, float, int, uint32_t*, hipStream_t, uint32_t*, uint32_t*,
+                                uint32_t*, uint32_t*);
 template void launch_g2p<double>(const Geo&, int64_t, const uint32_t*, const uint32_t*, double*, double*,
                                  const double*, const double*, const double*, const double*, const double*,
-                                 const double*, double, double, int, uint32_t*, hipStream_t);
+                                 const double*, double, double, int, uint32_t*, hipStream_t, uint32_t*, uint32_t*,
+                                 uint32_t*, uint32_t*);
 
 // ---------------------------------------------------------------------------
 // CFL time step (FLIP_FLAG_ADAPTIVE_DT, Sec. 3.1.4): the largest squared
