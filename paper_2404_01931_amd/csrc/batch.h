@@ -147,8 +147,8 @@ struct ProjectArgs {
     const uint8_t* diag;
     const int32_t* tile_slot;
     const V* p;
-    const T* star;
-    T* out;
+    const T* star[3];
+    T* out[3];
     V scale;
 };
 
@@ -235,8 +235,11 @@ template <typename V>
 void launch_b_pcg_direction(const BatchLaunch& L, hipStream_t st);
 template <typename V>
 void launch_b_pcg_update(bool r_form, const BatchLaunch& L, hipStream_t st);
+// the projection of the three components (one launch; project_blocks
+// workgroups per scene)
+int64_t project_blocks(const Geo& g);
 template <typename T, typename V>
-void launch_b_project(int axis, const BatchLaunch& L, hipStream_t st);
+void launch_b_project3(const BatchLaunch& L, hipStream_t st);
 template <typename T>
 void launch_b_g2p(const BatchLaunch& L, hipStream_t st);
 void launch_b_summary(const BatchLaunch& L, hipStream_t st);

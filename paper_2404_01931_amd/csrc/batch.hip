@@ -79,7 +79,7 @@ struct PhaseSites {
 };
 
 struct Sites {
-    Site fill_count, scan_c[3], scatter, tile_flags, scan_t[3], tile_compact, rhs, dir[2], upd[2], project[3],
+    Site fill_count, scan_c[3], scatter, tile_flags, scan_t[3], tile_compact, rhs, dir[2], upd[2], project,
         summary;
     PhaseSites ph[2];
     size_t summary_off = 0;  // SolveSummary[ns]
@@ -253,10 +253,8 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
         std::vector<RhsArgs<T, T>> r(ns);
         std::vector<DirArgs<T>> d0(ns), d1(ns);
         std::vector<UpdArgs<T>> u0(ns), u1(ns);
-        std::vector<ProjectArgs<T, T>> pr[3];
-        for (auto& v : pr) v.resize(ns);
-        std::vector<uint32_t> bg(ns), bf[3];
-        for (auto& v : bf) v.resize(ns);
+        std::vector<ProjectArgs<T, T>> pr(ns);
+        std::vector<uint32_t> bg(ns), bf(ns);
         for (size_t s = 0; s < ns; ++s) {
             flip_handle* h = hs[s];
             const flip_config& c = h->cfg;
@@ -293,11 +291,10 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
                 (k ? u1 : u0)[s] = u;
             }
             const T scale = (T)(c.dt / (c.density * c.dx));
-            for (int a = 0; a < 3; ++a) {
-                pr[a][s] = ProjectArgs<T, T>{h->geo, h->diag, h->tile_slot, (const T*)h->xin[0],
-                                             (const T*)h->f_star[a], (T*)h->f_new[a], scale};
-                bf[a][s] = elem_blocks(h->sz.F[a]);
-            }
+            pr[s] = ProjectArgs<T, T>{h->geo, h->diag, h->tile_slot, (const T*)h->xin[0],
+                                      {(const T*)h->f_star[0], (const T*)h->f_star[1], (const T*)h->f_star[2]},
+                                      {(T*)h->f_new[0], (T*)h->f_new[1], (T*)h->f_new[2]}, scale};
+            bf[s] = (uint32_t)project_blocks(h->geo);
             bg[s] = (uint32_t)h->groups;
         }
         S.rhs = add_site(t, r, bg, TILE_CELLS);
@@ -305,7 +302,7 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
         S.dir[1] = add_site(t, d1, bg, 256);
         S.upd[0] = add_site(t, u0, bg, 256);
         S.upd[1] = add_site(t, u1, bg, 256);
-        for (int a = 0; a < 3; ++a) S.project[a] = add_site(t, pr[a], bf[a], ELEM_NT);
+        S.project = add_site(t, pr, bf, 256);
     }
     if (S.mg) {
         // batched launches run every block of a level (no block lists)
@@ -377,10 +374,10 @@ void for_each_site(S_& S, F&& f)
     f(S.tile_compact);
     f(S.rhs);
     f(S.summary);
+    f(S.project);
     for (int i = 0; i < 3; ++i) {
         f(S.scan_c[i]);
         f(S.scan_t[i]);
-        f(S.project[i]);
     }
     for (int k = 0; k < 2; ++k) {
         f(S.dir[k]);
@@ -408,7 +405,8 @@ bool sites_fit(const Sites& S)
     auto ok = [](const Site& s) { return s.items < 0xFFFFFFFFull; };
     bool r = ok(S.fill_count) && ok(S.scatter) && ok(S.tile_flags) && ok(S.tile_compact) && ok(S.rhs) &&
              ok(S.summary);
-    for (int i = 0; i < 3; ++i) r = r && ok(S.scan_c[i]) && ok(S.scan_t[i]) && ok(S.project[i]);
+    r = r && ok(S.project);
+    for (int i = 0; i < 3; ++i) r = r && ok(S.scan_c[i]) && ok(S.scan_t[i]);
     for (int k = 0; k < 2; ++k)
         r = r && ok(S.dir[k]) && ok(S.upd[k]) && ok(S.ph[k].bin_keys) && ok(S.ph[k].gather) && ok(S.ph[k].p2g) &&
             ok(S.ph[k].g2p);
@@ -595,7 +593,7 @@ template <typename T>
 void enqueue_post(const flip_batch* b, int ph, hipStream_t st)
 {
     const Sites& S = b->S;
-    for (int a = 0; a < 3; ++a) launch_b_project<T, T>(a, L(b, S.project[a]), st);
+    launch_b_project3<T, T>(L(b, S.project), st);
     launch_b_g2p<T>(L(b, S.ph[ph].g2p), st);
 }
 

@@ -285,10 +285,7 @@ void launch_mg_fine(bool up, int groups, int na_hint, const Geo& g, const uint32
 template <typename V>
 void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st);
 
-template <typename T, typename V>
-void launch_project(const Geo& g, int axis, const uint8_t* diag, const int32_t* tile_slot,
-                    const V* p, const T* star, T* out, V scale, hipStream_t st);
-// the three components in one launch (the same values)
+// projection (Eq. (5)) of the three velocity components, one launch
 template <typename T, typename V>
 void launch_project3(const Geo& g, const uint8_t* diag, const int32_t* tile_slot, const V* p, T* const star[3],
                      T* const out[3], V scale, hipStream_t st);

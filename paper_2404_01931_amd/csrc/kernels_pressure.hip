@@ -1211,64 +1211,34 @@ __device__ inline bool tile_fluid(const Geo& g, const int32_t* __restrict__ tile
     return fl;
 }
 
-template <typename T, typename V, int A>
-__device__ __forceinline__ void project_body(Blk blk, Geo g, const uint8_t* __restrict__ diag,
-                                             const int32_t* __restrict__ tile_slot,
-                                             const V* __restrict__ p, const T* __restrict__ star,
-                                             T* __restrict__ out, V scale)
+// Projection (Eq. (5)) of all three components in one pass: thread (i, j, k)
+// updates the u, v and w faces at that index that exist. A face between two
+// cells of the domain with a fluid cell on either side takes
+// star - (dt / (rho dx)) (p+ - p-), the pressure of an air cell being 0 and
+// the difference and its scaling formed in the solution's precision, rounded
+// to the face precision once (mixed: the FP64 solution's difference is not
+// cut to FP32 before it cancels); every other face keeps its star value
+// (the six walls hold 0 from the force step). The fluid status and pressure
+// of cell (i, j, k) are looked up once for its three faces, with those of its
+// three lower neighbours. Workgroups of 64 x 4 threads cover x-contiguous
+// rows of faces: blocks of 64 indices in x, 4 in y and 1 in z, x fastest.
+constexpr int PRJ_BX = 64, PRJ_BY = 4;
+
+__host__ __device__ inline int64_t project3_blocks(const Geo& g)
 {
-    // face counts stay below 2^32 (cells below 2^31): 32-bit index arithmetic
-    const uint32_t dX = g.nx + (A == 0), dY = g.ny + (A == 1), dZ = g.nz + (A == 2);
-    const uint32_t F = dX * dY * dZ;
-    const uint32_t f = (uint32_t)blk.id * 256u + threadIdx.x;
-    if (f >= F) return;
-    const uint32_t row = f / dX;
-    const int i = (int)(f - row * dX), j = (int)(row % dY), k = (int)(row / dY);
-    const int idx = A == 0 ? i : (A == 1 ? j : k);
-    const int lim = A == 0 ? g.nx : (A == 1 ? g.ny : g.nz);
-    T o = star[f];
-    if (idx > 0 && idx < lim) {
-        const int im = i - (A == 0), jm = j - (A == 1), km = k - (A == 2);
-        V vp, vm;
-        const bool fp = tile_fluid(g, tile_slot, diag, p, i, j, k, vp);
-        const bool fm = tile_fluid(g, tile_slot, diag, p, im, jm, km, vm);
-        if (fp || fm) {
-            // the pressure difference and its scaling in the solution's
-            // precision, rounded to the face precision once (mixed: the FP64
-            // solution's difference is not cut to FP32 before it cancels)
-            const V pp = fp ? vp : V(0);
-            const V pm = fm ? vm : V(0);
-            o = o - (T)(scale * (pp - pm));
-        }
-    }
-    out[f] = o;
+    return (int64_t)((g.nx + PRJ_BX) / PRJ_BX) * ((g.ny + PRJ_BY) / PRJ_BY) * (g.nz + 1);
 }
 
-template <typename T, typename V, int A>
-__global__ __launch_bounds__(256) void k_project(Geo g, const uint8_t* __restrict__ diag,
-                                                 const int32_t* __restrict__ tile_slot,
-                                                 const V* __restrict__ p, const T* __restrict__ star,
-                                                 T* __restrict__ out, V scale)
-{
-    project_body<T, V, A>(plain_blk(), g, diag, tile_slot, p, star, out, scale);
-}
-
-// All three components in one launch (plain steps): thread (i, j, k) updates
-// the u, v and w faces at that index that exist, looking up the fluid status
-// and pressure of cell (i, j, k) once for all three and of its three lower
-// neighbours; each face takes the same operations as in project_body, so the
-// result is the same bit for bit. Rows of faces are x-contiguous per thread
-// block (64 x 4 threads), with no index division.
 template <typename T, typename V>
-__global__ __launch_bounds__(256) void k_project3(Geo g, const uint8_t* __restrict__ diag,
-                                                  const int32_t* __restrict__ tile_slot, const V* __restrict__ p,
-                                                  const T* __restrict__ su, const T* __restrict__ sv,
-                                                  const T* __restrict__ sw, T* __restrict__ ou, T* __restrict__ ov,
-                                                  T* __restrict__ ow, V scale)
+__device__ __forceinline__ void project3_body(Blk blk, const Geo& g, const uint8_t* __restrict__ diag,
+                                              const int32_t* __restrict__ tile_slot, const V* __restrict__ p,
+                                              const T* __restrict__ su, const T* __restrict__ sv,
+                                              const T* __restrict__ sw, T* __restrict__ ou, T* __restrict__ ov,
+                                              T* __restrict__ ow, V scale)
 {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int j = (int)(blockIdx.y * blockDim.y + threadIdx.y);
-    const int k = (int)blockIdx.z;
+    const int nbx = (g.nx + PRJ_BX) / PRJ_BX, nby = (g.ny + PRJ_BY) / PRJ_BY;
+    const int bx = blk.id % nbx, by = (blk.id / nbx) % nby, k = blk.id / (nbx * nby);
+    const int i = bx * PRJ_BX + (int)(threadIdx.x % PRJ_BX), j = by * PRJ_BY + (int)(threadIdx.x / PRJ_BX);
     if (i > g.nx || j > g.ny || k > g.nz) return;
     const bool in_c = i < g.nx && j < g.ny && k < g.nz;
     // faces that exist at this index, and those between two cells of the domain
@@ -1293,29 +1263,39 @@ __global__ __launch_bounds__(256) void k_project3(Geo g, const uint8_t* __restri
     if (has_w) ow[fw] = o_w;
 }
 
-template <typename T, typename V, int A>
-__global__ __launch_bounds__(256) void kb_project(const ProjectArgs<T, V>* __restrict__ tab,
-                                                  const uint32_t* __restrict__ first, int ns)
+template <typename T, typename V>
+__global__ __launch_bounds__(PRJ_BX * PRJ_BY) void k_project3(Geo g, const uint8_t* __restrict__ diag,
+                                                              const int32_t* __restrict__ tile_slot,
+                                                              const V* __restrict__ p, const T* __restrict__ su,
+                                                              const T* __restrict__ sv, const T* __restrict__ sw,
+                                                              T* __restrict__ ou, T* __restrict__ ov,
+                                                              T* __restrict__ ow, V scale)
 {
-    batch_for_each(tab, first, ns, [&](Blk blk, const ProjectArgs<T, V>& a) {
-        project_body<T, V, A>(blk, a.g, as_global(a.diag), as_global(a.tile_slot), as_global(a.p), as_global(a.star), as_global(a.out), a.scale);
-    });
+    project3_body<T, V>(plain_blk(), g, diag, tile_slot, p, su, sv, sw, ou, ov, ow, scale);
 }
 
 template <typename T, typename V>
-void launch_b_project(int axis, const BatchLaunch& L, hipStream_t st)
+__global__ __launch_bounds__(PRJ_BX * PRJ_BY) void kb_project3(const ProjectArgs<T, V>* __restrict__ tab,
+                                                               const uint32_t* __restrict__ first, int ns)
+{
+    batch_for_each(tab, first, ns, [&](Blk blk, const ProjectArgs<T, V>& a) {
+        project3_body<T, V>(blk, a.g, as_global(a.diag), as_global(a.tile_slot), as_global(a.p),
+                            as_global(a.star[0]), as_global(a.star[1]), as_global(a.star[2]), as_global(a.out[0]),
+                            as_global(a.out[1]), as_global(a.out[2]), a.scale);
+    });
+}
+
+int64_t project_blocks(const Geo& g) { return project3_blocks(g); }
+
+template <typename T, typename V>
+void launch_b_project3(const BatchLaunch& L, hipStream_t st)
 {
     if (L.blocks == 0) return;
-    const ProjectArgs<T, V>* tab = (const ProjectArgs<T, V>*)L.args;
-    if (axis == 0)
-        hipLaunchKernelGGL((kb_project<T, V, 0>), dim3(L.blocks), dim3(256), 0, st, tab, L.first, L.ns);
-    else if (axis == 1)
-        hipLaunchKernelGGL((kb_project<T, V, 1>), dim3(L.blocks), dim3(256), 0, st, tab, L.first, L.ns);
-    else
-        hipLaunchKernelGGL((kb_project<T, V, 2>), dim3(L.blocks), dim3(256), 0, st, tab, L.first, L.ns);
+    hipLaunchKernelGGL((kb_project3<T, V>), dim3(L.blocks), dim3(PRJ_BX * PRJ_BY), 0, st,
+                       (const ProjectArgs<T, V>*)L.args, L.first, L.ns);
 }
-template void launch_b_project<float, float>(int, const BatchLaunch&, hipStream_t);
-template void launch_b_project<double, double>(int, const BatchLaunch&, hipStream_t);
+template void launch_b_project3<float, float>(const BatchLaunch&, hipStream_t);
+template void launch_b_project3<double, double>(const BatchLaunch&, hipStream_t);
 
 // one thread per scene: copy the solver state a host poll needs
 __global__ __launch_bounds__(64) void kb_summary(const SummaryArgs* __restrict__ tab,
@@ -1344,27 +1324,11 @@ void launch_b_summary(const BatchLaunch& L, hipStream_t st)
 }
 
 template <typename T, typename V>
-void launch_project(const Geo& g, int axis, const uint8_t* diag, const int32_t* tile_slot,
-                    const V* p, const T* star, T* out, V scale, hipStream_t st)
-{
-    const int64_t F = (int64_t)(g.nx + (axis == 0)) * (g.ny + (axis == 1)) * (g.nz + (axis == 2));
-    const dim3 grid((unsigned)((F + 255) / 256)), block(256);
-    if (axis == 0)
-        hipLaunchKernelGGL((k_project<T, V, 0>), grid, block, 0, st, g, diag, tile_slot, p, star, out, scale);
-    else if (axis == 1)
-        hipLaunchKernelGGL((k_project<T, V, 1>), grid, block, 0, st, g, diag, tile_slot, p, star, out, scale);
-    else
-        hipLaunchKernelGGL((k_project<T, V, 2>), grid, block, 0, st, g, diag, tile_slot, p, star, out, scale);
-}
-
-template <typename T, typename V>
 void launch_project3(const Geo& g, const uint8_t* diag, const int32_t* tile_slot, const V* p, T* const star[3],
                      T* const out[3], V scale, hipStream_t st)
 {
-    const dim3 block(64, 4), grid((unsigned)((g.nx + 1 + 63) / 64), (unsigned)((g.ny + 1 + 3) / 4),
-                                  (unsigned)(g.nz + 1));
-    hipLaunchKernelGGL((k_project3<T, V>), grid, block, 0, st, g, diag, tile_slot, p, star[0], star[1], star[2],
-                       out[0], out[1], out[2], scale);
+    hipLaunchKernelGGL((k_project3<T, V>), dim3((unsigned)project3_blocks(g)), dim3(PRJ_BX * PRJ_BY), 0, st, g,
+                       diag, tile_slot, p, star[0], star[1], star[2], out[0], out[1], out[2], scale);
 }
 template void launch_project3<float, float>(const Geo&, const uint8_t*, const int32_t*, const float*,
                                             float* const[3], float* const[3], float, hipStream_t);
@@ -1373,14 +1337,6 @@ template void launch_project3<double, double>(const Geo&, const uint8_t*, const 
 template void launch_project3<float, double>(const Geo&, const uint8_t*, const int32_t*, const double*,
                                              float* const[3], float* const[3], double, hipStream_t);
 
-template void launch_project<float, float>(const Geo&, int, const uint8_t*, const int32_t*,
-                                           const float*, const float*, float*, float, hipStream_t);
-template void launch_project<double, double>(const Geo&, int, const uint8_t*, const int32_t*,
-                                             const double*, const double*, double*, double,
-                                             hipStream_t);
-template void launch_project<float, double>(const Geo&, int, const uint8_t*, const int32_t*,
-                                            const double*, const float*, float*, double,
-                                            hipStream_t);
 
 // ---------------------------------------------------------------------------
 // compact tile storage -> dense cell array (readback of b and p)
