@@ -246,7 +246,7 @@ void launch_b_summary(const BatchLaunch& L, hipStream_t st);
 void launch_b_mg_types_fine(const BatchLaunch& L, hipStream_t st);
 void launch_b_mg_types(const BatchLaunch& L, hipStream_t st);
 template <typename V>
-void launch_b_mg_level(int kind, const BatchLaunch& L, hipStream_t st);
+void launch_b_mg_level(int kind, bool two_sweeps, const BatchLaunch& L, hipStream_t st);
 template <typename V>
 void launch_b_mg_fine(bool up, const BatchLaunch& L, hipStream_t st);
 

@@ -541,9 +541,10 @@ void enqueue_vcycle(const flip_batch* b, hipStream_t st)
 {
     const Sites& S = b->S;
     launch_b_mg_fine<T>(false, L(b, S.mg_fine_down), st);
-    for (int l = 0; l + 1 < S.mg_levels; ++l) launch_b_mg_level<T>(MG_B_DOWN, L(b, S.mg_down[l]), st);
-    launch_b_mg_level<T>(MG_B_BOTTOM, L(b, S.mg_bottom), st);
-    for (int l = S.mg_levels - 2; l >= 0; --l) launch_b_mg_level<T>(MG_B_UP, L(b, S.mg_up[l]), st);
+    for (int l = 0; l + 1 < S.mg_levels; ++l)
+        launch_b_mg_level<T>(MG_B_DOWN, mg_two_sweeps(l), L(b, S.mg_down[l]), st);
+    launch_b_mg_level<T>(MG_B_BOTTOM, false, L(b, S.mg_bottom), st);
+    for (int l = S.mg_levels - 2; l >= 0; --l) launch_b_mg_level<T>(MG_B_UP, mg_two_sweeps(l), L(b, S.mg_up[l]), st);
     launch_b_mg_fine<T>(true, L(b, S.mg_fine_up), st);
 }
 

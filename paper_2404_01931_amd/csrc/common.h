@@ -266,6 +266,12 @@ struct MgLevel {
 constexpr int MG_MAX_LEVELS = 32;
 constexpr int MG_BOTTOM_SIDE = 8;      // coarsen until every axis has at most 8 cells
 constexpr int MG_BOTTOM_SWEEPS = 10;   // Jacobi sweeps on the coarsest level
+// Smoothing sweeps before and after the coarse-grid correction on a dense
+// level: one on the first dense level (level 1), two on every level below
+// it down to the coarsest. Indices are those of the dense levels (0 = level
+// 1); the fine level has one sweep.
+constexpr int MG_TWO_SWEEPS_FROM = 1;
+inline bool mg_two_sweeps(int dense_index) { return dense_index >= MG_TWO_SWEEPS_FROM; }
 // cell types of the first coarse level from the fine n_c, and of each next one
 void launch_mg_types_fine(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const MgLevel& c,
                           hipStream_t st);

@@ -13,6 +13,10 @@
 //   down, level l:  x0 = w b / n;  t = b - A x0;  b_{l+1} = (R t) / 2
 //   bottom:         x = 0, then 10 sweeps x += w (b - A x) / n
 //   up, level l:    y = x0 + P x_{l+1};  x_l = y + w (b - A y) / n
+// The levels below level 1 take two sweeps on each side instead of one
+// (down: x1 = x0 + w (b - A x0) / n, t = b - A x1; up: y = x1 + P x_{l+1},
+// then two sweeps), which costs their latency-bound kernels little and
+// takes the 256^3 drop scene from 24 to about 21 iterations.
 // Between the fine grid and level 1, P copies a coarse value to its fluid
 // children and R sums the children; between dense levels P is cell-centred
 // trilinear and R its transpose (described with those kernels). Both R have
@@ -125,6 +129,42 @@ __host__ __device__ inline int64_t mg_down_blocks(const MgLevel& c)
     return (int64_t)mg_down_blocks_x(c) * mg_down_blocks_y(c) * ((c.nz + MGD_CZ - 1) / MGD_CZ);
 }
 
+// The restriction of t (on the t region, in ts) to the block's coarse
+// cells, along x, then y, then z, with the two intermediate passes in the
+// scratch area w (at least (TZ TY + TZ CY) CX values); writes c.b = R t / 2.
+template <typename V, int NT>
+__device__ __forceinline__ void mg_restrict_block(const V* ts, V* w, int cx0, int cy0, int cz0, const MgLevel& c)
+{
+    const int tid = threadIdx.x;
+    V* const rx = w;                                  // [TZ][TY][CX]
+    V* const ry = w + MGD_TZ * MGD_TY * MGD_CX;       // [TZ][CY][CX]
+    for (int q = tid; q < MGD_TZ * MGD_TY * MGD_CX; q += NT) {
+        const int i = q % MGD_CX, row = q / MGD_CX;   // row = ly + TY lz
+        const int C = cx0 + i;
+        const V* t = ts + row * MGD_TX + 2 * i;
+        rx[q] = (restrict_weight<V>(0, C, c.nx) * t[0] + restrict_weight<V>(1, C, c.nx) * t[1]) +
+                (restrict_weight<V>(2, C, c.nx) * t[2] + restrict_weight<V>(3, C, c.nx) * t[3]);
+    }
+    __syncthreads();
+    for (int q = tid; q < MGD_TZ * MGD_CY * MGD_CX; q += NT) {
+        const int i = q % MGD_CX, j = (q / MGD_CX) % MGD_CY, lz = q / (MGD_CX * MGD_CY);
+        const int C = cy0 + j;
+        const V* t = rx + (lz * MGD_TY + 2 * j) * MGD_CX + i;
+        ry[q] = (restrict_weight<V>(0, C, c.ny) * t[0] + restrict_weight<V>(1, C, c.ny) * t[MGD_CX]) +
+                (restrict_weight<V>(2, C, c.ny) * t[2 * MGD_CX] + restrict_weight<V>(3, C, c.ny) * t[3 * MGD_CX]);
+    }
+    __syncthreads();
+    if (tid < MGD_CX * MGD_CY * MGD_CZ) {
+        const int i = tid % MGD_CX, j = (tid / MGD_CX) % MGD_CY, k = tid / (MGD_CX * MGD_CY);
+        const int ci = cx0 + i, cj = cy0 + j, ck = cz0 + k;
+        constexpr int S = MGD_CY * MGD_CX;
+        const V* t = ry + (2 * k) * S + j * MGD_CX + i;
+        const V v = (restrict_weight<V>(0, ck, c.nz) * t[0] + restrict_weight<V>(1, ck, c.nz) * t[S]) +
+                    (restrict_weight<V>(2, ck, c.nz) * t[2 * S] + restrict_weight<V>(3, ck, c.nz) * t[3 * S]);
+        if (ci < c.nx && cj < c.ny && ck < c.nz) ((V*)c.b)[level_index(c, ci, cj, ck)] = V(0.5) * v;
+    }
+}
+
 // NT threads per workgroup: 512, or 1024 on the small levels, where a
 // launch has few workgroups and the time is the chain of each thread's
 // serial work (the values are the same either way; batched launches use
@@ -190,33 +230,7 @@ __device__ __forceinline__ void mg_down_body(Blk blk, const MgLevel& f, const Mg
         }
     }
     __syncthreads();
-    V* const rx = bs;                                 // [TZ][TY][CX]
-    V* const ry = bs + MGD_TZ * MGD_TY * MGD_CX;      // [TZ][CY][CX]
-    for (int q = tid; q < MGD_TZ * MGD_TY * MGD_CX; q += NT) {
-        const int i = q % MGD_CX, row = q / MGD_CX;   // row = ly + TY lz
-        const int C = cx0 + i;
-        const V* t = ts + row * MGD_TX + 2 * i;
-        rx[q] = (restrict_weight<V>(0, C, c.nx) * t[0] + restrict_weight<V>(1, C, c.nx) * t[1]) +
-                (restrict_weight<V>(2, C, c.nx) * t[2] + restrict_weight<V>(3, C, c.nx) * t[3]);
-    }
-    __syncthreads();
-    for (int q = tid; q < MGD_TZ * MGD_CY * MGD_CX; q += NT) {
-        const int i = q % MGD_CX, j = (q / MGD_CX) % MGD_CY, lz = q / (MGD_CX * MGD_CY);
-        const int C = cy0 + j;
-        const V* t = rx + (lz * MGD_TY + 2 * j) * MGD_CX + i;
-        ry[q] = (restrict_weight<V>(0, C, c.ny) * t[0] + restrict_weight<V>(1, C, c.ny) * t[MGD_CX]) +
-                (restrict_weight<V>(2, C, c.ny) * t[2 * MGD_CX] + restrict_weight<V>(3, C, c.ny) * t[3 * MGD_CX]);
-    }
-    __syncthreads();
-    if (tid < MGD_CX * MGD_CY * MGD_CZ) {
-        const int i = tid % MGD_CX, j = (tid / MGD_CX) % MGD_CY, k = tid / (MGD_CX * MGD_CY);
-        const int ci = cx0 + i, cj = cy0 + j, ck = cz0 + k;
-        constexpr int S = MGD_CY * MGD_CX;
-        const V* t = ry + (2 * k) * S + j * MGD_CX + i;
-        const V v = (restrict_weight<V>(0, ck, c.nz) * t[0] + restrict_weight<V>(1, ck, c.nz) * t[S]) +
-                    (restrict_weight<V>(2, ck, c.nz) * t[2 * S] + restrict_weight<V>(3, ck, c.nz) * t[3 * S]);
-        if (ci < c.nx && cj < c.ny && ck < c.nz) ((V*)c.b)[level_index(c, ci, cj, ck)] = V(0.5) * v;
-    }
+    mg_restrict_block<V, NT>(ts, bs, cx0, cy0, cz0, c);
 }
 
 template <typename V, int NT>
@@ -231,6 +245,113 @@ __global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_down(const MgPairArgs* __re
 {
     batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {
         mg_down_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    });
+}
+
+// ---- down with two sweeps (the levels below level 1) ------------------------------
+//
+// The same blocks; two damped-Jacobi sweeps from zero before the restriction:
+// x0 = w b / n, x1 = x0 + w (b - A x0) / n, t = b - A x1. t on the t region
+// reads x1 one cell further out (the v region, 20 x 12 x 12), and x1 there
+// reads x0, b and n one more cell out (the u region, 22 x 14 x 14).
+constexpr int MGD2_VX = MGD_TX + 2, MGD2_VY = MGD_TY + 2, MGD2_VZ = MGD_TZ + 2;
+constexpr int MGD2_UX = MGD_TX + 4, MGD2_UY = MGD_TY + 4, MGD2_UZ = MGD_TZ + 4;
+constexpr int MGD2_V = MGD2_VX * MGD2_VY * MGD2_VZ;  // 2880
+constexpr int MGD2_U = MGD2_UX * MGD2_UY * MGD2_UZ;  // 4312
+static_assert(MGD_TZ * MGD_TY * MGD_CX + MGD_TZ * MGD_CY * MGD_CX <= MGD2_U, "x and y passes fit the b buffer");
+
+template <typename V, int NT>
+__device__ __forceinline__ void mg_down2_body(Blk blk, const MgLevel& f, const MgLevel& c,
+                                              const PcgState* __restrict__ ps)
+{
+    using CU = Cols<MGD2_UX, MGD2_UY, MGD2_UZ, NT>;
+    using CV = Cols<MGD2_VX, MGD2_VY, MGD2_VZ, NT>;
+    using CT = Cols<MGD_TX, MGD_TY, MGD_TZ, NT>;
+    __shared__ V us[MGD2_U];       // x0 on the u region
+    __shared__ V bs[MGD2_U];       // b on the u region; later the x and y passes
+    __shared__ uint8_t ds[MGD2_U];  // n (0: not fluid or outside the level)
+    __shared__ V vs[MGD2_V];       // x1 on the v region
+    __shared__ V ts[MGD_T];
+    const int tid = threadIdx.x;
+    const int gbx = mg_down_blocks_x(c), gby = mg_down_blocks_y(c);
+    const int bid = c.dlist ? (int)c.dlist[blk.id] : blk.id;  // plain launches: the listed blocks
+    const int cx0 = (bid % gbx) * MGD_CX, cy0 = ((bid / gbx) % gby) * MGD_CY;
+    const int cz0 = (bid / (gbx * gby)) * MGD_CZ;
+    const int ox = 2 * cx0 - 3, oy = 2 * cy0 - 3, oz = 2 * cz0 - 3;  // u region origin on level f
+    const V* const fb = (const V*)f.b;
+    const int ucol = tid % CU::C, uzg = tid / CU::C;
+    const bool uact = tid < CU::C * CU::P;
+    const int ugx = ox + ucol % MGD2_UX, ugy = oy + ucol / MGD2_UX;
+    const bool uxy = ugx >= 0 && ugx < f.nx && ugy >= 0 && ugy < f.ny;
+    const int ubase = min(max(ugx, 0), f.nx - 1) + f.nx * min(max(ugy, 0), f.ny - 1);
+    const int sxy = f.nx * f.ny;
+    V bv[CU::J];
+    int dv[CU::J];
+    bool iv[CU::J];
+#pragma unroll
+    for (int m = 0; m < CU::J; ++m) {
+        const int lz = uzg + CU::P * m, gz = oz + lz;
+        iv[m] = uact && lz < MGD2_UZ && uxy && gz >= 0 && gz < f.nz;
+        const int e = ubase + sxy * min(max(gz, 0), f.nz - 1);
+        dv[m] = f.d[e];
+        bv[m] = fb[e];
+    }
+    if (ps->done != PCG_RUNNING) return;
+    const V w = mg_omega<V>();
+#pragma unroll
+    for (int m = 0; m < CU::J; ++m) {
+        const int lz = uzg + CU::P * m;
+        if (uact && lz < MGD2_UZ) {
+            const int q = ucol + CU::C * lz;
+            const int d = iv[m] ? dv[m] : 0;
+            us[q] = d ? w * bv[m] * recip_nc<V>(d) : V(0);
+            bs[q] = bv[m];
+            ds[q] = (uint8_t)d;
+        }
+    }
+    __syncthreads();
+    constexpr int SY = MGD2_UX, SZ = MGD2_UX * MGD2_UY;
+    if (tid < CV::C * CV::P) {
+        const int vcol = tid % CV::C;
+        const int ub = (vcol % MGD2_VX + 1) + SY * (vcol / MGD2_VX + 1);
+        for (int lz = tid / CV::C; lz < MGD2_VZ; lz += CV::P) {
+            const int u = ub + SZ * (lz + 1);
+            const int d = ds[u];
+            const V x0 = us[u];
+            const V nsum = ((us[u - 1] + us[u + 1]) + (us[u - SY] + us[u + SY])) + (us[u - SZ] + us[u + SZ]);
+            vs[vcol + CV::C * lz] = d ? x0 + w * ((bs[u] - (V)d * x0) + nsum) * recip_nc<V>(d) : V(0);
+        }
+    }
+    __syncthreads();
+    constexpr int VY = MGD2_VX, VZ = MGD2_VX * MGD2_VY;
+    if (tid < CT::C * CT::P) {
+        const int tcol = tid % CT::C;
+        const int tx = tcol % MGD_TX, ty = tcol / MGD_TX;
+        const int vb = (tx + 1) + VY * (ty + 1), ub = (tx + 2) + SY * (ty + 2);
+        for (int lz = tid / CT::C; lz < MGD_TZ; lz += CT::P) {
+            const int v = vb + VZ * (lz + 1), u = ub + SZ * (lz + 2);
+            const int d = ds[u];
+            const V x1 = vs[v];
+            const V nsum = ((vs[v - 1] + vs[v + 1]) + (vs[v - VY] + vs[v + VY])) + (vs[v - VZ] + vs[v + VZ]);
+            ts[tcol + CT::C * lz] = d ? (bs[u] - (V)d * x1) + nsum : V(0);
+        }
+    }
+    __syncthreads();
+    mg_restrict_block<V, NT>(ts, bs, cx0, cy0, cz0, c);
+}
+
+template <typename V, int NT>
+__global__ __launch_bounds__(NT) void k_mg_down2(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
+{
+    mg_down2_body<V, NT>(plain_blk(), f, c, ps);
+}
+
+template <typename V>
+__global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_down2(const MgPairArgs* __restrict__ tab,
+                                                   const uint32_t* __restrict__ first, int ns)
+{
+    batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {
+        mg_down2_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
     });
 }
 
@@ -428,6 +549,170 @@ __global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_up(const MgPairArgs* __rest
     });
 }
 
+// ---- up with two sweeps (the levels below level 1) ----------------------------------
+//
+// The same blocks; the down kernel's two sweeps recomputed, the correction
+// added, then two sweeps: y0 = x1 + P x_c, y1 = y0 + w (b - A y0) / n,
+// x = y1 + w (b - A y1) / n. x on the block reads y1 one cell around it (the
+// y region, 18 x 10 x 10), y1 there reads y0 one more cell out (the z region,
+// 20 x 12 x 12, whose parents and their neighbours are the same 12 x 8 x 8
+// coarse cells), and x1 on the z region reads x0, b and n one more cell out
+// (the b region, 22 x 14 x 14).
+constexpr int MGU2_ZX = MGU_FX + 4, MGU2_ZY = MGU_FY + 4, MGU2_ZZ = MGU_FZ + 4;
+constexpr int MGU2_BX = MGU_FX + 6, MGU2_BY = MGU_FY + 6, MGU2_BZ = MGU_FZ + 6;
+constexpr int MGU2_Z = MGU2_ZX * MGU2_ZY * MGU2_ZZ;  // 2880
+constexpr int MGU2_B = MGU2_BX * MGU2_BY * MGU2_BZ;  // 4312
+
+template <typename V, int NT>
+__device__ __forceinline__ void mg_up2_body(Blk blk, const MgLevel& f, const MgLevel& c,
+                                            const PcgState* __restrict__ ps)
+{
+    using CC = Cols<MGU_CX, MGU_CY, MGU_CZ, NT>;
+    using CB = Cols<MGU2_BX, MGU2_BY, MGU2_BZ, NT>;
+    using CZ = Cols<MGU2_ZX, MGU2_ZY, MGU2_ZZ, NT>;
+    using CY = Cols<MGU_YX, MGU_YY, MGU_YZ, NT>;
+    using CF = Cols<MGU_FX, MGU_FY, MGU_FZ, NT>;
+    __shared__ V xs[MGU_C];         // x_c on the coarse region
+    __shared__ V us[MGU2_B];        // x0 on the b region
+    __shared__ V bs[MGU2_B];        // b on the b region
+    __shared__ uint8_t ds[MGU2_B];  // n (0: not fluid or outside the level)
+    __shared__ V zs[MGU2_Z];        // y0 on the z region
+    __shared__ V ys[MGU_Y];         // y1 on the y region
+    const int tid = threadIdx.x;
+    const int gbx = mg_up_blocks_x(f), gby = mg_up_blocks_y(f);
+    const int bid = f.ulist ? (int)f.ulist[blk.id] : blk.id;  // plain launches: the listed blocks
+    const int fx0 = (bid % gbx) * MGU_FX, fy0 = ((bid / gbx) % gby) * MGU_FY;
+    const int fz0 = (bid / (gbx * gby)) * MGU_FZ;
+    const int px0 = fx0 / 2 - 2, py0 = fy0 / 2 - 2, pz0 = fz0 / 2 - 2;
+    const V* const cx = (const V*)c.x;
+    const V* const fb = (const V*)f.b;
+    const int ccol = tid % CC::C, czg = tid / CC::C;
+    const bool cact = tid < CC::C * CC::P;
+    const int cbase = min(max(px0 + ccol % MGU_CX, 0), c.nx - 1) + c.nx * min(max(py0 + ccol / MGU_CX, 0), c.ny - 1);
+    V xv[CC::J];
+#pragma unroll
+    for (int m = 0; m < CC::J; ++m) {
+        const int k = pz0 + czg + CC::P * m;
+        xv[m] = cx[cbase + c.nx * c.ny * min(max(k, 0), c.nz - 1)];
+    }
+    // b region (origin three cells below the block), a column per thread
+    const int bcol = tid % CB::C, bzg = tid / CB::C;
+    const bool bact = tid < CB::C * CB::P;
+    const int bgx = fx0 - 3 + bcol % MGU2_BX, bgy = fy0 - 3 + bcol / MGU2_BX;
+    const bool bxy = bgx >= 0 && bgx < f.nx && bgy >= 0 && bgy < f.ny;
+    const int bbase = min(max(bgx, 0), f.nx - 1) + f.nx * min(max(bgy, 0), f.ny - 1);
+    const int sxy = f.nx * f.ny;
+    V bv[CB::J];
+    int dv[CB::J];
+    bool iv[CB::J];
+#pragma unroll
+    for (int m = 0; m < CB::J; ++m) {
+        const int lz = bzg + CB::P * m, gz = fz0 - 3 + lz;
+        iv[m] = bact && lz < MGU2_BZ && bxy && gz >= 0 && gz < f.nz;
+        const int e = bbase + sxy * min(max(gz, 0), f.nz - 1);
+        dv[m] = f.d[e];
+        bv[m] = fb[e];
+    }
+    if (ps->done != PCG_RUNNING) return;
+    const V w = mg_omega<V>();
+#pragma unroll
+    for (int m = 0; m < CC::J; ++m) {
+        const int lz = czg + CC::P * m;
+        if (cact && lz < MGU_CZ) xs[ccol + CC::C * lz] = xv[m];
+    }
+#pragma unroll
+    for (int m = 0; m < CB::J; ++m) {
+        const int lz = bzg + CB::P * m;
+        if (bact && lz < MGU2_BZ) {
+            const int q = bcol + CB::C * lz;
+            const int d = iv[m] ? dv[m] : 0;
+            us[q] = d ? w * bv[m] * recip_nc<V>(d) : V(0);
+            bs[q] = bv[m];
+            ds[q] = (uint8_t)d;
+        }
+    }
+    __syncthreads();
+    constexpr int BY = MGU2_BX, BZ = MGU2_BX * MGU2_BY;
+    constexpr int CS = MGU_CX * MGU_CY;
+    // y0 = x1 + P x_c on the z region (origin two cells below the block)
+    if (tid < CZ::C * CZ::P) {
+        const int zcol = tid % CZ::C;
+        const int lx = zcol % MGU2_ZX, ly = zcol / MGU2_ZX;
+        const int gx = fx0 - 2 + lx, gy = fy0 - 2 + ly;
+        const int ax = (gx >> 1) - px0, ay = (gy >> 1) - py0;
+        const int sx = (gx & 1) ? 1 : -1, sy = (gy & 1) ? MGU_CX : -MGU_CX;
+        const int ub = (lx + 1) + BY * (ly + 1);
+        for (int lz = tid / CZ::C; lz < MGU2_ZZ; lz += CZ::P) {
+            const int u = ub + BZ * (lz + 1);
+            const int d = ds[u];
+            V y = V(0);
+            if (d) {
+                const V x0 = us[u];
+                const V nsum = ((us[u - 1] + us[u + 1]) + (us[u - BY] + us[u + BY])) + (us[u - BZ] + us[u + BZ]);
+                const V x1 = x0 + w * ((bs[u] - (V)d * x0) + nsum) * recip_nc<V>(d);
+                const int gz = fz0 - 2 + lz;
+                const int az = (gz >> 1) - pz0, sz = (gz & 1) ? CS : -CS;
+                const V* p = xs + ax + MGU_CX * ay + CS * az;
+                const V x00 = V(0.75) * p[0] + V(0.25) * p[sx];
+                const V x10 = V(0.75) * p[sy] + V(0.25) * p[sy + sx];
+                const V x01 = V(0.75) * p[sz] + V(0.25) * p[sz + sx];
+                const V x11 = V(0.75) * p[sz + sy] + V(0.25) * p[sz + sy + sx];
+                const V y0 = V(0.75) * x00 + V(0.25) * x10, y1 = V(0.75) * x01 + V(0.25) * x11;
+                y = x1 + (V(0.75) * y0 + V(0.25) * y1);
+            }
+            zs[zcol + CZ::C * lz] = y;
+        }
+    }
+    __syncthreads();
+    // y1 on the y region (origin one cell below the block)
+    constexpr int ZY = MGU2_ZX, ZZ = MGU2_ZX * MGU2_ZY;
+    if (tid < CY::C * CY::P) {
+        const int ycol = tid % CY::C;
+        const int lx = ycol % MGU_YX, ly = ycol / MGU_YX;
+        const int zb = (lx + 1) + ZY * (ly + 1), ub = (lx + 2) + BY * (ly + 2);
+        for (int lz = tid / CY::C; lz < MGU_YZ; lz += CY::P) {
+            const int z = zb + ZZ * (lz + 1), u = ub + BZ * (lz + 2);
+            const int d = ds[u];
+            const V yc = zs[z];
+            const V nsum = ((zs[z - 1] + zs[z + 1]) + (zs[z - ZY] + zs[z + ZY])) + (zs[z - ZZ] + zs[z + ZZ]);
+            ys[ycol + CY::C * lz] = d ? yc + w * ((bs[u] - (V)d * yc) + nsum) * recip_nc<V>(d) : V(0);
+        }
+    }
+    __syncthreads();
+    constexpr int SY = MGU_YX, SZ = MGU_YX * MGU_YY;
+    const int fcol = tid % CF::C, fzg = tid / CF::C;
+    const int lx = fcol % MGU_FX, ly = fcol / MGU_FX;
+    const int i = fx0 + lx, j = fy0 + ly;
+    const int yb = (lx + 1) + SY * (ly + 1), ub = (lx + 3) + BY * (ly + 3);
+    if (tid < CF::C * CF::P && i < f.nx && j < f.ny) {
+#pragma unroll
+        for (int m = 0; m < CF::J; ++m) {
+            const int lz = fzg + CF::P * m, k = fz0 + lz;
+            if (lz >= MGU_FZ || k >= f.nz) break;
+            const int y = yb + SZ * (lz + 1), u = ub + BZ * (lz + 3);
+            const int d = ds[u];
+            const V yc = ys[y];
+            const V nsum = ((ys[y - 1] + ys[y + 1]) + (ys[y - SY] + ys[y + SY])) + (ys[y - SZ] + ys[y + SZ]);
+            ((V*)f.x)[level_index(f, i, j, k)] = d ? yc + w * ((bs[u] - (V)d * yc) + nsum) * recip_nc<V>(d) : V(0);
+        }
+    }
+}
+
+template <typename V, int NT>
+__global__ __launch_bounds__(NT) void k_mg_up2(MgLevel f, MgLevel c, const PcgState* __restrict__ ps)
+{
+    mg_up2_body<V, NT>(plain_blk(), f, c, ps);
+}
+
+template <typename V>
+__global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_up2(const MgPairArgs* __restrict__ tab,
+                                                 const uint32_t* __restrict__ first, int ns)
+{
+    batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {
+        mg_up2_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
+    });
+}
+
 // ---- cell types of the coarse levels -----------------------------------------
 //
 // One wave per restriction block of level c (8 x 4 x 4 cells, two per lane):
@@ -563,10 +848,9 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
         if (nb < SMALL) c.dlist = nullptr;
         const int64_t grid = c.dlist ? c.nd : nb;
         if (grid <= 0) continue;
-        if (nb < SMALL)
-            hipLaunchKernelGGL((k_mg_down<V, 1024>), dim3((unsigned)grid), dim3(1024), 0, st, lv[l], c, ps);
-        else
-            hipLaunchKernelGGL((k_mg_down<V, 512>), dim3((unsigned)grid), dim3(512), 0, st, lv[l], c, ps);
+        auto kern = mg_two_sweeps(l) ? (nb < SMALL ? k_mg_down2<V, 1024> : k_mg_down2<V, 512>)
+                                     : (nb < SMALL ? k_mg_down<V, 1024> : k_mg_down<V, 512>);
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(nb < SMALL ? 1024 : 512), 0, st, lv[l], c, ps);
     }
     hipLaunchKernelGGL(k_mg_bottom<V>, dim3(1), dim3(512), 0, st, lv[nlev - 1], ps);
     for (int l = nlev - 2; l >= 0; --l) {
@@ -575,10 +859,9 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
         if (nb < SMALL) f.ulist = nullptr;
         const int64_t grid = f.ulist ? f.nu : nb;
         if (grid <= 0) continue;
-        if (nb < SMALL)
-            hipLaunchKernelGGL((k_mg_up<V, 1024>), dim3((unsigned)grid), dim3(1024), 0, st, f, lv[l + 1], ps);
-        else
-            hipLaunchKernelGGL((k_mg_up<V, 512>), dim3((unsigned)grid), dim3(512), 0, st, f, lv[l + 1], ps);
+        auto kern = mg_two_sweeps(l) ? (nb < SMALL ? k_mg_up2<V, 1024> : k_mg_up2<V, 512>)
+                                     : (nb < SMALL ? k_mg_up<V, 1024> : k_mg_up<V, 512>);
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(nb < SMALL ? 1024 : 512), 0, st, f, lv[l + 1], ps);
     }
 }
 
@@ -611,18 +894,20 @@ void launch_b_mg_types(const BatchLaunch& L, hipStream_t st)
 }
 
 template <typename V>
-void launch_b_mg_level(int kind, const BatchLaunch& L, hipStream_t st)
+void launch_b_mg_level(int kind, bool two_sweeps, const BatchLaunch& L, hipStream_t st)
 {
     if (L.blocks == 0) return;
     const MgPairArgs* a = (const MgPairArgs*)L.args;
     if (kind == MG_B_DOWN)
-        hipLaunchKernelGGL(kb_mg_down<V>, dim3(L.blocks), dim3(MG_BATCH_NT), 0, st, a, L.first, L.ns);
+        hipLaunchKernelGGL(two_sweeps ? kb_mg_down2<V> : kb_mg_down<V>, dim3(L.blocks), dim3(MG_BATCH_NT), 0, st, a,
+                           L.first, L.ns);
     else if (kind == MG_B_BOTTOM)
         hipLaunchKernelGGL(kb_mg_bottom<V>, dim3(L.blocks), dim3(512), 0, st, a, L.first, L.ns);
     else
-        hipLaunchKernelGGL(kb_mg_up<V>, dim3(L.blocks), dim3(MG_BATCH_NT), 0, st, a, L.first, L.ns);
+        hipLaunchKernelGGL(two_sweeps ? kb_mg_up2<V> : kb_mg_up<V>, dim3(L.blocks), dim3(MG_BATCH_NT), 0, st, a,
+                           L.first, L.ns);
 }
-template void launch_b_mg_level<float>(int, const BatchLaunch&, hipStream_t);
-template void launch_b_mg_level<double>(int, const BatchLaunch&, hipStream_t);
+template void launch_b_mg_level<float>(int, bool, const BatchLaunch&, hipStream_t);
+template void launch_b_mg_level<double>(int, bool, const BatchLaunch&, hipStream_t);
 
 }  // namespace flipmi
