@@ -59,14 +59,20 @@ def mg_coarse_cells(nx: int, ny: int, nz: int) -> int:
 
 
 def algorithmic_bytes(kind: str, rb: int, n: int, cells: int, faces: list, fluid: float,
-                      coarse: int = 0) -> float:
+                      coarse: int = 0, mg: bool = False) -> float:
     """Bytes the method must move per launch of each kernel (no cache re-reads).
 
     rb: bytes of the real type; n: particles; cells: grid cells; faces: face
     counts per component; fluid: fluid cells of the solve; coarse: cells of the
-    multigrid's coarse levels.
+    multigrid's coarse levels; mg: the multigrid solve, whose direction kernel
+    also stores q = A s and whose update kernel also does the V-cycle's
+    fine-level restriction (mg_down_fine then runs once per solve).
     """
     F = sum(faces)
+    if mg and kind == "pcg_direction":
+        return fluid * (4 * rb + 1)                     # z, s_old, diag in; s, q out
+    if mg and kind == "pcg_update":
+        return fluid * (6 * rb + 1) + cells / 8 * rb    # x, s, r, q, diag in; x, r, level-1 b out
     return {
         # multigrid V-cycle: fine level r, n_c in, level-1 b out (down); r, n_c,
         # level-1 x in, z out (up); each coarse cell b, n_c in and b out below
@@ -338,14 +344,17 @@ def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
         if cnt <= 0:
             continue
         avg = ms / cnt
-        launches = d_iter if name.startswith(("pcg_", "mg_")) else cnt
+        # the iteration kernels are timed on a sample of the iterations; the
+        # fine restriction of the multigrid solve's first V-cycle (the later
+        # ones are inside the update kernel) on every launch
+        launches = d_iter if name.startswith(("pcg_", "mg_")) and name != "mg_down_fine" else cnt
         kernels[name] = {"avg_ms": avg, "launches": launches, "est_total_ms": avg * launches}
     ts = args.timing_steps
     # the dominant single kernel (mg_coarse times several launches together)
     dominant = max((k for k in kernels if k != "mg_coarse"), key=lambda k: kernels[k]["est_total_ms"])
     kd = kernels[dominant]
     coarse = mg_coarse_cells(cfg.nx, cfg.ny, cfg.nz) if mgflag else 0
-    abytes = algorithmic_bytes(dominant, rb, n, cells, faces, fluid_avg, coarse)
+    abytes = algorithmic_bytes(dominant, rb, n, cells, faces, fluid_avg, coarse, bool(mgflag))
     achieved = abytes / (kd["avg_ms"] * 1e-3) / 1e9
     traffic = traffic_for(dominant, sc.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -354,7 +363,10 @@ def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
     pcg_ms = sum(v["est_total_ms"] for k, v in kernels.items() if k.startswith(("pcg_", "mg_")))
     pcg_bytes = d_cell_iter * (8 * rb + 2)
     if mgflag:
-        pcg_bytes += d_cell_iter * (3 * rb + 2) + d_iter * (cells / 4 * rb + coarse * (3 * rb + 2))
+        # direction 4 rb + 1, update with the fine restriction 6 rb + 1, fine
+        # prolongation 2 rb + 1 per fluid cell; level-1 b out and x in; the
+        # coarse levels
+        pcg_bytes = d_cell_iter * (12 * rb + 3) + d_iter * (cells / 4 * rb + coarse * (3 * rb + 2))
     pcg = {"iterations_per_step": (s_last.pcg_iterations_total - s_pre.pcg_iterations_total) / args.steps,
            "iterations_per_step_timing_run": d_iter / ts, "fluid_cells": round(fluid_avg),
            "last_residual_rel": s_last.max_r / s_last.max_b if s_last.max_b else 0.0,

@@ -126,6 +126,7 @@ struct DirArgs {
     const uint8_t* diag;
     const V *z, *s_old;
     V* s_new;
+    V* q;  // q = A s_new for the multigrid update, or null
     double* pslots;
     PcgState* ps;
 };
@@ -137,6 +138,23 @@ struct UpdArgs {
     const uint8_t* diag;
     const V* s;
     V *x, *z;
+    double* pslots;
+    PcgState* ps;
+};
+
+// the multigrid solve's update fused with the fine level's down kernel
+template <typename V>
+struct UpdDownArgs {
+    int na_hint;  // -1: as in DirArgs
+    Geo g;
+    const uint32_t* tile_list;
+    const int32_t* nbr;
+    const uint8_t* diag;
+    const V *s, *q;
+    V* x;
+    const V* r;
+    V* r_out;
+    MgLevel c;
     double* pslots;
     PcgState* ps;
 };
@@ -235,6 +253,8 @@ template <typename V>
 void launch_b_pcg_direction(const BatchLaunch& L, hipStream_t st);
 template <typename V>
 void launch_b_pcg_update(bool r_form, const BatchLaunch& L, hipStream_t st);
+template <typename V>
+void launch_b_pcg_update_down(const BatchLaunch& L, hipStream_t st);
 // the projection of the three components (one launch; project_blocks
 // workgroups per scene)
 int64_t project_blocks(const Geo& g);

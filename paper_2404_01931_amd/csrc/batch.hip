@@ -86,7 +86,7 @@ struct Sites {
     // multigrid (all scenes or none): levels below the fine grid, deepest scene
     bool mg = false;
     int mg_levels = 0;
-    Site mg_types_fine, mg_fine_down, mg_fine_up, mg_bottom;
+    Site mg_types_fine, mg_fine_down, mg_fine_up[2], mg_bottom, upd_down[2];
     Site mg_types[MG_MAX_LEVELS], mg_down[MG_MAX_LEVELS], mg_up[MG_MAX_LEVELS];
 };
 
@@ -280,11 +280,13 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
             q.max_iters = solve_iter_cap(c);
             q.r_form = S.mg ? 1 : 0;
             r[s] = q;
-            // with multigrid the direction kernel reads z = M r (h->z holds r)
-            const T* zdir = (const T*)(S.mg ? h->mgz : h->z);
             for (int k = 0; k < 2; ++k) {
-                DirArgs<T> d{-1, h->tile_nbr, h->diag, zdir, (const T*)h->s[k], (T*)h->s[k ^ 1], h->pslots,
-                             h->ps};
+                // with multigrid the direction kernel of an even iteration
+                // reads z = M r from h->mgz, of an odd one from h->z (r and z
+                // trade places at every update; see enqueue_chunk)
+                const T* zdir = (const T*)(S.mg ? (k ? h->z : h->mgz) : h->z);
+                DirArgs<T> d{-1, h->tile_nbr, h->diag, zdir, (const T*)h->s[k], (T*)h->s[k ^ 1],
+                             S.mg ? (T*)h->q : nullptr, h->pslots, h->ps};
                 UpdArgs<T> u{-1, h->tile_nbr, h->diag, (const T*)h->s[k ^ 1], (T*)h->xin[0], (T*)h->z, h->pslots,
                              h->ps};
                 (k ? d1 : d0)[s] = d;
@@ -313,8 +315,9 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
         const int L = mg_levels;
         S.mg_levels = L;
         std::vector<MgTypesFineArgs> tf(ns);
-        std::vector<MgFineArgs<T>> fd(ns), fu(ns);
+        std::vector<MgFineArgs<T>> fd(ns), fu0(ns), fu1(ns);
         std::vector<MgPairArgs> bo(ns);
+        std::vector<UpdDownArgs<T>> ud0(ns), ud1(ns);
         std::vector<uint32_t> btf(ns), bfine(ns), bbot(ns, 1u);
         for (size_t s = 0; s < ns; ++s) {
             flip_handle* h = hs[s];
@@ -323,16 +326,30 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
             btf[s] = (uint32_t)mg_blocks(MG_B_TYPES, l0, l0);
             fd[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, nullptr,
                                   nullptr, h->ps};
-            fu[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, (T*)h->mgz,
-                                  h->pslots, h->ps};
+            // the V-cycle before an even iteration's direction: r in h->z, z
+            // to h->mgz; before an odd one the other way round
+            fu0[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, (T*)h->mgz,
+                                   h->pslots, h->ps};
+            fu1[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->mgz, l0, (T*)h->z,
+                                   h->pslots, h->ps};
             bfine[s] = (uint32_t)h->groups;
+            for (int k = 0; k < 2; ++k) {
+                T* const r = (T*)(k ? h->mgz : h->z);  // r before update k; the new r goes to the other
+                T* const r_out = (T*)(k ? h->z : h->mgz);
+                (k ? ud1 : ud0)[s] = UpdDownArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag,
+                                                    (const T*)h->s[k ^ 1], (const T*)h->q, (T*)h->xin[0], r, r_out,
+                                                    l0, h->pslots, h->ps};
+            }
             const MgLevel bottom = unlisted(h->mg[h->nmg > 0 ? h->nmg - 1 : 0]);
             bo[s] = MgPairArgs{bottom, bottom, h->ps};
         }
         S.mg_types_fine = add_site(t, tf, btf, 256);
         S.mg_fine_down = add_site(t, fd, bfine, 256);
-        S.mg_fine_up = add_site(t, fu, bfine, 256);
+        S.mg_fine_up[0] = add_site(t, fu0, bfine, 256);
+        S.mg_fine_up[1] = add_site(t, fu1, bfine, 256);
         S.mg_bottom = add_site(t, bo, bbot, 512);
+        S.upd_down[0] = add_site(t, ud0, bfine, 256);
+        S.upd_down[1] = add_site(t, ud1, bfine, 256);
         for (int l = 0; l + 1 < L; ++l) {
             // level l to l + 1, for the scenes that have both
             std::vector<MgPairArgs> a(ns);
@@ -390,8 +407,11 @@ void for_each_site(S_& S, F&& f)
     if (S.mg) {
         f(S.mg_types_fine);
         f(S.mg_fine_down);
-        f(S.mg_fine_up);
+        f(S.mg_fine_up[0]);
+        f(S.mg_fine_up[1]);
         f(S.mg_bottom);
+        f(S.upd_down[0]);
+        f(S.upd_down[1]);
         for (int l = 0; l + 1 < S.mg_levels; ++l) {
             f(S.mg_types[l]);
             f(S.mg_down[l]);
@@ -411,7 +431,9 @@ bool sites_fit(const Sites& S)
         r = r && ok(S.dir[k]) && ok(S.upd[k]) && ok(S.ph[k].bin_keys) && ok(S.ph[k].gather) && ok(S.ph[k].p2g) &&
             ok(S.ph[k].g2p);
     if (S.mg) {
-        r = r && ok(S.mg_types_fine) && ok(S.mg_fine_down) && ok(S.mg_fine_up) && ok(S.mg_bottom);
+        r = r && ok(S.mg_types_fine) && ok(S.mg_fine_down) && ok(S.mg_fine_up[0]) && ok(S.mg_fine_up[1]) &&
+            ok(S.mg_bottom) &&
+            ok(S.upd_down[0]) && ok(S.upd_down[1]);
         for (int l = 0; l + 1 < S.mg_levels; ++l) r = r && ok(S.mg_types[l]) && ok(S.mg_down[l]) && ok(S.mg_up[l]);
     }
     return r;
@@ -536,16 +558,19 @@ BatchLaunch L(const flip_batch* b, const Site& s)
 // level down to the deepest scene's coarsest level, every scene's coarsest
 // sweeps, then the prolongations back up (a scene takes part in the level
 // launches it has, so its own order is down, bottom, up)
+// (fine_down false: the fine level's down kernel ran inside the update;
+// parity: that of the direction kernel that follows, which sets where r and
+// z are)
 template <typename T>
-void enqueue_vcycle(const flip_batch* b, hipStream_t st)
+void enqueue_vcycle(const flip_batch* b, hipStream_t st, bool fine_down, int parity)
 {
     const Sites& S = b->S;
-    launch_b_mg_fine<T>(false, L(b, S.mg_fine_down), st);
+    if (fine_down) launch_b_mg_fine<T>(false, L(b, S.mg_fine_down), st);
     for (int l = 0; l + 1 < S.mg_levels; ++l)
         launch_b_mg_level<T>(MG_B_DOWN, mg_two_sweeps(l), L(b, S.mg_down[l]), st);
     launch_b_mg_level<T>(MG_B_BOTTOM, false, L(b, S.mg_bottom), st);
     for (int l = S.mg_levels - 2; l >= 0; --l) launch_b_mg_level<T>(MG_B_UP, mg_two_sweeps(l), L(b, S.mg_up[l]), st);
-    launch_b_mg_fine<T>(true, L(b, S.mg_fine_up), st);
+    launch_b_mg_fine<T>(true, L(b, S.mg_fine_up[parity]), st);
 }
 
 // binning, tiles, particle-to-grid and the solver start of every scene
@@ -570,7 +595,7 @@ void enqueue_pre(const flip_batch* b, int ph, hipStream_t st)
     if (S.mg) {
         launch_b_mg_types_fine(L(b, S.mg_types_fine), st);
         for (int l = 0; l + 1 < S.mg_levels; ++l) launch_b_mg_types(L(b, S.mg_types[l]), st);
-        enqueue_vcycle<T>(b, st);
+        enqueue_vcycle<T>(b, st, true, 0);
     }
     launch_b_pcg_direction<T>(L(b, S.dir[0]), st);  // D_0
 }
@@ -583,8 +608,12 @@ void enqueue_chunk(const flip_batch* b, int iters, hipStream_t st)
 {
     const Sites& S = b->S;
     for (int i = 0; i < iters; ++i) {
-        launch_b_pcg_update<T>(S.mg, L(b, S.upd[i & 1]), st);
-        if (S.mg) enqueue_vcycle<T>(b, st);
+        if (S.mg) {
+            launch_b_pcg_update_down<T>(L(b, S.upd_down[i & 1]), st);
+            enqueue_vcycle<T>(b, st, false, (i + 1) & 1);
+        } else {
+            launch_b_pcg_update<T>(false, L(b, S.upd[i & 1]), st);
+        }
         launch_b_pcg_direction<T>(L(b, S.dir[(i + 1) & 1]), st);
     }
     launch_b_summary(L(b, S.summary), st);

@@ -291,6 +291,7 @@ void carve(flip_handle* h, Carver& cv)
         // z = M r, then the coarse levels: every axis halved (ceil) until
         // none has more than MG_BOTTOM_SIDE cells
         h->mgz = cv.take<void>(s.cap * rb);
+        h->q = cv.take<void>(s.cap * rb);
         int nx = h->cfg.nx, ny = h->cfg.ny, nz = h->cfg.nz;
         do {
             nx = (nx + 1) / 2;
@@ -411,44 +412,59 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
     const int next_chunk = mg_solve ? 2 : 8;
     int launched = 0;
     const int first_sample = h->ev_used / 2;
+    // FLIP_FLAG_MULTIGRID: r and z = M r live in h->z and h->mgz, which trade
+    // places at every update (the update kernel writes the new r to the
+    // vector that held z; see launch_pcg_update_down): before update k, r is
+    // in rvec(k) and the last V-cycle's z in zvec(k). A V-cycle runs before
+    // every direction kernel; after an update the V-cycle's fine down kernel
+    // is part of the update kernel, so `precondition` then starts at level 1.
+    // Without multigrid r / n lives in h->z.
+    const bool mg = h->nmg > 0;
+    auto rvec = [&](int k) { return (V*)((k & 1) ? h->mgz : h->z); };
+    auto zvec = [&](int k) { return (V*)((k & 1) ? h->z : h->mgz); };
     auto direction = [&](int k) {
         const int sc = h->scur;
         const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_pair(h, FLIP_KERNEL_PCG_DIRECTION, k) : -1;
-        launch_pcg_direction<V>(h->groups, h->na, h->tile_nbr, h->diag,
-                                (const V*)(h->nmg > 0 ? h->mgz : h->z), (const V*)h->s[sc],
-                                (V*)h->s[sc ^ 1], h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
-                                q >= 0 ? h->ev[q + 1] : nullptr);
+        launch_pcg_direction<V>(h->groups, h->na, h->tile_nbr, h->diag, mg ? zvec(k) : (const V*)h->z,
+                                (const V*)h->s[sc], (V*)h->s[sc ^ 1], mg ? (V*)h->q : nullptr, h->pslots, h->ps,
+                                st, q >= 0 ? h->ev[q] : nullptr, q >= 0 ? h->ev[q + 1] : nullptr);
     };
-    // FLIP_FLAG_MULTIGRID: h->z holds r, and z = M r goes to h->mgz; a
-    // V-cycle runs before every direction kernel
-    const bool mg = h->nmg > 0;
-    auto precondition = [&](int k) {
+    auto precondition = [&](int k, bool fine_down) {
         if (!mg) return;
         const bool timed = (k % TIMED_PCG_EVERY) == 0;
-        int q = timed ? timer_pair(h, FLIP_KERNEL_MG_DOWN_FINE, k) : -1;
-        launch_mg_fine<V>(false, h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag, (const V*)h->z,
-                          h->mg[0], nullptr, nullptr, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
-                          q >= 0 ? h->ev[q + 1] : nullptr);
+        int q = -1;
+        if (fine_down) {
+            q = timed ? timer_pair(h, FLIP_KERNEL_MG_DOWN_FINE, k) : -1;
+            launch_mg_fine<V>(false, h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag, rvec(k),
+                              h->mg[0], nullptr, nullptr, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
+                              q >= 0 ? h->ev[q + 1] : nullptr);
+        }
         q = timed ? timer_begin(h, FLIP_KERNEL_MG_COARSE, st, k) : -1;
         launch_mg_coarse<V>(h->mg, h->nmg, h->ps, st);
         timer_end(h, q, st);
         q = timed ? timer_pair(h, FLIP_KERNEL_MG_UP_FINE, k) : -1;
-        launch_mg_fine<V>(true, h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag, (const V*)h->z,
-                          h->mg[0], (V*)h->mgz, h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
+        launch_mg_fine<V>(true, h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag, rvec(k), h->mg[0],
+                          zvec(k), h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
                           q >= 0 ? h->ev[q + 1] : nullptr);
     };
-    precondition(0);
+    precondition(0, true);
     direction(0);
     for (;;) {
         for (int it = 0; it < chunk; ++it) {
             const int k = launched + it;
             const int sc = h->scur;
             const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_pair(h, FLIP_KERNEL_PCG_UPDATE, k) : -1;
-            launch_pcg_update<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
-                                 h->pslots, h->ps, mg, st, q >= 0 ? h->ev[q] : nullptr,
-                                 q >= 0 ? h->ev[q + 1] : nullptr);
+            if (mg)
+                launch_pcg_update_down<V>(h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag,
+                                          (const V*)h->s[sc ^ 1], (const V*)h->q, x, rvec(k), rvec(k + 1),
+                                          h->mg[0], h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
+                                          q >= 0 ? h->ev[q + 1] : nullptr);
+            else
+                launch_pcg_update<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
+                                     h->pslots, h->ps, false, st, q >= 0 ? h->ev[q] : nullptr,
+                                     q >= 0 ? h->ev[q + 1] : nullptr);
             h->scur = sc ^ 1;
-            precondition(k + 1);
+            precondition(k + 1, false);
             direction(k + 1);
         }
         launched += chunk;

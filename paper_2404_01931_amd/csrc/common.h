@@ -220,9 +220,10 @@ void launch_rhs(const Geo& g, int groups, const uint32_t* tile_list, const uint3
 // before the solver state is read), else -1. With ev_start/ev_stop non-null
 // the launch records the kernel's own start and end in those events
 // (dispatch latency excluded).
+// q_out: where the direction kernel stores q = A s (the multigrid solve), or null
 template <typename V>
 void launch_pcg_direction(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
-                          const V* s_old, V* s_new, double* pslots, PcgState* st_dev,
+                          const V* s_old, V* s_new, V* q_out, double* pslots, PcgState* st_dev,
                           hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 template <typename V>
 void launch_pcg_update(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* s, V* x,
@@ -290,6 +291,16 @@ void launch_mg_fine(bool up, int groups, int na_hint, const Geo& g, const uint32
 // the coarsest level, its sweeps, prolongations and smoothing back up to lv[0]
 template <typename V>
 void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream_t st);
+// the multigrid solve's update (residual form) fused with the fine level's
+// down kernel: x += alpha s, r_out = r - alpha q (q from the direction
+// kernel), level-1 b from r_out, as launch_pcg_update then
+// launch_mg_fine(down). r_out must not be r (the kernel reads r's halos
+// while it writes r_out).
+template <typename V>
+void launch_pcg_update_down(int groups, int na_hint, const Geo& g, const uint32_t* tile_list,
+                            const int32_t* tile_nbr, const uint8_t* diag, const V* s, const V* q, V* x,
+                            const V* r, V* r_out, const MgLevel& c, double* pslots, PcgState* st_dev,
+                            hipStream_t st, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 
 // projection (Eq. (5)) of the three velocity components, one launch
 template <typename T, typename V>

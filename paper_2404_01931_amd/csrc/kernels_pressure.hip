@@ -384,7 +384,7 @@ template <typename V, int AH>
 __device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tlast, int32_t& nn,
                                   const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
                                   const V* __restrict__ z, const V* __restrict__ s_old, V* __restrict__ s_new,
-                                  int tid, const HaloLane& hl)
+                                  V* __restrict__ q_out, int tid, const HaloLane& hl)
 {
     const V sc0 = fma(beta, cur.s.a, cur.z.a), sc1 = fma(beta, cur.s.b, cur.z.b);
     const V hv0 = fma(beta, cur.hs.a, cur.hz.a), hv1 = fma(beta, cur.hs.b, cur.hz.b);
@@ -400,6 +400,7 @@ __device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tla
     pair_neighbour_sums(st, tid, sc0, sc1, n0, n1);
     const V q0 = d0 ? fma((V)d0, sc0, -n0) : V(0);
     const V q1 = d1 ? fma((V)d1, sc1, -n1) : V(0);
+    if (q_out) st2(q_out, (int64_t)t * TILE_CELLS + 2 * tid, q0, q1);
     const double dot = (double)sc0 * (double)q0 + (double)sc1 * (double)q1;
     // The loads AH tiles ahead go out once nothing computed from cur's old
     // values is live (the compiler computes s in place of the loaded z), so
@@ -414,13 +415,14 @@ __device__ inline double dir_tile(V* st, DirRegs<V>& cur, V beta, int t, int tla
     return dot;
 }
 
-// direction kernel: s = z + beta s_old, q = A s, sigma = s.q
+// direction kernel: s = z + beta s_old, q = A s, sigma = s.q; q is stored
+// when q_out is set (the multigrid solve's update reads it)
 template <typename V>
 __device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const int32_t* __restrict__ nbr,
                                                    const uint8_t* __restrict__ diag,
                                                    const V* __restrict__ z, const V* __restrict__ s_old,
-                                                   V* __restrict__ s_new, double* __restrict__ pslots,
-                                                   PcgState* __restrict__ ps)
+                                                   V* __restrict__ s_new, V* __restrict__ q_out,
+                                                   double* __restrict__ pslots, PcgState* __restrict__ ps)
 {
     __shared__ alignas(16) V stg[2][STAGE2];
     __shared__ double red[2 * (PCG_NT / WAVE)];
@@ -479,10 +481,10 @@ __device__ __forceinline__ void pcg_direction_body(Blk blk, int na_hint, const i
         // makes the compiler wait for nearly all of them); the pairs left
         // over, fewer than AH / 2, follow the loop.
         auto pair = [&](DirRegs<V>& ra, DirRegs<V>& rb, int t) {
-            acc += dir_tile<V, AH>(stg[0], ra, beta, t, tlast, nn, nbr, diag, z, s_old, s_new, tid, hl);
+            acc += dir_tile<V, AH>(stg[0], ra, beta, t, tlast, nn, nbr, diag, z, s_old, s_new, q_out, tid, hl);
             const bool real = t + 1 < t1;
             const double v = dir_tile<V, AH>(stg[1], rb, beta, real ? t + 1 : tlast, tlast, nn, nbr, diag, z,
-                                             s_old, s_new, tid, hl);
+                                             s_old, s_new, q_out, tid, hl);
             acc += real ? v : 0.0;
         };
         const int pairs = (t1 - t0 + 1) >> 1;
@@ -504,11 +506,11 @@ __global__ __launch_bounds__(PCG_NT) void k_pcg_direction(int na_hint, const int
                                                           const uint8_t* __restrict__ diag,
                                                           const V* __restrict__ z,
                                                           const V* __restrict__ s_old,
-                                                          V* __restrict__ s_new,
+                                                          V* __restrict__ s_new, V* __restrict__ q_out,
                                                           double* __restrict__ pslots,
                                                           PcgState* __restrict__ ps)
 {
-    pcg_direction_body<V>(plain_blk(), na_hint, nbr, diag, z, s_old, s_new, pslots, ps);
+    pcg_direction_body<V>(plain_blk(), na_hint, nbr, diag, z, s_old, s_new, q_out, pslots, ps);
 }
 
 template <typename V>
@@ -516,7 +518,9 @@ __global__ __launch_bounds__(PCG_NT) void kb_pcg_direction(const DirArgs<V>* __r
                                                            const uint32_t* __restrict__ first, int ns)
 {
     batch_for_each(tab, first, ns, [&](Blk blk, const DirArgs<V>& a) {
-        pcg_direction_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old), as_global(a.s_new), as_global(a.pslots), as_global(a.ps));
+        pcg_direction_body<V>(blk, a.na_hint, as_global(a.nbr), as_global(a.diag), as_global(a.z), as_global(a.s_old),
+                              as_global(a.s_new), a.q ? as_global(a.q) : nullptr, as_global(a.pslots),
+                              as_global(a.ps));
     });
 }
 
@@ -532,22 +536,22 @@ template void launch_b_pcg_direction<double>(const BatchLaunch&, hipStream_t);
 
 template <typename V>
 void launch_pcg_direction(int groups, int na_hint, const int32_t* tile_nbr, const uint8_t* diag, const V* z,
-                          const V* s_old, V* s_new, double* pslots, PcgState* st_dev,
+                          const V* s_old, V* s_new, V* q_out, double* pslots, PcgState* st_dev,
                           hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
 {
     if (ev_start)
         hipExtLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop,
-                              0, na_hint, tile_nbr, diag, z, s_old, s_new, pslots, st_dev);
+                              0, na_hint, tile_nbr, diag, z, s_old, s_new, q_out, pslots, st_dev);
     else
         hipLaunchKernelGGL(k_pcg_direction<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, tile_nbr, diag,
-                           z, s_old, s_new, pslots, st_dev);
+                           z, s_old, s_new, q_out, pslots, st_dev);
 }
 
 template void launch_pcg_direction<float>(int, int, const int32_t*, const uint8_t*, const float*,
-                                          const float*, float*, double*, PcgState*, hipStream_t, hipEvent_t,
+                                          const float*, float*, float*, double*, PcgState*, hipStream_t, hipEvent_t,
                                           hipEvent_t);
 template void launch_pcg_direction<double>(int, int, const int32_t*, const uint8_t*, const double*,
-                                           const double*, double*, double*, PcgState*,
+                                           const double*, double*, double*, double*, PcgState*,
                                            hipStream_t, hipEvent_t, hipEvent_t);
 
 // ---------------------------------------------------------------------------
@@ -610,23 +614,18 @@ __device__ inline V mg_recip(int d)
     return smoother_recip<V>(d);
 }
 
-// one tile of the down kernel; returns nothing, writes level-1 b for the
-// tile's 4x4x4 parents (those inside level 1)
-template <typename V>
-__device__ inline void mg_down_tile(V* st, V* psum, MgRegs<V>& cur, int t, int tlast, int32_t& nn, uint32_t& tn,
-                                    const int32_t* __restrict__ nbr, const uint32_t* __restrict__ tile_list,
-                                    const uint8_t* __restrict__ diag, const V* __restrict__ r, const Geo& g,
-                                    const MgLevel& c, V* __restrict__ cb, int tid, const HaloLane& hl)
+// The down kernel's work on one tile from the pair's r and x0 = w r / n (u0,
+// u1) and the halo lane's x0 (h0, h1): writes level-1 b for the tile's
+// 4x4x4 parents (those inside level 1). fetch(slot, nbr slot, tile) loads
+// the tile two ahead once this tile's values are no longer needed.
+template <typename V, typename Fetch>
+__device__ inline void mg_down_stage(V* st, V* psum, V r0, V r1, V u0, V u1, V h0, V h1, int d0, int d1,
+                                     uint32_t tile_cur, int t, int tlast, int32_t& nn, uint32_t& tn,
+                                     const int32_t* __restrict__ nbr, const uint32_t* __restrict__ tile_list,
+                                     const Geo& g, const MgLevel& c, V* __restrict__ cb, int tid, const HaloLane& hl,
+                                     Fetch&& fetch)
 {
     const V w = V(6) / V(7);
-    const int d0 = (int)(cur.d & 0xFFu), d1 = (int)(cur.d >> 8);
-    const int hd0 = (int)(cur.hd & 0xFFu), hd1 = (int)(cur.hd >> 8);
-    const V r0 = cur.r.a, r1 = cur.r.b;
-    const V u0 = w * r0 * mg_recip<V>(d0), u1 = w * r1 * mg_recip<V>(d1);
-    const V hu0 = w * cur.hr.a * mg_recip<V>(hd0), hu1 = w * cur.hr.b * mg_recip<V>(hd1);
-    const V h0 = cur.m ? (hl.hi ? hu1 : hu0) : V(0);
-    const V h1 = cur.m ? hu1 : V(0);
-    const uint32_t tile_cur = cur.tile;
     st2(st, 2 * tid, u0, u1);
     st2(st, hl.dst, h0, h1);
     lds_barrier();
@@ -651,10 +650,31 @@ __device__ inline void mg_down_tile(V* st, V* psum, MgRegs<V>& cur, int t, int t
     }
     // nn and tn belong to tile t + 2 (loaded one tile ahead, like nn)
     __builtin_amdgcn_sched_barrier(0);
-    mg_fetch<V, false>(cur, r, diag, nullptr, g, c, min(t + 2, tlast), nn, tn, tid, hl);
+    fetch(min(t + 2, tlast), nn, tn);
     nn = nn3;
     tn = tn3;
     __builtin_amdgcn_sched_barrier(0);
+}
+
+// one tile of the down kernel
+template <typename V>
+__device__ inline void mg_down_tile(V* st, V* psum, MgRegs<V>& cur, int t, int tlast, int32_t& nn, uint32_t& tn,
+                                    const int32_t* __restrict__ nbr, const uint32_t* __restrict__ tile_list,
+                                    const uint8_t* __restrict__ diag, const V* __restrict__ r, const Geo& g,
+                                    const MgLevel& c, V* __restrict__ cb, int tid, const HaloLane& hl)
+{
+    const V w = V(6) / V(7);
+    const int d0 = (int)(cur.d & 0xFFu), d1 = (int)(cur.d >> 8);
+    const int hd0 = (int)(cur.hd & 0xFFu), hd1 = (int)(cur.hd >> 8);
+    const V r0 = cur.r.a, r1 = cur.r.b;
+    const V u0 = w * r0 * mg_recip<V>(d0), u1 = w * r1 * mg_recip<V>(d1);
+    const V hu0 = w * cur.hr.a * mg_recip<V>(hd0), hu1 = w * cur.hr.b * mg_recip<V>(hd1);
+    const V h0 = cur.m ? (hl.hi ? hu1 : hu0) : V(0);
+    const V h1 = cur.m ? hu1 : V(0);
+    mg_down_stage<V>(st, psum, r0, r1, u0, u1, h0, h1, d0, d1, cur.tile, t, tlast, nn, tn, nbr, tile_list, g, c, cb,
+                     tid, hl, [&](int slot, int32_t ns, uint32_t tl) {
+                         mg_fetch<V, false>(cur, r, diag, nullptr, g, c, slot, ns, tl, tid, hl);
+                     });
 }
 
 template <typename V>
@@ -974,6 +994,186 @@ template void launch_pcg_update<float>(int, int, const int32_t*, const uint8_t*,
                                        float*, double*, PcgState*, bool, hipStream_t, hipEvent_t, hipEvent_t);
 template void launch_pcg_update<double>(int, int, const int32_t*, const uint8_t*, const double*, double*,
                                         double*, double*, PcgState*, bool, hipStream_t, hipEvent_t, hipEvent_t);
+
+// ---------------------------------------------------------------------------
+// The multigrid solve's update and the fine level's down kernel in one pass.
+// The update leaves r' = r - alpha q (q = A s, stored by the direction
+// kernel) and the down kernel's first read is r' with its face halo, so one
+// kernel updates x and r and restricts r' to level 1. r' on the halo is
+// formed from the neighbour tile's r and q by the same operations as that
+// tile's own workgroup uses, and q is the value the update kernel would
+// recompute (the same fma on the same staged s), so every value written is
+// the one the two kernels write apart. The halo reads need the neighbour's r
+// unchanged while the kernel runs, so r' goes to another vector (r_out): the
+// caller alternates two vectors between r and the V-cycle's z.
+// ---------------------------------------------------------------------------
+
+template <typename V>
+struct UdRegs {
+    Pair<V> r, hr, q, hq, x, s;  // the pair's and the halo pair's r and q; the pair's x and s
+    uint32_t d, hd;              // n_c bytes of the pair and of the halo pair
+    uint32_t tile;               // grid index of the tile
+    bool m;                      // the halo's neighbour tile exists
+};
+
+template <typename V>
+__device__ inline void ud_fetch(UdRegs<V>& u, const V* __restrict__ r, const V* __restrict__ q,
+                                const V* __restrict__ x, const V* __restrict__ s, const uint8_t* __restrict__ diag,
+                                int slot, int32_t nslot, uint32_t tile, int tid, const HaloLane& hl)
+{
+    const int64_t e = (int64_t)slot * TILE_CELLS + 2 * tid;
+    const int64_t h = nslot >= 0 ? (int64_t)nslot * TILE_CELLS + hl.src : e;
+    u.r = ld2(r, e);
+    u.q = ld2(q, e);
+    u.x = ld2(x, e);
+    u.s = ld2(s, e);
+    u.d = *(const uint16_t*)(diag + e);
+    u.hr = ld2(r, h);
+    u.hq = ld2(q, h);
+    u.hd = *(const uint16_t*)(diag + h);
+    u.m = nslot >= 0;
+    u.tile = tile;
+}
+
+template <typename V>
+__device__ inline void ud_tile(V* st, V* psum, UdRegs<V>& cur, V alpha, int t, int tlast, int32_t& nn, uint32_t& tn,
+                               const int32_t* __restrict__ nbr, const uint32_t* __restrict__ tile_list,
+                               const uint8_t* __restrict__ diag, const V* __restrict__ s, const V* __restrict__ q,
+                               V* __restrict__ x, const V* __restrict__ r, V* __restrict__ r_out, const Geo& g,
+                               const MgLevel& c, V* __restrict__ cb, int tid, const HaloLane& hl)
+{
+    const V w = V(6) / V(7);
+    const int d0 = (int)(cur.d & 0xFFu), d1 = (int)(cur.d >> 8);
+    const int hd0 = (int)(cur.hd & 0xFFu), hd1 = (int)(cur.hd >> 8);
+    // the update in residual form (upd_cell)
+    const V x0 = fma(alpha, cur.s.a, cur.x.a), x1 = fma(alpha, cur.s.b, cur.x.b);
+    const V r0 = d0 ? fma(-alpha, cur.q.a, cur.r.a) : V(0);
+    const V r1 = d1 ? fma(-alpha, cur.q.b, cur.r.b) : V(0);
+    const V hr0 = hd0 ? fma(-alpha, cur.hq.a, cur.hr.a) : V(0);
+    const V hr1 = hd1 ? fma(-alpha, cur.hq.b, cur.hr.b) : V(0);
+    const int64_t e = (int64_t)t * TILE_CELLS + 2 * tid;
+    st2(x, e, x0, x1);
+    st2(r_out, e, r0, r1);
+    // the down kernel on r' (mg_down_tile)
+    const V u0 = w * r0 * mg_recip<V>(d0), u1 = w * r1 * mg_recip<V>(d1);
+    const V hu0 = w * hr0 * mg_recip<V>(hd0), hu1 = w * hr1 * mg_recip<V>(hd1);
+    const V h0 = cur.m ? (hl.hi ? hu1 : hu0) : V(0);
+    const V h1 = cur.m ? hu1 : V(0);
+    mg_down_stage<V>(st, psum, r0, r1, u0, u1, h0, h1, d0, d1, cur.tile, t, tlast, nn, tn, nbr, tile_list, g, c, cb,
+                     tid, hl, [&](int slot, int32_t ns, uint32_t tl) {
+                         ud_fetch<V>(cur, r, q, x, s, diag, slot, ns, tl, tid, hl);
+                     });
+}
+
+// x += alpha s; r_out = r - alpha q; level-1 b = R (r_out - A w r_out / n) / 2
+template <typename V>
+__device__ __forceinline__ void pcg_update_down_body(Blk blk, int na_hint, const Geo& g,
+                                                     const uint32_t* __restrict__ tile_list,
+                                                     const int32_t* __restrict__ nbr, const uint8_t* __restrict__ diag,
+                                                     const V* __restrict__ s, const V* __restrict__ q,
+                                                     V* __restrict__ x, const V* __restrict__ r,
+                                                     V* __restrict__ r_out, const MgLevel& c,
+                                                     double* __restrict__ pslots, PcgState* __restrict__ ps)
+{
+    __shared__ alignas(16) V stg[2][STAGE2];
+    __shared__ V psum[2][PCG_NT];
+    __shared__ double red[2 * (PCG_NT / WAVE)];
+    const int tid = threadIdx.x;
+    const HaloLane hl = halo_lane(tid);
+    const int na = na_hint >= 0 ? na_hint : ps->n_active;
+    int t0, t1;
+    tile_range(blk, na, t0, t1);
+    const int tlast = t0 < t1 ? t1 - 1 : max(min(t0, na - 1), 0);
+    V* const cb = (V*)c.b;
+    UdRegs<V> A, B;
+    int32_t nn = next_nbr(nbr, min(t0, tlast), hl);
+    uint32_t tn = next_tile(tile_list, min(t0, tlast));
+    ud_fetch<V>(A, r, q, x, s, diag, min(t0, tlast), nn, tn, tid, hl);
+    nn = next_nbr(nbr, min(t0 + 1, tlast), hl);
+    tn = next_tile(tile_list, min(t0 + 1, tlast));
+    ud_fetch<V>(B, r, q, x, s, diag, min(t0 + 1, tlast), nn, tn, tid, hl);
+    nn = next_nbr(nbr, min(t0 + 2, tlast), hl);
+    tn = next_tile(tile_list, min(t0 + 2, tlast));
+    // complete the direction kernel's reduction: alpha = rho / s.q (as in
+    // the update kernel)
+    const double sigma = reduce_slots_all<PCG_NT>(slot_sig(pslots, blk.n), blk.n, red);
+    if (ps->done != PCG_RUNNING) return;
+    const double rho = ps->rho;
+    const bool bad = !(sigma > 0.0) || !(sigma <= DBL_MAX);
+    const double alpha_d = rho / sigma;
+    if (blk.id == 0 && tid == 0) {
+        if (bad) ps->done = PCG_BREAKDOWN;
+        ps->alpha = alpha_d;
+        ps->rho_prev = rho;
+        ps->iter = ps->kd + 1;
+    }
+    if (bad || na == 0) return;
+    const V alpha = (V)alpha_d;
+    // unconditional tile pairs; an odd count repeats the last tile, which
+    // rewrites the same values
+    for (int t = t0; t < t1; t += 2) {
+        const bool real = t + 1 < t1;
+        ud_tile<V>(stg[0], psum[0], A, alpha, t, tlast, nn, tn, nbr, tile_list, diag, s, q, x, r, r_out, g, c, cb,
+                   tid, hl);
+        ud_tile<V>(stg[1], psum[1], B, alpha, real ? t + 1 : tlast, tlast, nn, tn, nbr, tile_list, diag, s, q, x, r,
+                   r_out, g, c, cb, tid, hl);
+    }
+}
+
+template <typename V>
+__global__ __launch_bounds__(PCG_NT) void k_pcg_update_down(int na_hint, Geo g, const uint32_t* __restrict__ tile_list,
+                                                            const int32_t* __restrict__ nbr,
+                                                            const uint8_t* __restrict__ diag, const V* __restrict__ s,
+                                                            const V* __restrict__ q, V* __restrict__ x,
+                                                            const V* __restrict__ r, V* __restrict__ r_out, MgLevel c,
+                                                            double* __restrict__ pslots, PcgState* __restrict__ ps)
+{
+    pcg_update_down_body<V>(plain_blk(), na_hint, g, tile_list, nbr, diag, s, q, x, r, r_out, c, pslots, ps);
+}
+
+template <typename V>
+__global__ __launch_bounds__(PCG_NT) void kb_pcg_update_down(const UpdDownArgs<V>* __restrict__ tab,
+                                                             const uint32_t* __restrict__ first, int ns)
+{
+    batch_for_each(tab, first, ns, [&](Blk blk, const UpdDownArgs<V>& a) {
+        MgLevel c = a.c;
+        c.b = as_global(c.b);
+        pcg_update_down_body<V>(blk, a.na_hint, a.g, as_global(a.tile_list), as_global(a.nbr), as_global(a.diag),
+                                as_global(a.s), as_global(a.q), as_global(a.x), as_global(a.r),
+                                as_global(a.r_out), c, as_global(a.pslots), as_global(a.ps));
+    });
+}
+
+template <typename V>
+void launch_b_pcg_update_down(const BatchLaunch& L, hipStream_t st)
+{
+    if (L.blocks == 0) return;
+    hipLaunchKernelGGL(kb_pcg_update_down<V>, dim3(L.blocks), dim3(PCG_NT), 0, st, (const UpdDownArgs<V>*)L.args,
+                       L.first, L.ns);
+}
+template void launch_b_pcg_update_down<float>(const BatchLaunch&, hipStream_t);
+template void launch_b_pcg_update_down<double>(const BatchLaunch&, hipStream_t);
+
+template <typename V>
+void launch_pcg_update_down(int groups, int na_hint, const Geo& g, const uint32_t* tile_list,
+                            const int32_t* tile_nbr, const uint8_t* diag, const V* s, const V* q, V* x,
+                            const V* r, V* r_out, const MgLevel& c, double* pslots, PcgState* st_dev,
+                            hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop)
+{
+    if (ev_start)
+        hipExtLaunchKernelGGL(k_pcg_update_down<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, ev_start, ev_stop,
+                              0, na_hint, g, tile_list, tile_nbr, diag, s, q, x, r, r_out, c, pslots, st_dev);
+    else
+        hipLaunchKernelGGL(k_pcg_update_down<V>, dim3((unsigned)groups), dim3(PCG_NT), 0, st, na_hint, g, tile_list,
+                           tile_nbr, diag, s, q, x, r, r_out, c, pslots, st_dev);
+}
+template void launch_pcg_update_down<float>(int, int, const Geo&, const uint32_t*, const int32_t*, const uint8_t*,
+                                            const float*, const float*, float*, const float*, float*, const MgLevel&,
+                                            double*, PcgState*, hipStream_t, hipEvent_t, hipEvent_t);
+template void launch_pcg_update_down<double>(int, int, const Geo&, const uint32_t*, const int32_t*,
+                                             const uint8_t*, const double*, const double*, double*, const double*,
+                                             double*, const MgLevel&, double*, PcgState*, hipStream_t, hipEvent_t,
+                                             hipEvent_t);
 
 // ---------------------------------------------------------------------------
 // Mixed precision (FLIP_MIXED): FP32 inner Jacobi-PCG (FP32 vectors and
