@@ -64,9 +64,9 @@ def algorithmic_bytes(kind: str, rb: int, n: int, cells: int, faces: list, fluid
 
     rb: bytes of the real type; n: particles; cells: grid cells; faces: face
     counts per component; fluid: fluid cells of the solve; coarse: cells of the
-    multigrid's coarse levels; mg: the multigrid solve, whose direction kernel
-    also stores q = A s and whose update kernel also does the V-cycle's
-    fine-level restriction (mg_down_fine then runs once per solve).
+    multigrid's coarse levels; mg: the multigrid solve with FP32 vectors, whose
+    direction kernel also stores q = A s and whose update kernel also does the
+    V-cycle's fine-level restriction (mg_down_fine then runs once per solve).
     """
     F = sum(faces)
     if mg and kind == "pcg_direction":
@@ -332,6 +332,7 @@ def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
     progress(f"kernel timing over {args.timing_steps} steps")
 
     rb = 8 if cfg.precision == flip.FLIP_FP64 else 4
+    fused = bool(mgflag) and rb == 4  # the FP32-vector multigrid solve fuses its update and fine restriction
     cells = cfg.nx * cfg.ny * cfg.nz
     faces = [(cfg.nx + 1) * cfg.ny * cfg.nz, cfg.nx * (cfg.ny + 1) * cfg.nz, cfg.nx * cfg.ny * (cfg.nz + 1)]
     d_iter = s1.pcg_iterations_total - s0.pcg_iterations_total
@@ -345,16 +346,17 @@ def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
             continue
         avg = ms / cnt
         # the iteration kernels are timed on a sample of the iterations; the
-        # fine restriction of the multigrid solve's first V-cycle (the later
-        # ones are inside the update kernel) on every launch
-        launches = d_iter if name.startswith(("pcg_", "mg_")) and name != "mg_down_fine" else cnt
+        # fine restriction of the FP32 multigrid solve's first V-cycle (the
+        # later ones are inside the update kernel) on every launch
+        sampled = name.startswith(("pcg_", "mg_")) and not (fused and name == "mg_down_fine")
+        launches = d_iter if sampled else cnt
         kernels[name] = {"avg_ms": avg, "launches": launches, "est_total_ms": avg * launches}
     ts = args.timing_steps
     # the dominant single kernel (mg_coarse times several launches together)
     dominant = max((k for k in kernels if k != "mg_coarse"), key=lambda k: kernels[k]["est_total_ms"])
     kd = kernels[dominant]
     coarse = mg_coarse_cells(cfg.nx, cfg.ny, cfg.nz) if mgflag else 0
-    abytes = algorithmic_bytes(dominant, rb, n, cells, faces, fluid_avg, coarse, bool(mgflag))
+    abytes = algorithmic_bytes(dominant, rb, n, cells, faces, fluid_avg, coarse, fused)
     achieved = abytes / (kd["avg_ms"] * 1e-3) / 1e9
     traffic = traffic_for(dominant, sc.name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -362,11 +364,13 @@ def measure(args, sc, solver: str, with_surface: bool = False) -> dict:
                 "avg_launch_ms": round(kd["avg_ms"], 5), "bytes_per_launch": abytes}
     pcg_ms = sum(v["est_total_ms"] for k, v in kernels.items() if k.startswith(("pcg_", "mg_")))
     pcg_bytes = d_cell_iter * (8 * rb + 2)
-    if mgflag:
+    if fused:
         # direction 4 rb + 1, update with the fine restriction 6 rb + 1, fine
         # prolongation 2 rb + 1 per fluid cell; level-1 b out and x in; the
         # coarse levels
         pcg_bytes = d_cell_iter * (12 * rb + 3) + d_iter * (cells / 4 * rb + coarse * (3 * rb + 2))
+    elif mgflag:
+        pcg_bytes += d_cell_iter * (3 * rb + 2) + d_iter * (cells / 4 * rb + coarse * (3 * rb + 2))
     pcg = {"iterations_per_step": (s_last.pcg_iterations_total - s_pre.pcg_iterations_total) / args.steps,
            "iterations_per_step_timing_run": d_iter / ts, "fluid_cells": round(fluid_avg),
            "last_residual_rel": s_last.max_r / s_last.max_b if s_last.max_b else 0.0,

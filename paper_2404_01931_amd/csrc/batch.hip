@@ -85,6 +85,7 @@ struct Sites {
     size_t summary_off = 0;  // SolveSummary[ns]
     // multigrid (all scenes or none): levels below the fine grid, deepest scene
     bool mg = false;
+    bool fused = false;  // the multigrid update with the fine restriction (FP32 vectors)
     int mg_levels = 0;
     Site mg_types_fine, mg_fine_down, mg_fine_up[2], mg_bottom, upd_down[2];
     Site mg_types[MG_MAX_LEVELS], mg_down[MG_MAX_LEVELS], mg_up[MG_MAX_LEVELS];
@@ -123,6 +124,8 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
                  const char* dws, Tables& t, Sites& S)
 {
     const size_t ns = slots.size();
+    S.fused = S.mg && mg_fused_update(sizeof(T));
+    const bool fused = S.fused;
     static flip_handle empty_slot;  // stands in for an empty slot (zero sizes, null pointers)
     std::vector<flip_handle*> hs(ns);
     t.live.assign(ns, 0);
@@ -281,12 +284,12 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
             q.r_form = S.mg ? 1 : 0;
             r[s] = q;
             for (int k = 0; k < 2; ++k) {
-                // with multigrid the direction kernel of an even iteration
-                // reads z = M r from h->mgz, of an odd one from h->z (r and z
-                // trade places at every update; see enqueue_chunk)
-                const T* zdir = (const T*)(S.mg ? (k ? h->z : h->mgz) : h->z);
+                // with multigrid the direction kernel reads z = M r from
+                // h->mgz, with the fused update that of an odd iteration from
+                // h->z (r and z trade places at every update; see enqueue_chunk)
+                const T* zdir = (const T*)(S.mg ? (fused && k ? h->z : h->mgz) : h->z);
                 DirArgs<T> d{-1, h->tile_nbr, h->diag, zdir, (const T*)h->s[k], (T*)h->s[k ^ 1],
-                             S.mg ? (T*)h->q : nullptr, h->pslots, h->ps};
+                             fused ? (T*)h->q : nullptr, h->pslots, h->ps};
                 UpdArgs<T> u{-1, h->tile_nbr, h->diag, (const T*)h->s[k ^ 1], (T*)h->xin[0], (T*)h->z, h->pslots,
                              h->ps};
                 (k ? d1 : d0)[s] = d;
@@ -330,8 +333,9 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
             // to h->mgz; before an odd one the other way round
             fu0[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->z, l0, (T*)h->mgz,
                                    h->pslots, h->ps};
-            fu1[s] = MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->mgz, l0, (T*)h->z,
-                                   h->pslots, h->ps};
+            fu1[s] = fused ? MgFineArgs<T>{-1, h->geo, h->tile_list, h->tile_nbr, h->diag, (const T*)h->mgz, l0,
+                                           (T*)h->z, h->pslots, h->ps}
+                           : fu0[s];
             bfine[s] = (uint32_t)h->groups;
             for (int k = 0; k < 2; ++k) {
                 T* const r = (T*)(k ? h->mgz : h->z);  // r before update k; the new r goes to the other
@@ -608,11 +612,12 @@ void enqueue_chunk(const flip_batch* b, int iters, hipStream_t st)
 {
     const Sites& S = b->S;
     for (int i = 0; i < iters; ++i) {
-        if (S.mg) {
+        if (S.fused) {
             launch_b_pcg_update_down<T>(L(b, S.upd_down[i & 1]), st);
             enqueue_vcycle<T>(b, st, false, (i + 1) & 1);
         } else {
-            launch_b_pcg_update<T>(false, L(b, S.upd[i & 1]), st);
+            launch_b_pcg_update<T>(S.mg, L(b, S.upd[i & 1]), st);
+            if (S.mg) enqueue_vcycle<T>(b, st, true, (i + 1) & 1);
         }
         launch_b_pcg_direction<T>(L(b, S.dir[(i + 1) & 1]), st);
     }

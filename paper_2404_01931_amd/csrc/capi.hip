@@ -291,7 +291,7 @@ void carve(flip_handle* h, Carver& cv)
         // z = M r, then the coarse levels: every axis halved (ceil) until
         // none has more than MG_BOTTOM_SIDE cells
         h->mgz = cv.take<void>(s.cap * rb);
-        h->q = cv.take<void>(s.cap * rb);
+        if (mg_fused_update(rb)) h->q = cv.take<void>(s.cap * rb);
         int nx = h->cfg.nx, ny = h->cfg.ny, nz = h->cfg.nz;
         do {
             nx = (nx + 1) / 2;
@@ -412,21 +412,22 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
     const int next_chunk = mg_solve ? 2 : 8;
     int launched = 0;
     const int first_sample = h->ev_used / 2;
-    // FLIP_FLAG_MULTIGRID: r and z = M r live in h->z and h->mgz, which trade
-    // places at every update (the update kernel writes the new r to the
-    // vector that held z; see launch_pcg_update_down): before update k, r is
-    // in rvec(k) and the last V-cycle's z in zvec(k). A V-cycle runs before
-    // every direction kernel; after an update the V-cycle's fine down kernel
-    // is part of the update kernel, so `precondition` then starts at level 1.
-    // Without multigrid r / n lives in h->z.
+    // FLIP_FLAG_MULTIGRID: r lives in rvec(k) before update k and the last
+    // V-cycle's z = M r in zvec(k); a V-cycle runs before every direction
+    // kernel. With FP32 vectors the update kernel also does the V-cycle's
+    // fine down kernel (launch_pcg_update_down), so `precondition` then
+    // starts at level 1, and it writes the new r to the vector that held z:
+    // h->z and h->mgz trade places at every update. In FP64, r stays in h->z
+    // and z in h->mgz. Without multigrid r / n lives in h->z.
     const bool mg = h->nmg > 0;
-    auto rvec = [&](int k) { return (V*)((k & 1) ? h->mgz : h->z); };
-    auto zvec = [&](int k) { return (V*)((k & 1) ? h->z : h->mgz); };
+    const bool fused = mg && mg_fused_update(sizeof(V));
+    auto rvec = [&](int k) { return (V*)(fused && (k & 1) ? h->mgz : h->z); };
+    auto zvec = [&](int k) { return (V*)(fused && (k & 1) ? h->z : h->mgz); };
     auto direction = [&](int k) {
         const int sc = h->scur;
         const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_pair(h, FLIP_KERNEL_PCG_DIRECTION, k) : -1;
         launch_pcg_direction<V>(h->groups, h->na, h->tile_nbr, h->diag, mg ? zvec(k) : (const V*)h->z,
-                                (const V*)h->s[sc], (V*)h->s[sc ^ 1], mg ? (V*)h->q : nullptr, h->pslots, h->ps,
+                                (const V*)h->s[sc], (V*)h->s[sc ^ 1], fused ? (V*)h->q : nullptr, h->pslots, h->ps,
                                 st, q >= 0 ? h->ev[q] : nullptr, q >= 0 ? h->ev[q + 1] : nullptr);
     };
     auto precondition = [&](int k, bool fine_down) {
@@ -454,17 +455,17 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
             const int k = launched + it;
             const int sc = h->scur;
             const int q = (k % TIMED_PCG_EVERY) == 0 ? timer_pair(h, FLIP_KERNEL_PCG_UPDATE, k) : -1;
-            if (mg)
+            if (fused)
                 launch_pcg_update_down<V>(h->groups, h->na, h->geo, h->tile_list, h->tile_nbr, h->diag,
                                           (const V*)h->s[sc ^ 1], (const V*)h->q, x, rvec(k), rvec(k + 1),
                                           h->mg[0], h->pslots, h->ps, st, q >= 0 ? h->ev[q] : nullptr,
                                           q >= 0 ? h->ev[q + 1] : nullptr);
             else
                 launch_pcg_update<V>(h->groups, h->na, h->tile_nbr, h->diag, (const V*)h->s[sc ^ 1], x, (V*)h->z,
-                                     h->pslots, h->ps, false, st, q >= 0 ? h->ev[q] : nullptr,
+                                     h->pslots, h->ps, mg, st, q >= 0 ? h->ev[q] : nullptr,
                                      q >= 0 ? h->ev[q + 1] : nullptr);
             h->scur = sc ^ 1;
-            precondition(k + 1, false);
+            precondition(k + 1, !fused);
             direction(k + 1);
         }
         launched += chunk;

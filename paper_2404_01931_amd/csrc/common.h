@@ -273,6 +273,10 @@ constexpr int MG_BOTTOM_SWEEPS = 10;   // Jacobi sweeps on the coarsest level
 // 1); the fine level has one sweep.
 constexpr int MG_TWO_SWEEPS_FROM = 1;
 inline bool mg_two_sweeps(int dense_index) { return dense_index >= MG_TWO_SWEEPS_FROM; }
+// whether a multigrid solve with solver vectors of `vector_bytes` bytes runs
+// the fused update (launch_pcg_update_down): FP32 vectors (the FP32 path and
+// the mixed path's inner solves), not FP64
+inline bool mg_fused_update(size_t vector_bytes) { return vector_bytes == 4; }
 // cell types of the first coarse level from the fine n_c, and of each next one
 void launch_mg_types_fine(const Geo& g, const int32_t* tile_slot, const uint8_t* diag, const MgLevel& c,
                           hipStream_t st);
@@ -295,7 +299,9 @@ void launch_mg_coarse(const MgLevel* lv, int nlev, const PcgState* ps, hipStream
 // down kernel: x += alpha s, r_out = r - alpha q (q from the direction
 // kernel), level-1 b from r_out, as launch_pcg_update then
 // launch_mg_fine(down). r_out must not be r (the kernel reads r's halos
-// while it writes r_out).
+// while it writes r_out). Used with FP32 solver vectors (mg_fused_update);
+// in FP64 the extra q vector costs the direction kernel more than the
+// fusion saves.
 template <typename V>
 void launch_pcg_update_down(int groups, int na_hint, const Geo& g, const uint32_t* tile_list,
                             const int32_t* tile_nbr, const uint8_t* diag, const V* s, const V* q, V* x,

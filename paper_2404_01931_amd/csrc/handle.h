@@ -54,7 +54,7 @@ struct flip_handle {
     int xi = 0;                                // current solution buffer
     int scur = 0;                              // current direction buffer
     void* mgz = nullptr;                       // FLIP_FLAG_MULTIGRID: z = M r
-    void* q = nullptr;                         // FLIP_FLAG_MULTIGRID: q = A s from the direction kernel
+    void* q = nullptr;                         // FLIP_FLAG_MULTIGRID, FP32 vectors: q = A s from the direction kernel
     flipmi::MgLevel mg[flipmi::MG_MAX_LEVELS] = {};  // coarse levels below the fine grid
     int nmg = 0;
     uint32_t* mg_cnt = nullptr;     // block counts of every level (2 per level)
