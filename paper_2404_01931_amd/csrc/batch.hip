@@ -305,8 +305,10 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
         S.rhs = add_site(t, r, bg, TILE_CELLS);
         S.dir[0] = add_site(t, d0, bg, 256);
         S.dir[1] = add_site(t, d1, bg, 256);
-        S.upd[0] = add_site(t, u0, bg, 256);
-        S.upd[1] = add_site(t, u1, bg, 256);
+        if (!fused) {  // the fused multigrid update has its own sites
+            S.upd[0] = add_site(t, u0, bg, 256);
+            S.upd[1] = add_site(t, u1, bg, 256);
+        }
         S.project = add_site(t, pr, bf, 256);
     }
     if (S.mg) {
@@ -352,8 +354,10 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
         S.mg_fine_up[0] = add_site(t, fu0, bfine, 256);
         S.mg_fine_up[1] = add_site(t, fu1, bfine, 256);
         S.mg_bottom = add_site(t, bo, bbot, 512);
-        S.upd_down[0] = add_site(t, ud0, bfine, 256);
-        S.upd_down[1] = add_site(t, ud1, bfine, 256);
+        if (fused) {
+            S.upd_down[0] = add_site(t, ud0, bfine, 256);
+            S.upd_down[1] = add_site(t, ud1, bfine, 256);
+        }
         for (int l = 0; l + 1 < L; ++l) {
             // level l to l + 1, for the scenes that have both
             std::vector<MgPairArgs> a(ns);
