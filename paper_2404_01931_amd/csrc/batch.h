@@ -216,6 +216,9 @@ enum { MG_B_TYPES = 0, MG_B_DOWN = 1, MG_B_BOTTOM = 2, MG_B_UP = 3 };
 // a serving batch's scenes are 32^3 to 96^3, all their dense levels small; on
 // the serving stream 512 measured 1% above 256 and 1024
 constexpr int MG_BATCH_NT = 512;
+// the same for the two-sweep levels, whose regions have more columns (22 x 14
+// of b and n: with 512 threads one thread per column walks all 14 planes)
+constexpr int MG_BATCH_NT2 = 1024;
 // workgroups of one scene's plain launch of a coarse kernel of that kind
 int64_t mg_blocks(int kind, const MgLevel& f, const MgLevel& c);
 

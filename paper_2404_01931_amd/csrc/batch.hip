@@ -374,8 +374,9 @@ void build_sites(const std::vector<flip_handle*>& slots, const std::vector<int>&
                 bu[s] = (uint32_t)mg_blocks(MG_B_UP, f, c);
             }
             S.mg_types[l] = add_site(t, a, bt, 256);
-            S.mg_down[l] = add_site(t, a, bd, MG_BATCH_NT);
-            S.mg_up[l] = add_site(t, a, bu, MG_BATCH_NT);
+            const int nt = mg_two_sweeps(l) ? MG_BATCH_NT2 : MG_BATCH_NT;
+            S.mg_down[l] = add_site(t, a, bd, nt);
+            S.mg_up[l] = add_site(t, a, bu, nt);
         }
     }
     {

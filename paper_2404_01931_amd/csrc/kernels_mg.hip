@@ -347,11 +347,11 @@ __global__ __launch_bounds__(NT) void k_mg_down2(MgLevel f, MgLevel c, const Pcg
 }
 
 template <typename V>
-__global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_down2(const MgPairArgs* __restrict__ tab,
+__global__ __launch_bounds__(MG_BATCH_NT2) void kb_mg_down2(const MgPairArgs* __restrict__ tab,
                                                    const uint32_t* __restrict__ first, int ns)
 {
     batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {
-        mg_down2_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
+        mg_down2_body<V, MG_BATCH_NT2>(b, glob(a.f), glob(a.c), as_global(a.ps));
     });
 }
 
@@ -705,11 +705,11 @@ __global__ __launch_bounds__(NT) void k_mg_up2(MgLevel f, MgLevel c, const PcgSt
 }
 
 template <typename V>
-__global__ __launch_bounds__(MG_BATCH_NT) void kb_mg_up2(const MgPairArgs* __restrict__ tab,
+__global__ __launch_bounds__(MG_BATCH_NT2) void kb_mg_up2(const MgPairArgs* __restrict__ tab,
                                                  const uint32_t* __restrict__ first, int ns)
 {
     batch_for_each(tab, first, ns, [&](Blk b, const MgPairArgs& a) {
-        mg_up2_body<V, MG_BATCH_NT>(b, glob(a.f), glob(a.c), as_global(a.ps));
+        mg_up2_body<V, MG_BATCH_NT2>(b, glob(a.f), glob(a.c), as_global(a.ps));
     });
 }
 
@@ -899,13 +899,13 @@ void launch_b_mg_level(int kind, bool two_sweeps, const BatchLaunch& L, hipStrea
     if (L.blocks == 0) return;
     const MgPairArgs* a = (const MgPairArgs*)L.args;
     if (kind == MG_B_DOWN)
-        hipLaunchKernelGGL(two_sweeps ? kb_mg_down2<V> : kb_mg_down<V>, dim3(L.blocks), dim3(MG_BATCH_NT), 0, st, a,
-                           L.first, L.ns);
+        hipLaunchKernelGGL(two_sweeps ? kb_mg_down2<V> : kb_mg_down<V>, dim3(L.blocks),
+                           dim3(two_sweeps ? MG_BATCH_NT2 : MG_BATCH_NT), 0, st, a, L.first, L.ns);
     else if (kind == MG_B_BOTTOM)
         hipLaunchKernelGGL(kb_mg_bottom<V>, dim3(L.blocks), dim3(512), 0, st, a, L.first, L.ns);
     else
-        hipLaunchKernelGGL(two_sweeps ? kb_mg_up2<V> : kb_mg_up<V>, dim3(L.blocks), dim3(MG_BATCH_NT), 0, st, a,
-                           L.first, L.ns);
+        hipLaunchKernelGGL(two_sweeps ? kb_mg_up2<V> : kb_mg_up<V>, dim3(L.blocks),
+                           dim3(two_sweeps ? MG_BATCH_NT2 : MG_BATCH_NT), 0, st, a, L.first, L.ns);
 }
 template void launch_b_mg_level<float>(int, bool, const BatchLaunch&, hipStream_t);
 template void launch_b_mg_level<double>(int, bool, const BatchLaunch&, hipStream_t);
