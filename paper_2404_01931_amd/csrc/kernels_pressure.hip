@@ -1396,21 +1396,6 @@ void launch_ir_update(int groups, const int32_t* tile_nbr, const uint8_t* diag, 
 // face touching a fluid cell; p = 0 in air
 // ---------------------------------------------------------------------------
 
-// Fluid status and pressure of cell (i, j, k), both from the tile layout: a
-// fluid cell of an active tile has a nonzero n_c byte (every cell of a grid
-// with more than one cell has a neighbour; a one-cell grid has no interior
-// face), every other cell is not fluid and holds p = 0.
-template <typename V>
-__device__ inline bool tile_fluid(const Geo& g, const int32_t* __restrict__ tile_slot, const uint8_t* __restrict__ diag,
-                                  const V* __restrict__ p, int i, int j, int k, V& pv)
-{
-    const int32_t s = tile_slot[(i >> 3) + g.tx * ((j >> 3) + g.ty * (k >> 3))];
-    const int64_t e = (int64_t)(s >= 0 ? s : 0) * TILE_CELLS + (i & 7) + 8 * (j & 7) + 64 * (k & 7);
-    const bool fl = s >= 0 && diag[e] > 0;
-    pv = fl ? p[e] : V(0);
-    return fl;
-}
-
 // Projection (Eq. (5)) of all three components in one pass: thread (i, j, k)
 // updates the u, v and w faces at that index that exist. A face between two
 // cells of the domain with a fluid cell on either side takes
@@ -1449,11 +1434,32 @@ __device__ __forceinline__ void project3_body(Blk blk, const Geo& g, const uint8
     const int64_t fv = i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k);
     const int64_t fw = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
     T o_u = has_u ? su[fu] : T(0), o_v = has_v ? sv[fv] : T(0), o_w = has_w ? sw[fw] : T(0);
-    V vc = V(0), vx = V(0), vy = V(0), vz = V(0);
-    const bool fc = (int_u || int_v || int_w) && in_c && tile_fluid(g, tile_slot, diag, p, i, j, k, vc);
-    const bool fx = int_u && tile_fluid(g, tile_slot, diag, p, i - 1, j, k, vx);
-    const bool fy = int_v && tile_fluid(g, tile_slot, diag, p, i, j - 1, k, vy);
-    const bool fz = int_w && tile_fluid(g, tile_slot, diag, p, i, j, k - 1, vz);
+    // Fluid status and pressure of this cell and its three lower neighbours,
+    // from the tile layout: a fluid cell of an active tile has a nonzero n_c
+    // byte (every cell of a grid with more than one cell has a neighbour; a
+    // one-cell grid has no interior face), every other cell is not fluid and
+    // holds p = 0. The four lookups go out at once, at coordinates clamped
+    // into the grid (a lookup whose face does not need it is masked below):
+    // two rounds of loads instead of a chain of four lookups.
+    const int ic = min(i, g.nx - 1), jc = min(j, g.ny - 1), kc = min(k, g.nz - 1);
+    const int ci[4] = {ic, max(i - 1, 0), ic, ic}, cj[4] = {jc, jc, max(j - 1, 0), jc};
+    const int ck[4] = {kc, kc, kc, max(k - 1, 0)};
+    int32_t sl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sl[q] = tile_slot[(ci[q] >> 3) + g.tx * ((cj[q] >> 3) + g.ty * (ck[q] >> 3))];
+    bool fl[4];
+    V pv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t e = (int64_t)(sl[q] >= 0 ? sl[q] : 0) * TILE_CELLS + (ci[q] & 7) + 8 * (cj[q] & 7) +
+                          64 * (ck[q] & 7);
+        const V pr = p[e];
+        fl[q] = sl[q] >= 0 && diag[e] > 0;
+        pv[q] = fl[q] ? pr : V(0);
+    }
+    const bool fc = (int_u || int_v || int_w) && in_c && fl[0];
+    const bool fx = int_u && fl[1], fy = int_v && fl[2], fz = int_w && fl[3];
+    const V vc = pv[0], vx = pv[1], vy = pv[2], vz = pv[3];
     const V pp = fc ? vc : V(0);
     if (int_u && (fc || fx)) o_u = o_u - (T)(scale * (pp - (fx ? vx : V(0))));
     if (int_v && (fc || fy)) o_v = o_v - (T)(scale * (pp - (fy ? vy : V(0))));
