@@ -21,7 +21,7 @@ constexpr size_t TABLE_ALIGN = 256;
 constexpr int GRAPH_CHUNK = 8;  // solver iterations per recorded chunk (even: direction buffers alternate)
 constexpr int FIRST_CHUNK = 16; // solver iterations before the first convergence check, without history
 constexpr int NEXT_CHUNK = 8;   // solver iterations between later checks
-// Multigrid batches: an iteration launched past convergence costs fourteen
+// Multigrid batches: an iteration launched past convergence costs a dozen
 // launches, so they start with the previous step's largest count and then
 // test every MG_NEXT_CHUNK iterations (a recorded chunk of that size too).
 constexpr int MG_NEXT_CHUNK = 2;

@@ -404,7 +404,7 @@ flip_status pcg_loop(flip_handle* h, V* x, int max_iters, hipStream_t st, PcgSta
 {
     // Chunk sizes: each host test idles the GPU for a round trip, and each
     // iteration launched past convergence still costs its launches (two with
-    // Jacobi, fourteen with the V-cycle), so the multigrid solve starts with
+    // Jacobi, a dozen with the V-cycle), so the multigrid solve starts with
     // the previous step's count and then tests every two iterations, the
     // Jacobi solve with two fewer than before and then every eight.
     const bool mg_solve = h->nmg > 0;
